@@ -1,0 +1,457 @@
+"""FP64 CPU oracle of multilevel maxent-stress layout.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the GPU library never
+calls it and shares no code with it.  The heavy loops live in mm_oracle.c
+(plain C, FP64); this module marshals numpy arrays and restates the
+multilevel driver of the paper's Section 3:
+
+* hierarchy (Section 3.1): size-constrained label propagation with
+  U = max(max_v c(v), W), W = min(b^h, |V|/f), contraction, and the rule
+  "contracted graph not 10% smaller -> f := 0.7 f";
+* initial layout and prolongation (Sections 3.1, 3.2);
+* local improvement (Section 3.2): Jacobi iterations of Eq. 2 with
+  target distances sqrt(c_u)+sqrt(c_v) on coarse levels, the alpha schedule
+  alpha := decay*alpha down to alpha_min with at most `a` iterations per
+  round, an early alpha drop when the relative change is below epsilon, and
+  iteration at alpha_min until the relative change is below eps_final.
+
+Readings of points the paper leaves open are listed in the repository's
+design notes and restated in the docstrings below.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+from .build import LIB, build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            _build()
+        L = C.CDLL(LIB)
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+        vp = C.c_void_p
+        L.orc_splitmix64_at.restype = C.c_uint64
+        L.orc_splitmix64_at.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_draws.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_int64, u64p]
+        L.orc_validate.argtypes = [C.c_int32, i32p, i32p, vp, vp]
+        L.orc_khop_build.argtypes = [C.c_int32, i32p, i32p, C.c_int32, i64p, vp, vp]
+        L.orc_farfield_exact.argtypes = [C.c_int32, f64p, C.c_double, f64p]
+        L.orc_bh.argtypes = [C.c_int32, f64p, C.c_double, C.c_double, f64p, vp, vp, vp,
+                             C.c_int64, i64p]
+        L.orc_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, i64p, i32p, i32p, vp,
+                                C.c_double, f64p, f64p, C.c_double, C.c_double, f64p, f64p]
+        L.orc_sweep_direct.argtypes = [C.c_int32, C.c_int32, C.c_int32, i64p, i32p, i32p, vp,
+                                       C.c_double, f64p, C.c_double, C.c_double, f64p, f64p]
+        L.orc_sweep_rows.argtypes = [C.c_int32, i32p, i32p, C.c_int32, C.c_int32, vp,
+                                     C.c_double, f64p, f64p, C.c_double, C.c_double, i32p,
+                                     C.c_int32, f64p, i64p]
+        L.orc_lp.argtypes = [C.c_int32, i32p, i32p, vp, vp, C.c_double, C.c_int32,
+                             C.c_uint64, C.c_int32, i32p, i32p]
+        L.orc_contract.restype = C.c_int32
+        L.orc_contract.argtypes = [C.c_int32, i32p, i32p, vp, vp, i32p, i32p, i32p, i32p,
+                                   i32p, i32p, i64p]
+        L.orc_init_layout.argtypes = [C.c_int32, C.c_uint64, C.c_int32, f64p]
+        L.orc_prolong.argtypes = [C.c_int32, i32p, vp, f64p, C.c_uint64, C.c_int32, f64p]
+        L.orc_objective.argtypes = [C.c_int32, C.c_int32, C.c_int32, i64p, i32p, i32p, vp,
+                                    C.c_double, f64p, C.c_double, f64p]
+        L.orc_full_stress.argtypes = [C.c_int32, i32p, i32p, f64p, f64p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ------------------------------------------------------------------ primitives
+
+def splitmix64_at(state: int, i: int) -> int:
+    return int(lib().orc_splitmix64_at(state, i))
+
+
+def draws(seed: int, level: int, tag: int, i0: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    lib().orc_draws(seed, level, tag, i0, count, out)
+    return out
+
+
+def validate(row_ptr, col, node_w=None, edge_w=None) -> int:
+    row_ptr, col = _i32(row_ptr), _i32(col)
+    node_w, edge_w = _i32(node_w), _i32(edge_w)
+    n = row_ptr.size - 1
+    if n < 2:
+        return 1
+    return int(lib().orc_validate(n, row_ptr, col, _ptr(node_w), _ptr(edge_w)))
+
+
+@dataclass
+class KHop:
+    """S_k(u) for every u: off[n+1], hend[n*k] (cumulative per-hop counts), nbr."""
+
+    k: int
+    off: np.ndarray
+    hend: np.ndarray
+    nbr: np.ndarray
+
+    @property
+    def n(self):
+        return self.off.size - 1
+
+    def row(self, u):
+        return self.nbr[self.off[u]:self.off[u + 1]]
+
+    def hops(self, u):
+        """hop of every entry of row u."""
+        hc = self.hend[u * self.k:(u + 1) * self.k]
+        return np.repeat(np.arange(1, self.k + 1), np.diff(np.concatenate([[0], hc])))
+
+
+def khop_build(row_ptr, col, k: int) -> KHop:
+    row_ptr, col = _i32(row_ptr), _i32(col)
+    n = row_ptr.size - 1
+    off = np.zeros(n + 1, dtype=np.int64)
+    if lib().orc_khop_build(n, row_ptr, col, k, off, None, None) != 0:
+        raise MemoryError("khop count")
+    hend = np.zeros(n * k, dtype=np.int32)
+    nbr = np.zeros(int(off[-1]), dtype=np.int32)
+    if lib().orc_khop_build(n, row_ptr, col, k, off, _ptr(hend), _ptr(nbr)) != 0:
+        raise MemoryError("khop fill")
+    return KHop(k, off, hend, nbr)
+
+
+def farfield_exact(xy, q: float = 0.0) -> np.ndarray:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    n = xy.size // 2
+    F = np.zeros(2 * n)
+    lib().orc_farfield_exact(n, xy, q, F)
+    return F.reshape(n, 2)
+
+
+@dataclass
+class BHResult:
+    F: np.ndarray
+    codes: np.ndarray
+    order: np.ndarray
+    nodes: np.ndarray  # (count, 5): depth, first, count, is_leaf, prefix (pre-order)
+    accepted: int
+    leaf_pairs: int
+    coincident: int
+
+
+def barnes_hut(xy, theta: float, q: float = 0.0) -> BHResult:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    n = xy.size // 2
+    F = np.zeros(2 * n)
+    codes = np.zeros(n, dtype=np.uint64)
+    order = np.zeros(n, dtype=np.int32)
+    cap = 2 * n + 1
+    nodes = np.zeros(5 * cap, dtype=np.int64)
+    stats = np.zeros(4, dtype=np.int64)
+    rc = lib().orc_bh(n, xy, q, theta, F, _ptr(codes), _ptr(order), _ptr(nodes), cap, stats)
+    if rc != 0:
+        raise MemoryError("orc_bh")
+    nn = int(stats[3])
+    return BHResult(F.reshape(n, 2), codes, order, nodes[:5 * nn].reshape(nn, 5),
+                    int(stats[0]), int(stats[1]), int(stats[2]))
+
+
+def sweep(kh: KHop, x, F, alpha: float, q: float = 0.0, level: int = 0,
+          c=None, scale: float = 1.0):
+    """One Jacobi iteration (Eq. 2) with the far field F given (all v != u).
+
+    Returns (x', delta) with delta = |x'-x| / |x|."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(-1)
+    c = _i32(c)
+    n = x.size // 2
+    xo = np.zeros(2 * n)
+    d = np.zeros(2)
+    lib().orc_sweep(n, level, kh.k, kh.off, kh.hend, kh.nbr, _ptr(c), scale, x, F, alpha, q,
+                    xo, d)
+    return xo.reshape(n, 2), math.sqrt(d[0] / d[1]) if d[1] > 0 else math.inf
+
+
+def sweep_direct(kh: KHop, x, alpha: float, q: float = 0.0, level: int = 0, c=None,
+                 scale: float = 1.0):
+    """Eq. 2 with the entropy sum taken directly over v not in S(u)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    c = _i32(c)
+    n = x.size // 2
+    xo = np.zeros(2 * n)
+    d = np.zeros(2)
+    if lib().orc_sweep_direct(n, level, kh.k, kh.off, kh.hend, kh.nbr, _ptr(c), scale, x,
+                              alpha, q, xo, d) != 0:
+        raise MemoryError("sweep_direct")
+    return xo.reshape(n, 2), math.sqrt(d[0] / d[1]) if d[1] > 0 else math.inf
+
+
+def sweep_rows(row_ptr, col, k: int, x, F, alpha: float, rows, q: float = 0.0, level: int = 0,
+               c=None, scale: float = 1.0):
+    """Eq. 2 for the given rows only, each S(u) found by its own BFS."""
+    row_ptr, col, c = _i32(row_ptr), _i32(col), _i32(c)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(-1)
+    rows = _i32(rows)
+    n = row_ptr.size - 1
+    out = np.zeros(2 * rows.size)
+    sizes = np.zeros(rows.size, dtype=np.int64)
+    if lib().orc_sweep_rows(n, row_ptr, col, level, k, _ptr(c), scale, x, F, alpha, q, rows,
+                            rows.size, out, sizes) != 0:
+        raise MemoryError("sweep_rows")
+    return out.reshape(-1, 2), sizes
+
+
+def lp(row_ptr, col, U: float, rounds: int, seed: int, level_h: int, c=None, w=None,
+       label=None):
+    """Synchronous size-constrained label propagation (see mm_oracle.h)."""
+    row_ptr, col, c, w = _i32(row_ptr), _i32(col), _i32(c), _i32(w)
+    n = row_ptr.size - 1
+    lab = np.arange(n, dtype=np.int32) if label is None else _i32(label).copy()
+    moves = np.zeros(max(rounds, 1), dtype=np.int32)
+    r = lib().orc_lp(n, row_ptr, col, _ptr(c), _ptr(w), U, rounds, seed, level_h, lab, moves)
+    if r < 0:
+        raise MemoryError("lp")
+    return lab, moves[:r]
+
+
+@dataclass
+class Level:
+    row_ptr: np.ndarray
+    col: np.ndarray
+    c: np.ndarray | None = None  # node weights (None = 1)
+    w: np.ndarray | None = None  # edge weights (None = 1)
+
+    @property
+    def n(self):
+        return self.row_ptr.size - 1
+
+
+def contract(lv: Level, label):
+    n = lv.n
+    nnz = lv.col.size
+    cluster = np.zeros(n, dtype=np.int32)
+    crp = np.zeros(n + 1, dtype=np.int32)
+    ccol = np.zeros(max(nnz, 1), dtype=np.int32)
+    cc = np.zeros(n, dtype=np.int32)
+    cw = np.zeros(max(nnz, 1), dtype=np.int32)
+    cnnz = np.zeros(1, dtype=np.int64)
+    nc = lib().orc_contract(n, _i32(lv.row_ptr), _i32(lv.col), _ptr(_i32(lv.c)),
+                            _ptr(_i32(lv.w)), _i32(label), cluster, crp, ccol, cc, cw, cnnz)
+    if nc < 0:
+        raise MemoryError("contract")
+    e = int(cnnz[0])
+    return cluster, Level(crp[:nc + 1].copy(), ccol[:e].copy(), cc[:nc].copy(), cw[:e].copy())
+
+
+def init_layout(n: int, seed: int, level: int) -> np.ndarray:
+    xy = np.zeros(2 * n)
+    lib().orc_init_layout(n, seed, level, xy)
+    return xy.reshape(n, 2)
+
+
+def prolong(cluster, coarse_c, coarse_xy, seed: int, level: int) -> np.ndarray:
+    cluster = _i32(cluster)
+    cxy = np.ascontiguousarray(coarse_xy, dtype=np.float64).reshape(-1)
+    out = np.zeros(2 * cluster.size)
+    lib().orc_prolong(cluster.size, cluster, _ptr(_i32(coarse_c)), cxy, seed, level, out)
+    return out.reshape(-1, 2)
+
+
+def objective(kh: KHop, x, alpha: float, q: float = 0.0, level: int = 0, c=None,
+              scale: float = 1.0) -> dict:
+    """Maxent-stress (Eq. 1 over the stress set S = S_k): M = stress - alpha*ent."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    n = x.size // 2
+    out = np.zeros(3)
+    if lib().orc_objective(n, level, kh.k, kh.off, kh.hend, kh.nbr, _ptr(_i32(c)), scale, x, q,
+                           out) != 0:
+        raise MemoryError("objective")
+    return {"stress": out[0], "ent": out[1], "coincident": int(out[2]),
+            "M": out[0] - alpha * out[1]}
+
+
+def full_stress(row_ptr, col, x) -> dict:
+    """Full stress over all pairs with hop distances; F at the optimal scale s*."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    n = x.size // 2
+    out = np.zeros(3)
+    if lib().orc_full_stress(n, _i32(row_ptr), _i32(col), x, out) != 0:
+        raise MemoryError("full_stress")
+    return {"F_unscaled": out[0], "s_opt": out[1], "F": out[2]}
+
+
+# ------------------------------------------------------------------ driver
+
+@dataclass
+class Params:
+    """Layout parameters; defaults are the paper's configuration.
+
+    k: hop radius of the stress set (1 = edges only, the paper's default model).
+    theta < 0 selects the exact all-pairs far field, theta >= 0 Barnes-Hut.
+    """
+
+    k: int = 1
+    q: float = 0.0
+    theta: float = 0.5
+    alpha0: float = 1.0
+    alpha_decay: float = 0.3
+    alpha_min: float = 0.008
+    iters_per_round: int = 2
+    eps_round: float = 1e-4
+    eps_final: float = 1e-4
+    max_final_iters: int = 200
+    max_levels: int = 64
+    coarsest_n: int = 2
+    b: float = 2.0
+    f: float = 20.0
+    lp_rounds: int = 10
+    coarse_dist_scale: float = 1.0
+    seed: int = 1
+
+
+def schedule(alpha0, alpha_decay, alpha_min):
+    """alpha values of the rounds before the final phase at alpha_min."""
+    out = []
+    a = alpha0
+    while a > alpha_min:
+        out.append(a)
+        a = max(a * alpha_decay, alpha_min)
+    return out
+
+
+def hierarchy(g0: Level, p: Params):
+    """Coarsening (Section 3.1).  Returns (levels, clusters, info).
+
+    Reading: |V| in W = min(b^h, |V|/f) is the total node weight; h is the
+    index of the level being built (1 for the first contraction).  When the
+    contracted graph is not 10% smaller, f := 0.7 f for all later levels, and
+    the level is rebuilt with the new f only if W was bounded by |V|/f (else
+    a rebuild could not change the result); at most 10 rebuilds per level.
+    Coarsening stops at max_levels, at <= max(coarsest_n, 2) vertices, or
+    when a contraction makes no progress or would leave fewer than 2
+    vertices (the paper coarsens down to two nodes).
+    """
+    levels = [g0]
+    clusters = []
+    f = p.f
+    cV = float(g0.n if g0.c is None else int(np.sum(g0.c, dtype=np.int64)))
+    h = 1
+    redo = 0
+    info = []
+    while len(levels) - 1 < p.max_levels and levels[-1].n > max(p.coarsest_n, 2):
+        G = levels[-1]
+        W = min(p.b ** h, cV / f)
+        maxc = 1 if G.c is None else int(G.c.max())
+        U = max(float(maxc), W)
+        label, moves = lp(G.row_ptr, G.col, U, p.lp_rounds, p.seed, h, G.c, G.w)
+        cluster, Gc = contract(G, label)
+        if Gc.n > 0.9 * G.n:
+            bounded_by_f = (cV / f) < p.b ** h
+            f = 0.7 * f
+            if bounded_by_f and redo < 10:
+                redo += 1
+                continue
+        if Gc.n >= G.n or Gc.n < 2:
+            break
+        info.append({"h": h, "U": U, "n": Gc.n, "lp_rounds": int(moves.size), "redo": redo})
+        levels.append(Gc)
+        clusters.append(cluster)
+        h += 1
+        redo = 0
+    return levels, clusters, info
+
+
+def far_field(x, p: Params):
+    if p.theta < 0:
+        return farfield_exact(x, p.q)
+    return barnes_hut(x, p.theta, p.q).F
+
+
+def refine(lv: Level, level: int, x, p: Params, kh: KHop | None = None, start_alpha=None):
+    """Local improvement on one level (Section 3.2)."""
+    if kh is None:
+        kh = khop_build(lv.row_ptr, lv.col, p.k)
+    alpha = p.alpha0 if start_alpha is None else start_alpha
+    iters = 0
+    hist = []
+
+    def T(x, a):
+        F = far_field(x, p)
+        return sweep(kh, x, F, a, p.q, level, lv.c, p.coarse_dist_scale)
+
+    while alpha > p.alpha_min:
+        for _ in range(p.iters_per_round):
+            x, d = T(x, alpha)
+            iters += 1
+            hist.append((alpha, d))
+            if d < p.eps_round:
+                break
+        alpha = max(alpha * p.alpha_decay, p.alpha_min)
+    final = 0
+    for _ in range(p.max_final_iters):
+        x, d = T(x, p.alpha_min)
+        iters += 1
+        final += 1
+        hist.append((p.alpha_min, d))
+        if d < p.eps_final:
+            break
+    return x, {"iters": iters, "final_iters": final, "hist": hist, "khop_entries": int(kh.off[-1])}
+
+
+def place_pair(x, lv: Level, level: int, p: Params):
+    """Two-vertex coarsest graph: keep the seeded direction, set the distance to
+    the optimal one (Section 3.1), i.e. the target distance of the pair."""
+    c0 = 1 if lv.c is None else int(lv.c[0])
+    c1 = 1 if lv.c is None else int(lv.c[1])
+    d = 1.0 if level == 0 else (math.sqrt(c0) + math.sqrt(c1)) * p.coarse_dist_scale
+    x = np.array(x, dtype=np.float64).reshape(2, 2)
+    dx, dy = x[1, 0] - x[0, 0], x[1, 1] - x[0, 1]
+    D = math.sqrt(dx * dx + dy * dy)
+    if D == 0.0:
+        dx, dy, D = 1.0, 0.0, 1.0
+    x[1, 0] = x[0, 0] + d * dx / D
+    x[1, 1] = x[0, 1] + d * dy / D
+    return x
+
+
+def layout(g, p: Params, init_xy=None):
+    """Full multilevel layout.  g: object with row_ptr/col (+ optional node_w,
+    edge_w).  Returns (x[n,2] FP64, stats)."""
+    g0 = Level(_i32(g.row_ptr), _i32(g.col), _i32(getattr(g, "node_w", None)),
+               _i32(getattr(g, "edge_w", None)))
+    levels, clusters, info = hierarchy(g0, p)
+    L = len(levels) - 1
+    stats = {"levels": [], "hierarchy": info}
+    if init_xy is not None:
+        # warm start on the finest level only (dynamic update)
+        x, st = refine(levels[0], 0, np.asarray(init_xy, dtype=np.float64), p,
+                       start_alpha=p.alpha_min)
+        stats["levels"].append({"level": 0, "n": levels[0].n, **st})
+        return x, stats
+    x = init_layout(levels[L].n, p.seed, L)
+    if levels[L].n == 2:
+        x = place_pair(x, levels[L], L, p)
+    for lvl in range(L, -1, -1):
+        if lvl < L:
+            x = prolong(clusters[lvl], levels[lvl + 1].c, x, p.seed, lvl)
+        x, st = refine(levels[lvl], lvl, x, p)
+        stats["levels"].append({"level": lvl, "n": levels[lvl].n, **st})
+    return x, stats
