@@ -1,0 +1,180 @@
+/*
+ * mulment: multilevel maxent-stress graph layout on one MI355X (gfx950).
+ *
+ * C-ABI of libmulment.so.  Plain pointers and sizes only.  Every call returns
+ * an mm_status; on failure the outputs are left untouched and
+ * mm_last_error() describes the failure (thread-local, valid until the next
+ * call on the same thread).  No exception or abort crosses this boundary.
+ *
+ * Memory.  Unless a parameter says "host", pointers are device pointers
+ * (HBM) and are used in place on the context's HIP stream; the caller owns
+ * them and keeps them alive until mm_sync() returns.  Objects the library
+ * allocates (mm_khop, mm_coarse) are released with their *_free call.
+ * A context is bound to one device and one stream and is not thread-safe;
+ * separate contexts are independent.
+ *
+ * Graphs are undirected simple graphs (Preliminaries, "Basic Concepts"):
+ * CSR with int32 row_ptr[n+1] and col[nnz], both directions stored, rows
+ * strictly ascending, no self-loops; node weights c >= 1 and edge weights
+ * w >= 1 (NULL = all 1, the paper's default inputs).
+ */
+#ifndef MULMENT_H
+#define MULMENT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_EINVAL = 1,       /* invalid argument or malformed graph */
+  MM_ENOMEM = 2,       /* device allocation failed */
+  MM_EDEVICE = 3,      /* HIP runtime / kernel error */
+  MM_EUNSUPPORTED = 4, /* valid request outside the implemented range */
+  MM_EINTERNAL = 5
+} mm_status;
+
+typedef enum { MM_HOST = 0, MM_DEVICE = 1 } mm_mem;
+
+typedef struct mm_context mm_context;
+typedef struct mm_khop mm_khop;
+typedef struct mm_coarse mm_coarse;
+
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* row_ptr; /* n+1 */
+  const int32_t* col;     /* nnz */
+  const int32_t* node_w;  /* n, or NULL (all 1) */
+  const int32_t* edge_w;  /* nnz, or NULL (all 1) */
+  int32_t mem;            /* mm_mem: where the four arrays live */
+} mm_graph;
+
+/* Layout parameters.  mm_params_default() gives the paper's configuration
+ * (Section 4, "Algorithm Configuration"; Section 3.2 for the alpha decay). */
+typedef struct {
+  int32_t k;               /* stress set S = pairs within k hops (1 = edges, Eq. 1) */
+  double q;                /* entropy exponent: r_q = (x_u-x_v)/|x_u-x_v|^(q+2); 0 = ln */
+  double theta;            /* Barnes-Hut opening angle; < 0 = exact all-pairs far field */
+  double alpha0;           /* initial entropy weight (1) */
+  double alpha_decay;      /* alpha := decay * alpha per round (0.3) */
+  double alpha_min;        /* final alpha (0.008) */
+  int32_t iters_per_round; /* a: iterations per alpha round (2) */
+  double eps_round;        /* early alpha drop when relative change < eps_round (1e-4) */
+  double eps_final;        /* stop at alpha_min when relative change < eps_final (1e-4) */
+  int32_t max_final_iters; /* cap on iterations at alpha_min (200) */
+  int32_t max_levels;      /* max number of contractions (62) */
+  int32_t coarsest_n;      /* stop coarsening at <= this many vertices (2) */
+  double b, f;             /* W = min(b^h, |V|/f) (2, 20) */
+  int32_t lp_rounds;       /* label-propagation rounds per level (10) */
+  double coarse_dist_scale;/* d = hop (sqrt c_u + sqrt c_v) scale on coarse levels (1) */
+  uint64_t seed;
+  int32_t validate;        /* 1: full host-side graph validation (default) */
+} mm_params;
+
+#define MM_MAX_LEVELS 64
+typedef struct {
+  int32_t levels;                        /* graphs in the hierarchy incl. the input */
+  int32_t level_n[MM_MAX_LEVELS];
+  int64_t level_nnz[MM_MAX_LEVELS];
+  int64_t level_khop[MM_MAX_LEVELS];     /* sum |S(u)| */
+  int32_t level_iters[MM_MAX_LEVELS];
+  int32_t level_final_iters[MM_MAX_LEVELS];
+  int32_t level_cap_hit[MM_MAX_LEVELS];  /* final phase stopped by max_final_iters */
+  double level_delta[MM_MAX_LEVELS];     /* last relative change */
+  double t_total_ms, t_coarsen_ms, t_khop_ms, t_farfield_ms, t_sweep_ms, t_other_ms;
+  int64_t vertex_updates;                /* sum over levels of n * iterations */
+  int64_t finest_updates;                /* n_0 * iterations on the input graph */
+} mm_stats;
+
+mm_status mm_params_default(mm_params* p);
+
+/* device: HIP device ordinal; stream: hipStream_t or NULL (default stream). */
+mm_status mm_context_create(mm_context** out, int32_t device, void* stream);
+void mm_context_destroy(mm_context* ctx);
+/* Waits for the context's stream; reports asynchronous device errors. */
+mm_status mm_sync(mm_context* ctx);
+const char* mm_last_error(void);
+
+/* Full multilevel layout (Section 3): coarsening, initial layout,
+ * prolongation and local improvement on every level.  init_xy (n*2,
+ * interleaved, same memory kind as the graph, or NULL): when given, the
+ * hierarchy is skipped and only the finest level is iterated starting at
+ * alpha_min (the warm start of the dynamic-graph update).  out_xy: n*2 in
+ * the graph's memory kind.  stats: host, may be NULL. */
+mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
+                    const float* init_xy, float* out_xy, mm_stats* stats);
+
+/* ---- step-level entry points (device graphs) ---------------------------- */
+
+/* k-hop distance sets S_k(u) = {v != u : hop(u,v) <= k}, sorted by (hop, v)
+ * (stress superset S of the general model, footnote to Eq. 1).  g must be
+ * MM_DEVICE.  Row offsets int64 off[n+1]; hend[u*k + h-1] = entries of row u
+ * with hop <= h; ids int32. */
+mm_status mm_khop_build(mm_context* ctx, const mm_graph* g, int32_t k, mm_khop** out);
+void mm_khop_free(mm_khop* kh);
+/* host: n, k, total entries */
+mm_status mm_khop_info(const mm_khop* kh, int32_t* n, int32_t* k, int64_t* total);
+/* device pointers of the sets (valid until mm_khop_free) */
+mm_status mm_khop_arrays(const mm_khop* kh, const int64_t** off, const int32_t** hend,
+                         const int32_t** nbr);
+/* copy the sets into caller buffers (off n+1, hend n*k, nbr total) of kind mem */
+mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32_t* hend,
+                         int32_t* nbr, int32_t mem);
+
+/* Far field F_u = sum_{v != u} r_q(u,v) (the entropy term of Eq. 2 before
+ * removing S).  theta < 0: exact all-pairs; theta >= 0: Barnes-Hut quadtree.
+ * xy, F: n*2 FP32 device.  codes (n, Morton codes in id order), order (n,
+ * ids sorted by (code, id)), nodes (5 int64 per node, pre-order: depth,
+ * first sorted index, count, is_leaf, prefix) are optional device outputs
+ * (Barnes-Hut only; nodes needs room for 2n entries); counters (host, 4
+ * int64: accepted cells, exact leaf pairs, reserved, node count) optional. */
+mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, double theta,
+                       float* F, uint64_t* codes, int32_t* order, int64_t* nodes,
+                       int64_t* counters);
+
+/* One Jacobi iteration of Eq. 2 at entropy weight alpha: xy_out from xy_in
+ * only.  level 0: d = hop; level > 0: d = hop (sqrt c_u + sqrt c_v) scale
+ * with c = node_w (device, n; NULL = 1).  F: far field from mm_repulsion.
+ * delta (host, 2 doubles, may be NULL): |x'-x|^2 and |x|^2. */
+mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
+                   double scale, const float* xy_in, const float* F, double alpha, double q,
+                   float* xy_out, double* delta);
+
+/* One coarsening step (Section 3.1): size-constrained label propagation with
+ * bound U at hierarchy level level_h, then contraction.  cluster (device, n)
+ * receives the coarse vertex of every vertex; *out the coarse graph
+ * (device arrays owned by the library).  rounds_run / moves (host) optional. */
+mm_status mm_coarsen(mm_context* ctx, const mm_graph* g, double U, int32_t lp_rounds,
+                     uint64_t seed, int32_t level_h, int32_t* cluster, mm_coarse** out,
+                     int32_t* rounds_run, int64_t* moves);
+/* view of a coarse graph (device arrays, node_w and edge_w always set) */
+mm_status mm_coarse_graph(const mm_coarse* cg, mm_graph* view);
+/* copy the coarse graph into caller buffers (n+1, nnz, n, nnz) of kind mem */
+mm_status mm_coarse_export(mm_context* ctx, const mm_coarse* cg, int32_t* row_ptr, int32_t* col,
+                           int32_t* node_w, int32_t* edge_w, int32_t mem);
+void mm_coarse_free(mm_coarse* cg);
+
+/* Initial layout of the coarsest graph: uniform [0,1)^2 from the seed. */
+mm_status mm_init_layout(mm_context* ctx, int32_t n, uint64_t seed, int32_t level, float* xy);
+
+/* Prolongation (Section 3.2): fine v placed uniformly in angle and radius
+ * around coarse_xy[cluster[v]] within sqrt(coarse_w). */
+mm_status mm_prolong(mm_context* ctx, int32_t n_fine, const int32_t* cluster,
+                     const int32_t* coarse_w, const float* coarse_xy, uint64_t seed,
+                     int32_t level, float* fine_xy);
+
+/* Maxent-stress parts over S (Eq. 1): out (host, 3) = {stress over S,
+ * entropy sum over pairs not in S, coincident pairs}; M = out[0] - alpha*out[1]. */
+mm_status mm_objective(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
+                       double scale, const float* xy, double q, double* out);
+
+/* Full stress over all connected pairs with hop distances (Section 4):
+ * out (host, 3) = {F(x), s*, F(s* x)}.  Requires n <= 1179648. */
+mm_status mm_full_stress(mm_context* ctx, const mm_graph* g, const float* xy, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

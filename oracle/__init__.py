@@ -318,7 +318,7 @@ class Params:
     eps_round: float = 1e-4
     eps_final: float = 1e-4
     max_final_iters: int = 200
-    max_levels: int = 64
+    max_levels: int = 62
     coarsest_n: int = 2
     b: float = 2.0
     f: float = 20.0

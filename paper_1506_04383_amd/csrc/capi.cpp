@@ -1,0 +1,671 @@
+// C-ABI of libmulment and the multilevel driver (Section 3 of the paper):
+// coarsening loop with the size bound U = max(max c, min(b^h, |V|/f)) and the
+// f := 0.7 f rule, initial layout, prolongation, and on every level the
+// alpha schedule of the local improvement (at most `a` Jacobi iterations per
+// alpha, early drop below eps_round, iteration at alpha_min until the
+// relative change is below eps_final).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mulment.h"
+#include "kernels.hpp"
+
+struct mm_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mm::BHWork* bh = nullptr;
+  double* pinned = nullptr;  // 4 doubles for small read-backs
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+struct mm_khop {
+  mm::KhopDev kh;
+};
+struct mm_coarse {
+  mm::GraphDev g;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+mm_status fail(mm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+mm_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? MM_ENOMEM : MM_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+#define HIPCHK(expr)                                        \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);       \
+  } while (0)
+#define STCHK(expr)                                         \
+  do {                                                      \
+    mm_status _s = (expr);                                  \
+    if (_s != MM_OK) return _s;                             \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Host-side structural validation (undirected simple graph, weights >= 1).
+mm_status validate_graph(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                         const int32_t* c, const int32_t* w) {
+  if (n < 2) return fail(MM_EINVAL, "graph needs at least 2 vertices (n=%d)", n);
+  if (rp[0] != 0 || (int64_t)rp[n] != nnz) return fail(MM_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
+  for (int32_t u = 0; u < n; ++u)
+    if (rp[u + 1] < rp[u]) return fail(MM_EINVAL, "row_ptr not monotone at %d", u);
+  for (int32_t u = 0; u < n; ++u) {
+    if (rp[u + 1] == rp[u]) return fail(MM_EINVAL, "vertex %d is isolated (rho_u = 0)", u);
+    if (c && c[u] < 1) return fail(MM_EINVAL, "node weight of %d < 1", u);
+    for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+      const int32_t v = col[e];
+      if (v < 0 || v >= n) return fail(MM_EINVAL, "column %d out of range in row %d", v, u);
+      if (v == u) return fail(MM_EINVAL, "self-loop at %d", u);
+      if (e > rp[u] && col[e - 1] >= v) return fail(MM_EINVAL, "row %d not strictly ascending", u);
+      if (w && w[e] < 1) return fail(MM_EINVAL, "edge weight < 1 in row %d", u);
+    }
+  }
+  for (int32_t u = 0; u < n; ++u) {
+    for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+      const int32_t v = col[e];
+      const int32_t* b = col + rp[v];
+      const int32_t* en = col + rp[v + 1];
+      const int32_t* it = std::lower_bound(b, en, u);
+      if (it == en || *it != u) return fail(MM_EINVAL, "edge %d-%d has no reverse", u, v);
+      if (w && w[it - col] != w[e]) return fail(MM_EINVAL, "edge weights of %d-%d differ", u, v);
+    }
+  }
+  return MM_OK;
+}
+
+mm_status validate_params(const mm_params* p) {
+  if (!p) return fail(MM_EINVAL, "params is NULL");
+  if (p->k < 1 || p->k > 8) return fail(MM_EINVAL, "k must be in [1, 8]");
+  if (std::isnan(p->theta) || std::isnan(p->q)) return fail(MM_EINVAL, "theta/q NaN");
+  if (!(p->alpha0 > 0) || !(p->alpha_min > 0)) return fail(MM_EINVAL, "alpha0, alpha_min must be > 0");
+  if (p->alpha0 < p->alpha_min) return fail(MM_EINVAL, "alpha schedule inverted (alpha0 < alpha_min)");
+  if (!(p->alpha_decay > 0 && p->alpha_decay < 1)) return fail(MM_EINVAL, "alpha_decay must be in (0,1)");
+  if (p->iters_per_round < 1 || p->max_final_iters < 0) return fail(MM_EINVAL, "iteration counts");
+  if (!(p->eps_round >= 0) || !(p->eps_final >= 0)) return fail(MM_EINVAL, "eps must be >= 0");
+  if (p->max_levels < 0 || p->max_levels >= MM_MAX_LEVELS) return fail(MM_EINVAL, "max_levels in [0, 63]");
+  if (!(p->b > 1) || !(p->f > 0)) return fail(MM_EINVAL, "b > 1 and f > 0 required");
+  if (p->lp_rounds < 0) return fail(MM_EINVAL, "lp_rounds < 0");
+  if (!(p->coarse_dist_scale > 0)) return fail(MM_EINVAL, "coarse_dist_scale must be > 0");
+  return MM_OK;
+}
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  Timer(hipEvent_t a_, hipEvent_t b_, hipStream_t s_) : a(a_), b(b_), s(s_) {}
+};
+
+struct LevelGraph {
+  mm::GraphDev g;      // owned arrays for coarse levels
+  std::vector<int32_t> c_host;
+};
+
+// sqrt of node weights (ones when c is NULL)
+hipError_t make_sqrtc(int32_t n, const int32_t* c, mm::DevBuf& buf, hipStream_t s) {
+  MM_TRY(buf.alloc(sizeof(float) * (size_t)n, s));
+  return mm::sqrt_weights(n, c, buf.as<float>(), s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mm_last_error(void) { return g_err.c_str(); }
+
+mm_status mm_params_default(mm_params* p) {
+  if (!p) return fail(MM_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->k = 1;
+  p->q = 0.0;
+  p->theta = 0.5;
+  p->alpha0 = 1.0;
+  p->alpha_decay = 0.3;
+  p->alpha_min = 0.008;
+  p->iters_per_round = 2;
+  p->eps_round = 1e-4;
+  p->eps_final = 1e-4;
+  p->max_final_iters = 200;
+  p->max_levels = 62;
+  p->coarsest_n = 2;
+  p->b = 2.0;
+  p->f = 20.0;
+  p->lp_rounds = 10;
+  p->coarse_dist_scale = 1.0;
+  p->seed = 1;
+  p->validate = 1;
+  return MM_OK;
+}
+
+mm_status mm_context_create(mm_context** out, int32_t device, void* stream) {
+  try {
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(MM_EINVAL, "device %d out of range (%d)", device, count);
+    DeviceGuard dg(device);
+    std::unique_ptr<mm_context> c(new mm_context());
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->bh = mm::bh_work_create();
+    HIPCHK(hipHostMalloc((void**)&c->pinned, 4 * sizeof(double), hipHostMallocDefault));
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    *out = c.release();
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_context_create");
+  }
+}
+
+void mm_context_destroy(mm_context* ctx) {
+  if (!ctx) return;
+  DeviceGuard dg(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  mm::bh_work_destroy(ctx->bh);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+mm_status mm_sync(mm_context* ctx) {
+  if (!ctx) return fail(MM_EINVAL, "ctx is NULL");
+  DeviceGuard dg(ctx->device);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipGetLastError());
+  return MM_OK;
+}
+
+// ------------------------------------------------------------------ k-hop
+
+mm_status mm_khop_build(mm_context* ctx, const mm_graph* g, int32_t k, mm_khop** out) {
+  try {
+    if (!ctx || !g || !out) return fail(MM_EINVAL, "NULL argument");
+    if (g->mem != MM_DEVICE) return fail(MM_EINVAL, "mm_khop_build needs a device graph");
+    if (k < 1 || k > 8) return fail(MM_EINVAL, "k must be in [1, 8]");
+    if (g->n < 2) return fail(MM_EINVAL, "n < 2");
+    DeviceGuard dg(ctx->device);
+    std::unique_ptr<mm_khop> kh(new mm_khop());
+    HIPCHK(mm::khop_build(g->n, g->row_ptr, g->col, k, &kh->kh, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = kh.release();
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_khop_build");
+  }
+}
+
+void mm_khop_free(mm_khop* kh) { delete kh; }
+
+mm_status mm_khop_info(const mm_khop* kh, int32_t* n, int32_t* k, int64_t* total) {
+  if (!kh) return fail(MM_EINVAL, "kh is NULL");
+  if (n) *n = kh->kh.n;
+  if (k) *k = kh->kh.k;
+  if (total) *total = kh->kh.total;
+  return MM_OK;
+}
+
+mm_status mm_khop_arrays(const mm_khop* kh, const int64_t** off, const int32_t** hend,
+                         const int32_t** nbr) {
+  if (!kh) return fail(MM_EINVAL, "kh is NULL");
+  if (off) *off = kh->kh.off;
+  if (hend) *hend = kh->kh.hend;
+  if (nbr) *nbr = kh->kh.nbr;
+  return MM_OK;
+}
+
+mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32_t* hend,
+                         int32_t* nbr, int32_t mem) {
+  if (!ctx || !kh) return fail(MM_EINVAL, "NULL argument");
+  if (mem != MM_HOST && mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");
+  DeviceGuard dg(ctx->device);
+  const hipMemcpyKind kd = mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const mm::KhopDev& K = kh->kh;
+  if (off) HIPCHK(hipMemcpyAsync(off, K.off, sizeof(int64_t) * (size_t)(K.n + 1), kd, ctx->stream));
+  if (hend) HIPCHK(hipMemcpyAsync(hend, K.hend, sizeof(int32_t) * (size_t)K.n * K.k, kd, ctx->stream));
+  if (nbr && K.total > 0) HIPCHK(hipMemcpyAsync(nbr, K.nbr, sizeof(int32_t) * (size_t)K.total, kd, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return MM_OK;
+}
+
+// ------------------------------------------------------------- far field
+
+mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, double theta,
+                       float* F, uint64_t* codes, int32_t* order, int64_t* nodes,
+                       int64_t* counters) {
+  try {
+    if (!ctx || !xy || !F) return fail(MM_EINVAL, "NULL argument");
+    if (n < 1) return fail(MM_EINVAL, "n < 1");
+    if (std::isnan(theta) || std::isnan(q)) return fail(MM_EINVAL, "theta/q NaN");
+    DeviceGuard dg(ctx->device);
+    if (theta < 0) {
+      HIPCHK(mm::farfield_exact(n, xy, q, F, ctx->stream));
+      if (counters) { counters[0] = 0; counters[1] = (int64_t)n * (n - 1); counters[2] = 0; counters[3] = 0; }
+    } else {
+      mm::FarStats st{};
+      int64_t nn = 0;
+      HIPCHK(mm::farfield_bh(ctx->bh, n, xy, q, theta, F, codes, order, nodes, &nn,
+                             counters ? 1 : 0, &st, ctx->stream));
+      if (counters) { counters[0] = st.accepted; counters[1] = st.leaf_pairs; counters[2] = 0; counters[3] = nn; }
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_repulsion");
+  }
+}
+
+// ------------------------------------------------------------------ sweep
+
+mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
+                   double scale, const float* xy_in, const float* F, double alpha, double q,
+                   float* xy_out, double* delta) {
+  try {
+    if (!ctx || !kh || !xy_in || !F || !xy_out) return fail(MM_EINVAL, "NULL argument");
+    if (xy_in == xy_out) return fail(MM_EINVAL, "Jacobi update needs separate in/out buffers");
+    if (level < 0 || !(scale > 0) || std::isnan(alpha) || std::isnan(q)) return fail(MM_EINVAL, "bad level/scale/alpha/q");
+    DeviceGuard dg(ctx->device);
+    mm::DevBuf sq, d2;
+    const float* sqrtc = nullptr;
+    if (level > 0) {
+      HIPCHK(make_sqrtc(kh->kh.n, node_w, sq, ctx->stream));
+      sqrtc = sq.as<float>();
+    }
+    HIPCHK(d2.alloc(2 * sizeof(double), ctx->stream));
+    HIPCHK(mm::sweep(kh->kh, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2.as<double>(),
+                     ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (delta) { delta[0] = ctx->pinned[0]; delta[1] = ctx->pinned[1]; }
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_sweep");
+  }
+}
+
+// ------------------------------------------------------------- coarsening
+
+mm_status mm_coarsen(mm_context* ctx, const mm_graph* g, double U, int32_t lp_rounds,
+                     uint64_t seed, int32_t level_h, int32_t* cluster, mm_coarse** out,
+                     int32_t* rounds_run, int64_t* moves) {
+  try {
+    if (!ctx || !g || !cluster || !out) return fail(MM_EINVAL, "NULL argument");
+    if (g->mem != MM_DEVICE) return fail(MM_EINVAL, "mm_coarsen needs a device graph");
+    if (g->n < 2 || std::isnan(U) || lp_rounds < 0) return fail(MM_EINVAL, "bad n/U/rounds");
+    DeviceGuard dg(ctx->device);
+    mm::GraphDev G;
+    G.n = g->n; G.nnz = g->nnz;
+    G.row_ptr = const_cast<int32_t*>(g->row_ptr);
+    G.col = const_cast<int32_t*>(g->col);
+    G.c = const_cast<int32_t*>(g->node_w);
+    G.w = const_cast<int32_t*>(g->edge_w);
+    mm::DevBuf label;
+    HIPCHK(label.alloc(sizeof(int32_t) * (size_t)g->n, ctx->stream));
+    int32_t rr = 0;
+    std::vector<int64_t> mv((size_t)std::max(lp_rounds, 1), 0);
+    HIPCHK(mm::lp_cluster(G, U, lp_rounds, seed, level_h, label.as<int32_t>(), &rr, mv.data(),
+                          ctx->stream));
+    std::unique_ptr<mm_coarse> cg(new mm_coarse());
+    HIPCHK(mm::contract(G, label.as<int32_t>(), cluster, &cg->g, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (rounds_run) *rounds_run = rr;
+    if (moves) for (int32_t i = 0; i < rr; ++i) moves[i] = mv[(size_t)i];
+    *out = cg.release();
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_coarsen");
+  }
+}
+
+mm_status mm_coarse_graph(const mm_coarse* cg, mm_graph* v) {
+  if (!cg || !v) return fail(MM_EINVAL, "NULL argument");
+  v->n = cg->g.n;
+  v->nnz = cg->g.nnz;
+  v->row_ptr = cg->g.row_ptr;
+  v->col = cg->g.col;
+  v->node_w = cg->g.c;
+  v->edge_w = cg->g.w;
+  v->mem = MM_DEVICE;
+  return MM_OK;
+}
+
+void mm_coarse_free(mm_coarse* cg) { delete cg; }
+
+mm_status mm_coarse_export(mm_context* ctx, const mm_coarse* cg, int32_t* row_ptr, int32_t* col,
+                           int32_t* node_w, int32_t* edge_w, int32_t mem) {
+  if (!ctx || !cg) return fail(MM_EINVAL, "NULL argument");
+  if (mem != MM_HOST && mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");
+  DeviceGuard dg(ctx->device);
+  const hipMemcpyKind kd = mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const mm::GraphDev& G = cg->g;
+  if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, G.row_ptr, sizeof(int32_t) * (size_t)(G.n + 1), kd, ctx->stream));
+  if (col && G.nnz > 0) HIPCHK(hipMemcpyAsync(col, G.col, sizeof(int32_t) * (size_t)G.nnz, kd, ctx->stream));
+  if (node_w) HIPCHK(hipMemcpyAsync(node_w, G.c, sizeof(int32_t) * (size_t)G.n, kd, ctx->stream));
+  if (edge_w && G.nnz > 0) HIPCHK(hipMemcpyAsync(edge_w, G.w, sizeof(int32_t) * (size_t)G.nnz, kd, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return MM_OK;
+}
+
+// -------------------------------------------------------------- placement
+
+mm_status mm_init_layout(mm_context* ctx, int32_t n, uint64_t seed, int32_t level, float* xy) {
+  if (!ctx || !xy || n < 1 || level < 0) return fail(MM_EINVAL, "bad argument");
+  DeviceGuard dg(ctx->device);
+  HIPCHK(mm::init_layout(n, seed, level, xy, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return MM_OK;
+}
+
+mm_status mm_prolong(mm_context* ctx, int32_t n_fine, const int32_t* cluster,
+                     const int32_t* coarse_w, const float* coarse_xy, uint64_t seed,
+                     int32_t level, float* fine_xy) {
+  if (!ctx || !cluster || !coarse_xy || !fine_xy || n_fine < 1 || level < 0)
+    return fail(MM_EINVAL, "bad argument");
+  DeviceGuard dg(ctx->device);
+  HIPCHK(mm::prolong(n_fine, cluster, coarse_w, coarse_xy, seed, level, fine_xy, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return MM_OK;
+}
+
+// ------------------------------------------------------------- objectives
+
+mm_status mm_objective(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
+                       double scale, const float* xy, double q, double* out) {
+  try {
+    if (!ctx || !kh || !xy || !out) return fail(MM_EINVAL, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    mm::DevBuf sq;
+    const float* sqrtc = nullptr;
+    if (level > 0) {
+      HIPCHK(make_sqrtc(kh->kh.n, node_w, sq, ctx->stream));
+      sqrtc = sq.as<float>();
+    }
+    HIPCHK(mm::objective(kh->kh, level, sqrtc, scale, xy, q, out, ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_objective");
+  }
+}
+
+mm_status mm_full_stress(mm_context* ctx, const mm_graph* g, const float* xy, double* out) {
+  try {
+    if (!ctx || !g || !xy || !out) return fail(MM_EINVAL, "NULL argument");
+    if (g->mem != MM_DEVICE) return fail(MM_EINVAL, "mm_full_stress needs a device graph");
+    if (g->n > 1179648) return fail(MM_EUNSUPPORTED, "full stress limited to n <= 1179648");
+    DeviceGuard dg(ctx->device);
+    mm::GraphDev G;
+    G.n = g->n; G.nnz = g->nnz;
+    G.row_ptr = const_cast<int32_t*>(g->row_ptr);
+    G.col = const_cast<int32_t*>(g->col);
+    HIPCHK(mm::full_stress(G, xy, out, ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_full_stress");
+  }
+}
+
+// ---------------------------------------------------------------- layout
+
+mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
+                    const float* init_xy, float* out_xy, mm_stats* stats) {
+  try {
+    if (!ctx || !g || !out_xy) return fail(MM_EINVAL, "NULL argument");
+    STCHK(validate_params(p));
+    if (g->n < 2) return fail(MM_EINVAL, "graph needs at least 2 vertices (n=%d)", g->n);
+    if (g->nnz < 1 || g->nnz >= (1ll << 31)) return fail(MM_EINVAL, "nnz out of range");
+    if (g->mem != MM_HOST && g->mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int32_t n = g->n;
+    const int64_t nnz = g->nnz;
+    auto t_start = std::chrono::steady_clock::now();
+
+    // host copies for validation and bookkeeping
+    std::vector<int32_t> h_rp(n + 1), h_col((size_t)nnz), h_c, h_w;
+    const hipMemcpyKind k2h = g->mem == MM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPCHK(hipMemcpy(h_rp.data(), g->row_ptr, sizeof(int32_t) * (size_t)(n + 1), k2h));
+    if (p->validate || g->mem == MM_HOST)
+      HIPCHK(hipMemcpy(h_col.data(), g->col, sizeof(int32_t) * (size_t)nnz, k2h));
+    if (g->node_w) { h_c.resize(n); HIPCHK(hipMemcpy(h_c.data(), g->node_w, sizeof(int32_t) * (size_t)n, k2h)); }
+    if (g->edge_w) { h_w.resize((size_t)nnz); HIPCHK(hipMemcpy(h_w.data(), g->edge_w, sizeof(int32_t) * (size_t)nnz, k2h)); }
+    if (p->validate) {
+      STCHK(validate_graph(n, nnz, h_rp.data(), h_col.data(), h_c.empty() ? nullptr : h_c.data(),
+                           h_w.empty() ? nullptr : h_w.data()));
+    } else if (h_rp[0] != 0 || (int64_t)h_rp[n] != nnz) {
+      return fail(MM_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
+    }
+    if (init_xy) {
+      std::vector<float> hx(2 * (size_t)n);
+      HIPCHK(hipMemcpy(hx.data(), init_xy, sizeof(float) * hx.size(), k2h));
+      for (float v : hx) if (!std::isfinite(v)) return fail(MM_EINVAL, "init_xy not finite");
+    }
+
+    // level 0 on the device
+    std::vector<std::unique_ptr<LevelGraph>> levels;
+    levels.emplace_back(new LevelGraph());
+    mm::GraphDev& G0 = levels[0]->g;
+    G0.n = n;
+    G0.nnz = nnz;
+    if (g->mem == MM_DEVICE) {
+      G0.row_ptr = const_cast<int32_t*>(g->row_ptr);
+      G0.col = const_cast<int32_t*>(g->col);
+      G0.c = const_cast<int32_t*>(g->node_w);
+      G0.w = const_cast<int32_t*>(g->edge_w);
+    } else {
+      HIPCHK(G0.b_rp.alloc(sizeof(int32_t) * (size_t)(n + 1), s));
+      HIPCHK(G0.b_col.alloc(sizeof(int32_t) * (size_t)nnz, s));
+      G0.row_ptr = G0.b_rp.as<int32_t>();
+      G0.col = G0.b_col.as<int32_t>();
+      HIPCHK(hipMemcpyAsync(G0.row_ptr, h_rp.data(), sizeof(int32_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(G0.col, h_col.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s));
+      if (!h_c.empty()) {
+        HIPCHK(G0.b_c.alloc(sizeof(int32_t) * (size_t)n, s));
+        G0.c = G0.b_c.as<int32_t>();
+        HIPCHK(hipMemcpyAsync(G0.c, h_c.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+      }
+      if (!h_w.empty()) {
+        HIPCHK(G0.b_w.alloc(sizeof(int32_t) * (size_t)nnz, s));
+        G0.w = G0.b_w.as<int32_t>();
+        HIPCHK(hipMemcpyAsync(G0.w, h_w.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s));
+      }
+    }
+    levels[0]->c_host = h_c;
+    HIPCHK(hipStreamSynchronize(s));
+
+    mm_stats st;
+    std::memset(&st, 0, sizeof(st));
+    double t_coarsen = 0, t_khop = 0, t_far = 0, t_sweep = 0;
+
+    // ---- hierarchy (Section 3.1)
+    std::vector<mm::DevBuf> clusters;
+    auto t0 = std::chrono::steady_clock::now();
+    if (!init_xy) {
+      double cV = 0;
+      if (h_c.empty()) cV = (double)n;
+      else for (int32_t v = 0; v < n; ++v) cV += h_c[v];
+      double f = p->f;
+      int32_t h = 1, redo = 0;
+      while ((int32_t)levels.size() - 1 < p->max_levels &&
+             levels.back()->g.n > std::max(p->coarsest_n, 2)) {
+        LevelGraph& L = *levels.back();
+        const double W = std::min(std::pow(p->b, (double)h), cV / f);
+        int32_t maxc = 1;
+        for (int32_t x : L.c_host) maxc = std::max(maxc, x);
+        const double U = std::max((double)maxc, W);
+        mm::DevBuf label, cluster;
+        HIPCHK(label.alloc(sizeof(int32_t) * (size_t)L.g.n, s));
+        HIPCHK(cluster.alloc(sizeof(int32_t) * (size_t)L.g.n, s));
+        int32_t rr = 0;
+        std::vector<int64_t> mv((size_t)std::max(p->lp_rounds, 1), 0);
+        HIPCHK(mm::lp_cluster(L.g, U, p->lp_rounds, p->seed, h, label.as<int32_t>(), &rr, mv.data(), s));
+        std::unique_ptr<LevelGraph> C(new LevelGraph());
+        HIPCHK(mm::contract(L.g, label.as<int32_t>(), cluster.as<int32_t>(), &C->g, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (C->g.n > 0.9 * L.g.n) {
+          const bool bounded_by_f = (cV / f) < std::pow(p->b, (double)h);
+          f = 0.7 * f;
+          if (bounded_by_f && redo < 10) { redo++; continue; }
+        }
+        if (C->g.n >= L.g.n || C->g.n < 2) break;
+        C->c_host.resize((size_t)C->g.n);
+        HIPCHK(hipMemcpy(C->c_host.data(), C->g.c, sizeof(int32_t) * (size_t)C->g.n, hipMemcpyDeviceToHost));
+        levels.push_back(std::move(C));
+        clusters.push_back(std::move(cluster));
+        h++;
+        redo = 0;
+      }
+    }
+    t_coarsen = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const int32_t Lmax = (int32_t)levels.size() - 1;
+    st.levels = Lmax + 1;
+
+    // ---- placement of the coarsest level
+    mm::DevBuf xa, xb, F, d2;
+    const int32_t nL = levels[Lmax]->g.n;
+    HIPCHK(xa.alloc(sizeof(float) * 2 * (size_t)nL, s));
+    if (init_xy) {
+      HIPCHK(hipMemcpyAsync(xa.p, init_xy, sizeof(float) * 2 * (size_t)n,
+                            g->mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    } else {
+      HIPCHK(mm::init_layout(nL, p->seed, Lmax, xa.as<float>(), s));
+      if (nL == 2) {
+        // two vertices: optimal distance (initial layout, Section 3.1)
+        float hx[4];
+        HIPCHK(hipMemcpyAsync(hx, xa.p, sizeof(hx), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const std::vector<int32_t>& cc = levels[Lmax]->c_host;
+        const double c0 = cc.empty() ? 1.0 : cc[0], c1 = cc.empty() ? 1.0 : cc[1];
+        const double d = Lmax == 0 ? 1.0 : (std::sqrt(c0) + std::sqrt(c1)) * p->coarse_dist_scale;
+        double dx = (double)hx[2] - hx[0], dy = (double)hx[3] - hx[1];
+        double D = std::sqrt(dx * dx + dy * dy);
+        if (D == 0.0) { dx = 1.0; dy = 0.0; D = 1.0; }
+        hx[2] = (float)(hx[0] + d * dx / D);
+        hx[3] = (float)(hx[1] + d * dy / D);
+        HIPCHK(hipMemcpyAsync(xa.p, hx, sizeof(hx), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+    }
+    HIPCHK(d2.alloc(2 * sizeof(double), s));
+
+    // ---- level loop (Section 3.2)
+    for (int32_t lvl = Lmax; lvl >= 0; --lvl) {
+      mm::GraphDev& G = levels[lvl]->g;
+      const int32_t nl = G.n;
+      if (lvl < Lmax) {
+        HIPCHK(xb.alloc(sizeof(float) * 2 * (size_t)nl, s));
+        HIPCHK(mm::prolong(nl, clusters[lvl].as<int32_t>(), levels[lvl + 1]->g.c, xa.as<float>(),
+                           p->seed, lvl, xb.as<float>(), s));
+        std::swap(xa, xb);
+      }
+      HIPCHK(xb.alloc(sizeof(float) * 2 * (size_t)nl, s));
+      HIPCHK(F.alloc(sizeof(float) * 2 * (size_t)nl, s));
+      auto tk = std::chrono::steady_clock::now();
+      mm::KhopDev kh;
+      HIPCHK(mm::khop_build(nl, G.row_ptr, G.col, p->k, &kh, s));
+      HIPCHK(hipStreamSynchronize(s));
+      t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
+      mm::DevBuf sq;
+      const float* sqrtc = nullptr;
+      if (lvl > 0) {
+        HIPCHK(make_sqrtc(nl, G.c, sq, s));
+        sqrtc = sq.as<float>();
+      }
+      int32_t iters = 0, final_iters = 0, cap_hit = 0;
+      double delta = 0;
+      auto iterate = [&](double alpha) -> mm_status {
+        HIPCHK(hipEventRecord(ctx->ev[0], s));
+        if (p->theta < 0) {
+          HIPCHK(mm::farfield_exact(nl, xa.as<float>(), p->q, F.as<float>(), s));
+        } else {
+          HIPCHK(mm::farfield_bh(ctx->bh, nl, xa.as<float>(), p->q, p->theta, F.as<float>(), nullptr,
+                                 nullptr, nullptr, nullptr, 0, nullptr, s));
+        }
+        HIPCHK(hipEventRecord(ctx->ev[1], s));
+        HIPCHK(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa.as<float>(), F.as<float>(), alpha,
+                         p->q, xb.as<float>(), d2.as<double>(), s));
+        HIPCHK(hipEventRecord(ctx->ev[2], s));
+        HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float a = 0, b = 0;
+        HIPCHK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+        HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+        t_far += a;
+        t_sweep += b;
+        delta = ctx->pinned[1] > 0 ? std::sqrt(ctx->pinned[0] / ctx->pinned[1]) : INFINITY;
+        if (!std::isfinite(delta)) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
+        std::swap(xa, xb);
+        iters++;
+        return MM_OK;
+      };
+      double alpha = init_xy ? p->alpha_min : p->alpha0;
+      while (alpha > p->alpha_min) {
+        for (int32_t it = 0; it < p->iters_per_round; ++it) {
+          STCHK(iterate(alpha));
+          if (delta < p->eps_round) break;
+        }
+        alpha = std::max(alpha * p->alpha_decay, p->alpha_min);
+      }
+      for (int32_t it = 0; it < p->max_final_iters; ++it) {
+        STCHK(iterate(p->alpha_min));
+        final_iters++;
+        if (delta < p->eps_final) break;
+        if (it == p->max_final_iters - 1) cap_hit = 1;
+      }
+      if (lvl < MM_MAX_LEVELS) {
+        st.level_n[lvl] = nl;
+        st.level_nnz[lvl] = G.nnz;
+        st.level_khop[lvl] = kh.total;
+        st.level_iters[lvl] = iters;
+        st.level_final_iters[lvl] = final_iters;
+        st.level_cap_hit[lvl] = cap_hit;
+        st.level_delta[lvl] = delta;
+      }
+      st.vertex_updates += (int64_t)nl * iters;
+      if (lvl == 0) st.finest_updates = (int64_t)nl * iters;
+    }
+    HIPCHK(hipMemcpyAsync(out_xy, xa.p, sizeof(float) * 2 * (size_t)n,
+                          g->mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    st.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    st.t_coarsen_ms = t_coarsen;
+    st.t_khop_ms = t_khop;
+    st.t_farfield_ms = t_far;
+    st.t_sweep_ms = t_sweep;
+    st.t_other_ms = st.t_total_ms - t_coarsen - t_khop - t_far - t_sweep;
+    if (stats) *stats = st;
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_layout");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,362 @@
+// Coarsening (Section 3.1): size-constrained label propagation and
+// contraction, in a synchronous two-colour form with a fixed tie-break so the
+// result is a function of (graph, U, seed, level) only.
+//
+// Per round r and colour s: v is active iff bit 0 of SplitMix64 draw
+// (seed, level, tag 16 + r, v) equals s.  Cluster weights W are frozen at the
+// start of the sub-round.  An active v scores each neighbouring label by the
+// summed edge weight; a label is feasible iff it is v's own or
+// W(L) + c(v) <= U; the best feasible label has the highest score, ties going
+// to v's own label, then to the smallest id; foreign labels of score 0 never
+// win.  Proposals to L are admitted in ascending v while W(L) plus the running
+// sum of c over proposals to L stays <= U.  Every quantity is an integer, so
+// the GPU result equals the sequential definition bit for bit.
+//
+// Scoring uses one wavefront per active vertex with an open-addressing hash
+// table (label -> score) in LDS for degree <= 128, in global memory otherwise.
+// Admission: proposals compacted in v order, stably radix-sorted by target,
+// then an int64 prefix sum of c gives every proposal its running sum.
+// Contraction: labels are ranked, cut edges keyed (C(u), C(v)) and radix
+// sorted, equal keys merged with prefix sums of w (exact integer sums).
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace {
+
+constexpr int LP_WAVES = 4;
+constexpr int LP_SLOTS = 256;  // LDS hash slots per wave (degree <= 128)
+constexpr int LP_SMALL = 128;
+
+__global__ void k_weights(int32_t n, const int32_t* __restrict__ label, const int32_t* __restrict__ c,
+                          unsigned long long* __restrict__ W) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicAdd(&W[label[v]], (unsigned long long)(c ? c[v] : 1));
+}
+
+struct Cand {
+  long long sc;
+  int32_t lab;
+  int32_t own;
+};
+__device__ inline bool better(const Cand& a, const Cand& b) {
+  if (a.sc != b.sc) return a.sc > b.sc;
+  if (a.own != b.own) return a.own > b.own;
+  return a.lab < b.lab;
+}
+__device__ inline Cand wave_best(Cand c) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Cand d;
+    d.sc = __shfl_xor(c.sc, o, 64);
+    d.lab = __shfl_xor(c.lab, o, 64);
+    d.own = __shfl_xor(c.own, o, 64);
+    if (better(d, c)) c = d;
+  }
+  return c;
+}
+__device__ inline uint32_t hslot(int32_t lab, uint32_t mask) {
+  return ((uint32_t)lab * 2654435761u) & mask;
+}
+
+// big: nonzero => use global tables; gkeys/gsc sized by hoff (per-vertex table offsets).
+__global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
+    int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ c, const int32_t* __restrict__ ew, const int32_t* __restrict__ label,
+    const unsigned long long* __restrict__ W, double U, uint64_t stream, int colour,
+    int32_t* __restrict__ prop, const int64_t* __restrict__ hoff, int32_t* __restrict__ gkeys,
+    long long* __restrict__ gsc) {
+  __shared__ int32_t skey[LP_WAVES][LP_SLOTS];
+  __shared__ long long ssc[LP_WAVES][LP_SLOTS];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t v = blockIdx.x * LP_WAVES + w;
+  if (v >= n) return;
+  const bool active = (int)(sm64_at(stream, (uint64_t)v) & 1ull) == colour;
+  if (!active) { if (l == 0) prop[v] = -1; return; }
+  const int32_t beg = rp[v], deg = rp[v + 1] - beg;
+  const int32_t own = label[v];
+  const long long cv = c ? c[v] : 1;
+  int32_t* keys;
+  long long* sc;
+  uint32_t mask;
+  if (deg <= LP_SMALL) {
+    keys = skey[w]; sc = ssc[w]; mask = LP_SLOTS - 1;
+  } else {
+    keys = gkeys + hoff[v]; sc = gsc + hoff[v];
+    mask = (uint32_t)(hoff[v + 1] - hoff[v]) - 1u;
+  }
+  for (uint32_t i = l; i <= mask; i += 64) { keys[i] = -1; sc[i] = 0; }
+  __threadfence();
+  __builtin_amdgcn_wave_barrier();
+  for (int32_t e = l; e < deg; e += 64) {
+    const int32_t lab = label[col[beg + e]];
+    const long long wt = ew ? ew[beg + e] : 1;
+    uint32_t s = hslot(lab, mask);
+    for (;;) {
+      int32_t prev = atomicCAS(&keys[s], -1, lab);
+      if (prev == -1 || prev == lab) break;
+      s = (s + 1) & mask;
+    }
+    atomicAdd((unsigned long long*)&sc[s], (unsigned long long)wt);
+  }
+  __threadfence();
+  __builtin_amdgcn_wave_barrier();
+  Cand best;
+  best.sc = -1; best.lab = 0x7fffffff; best.own = 0;
+  for (uint32_t i = l; i <= mask; i += 64) {
+    const int32_t lab = keys[i];
+    if (lab < 0) continue;
+    Cand cd;
+    cd.sc = sc[i];
+    cd.lab = lab;
+    cd.own = (lab == own);
+    if (!cd.own) {
+      if (cd.sc <= 0) continue;
+      if ((double)((long long)W[lab] + cv) > U) continue;  // infeasible
+    }
+    if (better(cd, best)) best = cd;
+  }
+  // own label always competes (score 0 when no neighbour carries it)
+  if (l == 0) {
+    Cand o; o.sc = 0; o.lab = own; o.own = 1;
+    if (better(o, best)) best = o;
+  }
+  best = wave_best(best);
+  if (l == 0) prop[v] = (best.lab != own) ? best.lab : -1;
+}
+
+__global__ void k_prop_flags(int32_t n, const int32_t* __restrict__ prop, int32_t* __restrict__ flag) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = prop[v] >= 0 ? 1 : 0;
+}
+__global__ void k_prop_compact(int32_t n, const int32_t* __restrict__ prop,
+                               const int64_t* __restrict__ pos, uint64_t* __restrict__ keys,
+                               int32_t* __restrict__ vals) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && prop[v] >= 0) {
+    keys[pos[v]] = (uint64_t)prop[v];
+    vals[pos[v]] = v;
+  }
+}
+__global__ void k_gather_c(int64_t m, const int32_t* __restrict__ vals, const int32_t* __restrict__ c,
+                           int32_t* __restrict__ cs) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) cs[j] = c ? c[vals[j]] : 1;
+}
+__global__ void k_admit(int64_t m, const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
+                        const int64_t* __restrict__ csum, const unsigned long long* __restrict__ W,
+                        double U, int32_t* __restrict__ label, int32_t* __restrict__ moves) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint64_t L = keys[j];
+  int64_t lo = 0, hi = j;  // first index with key == L
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < L) lo = mid + 1; else hi = mid;
+  }
+  const long long run = csum[j + 1] - csum[lo];
+  if ((double)((long long)W[L] + run) <= U) {
+    label[vals[j]] = (int32_t)L;
+    atomicAdd(moves, 1);
+  }
+}
+
+__global__ void k_hash_sizes(int32_t n, const int32_t* __restrict__ rp, int64_t* __restrict__ sz) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t d = rp[v + 1] - rp[v];
+  int64_t s = 0;
+  if (d > LP_SMALL) { s = 1; while (s < 2 * (int64_t)d) s <<= 1; }
+  sz[v] = s;
+}
+
+// ---- contraction
+__global__ void k_mark(int32_t n, const int32_t* __restrict__ label, int32_t* __restrict__ present) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) present[label[v]] = 1;
+}
+__global__ void k_cluster(int32_t n, const int32_t* __restrict__ label, const int64_t* __restrict__ rank,
+                          const int32_t* __restrict__ c, int32_t* __restrict__ cluster,
+                          int32_t* __restrict__ cc) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t C = (int32_t)rank[label[v]];
+  cluster[v] = C;
+  atomicAdd(&cc[C], c ? c[v] : 1);
+}
+__global__ void k_cut_flags(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ cluster, int32_t* __restrict__ flag) {
+  int32_t v = blockIdx.x;
+  const int32_t cv = cluster[v];
+  for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += blockDim.x)
+    flag[e] = cluster[col[e]] != cv ? 1 : 0;
+}
+__global__ void k_cut_emit(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const int32_t* __restrict__ ew, const int32_t* __restrict__ cluster,
+                           const int64_t* __restrict__ pos, int64_t nc, uint64_t* __restrict__ keys,
+                           int32_t* __restrict__ vals) {
+  int32_t v = blockIdx.x;
+  const int32_t cv = cluster[v];
+  for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += blockDim.x) {
+    const int32_t cu = cluster[col[e]];
+    if (cu != cv) {
+      keys[pos[e]] = (uint64_t)cv * (uint64_t)nc + (uint64_t)cu;
+      vals[pos[e]] = ew ? ew[e] : 1;
+    }
+  }
+}
+__global__ void k_heads(int64_t m, const uint64_t* __restrict__ keys, int32_t* __restrict__ head) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) head[j] = (j == 0 || keys[j - 1] != keys[j]) ? 1 : 0;
+}
+__global__ void k_coarse_edges(int64_t m, const uint64_t* __restrict__ keys,
+                               const int32_t* __restrict__ head, const int64_t* __restrict__ hpos,
+                               const int64_t* __restrict__ wsum, int64_t nc,
+                               int32_t* __restrict__ ccol, int32_t* __restrict__ cw,
+                               int32_t* __restrict__ rowcnt) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m || !head[j]) return;
+  const uint64_t K = keys[j];
+  int64_t lo = j + 1, hi = m;  // end of run
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] <= K) lo = mid + 1; else hi = mid;
+  }
+  const int64_t q = hpos[j];
+  ccol[q] = (int32_t)(K % (uint64_t)nc);
+  cw[q] = (int32_t)(wsum[lo] - wsum[j]);
+  atomicAdd(&rowcnt[(int32_t)(K / (uint64_t)nc)], 1);
+}
+__global__ void k_i64_to_i32(int64_t n, const int64_t* __restrict__ a, int32_t* __restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed, int32_t level_h,
+                      int32_t* label, int32_t* rounds_run, int64_t* moves_host, hipStream_t s) {
+  const int32_t n = g.n;
+  DevBuf W, prop, flag, pos, keys, vals, cs, csum, moves, hsz, hoff, gk, gsc;
+  MM_TRY(W.alloc(sizeof(unsigned long long) * (size_t)n, s));
+  MM_TRY(prop.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(pos.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  MM_TRY(keys.alloc(sizeof(uint64_t) * (size_t)n, s));
+  MM_TRY(vals.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(cs.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(csum.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  MM_TRY(moves.alloc(sizeof(int32_t) * 2, s));
+  MM_TRY(hsz.alloc(sizeof(int64_t) * (size_t)n, s));
+  MM_TRY(hoff.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  k_hash_sizes<<<nblk(n), 256, 0, s>>>(n, g.row_ptr, hsz.as<int64_t>());
+  MM_TRY(scan_excl_i64(hsz.as<int64_t>(), hoff.as<int64_t>(), n, s));
+  int64_t hslots = 0;
+  MM_TRY(hipMemcpyAsync(&hslots, hoff.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  MM_TRY(gk.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(hslots, 1), s));
+  MM_TRY(gsc.alloc(sizeof(long long) * (size_t)std::max<int64_t>(hslots, 1), s));
+  MM_TRY(iota_i32(label, n, s));
+  int lbits = 1;
+  while ((1ll << lbits) < (int64_t)n) lbits++;
+  int32_t r_done = 0;
+  for (int32_t r = 0; r < rounds; ++r) {
+    const uint64_t st = rng_stream(seed, (uint32_t)level_h, TAG_LP + (uint32_t)r);
+    MM_TRY(hipMemsetAsync(moves.p, 0, sizeof(int32_t), s));
+    for (int colour = 0; colour < 2; ++colour) {
+      MM_TRY(hipMemsetAsync(W.p, 0, sizeof(unsigned long long) * (size_t)n, s));
+      k_weights<<<nblk(n), 256, 0, s>>>(n, label, g.c, W.as<unsigned long long>());
+      k_lp_propose<<<nblk(n, LP_WAVES), 64 * LP_WAVES, 0, s>>>(
+          n, g.row_ptr, g.col, g.c, g.w, label, W.as<unsigned long long>(), U, st, colour,
+          prop.as<int32_t>(), hoff.as<int64_t>(), gk.as<int32_t>(), gsc.as<long long>());
+      k_prop_flags<<<nblk(n), 256, 0, s>>>(n, prop.as<int32_t>(), flag.as<int32_t>());
+      MM_TRY(scan_excl_i32(flag.as<int32_t>(), pos.as<int64_t>(), n, s));
+      int64_t m = 0;
+      MM_TRY(hipMemcpyAsync(&m, pos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      MM_TRY(hipStreamSynchronize(s));
+      if (m == 0) continue;
+      k_prop_compact<<<nblk(n), 256, 0, s>>>(n, prop.as<int32_t>(), pos.as<int64_t>(),
+                                             keys.as<uint64_t>(), vals.as<int32_t>());
+      MM_TRY(radix_sort_pairs(keys.as<uint64_t>(), vals.as<int32_t>(), m, lbits, s));
+      k_gather_c<<<nblk(m), 256, 0, s>>>(m, vals.as<int32_t>(), g.c, cs.as<int32_t>());
+      MM_TRY(scan_excl_i32(cs.as<int32_t>(), csum.as<int64_t>(), m, s));
+      k_admit<<<nblk(m), 256, 0, s>>>(m, keys.as<uint64_t>(), vals.as<int32_t>(), csum.as<int64_t>(),
+                                      W.as<unsigned long long>(), U, label, moves.as<int32_t>());
+      MM_TRY(hipGetLastError());
+    }
+    int32_t mv = 0;
+    MM_TRY(hipMemcpyAsync(&mv, moves.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_TRY(hipStreamSynchronize(s));
+    if (moves_host) moves_host[r] = mv;
+    r_done = r + 1;
+    if (mv == 0) break;
+  }
+  *rounds_run = r_done;
+  return hipGetLastError();
+}
+
+hipError_t contract(const GraphDev& g, const int32_t* label, int32_t* cluster, GraphDev* out,
+                    hipStream_t s) {
+  const int32_t n = g.n;
+  const int64_t nnz = g.nnz;
+  DevBuf present, rank, flag, pos, keys, vals, head, hpos, wsum, rowcnt, rp64;
+  MM_TRY(present.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(rank.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  MM_TRY(hipMemsetAsync(present.p, 0, sizeof(int32_t) * (size_t)n, s));
+  k_mark<<<nblk(n), 256, 0, s>>>(n, label, present.as<int32_t>());
+  MM_TRY(scan_excl_i32(present.as<int32_t>(), rank.as<int64_t>(), n, s));
+  int64_t nc = 0;
+  MM_TRY(hipMemcpyAsync(&nc, rank.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  out->n = (int32_t)nc;
+  MM_TRY(out->b_c.alloc(sizeof(int32_t) * (size_t)nc, s));
+  out->c = out->b_c.as<int32_t>();
+  MM_TRY(hipMemsetAsync(out->c, 0, sizeof(int32_t) * (size_t)nc, s));
+  k_cluster<<<nblk(n), 256, 0, s>>>(n, label, rank.as<int64_t>(), g.c, cluster, out->c);
+  MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), s));
+  MM_TRY(pos.alloc(sizeof(int64_t) * (size_t)(nnz + 1), s));
+  k_cut_flags<<<n, 128, 0, s>>>(n, g.row_ptr, g.col, cluster, flag.as<int32_t>());
+  MM_TRY(scan_excl_i32(flag.as<int32_t>(), pos.as<int64_t>(), nnz, s));
+  int64_t m = 0;
+  MM_TRY(hipMemcpyAsync(&m, pos.as<int64_t>() + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  MM_TRY(keys.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1), s));
+  MM_TRY(vals.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1), s));
+  k_cut_emit<<<n, 128, 0, s>>>(n, g.row_ptr, g.col, g.w, cluster, pos.as<int64_t>(), nc,
+                               keys.as<uint64_t>(), vals.as<int32_t>());
+  MM_TRY(hipGetLastError());
+  int kb = 1;
+  while ((1ull << kb) < (uint64_t)nc * (uint64_t)nc) kb++;
+  MM_TRY(radix_sort_pairs(keys.as<uint64_t>(), vals.as<int32_t>(), m, kb, s));
+  MM_TRY(head.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1), s));
+  MM_TRY(hpos.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  MM_TRY(wsum.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  k_heads<<<nblk(m), 256, 0, s>>>(m, keys.as<uint64_t>(), head.as<int32_t>());
+  MM_TRY(scan_excl_i32(head.as<int32_t>(), hpos.as<int64_t>(), m, s));
+  MM_TRY(scan_excl_i32(vals.as<int32_t>(), wsum.as<int64_t>(), m, s));
+  int64_t cnnz = 0;
+  MM_TRY(hipMemcpyAsync(&cnnz, hpos.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  out->nnz = cnnz;
+  MM_TRY(out->b_col.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(cnnz, 1), s));
+  MM_TRY(out->b_w.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(cnnz, 1), s));
+  MM_TRY(out->b_rp.alloc(sizeof(int32_t) * (size_t)(nc + 1), s));
+  out->col = out->b_col.as<int32_t>();
+  out->w = out->b_w.as<int32_t>();
+  out->row_ptr = out->b_rp.as<int32_t>();
+  MM_TRY(rowcnt.alloc(sizeof(int32_t) * (size_t)nc, s));
+  MM_TRY(hipMemsetAsync(rowcnt.p, 0, sizeof(int32_t) * (size_t)nc, s));
+  k_coarse_edges<<<nblk(m), 256, 0, s>>>(m, keys.as<uint64_t>(), head.as<int32_t>(),
+                                         hpos.as<int64_t>(), wsum.as<int64_t>(), nc, out->col,
+                                         out->w, rowcnt.as<int32_t>());
+  MM_TRY(rp64.alloc(sizeof(int64_t) * (size_t)(nc + 1), s));
+  MM_TRY(scan_excl_i32(rowcnt.as<int32_t>(), rp64.as<int64_t>(), nc, s));
+  k_i64_to_i32<<<nblk(nc + 1), 256, 0, s>>>(nc + 1, rp64.as<int64_t>(), out->row_ptr);
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -1,0 +1,502 @@
+// Far field of Eq. 2: F_u = sum_{v != u} r_q(u, v), r_q = (x_u - x_v)/|x_u - x_v|^(q+2).
+//
+// Exact mode: LDS-tiled all-pairs sum (one thread per target, sources staged
+// through LDS in ascending order).
+//
+// Barnes-Hut mode (the quadtree approximation the paper cites for long-range
+// forces):
+//  1. bounding box -> square box with power-of-two side 2^e, origin (xmin, ymin);
+//     cell index floor((x - xmin) * 2^(24-e)) in FP64, clamped to 24 bits;
+//     48-bit Morton code (x bits even, y bits odd);
+//  2. stable radix sort of (code, id);
+//  3. compressed quadtree from the sorted codes: every adjacent pair with
+//     different codes splits at depth floor(lcp/2); the leftmost such pair of
+//     a cell owns the internal node; runs of equal codes are leaves.  Nodes
+//     are sorted into pre-order by (first point, depth); each node stores a
+//     skip index (next node after its subtree), so traversal is stackless;
+//  4. moments: mass = point count, centre of mass from FP64 prefix sums of the
+//     sorted coordinates (exact to FP64 rounding, independent of tree shape);
+//  5. traversal: one wavefront walks the pre-order array for 64 targets that
+//     are consecutive in Morton order.  Each lane keeps its own next-node
+//     index; the wave visits the smallest one, so every node record is a
+//     wave-uniform load.  Lanes that accept a cell or finish a leaf jump to its
+//     skip index, which masks them for the whole subtree: each lane sees
+//     exactly the nodes its own depth-first traversal would, in the same
+//     order.  The opening test is exact integer geometry evaluated in FP64:
+//     accept cell C (not containing u) iff
+//       theta^2 * |(2 iu + 1) - (2 o_C + S_C)|^2 > 4 S_C^2.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+
+// Pre-order node record.  The centre of mass stays in FP64: rounding it to
+// FP32 would add an absolute error of half an ulp of |x|, which dominates the
+// offset to nearby targets in dense regions.
+struct BHNode {
+  double cx, cy;
+  float mass;
+  int32_t skip;
+  uint32_t ox, oy;
+  int32_t meta;   // depth | leaf << 8
+  int32_t first;  // first point (sorted order)
+};
+
+struct BoxInfo {
+  double xmin, ymin, scale;
+  int32_t e;
+  int32_t pad;
+};
+
+struct BHWork {
+  int32_t cap = 0;
+  DevBuf codes, order, xsx, xsy, ix, px, py, nkeys, nvals, ntmp, first_at, nodes, counter, box,
+      partial, statc;
+};
+
+BHWork* bh_work_create() { return new BHWork(); }
+void bh_work_destroy(BHWork* w) { delete w; }
+
+namespace {
+
+constexpr int BB_T = 256;
+
+__global__ __launch_bounds__(BB_T) void k_bbox_partial(const float2* __restrict__ xy, int32_t n,
+                                                       float4* __restrict__ part) {
+  float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+  for (int32_t i = blockIdx.x * BB_T + threadIdx.x; i < n; i += gridDim.x * BB_T) {
+    float2 p = xy[i];
+    xmin = fminf(xmin, p.x); xmax = fmaxf(xmax, p.x);
+    ymin = fminf(ymin, p.y); ymax = fmaxf(ymax, p.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    xmin = fminf(xmin, __shfl_xor(xmin, o, 64)); xmax = fmaxf(xmax, __shfl_xor(xmax, o, 64));
+    ymin = fminf(ymin, __shfl_xor(ymin, o, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, o, 64));
+  }
+  __shared__ float4 sh[BB_T / 64];
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = make_float4(xmin, ymin, xmax, ymax);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float4 r = sh[0];
+    for (int i = 1; i < BB_T / 64; ++i) {
+      r.x = fminf(r.x, sh[i].x); r.y = fminf(r.y, sh[i].y);
+      r.z = fmaxf(r.z, sh[i].z); r.w = fmaxf(r.w, sh[i].w);
+    }
+    part[blockIdx.x] = r;
+  }
+}
+
+__global__ void k_bbox_final(const float4* __restrict__ part, int nb, BoxInfo* box) {
+  if (threadIdx.x != 0) return;
+  float4 r = part[0];
+  for (int i = 1; i < nb; ++i) {
+    r.x = fminf(r.x, part[i].x); r.y = fminf(r.y, part[i].y);
+    r.z = fmaxf(r.z, part[i].z); r.w = fmaxf(r.w, part[i].w);
+  }
+  double xmin = r.x, ymin = r.y;
+  double ext = fmax((double)r.z - xmin, (double)r.w - ymin);
+  int e = 0;
+  if (ext > 0.0) {
+    int ex;
+    double m = frexp(ext, &ex);
+    e = (m == 0.5) ? ex - 1 : ex;
+  }
+  box->xmin = xmin;
+  box->ymin = ymin;
+  box->scale = ldexp(1.0, 24 - e);
+  box->e = e;
+}
+
+__device__ inline uint64_t spread24(uint32_t v) {
+  uint64_t x = v & 0xFFFFFFull;
+  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+__device__ inline uint32_t compact24(uint64_t x) {
+  x &= 0x5555555555555555ull;
+  x = (x | (x >> 1)) & 0x3333333333333333ull;
+  x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+  return (uint32_t)x & 0xFFFFFFu;
+}
+
+__global__ void k_morton(const float2* __restrict__ xy, int32_t n, const BoxInfo* __restrict__ box,
+                         uint64_t* __restrict__ codes, int32_t* __restrict__ ids) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BoxInfo b = *box;
+  float2 p = xy[i];
+  double fx = floor(((double)p.x - b.xmin) * b.scale);
+  double fy = floor(((double)p.y - b.ymin) * b.scale);
+  fx = fmin(fmax(fx, 0.0), 16777215.0);
+  fy = fmin(fmax(fy, 0.0), 16777215.0);
+  codes[i] = spread24((uint32_t)fx) | (spread24((uint32_t)fy) << 1);
+  ids[i] = i;
+}
+
+__global__ void k_gather_sorted(const float2* __restrict__ xy, const int32_t* __restrict__ order,
+                                const uint64_t* __restrict__ codes, int32_t n,
+                                float* __restrict__ xsx, float* __restrict__ xsy,
+                                uint2* __restrict__ ixy) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float2 p = xy[order[i]];
+  xsx[i] = p.x;
+  xsy[i] = p.y;
+  uint64_t c = codes[i];
+  ixy[i] = make_uint2(compact24(c), compact24(c >> 1));
+}
+
+// Inclusive-exclusive FP64 prefix sums of a float array (fixed tiles).
+constexpr int PS_T = 256, PS_I = 8, PS_TILE = PS_T * PS_I;
+__global__ __launch_bounds__(PS_T) void k_fsum_tiles(const float* __restrict__ a, int32_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[PS_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
+  double s = 0.0;
+  for (int i = 0; i < PS_I; ++i) if (base + i < n) s += (double)a[base + i];
+  double tot;
+  block_excl_scan<double>(s, sh, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(1024) void k_fsum_parts(double* part, int32_t m) {
+  __shared__ double sh[1024 / 64 + 1];
+  double carry = 0.0;
+  for (int32_t b = 0; b < m; b += blockDim.x) {
+    int32_t j = b + threadIdx.x;
+    double v = j < m ? part[j] : 0.0;
+    double tot;
+    double ex = block_excl_scan<double>(v, sh, &tot);
+    if (j < m) part[j] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[m] = carry;
+}
+__global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ a, int32_t n,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[PS_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
+  double v[PS_I], s = 0.0;
+  for (int i = 0; i < PS_I; ++i) { v[i] = base + i < n ? (double)a[base + i] : 0.0; s += v[i]; }
+  double tot;
+  double ex = block_excl_scan<double>(s, sh, &tot) + part[blockIdx.x];
+  for (int i = 0; i < PS_I; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+}
+
+__device__ inline int lcp48(uint64_t a, uint64_t b) {
+  uint64_t x = (a ^ b) << 16;  // codes live in the low 48 bits
+  return x == 0 ? 48 : __clzll(x);
+}
+
+// Emit nodes: leaves at bucket starts, internal nodes at owner pairs.
+// key = first << 5 | depth (leaves use depth code 31); val = temp index.
+__global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
+                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                             int4* __restrict__ tmp, int32_t* __restrict__ counter) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t ci = codes[i];
+  if (i == 0 || codes[i - 1] != ci) {
+    // leaf: run of equal codes starting at i
+    int32_t lo = i, hi = n;  // first index with code > ci
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if (codes[mid] <= ci) lo = mid + 1; else hi = mid;
+    }
+    int32_t slot = atomicAdd(counter, 1);
+    keys[slot] = ((uint64_t)i << 5) | 31u;
+    vals[slot] = slot;
+    tmp[slot] = make_int4(i, lo - 1, 24, 1);
+  }
+  if (i + 1 < n && codes[i + 1] != ci) {
+    const int t = lcp48(ci, codes[i + 1]) >> 1;
+    const int sh = 48 - 2 * t;
+    const uint64_t pre = ci >> sh;
+    // a: first index with the same 2t-bit prefix
+    int32_t lo = 0, hi = i;
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if ((codes[mid] >> sh) < pre) lo = mid + 1; else hi = mid;
+    }
+    const int32_t a = lo;
+    // owner iff points a..i lie in the same child (no split of depth t left of i)
+    if ((codes[a] >> (sh - 2)) == (ci >> (sh - 2))) {
+      lo = i + 1; hi = n;
+      while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if ((codes[mid] >> sh) <= pre) lo = mid + 1; else hi = mid;
+      }
+      int32_t slot = atomicAdd(counter, 1);
+      keys[slot] = ((uint64_t)a << 5) | (uint32_t)t;
+      vals[slot] = slot;
+      tmp[slot] = make_int4(a, lo - 1, t, 0);
+    }
+  }
+}
+
+__global__ void k_first_at(const uint64_t* __restrict__ keys, int32_t N, int32_t* __restrict__ first_at) {
+  int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  int32_t f = (int32_t)(keys[p] >> 5);
+  if (p == 0 || (int32_t)(keys[p - 1] >> 5) != f) first_at[f] = p;
+}
+
+__global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* __restrict__ tmp,
+                                 int32_t N, int32_t n, const int32_t* __restrict__ first_at,
+                                 const double* __restrict__ px, const double* __restrict__ py,
+                                 const uint2* __restrict__ ixy, BHNode* __restrict__ nodes,
+                                 int64_t* __restrict__ export_nodes,
+                                 const uint64_t* __restrict__ codes) {
+  int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  int4 t = tmp[vals[p]];
+  const int32_t first = t.x, last = t.y, depth = t.z, leaf = t.w;
+  const int32_t cnt = last - first + 1;
+  BHNode nd;
+  nd.cx = (px[last + 1] - px[first]) / (double)cnt;
+  nd.cy = (py[last + 1] - py[first]) / (double)cnt;
+  nd.mass = (float)cnt;
+  nd.skip = (last + 1 < n) ? first_at[last + 1] : N;
+  const uint32_t mask = depth >= 24 ? 0xFFFFFFu : ~((1u << (24 - depth)) - 1u) & 0xFFFFFFu;
+  uint2 q = ixy[first];
+  nd.ox = q.x & mask;
+  nd.oy = q.y & mask;
+  nd.meta = depth | (leaf << 8);
+  nd.first = first;
+  nodes[p] = nd;
+  if (export_nodes) {
+    int64_t* o = export_nodes + 5 * (int64_t)p;
+    o[0] = depth; o[1] = first; o[2] = cnt; o[3] = leaf;
+    o[4] = (int64_t)(codes[first] >> (2 * (24 - depth)));
+  }
+}
+
+// Adds m * r_q for the offset (dx, dy); coincident points add nothing.
+__device__ inline bool rq_add(float dx, float dy, float q, float m, float& fx, float& fy) {
+  float d2 = dx * dx + dy * dy;
+  if (d2 > 0.f) {
+    float f = (q == 0.f) ? __builtin_amdgcn_rcpf(d2) : powf(d2, -0.5f * (q + 2.f));
+    f *= m;
+    fx += dx * f;
+    fy += dy * f;
+    return true;
+  }
+  return false;
+}
+
+constexpr int TR_WAVES = 4;
+
+template <bool STATS>
+__global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
+    const BHNode* __restrict__ nodes, int32_t N, const float* __restrict__ xsx,
+    const float* __restrict__ xsy, const uint2* __restrict__ ixy, const int32_t* __restrict__ order,
+    int32_t n, float q, double theta2, float2* __restrict__ F, unsigned long long* __restrict__ stats) {
+  const int l = lane_id();
+  const int32_t i = (blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 + l;
+  if ((blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 >= n) return;
+  const bool valid = i < n;
+  const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
+  const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
+  const double qx2 = 2.0 * (double)qt.x + 1.0, qy2 = 2.0 * (double)qt.y + 1.0;
+  float fx = 0.f, fy = 0.f;
+  int32_t next = valid ? 0 : 0x7fffffff;
+  unsigned long long acc = 0, pairs = 0;
+  int32_t p = 0;
+  while (p < N) {
+    p = __builtin_amdgcn_readfirstlane(p);
+    const BHNode nd = nodes[p];
+    const bool act = (next == p);
+    const int depth = nd.meta & 0xff;
+    if (nd.meta >> 8) {
+      // leaf: exact terms for its points
+      const int32_t cnt = (int32_t)nd.mass;
+      for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
+        const float sx = xsx[j], sy = xsy[j];
+        if (act && j != i) {
+          const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
+          if (STATS && added) pairs++;
+        }
+      }
+      if (act) next = nd.skip;
+      p = wave_min(next);
+    } else {
+      bool opened = false;
+      if (act) {
+        const int sh = 24 - depth;
+        const bool contains = ((qt.x >> sh) == (nd.ox >> sh)) && ((qt.y >> sh) == (nd.oy >> sh));
+        bool accept = false;
+        if (!contains) {
+          const double S = (double)(1u << sh);
+          const double dx = qx2 - (2.0 * (double)nd.ox + S);
+          const double dy = qy2 - (2.0 * (double)nd.oy + S);
+          const double d4 = dx * dx + dy * dy;
+          accept = theta2 * d4 > 4.0 * S * S;
+        }
+        if (accept) {
+          rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, nd.mass, fx, fy);
+          if (STATS) acc++;
+          next = nd.skip;
+        } else {
+          next = p + 1;
+          opened = true;
+        }
+      }
+      if (__any(opened)) p = p + 1;
+      else p = wave_min(next);
+    }
+  }
+  if (valid) F[order[i]] = make_float2(fx, fy);
+  if (STATS) {
+    acc = wave_sum(acc);
+    pairs = wave_sum(pairs);
+    if (l == 0) { atomicAdd(&stats[0], acc); atomicAdd(&stats[1], pairs); }
+  }
+}
+
+// ---- exact all-pairs
+constexpr int EX_T = 256;
+__global__ __launch_bounds__(EX_T) void k_exact(const float2* __restrict__ xy, int32_t n, float q,
+                                                float2* __restrict__ F) {
+  __shared__ float2 tile[EX_T];
+  const int32_t u = blockIdx.x * EX_T + threadIdx.x;
+  const float2 xu = u < n ? xy[u] : make_float2(0.f, 0.f);
+  float fx = 0.f, fy = 0.f;
+  for (int32_t b = 0; b < n; b += EX_T) {
+    __syncthreads();
+    if (b + threadIdx.x < n) tile[threadIdx.x] = xy[b + threadIdx.x];
+    __syncthreads();
+    const int32_t m = min(EX_T, n - b);
+    for (int32_t j = 0; j < m; ++j) {
+      if (b + j == u) continue;
+      const float2 p = tile[j];
+      rq_add(xu.x - p.x, xu.y - p.y, q, 1.f, fx, fy);
+    }
+  }
+  if (u < n) F[u] = make_float2(fx, fy);
+}
+
+template <typename T>
+hipError_t ensure(DevBuf& b, size_t count, hipStream_t s) {
+  size_t need = sizeof(T) * (count ? count : 1);
+  if (b.bytes >= need) return hipSuccess;
+  return b.alloc(need, s);
+}
+
+}  // namespace
+
+hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStream_t s) {
+  k_exact<<<(n + EX_T - 1) / EX_T, EX_T, 0, s>>>((const float2*)xy, n, (float)q, (float2*)F);
+  return hipGetLastError();
+}
+
+hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
+                       uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
+                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s) {
+  const size_t N2 = 2 * (size_t)n;
+  MM_TRY(ensure<uint64_t>(w->codes, n, s));
+  MM_TRY(ensure<int32_t>(w->order, n, s));
+  MM_TRY(ensure<float>(w->xsx, n, s));
+  MM_TRY(ensure<float>(w->xsy, n, s));
+  MM_TRY(ensure<uint2>(w->ix, n, s));
+  MM_TRY(ensure<double>(w->px, n + 1, s));
+  MM_TRY(ensure<double>(w->py, n + 1, s));
+  MM_TRY(ensure<uint64_t>(w->nkeys, N2, s));
+  MM_TRY(ensure<int32_t>(w->nvals, N2, s));
+  MM_TRY(ensure<int4>(w->ntmp, N2, s));
+  MM_TRY(ensure<int32_t>(w->first_at, n, s));
+  MM_TRY(ensure<BHNode>(w->nodes, N2, s));
+  MM_TRY(ensure<int32_t>(w->counter, 1, s));
+  MM_TRY(ensure<BoxInfo>(w->box, 1, s));
+  const int nbb = std::min(1024, std::max(1, (n + BB_T - 1) / BB_T));
+  MM_TRY(ensure<float4>(w->partial, nbb, s));
+  const int32_t nps = (n + PS_TILE - 1) / PS_TILE;
+  DevBuf pparts;
+  MM_TRY(pparts.alloc(sizeof(double) * (size_t)(nps + 1), s));
+  MM_TRY(ensure<unsigned long long>(w->statc, 2, s));
+
+  k_bbox_partial<<<nbb, BB_T, 0, s>>>((const float2*)xy, n, w->partial.as<float4>());
+  k_bbox_final<<<1, 64, 0, s>>>(w->partial.as<float4>(), nbb, w->box.as<BoxInfo>());
+  k_morton<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(),
+                                           w->codes.as<uint64_t>(), w->order.as<int32_t>());
+  MM_TRY(hipGetLastError());
+  MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, 48, s));
+  k_gather_sorted<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, w->order.as<int32_t>(),
+                                                  w->codes.as<uint64_t>(), n, w->xsx.as<float>(),
+                                                  w->xsy.as<float>(), w->ix.as<uint2>());
+  // FP64 prefix sums of sorted coordinates
+  for (int c = 0; c < 2; ++c) {
+    const float* a = c == 0 ? w->xsx.as<float>() : w->xsy.as<float>();
+    double* out = c == 0 ? w->px.as<double>() : w->py.as<double>();
+    k_fsum_tiles<<<nps, PS_T, 0, s>>>(a, n, pparts.as<double>());
+    k_fsum_parts<<<1, 1024, 0, s>>>(pparts.as<double>(), nps);
+    k_fsum_scan<<<nps, PS_T, 0, s>>>(a, n, pparts.as<double>(), out);
+  }
+  MM_TRY(hipMemsetAsync(w->counter.p, 0, sizeof(int32_t), s));
+  k_emit_nodes<<<(n + 255) / 256, 256, 0, s>>>(w->codes.as<uint64_t>(), n, w->nkeys.as<uint64_t>(),
+                                               w->nvals.as<int32_t>(), w->ntmp.as<int4>(),
+                                               w->counter.as<int32_t>());
+  MM_TRY(hipGetLastError());
+  int32_t N = 0;
+  MM_TRY(hipMemcpyAsync(&N, w->counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  int kbits = 5;
+  while ((1ll << (kbits - 5)) < (int64_t)n) kbits++;
+  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), N, kbits, s));
+  k_first_at<<<(N + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), N, w->first_at.as<int32_t>());
+  k_finalize_nodes<<<(N + 255) / 256, 256, 0, s>>>(
+      w->nvals.as<int32_t>(), w->ntmp.as<int4>(), N, n, w->first_at.as<int32_t>(),
+      w->px.as<double>(), w->py.as<double>(), w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
+      w->codes.as<uint64_t>());
+  MM_TRY(hipGetLastError());
+  if (count_stats) MM_TRY(hipMemsetAsync(w->statc.p, 0, 2 * sizeof(unsigned long long), s));
+  const int32_t nw = (n + 63) / 64;
+  const int32_t nblk = (nw + TR_WAVES - 1) / TR_WAVES;
+  if (count_stats)
+    k_traverse<true><<<nblk, 64 * TR_WAVES, 0, s>>>(
+        w->nodes.as<BHNode>(), N, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
+        w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F,
+        w->statc.as<unsigned long long>());
+  else
+    k_traverse<false><<<nblk, 64 * TR_WAVES, 0, s>>>(
+        w->nodes.as<BHNode>(), N, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
+        w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F, nullptr);
+  MM_TRY(hipGetLastError());
+  if (codes_out) {
+    // codes in id order
+    DevBuf tmp;
+    MM_TRY(tmp.alloc(sizeof(uint64_t) * (size_t)n, s));
+    k_morton<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(),
+                                             codes_out, tmp.as<int32_t>());
+  }
+  if (order_out)
+    MM_TRY(hipMemcpyAsync(order_out, w->order.p, sizeof(int32_t) * (size_t)n,
+                          hipMemcpyDeviceToDevice, s));
+  if (n_nodes_out) *n_nodes_out = N;
+  if (st) {
+    st->nodes = N;
+    st->accepted = st->leaf_pairs = st->coincident = 0;
+    if (count_stats) {
+      unsigned long long h[2];
+      MM_TRY(hipMemcpyAsync(h, w->statc.p, sizeof(h), hipMemcpyDeviceToHost, s));
+      MM_TRY(hipStreamSynchronize(s));
+      st->accepted = (int64_t)h[0];
+      st->leaf_pairs = (int64_t)h[1];
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -1,0 +1,116 @@
+// Host-side launchers of the HIP kernels (internal to libmulment).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+// Stream-ordered temporary device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; s = o.s; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  hipError_t alloc(size_t b, hipStream_t st) {
+    release();
+    s = st;
+    bytes = b;
+    if (b == 0) return hipSuccess;
+    return hipMallocAsync(&p, b, st);
+  }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+#define MM_TRY(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return _e;                  \
+  } while (0)
+
+// ---- primitives (prims.hip)
+// out[0..n]: exclusive prefix sums of in (out[n] = total).
+hipError_t scan_excl_i32(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+// Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
+// Sorted result ends in keys/vals (the buffers are ping-ponged internally).
+hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
+hipError_t iota_i32(int32_t* out, int64_t n, hipStream_t s);
+
+// ---- k-hop distance sets (khop.hip)
+struct KhopDev {
+  int32_t n = 0, k = 0;
+  int64_t total = 0;
+  int64_t* off = nullptr;  // n+1
+  int32_t* hend = nullptr; // n*k
+  int32_t* nbr = nullptr;  // total
+  DevBuf b_off, b_hend, b_nbr;
+};
+hipError_t khop_build(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
+                      KhopDev* out, hipStream_t s);
+
+// ---- far field (farfield.hip)
+struct FarStats { int64_t accepted, leaf_pairs, coincident, nodes; };
+hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStream_t s);
+// Barnes-Hut quadtree far field; optional exports (device pointers, may be null):
+// codes[n], order[n], nodes[5*(2n)] (depth, first, count, leaf, prefix per node in pre-order),
+// stats (host) receives counters (nodes always; interaction counters when count_stats).
+struct BHWork;  // persistent buffers, sized by n
+BHWork* bh_work_create();
+void bh_work_destroy(BHWork*);
+hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
+                       uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
+                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s);
+
+// ---- sweep (sweep.hip)
+// One Jacobi iteration of Eq. 2 over the k-hop sets. sqrtc: sqrt of node
+// weights (null at level 0 => d = hop). delta2 (device, 2 doubles) receives
+// sum |x'-x|^2 and sum |x|^2.
+hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
+                 const float* xy, const float* F, double alpha, double q, float* xy_out,
+                 double* delta2_dev, hipStream_t s);
+
+// ---- coarsening (coarsen.hip)
+struct GraphDev {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int32_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  int32_t* c = nullptr;  // node weights (null = 1)
+  int32_t* w = nullptr;  // edge weights (null = 1)
+  DevBuf b_rp, b_col, b_c, b_w;
+};
+// Runs synchronous size-constrained label propagation; label[n] (device) is
+// initialised to v. Returns rounds run in *rounds_run.
+hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed, int32_t level_h,
+                      int32_t* label, int32_t* rounds_run, int64_t* moves_host, hipStream_t s);
+hipError_t contract(const GraphDev& g, const int32_t* label, int32_t* cluster, GraphDev* out,
+                    hipStream_t s);
+
+// ---- placement (layout.hip)
+hipError_t init_layout(int32_t n, uint64_t seed, int32_t level, float* xy, hipStream_t s);
+hipError_t prolong(int32_t n_fine, const int32_t* cluster, const int32_t* coarse_c,
+                   const float* coarse_xy, uint64_t seed, int32_t level, float* fine_xy,
+                   hipStream_t s);
+hipError_t sqrt_weights(int32_t n, const int32_t* c, float* out, hipStream_t s);
+
+// ---- objectives (objective.hip)
+// out (host, 3 doubles): stress over S, entropy sum over pairs not in S, coincident pairs.
+hipError_t objective(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
+                     const float* xy, double q, double* out_host, hipStream_t s);
+// out (host, 3 doubles): F unscaled, s*, F(s* x).
+hipError_t full_stress(const GraphDev& g, const float* xy, double* out_host, hipStream_t s);
+
+}  // namespace mm

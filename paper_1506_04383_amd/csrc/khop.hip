@@ -1,0 +1,355 @@
+// k-hop distance sets S_k(u) = { v != u : hop(u,v) <= k }, sorted by (hop, v):
+// the stress superset of the general maxent-stress model (footnote to Eq. 1),
+// found by a frontier BFS per source vertex.
+//
+// Two kernels, each run once to count (row lengths and per-hop ends) and once
+// to fill (after an int64 scan of the counts gives the row offsets):
+//  * small rows: one wavefront per source; the hop-h frontier lives in LDS;
+//    candidates (neighbours of the hop-(h-1) frontier) are bitonic-sorted in
+//    LDS, deduplicated, and filtered against hops h-1 and h-2 (a neighbour of
+//    a hop-(h-1) vertex has hop h-2, h-1 or h).  Rows whose candidates exceed
+//    the LDS capacity are flagged for the big-row kernel.
+//  * big rows: one workgroup per source with two n-bit bitmaps (visited and
+//    new) in LDS when they fit, otherwise in global memory per workgroup
+//    slot; the hop-h set is extracted in ascending order by scanning the new
+//    bitmap with wave-level prefix sums.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace {
+
+constexpr int KS_CAP = 1024;     // list capacity per wave (entries)
+constexpr int KS_WAVES = 2;      // waves per block
+constexpr int KB_T = 512;        // threads per big-row block
+constexpr int KB_NW = KB_T / 64;
+constexpr int KB_LDS_WORDS = 19968;  // per bitmap (2 bitmaps in LDS => n <= 638976)
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// lower_bound in a sorted LDS list
+__device__ inline bool in_sorted(const int32_t* a, int len, int32_t v) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo < len && a[lo] == v;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
+    int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t k,
+    const int64_t* __restrict__ off, int32_t* __restrict__ hend, int32_t* __restrict__ nbr,
+    int32_t* __restrict__ cnt, int32_t* __restrict__ big) {
+  __shared__ int32_t lds[KS_WAVES][5][KS_CAP];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  int32_t u = blockIdx.x * KS_WAVES + w;
+  if (u >= n) return;
+  if (FILL && big[u]) return;
+  int32_t* L0 = lds[w][0];  // hop h-2 list
+  int32_t* L1 = lds[w][1];  // hop h-1 list
+  int32_t* NW = lds[w][2];  // hop h list
+  int32_t* CA = lds[w][3];  // candidates
+  int32_t* PF = lds[w][4];  // frontier degree prefix
+  const int32_t beg = rp[u], deg = rp[u + 1] - beg;
+  int64_t o = FILL ? off[u] : 0;
+  if (deg > KS_CAP) {
+    if (!FILL) { if (l == 0) big[u] = 1; }
+    return;
+  }
+  // hop 1: N(u)
+  for (int i = l; i < deg; i += 64) {
+    int32_t v = col[beg + i];
+    L1[i] = v;
+    if (FILL) nbr[o + i] = v;
+  }
+  int len0 = 0, len1 = deg;   // L0 holds {u} implicitly for h = 2
+  int32_t total = deg;
+  if (!FILL && l == 0) hend[(int64_t)u * k] = deg;
+  wave_sync();
+  for (int h = 2; h <= k; ++h) {
+    // frontier degree prefix
+    int32_t run = 0;
+    for (int b = 0; b < len1; b += 64) {
+      int i = b + l;
+      int32_t d = 0;
+      if (i < len1) { int32_t x = L1[i]; d = rp[x + 1] - rp[x]; }
+      int32_t inc = wave_incl_scan(d);
+      if (i < len1) PF[i] = run + inc - d;
+      run += __shfl(inc, 63, 64);
+    }
+    const int32_t ncand = run;
+    if (ncand > KS_CAP) {
+      if (!FILL) { if (l == 0) big[u] = 1; }
+      return;
+    }
+    wave_sync();
+    int P = 1;
+    while (P < ncand) P <<= 1;
+    for (int j = l; j < P; j += 64) {
+      int32_t v = 0x7fffffff;
+      if (j < ncand) {
+        int lo = 0, hi = len1;  // last i with PF[i] <= j
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (PF[mid] <= j) lo = mid; else hi = mid;
+        }
+        int32_t x = L1[lo];
+        v = col[rp[x] + (j - PF[lo])];
+      }
+      CA[j] = v;
+    }
+    wave_sync();
+    // bitonic sort of CA[0..P)
+    for (int size = 2; size <= P; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = l; i < (P >> 1); i += 64) {
+          int a = 2 * stride * (i / stride) + (i % stride);
+          int b = a + stride;
+          bool up = (a & size) == 0;
+          int32_t x = CA[a], y = CA[b];
+          if ((x > y) == up) { CA[a] = y; CA[b] = x; }
+        }
+        wave_sync();
+      }
+    }
+    // dedupe + filter, compact into NW in order
+    int32_t cnt_h = 0;
+    for (int b = 0; b < ncand; b += 64) {
+      int j = b + l;
+      bool keep = false;
+      int32_t v = 0;
+      if (j < ncand) {
+        v = CA[j];
+        keep = (j == 0 || CA[j - 1] != v) && v != u && !in_sorted(L1, len1, v) &&
+               (h == 2 || !in_sorted(L0, len0, v));
+      }
+      uint64_t m = __ballot(keep);
+      int pos = cnt_h + __popcll(m & lanemask_lt());
+      if (keep) {
+        NW[pos] = v;
+        if (FILL) nbr[o + total + pos] = v;
+      }
+      cnt_h += __popcll(m);
+    }
+    total += cnt_h;
+    if (!FILL && l == 0) hend[(int64_t)u * k + (h - 1)] = total;
+    wave_sync();
+    // rotate lists: L0 <- L1, L1 <- NW
+    int32_t* t0 = L0; L0 = L1; L1 = NW; NW = t0;
+    len0 = len1; len1 = cnt_h;
+  }
+  if (!FILL && l == 0) { cnt[u] = total; big[u] = 0; }
+}
+
+// ---- big rows: bitmap BFS, one workgroup per source
+template <bool FILL, bool LDSBM>
+__global__ __launch_bounds__(KB_T) void k_khop_big(
+    int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t k,
+    const int32_t* __restrict__ rows, int32_t nrows, const int64_t* __restrict__ off,
+    int32_t* __restrict__ hend, int32_t* __restrict__ nbr, int32_t* __restrict__ cnt,
+    uint32_t* __restrict__ gbm, int32_t* __restrict__ gscratch) {
+  extern __shared__ uint32_t dyn[];
+  __shared__ int32_t wtot[KB_NW + 1];
+  const int32_t W = (n + 31) >> 5;
+  uint32_t* VIS = LDSBM ? dyn : gbm + (size_t)blockIdx.x * 2 * (size_t)W;
+  uint32_t* NEW = VIS + W;
+  int32_t* scratch = gscratch ? gscratch + (size_t)blockIdx.x * (size_t)n : nullptr;
+  const int t = threadIdx.x, wv = t >> 6, l = lane_id();
+  for (int32_t i = t; i < 2 * W; i += KB_T) VIS[i] = 0;
+  __syncthreads();
+  // word chunk per wave for the ordered extraction
+  const int32_t CW = ((W + KB_NW - 1) / KB_NW + 63) & ~63;
+  const int32_t wlo = wv * CW, whi = min(W, wlo + CW);
+  for (int32_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const int32_t u = rows[r];
+    const int32_t beg = rp[u], deg = rp[u + 1] - beg;
+    const int64_t o = FILL ? off[u] : 0;
+    // hop 1
+    for (int32_t i = t; i < deg; i += KB_T) {
+      int32_t v = col[beg + i];
+      atomicOr(&VIS[v >> 5], 1u << (v & 31));
+      if (FILL) nbr[o + i] = v;
+    }
+    if (t == 0) atomicOr(&VIS[u >> 5], 1u << (u & 31));
+    int64_t total = deg;
+    if (!FILL && t == 0) hend[(int64_t)u * k] = deg;
+    // frontier: hop-(h-1) list
+    const int32_t* F = col + beg;
+    int32_t flen = deg;
+    __syncthreads();
+    for (int h = 2; h <= k; ++h) {
+      // mark neighbours of the frontier not yet visited
+      for (int32_t i = wv; i < flen; i += KB_NW) {
+        int32_t x = F[i];
+        int32_t b0 = rp[x], b1 = rp[x + 1];
+        for (int32_t e = b0 + l; e < b1; e += 64) {
+          int32_t v = col[e];
+          uint32_t bit = 1u << (v & 31);
+          if (!(VIS[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
+        }
+      }
+      __syncthreads();
+      // count per wave chunk
+      int32_t c = 0;
+      for (int32_t b = wlo; b < whi; b += 64) {
+        int32_t wi = b + l;
+        if (wi < whi) c += __popc(NEW[wi]);
+      }
+      c = wave_sum(c);
+      if (l == 0) wtot[wv] = c;
+      __syncthreads();
+      if (t == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < KB_NW; ++i) { int32_t x = wtot[i]; wtot[i] = run; run += x; }
+        wtot[KB_NW] = run;
+      }
+      __syncthreads();
+      const int32_t cnt_h = wtot[KB_NW];
+      const bool last = (h == k);
+      int32_t* dst = FILL ? nbr + o + total : (last ? nullptr : scratch);
+      int32_t run = wtot[wv];
+      for (int32_t b = wlo; b < whi; b += 64) {
+        int32_t wi = b + l;
+        uint32_t bits = wi < whi ? NEW[wi] : 0u;
+        int32_t pc = __popc(bits);
+        int32_t inc = wave_incl_scan(pc);
+        int32_t pos = run + inc - pc;
+        if (wi < whi && bits) {
+          if (dst) {
+            uint32_t bb = bits;
+            while (bb) {
+              int j = __ffs(bb) - 1;
+              bb &= bb - 1;
+              dst[pos++] = (wi << 5) + j;
+            }
+          }
+          NEW[wi] = 0u;
+          if (!last) VIS[wi] |= bits;
+        }
+        run += __shfl(inc, 63, 64);
+      }
+      total += cnt_h;
+      if (!FILL && t == 0) hend[(int64_t)u * k + (h - 1)] = (int32_t)total;
+      __syncthreads();
+      F = dst;
+      flen = cnt_h;
+    }
+    // clear VIS: u and hops 1..k-1
+    if (t == 0) VIS[u >> 5] = 0u;
+    for (int32_t i = t; i < deg; i += KB_T) VIS[col[beg + i] >> 5] = 0u;
+    if (k >= 3) {
+      // hops 2..k-1 are in the output (fill) or were merged into VIS from
+      // scratch lists that are gone (count) -> clear the whole bitmap
+      for (int32_t i = t; i < W; i += KB_T) VIS[i] = 0u;
+    }
+    if (!FILL && t == 0) cnt[u] = (int32_t)total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_collect_big(const int32_t* big, int32_t n, const int64_t* pos, int32_t* rows) {
+  int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n && big[u]) rows[pos[u]] = u;
+}
+
+__global__ void k_hop1(int32_t n, const int32_t* rp, int32_t* hend, int32_t* cnt) {
+  int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) { int32_t d = rp[u + 1] - rp[u]; hend[u] = d; cnt[u] = d; }
+}
+
+}  // namespace
+
+hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, KhopDev* out,
+                      hipStream_t s) {
+  out->n = n;
+  out->k = k;
+  MM_TRY(out->b_off.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  MM_TRY(out->b_hend.alloc(sizeof(int32_t) * (size_t)n * (size_t)k, s));
+  out->off = out->b_off.as<int64_t>();
+  out->hend = out->b_hend.as<int32_t>();
+  if (k == 1) {
+    // S_1(u) = N(u): the CSR row itself
+    DevBuf cnt;
+    MM_TRY(cnt.alloc(sizeof(int32_t) * (size_t)n, s));
+    k_hop1<<<(n + 255) / 256, 256, 0, s>>>(n, rp, out->hend, cnt.as<int32_t>());
+    MM_TRY(scan_excl_i32(cnt.as<int32_t>(), out->off, n, s));
+    MM_TRY(hipMemcpyAsync(&out->total, out->off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MM_TRY(hipStreamSynchronize(s));
+    MM_TRY(out->b_nbr.alloc(sizeof(int32_t) * (size_t)out->total, s));
+    out->nbr = out->b_nbr.as<int32_t>();
+    MM_TRY(hipMemcpyAsync(out->nbr, col, sizeof(int32_t) * (size_t)out->total,
+                          hipMemcpyDeviceToDevice, s));
+    return hipGetLastError();
+  }
+  DevBuf cnt, big, bigpos, rows;
+  MM_TRY(cnt.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(big.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(bigpos.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  MM_TRY(hipMemsetAsync(big.p, 0, sizeof(int32_t) * (size_t)n, s));
+  const unsigned gs = (unsigned)((n + KS_WAVES - 1) / KS_WAVES);
+  k_khop_small<false><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, nullptr, out->hend, nullptr,
+                                                  cnt.as<int32_t>(), big.as<int32_t>());
+  MM_TRY(hipGetLastError());
+  MM_TRY(scan_excl_i32(big.as<int32_t>(), bigpos.as<int64_t>(), n, s));
+  int64_t nbig = 0;
+  MM_TRY(hipMemcpyAsync(&nbig, bigpos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  const bool lds_bm = ((n + 31) >> 5) <= KB_LDS_WORDS;
+  int dev = 0, ncu = 0;
+  MM_TRY(hipGetDevice(&dev));
+  MM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int32_t W = (n + 31) >> 5;
+  const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * (lds_bm ? 1 : 2));
+  DevBuf gbm, gscr;
+  if (nbig > 0) {
+    MM_TRY(rows.alloc(sizeof(int32_t) * (size_t)nbig, s));
+    k_collect_big<<<(n + 255) / 256, 256, 0, s>>>(big.as<int32_t>(), n, bigpos.as<int64_t>(),
+                                                  rows.as<int32_t>());
+    if (!lds_bm) MM_TRY(gbm.alloc(sizeof(uint32_t) * 2 * (size_t)W * (size_t)slots, s));
+    if (k >= 3) MM_TRY(gscr.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
+    const size_t shm = lds_bm ? sizeof(uint32_t) * 2 * (size_t)W : 0;
+    if (lds_bm) {
+      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_khop_big<false, true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_khop_big<true, true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    }
+    if (lds_bm)
+      k_khop_big<false, true><<<slots, KB_T, shm, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
+                                                      nullptr, out->hend, nullptr, cnt.as<int32_t>(),
+                                                      nullptr, gscr.as<int32_t>());
+    else
+      k_khop_big<false, false><<<slots, KB_T, 0, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
+                                                      nullptr, out->hend, nullptr, cnt.as<int32_t>(),
+                                                      gbm.as<uint32_t>(), gscr.as<int32_t>());
+    MM_TRY(hipGetLastError());
+  }
+  MM_TRY(scan_excl_i32(cnt.as<int32_t>(), out->off, n, s));
+  MM_TRY(hipMemcpyAsync(&out->total, out->off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  MM_TRY(out->b_nbr.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(out->total, 1), s));
+  out->nbr = out->b_nbr.as<int32_t>();
+  k_khop_small<true><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, out->off, out->hend, out->nbr,
+                                                 nullptr, big.as<int32_t>());
+  MM_TRY(hipGetLastError());
+  if (nbig > 0) {
+    const size_t shm = lds_bm ? sizeof(uint32_t) * 2 * (size_t)W : 0;
+    if (lds_bm)
+      k_khop_big<true, true><<<slots, KB_T, shm, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
+                                                     out->off, out->hend, out->nbr, nullptr, nullptr,
+                                                     nullptr);
+    else
+      k_khop_big<true, false><<<slots, KB_T, 0, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
+                                                     out->off, out->hend, out->nbr, nullptr,
+                                                     gbm.as<uint32_t>(), nullptr);
+    MM_TRY(hipGetLastError());
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -1,0 +1,203 @@
+// Scan and radix-sort primitives (deterministic: fixed tiles, fixed order).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+
+namespace {
+
+constexpr int SCAN_T = 256;          // threads per block
+constexpr int SCAN_I = 8;            // items per thread
+constexpr int SCAN_TILE = SCAN_T * SCAN_I;
+
+template <typename Tin>
+__global__ __launch_bounds__(SCAN_T) void k_tile_sums(const Tin* __restrict__ in, int64_t n,
+                                                      int64_t* __restrict__ part) {
+  __shared__ int64_t sh[SCAN_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    int64_t j = base + i;
+    if (j < n) s += (int64_t)in[j];
+  }
+  int64_t tot;
+  block_excl_scan<int64_t>(s, sh, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Single-block exclusive scan of the tile sums (any count), in place.
+__global__ __launch_bounds__(1024) void k_scan_parts(int64_t* part, int64_t m) {
+  __shared__ int64_t sh[1024 / 64 + 1];
+  int64_t carry = 0;
+  for (int64_t b = 0; b < m; b += blockDim.x) {
+    int64_t j = b + threadIdx.x;
+    int64_t v = j < m ? part[j] : 0;
+    int64_t tot;
+    int64_t ex = block_excl_scan<int64_t>(v, sh, &tot);
+    if (j < m) part[j] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[m] = carry;
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(SCAN_T) void k_tile_scan(const Tin* __restrict__ in, int64_t n,
+                                                      const int64_t* __restrict__ part,
+                                                      int64_t* __restrict__ out) {
+  __shared__ int64_t sh[SCAN_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+  int64_t v[SCAN_I];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    int64_t j = base + i;
+    v[i] = j < n ? (int64_t)in[j] : 0;
+    s += v[i];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan<int64_t>(s, sh, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    int64_t j = base + i;
+    if (j < n) out[j] = ex;
+    ex += v[i];
+  }
+}
+
+__global__ void k_set_last(int64_t* out, int64_t n, const int64_t* part, int64_t m) {
+  out[n] = part[m];
+}
+
+template <typename Tin>
+hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s) {
+  int64_t m = (n + SCAN_TILE - 1) / SCAN_TILE;
+  DevBuf part;
+  MM_TRY(part.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  if (m > 0) {
+    k_tile_sums<Tin><<<(unsigned)m, SCAN_T, 0, s>>>(in, n, part.as<int64_t>());
+  }
+  k_scan_parts<<<1, 1024, 0, s>>>(part.as<int64_t>(), m);
+  if (m > 0) {
+    k_tile_scan<Tin><<<(unsigned)m, SCAN_T, 0, s>>>(in, n, part.as<int64_t>(), out);
+  }
+  k_set_last<<<1, 1, 0, s>>>(out, n, part.as<int64_t>(), m);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int RS_T = 256;
+constexpr int RS_TILE = 4096;  // elements per block
+constexpr int RS_NW = RS_T / 64;
+
+__global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                  int shift, int nblocks,
+                                                  int32_t* __restrict__ hist) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  int64_t end = base + RS_TILE < n ? base + RS_TILE : n;
+  for (int64_t j = base + threadIdx.x; j < end; j += RS_T) {
+    int d = (int)((keys[j] >> shift) & 255u);
+    atomicAdd(&h[d], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ vals, int64_t n,
+                                                     int shift, int nblocks,
+                                                     const int64_t* __restrict__ offs,
+                                                     uint64_t* __restrict__ okeys,
+                                                     int32_t* __restrict__ ovals) {
+  __shared__ int64_t base_d[256];
+  __shared__ int32_t wc[RS_NW][256];
+  const int t = threadIdx.x, w = t >> 6, l = lane_id();
+  base_d[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+  int64_t end = tile0 + RS_TILE < n ? tile0 + RS_TILE : n;
+  const uint64_t lt = lanemask_lt();
+  for (int64_t c0 = tile0; c0 < end; c0 += RS_T) {
+#pragma unroll
+    for (int i = 0; i < RS_NW; ++i) wc[i][t] = 0;
+    __syncthreads();
+    int64_t j = c0 + t;
+    bool valid = j < end;
+    uint64_t key = valid ? keys[j] : 0;
+    int32_t val = valid ? vals[j] : 0;
+    int d = (int)((key >> shift) & 255u);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      uint64_t bb = __ballot((d >> b) & 1);
+      m &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    int rank = __popcll(m & lt);
+    if (valid && (m >> l) == 1ull) wc[w][d] = __popcll(m);  // highest lane of its digit group
+    __syncthreads();
+    if (valid) {
+      int64_t pos = base_d[d] + rank;
+      for (int i = 0; i < w; ++i) pos += wc[i][d];
+      okeys[pos] = key;
+      ovals[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int i = 0; i < RS_NW; ++i) add += wc[i][t];
+    base_d[t] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void k_iota(int32_t* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int32_t)i;
+}
+
+}  // namespace
+
+hipError_t scan_excl_i32(const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  return scan_excl_impl<int32_t>(in, out, n, s);
+}
+hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  return scan_excl_impl<int64_t>(in, out, n, s);
+}
+
+hipError_t iota_i32(int32_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_iota<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n);
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
+  if (n <= 1 || bits <= 0) return hipSuccess;
+  int passes = (bits + 7) / 8;
+  int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+  if (nb > (1ll << 30)) return hipErrorInvalidValue;
+  DevBuf k2, v2, hist, offs;
+  MM_TRY(k2.alloc(sizeof(uint64_t) * (size_t)n, s));
+  MM_TRY(v2.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(hist.alloc(sizeof(int32_t) * (size_t)(256 * nb), s));
+  MM_TRY(offs.alloc(sizeof(int64_t) * (size_t)(256 * nb + 1), s));
+  uint64_t* ka = keys; int32_t* va = vals;
+  uint64_t* kb = k2.as<uint64_t>(); int32_t* vb = v2.as<int32_t>();
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    k_rs_hist<<<(unsigned)nb, RS_T, 0, s>>>(ka, n, shift, (int)nb, hist.as<int32_t>());
+    MM_TRY(scan_excl_i32(hist.as<int32_t>(), offs.as<int64_t>(), 256 * nb, s));
+    k_rs_scatter<<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, shift, (int)nb, offs.as<int64_t>(), kb, vb);
+    MM_TRY(hipGetLastError());
+    uint64_t* tk = ka; ka = kb; kb = tk;
+    int32_t* tv = va; va = vb; vb = tv;
+  }
+  if (ka != keys) {
+    MM_TRY(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    MM_TRY(hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mm

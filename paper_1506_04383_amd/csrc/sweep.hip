@@ -1,0 +1,154 @@
+// One Jacobi iteration of the local update, Eq. 2, over the k-hop sets:
+//   A_u = sum_{v in S(u)} w_uv (x_v + d_uv (x_u - x_v)/|x_u - x_v|)
+//   C_u = sum_{v in S(u)} r_q(u, v)
+//   x'_u = (A_u + alpha (F_u - C_u)) / rho_u,   rho_u = sum_{v in S(u)} w_uv
+// F is the far field over all v != u, so F - C is the entropy term over the
+// pairs outside S (the subtraction Eq. 3 uses for its last sum).  Target
+// distances: d = hop on the finest level, hop (sqrt c_u + sqrt c_v) scale on
+// coarse levels; w = d^-2.  A coincident pair contributes w x_v to A only.
+//
+// A group of G lanes owns one row and streams its ids (coalesced) while
+// gathering x_v; the row's hop boundaries sit in registers.  The relative
+// change |x'-x|^2, |x|^2 is reduced in FP64 per block in fixed order and the
+// block partials are summed in order by a second kernel (deterministic).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace {
+
+constexpr int SW_T = 256;
+constexpr int KMAX = 8;
+
+template <int G, bool COARSE, bool Q0>
+__global__ __launch_bounds__(SW_T) void k_sweep(
+    int32_t n, int32_t k, const int64_t* __restrict__ off, const int32_t* __restrict__ hend,
+    const int32_t* __restrict__ nbr, const float* __restrict__ sqrtc, float scale,
+    const float2* __restrict__ xy, const float2* __restrict__ F, float alpha, float q,
+    float2* __restrict__ out, double2* __restrict__ part) {
+  constexpr int RPB = SW_T / G;  // rows per block
+  __shared__ double2 red[RPB];
+  const int gl = threadIdx.x % G, gi = threadIdx.x / G;
+  const int32_t u = blockIdx.x * RPB + gi;
+  double2 dd = make_double2(0.0, 0.0);
+  if (u < n) {
+    const int64_t beg = off[u], end = off[u + 1];
+    int32_t he[KMAX];
+#pragma unroll
+    for (int h = 0; h < KMAX; ++h) he[h] = h < k ? hend[(int64_t)u * k + h] : 0x7fffffff;
+    const float2 xu = xy[u];
+    const float scu = COARSE ? sqrtc[u] : 0.f;
+    float ax = 0.f, ay = 0.f, cx = 0.f, cy = 0.f, rho = 0.f;
+    for (int64_t e = beg + gl; e < end; e += G) {
+      const int32_t rel = (int32_t)(e - beg);
+      int h = 1;
+#pragma unroll
+      for (int j = 0; j < KMAX - 1; ++j) h += (rel >= he[j]) ? 1 : 0;
+      const int32_t v = nbr[e];
+      const float2 xv = xy[v];
+      float d;
+      if (COARSE) d = (float)h * (scu + sqrtc[v]) * scale;
+      else d = (float)h;
+      const float w = 1.f / (d * d);
+      const float dx = xu.x - xv.x, dy = xu.y - xv.y;
+      const float D2 = dx * dx + dy * dy;
+      rho += w;
+      if (D2 > 0.f) {
+        const float inv = rsqrtf(D2);
+        ax += w * (xv.x + d * dx * inv);
+        ay += w * (xv.y + d * dy * inv);
+        float f;
+        if (Q0) f = inv * inv;
+        else f = powf(D2, -0.5f * (q + 2.f));
+        cx += dx * f;
+        cy += dy * f;
+      } else {
+        ax += w * xv.x;
+        ay += w * xv.y;
+      }
+    }
+    ax = group_sum(ax, G); ay = group_sum(ay, G);
+    cx = group_sum(cx, G); cy = group_sum(cy, G);
+    rho = group_sum(rho, G);
+    if (gl == 0) {
+      const float2 fu = F[u];
+      float2 xn;
+      xn.x = (ax + alpha * (fu.x - cx)) / rho;
+      xn.y = (ay + alpha * (fu.y - cy)) / rho;
+      out[u] = xn;
+      const double ex = (double)xn.x - (double)xu.x, ey = (double)xn.y - (double)xu.y;
+      dd.x = ex * ex + ey * ey;
+      dd.y = (double)xu.x * (double)xu.x + (double)xu.y * (double)xu.y;
+    }
+  }
+  if (gl == 0) red[gi] = dd;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < RPB; ++i) { s.x += red[i].x; s.y += red[i].y; }
+    part[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_sum_parts(const double2* __restrict__ part, int32_t m,
+                                                    double* __restrict__ out) {
+  __shared__ double shx[1024], shy[1024];
+  double sx = 0.0, sy = 0.0;
+  // fixed assignment: thread t sums parts t, t+1024, ... in order
+  for (int32_t i = threadIdx.x; i < m; i += 1024) { sx += part[i].x; sy += part[i].y; }
+  shx[threadIdx.x] = sx;
+  shy[threadIdx.x] = sy;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      shx[threadIdx.x] += shx[threadIdx.x + s];
+      shy[threadIdx.x] += shy[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = shx[0]; out[1] = shy[0]; }
+}
+
+template <int G>
+hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, float scale,
+                  const float* xy, const float* F, float alpha, float q, float* out, double2* part,
+                  int32_t nb, hipStream_t s) {
+  const float2* x2 = (const float2*)xy;
+  const float2* F2 = (const float2*)F;
+  float2* o2 = (float2*)out;
+#define MM_SW(C, Q)                                                                          \
+  k_sweep<G, C, Q><<<nb, SW_T, 0, s>>>(kh.n, kh.k, kh.off, kh.hend, kh.nbr, sqrtc, scale, x2, \
+                                       F2, alpha, q, o2, part)
+  if (coarse) { if (q0) MM_SW(true, true); else MM_SW(true, false); }
+  else { if (q0) MM_SW(false, true); else MM_SW(false, false); }
+#undef MM_SW
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
+                 const float* xy, const float* F, double alpha, double q, float* xy_out,
+                 double* delta2_dev, hipStream_t s) {
+  if (kh.k > KMAX) return hipErrorInvalidValue;
+  const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
+  int G = avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
+  const int32_t rpb = SW_T / G;
+  const int32_t nb = (kh.n + rpb - 1) / rpb;
+  DevBuf part;
+  MM_TRY(part.alloc(sizeof(double2) * (size_t)nb, s));
+  const bool coarse = (level > 0) && sqrtc != nullptr;
+  const bool q0 = (q == 0.0);
+  hipError_t e;
+  switch (G) {
+    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
+    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
+    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
+    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
+  }
+  MM_TRY(e);
+  k_sum_parts<<<1, 1024, 0, s>>>(part.as<double2>(), nb, delta2_dev);
+  return hipGetLastError();
+}
+
+}  // namespace mm

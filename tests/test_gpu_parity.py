@@ -1,0 +1,243 @@
+"""GPU path vs the FP64 oracle, element by element, through the C-ABI.
+
+Bars: bit-exact for integer work (k-hop sets, Morton codes, quadtree
+topology, interaction counts, cluster ids, coarse graphs, initial layout);
+far field within 1e-4 relative to max(|F_u|, mean |F|); one sweep within
+1e-4 * max(|x_orc|, 1) on identical (FP32) inputs; prolongation within
+1e-6 * max(|x|, 1); objectives within 1e-5 relative (same layout).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1506_04383_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mm):
+    c = mm.Context(0)
+    yield c
+    c.close()
+
+
+def _graphs():
+    # hub attached to a long path: big rows, and n > LDS bitmap capacity
+    n = 700_000
+    v = np.arange(n - 1)
+    hub_nb = np.arange(0, n - 1, 350)[:2000]
+    src = np.concatenate([v, np.full(hub_nb.size, n - 1)])
+    dst = np.concatenate([v + 1, hub_nb])
+    return {
+        "grid32": lambda: synth.grid(32, 32),
+        "rgg4k": lambda: synth.rgg(4000, 3),
+        "rmat12": lambda: synth.rmat(12, 8 * 4096, 5),
+        "star3k": lambda: synth.star(3000),
+        "tree": lambda: synth.random_tree(5000, 2),
+        "tri": synth.two_triangles,
+        "hubpath700k": lambda: synth.csr_from_edges(n, src, dst),
+    }
+
+
+KHOP_CASES = [("grid32", 3), ("grid32", 1), ("rgg4k", 3), ("rgg4k", 5), ("rmat12", 2),
+              ("rmat12", 3), ("star3k", 2), ("tree", 4), ("tri", 2), ("hubpath700k", 2)]
+
+
+@pytest.mark.parametrize("name,k", KHOP_CASES)
+def test_khop_bit_exact(orc, mm, ctx, name, k):
+    g = _graphs()[name]()
+    print(f"[khop] {name} n={g.n} k={k}", flush=True)
+    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), k)
+    off, hend, nbr = kh.export()
+    ref = orc.khop_build(g.row_ptr, g.col, k)
+    assert kh.total == int(ref.off[-1])
+    assert np.array_equal(off, ref.off)
+    assert np.array_equal(hend, ref.hend)
+    assert np.array_equal(nbr, ref.nbr)
+
+
+def _layout_points(n, seed, spread=1.0):
+    rng = np.random.default_rng(seed)
+    a = rng.random((n, 2)) * 20 * spread
+    a[: n // 5] = 7 + 0.002 * rng.standard_normal((n // 5, 2))  # dense clump
+    a[n // 5: n // 5 + 3] = a[n // 5 + 3]                      # exact duplicates
+    return a.astype(np.float32)
+
+
+def _far_err(F, Fr):
+    nr = np.linalg.norm(Fr, axis=1)
+    scale = np.maximum(nr, nr.mean())
+    return float(np.max(np.linalg.norm(F - Fr, axis=1) / scale))
+
+
+@pytest.mark.parametrize("n,theta", [(1000, 0.5), (5000, 0.5), (20000, 1.0), (3000, 0.0),
+                                     (777, 0.3)])
+def test_barnes_hut_parity(orc, mm, ctx, n, theta):
+    print(f"[bh] n={n} theta={theta}", flush=True)
+    x = _layout_points(n, n)
+    r = mm.repulsion(ctx, x, 0.0, theta, export=True)
+    ref = orc.barnes_hut(x.astype(np.float64), theta)
+    assert np.array_equal(r["codes"], ref.codes)
+    assert np.array_equal(r["order"].cpu().numpy(), ref.order)
+    nodes = r["nodes"].cpu().numpy()
+    assert nodes.shape == ref.nodes.shape
+    assert np.array_equal(nodes, ref.nodes)
+    assert r["accepted"] == ref.accepted and r["leaf_pairs"] == ref.leaf_pairs
+    assert _far_err(r["F"].cpu().numpy(), ref.F) < 1e-4
+
+
+@pytest.mark.parametrize("q", [0.0, 1.0])
+def test_exact_far_field(orc, mm, ctx, q):
+    x = _layout_points(2048, 9)
+    F = mm.repulsion(ctx, x, q, -1.0)["F"].cpu().numpy()
+    Fr = orc.farfield_exact(x.astype(np.float64), q)
+    assert _far_err(F, Fr) < 1e-4
+
+
+def test_bh_theta0_equals_exact(mm, ctx):
+    x = _layout_points(1500, 4)
+    a = mm.repulsion(ctx, x, 0.0, 0.0)["F"].cpu().numpy()
+    b = mm.repulsion(ctx, x, 0.0, -1.0)["F"].cpu().numpy()
+    assert _far_err(a, b.astype(np.float64)) < 1e-4
+
+
+@pytest.mark.parametrize("name,k,level", [("grid32", 3, 0), ("rgg4k", 3, 0), ("rmat12", 2, 0),
+                                          ("rgg4k", 2, 1), ("tree", 3, 2)])
+def test_sweep_replay(orc, mm, ctx, name, k, level):
+    """One Jacobi iteration of Eq. 2 on identical FP32 inputs."""
+    g = _graphs()[name]()
+    print(f"[sweep] {name} k={k} level={level}", flush=True)
+    rng = np.random.default_rng(7)
+    x = (rng.random((g.n, 2)) * math.sqrt(g.n)).astype(np.float32)
+    c = None
+    if level > 0:
+        c = rng.integers(1, 9, g.n).astype(np.int32)
+    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), k)
+    F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
+    alpha = 0.37
+    xo, d = mm.sweep(ctx, kh, x, F, alpha, 0.0, level, c, 1.0)
+    ref = orc.khop_build(g.row_ptr, g.col, k)
+    xr, dr = orc.sweep(ref, x.astype(np.float64), F.cpu().numpy().astype(np.float64), alpha,
+                       0.0, level, c, 1.0)
+    xo = xo.cpu().numpy()
+    err = np.abs(xo - xr) / np.maximum(np.abs(xr), 1.0)
+    print(f"  max err {err.max():.3e}", flush=True)
+    assert err.max() < 1e-4
+    assert abs(math.sqrt(d[0] / d[1]) - dr) <= 1e-3 * dr + 1e-7
+
+
+def test_sweep_deterministic(mm, ctx):
+    g = synth.rgg(4000, 3)
+    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), 3)
+    x = _layout_points(g.n, 1)
+    F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
+    a, da = mm.sweep(ctx, kh, x, F, 0.2)
+    b, db = mm.sweep(ctx, kh, x, F, 0.2)
+    assert (a == b).all().item() and da == db
+
+
+@pytest.mark.parametrize("name", ["grid32", "rgg4k", "rmat12", "tri", "star3k"])
+def test_coarsen_bit_exact(orc, mm, ctx, name):
+    g = _graphs()[name]()
+    lv = orc.Level(g.row_ptr, g.col)
+    dg = ctx.graph(g.row_ptr, g.col)
+    for h in (1, 2, 3):
+        U = max(1.0 if lv.c is None else float(lv.c.max()), 2.0 ** h)
+        cl, (rp, col, cw, ew), rounds, moves = mm.coarsen(ctx, dg, U, 10, 3, h)
+        lab, mv = orc.lp(lv.row_ptr, lv.col, U, 10, 3, h, lv.c, lv.w)
+        rcl, G = orc.contract(lv, lab)
+        assert rounds == mv.size and np.array_equal(moves, mv)
+        assert np.array_equal(cl.cpu().numpy(), rcl)
+        assert np.array_equal(rp, G.row_ptr) and np.array_equal(col, G.col)
+        assert np.array_equal(cw, G.c) and np.array_equal(ew, G.w)
+        if G.n < 3:
+            break
+        lv = G
+        dg = ctx.graph(G.row_ptr, G.col, G.c, G.w)
+
+
+def test_init_and_prolong(orc, mm, ctx):
+    x = mm.init_layout(ctx, 5000, 11, 3).cpu().numpy()
+    assert np.array_equal(x.astype(np.float64), orc.init_layout(5000, 11, 3))
+    n = 30000
+    rng = np.random.default_rng(3)
+    cluster = rng.integers(0, 4000, n).astype(np.int32)
+    cw = rng.integers(1, 60, 4000).astype(np.int32)
+    cx = (rng.random((4000, 2)) * 100).astype(np.float32)
+    fx = mm.prolong(ctx, cluster, cw, cx, 5, 2).cpu().numpy()
+    fr = orc.prolong(cluster, cw, cx.astype(np.float64), 5, 2)
+    assert np.max(np.abs(fx - fr) / np.maximum(np.abs(fr), 1.0)) < 1e-6
+
+
+@pytest.mark.parametrize("k,level", [(1, 0), (3, 0), (2, 1)])
+def test_objective_parity(orc, mm, ctx, k, level):
+    g = synth.rgg(3000, 8)
+    x = _layout_points(g.n, 2)
+    c = np.random.default_rng(1).integers(1, 5, g.n).astype(np.int32) if level else None
+    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), k)
+    o = mm.objective(ctx, kh, x, 0.008, 0.0, level, c)
+    r = orc.objective(orc.khop_build(g.row_ptr, g.col, k), x.astype(np.float64), 0.008, 0.0,
+                      level, c)
+    assert o["coincident"] == r["coincident"]
+    for key in ("stress", "ent", "M"):
+        assert abs(o[key] - r[key]) <= 1e-5 * abs(r[key]), key
+
+
+def test_full_stress_parity(orc, mm, ctx):
+    g = synth.rgg(2500, 4)
+    x = _layout_points(g.n, 5)
+    o = mm.full_stress(ctx, ctx.graph(g.row_ptr, g.col), x)
+    r = orc.full_stress(g.row_ptr, g.col, x.astype(np.float64))
+    for key in ("F_unscaled", "s_opt", "F"):
+        assert abs(o[key] - r[key]) <= 1e-6 * abs(r[key]), key
+
+
+def test_layout_small_config_end_to_end(orc, mm, ctx):
+    """32x32 grid, k = 3, alpha halves to 0.008, 3 coarsening levels, exact
+    far field: maxent-stress and full stress within 1% of the oracle."""
+    g = synth.grid(32, 32)
+    p = mm.Params(k=3, theta=-1.0, alpha_decay=0.5, max_levels=3)
+    xg, st = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), p)
+    xg = xg.cpu().numpy().astype(np.float64)
+    po = orc.Params(k=3, theta=-1.0, alpha_decay=0.5, max_levels=3)
+    xo, sto = orc.layout(g, po)
+    assert st["levels"] == len(sto["levels"])
+    assert [l["n"] for l in st["per_level"]][::-1] == [l["n"] for l in sto["levels"]]
+    kh = orc.khop_build(g.row_ptr, g.col, 3)
+    mg, mo = orc.objective(kh, xg, 0.008), orc.objective(kh, xo, 0.008)
+    fg, fo = orc.full_stress(g.row_ptr, g.col, xg), orc.full_stress(g.row_ptr, g.col, xo)
+    print(f"  M gpu {mg['M']:.6g} orc {mo['M']:.6g}  F gpu {fg['F']:.6g} orc {fo['F']:.6g}")
+    assert abs(mg["M"] - mo["M"]) <= 0.01 * abs(mo["M"])
+    assert abs(fg["F"] - fo["F"]) <= 0.01 * abs(fo["F"])
+    x2, _ = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), p)
+    assert np.array_equal(x2.cpu().numpy().astype(np.float64), xg)
+
+
+def test_invalid_inputs_rejected(mm, ctx):
+    g = synth.path(5)
+    rp, col = g.row_ptr.copy(), g.col.copy()
+    col[0] = 0  # self-loop at 0
+    with pytest.raises(mm.MulmentError, match="EINVAL"):
+        mm.layout(ctx, ctx.graph(rp, col))
+    rp2 = np.array([0, 1, 1, 2], np.int32)  # isolated vertex 1
+    with pytest.raises(mm.MulmentError, match="isolated"):
+        mm.layout(ctx, ctx.graph(rp2, np.array([2, 0], np.int32)))
+    with pytest.raises(mm.MulmentError, match="inverted"):
+        mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(alpha0=0.001))
+    with pytest.raises(mm.MulmentError, match="k must"):
+        mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(k=0))
+    with pytest.raises(mm.MulmentError, match="not finite"):
+        mm.layout(ctx, ctx.graph(g.row_ptr, g.col), init_xy=np.full((5, 2), np.nan, np.float32))
