@@ -83,6 +83,9 @@ typedef struct {
   int32_t level_final_iters[MM_MAX_LEVELS];
   int32_t level_cap_hit[MM_MAX_LEVELS];  /* final phase stopped by max_final_iters */
   double level_delta[MM_MAX_LEVELS];     /* last relative change */
+  double level_sweep_ms[MM_MAX_LEVELS];  /* summed HIP-event time of the sweep launches */
+  double level_far_ms[MM_MAX_LEVELS];    /* summed HIP-event time of the far-field launches */
+  double level_khop_ms[MM_MAX_LEVELS];   /* wall time of the k-hop build */
   double t_total_ms, t_coarsen_ms, t_khop_ms, t_farfield_ms, t_sweep_ms, t_other_ms;
   int64_t vertex_updates;                /* sum over levels of n * iterations */
   int64_t finest_updates;                /* n_0 * iterations on the input graph */

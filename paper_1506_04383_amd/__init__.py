@@ -51,7 +51,10 @@ class MMStats(C.Structure):
                 ("level_iters", C.c_int32 * MAX_LEVELS),
                 ("level_final_iters", C.c_int32 * MAX_LEVELS),
                 ("level_cap_hit", C.c_int32 * MAX_LEVELS),
-                ("level_delta", C.c_double * MAX_LEVELS), ("t_total_ms", C.c_double),
+                ("level_delta", C.c_double * MAX_LEVELS),
+                ("level_sweep_ms", C.c_double * MAX_LEVELS),
+                ("level_far_ms", C.c_double * MAX_LEVELS),
+                ("level_khop_ms", C.c_double * MAX_LEVELS), ("t_total_ms", C.c_double),
                 ("t_coarsen_ms", C.c_double), ("t_khop_ms", C.c_double),
                 ("t_farfield_ms", C.c_double), ("t_sweep_ms", C.c_double),
                 ("t_other_ms", C.c_double), ("vertex_updates", C.c_int64),
@@ -65,7 +68,8 @@ class MMStats(C.Structure):
                 {"level": i, "n": self.level_n[i], "nnz": self.level_nnz[i],
                  "khop_entries": self.level_khop[i], "iters": self.level_iters[i],
                  "final_iters": self.level_final_iters[i], "cap_hit": self.level_cap_hit[i],
-                 "delta": self.level_delta[i]}
+                 "delta": self.level_delta[i], "sweep_ms": self.level_sweep_ms[i],
+                 "far_ms": self.level_far_ms[i], "khop_ms": self.level_khop_ms[i]}
                 for i in range(L)],
             "t_total_ms": self.t_total_ms, "t_coarsen_ms": self.t_coarsen_ms,
             "t_khop_ms": self.t_khop_ms, "t_farfield_ms": self.t_farfield_ms,

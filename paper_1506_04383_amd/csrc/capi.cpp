@@ -592,7 +592,9 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       mm::KhopDev kh;
       HIPCHK(mm::khop_build(nl, G.row_ptr, G.col, p->k, &kh, s));
       HIPCHK(hipStreamSynchronize(s));
-      t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
+      const double khop_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
+      t_khop += khop_ms;
+      double lvl_far = 0, lvl_sweep = 0;
       mm::DevBuf sq;
       const float* sqrtc = nullptr;
       if (lvl > 0) {
@@ -620,6 +622,8 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
         t_far += a;
         t_sweep += b;
+        lvl_far += a;
+        lvl_sweep += b;
         delta = ctx->pinned[1] > 0 ? std::sqrt(ctx->pinned[0] / ctx->pinned[1]) : INFINITY;
         if (!std::isfinite(delta)) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
         std::swap(xa, xb);
@@ -648,6 +652,9 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         st.level_final_iters[lvl] = final_iters;
         st.level_cap_hit[lvl] = cap_hit;
         st.level_delta[lvl] = delta;
+        st.level_sweep_ms[lvl] = lvl_sweep;
+        st.level_far_ms[lvl] = lvl_far;
+        st.level_khop_ms[lvl] = khop_ms;
       }
       st.vertex_updates += (int64_t)nl * iters;
       if (lvl == 0) st.finest_updates = (int64_t)nl * iters;

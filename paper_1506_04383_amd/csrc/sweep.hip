@@ -39,32 +39,46 @@ __global__ __launch_bounds__(SW_T) void k_sweep(
     const float2 xu = xy[u];
     const float scu = COARSE ? sqrtc[u] : 0.f;
     float ax = 0.f, ay = 0.f, cx = 0.f, cy = 0.f, rho = 0.f;
-    for (int64_t e = beg + gl; e < end; e += G) {
-      const int32_t rel = (int32_t)(e - beg);
-      int h = 1;
+    // U independent entries per lane per step: their id and coordinate loads
+    // are issued before any is consumed, so U gathers are in flight per lane.
+    constexpr int U = 8;
+    for (int64_t e0 = beg + gl; e0 < end; e0 += (int64_t)U * G) {
+      int32_t vv[U];
+      float2 xv[U];
 #pragma unroll
-      for (int j = 0; j < KMAX - 1; ++j) h += (rel >= he[j]) ? 1 : 0;
-      const int32_t v = nbr[e];
-      const float2 xv = xy[v];
-      float d;
-      if (COARSE) d = (float)h * (scu + sqrtc[v]) * scale;
-      else d = (float)h;
-      const float w = 1.f / (d * d);
-      const float dx = xu.x - xv.x, dy = xu.y - xv.y;
-      const float D2 = dx * dx + dy * dy;
-      rho += w;
-      if (D2 > 0.f) {
-        const float inv = rsqrtf(D2);
-        ax += w * (xv.x + d * dx * inv);
-        ay += w * (xv.y + d * dy * inv);
-        float f;
-        if (Q0) f = inv * inv;
-        else f = powf(D2, -0.5f * (q + 2.f));
-        cx += dx * f;
-        cy += dy * f;
-      } else {
-        ax += w * xv.x;
-        ay += w * xv.y;
+      for (int j = 0; j < U; ++j) {
+        const int64_t e = e0 + (int64_t)j * G;
+        vv[j] = e < end ? nbr[e] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) xv[j] = vv[j] >= 0 ? xy[vv[j]] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        if (vv[j] < 0) continue;
+        const int32_t rel = (int32_t)(e0 + (int64_t)j * G - beg);
+        int h = 1;
+#pragma unroll
+        for (int q2 = 0; q2 < KMAX - 1; ++q2) h += (rel >= he[q2]) ? 1 : 0;
+        float d;
+        if (COARSE) d = (float)h * (scu + sqrtc[vv[j]]) * scale;
+        else d = (float)h;
+        const float w = 1.f / (d * d);
+        const float dx = xu.x - xv[j].x, dy = xu.y - xv[j].y;
+        const float D2 = dx * dx + dy * dy;
+        rho += w;
+        if (D2 > 0.f) {
+          const float inv = rsqrtf(D2);
+          ax += w * (xv[j].x + d * dx * inv);
+          ay += w * (xv[j].y + d * dy * inv);
+          float f;
+          if (Q0) f = inv * inv;
+          else f = powf(D2, -0.5f * (q + 2.f));
+          cx += dx * f;
+          cy += dy * f;
+        } else {
+          ax += w * xv[j].x;
+          ay += w * xv[j].y;
+        }
       }
     }
     ax = group_sum(ax, G); ay = group_sum(ay, G);
