@@ -145,6 +145,19 @@ mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int3
                    double scale, const float* xy_in, const float* F, double alpha, double q,
                    float* xy_out, double* delta);
 
+/* Kernel choice for mm_sweep_ex.  Both compute the same update.
+ * MM_SWEEP_ROWS: a group of lanes per row gathers x_v from HBM/L2.
+ * MM_SWEEP_TILED: the sets are re-laid tile-major (tiles of 8192 vertices,
+ * 16-bit entries) and each workgroup stages one tile's coordinates in LDS;
+ * needs k <= 7 and n <= 2^25 (else MM_EUNSUPPORTED).  The tile-major copy is
+ * built on first use and cached in the mm_khop.
+ * MM_SWEEP_AUTO: tiled when supported and the mean (row, tile) chunk has at
+ * least 8 entries, rows otherwise (what mm_layout does on every level). */
+enum { MM_SWEEP_AUTO = 0, MM_SWEEP_ROWS = 1, MM_SWEEP_TILED = 2 };
+mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
+                      double scale, const float* xy_in, const float* F, double alpha, double q,
+                      float* xy_out, double* delta, int32_t mode);
+
 /* One coarsening step (Section 3.1): size-constrained label propagation with
  * bound U at hierarchy level level_h, then contraction.  cluster (device, n)
  * receives the coarse vertex of every vertex; *out the coarse graph

@@ -80,7 +80,8 @@ class MMStats(C.Structure):
 
 EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_sync",
            "mm_last_error", "mm_layout", "mm_khop_build", "mm_khop_free", "mm_khop_info",
-           "mm_khop_arrays", "mm_khop_export", "mm_repulsion", "mm_sweep", "mm_coarsen",
+           "mm_khop_arrays", "mm_khop_export", "mm_repulsion", "mm_sweep", "mm_sweep_ex",
+           "mm_coarsen",
            "mm_coarse_graph", "mm_coarse_export", "mm_coarse_free", "mm_init_layout",
            "mm_prolong", "mm_objective", "mm_full_stress"]
 
@@ -109,6 +110,7 @@ def lib():
         "mm_khop_export": [vp, vp, vp, vp, vp, i32],
         "mm_repulsion": [vp, i32, vp, f64, f64, vp, vp, vp, vp, vp],
         "mm_sweep": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp],
+        "mm_sweep_ex": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32],
         "mm_coarsen": [vp, P(MMGraph), f64, i32, u64, i32, vp, P(vp), vp, vp],
         "mm_coarse_graph": [vp, P(MMGraph)],
         "mm_coarse_export": [vp, vp, vp, vp, vp, vp, i32],
@@ -325,17 +327,21 @@ def repulsion(ctx: Context, xy, q: float = 0.0, theta: float = 0.5, export: bool
     return out
 
 
+SWEEP_AUTO, SWEEP_ROWS, SWEEP_TILED = 0, 1, 2
+
+
 def sweep(ctx: Context, kh: KHop, xy, F, alpha: float, q: float = 0.0, level: int = 0,
-          node_w=None, scale: float = 1.0):
-    """One Jacobi iteration of Eq. 2; returns (xy_out, (|x'-x|^2, |x|^2))."""
+          node_w=None, scale: float = 1.0, mode: int = SWEEP_ROWS):
+    """One Jacobi iteration of Eq. 2; returns (xy_out, (|x'-x|^2, |x|^2)).
+    mode: SWEEP_ROWS (row-gather kernel), SWEEP_TILED (LDS-tiled), SWEEP_AUTO."""
     t = ctx.torch
     xy = ctx._dev(xy, t.float32)
     F = ctx._dev(F, t.float32)
     nw = None if node_w is None else ctx._dev(node_w, t.int32)
     out = t.empty_like(xy)
     d = np.zeros(2)
-    _check(lib().mm_sweep(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha, q,
-                          _ptr(out), d.ctypes.data_as(C.c_void_p)))
+    _check(lib().mm_sweep_ex(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha, q,
+                             _ptr(out), d.ctypes.data_as(C.c_void_p), mode))
     return out, (float(d[0]), float(d[1]))
 
 

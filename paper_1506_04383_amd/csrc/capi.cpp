@@ -28,6 +28,8 @@ struct mm_context {
 };
 struct mm_khop {
   mm::KhopDev kh;
+  mm::TiledSet ts;     // tile-major copy, built on first tiled sweep
+  bool ts_tried = false;
 };
 struct mm_coarse {
   mm::GraphDev g;
@@ -286,30 +288,59 @@ mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, do
 
 // ------------------------------------------------------------------ sweep
 
-mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
-                   double scale, const float* xy_in, const float* F, double alpha, double q,
-                   float* xy_out, double* delta) {
+mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
+                      double scale, const float* xy_in, const float* F, double alpha, double q,
+                      float* xy_out, double* delta, int32_t mode) {
   try {
     if (!ctx || !kh || !xy_in || !F || !xy_out) return fail(MM_EINVAL, "NULL argument");
     if (xy_in == xy_out) return fail(MM_EINVAL, "Jacobi update needs separate in/out buffers");
     if (level < 0 || !(scale > 0) || std::isnan(alpha) || std::isnan(q)) return fail(MM_EINVAL, "bad level/scale/alpha/q");
+    if (mode < MM_SWEEP_AUTO || mode > MM_SWEEP_TILED) return fail(MM_EINVAL, "bad sweep mode");
     DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
     mm::DevBuf sq, d2;
     const float* sqrtc = nullptr;
     if (level > 0) {
-      HIPCHK(make_sqrtc(kh->kh.n, node_w, sq, ctx->stream));
+      HIPCHK(make_sqrtc(kh->kh.n, node_w, sq, s));
       sqrtc = sq.as<float>();
     }
-    HIPCHK(d2.alloc(2 * sizeof(double), ctx->stream));
-    HIPCHK(mm::sweep(kh->kh, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2.as<double>(),
-                     ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(d2.alloc(2 * sizeof(double), s));
+    bool tiled = false;
+    if (mode != MM_SWEEP_ROWS) {
+      const bool ok = mm::tiled_eligible(kh->kh, mm::kTileBits);
+      if (mode == MM_SWEEP_TILED && !ok) return fail(MM_EUNSUPPORTED, "tiled sweep needs k <= 7 and n <= 2^25");
+      if (ok && !kh->ts_tried) {
+        HIPCHK(mm::tiled_build(kh->kh, mm::kTileBits, mode == MM_SWEEP_TILED ? 0.0 : 8.0, &kh->ts, s));
+        kh->ts_tried = true;
+      }
+      if (ok && !kh->ts.built && mode == MM_SWEEP_TILED) {
+        HIPCHK(mm::tiled_build(kh->kh, mm::kTileBits, 0.0, &kh->ts, s));
+      }
+      tiled = ok && kh->ts.built;
+    }
+    if (tiled) {
+      mm::DevBuf rho;
+      HIPCHK(rho.alloc(sizeof(float) * (size_t)kh->kh.n, s));
+      HIPCHK(mm::compute_rho(kh->kh, sqrtc, scale, rho.as<float>(), s));
+      HIPCHK(mm::sweep_tiled(kh->ts, level, sqrtc, scale, rho.as<float>(), xy_in, F, alpha, q,
+                             xy_out, d2.as<double>(), s));
+    } else {
+      HIPCHK(mm::sweep(kh->kh, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2.as<double>(), s));
+    }
+    HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     if (delta) { delta[0] = ctx->pinned[0]; delta[1] = ctx->pinned[1]; }
     return MM_OK;
   } catch (...) {
-    return fail(MM_EINTERNAL, "exception in mm_sweep");
+    return fail(MM_EINTERNAL, "exception in mm_sweep_ex");
   }
+}
+
+mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
+                   double scale, const float* xy_in, const float* F, double alpha, double q,
+                   float* xy_out, double* delta) {
+  return mm_sweep_ex(ctx, const_cast<mm_khop*>(kh), level, node_w, scale, xy_in, F, alpha, q,
+                     xy_out, delta, MM_SWEEP_ROWS);
 }
 
 // ------------------------------------------------------------- coarsening
@@ -601,6 +632,18 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         HIPCHK(make_sqrtc(nl, G.c, sq, s));
         sqrtc = sq.as<float>();
       }
+      // tile-major sets with LDS-staged coordinates when rows are long enough
+      mm::TiledSet ts;
+      mm::DevBuf rho;
+      if (mm::tiled_eligible(kh, mm::kTileBits)) {
+        auto tt = std::chrono::steady_clock::now();
+        HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
+        HIPCHK(mm::compute_rho(kh, sqrtc, p->coarse_dist_scale, rho.as<float>(), s));
+        HIPCHK(mm::tiled_build(kh, mm::kTileBits, 8.0, &ts, s));
+        if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
+        HIPCHK(hipStreamSynchronize(s));
+        t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
+      }
       int32_t iters = 0, final_iters = 0, cap_hit = 0;
       double delta = 0;
       auto iterate = [&](double alpha) -> mm_status {
@@ -612,8 +655,12 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
                                  nullptr, nullptr, nullptr, 0, nullptr, s));
         }
         HIPCHK(hipEventRecord(ctx->ev[1], s));
-        HIPCHK(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa.as<float>(), F.as<float>(), alpha,
-                         p->q, xb.as<float>(), d2.as<double>(), s));
+        if (ts.built)
+          HIPCHK(mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa.as<float>(),
+                                 F.as<float>(), alpha, p->q, xb.as<float>(), d2.as<double>(), s));
+        else
+          HIPCHK(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa.as<float>(), F.as<float>(), alpha,
+                           p->q, xb.as<float>(), d2.as<double>(), s));
         HIPCHK(hipEventRecord(ctx->ev[2], s));
         HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

@@ -48,6 +48,7 @@ hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t
 // Sorted result ends in keys/vals (the buffers are ping-ponged internally).
 hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
 hipError_t iota_i32(int32_t* out, int64_t n, hipStream_t s);
+hipError_t widen_i32_u64(const int32_t* in, uint64_t* out, int64_t n, hipStream_t s);
 
 // ---- k-hop distance sets (khop.hip)
 struct KhopDev {
@@ -60,6 +61,34 @@ struct KhopDev {
 };
 hipError_t khop_build(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
                       KhopDev* out, hipStream_t s);
+
+// ---- tile-major stress sets and the LDS-tiled sweep (tiled.hip)
+struct TiledSet {
+  int32_t n = 0, tbits = 0, ntiles = 0, nunits = 0;
+  int64_t nchunks = 0, total = 0, padded = 0;
+  double avg_chunk = 0;
+  bool built = false;
+  int64_t* rc_ptr = nullptr;     // n+1: row-major chunk slots of each row
+  int32_t* chunk_row = nullptr;  // chunks in (tile, row) order
+  int64_t* chunk_off = nullptr;  // nchunks+1: entry offsets (multiples of 8)
+  int32_t* chunk_slot = nullptr; // row-major slot of each chunk
+  uint16_t* ent = nullptr;       // (hop << tbits) | (v - tile * 2^tbits)
+  int32_t* unit_c0 = nullptr;    // nunits+1: first chunk of each work unit
+  int32_t* unit_tile = nullptr;  // tile of each work unit
+  DevBuf b_rc_ptr, b_chunk_row, b_chunk_off, b_chunk_slot, b_ent, b_unit_c0, b_unit_tile, b_partial;
+};
+bool tiled_eligible(const KhopDev& kh, int32_t tbits);
+// rho_u = sum_{v in S(u)} w_uv (sqrtc null: finest level, d = hop)
+hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, float* rho,
+                       hipStream_t s);
+// Builds the tile-major copy of kh; when the mean chunk length is below
+// min_avg_chunk it stops after counting (ts->built stays false).
+hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
+                       hipStream_t s);
+constexpr int32_t kTileBits = 13;
+hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
+                       const float* rho, const float* xy, const float* F, double alpha, double q,
+                       float* xy_out, double* delta2_dev, hipStream_t s);
 
 // ---- far field (farfield.hip)
 struct FarStats { int64_t accepted, leaf_pairs, coincident, nodes; };

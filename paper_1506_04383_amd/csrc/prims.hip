@@ -152,6 +152,11 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
   }
 }
 
+__global__ void k_widen(const int32_t* in, uint64_t* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (uint64_t)(uint32_t)in[i];
+}
+
 __global__ void k_iota(int32_t* out, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (int32_t)i;
@@ -169,6 +174,12 @@ hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t
 hipError_t iota_i32(int32_t* out, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_iota<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n);
+  return hipGetLastError();
+}
+
+hipError_t widen_i32_u64(const int32_t* in, uint64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_widen<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,575 @@
+// Tile-major stress sets and the LDS-tiled Jacobi sweep (Eq. 2).
+//
+// The k-hop sets are a sparse n x n pattern whose columns are gathered
+// (x_v) for every entry.  When rows are long, a row-at-a-time sweep is bound
+// by the L2 traffic of those random 8-byte gathers.  Here the columns are cut
+// into tiles of T = 2^tbits vertices; the coordinates (and sqrt c) of one
+// tile are staged in LDS and every (row, tile) chunk of the sets is swept
+// against them.  Entries are stored tile-major, 16 bits each:
+// (hop << tbits) | (v - tile * T), so hop <= 2^(16 - tbits) - 1.
+//
+// Per chunk the partial sum  P = sum w (x_v + d (x_u - x_v)/D) - alpha sum r_q(u,v)
+// is written to a row-major slot; the combine kernel adds a row's slots in
+// tile order and forms x'_u = (P + alpha F_u) / rho_u (fixed order: the
+// result is run-to-run identical).  rho_u = sum_{S(u)} w_uv is computed once
+// per level from the canonical sets.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace {
+
+constexpr int TB_WAVES = 4;          // waves per block of the conversion kernels
+constexpr int TB_MAXTILES = 4096;    // conversion keeps per-tile counters in LDS
+constexpr int TB_MAXW = TB_MAXTILES / 32;
+constexpr int TS_T = 512;            // sweep block
+constexpr int32_t UNIT_CH = 768;      // chunks per work unit (metadata staged in LDS)
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// wave inclusive max-scan
+__device__ inline int32_t wave_incl_max(int32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t w = __shfl_up(v, o, 64);
+    if (l >= o) v = max(v, w);
+  }
+  return v;
+}
+
+// K1: number of distinct tiles per row
+__global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(int32_t n, int32_t tbits, int32_t ntw,
+                                                            const int64_t* __restrict__ off,
+                                                            const int32_t* __restrict__ nbr,
+                                                            int32_t* __restrict__ nch) {
+  __shared__ uint32_t tbm[TB_WAVES][TB_MAXW];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t u = blockIdx.x * TB_WAVES + w;
+  if (u >= n) return;
+  uint32_t* bm = tbm[w];
+  for (int i = l; i < ntw; i += 64) bm[i] = 0u;
+  wave_sync();
+  for (int64_t e = off[u] + l; e < off[u + 1]; e += 64) {
+    const int32_t t = nbr[e] >> tbits;
+    const uint32_t bit = 1u << (t & 31);
+    if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+  }
+  wave_sync();
+  int32_t c = 0;
+  for (int i = l; i < ntw; i += 64) c += __popc(bm[i]);
+  c = wave_sum(c);
+  if (l == 0) nch[u] = c;
+}
+
+// K3 / K6: per row, per tile runs.  FILL=false: chunk sizes (row-major
+// slots).  FILL=true: write the 16-bit entries.
+template <bool FILL>
+__global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
+    int32_t n, int32_t k, int32_t tbits, int32_t ntiles, int32_t ntw,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ hend,
+    const int32_t* __restrict__ nbr, const int64_t* __restrict__ rc_ptr,
+    int32_t* __restrict__ cm_tile, int32_t* __restrict__ cm_size, int32_t* __restrict__ cm_row,
+    const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
+    uint16_t* __restrict__ ent) {
+  __shared__ uint32_t tbm[TB_WAVES][TB_MAXW];
+  __shared__ int32_t pre[TB_WAVES][TB_MAXW];
+  __shared__ int32_t cnt[TB_WAVES][TB_MAXTILES];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t u = blockIdx.x * TB_WAVES + w;
+  if (u >= n) return;
+  uint32_t* bm = tbm[w];
+  int32_t* pf = pre[w];
+  int32_t* ct = cnt[w];
+  const int64_t beg = off[u];
+  for (int i = l; i < ntw; i += 64) bm[i] = 0u;
+  wave_sync();
+  for (int64_t e = beg + l; e < off[u + 1]; e += 64) {
+    const int32_t t = nbr[e] >> tbits;
+    const uint32_t bit = 1u << (t & 31);
+    if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+  }
+  wave_sync();
+  // zero the counters of touched tiles; popcount prefix over words
+  for (int i = l; i < ntw; i += 64) {
+    uint32_t b = bm[i];
+    while (b) { int j = __ffs(b) - 1; b &= b - 1; ct[(i << 5) + j] = 0; }
+  }
+  if (l == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < ntw; ++i) { pf[i] = run; run += __popc(bm[i]); }
+  }
+  wave_sync();
+  const int64_t rbase = rc_ptr[u];
+  int32_t seg0 = 0;
+  for (int h = 1; h <= k; ++h) {
+    const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    for (int32_t b = seg0; b < seg1; b += 64) {
+      const int32_t i = b + l;
+      const bool valid = i < seg1;
+      const int32_t v = valid ? nbr[beg + i] : 0;
+      const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
+      const int32_t tprev = __shfl_up(t, 1, 64);
+      const bool start = valid && (l == 0 || tprev != t);
+      const int32_t rs = wave_incl_max(start ? l : -1);
+      const int32_t tnext = __shfl_down(t, 1, 64);
+      const bool end = valid && (l == 63 || i + 1 >= seg1 || tnext != t);
+      if (FILL && valid) {
+        const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
+        const int32_t c = pos_of_slot[rbase + rank];
+        const int64_t dst = chunk_off[c] + ct[t] + (l - rs);
+        ent[dst] = (uint16_t)((h << tbits) | (v & ((1 << tbits) - 1)));
+      }
+      wave_sync();
+      if (end) ct[t] += l - rs + 1;
+      wave_sync();
+    }
+    seg0 = seg1;
+  }
+  if (!FILL) {
+    for (int i = l; i < ntw; i += 64) {
+      uint32_t bb = bm[i];
+      int32_t r = pf[i];
+      while (bb) {
+        int j = __ffs(bb) - 1;
+        bb &= bb - 1;
+        const int32_t t = (i << 5) + j;
+        cm_tile[rbase + r] = t;
+        cm_size[rbase + r] = ct[t];
+        cm_row[rbase + r] = u;
+        r++;
+      }
+    }
+  }
+}
+
+__global__ void k_gather_sorted_chunks(int64_t m, const int32_t* __restrict__ svals,
+                                       const int32_t* __restrict__ cm_size,
+                                       const int32_t* __restrict__ cm_row,
+                                       int32_t* __restrict__ ssize, int32_t* __restrict__ chunk_row,
+                                       int32_t* __restrict__ pos_of_slot) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int32_t s = svals[c];
+  ssize[c] = (cm_size[s] + 7) & ~7;  // chunks padded to 16-byte blocks (hop 0 = padding)
+  chunk_row[c] = cm_row[s];
+  pos_of_slot[s] = (int32_t)c;
+}
+
+__global__ void k_tile_first(int64_t m, const uint64_t* __restrict__ stile,
+                             int32_t* __restrict__ tile_first) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  if (c == 0 || stile[c] != stile[c - 1]) tile_first[stile[c]] = (int32_t)c;
+}
+// unit starts: the first chunk of a tile and every UNIT_CH-th chunk after it
+__global__ void k_unit_flags(int64_t m, const uint64_t* __restrict__ stile,
+                             const int32_t* __restrict__ tile_first, int32_t* __restrict__ flag) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  flag[c] = ((c - tile_first[stile[c]]) % UNIT_CH == 0) ? 1 : 0;
+}
+__global__ void k_unit_fill(int64_t m, const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                           const uint64_t* __restrict__ stile, int32_t* __restrict__ unit_c0,
+                           int32_t* __restrict__ unit_tile) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m || !flag[c]) return;
+  unit_c0[pos[c]] = (int32_t)c;
+  unit_tile[pos[c]] = (int32_t)stile[c];
+}
+__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+
+// rho_u = sum over S(u) of w_uv (canonical sets)
+__global__ void k_rho(int32_t n, int32_t k, const int64_t* __restrict__ off,
+                      const int32_t* __restrict__ hend, const int32_t* __restrict__ nbr,
+                      const float* __restrict__ sqrtc, float scale, float* __restrict__ rho) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t u = blockIdx.x * (blockDim.x >> 6) + w;
+  if (u >= n) return;
+  float r = 0.f;
+  if (!sqrtc) {
+    if (l == 0) {
+      int32_t prev = 0;
+      for (int h = 1; h <= k; ++h) {
+        const int32_t e = hend[(int64_t)u * k + h - 1];
+        r += (float)(e - prev) / (float)(h * h);
+        prev = e;
+      }
+      rho[u] = r;
+    }
+    return;
+  }
+  const int64_t beg = off[u];
+  const float su = sqrtc[u];
+  int32_t seg0 = 0;
+  for (int h = 1; h <= k; ++h) {
+    const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    for (int32_t i = seg0 + l; i < seg1; i += 64) {
+      const float d = (float)h * (su + sqrtc[nbr[beg + i]]) * scale;
+      r += 1.f / (d * d);
+    }
+    seg0 = seg1;
+  }
+  r = wave_sum(r);
+  if (l == 0) rho[u] = r;
+}
+
+// ---- the tiled sweep
+//
+// One workgroup per work unit (<= UNIT_CH chunks of one tile).  Prologue:
+// the tile's coordinates (and sqrt c) and the unit's chunk metadata (first
+// block, slot, x_u) are staged in LDS.  Then each group of G lanes streams
+// chunks gi, gi + NG, ... one 16-byte block (8 entries) per lane per step.
+// The only global load in the loop is the entry block for the lane's next
+// step, issued unconditionally (clamped address) before the current block is
+// computed, so its latency overlaps one step of work.
+template <int G, bool COARSE, bool Q0>
+__global__ __launch_bounds__(TS_T) void k_sweep_tiled(
+    int32_t n, int32_t tbits, const int32_t* __restrict__ unit_c0,
+    const int32_t* __restrict__ unit_tile, const int64_t* __restrict__ chunk_off,
+    const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_slot,
+    const uint16_t* __restrict__ ent, const float2* __restrict__ xy,
+    const float* __restrict__ sqrtc, float scale, float alpha, float q,
+    float2* __restrict__ partial) {
+  extern __shared__ float2 sx[];
+  // per hop h: (w = 1/h^2, w*d = 1/h, alpha, h); h = 0 marks padding: all zero
+  __shared__ float4 lut[16];
+  __shared__ int32_t mblk[UNIT_CH + 1];   // first block of each chunk (absolute)
+  __shared__ int32_t mslot[UNIT_CH];
+  __shared__ float2 mxu[UNIT_CH];
+  __shared__ float mscu[COARSE ? UNIT_CH : 1];
+  const int32_t T = 1 << tbits;
+  float* ssc = reinterpret_cast<float*>(sx + T);
+  const int32_t tile = unit_tile[blockIdx.x];
+  const int32_t c0 = unit_c0[blockIdx.x], c1 = unit_c0[blockIdx.x + 1];
+  const int32_t nch = c1 - c0;
+  const int32_t v0 = tile * T;
+  const int32_t nv = min(T, n - v0);
+  for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
+    sx[i] = xy[v0 + i];
+    if (COARSE) ssc[i] = sqrtc[v0 + i];
+  }
+  for (int32_t i = threadIdx.x; i <= nch; i += TS_T) {
+    mblk[i] = (int32_t)(chunk_off[c0 + i] >> 3);
+    if (i < nch) {
+      const int32_t u = chunk_row[c0 + i];
+      mslot[i] = chunk_slot[c0 + i];
+      mxu[i] = xy[u];
+      if (COARSE) mscu[i] = sqrtc[u];
+    }
+  }
+  if (threadIdx.x < 16) {
+    const float h = (float)threadIdx.x;
+    lut[threadIdx.x] = threadIdx.x ? make_float4(1.f / (h * h), 1.f / h, alpha, h)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+  const int gl = threadIdx.x % G, gi = threadIdx.x / G;
+  constexpr int NG = TS_T / G;
+  const int32_t mask = T - 1;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4* __restrict__ ent4 = reinterpret_cast<const u32x4*>(ent);
+  int32_t ci = gi;                      // chunk (relative to the unit)
+  int32_t ae = ci < nch ? mblk[ci + 1] : 0;
+  int32_t a = ci < nch ? mblk[ci] + gl : 0;
+  bool valid = ci < nch && a < ae;
+  u32x4 blk = ent4[valid ? a : 0];
+  float2 xu = ci < nch ? mxu[ci] : make_float2(0.f, 0.f);
+  float scu = (COARSE && ci < nch) ? mscu[ci] : 0.f;
+  float px = 0.f, py = 0.f;
+  for (;;) {
+    const bool active = ci < nch;
+    if (!__any(active)) break;
+    // the group's next position: same chunk, or its next chunk if this step
+    // finishes the current one (same decision for all lanes of the group)
+    const bool sw = active && (a - gl + G >= ae);
+    int32_t a_nx = a + G;
+    bool v_nx = active && a_nx < ae;
+    int32_t ae_nx = ae;
+    if (sw) {
+      const int32_t cn = ci + NG;
+      if (cn < nch) {
+        a_nx = mblk[cn] + gl;
+        ae_nx = mblk[cn + 1];
+        v_nx = a_nx < ae_nx;
+      } else {
+        v_nx = false;
+      }
+    }
+    const u32x4 nblk = __builtin_nontemporal_load(&ent4[v_nx ? a_nx : 0]);
+    if (valid) {
+      const uint32_t wv[4] = {blk.x, blk.y, blk.z, blk.w};
+      // branch-free: decode the 8 entries, issue their LDS reads, then compute
+      float2 xv[8];
+      float4 lw[8];
+      float sc[8];
+#pragma unroll
+      for (int q2 = 0; q2 < 8; ++q2) {
+        const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
+        const uint32_t vl = pk & (uint32_t)mask;
+        xv[q2] = sx[vl];
+        lw[q2] = lut[pk >> tbits];
+        if (COARSE) sc[q2] = ssc[vl];
+      }
+#pragma unroll
+      for (int q2 = 0; q2 < 8; ++q2) {
+        const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
+        const float D2 = fmaf(dx, dx, dy * dy);
+        float w = lw[q2].x, wd = lw[q2].y;
+        if (COARSE) {
+          const float d = lw[q2].w * (scu + sc[q2]) * scale;
+          const float r = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
+          wd = r;
+          w = r * r;
+        }
+        float inv = __builtin_amdgcn_rsqf(D2);
+        inv = D2 > 0.f ? inv : 0.f;
+        float rq;
+        if (Q0) rq = inv * inv;
+        else rq = D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f;
+        // w d / D - alpha / D^(q+2); zero for padding and coincident pairs
+        const float coef = fmaf(wd, inv, -lw[q2].z * rq);
+        px = fmaf(w, xv[q2].x, px);
+        py = fmaf(w, xv[q2].y, py);
+        px = fmaf(coef, dx, px);
+        py = fmaf(coef, dy, py);
+      }
+    }
+    if (__any(sw)) {
+      const float rx = group_sum(px, G), ry = group_sum(py, G);
+      if (sw) {
+        if (gl == 0) partial[mslot[ci]] = make_float2(rx, ry);
+        px = 0.f;
+        py = 0.f;
+        ci += NG;
+        if (ci < nch) {
+          xu = mxu[ci];
+          if (COARSE) scu = mscu[ci];
+        }
+      }
+    }
+    a = a_nx;
+    ae = ae_nx;
+    valid = v_nx;
+    blk = nblk;
+  }
+}
+
+constexpr int CB_T = 256;
+constexpr int CB_G = 16;  // lanes per row in the combine
+__global__ __launch_bounds__(CB_T) void k_combine(int32_t n, const int64_t* __restrict__ rc_ptr,
+                                                  const float2* __restrict__ partial,
+                                                  const float* __restrict__ rho,
+                                                  const float2* __restrict__ xy,
+                                                  const float2* __restrict__ F, float alpha,
+                                                  float2* __restrict__ out,
+                                                  double2* __restrict__ dpart) {
+  constexpr int RPB = CB_T / CB_G;
+  __shared__ double2 red[RPB];
+  const int gl = threadIdx.x % CB_G, gi = threadIdx.x / CB_G;
+  const int32_t u = blockIdx.x * RPB + gi;
+  double2 dd = make_double2(0.0, 0.0);
+  if (u < n) {
+    float px = 0.f, py = 0.f;
+    for (int64_t s = rc_ptr[u] + gl; s < rc_ptr[u + 1]; s += CB_G) {
+      const float2 p = partial[s];
+      px += p.x;
+      py += p.y;
+    }
+    px = group_sum(px, CB_G);
+    py = group_sum(py, CB_G);
+    if (gl == 0) {
+      const float2 fu = F[u], xu = xy[u];
+      const float r = rho[u];
+      float2 xn;
+      xn.x = (px + alpha * fu.x) / r;
+      xn.y = (py + alpha * fu.y) / r;
+      out[u] = xn;
+      const double ex = (double)xn.x - (double)xu.x, ey = (double)xn.y - (double)xu.y;
+      dd.x = ex * ex + ey * ey;
+      dd.y = (double)xu.x * (double)xu.x + (double)xu.y * (double)xu.y;
+    }
+  }
+  if (gl == 0) red[gi] = dd;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < RPB; ++i) { s.x += red[i].x; s.y += red[i].y; }
+    dpart[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_sum_parts2(const double2* __restrict__ part, int32_t m,
+                                                     double* __restrict__ out) {
+  __shared__ double shx[1024], shy[1024];
+  double sx = 0.0, sy = 0.0;
+  for (int32_t i = threadIdx.x; i < m; i += 1024) { sx += part[i].x; sy += part[i].y; }
+  shx[threadIdx.x] = sx;
+  shy[threadIdx.x] = sy;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      shx[threadIdx.x] += shx[threadIdx.x + s];
+      shy[threadIdx.x] += shy[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = shx[0]; out[1] = shy[0]; }
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+bool tiled_eligible(const KhopDev& kh, int32_t tbits) {
+  const int64_t ntiles = ((int64_t)kh.n + (1 << tbits) - 1) >> tbits;
+  return kh.k <= ((1 << (16 - tbits)) - 1) && ntiles <= TB_MAXTILES && kh.total > 0;
+}
+
+hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, float* rho,
+                       hipStream_t s) {
+  k_rho<<<nblk(kh.n, 4), 256, 0, s>>>(kh.n, kh.k, kh.off, kh.hend, kh.nbr, sqrtc, (float)scale, rho);
+  return hipGetLastError();
+}
+
+hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
+                       hipStream_t s) {
+  const int32_t n = kh.n;
+  const int32_t ntiles = (int32_t)(((int64_t)n + (1 << tbits) - 1) >> tbits);
+  const int32_t ntw = (ntiles + 31) >> 5;
+  ts->n = n;
+  ts->tbits = tbits;
+  ts->ntiles = ntiles;
+  DevBuf nch, cm_tile, cm_size, cm_row, skeys, svals, ssize, flag, upos;
+  MM_TRY(nch.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(ts->b_rc_ptr.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  ts->rc_ptr = ts->b_rc_ptr.as<int64_t>();
+  k_row_tiles<<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(n, tbits, ntw, kh.off, kh.nbr, nch.as<int32_t>());
+  MM_TRY(hipGetLastError());
+  MM_TRY(scan_excl_i32(nch.as<int32_t>(), ts->rc_ptr, n, s));
+  int64_t m = 0;
+  MM_TRY(hipMemcpyAsync(&m, ts->rc_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  if (m >= (1ll << 31)) return hipErrorInvalidValue;
+  ts->nchunks = m;
+  ts->avg_chunk = (double)kh.total / (double)std::max<int64_t>(m, 1);
+  ts->built = false;
+  if (ts->avg_chunk < min_avg_chunk) return hipSuccess;  // chunks too short to pay off
+  MM_TRY(cm_tile.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(cm_size.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(cm_row.alloc(sizeof(int32_t) * (size_t)m, s));
+  k_row_chunks<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+      n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, cm_tile.as<int32_t>(),
+      cm_size.as<int32_t>(), cm_row.as<int32_t>(), nullptr, nullptr, nullptr);
+  MM_TRY(hipGetLastError());
+  // order chunks by (tile, row): stable sort of row-major slots by tile
+  MM_TRY(skeys.alloc(sizeof(uint64_t) * (size_t)m, s));
+  MM_TRY(svals.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(iota_i32(svals.as<int32_t>(), m, s));
+  MM_TRY(widen_i32_u64(cm_tile.as<int32_t>(), skeys.as<uint64_t>(), m, s));
+  int kbits = 1;
+  while ((1 << kbits) < ntiles) kbits++;
+  MM_TRY(radix_sort_pairs(skeys.as<uint64_t>(), svals.as<int32_t>(), m, kbits, s));
+  MM_TRY(ssize.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(ts->b_chunk_row.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(ts->b_chunk_off.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  ts->chunk_row = ts->b_chunk_row.as<int32_t>();
+  ts->chunk_off = ts->b_chunk_off.as<int64_t>();
+  // pos_of_slot reuses cm_tile's storage after the sort
+  int32_t* pos_of_slot = cm_tile.as<int32_t>();
+  k_gather_sorted_chunks<<<nblk(m), 256, 0, s>>>(m, svals.as<int32_t>(), cm_size.as<int32_t>(),
+                                                 cm_row.as<int32_t>(), ssize.as<int32_t>(),
+                                                 ts->chunk_row, pos_of_slot);
+  MM_TRY(scan_excl_i32(ssize.as<int32_t>(), ts->chunk_off, m, s));
+  // chunk -> row-major slot
+  MM_TRY(ts->b_chunk_slot.alloc(sizeof(int32_t) * (size_t)m, s));
+  ts->chunk_slot = ts->b_chunk_slot.as<int32_t>();
+  MM_TRY(hipMemcpyAsync(ts->chunk_slot, svals.p, sizeof(int32_t) * (size_t)m,
+                        hipMemcpyDeviceToDevice, s));
+  int64_t padded = 0;
+  MM_TRY(hipMemcpyAsync(&padded, ts->chunk_off + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  if ((padded >> 3) >= (1ll << 31)) return hipSuccess;  // block ids are int32 in the sweep
+  MM_TRY(ts->b_ent.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
+  ts->ent = ts->b_ent.as<uint16_t>();
+  MM_TRY(hipMemsetAsync(ts->ent, 0, sizeof(uint16_t) * (size_t)padded, s));
+  ts->total = kh.total;
+  ts->padded = padded;
+  k_row_chunks<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+      n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr, nullptr,
+      pos_of_slot, ts->chunk_off, ts->ent);
+  MM_TRY(hipGetLastError());
+  // work units
+  MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(upos.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  {
+    DevBuf tfirst;
+    MM_TRY(tfirst.alloc(sizeof(int32_t) * (size_t)ntiles, s));
+    k_tile_first<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>());
+    k_unit_flags<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>(),
+                                         flag.as<int32_t>());
+  }
+  MM_TRY(scan_excl_i32(flag.as<int32_t>(), upos.as<int64_t>(), m, s));
+  int64_t nu = 0;
+  MM_TRY(hipMemcpyAsync(&nu, upos.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  ts->nunits = (int32_t)nu;
+  MM_TRY(ts->b_unit_c0.alloc(sizeof(int32_t) * (size_t)(nu + 1), s));
+  MM_TRY(ts->b_unit_tile.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1), s));
+  ts->unit_c0 = ts->b_unit_c0.as<int32_t>();
+  ts->unit_tile = ts->b_unit_tile.as<int32_t>();
+  k_unit_fill<<<nblk(m), 256, 0, s>>>(m, flag.as<int32_t>(), upos.as<int64_t>(), skeys.as<uint64_t>(),
+                                      ts->unit_c0, ts->unit_tile);
+  k_set_i32<<<1, 1, 0, s>>>(ts->unit_c0 + nu, (int32_t)m);
+  MM_TRY(ts->b_partial.alloc(sizeof(float2) * (size_t)m, s));
+  ts->built = true;
+  return hipGetLastError();
+}
+
+hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
+                       const float* rho, const float* xy, const float* F, double alpha, double q,
+                       float* xy_out, double* delta2_dev, hipStream_t s) {
+  const bool coarse = level > 0 && sqrtc != nullptr;
+  const bool q0 = q == 0.0;
+  const int32_t T = 1 << ts.tbits;
+  const size_t shm = (size_t)T * (sizeof(float2) + (coarse ? sizeof(float) : 0));
+  // a group of G lanes (one 8-entry block each per step) per chunk
+  const int G = ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
+  float2* part = ts.b_partial.as<float2>();
+#define MM_TS(GG, C, Q)                                                                          \
+  do {                                                                                           \
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tiled<GG, C, Q>),          \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));           \
+    k_sweep_tiled<GG, C, Q><<<ts.nunits, TS_T, shm, s>>>(                                        \
+        ts.n, ts.tbits, ts.unit_c0, ts.unit_tile, ts.chunk_off, ts.chunk_row, ts.chunk_slot,     \
+        ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part);           \
+  } while (0)
+#define MM_TSG(GG)                                   \
+  do {                                               \
+    if (coarse) { if (q0) MM_TS(GG, true, true); else MM_TS(GG, true, false); } \
+    else { if (q0) MM_TS(GG, false, true); else MM_TS(GG, false, false); }      \
+  } while (0)
+  switch (G) {
+    case 16: MM_TSG(16); break;
+    case 8: MM_TSG(8); break;
+    default: MM_TSG(4); break;
+  }
+#undef MM_TSG
+#undef MM_TS
+  MM_TRY(hipGetLastError());
+  const int32_t nb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);
+  DevBuf dpart;
+  MM_TRY(dpart.alloc(sizeof(double2) * (size_t)nb, s));
+  k_combine<<<nb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, part, rho, (const float2*)xy, (const float2*)F,
+                                (float)alpha, (float2*)xy_out, dpart.as<double2>());
+  k_sum_parts2<<<1, 1024, 0, s>>>(dpart.as<double2>(), nb, delta2_dev);
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -49,6 +49,8 @@ def _graphs():
         "tree": lambda: synth.random_tree(5000, 2),
         "tri": synth.two_triangles,
         "hubpath700k": lambda: synth.csr_from_edges(n, src, dst),
+        "rmat15": lambda: synth.rmat(15, 8 * (1 << 15), 2),
+        "rgg30k": lambda: synth.rgg(30000, 6),
     }
 
 
@@ -114,12 +116,16 @@ def test_bh_theta0_equals_exact(mm, ctx):
     assert _far_err(a, b.astype(np.float64)) < 1e-4
 
 
-@pytest.mark.parametrize("name,k,level", [("grid32", 3, 0), ("rgg4k", 3, 0), ("rmat12", 2, 0),
-                                          ("rgg4k", 2, 1), ("tree", 3, 2)])
-def test_sweep_replay(orc, mm, ctx, name, k, level):
-    """One Jacobi iteration of Eq. 2 on identical FP32 inputs."""
+SWEEP_CASES = [("grid32", 3, 0), ("rgg4k", 3, 0), ("rmat12", 2, 0), ("rgg4k", 2, 1),
+               ("tree", 3, 2), ("rmat15", 2, 0), ("rmat15", 2, 1), ("rgg30k", 3, 0)]
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["rows", "tiled"])
+@pytest.mark.parametrize("name,k,level", SWEEP_CASES)
+def test_sweep_replay(orc, mm, ctx, name, k, level, mode):
+    """One Jacobi iteration of Eq. 2 on identical FP32 inputs, both kernels."""
     g = _graphs()[name]()
-    print(f"[sweep] {name} k={k} level={level}", flush=True)
+    print(f"[sweep] {name} n={g.n} k={k} level={level} mode={mode}", flush=True)
     rng = np.random.default_rng(7)
     x = (rng.random((g.n, 2)) * math.sqrt(g.n)).astype(np.float32)
     c = None
@@ -128,7 +134,7 @@ def test_sweep_replay(orc, mm, ctx, name, k, level):
     kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), k)
     F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
     alpha = 0.37
-    xo, d = mm.sweep(ctx, kh, x, F, alpha, 0.0, level, c, 1.0)
+    xo, d = mm.sweep(ctx, kh, x, F, alpha, 0.0, level, c, 1.0, mode=mode)
     ref = orc.khop_build(g.row_ptr, g.col, k)
     xr, dr = orc.sweep(ref, x.astype(np.float64), F.cpu().numpy().astype(np.float64), alpha,
                        0.0, level, c, 1.0)
@@ -139,13 +145,14 @@ def test_sweep_replay(orc, mm, ctx, name, k, level):
     assert abs(math.sqrt(d[0] / d[1]) - dr) <= 1e-3 * dr + 1e-7
 
 
-def test_sweep_deterministic(mm, ctx):
-    g = synth.rgg(4000, 3)
-    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), 3)
+@pytest.mark.parametrize("mode", [1, 2], ids=["rows", "tiled"])
+def test_sweep_deterministic(mm, ctx, mode):
+    g = synth.rmat(14, 8 * (1 << 14), 3)
+    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), 2)
     x = _layout_points(g.n, 1)
     F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
-    a, da = mm.sweep(ctx, kh, x, F, 0.2)
-    b, db = mm.sweep(ctx, kh, x, F, 0.2)
+    a, da = mm.sweep(ctx, kh, x, F, 0.2, mode=mode)
+    b, db = mm.sweep(ctx, kh, x, F, 0.2, mode=mode)
     assert (a == b).all().item() and da == db
 
 
