@@ -69,7 +69,7 @@ struct TiledSet {
   double avg_chunk = 0;
   bool built = false;
   int64_t* rc_ptr = nullptr;     // n+1: row-major chunk slots of each row
-  int32_t* chunk_row = nullptr;  // chunks in (tile, row) order
+  int32_t* chunk_row = nullptr;  // chunks by tile, largest first within a tile
   int64_t* chunk_off = nullptr;  // nchunks+1: entry offsets (multiples of 8)
   int32_t* chunk_slot = nullptr; // row-major slot of each chunk
   uint16_t* ent = nullptr;       // (hop << tbits) | (v - tile * 2^tbits)

@@ -162,26 +162,33 @@ __global__ void k_gather_sorted_chunks(int64_t m, const int32_t* __restrict__ sv
   pos_of_slot[s] = (int32_t)c;
 }
 
-__global__ void k_tile_first(int64_t m, const uint64_t* __restrict__ stile,
+__global__ void k_chunk_keys(int64_t m, const int32_t* __restrict__ cm_tile,
+                             const int32_t* __restrict__ cm_size, uint64_t* __restrict__ keys) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  keys[c] = ((uint64_t)(uint32_t)cm_tile[c] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)cm_size[c]);
+}
+__global__ void k_tile_first(int64_t m, const uint64_t* __restrict__ skey,
                              int32_t* __restrict__ tile_first) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m) return;
-  if (c == 0 || stile[c] != stile[c - 1]) tile_first[stile[c]] = (int32_t)c;
+  const uint32_t t = (uint32_t)(skey[c] >> 32);
+  if (c == 0 || (uint32_t)(skey[c - 1] >> 32) != t) tile_first[t] = (int32_t)c;
 }
 // unit starts: the first chunk of a tile and every UNIT_CH-th chunk after it
-__global__ void k_unit_flags(int64_t m, const uint64_t* __restrict__ stile,
+__global__ void k_unit_flags(int64_t m, const uint64_t* __restrict__ skey,
                              const int32_t* __restrict__ tile_first, int32_t* __restrict__ flag) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m) return;
-  flag[c] = ((c - tile_first[stile[c]]) % UNIT_CH == 0) ? 1 : 0;
+  flag[c] = ((c - tile_first[skey[c] >> 32]) % UNIT_CH == 0) ? 1 : 0;
 }
 __global__ void k_unit_fill(int64_t m, const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
-                           const uint64_t* __restrict__ stile, int32_t* __restrict__ unit_c0,
+                           const uint64_t* __restrict__ skey, int32_t* __restrict__ unit_c0,
                            int32_t* __restrict__ unit_tile) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m || !flag[c]) return;
   unit_c0[pos[c]] = (int32_t)c;
-  unit_tile[pos[c]] = (int32_t)stile[c];
+  unit_tile[pos[c]] = (int32_t)(skey[c] >> 32);
 }
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 
@@ -472,10 +479,13 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(skeys.alloc(sizeof(uint64_t) * (size_t)m, s));
   MM_TRY(svals.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(iota_i32(svals.as<int32_t>(), m, s));
-  MM_TRY(widen_i32_u64(cm_tile.as<int32_t>(), skeys.as<uint64_t>(), m, s));
+  // chunks of a tile in descending size (stable: ties keep row order), so the
+  // chunks of a work unit have similar sizes and its lane groups stay balanced
+  k_chunk_keys<<<nblk(m), 256, 0, s>>>(m, cm_tile.as<int32_t>(), cm_size.as<int32_t>(),
+                                       skeys.as<uint64_t>());
   int kbits = 1;
   while ((1 << kbits) < ntiles) kbits++;
-  MM_TRY(radix_sort_pairs(skeys.as<uint64_t>(), svals.as<int32_t>(), m, kbits, s));
+  MM_TRY(radix_sort_pairs(skeys.as<uint64_t>(), svals.as<int32_t>(), m, 32 + kbits, s));
   MM_TRY(ssize.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(ts->b_chunk_row.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(ts->b_chunk_off.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
