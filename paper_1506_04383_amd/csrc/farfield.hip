@@ -247,20 +247,23 @@ __global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
   }
 }
 
-__global__ void k_first_at(const uint64_t* __restrict__ keys, int32_t N, int32_t* __restrict__ first_at) {
+__global__ void k_first_at(const uint64_t* __restrict__ keys, const int32_t* __restrict__ Np,
+                           int32_t* __restrict__ first_at) {
   int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
+  if (p >= *Np) return;
   int32_t f = (int32_t)(keys[p] >> 5);
   if (p == 0 || (int32_t)(keys[p - 1] >> 5) != f) first_at[f] = p;
 }
 
 __global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* __restrict__ tmp,
-                                 int32_t N, int32_t n, const int32_t* __restrict__ first_at,
+                                 const int32_t* __restrict__ Np, int32_t n,
+                                 const int32_t* __restrict__ first_at,
                                  const double* __restrict__ px, const double* __restrict__ py,
                                  const uint2* __restrict__ ixy, BHNode* __restrict__ nodes,
                                  int64_t* __restrict__ export_nodes,
                                  const uint64_t* __restrict__ codes) {
   int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t N = *Np;
   if (p >= N) return;
   int4 t = tmp[vals[p]];
   const int32_t first = t.x, last = t.y, depth = t.z, leaf = t.w;
@@ -301,12 +304,13 @@ constexpr int TR_WAVES = 4;
 
 template <bool STATS>
 __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
-    const BHNode* __restrict__ nodes, int32_t N, const float* __restrict__ xsx,
+    const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np, const float* __restrict__ xsx,
     const float* __restrict__ xsy, const uint2* __restrict__ ixy, const int32_t* __restrict__ order,
     int32_t n, float q, double theta2, float2* __restrict__ F, unsigned long long* __restrict__ stats) {
   const int l = lane_id();
   const int32_t i = (blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 + l;
   if ((blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 >= n) return;
+  const int32_t N = *Np;
   const bool valid = i < n;
   const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
@@ -445,19 +449,21 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
     k_fsum_scan<<<nps, PS_T, 0, s>>>(a, n, pparts.as<double>(), out);
   }
   MM_TRY(hipMemsetAsync(w->counter.p, 0, sizeof(int32_t), s));
+  // at most n leaves and n - 1 internal nodes; unused slots keep the all-ones
+  // key and sort last, so the node count never has to reach the host
+  const int32_t NMAX = 2 * n;
+  MM_TRY(hipMemsetAsync(w->nkeys.p, 0xFF, sizeof(uint64_t) * (size_t)NMAX, s));
   k_emit_nodes<<<(n + 255) / 256, 256, 0, s>>>(w->codes.as<uint64_t>(), n, w->nkeys.as<uint64_t>(),
                                                w->nvals.as<int32_t>(), w->ntmp.as<int4>(),
                                                w->counter.as<int32_t>());
   MM_TRY(hipGetLastError());
-  int32_t N = 0;
-  MM_TRY(hipMemcpyAsync(&N, w->counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  MM_TRY(hipStreamSynchronize(s));
-  int kbits = 5;
-  while ((1ll << (kbits - 5)) < (int64_t)n) kbits++;
-  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), N, kbits, s));
-  k_first_at<<<(N + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), N, w->first_at.as<int32_t>());
-  k_finalize_nodes<<<(N + 255) / 256, 256, 0, s>>>(
-      w->nvals.as<int32_t>(), w->ntmp.as<int4>(), N, n, w->first_at.as<int32_t>(),
+  int kbits = 6;
+  while ((1ll << (kbits - 6)) < (int64_t)n) kbits++;
+  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), NMAX, kbits, s));
+  const int32_t* Np = w->counter.as<int32_t>();
+  k_first_at<<<(NMAX + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), Np, w->first_at.as<int32_t>());
+  k_finalize_nodes<<<(NMAX + 255) / 256, 256, 0, s>>>(
+      w->nvals.as<int32_t>(), w->ntmp.as<int4>(), Np, n, w->first_at.as<int32_t>(),
       w->px.as<double>(), w->py.as<double>(), w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
       w->codes.as<uint64_t>());
   MM_TRY(hipGetLastError());
@@ -466,12 +472,12 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
   const int32_t nblk = (nw + TR_WAVES - 1) / TR_WAVES;
   if (count_stats)
     k_traverse<true><<<nblk, 64 * TR_WAVES, 0, s>>>(
-        w->nodes.as<BHNode>(), N, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
+        w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
         w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F,
         w->statc.as<unsigned long long>());
   else
     k_traverse<false><<<nblk, 64 * TR_WAVES, 0, s>>>(
-        w->nodes.as<BHNode>(), N, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
+        w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
         w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F, nullptr);
   MM_TRY(hipGetLastError());
   if (codes_out) {
@@ -484,6 +490,11 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
   if (order_out)
     MM_TRY(hipMemcpyAsync(order_out, w->order.p, sizeof(int32_t) * (size_t)n,
                           hipMemcpyDeviceToDevice, s));
+  int32_t N = 0;
+  if (n_nodes_out || st) {
+    MM_TRY(hipMemcpyAsync(&N, w->counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_TRY(hipStreamSynchronize(s));
+  }
   if (n_nodes_out) *n_nodes_out = N;
   if (st) {
     st->nodes = N;

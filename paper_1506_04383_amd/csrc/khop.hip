@@ -23,7 +23,7 @@ constexpr int KS_CAP = 1024;     // list capacity per wave (entries)
 constexpr int KS_WAVES = 2;      // waves per block
 constexpr int KB_T = 512;        // threads per big-row block
 constexpr int KB_NW = KB_T / 64;
-constexpr int KB_LDS_WORDS = 19968;  // per bitmap (2 bitmaps in LDS => n <= 638976)
+constexpr int KB_LDS_WORDS = 19968;  // 2 x this many bitmap words fit in a CU's LDS
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -147,7 +147,10 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
 }
 
 // ---- big rows: bitmap BFS, one workgroup per source
-template <bool FILL, bool LDSBM>
+// ONE (k == 2): a single bitmap; the hop-2 candidates are marked without a
+// visited test and u and N(u) are cleared afterwards, which halves the LDS
+// footprint (two workgroups per CU for n up to ~650K).
+template <bool FILL, bool LDSBM, bool ONE>
 __global__ __launch_bounds__(KB_T) void k_khop_big(
     int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t k,
     const int32_t* __restrict__ rows, int32_t nrows, const int64_t* __restrict__ off,
@@ -156,11 +159,12 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
   extern __shared__ uint32_t dyn[];
   __shared__ int32_t wtot[KB_NW + 1];
   const int32_t W = (n + 31) >> 5;
-  uint32_t* VIS = LDSBM ? dyn : gbm + (size_t)blockIdx.x * 2 * (size_t)W;
-  uint32_t* NEW = VIS + W;
+  const int32_t NB = ONE ? 1 : 2;
+  uint32_t* VIS = LDSBM ? dyn : gbm + (size_t)blockIdx.x * NB * (size_t)W;
+  uint32_t* NEW = ONE ? VIS : VIS + W;
   int32_t* scratch = gscratch ? gscratch + (size_t)blockIdx.x * (size_t)n : nullptr;
   const int t = threadIdx.x, wv = t >> 6, l = lane_id();
-  for (int32_t i = t; i < 2 * W; i += KB_T) VIS[i] = 0;
+  for (int32_t i = t; i < NB * W; i += KB_T) VIS[i] = 0;
   __syncthreads();
   // word chunk per wave for the ordered extraction
   const int32_t CW = ((W + KB_NW - 1) / KB_NW + 63) & ~63;
@@ -172,10 +176,10 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     // hop 1
     for (int32_t i = t; i < deg; i += KB_T) {
       int32_t v = col[beg + i];
-      atomicOr(&VIS[v >> 5], 1u << (v & 31));
+      if (!ONE) atomicOr(&VIS[v >> 5], 1u << (v & 31));
       if (FILL) nbr[o + i] = v;
     }
-    if (t == 0) atomicOr(&VIS[u >> 5], 1u << (u & 31));
+    if (!ONE && t == 0) atomicOr(&VIS[u >> 5], 1u << (u & 31));
     int64_t total = deg;
     if (!FILL && t == 0) hend[(int64_t)u * k] = deg;
     // frontier: hop-(h-1) list
@@ -190,10 +194,23 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
         for (int32_t e = b0 + l; e < b1; e += 64) {
           int32_t v = col[e];
           uint32_t bit = 1u << (v & 31);
-          if (!(VIS[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
+          if (ONE) {
+            if (!(NEW[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
+          } else {
+            if (!(VIS[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
+          }
         }
       }
       __syncthreads();
+      if (ONE) {
+        // drop hop 0 and hop 1 from the candidates
+        if (t == 0) atomicAnd(&NEW[u >> 5], ~(1u << (u & 31)));
+        for (int32_t i = t; i < deg; i += KB_T) {
+          const int32_t v = col[beg + i];
+          atomicAnd(&NEW[v >> 5], ~(1u << (v & 31)));
+        }
+        __syncthreads();
+      }
       // count per wave chunk
       int32_t c = 0;
       for (int32_t b = wlo; b < whi; b += 64) {
@@ -229,7 +246,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
             }
           }
           NEW[wi] = 0u;
-          if (!last) VIS[wi] |= bits;
+          if (!ONE && !last) VIS[wi] |= bits;
         }
         run += __shfl(inc, 63, 64);
       }
@@ -239,9 +256,11 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
       F = dst;
       flen = cnt_h;
     }
-    // clear VIS: u and hops 1..k-1
-    if (t == 0) VIS[u >> 5] = 0u;
-    for (int32_t i = t; i < deg; i += KB_T) VIS[col[beg + i] >> 5] = 0u;
+    // clear VIS: u and hops 1..k-1 (with ONE the extraction already cleared it)
+    if (!ONE) {
+      if (t == 0) VIS[u >> 5] = 0u;
+      for (int32_t i = t; i < deg; i += KB_T) VIS[col[beg + i] >> 5] = 0u;
+    }
     if (k >= 3) {
       // hops 2..k-1 are in the output (fill) or were merged into VIS from
       // scratch lists that are gone (count) -> clear the whole bitmap
@@ -299,34 +318,42 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   int64_t nbig = 0;
   MM_TRY(hipMemcpyAsync(&nbig, bigpos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
-  const bool lds_bm = ((n + 31) >> 5) <= KB_LDS_WORDS;
+  const int32_t W = (n + 31) >> 5;
+  const bool one = (k == 2);
+  const int32_t nbw = (one ? 1 : 2) * W;  // bitmap words per workgroup
+  const bool lds_bm = nbw <= 2 * KB_LDS_WORDS;
   int dev = 0, ncu = 0;
   MM_TRY(hipGetDevice(&dev));
   MM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int32_t W = (n + 31) >> 5;
-  const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * (lds_bm ? 1 : 2));
+  const size_t shm = lds_bm ? sizeof(uint32_t) * (size_t)nbw : 0;
+  const int per_cu = lds_bm ? (int)std::max<size_t>(1, (160 * 1024 - 256) / std::max<size_t>(shm, 1)) : 2;
+  const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * std::min(per_cu, 4));
   DevBuf gbm, gscr;
+#define MM_BIG(FILLV, LDSV, ONEV, ...)                                                          \
+  do {                                                                                         \
+    if (LDSV)                                                                                  \
+      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_khop_big<FILLV, LDSV, ONEV>), \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));       \
+    k_khop_big<FILLV, LDSV, ONEV><<<slots, KB_T, LDSV ? shm : 0, s>>>(__VA_ARGS__);           \
+  } while (0)
+#define MM_BIG_ANY(FILLV, ...)                                                          \
+  do {                                                                                 \
+    if (lds_bm) {                                                                      \
+      if (one) MM_BIG(FILLV, true, true, __VA_ARGS__);                                 \
+      else MM_BIG(FILLV, true, false, __VA_ARGS__);                                    \
+    } else {                                                                           \
+      if (one) MM_BIG(FILLV, false, true, __VA_ARGS__);                                \
+      else MM_BIG(FILLV, false, false, __VA_ARGS__);                                   \
+    }                                                                                  \
+  } while (0)
   if (nbig > 0) {
     MM_TRY(rows.alloc(sizeof(int32_t) * (size_t)nbig, s));
     k_collect_big<<<(n + 255) / 256, 256, 0, s>>>(big.as<int32_t>(), n, bigpos.as<int64_t>(),
                                                   rows.as<int32_t>());
-    if (!lds_bm) MM_TRY(gbm.alloc(sizeof(uint32_t) * 2 * (size_t)W * (size_t)slots, s));
+    if (!lds_bm) MM_TRY(gbm.alloc(sizeof(uint32_t) * (size_t)nbw * (size_t)slots, s));
     if (k >= 3) MM_TRY(gscr.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
-    const size_t shm = lds_bm ? sizeof(uint32_t) * 2 * (size_t)W : 0;
-    if (lds_bm) {
-      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_khop_big<false, true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_khop_big<true, true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    }
-    if (lds_bm)
-      k_khop_big<false, true><<<slots, KB_T, shm, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
-                                                      nullptr, out->hend, nullptr, cnt.as<int32_t>(),
-                                                      nullptr, gscr.as<int32_t>());
-    else
-      k_khop_big<false, false><<<slots, KB_T, 0, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
-                                                      nullptr, out->hend, nullptr, cnt.as<int32_t>(),
-                                                      gbm.as<uint32_t>(), gscr.as<int32_t>());
+    MM_BIG_ANY(false, n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig, nullptr, out->hend,
+               nullptr, cnt.as<int32_t>(), gbm.as<uint32_t>(), gscr.as<int32_t>());
     MM_TRY(hipGetLastError());
   }
   MM_TRY(scan_excl_i32(cnt.as<int32_t>(), out->off, n, s));
@@ -338,17 +365,12 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
                                                  nullptr, big.as<int32_t>());
   MM_TRY(hipGetLastError());
   if (nbig > 0) {
-    const size_t shm = lds_bm ? sizeof(uint32_t) * 2 * (size_t)W : 0;
-    if (lds_bm)
-      k_khop_big<true, true><<<slots, KB_T, shm, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
-                                                     out->off, out->hend, out->nbr, nullptr, nullptr,
-                                                     nullptr);
-    else
-      k_khop_big<true, false><<<slots, KB_T, 0, s>>>(n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig,
-                                                     out->off, out->hend, out->nbr, nullptr,
-                                                     gbm.as<uint32_t>(), nullptr);
+    MM_BIG_ANY(true, n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig, out->off, out->hend,
+               out->nbr, nullptr, gbm.as<uint32_t>(), nullptr);
     MM_TRY(hipGetLastError());
   }
+#undef MM_BIG_ANY
+#undef MM_BIG
   return hipGetLastError();
 }
 

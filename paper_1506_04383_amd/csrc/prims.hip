@@ -69,8 +69,29 @@ __global__ void k_set_last(int64_t* out, int64_t n, const int64_t* part, int64_t
   out[n] = part[m];
 }
 
+// Small inputs: one workgroup walks the array in 1024-element steps.
+template <typename Tin>
+__global__ __launch_bounds__(1024) void k_scan_small(const Tin* __restrict__ in, int64_t n,
+                                                     int64_t* __restrict__ out) {
+  __shared__ int64_t sh[1024 / 64 + 1];
+  int64_t carry = 0;
+  for (int64_t b = 0; b < n; b += 1024) {
+    const int64_t j = b + threadIdx.x;
+    const int64_t v = j < n ? (int64_t)in[j] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t>(v, sh, &tot);
+    if (j < n) out[j] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
 template <typename Tin>
 hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= (1 << 16)) {
+    k_scan_small<Tin><<<1, 1024, 0, s>>>(in, n, out);
+    return hipGetLastError();
+  }
   int64_t m = (n + SCAN_TILE - 1) / SCAN_TILE;
   DevBuf part;
   MM_TRY(part.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
