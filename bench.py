@@ -46,6 +46,30 @@ def sweep_bytes(n: int, k: int, entries: int, coarse: bool) -> int:
     return 4 * entries + n * per_v + 8 * n
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_tiled_rmat20_traffic.md")
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per finest-level sweep step from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE passes (copy-calibrated), or None when the workload
+    differs or the kernel source changed since the counters were taken."""
+    import hashlib
+
+    if workload != "rmat20" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            key, _, val = line.partition(":")
+            kv[key.strip()] = val.strip()
+    src = os.path.join(ROOT, kv.get("kernel_source", "-"))
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("kernel_source_sha256"):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(g, k, x, F, alpha, seconds=15.0, seed=0):
     """The FP64 oracle's update of sampled rows (each row's stress set found by
     BFS, then Eq. 2), timed on the host cores."""
@@ -167,9 +191,11 @@ def main():
         "time_split_ms": {"sweep": total_sweep_ms, "far_field": total_far_ms,
                           "khop": st["t_khop_ms"], "coarsen": st["t_coarsen_ms"],
                           "other": st["t_other_ms"]},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep (finest level)",
+        "per_level": [[l["n"], l["khop_entries"], l["iters"], round(l["sweep_ms"], 1),
+                       round(l["far_ms"], 1)] for l in st["per_level"]],
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_tiled + k_combine (finest-level sweep step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "bytes_per_launch": bytes0, "avg_ms": sweep_avg_ms},
     }
     if not args.no_objective:
