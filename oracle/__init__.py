@@ -69,6 +69,10 @@ def lib():
         L.orc_objective.argtypes = [C.c_int32, C.c_int32, C.c_int32, i64p, i32p, i32p, vp,
                                     C.c_double, f64p, C.c_double, f64p]
         L.orc_full_stress.argtypes = [C.c_int32, i32p, i32p, f64p, f64p]
+        L.orc_far_samples.argtypes = [C.c_int32, f64p, C.c_double, C.c_int64, i32p, i64p, f64p,
+                                      f64p, f64p, i64p]
+        L.orc_bh_learned.argtypes = [C.c_int32, f64p, C.c_double, f64p, f64p]
+        L.orc_mlp_forward.argtypes = [f64p, C.c_int64, f64p, f64p]
         _lib = L
     return _lib
 
@@ -171,6 +175,57 @@ def barnes_hut(xy, theta: float, q: float = 0.0) -> BHResult:
     nn = int(stats[3])
     return BHResult(F.reshape(n, 2), codes, order, nodes[:5 * nn].reshape(nn, 5),
                     int(stats[0]), int(stats[1]), int(stats[2]))
+
+
+@dataclass
+class Samples:
+    """Accepted (target, cell) pairs of a Barnes-Hut traversal with features,
+    exact residual targets (h units) and kappa e, in (u, visit) order."""
+
+    u: np.ndarray
+    node: np.ndarray
+    feat: np.ndarray    # (count, 8)
+    target: np.ndarray  # (count, 2)
+    coef: np.ndarray    # (count, 2)
+
+
+def far_samples(xy, theta: float) -> Samples:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    n = xy.size // 2
+    cnt = np.zeros(1, dtype=np.int64)
+    z32, z64, zf = (np.zeros(1, dtype=np.int32), np.zeros(1, dtype=np.int64), np.zeros(8))
+    if lib().orc_far_samples(n, xy, theta, 0, z32, z64, zf, zf, zf, cnt) != 0:
+        raise MemoryError("far_samples")
+    m = int(cnt[0])
+    u = np.zeros(max(m, 1), dtype=np.int32)
+    node = np.zeros(max(m, 1), dtype=np.int64)
+    feat = np.zeros(8 * max(m, 1))
+    tgt = np.zeros(2 * max(m, 1))
+    coef = np.zeros(2 * max(m, 1))
+    if lib().orc_far_samples(n, xy, theta, m, u, node, feat, tgt, coef, cnt) != 0:
+        raise MemoryError("far_samples")
+    return Samples(u[:m], node[:m], feat[:8 * m].reshape(m, 8), tgt[:2 * m].reshape(m, 2),
+                   coef[:2 * m].reshape(m, 2))
+
+
+def barnes_hut_learned(xy, theta: float, weights) -> np.ndarray:
+    """Barnes-Hut far field (q = 0) with the learned cell correction."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    n = xy.size // 2
+    F = np.zeros(2 * n)
+    if lib().orc_bh_learned(n, xy, theta, w, F) != 0:
+        raise MemoryError("bh_learned")
+    return F.reshape(n, 2)
+
+
+def mlp_forward_c(weights, feat) -> np.ndarray:
+    """The C forward pass used inside barnes_hut_learned."""
+    w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    f = np.ascontiguousarray(feat, dtype=np.float64).reshape(-1)
+    out = np.zeros(f.size // 8 * 2)
+    lib().orc_mlp_forward(w, f.size // 8, f, out)
+    return out.reshape(-1, 2)
 
 
 def sweep(kh: KHop, x, F, alpha: float, q: float = 0.0, level: int = 0,
@@ -325,6 +380,7 @@ class Params:
     lp_rounds: int = 10
     coarse_dist_scale: float = 1.0
     seed: int = 1
+    mlp: np.ndarray | None = None  # far-field correction weights (q = 0, theta >= 0)
 
 
 def schedule(alpha0, alpha_decay, alpha_min):
@@ -382,6 +438,8 @@ def hierarchy(g0: Level, p: Params):
 def far_field(x, p: Params):
     if p.theta < 0:
         return farfield_exact(x, p.q)
+    if p.mlp is not None:
+        return barnes_hut_learned(x, p.theta, p.mlp)
     return barnes_hut(x, p.theta, p.q).F
 
 

@@ -200,6 +200,7 @@ typedef struct {
     int64_t count;
     uint32_t ox, oy;    /* integer origin of the cell (low 24-depth bits clear) */
     double cx, cy;      /* centre of mass, FP64 */
+    double mxx, myy, mxy; /* central second moments per unit mass */
     int32_t child[4];   /* node ids, -1 if empty (internal nodes only) */
     uint64_t prefix;    /* code >> 2*(24-depth) */
 } bh_node;
@@ -270,6 +271,13 @@ static int64_t bh_build(bh_tree* t, const int32_t* pts, int64_t first, int64_t c
         sx += xy[2 * p]; sy += xy[2 * p + 1];
     }
     nd->cx = sx / (double)cnt; nd->cy = sy / (double)cnt;
+    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+    for (int64_t i = 0; i < cnt; ++i) {
+        int32_t p = pts[first + i];
+        double dx = xy[2 * p] - nd->cx, dy = xy[2 * p + 1] - nd->cy;
+        sxx += dx * dx; syy += dy * dy; sxy += dx * dy;
+    }
+    nd->mxx = sxx / (double)cnt; nd->myy = syy / (double)cnt; nd->mxy = sxy / (double)cnt;
     if (nd->leaf) return id;
     int sh = 23 - depth;
     int64_t pos = first;
@@ -299,6 +307,7 @@ typedef struct {
     const uint32_t *ix, *iy;
     const double* xy;
     double q, theta2;
+    double xmin, ymin, scale; /* box origin and quanta per unit length */
 } bh_ctx;
 
 static void bh_visit(const bh_ctx* c, int64_t id, int32_t u, double* fx, double* fy,
@@ -361,9 +370,22 @@ static int cmp_code_id(const void* a, const void* b) {
     return (x->id > y->id) - (x->id < y->id);
 }
 
-int orc_bh(int32_t n, const double* xy, double q, double theta, double* F,
-           uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out, int64_t node_cap,
-           int64_t* stats) {
+typedef struct {
+    bh_tree t;
+    int64_t root;
+    uint32_t *ix, *iy;
+    int32_t* pts;
+    double xmin, ymin, scale;
+} bh_setup;
+
+static void bh_setup_free(bh_setup* b) {
+    free(b->t.nodes); free(b->ix); free(b->iy); free(b->pts);
+}
+
+/* Box, quantisation, (code, id) order and the quadtree of xy. */
+static int bh_setup_build(int32_t n, const double* xy, uint64_t* codes_out, int32_t* order_out,
+                          bh_setup* b) {
+    memset(b, 0, sizeof(*b));
     double xmin = xy[0], xmax = xy[0], ymin = xy[1], ymax = xy[1];
     for (int32_t v = 1; v < n; ++v) {
         if (xy[2 * v] < xmin) xmin = xy[2 * v];
@@ -379,11 +401,12 @@ int orc_bh(int32_t n, const double* xy, double q, double theta, double* F,
         e = (m == 0.5) ? ex - 1 : ex;
     }
     double scale = ldexp(1.0, 24 - e);
-    uint32_t* ix = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
-    uint32_t* iy = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+    b->xmin = xmin; b->ymin = ymin; b->scale = scale;
+    b->ix = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+    b->iy = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+    b->pts = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     code_id* ci = (code_id*)malloc(sizeof(code_id) * (size_t)n);
-    int32_t* pts = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    if (!ix || !iy || !ci || !pts) { free(ix); free(iy); free(ci); free(pts); return -1; }
+    if (!b->ix || !b->iy || !ci || !b->pts) { free(ci); bh_setup_free(b); return -1; }
     for (int32_t v = 0; v < n; ++v) {
         double fxq = floor((xy[2 * v] - xmin) * scale);
         double fyq = floor((xy[2 * v + 1] - ymin) * scale);
@@ -391,35 +414,227 @@ int orc_bh(int32_t n, const double* xy, double q, double theta, double* F,
         if (fyq > 16777215.0) fyq = 16777215.0;
         if (fxq < 0.0) fxq = 0.0;
         if (fyq < 0.0) fyq = 0.0;
-        ix[v] = (uint32_t)fxq; iy[v] = (uint32_t)fyq;
-        ci[v].code = interleave24(ix[v], iy[v]);
+        b->ix[v] = (uint32_t)fxq; b->iy[v] = (uint32_t)fyq;
+        ci[v].code = interleave24(b->ix[v], b->iy[v]);
         ci[v].id = v;
         if (codes_out) codes_out[v] = ci[v].code;
     }
     qsort(ci, (size_t)n, sizeof(code_id), cmp_code_id);
-    for (int32_t i = 0; i < n; ++i) pts[i] = ci[i].id;
-    if (order_out) memcpy(order_out, pts, sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) b->pts[i] = ci[i].id;
+    if (order_out) memcpy(order_out, b->pts, sizeof(int32_t) * (size_t)n);
     free(ci);
+    b->root = bh_build(&b->t, b->pts, 0, n, b->ix, b->iy, xy, 0, 0u, 0u);
+    if (b->root < 0 || b->t.failed) { bh_setup_free(b); return -1; }
+    return 0;
+}
 
-    bh_tree t = {NULL, 0, 0, 0};
-    int64_t root = bh_build(&t, pts, 0, n, ix, iy, xy, 0, 0u, 0u);
-    if (root < 0 || t.failed) { free(t.nodes); free(ix); free(iy); free(pts); return -1; }
-
-    bh_ctx c = {&t, pts, ix, iy, xy, q, theta * theta};
+int orc_bh(int32_t n, const double* xy, double q, double theta, double* F,
+           uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out, int64_t node_cap,
+           int64_t* stats) {
+    bh_setup b;
+    if (bh_setup_build(n, xy, codes_out, order_out, &b) != 0) return -1;
+    bh_ctx c = {&b.t, b.pts, b.ix, b.iy, xy, q, theta * theta, b.xmin, b.ymin, b.scale};
     int64_t acc = 0, pairs = 0, coinc = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : acc, pairs, coinc)
     for (int32_t u = 0; u < n; ++u) {
         double fx = 0.0, fy = 0.0;
-        bh_visit(&c, root, u, &fx, &fy, &acc, &pairs, &coinc);
+        bh_visit(&c, b.root, u, &fx, &fy, &acc, &pairs, &coinc);
         F[2 * u] = fx; F[2 * u + 1] = fy;
     }
     if (nodes_out) {
         int64_t k = 0;
-        bh_preorder(&t, root, nodes_out, node_cap, &k);
+        bh_preorder(&b.t, b.root, nodes_out, node_cap, &k);
     }
-    if (stats) { stats[0] = acc; stats[1] = pairs; stats[2] = coinc; stats[3] = t.count; }
-    free(t.nodes); free(ix); free(iy); free(pts);
+    if (stats) { stats[0] = acc; stats[1] = pairs; stats[2] = coinc; stats[3] = b.t.count; }
+    bh_setup_free(&b);
     return 0;
+}
+
+/* ------------------------------------------------ learned far field (q = 0)
+ * A cell C accepted for target u contributes m r(x_u - com) plus a learned
+ * correction kappa (h0 e + h1 p): e = (x_u - com)/d, p = e rotated by +90
+ * degrees, kappa = m t^2 / d with t = s/d, s the side of C's tight cell,
+ * and h = MLP(features).  The scaling makes h the cell's dimensionless
+ * multipole coefficient: for a far target h tends to
+ * (mu_ee - mu_pp, -2 mu_ep), the quadrupole term of the expansion of
+ * sum_v 1/conj(z - w_v). */
+
+#define MLP_IN 8
+#define MLP_H 64
+#define MLP_OUT 2
+
+/* Features of (u, C): t, centroid offset from the cell centre along e and p
+ * (in units of s), second central moments per unit mass rotated into the
+ * (e, p) frame (units of s^2), log2(m)/16, and a zero pad.  *ke receives
+ * kappa e (kappa p is its rotation).  Returns 0 when x_u == com. */
+static int cell_features(const bh_ctx* c, const bh_node* nd, double xu, double yu, double* f,
+                         double* kex, double* key) {
+    double dx = xu - nd->cx, dy = yu - nd->cy;
+    double d2 = dx * dx + dy * dy;
+    if (d2 == 0.0) return 0;
+    double d = sqrt(d2);
+    double ex = dx / d, ey = dy / d, px = -ey, py = ex;
+    double S = ldexp(1.0, 24 - nd->depth);
+    double s = S / c->scale;
+    double gx = c->xmin + ((double)nd->ox + 0.5 * S) / c->scale;
+    double gy = c->ymin + ((double)nd->oy + 0.5 * S) / c->scale;
+    double ox = nd->cx - gx, oy = nd->cy - gy;
+    double s2 = s * s;
+    double t = s / d;
+    f[0] = t;
+    f[1] = (ox * ex + oy * ey) / s;
+    f[2] = (ox * px + oy * py) / s;
+    f[3] = (ex * ex * nd->mxx + 2.0 * ex * ey * nd->mxy + ey * ey * nd->myy) / s2;
+    f[4] = (px * px * nd->mxx + 2.0 * px * py * nd->mxy + py * py * nd->myy) / s2;
+    f[5] = (ex * px * nd->mxx + (ex * py + ey * px) * nd->mxy + ey * py * nd->myy) / s2;
+    f[6] = log2((double)nd->count) / 16.0;
+    f[7] = 0.0;
+    double kappa = (double)nd->count * t * t / d;
+    *kex = kappa * ex;
+    *key = kappa * ey;
+    return 1;
+}
+
+/* Weights: W1[64][8], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]. */
+static void mlp_forward(const double* w, const double* f, double* h) {
+    const double* W1 = w;
+    const double* b1 = W1 + MLP_H * MLP_IN;
+    const double* W2 = b1 + MLP_H;
+    const double* b2 = W2 + MLP_H * MLP_H;
+    const double* W3 = b2 + MLP_H;
+    const double* b3 = W3 + MLP_OUT * MLP_H;
+    double a1[MLP_H], a2[MLP_H];
+    for (int o = 0; o < MLP_H; ++o) {
+        double z = b1[o];
+        for (int i = 0; i < MLP_IN; ++i) z += W1[o * MLP_IN + i] * f[i];
+        a1[o] = z > 0.0 ? z : 0.0;
+    }
+    for (int o = 0; o < MLP_H; ++o) {
+        double z = b2[o];
+        for (int i = 0; i < MLP_H; ++i) z += W2[o * MLP_H + i] * a1[i];
+        a2[o] = z > 0.0 ? z : 0.0;
+    }
+    for (int o = 0; o < MLP_OUT; ++o) {
+        double z = b3[o];
+        for (int i = 0; i < MLP_H; ++i) z += W3[o * MLP_H + i] * a2[i];
+        h[o] = z;
+    }
+}
+
+typedef struct {
+    int64_t cap, count;
+    int32_t* u;
+    int64_t* node;
+    double *feat, *target, *coef;
+} sample_sink;
+
+/* Depth-first visit as bh_visit (q = 0).  Leaves add exact terms; an accepted
+ * cell adds its plain term and, when `w` is given, the learned correction,
+ * or, when `sk` is given, is recorded as a training sample: features,
+ * kappa e, and the exact residual of the cell in h units. */
+static void bh_visit_learned(const bh_ctx* c, int64_t id, int32_t u, const double* w,
+                             sample_sink* sk, double* fx, double* fy) {
+    const bh_node* nd = &c->t->nodes[id];
+    double xu = c->xy[2 * u], yu = c->xy[2 * u + 1];
+    if (nd->leaf) {
+        for (int64_t i = 0; i < nd->count; ++i) {
+            int32_t v = c->pts[nd->first + i];
+            if (v == u) continue;
+            double rx, ry;
+            if (rq(xu - c->xy[2 * v], yu - c->xy[2 * v + 1], 0.0, &rx, &ry)) {
+                *fx += rx; *fy += ry;
+            }
+        }
+        return;
+    }
+    int sh = 24 - nd->depth;
+    int contains = ((c->ix[u] >> sh) == (nd->ox >> sh)) && ((c->iy[u] >> sh) == (nd->oy >> sh));
+    if (!contains) {
+        int64_t S = (int64_t)1 << sh;
+        int64_t dx = 2 * (int64_t)c->ix[u] + 1 - (2 * (int64_t)nd->ox + S);
+        int64_t dy = 2 * (int64_t)c->iy[u] + 1 - (2 * (int64_t)nd->oy + S);
+        double d4 = (double)(dx * dx + dy * dy);
+        double s4 = (double)(4 * S * S);
+        if (c->theta2 * d4 > s4) {
+            double rx, ry;
+            double m = (double)nd->count;
+            if (rq(xu - nd->cx, yu - nd->cy, 0.0, &rx, &ry)) {
+                *fx += m * rx; *fy += m * ry;
+            }
+            double f[MLP_IN], kex, key;
+            if (cell_features(c, nd, xu, yu, f, &kex, &key)) {
+                if (w) {
+                    double h[MLP_OUT];
+                    mlp_forward(w, f, h);
+                    /* kappa (h0 e + h1 p), p = (-e_y, e_x) */
+                    *fx += h[0] * kex - h[1] * key;
+                    *fy += h[0] * key + h[1] * kex;
+                }
+                if (sk && sk->count < sk->cap) {
+                    int64_t j = sk->count;
+                    double ex0 = 0.0, ey0 = 0.0;
+                    for (int64_t i = 0; i < nd->count; ++i) {
+                        int32_t v = c->pts[nd->first + i];
+                        double ax, ay;
+                        if (rq(xu - c->xy[2 * v], yu - c->xy[2 * v + 1], 0.0, &ax, &ay)) {
+                            ex0 += ax; ey0 += ay;
+                        }
+                    }
+                    double Rx = ex0 - m * rx, Ry = ey0 - m * ry;
+                    double k2 = kex * kex + key * key; /* kappa^2 */
+                    sk->u[j] = u;
+                    sk->node[j] = id;
+                    for (int i = 0; i < MLP_IN; ++i) sk->feat[MLP_IN * j + i] = f[i];
+                    /* h* = (R.e, R.p) / kappa = (R.(kappa e), R.(kappa p)) / kappa^2 */
+                    sk->target[2 * j] = (Rx * kex + Ry * key) / k2;
+                    sk->target[2 * j + 1] = (-Rx * key + Ry * kex) / k2;
+                    sk->coef[2 * j] = kex;
+                    sk->coef[2 * j + 1] = key;
+                }
+                if (sk) sk->count++;
+            }
+            return;
+        }
+    }
+    for (int d = 0; d < 4; ++d)
+        if (nd->child[d] >= 0) bh_visit_learned(c, nd->child[d], u, w, sk, fx, fy);
+}
+
+int orc_far_samples(int32_t n, const double* xy, double theta, int64_t cap, int32_t* u_out,
+                    int64_t* node_out, double* feat_out, double* target_out, double* coef_out,
+                    int64_t* count) {
+    bh_setup b;
+    if (bh_setup_build(n, xy, NULL, NULL, &b) != 0) return -1;
+    bh_ctx c = {&b.t, b.pts, b.ix, b.iy, xy, 0.0, theta * theta, b.xmin, b.ymin, b.scale};
+    sample_sink sk = {cap, 0, u_out, node_out, feat_out, target_out, coef_out};
+    /* sequential: samples are recorded in (u, visit) order */
+    for (int32_t u = 0; u < n; ++u) {
+        double fx = 0.0, fy = 0.0;
+        bh_visit_learned(&c, b.root, u, NULL, &sk, &fx, &fy);
+    }
+    *count = sk.count;
+    bh_setup_free(&b);
+    return 0;
+}
+
+int orc_bh_learned(int32_t n, const double* xy, double theta, const double* weights,
+                   double* F) {
+    bh_setup b;
+    if (bh_setup_build(n, xy, NULL, NULL, &b) != 0) return -1;
+    bh_ctx c = {&b.t, b.pts, b.ix, b.iy, xy, 0.0, theta * theta, b.xmin, b.ymin, b.scale};
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int32_t u = 0; u < n; ++u) {
+        double fx = 0.0, fy = 0.0;
+        bh_visit_learned(&c, b.root, u, weights, NULL, &fx, &fy);
+        F[2 * u] = fx; F[2 * u + 1] = fy;
+    }
+    bh_setup_free(&b);
+    return 0;
+}
+
+void orc_mlp_forward(const double* weights, int64_t count, const double* feat, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < count; ++j) mlp_forward(weights, feat + MLP_IN * j, out + 2 * j);
 }
 
 /* --------------------------------------------------------------- sweep */

@@ -72,6 +72,28 @@ int orc_bh(int32_t n, const double* xy, double q, double theta, double* F,
            uint64_t* codes, int32_t* order, int64_t* nodes, int64_t node_cap,
            int64_t* stats);
 
+/* ---- learned far-field correction (q = 0; an extension, not in the paper)
+ * Same tree, opening test and visit order as orc_bh.  An accepted cell C
+ * for target u adds m r(x_u - com) + kappa (h0 e + h1 p) where
+ * e = (x_u - com)/d, p = (-e_y, e_x), t = s/d (s: side of C's tight cell),
+ * kappa = m t^2/d and h = MLP(f), f = [t, offset of com from the cell
+ * centre along e and p / s, rotated central second moments per unit mass
+ * (ee, pp, ep) / s^2, log2(m)/16, 0].
+ * MLP: h = W3 relu(W2 relu(W1 f + b1) + b2) + b3 with W1 64x8, W2 64x64,
+ * W3 2x64 (row-major), packed W1, b1, W2, b2, W3, b3 (4866 doubles).
+ * orc_far_samples records, for u ascending and cells in visit order, the
+ * node id (pre-order index), f (8 per sample), the exact residual
+ * R = sum_{v in C} r(x_u - x_v) - m r(x_u - com) in h units
+ * ((R.e, R.p)/kappa, 2 per sample) and kappa e (2 per sample); at most cap
+ * are stored, *count receives the total.  Return 0, or -1 on allocation
+ * failure. */
+int orc_far_samples(int32_t n, const double* xy, double theta, int64_t cap, int32_t* u_out,
+                    int64_t* node_out, double* feat_out, double* target_out, double* coef_out,
+                    int64_t* count);
+int orc_bh_learned(int32_t n, const double* xy, double theta, const double* weights,
+                   double* F);
+void orc_mlp_forward(const double* weights, int64_t count, const double* feat, double* out);
+
 /* ---- one Jacobi iteration of the local update (Eq. 2) ----------------
  * For every u, from the old x only:
  *   A_u = sum_{v in S(u)} w_uv (x_v + d_uv (x_u-x_v)/|x_u-x_v|)
