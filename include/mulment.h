@@ -71,6 +71,8 @@ typedef struct {
   double coarse_dist_scale;/* d = hop (sqrt c_u + sqrt c_v) scale on coarse levels (1) */
   uint64_t seed;
   int32_t validate;        /* 1: full host-side graph validation (default) */
+  const float* mlp_weights;/* device, MM_MLP_PARAMS floats: learned far-field correction
+                              (Barnes-Hut only, q = 0); NULL = plain Barnes-Hut (default) */
 } mm_params;
 
 #define MM_MAX_LEVELS 64
@@ -136,6 +138,54 @@ mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32
 mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, double theta,
                        float* F, uint64_t* codes, int32_t* order, int64_t* nodes,
                        int64_t* counters);
+
+/* ---- learned far-field correction (an extension; the paper has none) ----
+ * Barnes-Hut as in mm_repulsion (q = 0) where every accepted cell C adds,
+ * besides m r(x_u - com), the correction kappa (h0 e + h1 p): d = |x_u - com|,
+ * e = (x_u - com)/d, p = (-e_y, e_x), t = s/d with s the side of C's tight
+ * cell, kappa = m t^2/d, h = MLP(f).  Features f (8): t; offset of com from
+ * the cell centre along e and p, over s; central second moments per unit
+ * mass rotated into (e, p) (ee, pp, ep), over s^2; log2(m)/16; 0.
+ * MLP: h = W3 relu(W2 relu(W1 f + b1) + b2) + b3, W1 64x8, W2 64x64, W3 2x64
+ * row-major; weights packed W1, b1, W2, b2, W3, b3 as MM_MLP_PARAMS FP32
+ * values.  Evaluated with BF16 weights and activations and FP32
+ * accumulation.  All pointers are device pointers; the calls are
+ * synchronous on the context's stream. */
+#define MM_MLP_PARAMS 4866
+
+/* F (n*2) from xy (n*2) with the correction of `weights`.  theta >= 0. */
+mm_status mm_repulsion_learned(mm_context* ctx, int32_t n, const float* xy, double theta,
+                               const float* weights, float* F);
+
+/* Training samples: every (u, C) the traversal at theta accepts, in
+ * ascending Morton rank of u and visit order within u.  Per sample: u,
+ * node (pre-order index of C), feat (8), target = exact residual
+ * R = sum_{v in C} r(x_u - x_v) - m r(x_u - com) in h units,
+ * ((R.e)/kappa, (R.p)/kappa) (2, computed in FP64), coef = kappa e (2).
+ * At most cap samples are written; *count (host) receives the total, so
+ * cap = 0 counts only. */
+mm_status mm_far_samples(mm_context* ctx, int32_t n, const float* xy, double theta, int64_t cap,
+                         int32_t* u_out, int32_t* node_out, float* feat, float* target,
+                         float* coef, int64_t* count);
+
+/* h = MLP(feat) for count rows (feat count*8, out count*2). */
+mm_status mm_mlp_forward(mm_context* ctx, int64_t count, const float* feat, const float* weights,
+                         float* out);
+
+/* Loss L = 1/(2 count) sum_rows |h - target|^2 and its gradient
+ * (grad: MM_MLP_PARAMS floats, packed like the weights; loss: 1 float). */
+mm_status mm_mlp_grad(mm_context* ctx, int64_t count, const float* feat, const float* target,
+                      const float* weights, float* grad, float* loss);
+
+/* `steps` Adam steps (beta 0.9/0.999, eps 1e-8, bias-corrected, step
+ * numbers step0+1 ...) on minibatches of `batch` rows drawn with replacement
+ * (SplitMix64 keyed by seed and step) from the count samples.  weights
+ * (FP32, updated in place); adam: 2*MM_MLP_PARAMS floats of moment state
+ * (zero before the first step); losses (steps floats, may be NULL): the
+ * minibatch loss before each step. */
+mm_status mm_mlp_train(mm_context* ctx, int64_t count, const float* feat, const float* target,
+                       float* weights, float* adam, int32_t steps, int32_t batch, double lr,
+                       uint64_t seed, int32_t step0, float* losses);
 
 /* One Jacobi iteration of Eq. 2 at entropy weight alpha: xy_out from xy_in
  * only.  level 0: d = hop; level > 0: d = hop (sqrt c_u + sqrt c_v) scale

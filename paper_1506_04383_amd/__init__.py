@@ -42,7 +42,7 @@ class MMParams(C.Structure):
                 ("eps_final", C.c_double), ("max_final_iters", C.c_int32),
                 ("max_levels", C.c_int32), ("coarsest_n", C.c_int32), ("b", C.c_double),
                 ("f", C.c_double), ("lp_rounds", C.c_int32), ("coarse_dist_scale", C.c_double),
-                ("seed", C.c_uint64), ("validate", C.c_int32)]
+                ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p)]
 
 
 class MMStats(C.Structure):
@@ -83,7 +83,10 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_khop_arrays", "mm_khop_export", "mm_repulsion", "mm_sweep", "mm_sweep_ex",
            "mm_coarsen",
            "mm_coarse_graph", "mm_coarse_export", "mm_coarse_free", "mm_init_layout",
-           "mm_prolong", "mm_objective", "mm_full_stress"]
+           "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
+           "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train"]
+
+MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
 
 _lib = None
 
@@ -118,6 +121,11 @@ def lib():
         "mm_prolong": [vp, i32, vp, vp, vp, u64, i32, vp],
         "mm_objective": [vp, vp, i32, vp, f64, vp, f64, vp],
         "mm_full_stress": [vp, P(MMGraph), vp, vp],
+        "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
+        "mm_far_samples": [vp, i32, vp, f64, i64, vp, vp, vp, vp, vp, P(i64)],
+        "mm_mlp_forward": [vp, i64, vp, vp, vp],
+        "mm_mlp_grad": [vp, i64, vp, vp, vp, vp, vp],
+        "mm_mlp_train": [vp, i64, vp, vp, vp, vp, i32, i32, f64, u64, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -170,19 +178,24 @@ class Params:
     coarse_dist_scale: float = 1.0
     seed: int = 1
     validate: int = 1
+    mlp_weights: object = None  # float32 device tensor of MLP_PARAMS (learned far field)
 
     def to_c(self) -> MMParams:
         p = MMParams()
         _check(lib().mm_params_default(C.byref(p)))
         for fd in fields(self):
-            setattr(p, fd.name, getattr(self, fd.name))
+            v = getattr(self, fd.name)
+            if fd.name == "mlp_weights":
+                v = None if v is None else C.c_void_p(v.data_ptr())
+            setattr(p, fd.name, v)
         return p
 
 
 def default_params() -> Params:
     p = MMParams()
     _check(lib().mm_params_default(C.byref(p)))
-    return Params(**{fd.name: getattr(p, fd.name) for fd in fields(Params)})
+    return Params(**{fd.name: getattr(p, fd.name) for fd in fields(Params)
+                     if fd.name != "mlp_weights"})
 
 
 # ------------------------------------------------------------------ context
@@ -325,6 +338,70 @@ def repulsion(ctx: Context, xy, q: float = 0.0, theta: float = 0.5, export: bool
     if counters or export:
         out.update(accepted=int(cnt[0]), leaf_pairs=int(cnt[1]), n_nodes=int(cnt[3]))
     return out
+
+
+def repulsion_learned(ctx: Context, xy, theta: float, weights):
+    """Barnes-Hut far field (q = 0) with the learned cell correction."""
+    t = ctx.torch
+    xy = ctx._dev(xy, t.float32)
+    w = ctx._dev(weights, t.float32)
+    F = t.empty((xy.shape[0], 2), dtype=t.float32, device=xy.device)
+    _check(lib().mm_repulsion_learned(ctx.h, xy.shape[0], _ptr(xy), theta, _ptr(w), _ptr(F)))
+    return F
+
+
+def far_samples(ctx: Context, xy, theta: float) -> dict:
+    """Accepted (target, cell) pairs with features, exact residual targets and
+    kappa e (device tensors), in Morton rank of the target and visit order."""
+    t = ctx.torch
+    xy = ctx._dev(xy, t.float32)
+    n = xy.shape[0]
+    cnt = C.c_int64(0)
+    _check(lib().mm_far_samples(ctx.h, n, _ptr(xy), theta, 0, None, None, None, None, None,
+                                C.byref(cnt)))
+    m = cnt.value
+    dev = xy.device
+    u = t.empty(m, dtype=t.int32, device=dev)
+    node = t.empty(m, dtype=t.int32, device=dev)
+    feat = t.empty((m, 8), dtype=t.float32, device=dev)
+    tgt = t.empty((m, 2), dtype=t.float32, device=dev)
+    coef = t.empty((m, 2), dtype=t.float32, device=dev)
+    _check(lib().mm_far_samples(ctx.h, n, _ptr(xy), theta, m, _ptr(u), _ptr(node), _ptr(feat),
+                                _ptr(tgt), _ptr(coef), C.byref(cnt)))
+    return {"u": u, "node": node, "feat": feat, "target": tgt, "coef": coef}
+
+
+def mlp_forward(ctx: Context, feat, weights):
+    t = ctx.torch
+    feat = ctx._dev(feat, t.float32)
+    w = ctx._dev(weights, t.float32)
+    out = t.empty((feat.shape[0], 2), dtype=t.float32, device=feat.device)
+    _check(lib().mm_mlp_forward(ctx.h, feat.shape[0], _ptr(feat), _ptr(w), _ptr(out)))
+    return out
+
+
+def mlp_grad(ctx: Context, feat, target, weights):
+    """(loss, gradient) of L = 1/(2B) sum |h - y|^2."""
+    t = ctx.torch
+    feat = ctx._dev(feat, t.float32)
+    target = ctx._dev(target, t.float32)
+    w = ctx._dev(weights, t.float32)
+    g = t.empty(MLP_PARAMS, dtype=t.float32, device=feat.device)
+    loss = t.empty(1, dtype=t.float32, device=feat.device)
+    _check(lib().mm_mlp_grad(ctx.h, feat.shape[0], _ptr(feat), _ptr(target), _ptr(w), _ptr(g),
+                             _ptr(loss)))
+    return float(loss.item()), g
+
+
+def mlp_train(ctx: Context, feat, target, weights, adam, steps: int, batch: int, lr: float,
+              seed: int, step0: int = 0):
+    """Adam steps in place on `weights` (and the 2*MLP_PARAMS `adam` state);
+    returns the per-step minibatch losses (device tensor)."""
+    t = ctx.torch
+    losses = t.empty(max(steps, 1), dtype=t.float32, device=weights.device)
+    _check(lib().mm_mlp_train(ctx.h, feat.shape[0], _ptr(feat), _ptr(target), _ptr(weights),
+                              _ptr(adam), steps, batch, lr, seed, step0, _ptr(losses)))
+    return losses[:steps]
 
 
 SWEEP_AUTO, SWEEP_ROWS, SWEEP_TILED = 0, 1, 2

@@ -18,7 +18,7 @@ INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmulment.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["prims.hip", "khop.hip", "farfield.hip", "sweep.hip", "tiled.hip", "coarsen.hip",
+SOURCES = ["prims.hip", "khop.hip", "farfield.hip", "learned.hip", "sweep.hip", "tiled.hip", "coarsen.hip",
            "layout.hip", "objective.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

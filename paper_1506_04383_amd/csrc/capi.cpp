@@ -118,6 +118,8 @@ mm_status validate_params(const mm_params* p) {
   if (!(p->b > 1) || !(p->f > 0)) return fail(MM_EINVAL, "b > 1 and f > 0 required");
   if (p->lp_rounds < 0) return fail(MM_EINVAL, "lp_rounds < 0");
   if (!(p->coarse_dist_scale > 0)) return fail(MM_EINVAL, "coarse_dist_scale must be > 0");
+  if (p->mlp_weights && (p->theta < 0 || p->q != 0.0))
+    return fail(MM_EUNSUPPORTED, "the learned far field needs theta >= 0 and q == 0");
   return MM_OK;
 }
 
@@ -283,6 +285,90 @@ mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, do
     return MM_OK;
   } catch (...) {
     return fail(MM_EINTERNAL, "exception in mm_repulsion");
+  }
+}
+
+// ------------------------------------------------------ learned far field
+
+mm_status mm_repulsion_learned(mm_context* ctx, int32_t n, const float* xy, double theta,
+                               const float* weights, float* F) {
+  try {
+    if (!ctx || !xy || !F || !weights) return fail(MM_EINVAL, "NULL argument");
+    if (n < 1) return fail(MM_EINVAL, "n < 1");
+    if (!(theta >= 0)) return fail(MM_EINVAL, "theta must be >= 0");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(mm::farfield_learned(ctx->bh, n, xy, theta, weights, F, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_repulsion_learned");
+  }
+}
+
+mm_status mm_far_samples(mm_context* ctx, int32_t n, const float* xy, double theta, int64_t cap,
+                         int32_t* u_out, int32_t* node_out, float* feat, float* target,
+                         float* coef, int64_t* count) {
+  try {
+    if (!ctx || !xy || !count) return fail(MM_EINVAL, "NULL argument");
+    if (n < 1) return fail(MM_EINVAL, "n < 1");
+    if (!(theta >= 0)) return fail(MM_EINVAL, "theta must be >= 0");
+    if (cap < 0) return fail(MM_EINVAL, "cap < 0");
+    if (cap > 0 && (!u_out || !node_out || !feat || !target || !coef))
+      return fail(MM_EINVAL, "NULL output with cap > 0");
+    DeviceGuard dg(ctx->device);
+    int64_t total = 0;
+    HIPCHK(mm::far_samples(ctx->bh, n, xy, theta, cap, u_out, node_out, feat, target, coef, &total,
+                           ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *count = total;
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_far_samples");
+  }
+}
+
+mm_status mm_mlp_forward(mm_context* ctx, int64_t count, const float* feat, const float* weights,
+                         float* out) {
+  try {
+    if (!ctx || (count > 0 && (!feat || !weights || !out))) return fail(MM_EINVAL, "NULL argument");
+    if (count < 0) return fail(MM_EINVAL, "count < 0");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(mm::mlp_forward(count, feat, weights, out, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_mlp_forward");
+  }
+}
+
+mm_status mm_mlp_grad(mm_context* ctx, int64_t count, const float* feat, const float* target,
+                      const float* weights, float* grad, float* loss) {
+  try {
+    if (!ctx || !feat || !target || !weights || !grad || !loss) return fail(MM_EINVAL, "NULL argument");
+    if (count < 1) return fail(MM_EINVAL, "count < 1");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(mm::mlp_grad(count, feat, target, weights, grad, loss, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_mlp_grad");
+  }
+}
+
+mm_status mm_mlp_train(mm_context* ctx, int64_t count, const float* feat, const float* target,
+                       float* weights, float* adam, int32_t steps, int32_t batch, double lr,
+                       uint64_t seed, int32_t step0, float* losses) {
+  try {
+    if (!ctx || !feat || !target || !weights || !adam) return fail(MM_EINVAL, "NULL argument");
+    if (count < 1 || steps < 0 || batch < 1 || step0 < 0) return fail(MM_EINVAL, "sizes");
+    if (!(lr > 0)) return fail(MM_EINVAL, "lr must be > 0");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(mm::mlp_train(count, feat, target, weights, adam, steps, batch, lr, seed, step0, losses,
+                         ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_mlp_train");
   }
 }
 
@@ -650,6 +736,9 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         HIPCHK(hipEventRecord(ctx->ev[0], s));
         if (p->theta < 0) {
           HIPCHK(mm::farfield_exact(nl, xa.as<float>(), p->q, F.as<float>(), s));
+        } else if (p->mlp_weights) {
+          HIPCHK(mm::farfield_learned(ctx->bh, nl, xa.as<float>(), p->theta, p->mlp_weights,
+                                      F.as<float>(), s));
         } else {
           HIPCHK(mm::farfield_bh(ctx->bh, nl, xa.as<float>(), p->q, p->theta, F.as<float>(), nullptr,
                                  nullptr, nullptr, nullptr, 0, nullptr, s));

@@ -27,34 +27,11 @@
 //       theta^2 * |(2 iu + 1) - (2 o_C + S_C)|^2 > 4 S_C^2.
 #include <algorithm>
 
+#include "bh.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace mm {
-
-// Pre-order node record.  The centre of mass stays in FP64: rounding it to
-// FP32 would add an absolute error of half an ulp of |x|, which dominates the
-// offset to nearby targets in dense regions.
-struct BHNode {
-  double cx, cy;
-  float mass;
-  int32_t skip;
-  uint32_t ox, oy;
-  int32_t meta;   // depth | leaf << 8
-  int32_t first;  // first point (sorted order)
-};
-
-struct BoxInfo {
-  double xmin, ymin, scale;
-  int32_t e;
-  int32_t pad;
-};
-
-struct BHWork {
-  int32_t cap = 0;
-  DevBuf codes, order, xsx, xsy, ix, px, py, nkeys, nvals, ntmp, first_at, nodes, counter, box,
-      partial, statc;
-};
 
 BHWork* bh_work_create() { return new BHWork(); }
 void bh_work_destroy(BHWork* w) { delete w; }
@@ -287,19 +264,6 @@ __global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* _
   }
 }
 
-// Adds m * r_q for the offset (dx, dy); coincident points add nothing.
-__device__ inline bool rq_add(float dx, float dy, float q, float m, float& fx, float& fy) {
-  float d2 = dx * dx + dy * dy;
-  if (d2 > 0.f) {
-    float f = (q == 0.f) ? __builtin_amdgcn_rcpf(d2) : powf(d2, -0.5f * (q + 2.f));
-    f *= m;
-    fx += dx * f;
-    fy += dy * f;
-    return true;
-  }
-  return false;
-}
-
 constexpr int TR_WAVES = 4;
 
 template <bool STATS>
@@ -392,13 +356,6 @@ __global__ __launch_bounds__(EX_T) void k_exact(const float2* __restrict__ xy, i
   if (u < n) F[u] = make_float2(fx, fy);
 }
 
-template <typename T>
-hipError_t ensure(DevBuf& b, size_t count, hipStream_t s) {
-  size_t need = sizeof(T) * (count ? count : 1);
-  if (b.bytes >= need) return hipSuccess;
-  return b.alloc(need, s);
-}
-
 }  // namespace
 
 hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStream_t s) {
@@ -406,9 +363,8 @@ hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStr
   return hipGetLastError();
 }
 
-hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
-                       uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
-                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s) {
+hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_out,
+                         hipStream_t s) {
   const size_t N2 = 2 * (size_t)n;
   MM_TRY(ensure<uint64_t>(w->codes, n, s));
   MM_TRY(ensure<int32_t>(w->order, n, s));
@@ -466,7 +422,14 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
       w->nvals.as<int32_t>(), w->ntmp.as<int4>(), Np, n, w->first_at.as<int32_t>(),
       w->px.as<double>(), w->py.as<double>(), w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
       w->codes.as<uint64_t>());
-  MM_TRY(hipGetLastError());
+  return hipGetLastError();
+}
+
+hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
+                       uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
+                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s) {
+  MM_TRY(bh_build_tree(w, n, xy, nodes_out, s));
+  const int32_t* Np = w->counter.as<int32_t>();
   if (count_stats) MM_TRY(hipMemsetAsync(w->statc.p, 0, 2 * sizeof(unsigned long long), s));
   const int32_t nw = (n + 63) / 64;
   const int32_t nblk = (nw + TR_WAVES - 1) / TR_WAVES;

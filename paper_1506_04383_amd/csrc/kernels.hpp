@@ -103,6 +103,21 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
                        uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
                        int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s);
 
+// ---- learned far-field correction (learned.hip), q = 0
+constexpr int32_t kMlpParams = 4866;  // W1 64x8, b1, W2 64x64, b2, W3 2x64, b3
+hipError_t farfield_learned(BHWork* w, int32_t n, const float* xy, double theta, const float* wts,
+                            float* F, hipStream_t s);
+hipError_t far_samples(BHWork* w, int32_t n, const float* xy, double theta, int64_t cap,
+                       int32_t* u_out, int32_t* node_out, float* feat, float* tgt, float* coef,
+                       int64_t* count_host, hipStream_t s);
+hipError_t mlp_forward(int64_t count, const float* feat, const float* wts, float* out,
+                       hipStream_t s);
+hipError_t mlp_grad(int64_t count, const float* feat, const float* tgt, const float* wts,
+                    float* grad, float* loss_dev, hipStream_t s);
+hipError_t mlp_train(int64_t N, const float* feat, const float* tgt, float* wts, float* adam,
+                     int32_t steps, int32_t batch, double lr, uint64_t seed, int32_t step0,
+                     float* losses, hipStream_t s);
+
 // ---- sweep (sweep.hip)
 // One Jacobi iteration of Eq. 2 over the k-hop sets. sqrtc: sqrt of node
 // weights (null at level 0 => d = hop). delta2 (device, 2 doubles) receives
