@@ -35,7 +35,92 @@ WORKLOADS = {
                   desc="RGG 2^17 points, mean degree ~6, LCC, k=3, theta=0.5"),
     "grid32": dict(graph="grid32", k=3, theta=-1.0, alpha_decay=0.5, max_levels=3,
                    desc="32x32 grid, k=3, exact far field, 3 coarsening levels"),
+    "rgg22": dict(graph="rgg22", k=3, theta=0.5, alpha_decay=0.5, coarsest_n=100,
+                  desc="RGG 2^22 points, mean degree ~8, LCC, k=3, theta=0.5"),
 }
+
+
+def learned_comparison(args):
+    """Learned far field vs plain Barnes-Hut on RGG 2^22 (k = 3): the network is
+    trained on the GPU on exact residuals of cells accepted at theta = 1 in
+    layouts of RGG 2^14 (mean degree 8) made by the method; then the layout
+    runs with theta = 1 + network, plain theta = 0.5 and plain theta = 1.
+    Prints one JSON line (times, final maxent-stress M_S, speedup)."""
+    import numpy as np
+    import torch
+
+    import paper_1506_04383_amd as mm
+    import synth
+
+    ctx = mm.Context(0)
+    base = dict(k=3, alpha_decay=0.5, coarsest_n=100, seed=args.seed, validate=0)
+    # training data
+    t0 = time.perf_counter()
+    feats, tgts = [], []
+    for s in range(101, 101 + args.train_graphs):
+        g = synth.config_graph("rgg14", s)
+        xy, _ = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(theta=0.5, **{**base, "seed": s}))
+        S = mm.far_samples(ctx, xy, 1.0)
+        feats.append(S["feat"])
+        tgts.append(S["target"])
+    feat, tgt = torch.cat(feats), torch.cat(tgts)
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    w = mm.mlp_init(11, out_scale=0.1)
+    adam = torch.zeros(2 * mm.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    losses = mm.mlp_train(ctx, feat, tgt, w, adam, args.train_steps, 4096, 2e-3, 5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = losses.cpu().numpy()
+    print(f"[learned] {feat.shape[0]} samples in {t_samples:.1f}s, {args.train_steps} Adam steps "
+          f"in {t_train:.2f}s, loss {losses[:20].mean():.3e} -> {losses[-100:].mean():.3e}",
+          file=sys.stderr, flush=True)
+
+    g = synth.config_graph("rgg22", args.seed)
+    dg = ctx.graph(g.row_ptr, g.col)
+    print(f"[learned] rgg22 n={g.n} m={g.m}", file=sys.stderr, flush=True)
+    kh = None
+    runs = {}
+    for name, p in [("plain_theta0.5", mm.Params(theta=0.5, **base)),
+                    ("learned_theta1", mm.Params(theta=1.0, mlp_weights=w, **base)),
+                    ("plain_theta1", mm.Params(theta=1.0, **base))]:
+        if args.warmup:
+            mm.layout(ctx, dg, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xy, st = mm.layout(ctx, dg, p)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        if kh is None:
+            kh = mm.khop_build(ctx, dg, 3)
+        M = mm.objective(ctx, kh, xy, 0.008)["M"]
+        L0 = st["per_level"][0]
+        runs[name] = {"time_to_layout_s": T, "final_maxent_stress": M,
+                      "far_field_ms": sum(l["far_ms"] for l in st["per_level"]),
+                      "sweep_ms": sum(l["sweep_ms"] for l in st["per_level"]),
+                      "finest_iters": L0["iters"],
+                      "finest_far_ms_per_iter": L0["far_ms"] / max(L0["iters"], 1)}
+        print(f"[learned] {name}: {T:.2f}s M_S={M:.6e}", file=sys.stderr, flush=True)
+    kh.free()
+    ref = runs["plain_theta0.5"]
+    lr_ = runs["learned_theta1"]
+    out = {"metric": "time-to-layout at equal maxent-stress, learned far field vs plain Barnes-Hut",
+           "value": ref["time_to_layout_s"] / lr_["time_to_layout_s"], "unit": "speedup (x)",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32+bf16", "data": "synthetic",
+           "config": {"workload": "RGG 2^22 points, mean degree ~8, LCC, k=3; learned: "
+                      "theta=1 + MLP 8-64-64-2 (BF16 MFMA) trained on RGG 2^14 layouts; "
+                      "plain: theta=0.5", "n": g.n, "m": g.m, "seed": args.seed},
+           "stress_ratio_learned_vs_plain": lr_["final_maxent_stress"] / ref["final_maxent_stress"],
+           "equal_stress_within_1pct": bool(abs(lr_["final_maxent_stress"] - ref["final_maxent_stress"])
+           <= 0.01 * abs(ref["final_maxent_stress"])),
+           "training": {"graphs": args.train_graphs, "samples": int(feat.shape[0]),
+                        "sample_s": t_samples, "steps": args.train_steps, "batch": 4096,
+                        "train_s": t_train, "loss_first": float(losses[:20].mean()),
+                        "loss_last": float(losses[-100:].mean())},
+           "runs": runs}
+    print(json.dumps(out))
+    ctx.close()
 
 
 def sweep_bytes(n: int, k: int, entries: int, coarse: bool) -> int:
@@ -104,6 +189,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
+    ap.add_argument("--mode", default="layout", choices=["layout", "learned"],
+                    help="layout: the layout benchmark; learned: learned far field vs plain "
+                         "Barnes-Hut on RGG 2^22")
+    ap.add_argument("--train-graphs", type=int, default=4)
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -123,6 +213,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
+
+    if args.mode == "learned":
+        learned_comparison(args)
         return
 
     import paper_1506_04383_amd as mm

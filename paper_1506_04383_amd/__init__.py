@@ -340,6 +340,18 @@ def repulsion(ctx: Context, xy, q: float = 0.0, theta: float = 0.5, export: bool
     return out
 
 
+def mlp_init(seed: int, out_scale: float = 0.1, device: str = "cuda"):
+    """Initial network weights (float32 device tensor of MLP_PARAMS): He-normal
+    hidden layers, output layer scaled by out_scale, zero biases."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, np.sqrt(2.0 / 8), 64 * 8), np.zeros(64),
+             rng.normal(0, np.sqrt(2.0 / 64), 64 * 64), np.zeros(64),
+             rng.normal(0, out_scale / 8.0, 2 * 64), np.zeros(2)]
+    return torch.as_tensor(np.concatenate(parts).astype(np.float32), device=device)
+
+
 def repulsion_learned(ctx: Context, xy, theta: float, weights):
     """Barnes-Hut far field (q = 0) with the learned cell correction."""
     t = ctx.torch

@@ -33,8 +33,8 @@ struct BHWork {
   int32_t cap = 0;
   DevBuf codes, order, xsx, xsy, ix, px, py, nkeys, nvals, ntmp, first_at, nodes, counter, box,
       partial, statc;
-  // learned far field: per-node second moments and tree links
-  DevBuf mom, parent, nch, arrive, scount, soff, wts;
+  // learned far field: per-node moments and cell records, sample offsets
+  DevBuf mom, cell, ndepth, scount, soff;
 };
 
 template <typename T>

@@ -88,7 +88,10 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     mask = (uint32_t)(hoff[v + 1] - hoff[v]) - 1u;
   }
   for (uint32_t i = l; i <= mask; i += 64) { keys[i] = -1; sc[i] = 0; }
-  __threadfence();
+  // the wave's own table writes/atomics before its reads: LDS tables need
+  // only the work-group fence; global tables the device-scope one
+  if (deg <= LP_SMALL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  else __threadfence();
   __builtin_amdgcn_wave_barrier();
   for (int32_t e = l; e < deg; e += 64) {
     const int32_t lab = label[col[beg + e]];
@@ -101,7 +104,10 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     }
     atomicAdd((unsigned long long*)&sc[s], (unsigned long long)wt);
   }
-  __threadfence();
+  // the wave's own table writes/atomics before its reads: LDS tables need
+  // only the work-group fence; global tables the device-scope one
+  if (deg <= LP_SMALL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  else __threadfence();
   __builtin_amdgcn_wave_barrier();
   Cand best;
   best.sc = -1; best.lab = 0x7fffffff; best.own = 0;

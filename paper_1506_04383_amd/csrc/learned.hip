@@ -129,50 +129,33 @@ __device__ inline v4f mlp16(const MlpLds& L, v4s x, v4f* z1, v4s* h1, v4f* z2, v
 }
 
 // ---------------------------------------------------------------- moments
-// Tree links: parent of every node, number of children, arrival counters.
-__global__ void k_bh_links(const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
-                           int32_t* __restrict__ parent, int32_t* __restrict__ nch,
-                           int32_t* __restrict__ arrive) {
+// Depth code of every node (leaves 24, internal nodes their tight depth).
+__global__ void k_node_depth(const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
+                             uint8_t* __restrict__ depth) {
   const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t N = *Np;
-  if (p >= N) return;
-  if (p == 0) parent[0] = -1;
-  arrive[p] = 0;
-  const BHNode nd = nodes[p];
-  int32_t k = 0;
-  if (!(nd.meta >> 8)) {
-    for (int32_t c = p + 1; c < nd.skip; c = nodes[c].skip) {
-      parent[c] = p;
-      ++k;
-    }
-  }
-  nch[p] = k;
+  if (p < *Np) depth[p] = (uint8_t)(nodes[p].meta & 0xff);
 }
 
-__device__ inline void mom_store(double* m, double a, double b, double c) {
-  __hip_atomic_store(m + 0, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(m + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(m + 2, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double mom_load(const double* m) {
-  return __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Per-node cell record for the features (FP32): {s, log2(m)/16, offset of
+// the centre of mass from the cell centre / s (x, y)}, {central second
+// moments per unit mass / s^2 (xx, yy, xy), 0}.
+struct Cell {
+  float4 a, b;
+};
 
-// Central second moments per unit mass of every node, bottom-up: each leaf
-// sums its own points; a node is merged (parallel-axis rule over its
-// children in child order) by whichever child arrives last, so the result
-// does not depend on timing.  No thread waits on another.
-__global__ void k_bh_moments(const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
-                             const float* __restrict__ xsx, const float* __restrict__ xsy,
-                             const int32_t* __restrict__ parent, const int32_t* __restrict__ nch,
-                             int32_t* __restrict__ arrive, double* __restrict__ mom) {
+// Central second moments per unit mass (FP64) of the nodes of depth D:
+// leaves (D = 24) sum their points, internal nodes merge their children
+// (parallel-axis rule, children in order) computed by earlier launches.
+__global__ void k_node_moments(const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
+                               const uint8_t* __restrict__ depth, int32_t D,
+                               const BoxInfo* __restrict__ box, const float* __restrict__ xsx,
+                               const float* __restrict__ xsy, double* __restrict__ mom,
+                               Cell* __restrict__ cell) {
   const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t N = *Np;
-  if (p >= N) return;
+  if (p >= *Np || depth[p] != D) return;
   const BHNode nd = nodes[p];
-  if (!(nd.meta >> 8)) return;
-  {
-    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+  double sxx = 0.0, syy = 0.0, sxy = 0.0;
+  if (nd.meta >> 8) {
     const int32_t cnt = (int32_t)nd.mass;
     for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
       const double dx = (double)xsx[j] - nd.cx, dy = (double)xsy[j] - nd.cy;
@@ -180,31 +163,36 @@ __global__ void k_bh_moments(const BHNode* __restrict__ nodes, const int32_t* __
       syy += dy * dy;
       sxy += dx * dy;
     }
-    mom_store(mom + 3 * (int64_t)p, sxx / cnt, syy / cnt, sxy / cnt);
-  }
-  int32_t c = p;
-  for (;;) {
-    const int32_t par = parent[c];
-    if (par < 0) break;
-    __threadfence();
-    const int32_t old = __hip_atomic_fetch_add(&arrive[par], 1, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    if (old != nch[par] - 1) break;
-    __threadfence();
-    const BHNode pn = nodes[par];
-    double sxx = 0.0, syy = 0.0, sxy = 0.0;
-    for (int32_t ch = par + 1; ch < pn.skip; ch = nodes[ch].skip) {
+  } else {
+    for (int32_t ch = p + 1; ch < nd.skip; ch = nodes[ch].skip) {
       const BHNode cn = nodes[ch];
-      const double mc = cn.mass, dx = cn.cx - pn.cx, dy = cn.cy - pn.cy;
+      const double mc = cn.mass, dx = cn.cx - nd.cx, dy = cn.cy - nd.cy;
       const double* cm = mom + 3 * (int64_t)ch;
-      sxx += mc * (mom_load(cm + 0) + dx * dx);
-      syy += mc * (mom_load(cm + 1) + dy * dy);
-      sxy += mc * (mom_load(cm + 2) + dx * dy);
+      sxx += mc * (cm[0] + dx * dx);
+      syy += mc * (cm[1] + dy * dy);
+      sxy += mc * (cm[2] + dx * dy);
     }
-    const double m = pn.mass;
-    mom_store(mom + 3 * (int64_t)par, sxx / m, syy / m, sxy / m);
-    c = par;
   }
+  const double m = nd.mass;
+  sxx /= m;
+  syy /= m;
+  sxy /= m;
+  double* o = mom + 3 * (int64_t)p;
+  o[0] = sxx;
+  o[1] = syy;
+  o[2] = sxy;
+  // cell geometry; the box scale is a power of two, so these are exact
+  const BoxInfo bx = *box;
+  const double inv_scale = 1.0 / bx.scale;
+  const double S = (double)(1u << (24 - D));
+  const double s = S * inv_scale, is = 1.0 / s;
+  const double gx = bx.xmin + ((double)nd.ox + 0.5 * S) * inv_scale;
+  const double gy = bx.ymin + ((double)nd.oy + 0.5 * S) * inv_scale;
+  Cell c;
+  c.a = make_float4((float)s, log2f(nd.mass) * 0.0625f, (float)((nd.cx - gx) * is),
+                    (float)((nd.cy - gy) * is));
+  c.b = make_float4((float)(sxx * is * is), (float)(syy * is * is), (float)(sxy * is * is), 0.f);
+  cell[p] = c;
 }
 
 // ---------------------------------------------------------------- features
@@ -213,29 +201,24 @@ struct Feat {
   float kex, key;  // kappa e
 };
 
-// Features of (target at (xt, yt), cell nd).  False when x_u == com.
-__device__ inline bool cell_features(const BHNode& nd, const double* __restrict__ mom,
-                                     const BoxInfo& bx, float xt, float yt, Feat& o) {
+// Features of (target at (xt, yt), cell nd with record c).  False when
+// x_u == com.
+__device__ inline bool cell_features(const BHNode& nd, const Cell& c, float xt, float yt,
+                                     Feat& o) {
   const float dx = (float)((double)xt - nd.cx), dy = (float)((double)yt - nd.cy);
   const float d2 = dx * dx + dy * dy;
   if (!(d2 > 0.f)) return false;
-  const float d = sqrtf(d2), inv = 1.f / d;
+  const float inv = __builtin_amdgcn_rsqf(d2);
   const float ex = dx * inv, ey = dy * inv, px = -ey, py = ex;
-  const int depth = nd.meta & 0xff;
-  const double S = ldexp(1.0, 24 - depth);
-  const double s = S / bx.scale;
-  const float ox = (float)(nd.cx - (bx.xmin + ((double)nd.ox + 0.5 * S) / bx.scale));
-  const float oy = (float)(nd.cy - (bx.ymin + ((double)nd.oy + 0.5 * S) / bx.scale));
-  const float is = (float)(1.0 / s), is2 = is * is;
-  const float mxx = (float)mom[0], myy = (float)mom[1], mxy = (float)mom[2];
-  const float t = (float)s * inv;
+  const float mxx = c.b.x, myy = c.b.y, mxy = c.b.z;
+  const float t = c.a.x * inv;
   o.f[0] = t;
-  o.f[1] = (ox * ex + oy * ey) * is;
-  o.f[2] = (ox * px + oy * py) * is;
-  o.f[3] = (ex * ex * mxx + 2.f * ex * ey * mxy + ey * ey * myy) * is2;
-  o.f[4] = (px * px * mxx + 2.f * px * py * mxy + py * py * myy) * is2;
-  o.f[5] = (ex * px * mxx + (ex * py + ey * px) * mxy + ey * py * myy) * is2;
-  o.f[6] = log2f(nd.mass) * 0.0625f;
+  o.f[1] = c.a.z * ex + c.a.w * ey;
+  o.f[2] = c.a.z * px + c.a.w * py;
+  o.f[3] = ex * ex * mxx + 2.f * ex * ey * mxy + ey * ey * myy;
+  o.f[4] = px * px * mxx + 2.f * px * py * mxy + py * py * myy;
+  o.f[5] = ex * px * mxx + (ex * py + ey * px) * mxy + ey * py * myy;
+  o.f[6] = c.a.y;
   o.f[7] = 0.f;
   const float kappa = nd.mass * t * t * inv;
   o.kex = kappa * ex;
@@ -294,10 +277,9 @@ __device__ inline void flush_rows(const MlpLds& L, const QRow* ring, int qh, int
 
 __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
     const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
-    const double* __restrict__ mom, const BoxInfo* __restrict__ box,
-    const float* __restrict__ xsx, const float* __restrict__ xsy, const uint2* __restrict__ ixy,
-    const int32_t* __restrict__ order, int32_t n, double theta2, const float* __restrict__ wts,
-    float2* __restrict__ F) {
+    const Cell* __restrict__ cell, const float* __restrict__ xsx, const float* __restrict__ xsy,
+    const uint2* __restrict__ ixy, const int32_t* __restrict__ order, int32_t n, double theta2,
+    const float* __restrict__ wts, float2* __restrict__ F) {
   __shared__ __align__(16) MlpLds L;
   __shared__ __align__(16) QRow ring_all[TL_WAVES][QCAP];
   stage_weights(wts, L);
@@ -308,7 +290,6 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
   QRow* ring = ring_all[wv];
   const int32_t i = wbase + l;
   const int32_t N = *Np;
-  const BoxInfo bx = *box;
   const bool valid = i < n;
   const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
@@ -336,7 +317,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
         bool contains;
         if (open_test(nd, qt, qx2, qy2, theta2, &contains)) {
           rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), 0.f, nd.mass, fx, fy);
-          push = cell_features(nd, mom + 3 * (int64_t)p, bx, xt, yt, ft);
+          push = cell_features(nd, cell[p], xt, yt, ft);
           next = nd.skip;
         } else {
           next = p + 1;
@@ -376,9 +357,9 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
 template <bool COUNT>
 __global__ __launch_bounds__(64 * TL_WAVES) void k_far_samples(
     const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
-    const double* __restrict__ mom, const BoxInfo* __restrict__ box,
-    const float* __restrict__ xsx, const float* __restrict__ xsy, const uint2* __restrict__ ixy,
-    const int32_t* __restrict__ order, int32_t n, double theta2, int32_t* __restrict__ cnt,
+    const Cell* __restrict__ cell, const float* __restrict__ xsx, const float* __restrict__ xsy,
+    const uint2* __restrict__ ixy, const int32_t* __restrict__ order, int32_t n, double theta2,
+    int32_t* __restrict__ cnt,
     const int64_t* __restrict__ off, int64_t cap, int32_t* __restrict__ u_out,
     int32_t* __restrict__ node_out, float* __restrict__ feat, float* __restrict__ tgt,
     float* __restrict__ coef) {
@@ -387,7 +368,6 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_far_samples(
   if (wbase >= n) return;
   const int32_t i = wbase + l;
   const int32_t N = *Np;
-  const BoxInfo bx = *box;
   const bool valid = i < n;
   const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
@@ -411,7 +391,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_far_samples(
     if (act) {
       bool contains;
       if (open_test(nd, qt, qx2, qy2, theta2, &contains)) {
-        take = cell_features(nd, mom + 3 * (int64_t)p, bx, xt, yt, ft);
+        take = cell_features(nd, cell[p], xt, yt, ft);
         next = nd.skip;
       } else {
         next = p + 1;
@@ -433,8 +413,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_far_samples(
         if (row < cap) {
           const double dx = ux - nd.cx, dy = uy - nd.cy, d2 = dx * dx + dy * dy;
           const double d = sqrt(d2), ex = dx / d, ey = dy / d;
-          const double S = ldexp(1.0, 24 - (nd.meta & 0xff));
-          const double t = S / bx.scale / d, kappa = (double)nd.mass * t * t / d;
+          const double t = (double)cell[p].a.x / d, kappa = (double)nd.mass * t * t / d;
           const double Rx = sx - (double)nd.mass * dx / d2, Ry = sy - (double)nd.mass * dy / d2;
           u_out[row] = u;
           node_out[row] = p;
@@ -703,16 +682,15 @@ inline int32_t grad_waves(int64_t B) { return (int32_t)((B + 16 * RB - 1) / (16 
 hipError_t tree_moments(BHWork* w, int32_t n, hipStream_t s) {
   const size_t NMAX = 2 * (size_t)n;
   MM_TRY(ensure<double>(w->mom, 3 * NMAX, s));
-  MM_TRY(ensure<int32_t>(w->parent, NMAX, s));
-  MM_TRY(ensure<int32_t>(w->nch, NMAX, s));
-  MM_TRY(ensure<int32_t>(w->arrive, NMAX, s));
+  MM_TRY(ensure<Cell>(w->cell, NMAX, s));
+  MM_TRY(ensure<uint8_t>(w->ndepth, NMAX, s));
   const int32_t* Np = w->counter.as<int32_t>();
   const int nb = (int)((NMAX + 255) / 256);
-  k_bh_links<<<nb, 256, 0, s>>>(w->nodes.as<BHNode>(), Np, w->parent.as<int32_t>(),
-                                w->nch.as<int32_t>(), w->arrive.as<int32_t>());
-  k_bh_moments<<<nb, 256, 0, s>>>(w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(),
-                                  w->parent.as<int32_t>(), w->nch.as<int32_t>(),
-                                  w->arrive.as<int32_t>(), w->mom.as<double>());
+  k_node_depth<<<nb, 256, 0, s>>>(w->nodes.as<BHNode>(), Np, w->ndepth.as<uint8_t>());
+  for (int32_t D = 24; D >= 0; --D)
+    k_node_moments<<<nb, 256, 0, s>>>(w->nodes.as<BHNode>(), Np, w->ndepth.as<uint8_t>(), D,
+                                      w->box.as<BoxInfo>(), w->xsx.as<float>(), w->xsy.as<float>(),
+                                      w->mom.as<double>(), w->cell.as<Cell>());
   return hipGetLastError();
 }
 
@@ -724,9 +702,9 @@ hipError_t farfield_learned(BHWork* w, int32_t n, const float* xy, double theta,
   MM_TRY(tree_moments(w, n, s));
   const int32_t nw = (n + 63) / 64;
   k_traverse_learned<<<(nw + TL_WAVES - 1) / TL_WAVES, 64 * TL_WAVES, 0, s>>>(
-      w->nodes.as<BHNode>(), w->counter.as<int32_t>(), w->mom.as<double>(), w->box.as<BoxInfo>(),
-      w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(), w->order.as<int32_t>(), n,
-      theta * theta, wts, (float2*)F);
+      w->nodes.as<BHNode>(), w->counter.as<int32_t>(), w->cell.as<Cell>(), w->xsx.as<float>(),
+      w->xsy.as<float>(), w->ix.as<uint2>(), w->order.as<int32_t>(), n, theta * theta, wts,
+      (float2*)F);
   return hipGetLastError();
 }
 
@@ -741,9 +719,9 @@ hipError_t far_samples(BHWork* w, int32_t n, const float* xy, double theta, int6
   const BHNode* nodes = w->nodes.as<BHNode>();
   const int32_t* Np = w->counter.as<int32_t>();
   k_far_samples<true><<<nb, 64 * TL_WAVES, 0, s>>>(
-      nodes, Np, w->mom.as<double>(), w->box.as<BoxInfo>(), w->xsx.as<float>(), w->xsy.as<float>(),
-      w->ix.as<uint2>(), w->order.as<int32_t>(), n, theta * theta, w->scount.as<int32_t>(),
-      nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
+      nodes, Np, w->cell.as<Cell>(), w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
+      w->order.as<int32_t>(), n, theta * theta, w->scount.as<int32_t>(), nullptr, 0, nullptr,
+      nullptr, nullptr, nullptr, nullptr);
   MM_TRY(hipGetLastError());
   MM_TRY(scan_excl_i32(w->scount.as<int32_t>(), w->soff.as<int64_t>(), n, s));
   int64_t total = 0;
@@ -752,9 +730,9 @@ hipError_t far_samples(BHWork* w, int32_t n, const float* xy, double theta, int6
   *count_host = total;
   if (cap > 0 && total > 0) {
     k_far_samples<false><<<nb, 64 * TL_WAVES, 0, s>>>(
-        nodes, Np, w->mom.as<double>(), w->box.as<BoxInfo>(), w->xsx.as<float>(),
-        w->xsy.as<float>(), w->ix.as<uint2>(), w->order.as<int32_t>(), n, theta * theta, nullptr,
-        w->soff.as<int64_t>(), cap, u_out, node_out, feat, tgt, coef);
+        nodes, Np, w->cell.as<Cell>(), w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
+        w->order.as<int32_t>(), n, theta * theta, nullptr, w->soff.as<int64_t>(), cap, u_out,
+        node_out, feat, tgt, coef);
     MM_TRY(hipGetLastError());
   }
   return hipSuccess;
