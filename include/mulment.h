@@ -111,6 +111,23 @@ const char* mm_last_error(void);
 mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
                     const float* init_xy, float* out_xy, mm_stats* stats);
 
+/* Batched layout of G independent graphs (an extension: the paper lays out
+ * one graph at a time).  g is their block-diagonal union: graph i owns the
+ * vertices [graph_off[i], graph_off[i+1]) (graph_off: host, G+1, from 0 to
+ * n; every graph has >= 2 vertices and no edge leaves its graph).  Every
+ * graph is laid out as mm_layout would lay it out alone -- its own
+ * hierarchy (U, f, stopping point), draws keyed by its local vertex ids,
+ * its own quadtree and alpha schedule -- while each step runs as one set of
+ * launches over the whole batch.  theta >= 0 (Barnes-Hut) only; no learned
+ * far field.  init_xy (n*2 or NULL): warm start of every graph as in
+ * mm_layout.  out_xy: n*2 in the graph's memory kind.  graph_levels (host,
+ * G, may be NULL): levels of each graph's hierarchy.  stats: per union
+ * level sizes and iteration counts (the union iterates until its last
+ * graph is done), totals. */
+mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, const mm_graph* g,
+                          const mm_params* p, const float* init_xy, float* out_xy,
+                          int32_t* graph_levels, mm_stats* stats);
+
 /* ---- step-level entry points (device graphs) ---------------------------- */
 
 /* k-hop distance sets S_k(u) = {v != u : hop(u,v) <= k}, sorted by (hop, v)

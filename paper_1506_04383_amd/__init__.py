@@ -84,7 +84,7 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_coarsen",
            "mm_coarse_graph", "mm_coarse_export", "mm_coarse_free", "mm_init_layout",
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
-           "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train"]
+           "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch"]
 
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
 
@@ -122,6 +122,7 @@ def lib():
         "mm_objective": [vp, vp, i32, vp, f64, vp, f64, vp],
         "mm_full_stress": [vp, P(MMGraph), vp, vp],
         "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
+        "mm_layout_batch": [vp, i32, vp, P(MMGraph), P(MMParams), vp, vp, vp, P(MMStats)],
         "mm_far_samples": [vp, i32, vp, f64, i64, vp, vp, vp, vp, vp, P(i64)],
         "mm_mlp_forward": [vp, i64, vp, vp, vp],
         "mm_mlp_grad": [vp, i64, vp, vp, vp, vp, vp],
@@ -276,6 +277,27 @@ def layout(ctx: Context, g: DeviceGraph, params: Params | None = None, init_xy=N
     gc = g.c()
     _check(lib().mm_layout(ctx.h, C.byref(gc), C.byref(p), _ptr(init), _ptr(out), C.byref(st)))
     return out, st.to_dict()
+
+
+def layout_batch(ctx: Context, row_ptr, col, graph_off, params: Params | None = None,
+                 init_xy=None):
+    """Lay out a batch of independent graphs given as their block-diagonal
+    union (row_ptr, col) with vertex offsets graph_off (G+1).  Returns
+    (xy float32 [n,2] device tensor, per-graph level counts, stats dict)."""
+    t = ctx.torch
+    offs = np.ascontiguousarray(graph_off, dtype=np.int64)
+    G = offs.size - 1
+    dg = row_ptr if isinstance(row_ptr, DeviceGraph) else DeviceGraph(ctx, row_ptr, col)
+    p = (params or Params()).to_c()
+    out = t.empty((dg.n, 2), dtype=t.float32, device=f"cuda:{ctx.device}")
+    init = None if init_xy is None else ctx._dev(init_xy, t.float32)
+    lev = np.zeros(G, dtype=np.int32)
+    st = MMStats()
+    gc = dg.c()
+    _check(lib().mm_layout_batch(ctx.h, G, offs.ctypes.data_as(C.c_void_p), C.byref(gc),
+                                 C.byref(p), _ptr(init), _ptr(out),
+                                 lev.ctypes.data_as(C.c_void_p), C.byref(st)))
+    return out, lev, st.to_dict()
 
 
 class KHop:

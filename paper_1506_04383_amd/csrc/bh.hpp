@@ -48,7 +48,7 @@ hipError_t ensure(DevBuf& b, size_t count, hipStream_t s) {
 // pre-order with skip links and FP64 centres of mass.  The node count stays
 // on the device (w->counter).
 hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_out,
-                         hipStream_t s);
+                         hipStream_t s, const BHSeg* seg = nullptr);
 
 // Adds m * r_q for the offset (dx, dy); coincident points add nothing.
 __device__ inline bool rq_add(float dx, float dy, float q, float m, float& fx, float& fy) {

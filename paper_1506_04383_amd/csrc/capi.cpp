@@ -812,3 +812,346 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+// One level of a batch: the union of the graphs still present at this level.
+struct BatchLevel {
+  mm::GraphDev g;
+  std::vector<int32_t> orig;     // batch index of every member graph
+  std::vector<int32_t> goff_h;   // member vertex offsets (M+1)
+  mm::DevBuf d_gid, d_goff;      // per-vertex member index, offsets
+  mm::DevBuf cl;                 // vertex -> next level vertex, -1 = graph stops here
+  std::vector<uint8_t> top;      // member's coarsest level is this one
+  int32_t M() const { return (int32_t)orig.size(); }
+};
+
+mm_status upload_offsets(BatchLevel& L, hipStream_t s) {
+  const int32_t M = L.M();
+  HIPCHK(L.d_goff.alloc(sizeof(int32_t) * (size_t)(M + 1), s));
+  HIPCHK(hipMemcpyAsync(L.d_goff.p, L.goff_h.data(), sizeof(int32_t) * (size_t)(M + 1),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(L.d_gid.alloc(sizeof(int32_t) * (size_t)std::max(L.g.n, 1), s));
+  HIPCHK(mm::batch_fill_gid(M, L.d_goff.as<int32_t>(), L.d_gid.as<int32_t>(), s));
+  return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, const mm_graph* g,
+                          const mm_params* p, const float* init_xy, float* out_xy,
+                          int32_t* graph_levels, mm_stats* stats) {
+  try {
+    if (!ctx || !g || !out_xy || !graph_off) return fail(MM_EINVAL, "NULL argument");
+    STCHK(validate_params(p));
+    if (p->theta < 0) return fail(MM_EUNSUPPORTED, "batches use the Barnes-Hut far field (theta >= 0)");
+    if (p->mlp_weights) return fail(MM_EUNSUPPORTED, "batches use the plain Barnes-Hut far field");
+    if (G < 1) return fail(MM_EINVAL, "G < 1");
+    if (g->mem != MM_HOST && g->mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");
+    if (graph_off[0] != 0 || graph_off[G] != (int64_t)g->n) return fail(MM_EINVAL, "graph_off must run from 0 to n");
+    for (int32_t i = 0; i < G; ++i)
+      if (graph_off[i + 1] - graph_off[i] < 2) return fail(MM_EINVAL, "graph %d has fewer than 2 vertices", i);
+    if (g->nnz < 1 || g->nnz >= (1ll << 31)) return fail(MM_EINVAL, "nnz out of range");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int32_t n = g->n;
+    const int64_t nnz = g->nnz;
+    auto t_start = std::chrono::steady_clock::now();
+
+    std::vector<int32_t> h_rp(n + 1), h_col((size_t)nnz), h_c;
+    const hipMemcpyKind k2h = g->mem == MM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPCHK(hipMemcpy(h_rp.data(), g->row_ptr, sizeof(int32_t) * (size_t)(n + 1), k2h));
+    HIPCHK(hipMemcpy(h_col.data(), g->col, sizeof(int32_t) * (size_t)nnz, k2h));
+    if (g->node_w) { h_c.resize(n); HIPCHK(hipMemcpy(h_c.data(), g->node_w, sizeof(int32_t) * (size_t)n, k2h)); }
+    if (p->validate) {
+      std::vector<int32_t> h_w;
+      if (g->edge_w) { h_w.resize((size_t)nnz); HIPCHK(hipMemcpy(h_w.data(), g->edge_w, sizeof(int32_t) * (size_t)nnz, k2h)); }
+      STCHK(validate_graph(n, nnz, h_rp.data(), h_col.data(), h_c.empty() ? nullptr : h_c.data(),
+                           h_w.empty() ? nullptr : h_w.data()));
+    } else if (h_rp[0] != 0 || (int64_t)h_rp[n] != nnz) {
+      return fail(MM_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
+    }
+    // edges stay inside their graph
+    for (int32_t i = 0; i < G; ++i)
+      for (int64_t v = graph_off[i]; v < graph_off[i + 1]; ++v)
+        for (int32_t e = h_rp[v]; e < h_rp[v + 1]; ++e)
+          if (h_col[e] < graph_off[i] || h_col[e] >= graph_off[i + 1])
+            return fail(MM_EINVAL, "edge %lld-%d leaves graph %d", (long long)v, h_col[e], i);
+    if (init_xy) {
+      std::vector<float> hx(2 * (size_t)n);
+      HIPCHK(hipMemcpy(hx.data(), init_xy, sizeof(float) * hx.size(), k2h));
+      for (float v : hx) if (!std::isfinite(v)) return fail(MM_EINVAL, "init_xy not finite");
+    }
+
+    // level 0: the whole batch
+    std::vector<std::unique_ptr<BatchLevel>> levels;
+    levels.emplace_back(new BatchLevel());
+    {
+      BatchLevel& L0 = *levels[0];
+      L0.g.n = n;
+      L0.g.nnz = nnz;
+      HIPCHK(L0.g.b_rp.alloc(sizeof(int32_t) * (size_t)(n + 1), s));
+      HIPCHK(L0.g.b_col.alloc(sizeof(int32_t) * (size_t)nnz, s));
+      L0.g.row_ptr = L0.g.b_rp.as<int32_t>();
+      L0.g.col = L0.g.b_col.as<int32_t>();
+      HIPCHK(hipMemcpyAsync(L0.g.row_ptr, h_rp.data(), sizeof(int32_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(L0.g.col, h_col.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s));
+      if (!h_c.empty()) {
+        HIPCHK(L0.g.b_c.alloc(sizeof(int32_t) * (size_t)n, s));
+        L0.g.c = L0.g.b_c.as<int32_t>();
+        HIPCHK(hipMemcpyAsync(L0.g.c, h_c.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+      }
+      if (g->edge_w) {
+        HIPCHK(L0.g.b_w.alloc(sizeof(int32_t) * (size_t)nnz, s));
+        L0.g.w = L0.g.b_w.as<int32_t>();
+        HIPCHK(hipMemcpyAsync(L0.g.w, g->edge_w, sizeof(int32_t) * (size_t)nnz,
+                              g->mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+      }
+      L0.orig.resize(G);
+      L0.goff_h.resize(G + 1);
+      for (int32_t i = 0; i < G; ++i) L0.orig[i] = i;
+      for (int32_t i = 0; i <= G; ++i) L0.goff_h[i] = (int32_t)graph_off[i];
+      STCHK(upload_offsets(L0, s));
+    }
+
+    // ---- hierarchy, every graph with its own U, f and stopping point
+    std::vector<double> cV(G, 0.0), f(G, p->f);
+    std::vector<int32_t> redo(G, 0), nlev(G, 1);
+    std::vector<uint8_t> alive(G, init_xy ? 0 : 1);
+    for (int32_t i = 0; i < G; ++i) {
+      if (h_c.empty()) cV[i] = (double)(graph_off[i + 1] - graph_off[i]);
+      else for (int64_t v = graph_off[i]; v < graph_off[i + 1]; ++v) cV[i] += h_c[v];
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    for (int32_t h = 1;; ++h) {
+      BatchLevel& cur = *levels.back();
+      const int32_t M = cur.M();
+      std::vector<uint8_t> cand(M, 0);
+      bool any = false;
+      for (int32_t m = 0; m < M; ++m) {
+        const int32_t gi = cur.orig[m];
+        const int32_t nm = cur.goff_h[m + 1] - cur.goff_h[m];
+        cand[m] = alive[gi] && (h - 1) < p->max_levels && nm > std::max(p->coarsest_n, 2);
+        if (!cand[m]) alive[gi] = 0;
+        any = any || cand[m];
+      }
+      if (!any) break;
+      std::vector<int32_t> maxc(M, 1);
+      if (cur.g.c) {
+        mm::DevBuf dm;
+        HIPCHK(dm.alloc(sizeof(int32_t) * (size_t)M, s));
+        HIPCHK(mm::batch_max_c(M, cur.d_goff.as<int32_t>(), cur.g.c, dm.as<int32_t>(), s));
+        HIPCHK(hipMemcpyAsync(maxc.data(), dm.p, sizeof(int32_t) * (size_t)M, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+      auto Uof = [&](int32_t m) {
+        const int32_t gi = cur.orig[m];
+        const double W = std::min(std::pow(p->b, (double)h), cV[gi] / f[gi]);
+        return std::max((double)maxc[m], W);
+      };
+      std::vector<double> U(M, 1.0);
+      for (int32_t m = 0; m < M; ++m) if (cand[m]) U[m] = Uof(m);
+      // decision per member: 0 pending, 1 accept, 2 stop
+      std::vector<int32_t> decide(M, 0);
+      for (int32_t m = 0; m < M; ++m) if (!cand[m]) decide[m] = 2;
+      mm::DevBuf d_U, d_stop, label, cluster, gidc, goffc;
+      HIPCHK(d_U.alloc(sizeof(double) * (size_t)M, s));
+      HIPCHK(d_stop.alloc(sizeof(int32_t) * (size_t)M, s));
+      HIPCHK(label.alloc(sizeof(int32_t) * (size_t)cur.g.n, s));
+      HIPCHK(cluster.alloc(sizeof(int32_t) * (size_t)cur.g.n, s));
+      std::unique_ptr<mm::GraphDev> C;
+      std::vector<int32_t> goffc_h(M + 1);
+      for (;;) {
+        std::vector<int32_t> stop(M);
+        for (int32_t m = 0; m < M; ++m) stop[m] = cand[m] ? 0 : 1;
+        HIPCHK(hipMemcpyAsync(d_U.p, U.data(), sizeof(double) * (size_t)M, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_stop.p, stop.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
+        mm::LpSeg seg;
+        seg.M = M;
+        seg.gid = cur.d_gid.as<int32_t>();
+        seg.goff = cur.d_goff.as<int32_t>();
+        seg.Ug = d_U.as<double>();
+        seg.gstop = d_stop.as<int32_t>();
+        int32_t rr = 0;
+        HIPCHK(mm::lp_cluster(cur.g, 0.0, p->lp_rounds, p->seed, h, label.as<int32_t>(), &rr, nullptr,
+                              s, &seg));
+        C.reset(new mm::GraphDev());
+        HIPCHK(mm::contract(cur.g, label.as<int32_t>(), cluster.as<int32_t>(), C.get(), s));
+        HIPCHK(gidc.alloc(sizeof(int32_t) * (size_t)std::max(C->n, 1), s));
+        HIPCHK(goffc.alloc(sizeof(int32_t) * (size_t)(M + 1), s));
+        HIPCHK(mm::batch_coarse_offsets(cur.g.n, M, C->n, cluster.as<int32_t>(), cur.d_gid.as<int32_t>(),
+                                        gidc.as<int32_t>(), goffc.as<int32_t>(), s));
+        HIPCHK(hipMemcpyAsync(goffc_h.data(), goffc.p, sizeof(int32_t) * (size_t)(M + 1),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool any_redo = false;
+        for (int32_t m = 0; m < M; ++m) {
+          if (decide[m] != 0) continue;
+          const int32_t gi = cur.orig[m];
+          const int32_t nm = cur.goff_h[m + 1] - cur.goff_h[m];
+          const int32_t nc = goffc_h[m + 1] - goffc_h[m];
+          if (nc > 0.9 * nm) {
+            const bool bounded_by_f = (cV[gi] / f[gi]) < std::pow(p->b, (double)h);
+            f[gi] = 0.7 * f[gi];
+            if (bounded_by_f && redo[gi] < 10) {
+              redo[gi]++;
+              U[m] = Uof(m);
+              any_redo = true;
+              continue;
+            }
+          }
+          decide[m] = (nc >= nm || nc < 2) ? 2 : 1;
+        }
+        if (!any_redo) break;
+      }
+      // next level: the accepted graphs
+      std::vector<uint8_t> keep(M, 0);
+      std::unique_ptr<BatchLevel> next(new BatchLevel());
+      next->goff_h.push_back(0);
+      for (int32_t m = 0; m < M; ++m) {
+        const int32_t gi = cur.orig[m];
+        if (decide[m] == 1) {
+          keep[m] = 1;
+          next->orig.push_back(gi);
+          next->goff_h.push_back(next->goff_h.back() + goffc_h[m + 1] - goffc_h[m]);
+          redo[gi] = 0;
+          nlev[gi]++;
+        } else {
+          alive[gi] = 0;
+        }
+      }
+      if (next->orig.empty()) break;
+      mm::DevBuf d_keep, cflag, cnewid;
+      HIPCHK(d_keep.alloc((size_t)M, s));
+      HIPCHK(hipMemcpyAsync(d_keep.p, keep.data(), (size_t)M, hipMemcpyHostToDevice, s));
+      HIPCHK(cflag.alloc(sizeof(int32_t) * (size_t)C->n, s));
+      HIPCHK(cnewid.alloc(sizeof(int64_t) * (size_t)(C->n + 1), s));
+      HIPCHK(mm::batch_subset(*C, gidc.as<int32_t>(), d_keep.as<uint8_t>(), &next->g,
+                              cflag.as<int32_t>(), cnewid.as<int64_t>(), s));
+      HIPCHK(cur.cl.alloc(sizeof(int32_t) * (size_t)cur.g.n, s));
+      HIPCHK(mm::batch_cl_map(cur.g.n, cluster.as<int32_t>(), cflag.as<int32_t>(), cnewid.as<int64_t>(),
+                              cur.cl.as<int32_t>(), s));
+      STCHK(upload_offsets(*next, s));
+      HIPCHK(hipStreamSynchronize(s));
+      levels.push_back(std::move(next));
+    }
+    const double t_coarsen = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const int32_t H = (int32_t)levels.size() - 1;
+    // member flags: coarsest level of the graph
+    for (int32_t l = 0; l <= H; ++l) {
+      BatchLevel& L = *levels[l];
+      L.top.assign(L.M(), 1);
+      if (l < H) {
+        const BatchLevel& N = *levels[l + 1];
+        size_t j = 0;
+        for (int32_t m = 0; m < L.M(); ++m) {
+          while (j < N.orig.size() && N.orig[j] < L.orig[m]) ++j;
+          L.top[m] = (j < N.orig.size() && N.orig[j] == L.orig[m]) ? 0 : 1;
+        }
+      }
+    }
+
+    // ---- levels, coarsest first
+    mm_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.levels = H + 1;
+    double t_khop = 0;
+    mm::BatchSched prm;
+    prm.alpha_min = p->alpha_min;
+    prm.decay = p->alpha_decay;
+    prm.eps_round = p->eps_round;
+    prm.eps_final = p->eps_final;
+    prm.a = p->iters_per_round;
+    prm.max_final = p->max_final_iters;
+    mm::DevBuf xa, xb, F, d2, gd, gst, galpha, cnt;
+    HIPCHK(d2.alloc(2 * sizeof(double), s));
+    HIPCHK(cnt.alloc(2 * sizeof(int32_t), s));
+    for (int32_t lvl = H; lvl >= 0; --lvl) {
+      BatchLevel& L = *levels[lvl];
+      const int32_t nl = L.g.n, M = L.M();
+      HIPCHK(xb.alloc(sizeof(float) * 2 * (size_t)nl, s));
+      if (init_xy) {
+        HIPCHK(hipMemcpyAsync(xb.p, init_xy, sizeof(float) * 2 * (size_t)n,
+                              g->mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+      } else {
+        if (lvl < H)
+          HIPCHK(mm::prolong_seg(nl, L.cl.as<int32_t>(), levels[lvl + 1]->g.c, xa.as<float>(), p->seed,
+                                 lvl, L.d_gid.as<int32_t>(), L.d_goff.as<int32_t>(), xb.as<float>(), s));
+        mm::DevBuf d_top;
+        HIPCHK(d_top.alloc((size_t)M, s));
+        HIPCHK(hipMemcpyAsync(d_top.p, L.top.data(), (size_t)M, hipMemcpyHostToDevice, s));
+        HIPCHK(mm::init_layout_seg(nl, p->seed, lvl, L.d_gid.as<int32_t>(), L.d_goff.as<int32_t>(),
+                                   d_top.as<uint8_t>(), xb.as<float>(), s));
+        HIPCHK(mm::place_pairs_seg(M, L.d_goff.as<int32_t>(), d_top.as<uint8_t>(), L.g.c, lvl,
+                                   p->coarse_dist_scale, xb.as<float>(), s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+      std::swap(xa, xb);
+      HIPCHK(xb.alloc(sizeof(float) * 2 * (size_t)nl, s));
+      HIPCHK(F.alloc(sizeof(float) * 2 * (size_t)nl, s));
+      auto tk = std::chrono::steady_clock::now();
+      mm::KhopDev kh;
+      HIPCHK(mm::khop_build(nl, L.g.row_ptr, L.g.col, p->k, &kh, s));
+      HIPCHK(hipStreamSynchronize(s));
+      t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
+      mm::DevBuf sq;
+      const float* sqrtc = nullptr;
+      if (lvl > 0) {
+        HIPCHK(make_sqrtc(nl, L.g.c, sq, s));
+        sqrtc = sq.as<float>();
+      }
+      HIPCHK(gd.alloc(2 * sizeof(double) * (size_t)M, s));
+      HIPCHK(gst.alloc(sizeof(mm::BatchState) * (size_t)M, s));
+      HIPCHK(galpha.alloc(sizeof(float) * (size_t)M, s));
+      HIPCHK(mm::batch_sched_init(M, prm, init_xy ? p->alpha_min : p->alpha0, gst.as<mm::BatchState>(),
+                                  galpha.as<float>(), s));
+      mm::BHSeg bseg;
+      bseg.M = M;
+      bseg.gid = L.d_gid.as<int32_t>();
+      bseg.goff = L.d_goff.as<int32_t>();
+      int32_t iters = 0;
+      for (;;) {
+        HIPCHK(mm::farfield_bh(ctx->bh, nl, xa.as<float>(), p->q, p->theta, F.as<float>(), nullptr,
+                               nullptr, nullptr, nullptr, 0, nullptr, s, &bseg));
+        HIPCHK(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa.as<float>(), F.as<float>(), 0.0, p->q,
+                         xb.as<float>(), d2.as<double>(), s, L.d_gid.as<int32_t>(), galpha.as<float>()));
+        HIPCHK(mm::batch_delta(M, L.d_goff.as<int32_t>(), xa.as<float>(), xb.as<float>(), gd.as<double>(), s));
+        HIPCHK(hipMemsetAsync(cnt.p, 0, 2 * sizeof(int32_t), s));
+        HIPCHK(mm::batch_schedule(M, gd.as<double>(), prm, gst.as<mm::BatchState>(), galpha.as<float>(),
+                                  cnt.as<int32_t>(), s));
+        int32_t hc[2];
+        HIPCHK(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::swap(xa, xb);
+        iters++;
+        if (hc[1] > 0) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
+        if (hc[0] == 0) break;
+      }
+      if (lvl < MM_MAX_LEVELS) {
+        st.level_n[lvl] = nl;
+        st.level_nnz[lvl] = L.g.nnz;
+        st.level_khop[lvl] = kh.total;
+        st.level_iters[lvl] = iters;
+      }
+      st.vertex_updates += (int64_t)nl * iters;
+      if (lvl == 0) st.finest_updates = (int64_t)nl * iters;
+    }
+    HIPCHK(hipMemcpyAsync(out_xy, xa.p, sizeof(float) * 2 * (size_t)n,
+                          g->mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (graph_levels) for (int32_t i = 0; i < G; ++i) graph_levels[i] = nlev[i];
+    st.t_coarsen_ms = t_coarsen;
+    st.t_khop_ms = t_khop;
+    st.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = st;
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_layout_batch");
+  }
+}
+
+}  // extern "C"

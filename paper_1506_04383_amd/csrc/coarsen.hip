@@ -67,13 +67,23 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     const int32_t* __restrict__ c, const int32_t* __restrict__ ew, const int32_t* __restrict__ label,
     const unsigned long long* __restrict__ W, double U, uint64_t stream, int colour,
     int32_t* __restrict__ prop, const int64_t* __restrict__ hoff, int32_t* __restrict__ gkeys,
-    long long* __restrict__ gsc) {
+    long long* __restrict__ gsc, const int32_t* __restrict__ gid, const int32_t* __restrict__ goff,
+    const double* __restrict__ Ug, const int32_t* __restrict__ gstop) {
   __shared__ int32_t skey[LP_WAVES][LP_SLOTS];
   __shared__ long long ssc[LP_WAVES][LP_SLOTS];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t v = blockIdx.x * LP_WAVES + w;
   if (v >= n) return;
-  const bool active = (int)(sm64_at(stream, (uint64_t)v) & 1ull) == colour;
+  // batches: each graph has its own U, draws keyed by the local vertex id, and
+  // graphs that stopped take no part in later rounds
+  uint64_t vid = (uint64_t)v;
+  if (gid) {
+    const int32_t g = gid[v];
+    if (gstop[g]) { if (l == 0) prop[v] = -1; return; }
+    U = Ug[g];
+    vid = (uint64_t)(v - goff[g]);
+  }
+  const bool active = (int)(sm64_at(stream, vid) & 1ull) == colour;
   if (!active) { if (l == 0) prop[v] = -1; return; }
   const int32_t beg = rp[v], deg = rp[v + 1] - beg;
   const int32_t own = label[v];
@@ -153,10 +163,13 @@ __global__ void k_gather_c(int64_t m, const int32_t* __restrict__ vals, const in
 }
 __global__ void k_admit(int64_t m, const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
                         const int64_t* __restrict__ csum, const unsigned long long* __restrict__ W,
-                        double U, int32_t* __restrict__ label, int32_t* __restrict__ moves) {
+                        double U, int32_t* __restrict__ label, int32_t* __restrict__ moves,
+                        const int32_t* __restrict__ gid, const double* __restrict__ Ug,
+                        int32_t* __restrict__ gmoves) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const uint64_t L = keys[j];
+  if (gid) U = Ug[gid[vals[j]]];
   int64_t lo = 0, hi = j;  // first index with key == L
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
@@ -166,7 +179,17 @@ __global__ void k_admit(int64_t m, const uint64_t* __restrict__ keys, const int3
   if ((double)((long long)W[L] + run) <= U) {
     label[vals[j]] = (int32_t)L;
     atomicAdd(moves, 1);
+    if (gid) atomicAdd(&gmoves[gid[vals[j]]], 1);
   }
+}
+
+// After a round: graphs without moves stop (their result would not change
+// in the single-graph run, which ends there).
+__global__ void k_round_end(int32_t M, int32_t* __restrict__ gmoves, int32_t* __restrict__ gstop) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M) return;
+  if (gmoves[g] == 0) gstop[g] = 1;
+  gmoves[g] = 0;
 }
 
 __global__ void k_hash_sizes(int32_t n, const int32_t* __restrict__ rp, int64_t* __restrict__ sz) {
@@ -245,8 +268,18 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 }  // namespace
 
 hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed, int32_t level_h,
-                      int32_t* label, int32_t* rounds_run, int64_t* moves_host, hipStream_t s) {
+                      int32_t* label, int32_t* rounds_run, int64_t* moves_host, hipStream_t s,
+                      const LpSeg* seg) {
   const int32_t n = g.n;
+  const int32_t* gid = seg ? seg->gid : nullptr;
+  const int32_t* goff = seg ? seg->goff : nullptr;
+  const double* Ug = seg ? seg->Ug : nullptr;
+  int32_t* gstop = seg ? seg->gstop : nullptr;
+  DevBuf gmoves;
+  if (seg) {
+    MM_TRY(gmoves.alloc(sizeof(int32_t) * (size_t)seg->M, s));
+    MM_TRY(hipMemsetAsync(gmoves.p, 0, sizeof(int32_t) * (size_t)seg->M, s));
+  }
   DevBuf W, prop, flag, pos, keys, vals, cs, csum, moves, hsz, hoff, gk, gsc;
   MM_TRY(W.alloc(sizeof(unsigned long long) * (size_t)n, s));
   MM_TRY(prop.alloc(sizeof(int32_t) * (size_t)n, s));
@@ -278,7 +311,8 @@ hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed
       k_weights<<<nblk(n), 256, 0, s>>>(n, label, g.c, W.as<unsigned long long>());
       k_lp_propose<<<nblk(n, LP_WAVES), 64 * LP_WAVES, 0, s>>>(
           n, g.row_ptr, g.col, g.c, g.w, label, W.as<unsigned long long>(), U, st, colour,
-          prop.as<int32_t>(), hoff.as<int64_t>(), gk.as<int32_t>(), gsc.as<long long>());
+          prop.as<int32_t>(), hoff.as<int64_t>(), gk.as<int32_t>(), gsc.as<long long>(), gid, goff,
+          Ug, gstop);
       k_prop_flags<<<nblk(n), 256, 0, s>>>(n, prop.as<int32_t>(), flag.as<int32_t>());
       MM_TRY(scan_excl_i32(flag.as<int32_t>(), pos.as<int64_t>(), n, s));
       int64_t m = 0;
@@ -291,9 +325,11 @@ hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed
       k_gather_c<<<nblk(m), 256, 0, s>>>(m, vals.as<int32_t>(), g.c, cs.as<int32_t>());
       MM_TRY(scan_excl_i32(cs.as<int32_t>(), csum.as<int64_t>(), m, s));
       k_admit<<<nblk(m), 256, 0, s>>>(m, keys.as<uint64_t>(), vals.as<int32_t>(), csum.as<int64_t>(),
-                                      W.as<unsigned long long>(), U, label, moves.as<int32_t>());
+                                      W.as<unsigned long long>(), U, label, moves.as<int32_t>(),
+                                      gid, Ug, gmoves.as<int32_t>());
       MM_TRY(hipGetLastError());
     }
+    if (seg) k_round_end<<<nblk(seg->M), 256, 0, s>>>(seg->M, gmoves.as<int32_t>(), gstop);
     int32_t mv = 0;
     MM_TRY(hipMemcpyAsync(&mv, moves.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MM_TRY(hipStreamSynchronize(s));

@@ -65,6 +65,8 @@ __global__ __launch_bounds__(BB_T) void k_bbox_partial(const float2* __restrict_
   }
 }
 
+__device__ void make_box(float4 r, BoxInfo* box);
+
 __global__ void k_bbox_final(const float4* __restrict__ part, int nb, BoxInfo* box) {
   if (threadIdx.x != 0) return;
   float4 r = part[0];
@@ -72,6 +74,39 @@ __global__ void k_bbox_final(const float4* __restrict__ part, int nb, BoxInfo* b
     r.x = fminf(r.x, part[i].x); r.y = fminf(r.y, part[i].y);
     r.z = fmaxf(r.z, part[i].z); r.w = fmaxf(r.w, part[i].w);
   }
+  make_box(r, box);
+}
+
+// One box per graph of a batch (block per graph).
+__global__ __launch_bounds__(BB_T) void k_bbox_seg(const float2* __restrict__ xy,
+                                                   const int32_t* __restrict__ goff,
+                                                   BoxInfo* __restrict__ box) {
+  const int32_t a = goff[blockIdx.x], b = goff[blockIdx.x + 1];
+  float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+  for (int32_t i = a + threadIdx.x; i < b; i += BB_T) {
+    float2 p = xy[i];
+    xmin = fminf(xmin, p.x); xmax = fmaxf(xmax, p.x);
+    ymin = fminf(ymin, p.y); ymax = fmaxf(ymax, p.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    xmin = fminf(xmin, __shfl_xor(xmin, o, 64)); xmax = fmaxf(xmax, __shfl_xor(xmax, o, 64));
+    ymin = fminf(ymin, __shfl_xor(ymin, o, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, o, 64));
+  }
+  __shared__ float4 sh[BB_T / 64];
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = make_float4(xmin, ymin, xmax, ymax);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float4 r = sh[0];
+    for (int i = 1; i < BB_T / 64; ++i) {
+      r.x = fminf(r.x, sh[i].x); r.y = fminf(r.y, sh[i].y);
+      r.z = fmaxf(r.z, sh[i].z); r.w = fmaxf(r.w, sh[i].w);
+    }
+    make_box(r, box + blockIdx.x);
+  }
+}
+
+// Square box with power-of-two side over the extent r = (xmin, ymin, xmax, ymax).
+__device__ void make_box(float4 r, BoxInfo* box) {
   double xmin = r.x, ymin = r.y;
   double ext = fmax((double)r.z - xmin, (double)r.w - ymin);
   int e = 0;
@@ -105,17 +140,21 @@ __device__ inline uint32_t compact24(uint64_t x) {
   return (uint32_t)x & 0xFFFFFFu;
 }
 
+// gid (may be null): graph of each point in a batch; its index goes above
+// the 48 code bits and its own box is used.
 __global__ void k_morton(const float2* __restrict__ xy, int32_t n, const BoxInfo* __restrict__ box,
-                         uint64_t* __restrict__ codes, int32_t* __restrict__ ids) {
+                         const int32_t* __restrict__ gid, uint64_t* __restrict__ codes,
+                         int32_t* __restrict__ ids) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const BoxInfo b = *box;
+  const int32_t g = gid ? gid[i] : 0;
+  const BoxInfo b = box[g];
   float2 p = xy[i];
   double fx = floor(((double)p.x - b.xmin) * b.scale);
   double fy = floor(((double)p.y - b.ymin) * b.scale);
   fx = fmin(fmax(fx, 0.0), 16777215.0);
   fy = fmin(fmax(fy, 0.0), 16777215.0);
-  codes[i] = spread24((uint32_t)fx) | (spread24((uint32_t)fy) << 1);
+  codes[i] = spread24((uint32_t)fx) | (spread24((uint32_t)fy) << 1) | ((uint64_t)g << 48);
   ids[i] = i;
 }
 
@@ -198,7 +237,7 @@ __global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
     vals[slot] = slot;
     tmp[slot] = make_int4(i, lo - 1, 24, 1);
   }
-  if (i + 1 < n && codes[i + 1] != ci) {
+  if (i + 1 < n && codes[i + 1] != ci && (codes[i + 1] >> 48) == (ci >> 48)) {
     const int t = lcp48(ci, codes[i + 1]) >> 1;
     const int sh = 48 - 2 * t;
     const uint64_t pre = ci >> sh;
@@ -270,7 +309,9 @@ template <bool STATS>
 __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np, const float* __restrict__ xsx,
     const float* __restrict__ xsy, const uint2* __restrict__ ixy, const int32_t* __restrict__ order,
-    int32_t n, float q, double theta2, float2* __restrict__ F, unsigned long long* __restrict__ stats) {
+    int32_t n, float q, double theta2, float2* __restrict__ F, unsigned long long* __restrict__ stats,
+    const uint64_t* __restrict__ scodes, const int32_t* __restrict__ goff,
+    const int32_t* __restrict__ first_at) {
   const int l = lane_id();
   const int32_t i = (blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 + l;
   if ((blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 >= n) return;
@@ -280,9 +321,17 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
   const double qx2 = 2.0 * (double)qt.x + 1.0, qy2 = 2.0 * (double)qt.y + 1.0;
   float fx = 0.f, fy = 0.f;
-  int32_t next = valid ? 0 : 0x7fffffff;
+  // nodes of this lane's tree: [root, end) (a batch holds one tree per graph,
+  // graph g owning sorted points [goff[g], goff[g+1]))
+  int32_t root = 0, end = N;
+  if (goff && valid) {
+    const int32_t g = (int32_t)(scodes[i] >> 48);
+    root = first_at[goff[g]];
+    end = goff[g + 1] < n ? first_at[goff[g + 1]] : N;
+  }
+  int32_t next = valid ? root : 0x7fffffff;
   unsigned long long acc = 0, pairs = 0;
-  int32_t p = 0;
+  int32_t p = wave_min(next);
   while (p < N) {
     p = __builtin_amdgcn_readfirstlane(p);
     const BHNode nd = nodes[p];
@@ -298,7 +347,7 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
           if (STATS && added) pairs++;
         }
       }
-      if (act) next = nd.skip;
+      if (act) next = nd.skip >= end ? 0x7fffffff : nd.skip;
       p = wave_min(next);
     } else {
       bool opened = false;
@@ -316,7 +365,7 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
         if (accept) {
           rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, nd.mass, fx, fy);
           if (STATS) acc++;
-          next = nd.skip;
+          next = nd.skip >= end ? 0x7fffffff : nd.skip;
         } else {
           next = p + 1;
           opened = true;
@@ -364,7 +413,7 @@ hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStr
 }
 
 hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_out,
-                         hipStream_t s) {
+                         hipStream_t s, const BHSeg* seg) {
   const size_t N2 = 2 * (size_t)n;
   MM_TRY(ensure<uint64_t>(w->codes, n, s));
   MM_TRY(ensure<int32_t>(w->order, n, s));
@@ -379,7 +428,8 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   MM_TRY(ensure<int32_t>(w->first_at, n, s));
   MM_TRY(ensure<BHNode>(w->nodes, N2, s));
   MM_TRY(ensure<int32_t>(w->counter, 1, s));
-  MM_TRY(ensure<BoxInfo>(w->box, 1, s));
+  const int32_t M = seg ? seg->M : 1;
+  MM_TRY(ensure<BoxInfo>(w->box, (size_t)M, s));
   const int nbb = std::min(1024, std::max(1, (n + BB_T - 1) / BB_T));
   MM_TRY(ensure<float4>(w->partial, nbb, s));
   const int32_t nps = (n + PS_TILE - 1) / PS_TILE;
@@ -387,12 +437,19 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   MM_TRY(pparts.alloc(sizeof(double) * (size_t)(nps + 1), s));
   MM_TRY(ensure<unsigned long long>(w->statc, 2, s));
 
-  k_bbox_partial<<<nbb, BB_T, 0, s>>>((const float2*)xy, n, w->partial.as<float4>());
-  k_bbox_final<<<1, 64, 0, s>>>(w->partial.as<float4>(), nbb, w->box.as<BoxInfo>());
+  int cbits = 48;
+  if (seg) {
+    k_bbox_seg<<<M, BB_T, 0, s>>>((const float2*)xy, seg->goff, w->box.as<BoxInfo>());
+    while ((1ll << (cbits - 48)) < (int64_t)M) cbits++;
+  } else {
+    k_bbox_partial<<<nbb, BB_T, 0, s>>>((const float2*)xy, n, w->partial.as<float4>());
+    k_bbox_final<<<1, 64, 0, s>>>(w->partial.as<float4>(), nbb, w->box.as<BoxInfo>());
+  }
   k_morton<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(),
-                                           w->codes.as<uint64_t>(), w->order.as<int32_t>());
+                                           seg ? seg->gid : nullptr, w->codes.as<uint64_t>(),
+                                           w->order.as<int32_t>());
   MM_TRY(hipGetLastError());
-  MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, 48, s));
+  MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, cbits, s));
   k_gather_sorted<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, w->order.as<int32_t>(),
                                                   w->codes.as<uint64_t>(), n, w->xsx.as<float>(),
                                                   w->xsy.as<float>(), w->ix.as<uint2>());
@@ -427,8 +484,11 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
 
 hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
                        uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
-                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s) {
-  MM_TRY(bh_build_tree(w, n, xy, nodes_out, s));
+                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s,
+                       const BHSeg* seg) {
+  MM_TRY(bh_build_tree(w, n, xy, nodes_out, s, seg));
+  const uint64_t* sc = seg ? w->codes.as<uint64_t>() : nullptr;
+  const int32_t* go = seg ? seg->goff : nullptr;
   const int32_t* Np = w->counter.as<int32_t>();
   if (count_stats) MM_TRY(hipMemsetAsync(w->statc.p, 0, 2 * sizeof(unsigned long long), s));
   const int32_t nw = (n + 63) / 64;
@@ -437,18 +497,19 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
     k_traverse<true><<<nblk, 64 * TR_WAVES, 0, s>>>(
         w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
         w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F,
-        w->statc.as<unsigned long long>());
+        w->statc.as<unsigned long long>(), sc, go, w->first_at.as<int32_t>());
   else
     k_traverse<false><<<nblk, 64 * TR_WAVES, 0, s>>>(
         w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
-        w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F, nullptr);
+        w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F, nullptr, sc, go,
+        w->first_at.as<int32_t>());
   MM_TRY(hipGetLastError());
   if (codes_out) {
     // codes in id order
     DevBuf tmp;
     MM_TRY(tmp.alloc(sizeof(uint64_t) * (size_t)n, s));
     k_morton<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(),
-                                             codes_out, tmp.as<int32_t>());
+                                             seg ? seg->gid : nullptr, codes_out, tmp.as<int32_t>());
   }
   if (order_out)
     MM_TRY(hipMemcpyAsync(order_out, w->order.p, sizeof(int32_t) * (size_t)n,

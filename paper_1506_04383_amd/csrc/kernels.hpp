@@ -97,11 +97,20 @@ hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStr
 // codes[n], order[n], nodes[5*(2n)] (depth, first, count, leaf, prefix per node in pre-order),
 // stats (host) receives counters (nodes always; interaction counters when count_stats).
 struct BHWork;  // persistent buffers, sized by n
+// A batch of independent graphs laid out together: graph g owns points
+// [goff[g], goff[g+1]) (device arrays; gid[v] = graph of point v).  Each
+// graph gets its own box and its own tree.
+struct BHSeg {
+  int32_t M = 0;
+  const int32_t* gid = nullptr;
+  const int32_t* goff = nullptr;
+};
 BHWork* bh_work_create();
 void bh_work_destroy(BHWork*);
 hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
                        uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
-                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s);
+                       int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s,
+                       const BHSeg* seg = nullptr);
 
 // ---- learned far-field correction (learned.hip), q = 0
 constexpr int32_t kMlpParams = 4866;  // W1 64x8, b1, W2 64x64, b2, W3 2x64, b3
@@ -122,9 +131,12 @@ hipError_t mlp_train(int64_t N, const float* feat, const float* tgt, float* wts,
 // One Jacobi iteration of Eq. 2 over the k-hop sets. sqrtc: sqrt of node
 // weights (null at level 0 => d = hop). delta2 (device, 2 doubles) receives
 // sum |x'-x|^2 and sum |x|^2.
+// gid/galpha (batches, may be null): alpha of each graph; < 0 = finished
+// graph (coordinates copied).
 hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
-                 double* delta2_dev, hipStream_t s);
+                 double* delta2_dev, hipStream_t s, const int32_t* gid = nullptr,
+                 const float* galpha = nullptr);
 
 // ---- coarsening (coarsen.hip)
 struct GraphDev {
@@ -138,8 +150,21 @@ struct GraphDev {
 };
 // Runs synchronous size-constrained label propagation; label[n] (device) is
 // initialised to v. Returns rounds run in *rounds_run.
+// Batches (block-diagonal union of M graphs): graph of each vertex gid,
+// vertex offsets goff (M+1), per-graph U (Ug) and stop flags (gstop, in/out:
+// graphs flagged take no part; a graph stops after a round without moves).
+// Draws are keyed by the local vertex id, so every graph is clustered as it
+// would be alone.
+struct LpSeg {
+  int32_t M = 0;
+  const int32_t* gid = nullptr;
+  const int32_t* goff = nullptr;
+  const double* Ug = nullptr;
+  int32_t* gstop = nullptr;
+};
 hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed, int32_t level_h,
-                      int32_t* label, int32_t* rounds_run, int64_t* moves_host, hipStream_t s);
+                      int32_t* label, int32_t* rounds_run, int64_t* moves_host, hipStream_t s,
+                      const LpSeg* seg = nullptr);
 hipError_t contract(const GraphDev& g, const int32_t* label, int32_t* cluster, GraphDev* out,
                     hipStream_t s);
 
@@ -149,6 +174,44 @@ hipError_t prolong(int32_t n_fine, const int32_t* cluster, const int32_t* coarse
                    const float* coarse_xy, uint64_t seed, int32_t level, float* fine_xy,
                    hipStream_t s);
 hipError_t sqrt_weights(int32_t n, const int32_t* c, float* out, hipStream_t s);
+// Batches: draws keyed by local vertex ids.  init: graphs flagged in top;
+// prolong: vertices with cluster >= 0; pairs: flagged two-vertex graphs.
+hipError_t init_layout_seg(int32_t n, uint64_t seed, int32_t level, const int32_t* gid,
+                           const int32_t* goff, const uint8_t* top, float* xy, hipStream_t s);
+hipError_t prolong_seg(int32_t n_fine, const int32_t* cluster, const int32_t* coarse_c,
+                       const float* coarse_xy, uint64_t seed, int32_t level, const int32_t* gid,
+                       const int32_t* goff, float* fine_xy, hipStream_t s);
+hipError_t place_pairs_seg(int32_t M, const int32_t* goff, const uint8_t* top, const int32_t* c,
+                           int32_t level, double scale, float* xy, hipStream_t s);
+
+// ---- batches of independent graphs (batch.hip)
+struct BatchSched {
+  double alpha_min, decay, eps_round, eps_final;
+  int32_t a, max_final;
+};
+struct BatchState {
+  double alpha, delta;
+  int32_t phase;  // 0 rounds, 1 final phase at alpha_min, 2 done, 3 non-finite layout
+  int32_t k, iters, final_iters, cap_hit, pad;
+};
+hipError_t batch_fill_gid(int32_t M, const int32_t* goff, int32_t* gid, hipStream_t s);
+hipError_t batch_max_c(int32_t M, const int32_t* goff, const int32_t* c, int32_t* out,
+                       hipStream_t s);
+// out: 2 doubles per graph (sum |x'-x|^2, sum |x|^2)
+hipError_t batch_delta(int32_t M, const int32_t* goff, const float* x, const float* xn,
+                       double* out, hipStream_t s);
+hipError_t batch_sched_init(int32_t M, const BatchSched& prm, double alpha_start, BatchState* st,
+                            float* galpha, hipStream_t s);
+// counters[0] += graphs still iterating, counters[1] += graphs with a non-finite layout
+hipError_t batch_schedule(int32_t M, const double* gd, const BatchSched& prm, BatchState* st,
+                          float* galpha, int32_t* counters, hipStream_t s);
+hipError_t batch_coarse_offsets(int32_t n, int32_t M, int32_t nc, const int32_t* cluster,
+                                const int32_t* gid, int32_t* gidc, int32_t* goffc, hipStream_t s);
+// The graphs flagged in keep (vertex flags / new ids into flag[n], newid[n+1]).
+hipError_t batch_subset(const GraphDev& g, const int32_t* gid, const uint8_t* keep, GraphDev* out,
+                        int32_t* flag, int64_t* newid, hipStream_t s);
+hipError_t batch_cl_map(int32_t n, const int32_t* cluster, const int32_t* cflag,
+                        const int64_t* cnewid, int32_t* cl, hipStream_t s);
 
 // ---- objectives (objective.hip)
 // out (host, 3 doubles): stress over S, entropy sum over pairs not in S, coincident pairs.

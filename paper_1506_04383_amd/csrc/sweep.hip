@@ -25,13 +25,19 @@ __global__ __launch_bounds__(SW_T) void k_sweep(
     int32_t n, int32_t k, const int64_t* __restrict__ off, const int32_t* __restrict__ hend,
     const int32_t* __restrict__ nbr, const float* __restrict__ sqrtc, float scale,
     const float2* __restrict__ xy, const float2* __restrict__ F, float alpha, float q,
-    float2* __restrict__ out, double2* __restrict__ part) {
+    float2* __restrict__ out, double2* __restrict__ part, const int32_t* __restrict__ gid,
+    const float* __restrict__ galpha) {
   constexpr int RPB = SW_T / G;  // rows per block
   __shared__ double2 red[RPB];
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
   const int32_t u = blockIdx.x * RPB + gi;
   double2 dd = make_double2(0.0, 0.0);
-  if (u < n) {
+  // batches: each graph has its own alpha; a negative one marks a finished
+  // graph, whose coordinates are carried over unchanged
+  if (galpha && u < n) alpha = galpha[gid[u]];
+  if (u < n && alpha < 0.f) {
+    if (gl == 0) out[u] = xy[u];
+  } else if (u < n) {
     const int64_t beg = off[u], end = off[u + 1];
     int32_t he[KMAX];
 #pragma unroll
@@ -126,13 +132,13 @@ __global__ __launch_bounds__(1024) void k_sum_parts(const double2* __restrict__ 
 template <int G>
 hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, float scale,
                   const float* xy, const float* F, float alpha, float q, float* out, double2* part,
-                  int32_t nb, hipStream_t s) {
+                  int32_t nb, hipStream_t s, const int32_t* gid, const float* galpha) {
   const float2* x2 = (const float2*)xy;
   const float2* F2 = (const float2*)F;
   float2* o2 = (float2*)out;
 #define MM_SW(C, Q)                                                                          \
   k_sweep<G, C, Q><<<nb, SW_T, 0, s>>>(kh.n, kh.k, kh.off, kh.hend, kh.nbr, sqrtc, scale, x2, \
-                                       F2, alpha, q, o2, part)
+                                       F2, alpha, q, o2, part, gid, galpha)
   if (coarse) { if (q0) MM_SW(true, true); else MM_SW(true, false); }
   else { if (q0) MM_SW(false, true); else MM_SW(false, false); }
 #undef MM_SW
@@ -143,7 +149,7 @@ hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, f
 
 hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
-                 double* delta2_dev, hipStream_t s) {
+                 double* delta2_dev, hipStream_t s, const int32_t* gid, const float* galpha) {
   if (kh.k > KMAX) return hipErrorInvalidValue;
   const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
   int G = avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
@@ -155,10 +161,10 @@ hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double sc
   const bool q0 = (q == 0.0);
   hipError_t e;
   switch (G) {
-    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
-    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
-    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
-    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s); break;
+    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
+    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
+    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
+    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
   }
   MM_TRY(e);
   k_sum_parts<<<1, 1024, 0, s>>>(part.as<double2>(), nb, delta2_dev);

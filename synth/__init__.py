@@ -22,3 +22,4 @@ from .graphs import (  # noqa: F401
     config_graph,
 )
 from .dynamic import churn_snapshot  # noqa: F401
+from .batch import batch_graphs, concat  # noqa: F401
