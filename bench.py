@@ -40,6 +40,133 @@ WORKLOADS = {
 }
 
 
+def batch_comparison(args):
+    """4096 uneven graphs (64..8192 vertices; grids, random trees, RGGs) laid
+    out in one batch vs one at a time (a uniform random sample of the same
+    graphs, scaled to the batch), k = 3, theta = 0.5, hierarchy to <= 100
+    vertices per graph.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1506_04383_amd as mm
+    import synth
+
+    ctx = mm.Context(0)
+    t0 = time.perf_counter()
+    gs = synth.batch_graphs(args.batch_graphs, args.seed)
+    rp, col, offs = synth.concat(gs)
+    print(f"[batch] {len(gs)} graphs, n={int(offs[-1])}, generated in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    P = dict(k=3, theta=0.5, alpha_decay=0.5, coarsest_n=100, seed=args.seed, validate=0)
+    dg = ctx.graph(rp, col)
+    if args.warmup:
+        mm.layout_batch(ctx, dg, None, offs, mm.Params(**P))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xy, lev, st = mm.layout_batch(ctx, dg, None, offs, mm.Params(**P))
+    torch.cuda.synchronize()
+    T_batch = time.perf_counter() - t0
+    print(f"[batch] batched layout {T_batch:.2f}s, {st['levels']} union levels",
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng(args.seed)
+    sample = rng.choice(len(gs), size=min(args.batch_sample, len(gs)), replace=False)
+    times, rel = [], []
+    for j, i in enumerate(sample):
+        g = gs[int(i)]
+        dgi = ctx.graph(g.row_ptr, g.col)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x1, _ = mm.layout(ctx, dgi, mm.Params(**P))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        kh = mm.khop_build(ctx, dgi, 3)
+        Mb = mm.objective(ctx, kh, xy[int(offs[i]):int(offs[i + 1])], 0.008)["M"]
+        M1 = mm.objective(ctx, kh, x1, 0.008)["M"]
+        kh.free()
+        rel.append((Mb - M1) / abs(M1))
+        if j % 16 == 15:
+            print(f"[batch] {j + 1} single layouts timed", file=sys.stderr, flush=True)
+    times = np.array(times)
+    T_seq = float(times.mean() * len(gs))
+    T_seq_se = float(times.std(ddof=1) / np.sqrt(times.size) * len(gs))
+    rel = np.array(rel)
+    out = {"metric": "time to lay out 4096 uneven graphs, batched vs one at a time",
+           "value": T_seq / T_batch, "unit": "speedup (x)", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(gs)} graphs, n log-uniform in [64, 8192], grids / "
+                      "random recursive trees / RGG (deg 6, LCC); k=3, theta=0.5, hierarchy "
+                      "to <=100 vertices per graph", "graphs": len(gs), "n": int(offs[-1]),
+                      "m": int(rp[-1]) // 2, "seed": args.seed},
+           "batched_s": T_batch, "one_at_a_time_s_estimate": T_seq,
+           "one_at_a_time_s_stderr": T_seq_se,
+           "one_at_a_time_sample": int(times.size),
+           "batched_graphs_per_s": len(gs) / T_batch,
+           "union_levels": st["levels"], "union_iters_per_level":
+               [l["iters"] for l in st["per_level"]],
+           "stress_rel_diff_batched_vs_single": {"mean": float(rel.mean()),
+                                                 "max_abs": float(np.abs(rel).max())}}
+    print(json.dumps(out))
+    ctx.close()
+
+
+def snapshot_comparison(args):
+    """64 snapshots of RGG 2^16 (mean degree 6), each with 1% of its edges
+    replaced (non-tree edges dropped, new edges to vertices 2 hops away); each
+    snapshot warm-started from the previous layout at alpha_min on the finest
+    level, vs laying it out from scratch.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1506_04383_amd as mm
+    import synth
+
+    ctx = mm.Context(0)
+    g = synth.config_graph("rgg16", args.seed)
+    snaps = [g]
+    t0 = time.perf_counter()
+    for i in range(1, args.snapshots):
+        snaps.append(synth.churn_snapshot(snaps[-1], args.seed * 1000 + i, 0.01, 2))
+        if i % 8 == 0:
+            print(f"[snap] generated {i} snapshots ({time.perf_counter() - t0:.0f}s)",
+                  file=sys.stderr, flush=True)
+    dgs = [ctx.graph(s.row_ptr, s.col) for s in snaps]
+    P = dict(k=3, theta=0.5, alpha_decay=0.5, coarsest_n=100, seed=args.seed, validate=0)
+    x, _ = mm.layout(ctx, dgs[0], mm.Params(**P))
+    torch.cuda.synchronize()
+    warm_t, warm_M, scratch_t, scratch_M, idx = [], [], [], [], []
+    for i in range(1, len(snaps)):
+        t1 = time.perf_counter()
+        x, st = mm.layout(ctx, dgs[i], mm.Params(**P), init_xy=x)
+        torch.cuda.synchronize()
+        warm_t.append(time.perf_counter() - t1)
+        if i % args.snapshot_scratch_every == 0:
+            kh = mm.khop_build(ctx, dgs[i], 3)
+            t1 = time.perf_counter()
+            xs, _ = mm.layout(ctx, dgs[i], mm.Params(**P))
+            torch.cuda.synchronize()
+            scratch_t.append(time.perf_counter() - t1)
+            warm_M.append(mm.objective(ctx, kh, x, 0.008)["M"])
+            scratch_M.append(mm.objective(ctx, kh, xs, 0.008)["M"])
+            kh.free()
+            idx.append(i)
+    warm_t = np.array(warm_t)
+    ratio = np.array(warm_M) / np.array(scratch_M)
+    out = {"metric": "time per snapshot, warm-started dynamic update vs layout from scratch",
+           "value": float(np.mean(scratch_t) / warm_t.mean()), "unit": "speedup (x)",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(snaps)} snapshots of RGG 2^16 (deg 6, LCC), 1% edge "
+                      "churn per snapshot (D=2); warm start at alpha_min on the finest level; "
+                      "k=3, theta=0.5", "n": g.n, "m": g.m, "seed": args.seed},
+           "warm_s_per_snapshot": float(warm_t.mean()),
+           "warm_s_total": float(warm_t.sum()),
+           "scratch_s_per_snapshot": float(np.mean(scratch_t)),
+           "scratch_sample": idx,
+           "stress_ratio_warm_vs_scratch": {"mean": float(ratio.mean()),
+                                            "min": float(ratio.min()), "max": float(ratio.max())}}
+    print(json.dumps(out))
+    ctx.close()
+
+
 def learned_comparison(args):
     """Learned far field vs plain Barnes-Hut on RGG 2^22 (k = 3): the network is
     trained on the GPU on exact residuals of cells accepted at theta = 1 in
@@ -189,9 +316,15 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
-    ap.add_argument("--mode", default="layout", choices=["layout", "learned"],
+    ap.add_argument("--mode", default="layout",
+                    choices=["layout", "learned", "batch", "snapshots"],
                     help="layout: the layout benchmark; learned: learned far field vs plain "
-                         "Barnes-Hut on RGG 2^22")
+                         "Barnes-Hut on RGG 2^22; batch: 4096 graphs batched vs one at a "
+                         "time; snapshots: warm-started dynamic snapshots vs scratch")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-sample", type=int, default=96)
+    ap.add_argument("--snapshots", type=int, default=64)
+    ap.add_argument("--snapshot-scratch-every", type=int, default=8)
     ap.add_argument("--train-graphs", type=int, default=4)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -217,6 +350,12 @@ def main():
 
     if args.mode == "learned":
         learned_comparison(args)
+        return
+    if args.mode == "batch":
+        batch_comparison(args)
+        return
+    if args.mode == "snapshots":
+        snapshot_comparison(args)
         return
 
     import paper_1506_04383_amd as mm

@@ -288,6 +288,7 @@ def layout_batch(ctx: Context, row_ptr, col, graph_off, params: Params | None = 
     offs = np.ascontiguousarray(graph_off, dtype=np.int64)
     G = offs.size - 1
     dg = row_ptr if isinstance(row_ptr, DeviceGraph) else DeviceGraph(ctx, row_ptr, col)
+    # row_ptr may be a DeviceGraph already on the device (col is then ignored)
     p = (params or Params()).to_c()
     out = t.empty((dg.n, 2), dtype=t.float32, device=f"cuda:{ctx.device}")
     init = None if init_xy is None else ctx._dev(init_xy, t.float32)
