@@ -248,30 +248,95 @@ struct QRow {
   int32_t lane, pad;
 };
 
-// Runs the MLP on rows [qh, qh + rows) of the ring (rows <= 16, wave-
-// uniform) and adds each row's correction to its lane, in queue order.
+// Runs the MLP on rows [qh, qh + rows) of the ring (rows <= 64, wave-
+// uniform) as up to four 16-row blocks interleaved layer by layer (their
+// matrix-core chains are independent), then adds each row's correction to
+// its lane, in queue order.
 __device__ inline void flush_rows(const MlpLds& L, const QRow* ring, int qh, int rows,
                                   float& cfx, float& cfy) {
+  // the weights are read from LDS here rather than held in registers across
+  // the traversal (occupancy)
+  asm volatile("" ::: "memory");
   const int l = lane_id(), r = l & 15, g = l >> 4;
-  v4s x = {0, 0, 0, 0};
-  if (g < 2 && r < rows) {
-    const QRow& e = ring[(qh + r) & (QCAP - 1)];
+  const int nb = (rows + 15) >> 4;
+  v4s x[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = (short)f2bf(e.f[4 * g + j]);
+  for (int b = 0; b < 4; ++b) {
+    x[b] = v4s{0, 0, 0, 0};
+    if (b < nb && g < 2 && 16 * b + r < rows) {
+      const QRow& e = ring[(qh + 16 * b + r) & (QCAP - 1)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[b][j] = (short)f2bf(e.f[4 * g + j]);
+    }
   }
-  const v4f o = mlp16<false>(L, x, nullptr, nullptr, nullptr, nullptr);
-  float ax = 0.f, ay = 0.f;
-  int32_t tl = -1;
-  if (g == 0 && r < rows) {
-    const QRow& e = ring[(qh + r) & (QCAP - 1)];
-    ax = o[0] * e.kex - o[1] * e.key;
-    ay = o[0] * e.key + o[1] * e.kex;
-    tl = e.lane;
+  v4s a1[4][4], a2[4][4];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    const v4s w = ld4(&L.w1[(ob * 16 + r) * 16 + 4 * g]);
+    float bias[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias[j] = L.b1[ob * 16 + 4 * g + j];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b < nb) {
+        const v4f c = mfma(w, x[b], v4f{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a1[b][ob][j] = (short)f2bf(fmaxf(c[j] + bias[j], 0.f));
+      }
+    }
   }
-  for (int j = 0; j < rows; ++j) {
-    const float bx = __shfl(ax, j, 64), by = __shfl(ay, j, 64);
-    const int32_t t = __shfl(tl, j, 64);
-    if (l == t) { cfx += bx; cfy += by; }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    v4f c[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const v4s w = ld4(&L.w2[(ob * 16 + r) * NH + kb * 16 + 4 * g]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (b < nb) c[b] = mfma(w, a1[b][kb], c[b]);
+    }
+    float bias[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias[j] = L.b2[ob * 16 + 4 * g + j];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < nb) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a2[b][ob][j] = (short)f2bf(fmaxf(c[b][j] + bias[j], 0.f));
+      }
+  }
+  v4f o[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) o[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const v4s w = ld4(&L.w3[r * NH + kb * 16 + 4 * g]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < nb) o[b] = mfma(w, a2[b][kb], o[b]);
+  }
+  const float b30 = L.b3[0], b31 = L.b3[1];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (b >= nb) break;
+    float ax = 0.f, ay = 0.f;
+    int32_t tl = -1;
+    if (g == 0 && 16 * b + r < rows) {
+      const QRow& e = ring[(qh + 16 * b + r) & (QCAP - 1)];
+      const float h0 = o[b][0] + b30, h1 = o[b][1] + b31;
+      ax = h0 * e.kex - h1 * e.key;
+      ay = h0 * e.key + h1 * e.kex;
+      tl = e.lane;
+    }
+    const int m = min(16, rows - 16 * b);
+    for (int j = 0; j < m; ++j) {
+      const int32_t t = __builtin_amdgcn_readlane(tl, j);
+      const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), j));
+      const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), j));
+      if (l == t) { cfx += bx; cfy += by; }
+    }
   }
 }
 
@@ -336,9 +401,9 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
         }
         qt_ += __popcll(bal);
         wave_lds_sync();
-        while (qt_ - qh >= 16) {
-          flush_rows(L, ring, qh, 16, cfx, cfy);
-          qh += 16;
+        if (qt_ - qh >= 64) {
+          flush_rows(L, ring, qh, 64, cfx, cfy);
+          qh += 64;
         }
         wave_lds_sync();
       }
@@ -346,7 +411,10 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
       else p = wave_min(next);
     }
   }
-  if (qt_ > qh) flush_rows(L, ring, qh, qt_ - qh, cfx, cfy);
+  while (qt_ > qh) {
+    flush_rows(L, ring, qh, min(64, qt_ - qh), cfx, cfy);
+    qh += 64;
+  }
   if (valid) F[order[i]] = make_float2(fx + cfx, fy + cfy);
 }
 

@@ -175,12 +175,18 @@ __global__ void k_tile_first(int64_t m, const uint64_t* __restrict__ skey,
   const uint32_t t = (uint32_t)(skey[c] >> 32);
   if (c == 0 || (uint32_t)(skey[c - 1] >> 32) != t) tile_first[t] = (int32_t)c;
 }
-// unit starts: the first chunk of a tile and every UNIT_CH-th chunk after it
+// unit starts: the first chunk of a tile, every UNIT_CH-th chunk after it,
+// and every chunk that begins a new span of emax entries (so that levels with
+// few, long chunks still give enough work units to fill the chip)
 __global__ void k_unit_flags(int64_t m, const uint64_t* __restrict__ skey,
-                             const int32_t* __restrict__ tile_first, int32_t* __restrict__ flag) {
+                             const int32_t* __restrict__ tile_first,
+                             const int64_t* __restrict__ chunk_off, int64_t emax,
+                             int32_t* __restrict__ flag) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m) return;
-  flag[c] = ((c - tile_first[skey[c] >> 32]) % UNIT_CH == 0) ? 1 : 0;
+  const int64_t tf = tile_first[skey[c] >> 32];
+  flag[c] = ((c - tf) % UNIT_CH == 0 || (c > tf && chunk_off[c] / emax != chunk_off[c - 1] / emax))
+                ? 1 : 0;
 }
 __global__ void k_unit_fill(int64_t m, const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
                            const uint64_t* __restrict__ skey, int32_t* __restrict__ unit_c0,
@@ -522,8 +528,11 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
     DevBuf tfirst;
     MM_TRY(tfirst.alloc(sizeof(int32_t) * (size_t)ntiles, s));
     k_tile_first<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>());
+    // at least ~8 work units per CU when the level is small; never fewer
+    // than 64K entries per unit (the tile staging is amortised over them)
+    const int64_t emax = std::max<int64_t>(65536, padded / 2048);
     k_unit_flags<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>(),
-                                         flag.as<int32_t>());
+                                         ts->chunk_off, emax, flag.as<int32_t>());
   }
   MM_TRY(scan_excl_i32(flag.as<int32_t>(), upos.as<int64_t>(), m, s));
   int64_t nu = 0;
