@@ -73,6 +73,8 @@ typedef struct {
   int32_t validate;        /* 1: full host-side graph validation (default) */
   const float* mlp_weights;/* device, MM_MLP_PARAMS floats: learned far-field correction
                               (Barnes-Hut only, q = 0); NULL = plain Barnes-Hut (default) */
+  int32_t use_graphs;      /* 1: replay the iterations of levels with <= 2^18 vertices from
+                              HIP graphs (default; same results, fewer launches); 0: direct */
 } mm_params;
 
 #define MM_MAX_LEVELS 64

@@ -42,7 +42,8 @@ class MMParams(C.Structure):
                 ("eps_final", C.c_double), ("max_final_iters", C.c_int32),
                 ("max_levels", C.c_int32), ("coarsest_n", C.c_int32), ("b", C.c_double),
                 ("f", C.c_double), ("lp_rounds", C.c_int32), ("coarse_dist_scale", C.c_double),
-                ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p)]
+                ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p),
+                ("use_graphs", C.c_int32)]
 
 
 class MMStats(C.Structure):
@@ -180,6 +181,7 @@ class Params:
     seed: int = 1
     validate: int = 1
     mlp_weights: object = None  # float32 device tensor of MLP_PARAMS (learned far field)
+    use_graphs: int = 1  # replay small levels' iterations from HIP graphs
 
     def to_c(self) -> MMParams:
         p = MMParams()

@@ -32,7 +32,8 @@ struct BoxInfo {
 struct BHWork {
   int32_t cap = 0;
   DevBuf codes, order, xsx, xsy, ix, px, py, nkeys, nvals, ntmp, first_at, nodes, counter, box,
-      partial, statc;
+      partial, statc, pparts;
+  SortWork sort;
   // learned far field: per-node moments and cell records, sample offsets
   DevBuf mom, cell, ndepth, scount, soff;
 };

@@ -19,11 +19,19 @@
 #include "mulment.h"
 #include "kernels.hpp"
 
+// Levels up to this many vertices replay their iterations from HIP graphs
+// (their time is dominated by launches; the buffers of such levels keep the
+// single-launch scan paths, so no allocation happens inside a capture).
+constexpr int32_t kGraphMaxN = 1 << 18;
+
 struct mm_context {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the caller's stream
+  hipStream_t work = nullptr;    // the layout drivers' own stream (capturable)
   mm::BHWork* bh = nullptr;
-  double* pinned = nullptr;  // 4 doubles for small read-backs
+  double* pinned = nullptr;      // 4 doubles for small read-backs
+  float* alpha_pinned = nullptr; // alpha of the next replayed iteration
+  float* alpha_dev = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 struct mm_khop {
@@ -167,6 +175,8 @@ mm_status mm_params_default(mm_params* p) {
   p->coarse_dist_scale = 1.0;
   p->seed = 1;
   p->validate = 1;
+  p->mlp_weights = nullptr;
+  p->use_graphs = 1;
   return MM_OK;
 }
 
@@ -182,6 +192,9 @@ mm_status mm_context_create(mm_context** out, int32_t device, void* stream) {
     c->stream = (hipStream_t)stream;
     c->bh = mm::bh_work_create();
     HIPCHK(hipHostMalloc((void**)&c->pinned, 4 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->alpha_pinned, sizeof(float), hipHostMallocDefault));
+    HIPCHK(hipMalloc((void**)&c->alpha_dev, sizeof(float)));
+    HIPCHK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     *out = c.release();
     return MM_OK;
@@ -196,7 +209,11 @@ void mm_context_destroy(mm_context* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   mm::bh_work_destroy(ctx->bh);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->work) (void)hipStreamSynchronize(ctx->work);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->alpha_pinned) (void)hipHostFree(ctx->alpha_pinned);
+  if (ctx->alpha_dev) (void)hipFree(ctx->alpha_dev);
+  if (ctx->work) (void)hipStreamDestroy(ctx->work);
   for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -561,7 +578,11 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
     if (g->nnz < 1 || g->nnz >= (1ll << 31)) return fail(MM_EINVAL, "nnz out of range");
     if (g->mem != MM_HOST && g->mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");
     DeviceGuard dg(ctx->device);
-    hipStream_t s = ctx->stream;
+    // the layout runs on the context's own stream (capturable into HIP graphs),
+    // after the work the caller queued on its stream
+    hipStream_t s = ctx->work;
+    HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
+    HIPCHK(hipStreamWaitEvent(s, ctx->ev[3], 0));
     const int32_t n = g->n;
     const int64_t nnz = g->nnz;
     auto t_start = std::chrono::steady_clock::now();
@@ -732,37 +753,118 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       }
       int32_t iters = 0, final_iters = 0, cap_hit = 0;
       double delta = 0;
-      auto iterate = [&](double alpha) -> mm_status {
-        HIPCHK(hipEventRecord(ctx->ev[0], s));
+      mm::DevBuf sweep_part;
+      // one iteration: far field of xin, sweep into xout (alpha from device
+      // memory when replayed), relative-change partials to the pinned buffer
+      auto enqueue = [&](double alpha, const float* xin, float* xout, const float* adev) -> hipError_t {
         if (p->theta < 0) {
-          HIPCHK(mm::farfield_exact(nl, xa.as<float>(), p->q, F.as<float>(), s));
+          MM_TRY(mm::farfield_exact(nl, xin, p->q, F.as<float>(), s));
         } else if (p->mlp_weights) {
-          HIPCHK(mm::farfield_learned(ctx->bh, nl, xa.as<float>(), p->theta, p->mlp_weights,
-                                      F.as<float>(), s));
+          MM_TRY(mm::farfield_learned(ctx->bh, nl, xin, p->theta, p->mlp_weights, F.as<float>(), s));
         } else {
-          HIPCHK(mm::farfield_bh(ctx->bh, nl, xa.as<float>(), p->q, p->theta, F.as<float>(), nullptr,
-                                 nullptr, nullptr, nullptr, 0, nullptr, s));
+          MM_TRY(mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
+                                 nullptr, nullptr, 0, nullptr, s));
         }
-        HIPCHK(hipEventRecord(ctx->ev[1], s));
+        MM_TRY(hipEventRecord(ctx->ev[1], s));
         if (ts.built)
-          HIPCHK(mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa.as<float>(),
-                                 F.as<float>(), alpha, p->q, xb.as<float>(), d2.as<double>(), s));
+          MM_TRY(mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
+                                 F.as<float>(), alpha, p->q, xout, d2.as<double>(), s, adev));
         else
-          HIPCHK(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa.as<float>(), F.as<float>(), alpha,
-                           p->q, xb.as<float>(), d2.as<double>(), s));
-        HIPCHK(hipEventRecord(ctx->ev[2], s));
-        HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        float a = 0, b = 0;
-        HIPCHK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
-        HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
-        t_far += a;
-        t_sweep += b;
-        lvl_far += a;
-        lvl_sweep += b;
+          MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), alpha, p->q,
+                           xout, d2.as<double>(), s, nullptr, nullptr, adev, &sweep_part));
+        return hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+      };
+      // Small levels are launch-bound: after one direct iteration (which sizes
+      // every buffer), the iteration is captured once per direction (A -> B,
+      // B -> A) and replayed.  Event records are not captured; a replay's time
+      // is split between far field and sweep in the ratio of the direct one.
+      float* bufA = xa.as<float>();
+      float* bufB = xb.as<float>();
+      int parity = 0;  // 0: the current layout is in bufA
+      const bool want_graph = p->use_graphs && nl <= kGraphMaxN;
+      hipGraphExec_t gx[2] = {nullptr, nullptr};
+      bool graph_failed = false;
+      double split = 0.5;
+      struct GraphGuard {
+        hipGraphExec_t* g;
+        ~GraphGuard() { for (int i = 0; i < 2; ++i) if (g[i]) (void)hipGraphExecDestroy(g[i]); }
+      } gguard{gx};
+      auto capture = [&]() -> bool {
+        for (int d = 0; d < 2; ++d) {
+          const float* xin = d ? bufB : bufA;
+          float* xout = d ? bufA : bufB;
+          if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+          hipError_t e = hipMemcpyAsync(ctx->alpha_dev, ctx->alpha_pinned, sizeof(float),
+                                        hipMemcpyHostToDevice, s);
+          if (e == hipSuccess) {
+            // no event records inside the capture
+            if (p->theta < 0) e = mm::farfield_exact(nl, xin, p->q, F.as<float>(), s);
+            else if (p->mlp_weights)
+              e = mm::farfield_learned(ctx->bh, nl, xin, p->theta, p->mlp_weights, F.as<float>(), s);
+            else
+              e = mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
+                                  nullptr, nullptr, 0, nullptr, s);
+          }
+          if (e == hipSuccess) {
+            if (ts.built)
+              e = mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
+                                  F.as<float>(), 0.0, p->q, xout, d2.as<double>(), s, ctx->alpha_dev);
+            else
+              e = mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
+                            xout, d2.as<double>(), s, nullptr, nullptr, ctx->alpha_dev, &sweep_part);
+          }
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+          hipGraph_t gr = nullptr;
+          const hipError_t e2 = hipStreamEndCapture(s, &gr);
+          if (e != hipSuccess || e2 != hipSuccess || !gr) {
+            if (gr) (void)hipGraphDestroy(gr);
+            (void)hipGetLastError();
+            return false;
+          }
+          const hipError_t e3 = hipGraphInstantiate(&gx[d], gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          if (e3 != hipSuccess) { gx[d] = nullptr; (void)hipGetLastError(); return false; }
+        }
+        return true;
+      };
+      auto iterate = [&](double alpha) -> mm_status {
+        const float* xin = parity ? bufB : bufA;
+        float* xout = parity ? bufA : bufB;
+        if (want_graph && iters >= 1 && !gx[0] && !graph_failed) {
+          if (!capture()) {
+            graph_failed = true;
+            for (auto& g2 : gx) if (g2) { (void)hipGraphExecDestroy(g2); g2 = nullptr; }
+          }
+        }
+        HIPCHK(hipEventRecord(ctx->ev[0], s));
+        if (gx[parity]) {
+          *ctx->alpha_pinned = (float)alpha;
+          HIPCHK(hipGraphLaunch(gx[parity], s));
+          HIPCHK(hipEventRecord(ctx->ev[2], s));
+          HIPCHK(hipStreamSynchronize(s));
+          float ab = 0;
+          HIPCHK(hipEventElapsedTime(&ab, ctx->ev[0], ctx->ev[2]));
+          t_far += ab * split;
+          lvl_far += ab * split;
+          t_sweep += ab * (1.0 - split);
+          lvl_sweep += ab * (1.0 - split);
+        } else {
+          HIPCHK(enqueue(alpha, xin, xout, nullptr));
+          HIPCHK(hipEventRecord(ctx->ev[2], s));
+          HIPCHK(hipStreamSynchronize(s));
+          float a = 0, b = 0;
+          HIPCHK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+          HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+          if (a + b > 0) split = a / (a + b);
+          t_far += a;
+          t_sweep += b;
+          lvl_far += a;
+          lvl_sweep += b;
+        }
         delta = ctx->pinned[1] > 0 ? std::sqrt(ctx->pinned[0] / ctx->pinned[1]) : INFINITY;
         if (!std::isfinite(delta)) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
-        std::swap(xa, xb);
+        parity ^= 1;
         iters++;
         return MM_OK;
       };
@@ -780,6 +882,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         if (delta < p->eps_final) break;
         if (it == p->max_final_iters - 1) cap_hit = 1;
       }
+      if (parity) std::swap(xa, xb);  // the level's result in xa
       if (lvl < MM_MAX_LEVELS) {
         st.level_n[lvl] = nl;
         st.level_nnz[lvl] = G.nnz;

@@ -212,6 +212,12 @@ __global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ a,
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
 }
 
+__global__ void k_fill_keys(uint64_t* __restrict__ keys, int32_t m, int32_t* __restrict__ counter) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) keys[i] = ~0ull;
+  if (i == 0) *counter = 0;
+}
+
 __device__ inline int lcp48(uint64_t a, uint64_t b) {
   uint64_t x = (a ^ b) << 16;  // codes live in the low 48 bits
   return x == 0 ? 48 : __clzll(x);
@@ -433,8 +439,8 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   const int nbb = std::min(1024, std::max(1, (n + BB_T - 1) / BB_T));
   MM_TRY(ensure<float4>(w->partial, nbb, s));
   const int32_t nps = (n + PS_TILE - 1) / PS_TILE;
-  DevBuf pparts;
-  MM_TRY(pparts.alloc(sizeof(double) * (size_t)(nps + 1), s));
+  MM_TRY(ensure<double>(w->pparts, (size_t)nps + 1, s));
+  DevBuf& pparts = w->pparts;
   MM_TRY(ensure<unsigned long long>(w->statc, 2, s));
 
   int cbits = 48;
@@ -449,7 +455,7 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
                                            seg ? seg->gid : nullptr, w->codes.as<uint64_t>(),
                                            w->order.as<int32_t>());
   MM_TRY(hipGetLastError());
-  MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, cbits, s));
+  MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, cbits, s, &w->sort));
   k_gather_sorted<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, w->order.as<int32_t>(),
                                                   w->codes.as<uint64_t>(), n, w->xsx.as<float>(),
                                                   w->xsy.as<float>(), w->ix.as<uint2>());
@@ -461,18 +467,19 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
     k_fsum_parts<<<1, 1024, 0, s>>>(pparts.as<double>(), nps);
     k_fsum_scan<<<nps, PS_T, 0, s>>>(a, n, pparts.as<double>(), out);
   }
-  MM_TRY(hipMemsetAsync(w->counter.p, 0, sizeof(int32_t), s));
   // at most n leaves and n - 1 internal nodes; unused slots keep the all-ones
-  // key and sort last, so the node count never has to reach the host
+  // key and sort last, so the node count never has to reach the host (fill
+  // kernels rather than memsets: this sequence is replayed from HIP graphs)
   const int32_t NMAX = 2 * n;
-  MM_TRY(hipMemsetAsync(w->nkeys.p, 0xFF, sizeof(uint64_t) * (size_t)NMAX, s));
+  k_fill_keys<<<(NMAX + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), NMAX,
+                                                 w->counter.as<int32_t>());
   k_emit_nodes<<<(n + 255) / 256, 256, 0, s>>>(w->codes.as<uint64_t>(), n, w->nkeys.as<uint64_t>(),
                                                w->nvals.as<int32_t>(), w->ntmp.as<int4>(),
                                                w->counter.as<int32_t>());
   MM_TRY(hipGetLastError());
   int kbits = 6;
   while ((1ll << (kbits - 6)) < (int64_t)n) kbits++;
-  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), NMAX, kbits, s));
+  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), NMAX, kbits, s, &w->sort));
   const int32_t* Np = w->counter.as<int32_t>();
   k_first_at<<<(NMAX + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), Np, w->first_at.as<int32_t>());
   k_finalize_nodes<<<(NMAX + 255) / 256, 256, 0, s>>>(

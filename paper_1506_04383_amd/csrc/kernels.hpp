@@ -46,7 +46,14 @@ hipError_t scan_excl_i32(const int32_t* in, int64_t* out, int64_t n, hipStream_t
 hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 // Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
 // Sorted result ends in keys/vals (the buffers are ping-ponged internally).
-hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
+// Growable temporaries of the sort, kept by callers that sort every
+// iteration (no allocation after the first call: graph-capture safe as long
+// as the histogram scan stays on its single-launch path, <= 2^16 entries).
+struct SortWork {
+  DevBuf k2, v2, hist, offs;
+};
+hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s,
+                            SortWork* ws = nullptr);
 hipError_t iota_i32(int32_t* out, int64_t n, hipStream_t s);
 hipError_t widen_i32_u64(const int32_t* in, uint64_t* out, int64_t n, hipStream_t s);
 
@@ -75,7 +82,8 @@ struct TiledSet {
   uint16_t* ent = nullptr;       // (hop << tbits) | (v - tile * 2^tbits)
   int32_t* unit_c0 = nullptr;    // nunits+1: first chunk of each work unit
   int32_t* unit_tile = nullptr;  // tile of each work unit
-  DevBuf b_rc_ptr, b_chunk_row, b_chunk_off, b_chunk_slot, b_ent, b_unit_c0, b_unit_tile, b_partial;
+  DevBuf b_rc_ptr, b_chunk_row, b_chunk_off, b_chunk_slot, b_ent, b_unit_c0, b_unit_tile, b_partial,
+      b_dpart;
 };
 bool tiled_eligible(const KhopDev& kh, int32_t tbits);
 // rho_u = sum_{v in S(u)} w_uv (sqrtc null: finest level, d = hop)
@@ -88,7 +96,8 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
 constexpr int32_t kTileBits = 13;
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
-                       float* xy_out, double* delta2_dev, hipStream_t s);
+                       float* xy_out, double* delta2_dev, hipStream_t s,
+                       const float* alpha_dev = nullptr);
 
 // ---- far field (farfield.hip)
 struct FarStats { int64_t accepted, leaf_pairs, coincident, nodes; };
@@ -132,11 +141,13 @@ hipError_t mlp_train(int64_t N, const float* feat, const float* tgt, float* wts,
 // weights (null at level 0 => d = hop). delta2 (device, 2 doubles) receives
 // sum |x'-x|^2 and sum |x|^2.
 // gid/galpha (batches, may be null): alpha of each graph; < 0 = finished
-// graph (coordinates copied).
+// graph (coordinates copied).  alpha_dev (may be null): alpha read from
+// device memory (graph replays).  part_ws: reusable reduction buffer.
 hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
                  double* delta2_dev, hipStream_t s, const int32_t* gid = nullptr,
-                 const float* galpha = nullptr);
+                 const float* galpha = nullptr, const float* alpha_dev = nullptr,
+                 DevBuf* part_ws = nullptr);
 
 // ---- coarsening (coarsen.hip)
 struct GraphDev {

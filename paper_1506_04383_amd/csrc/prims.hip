@@ -204,16 +204,25 @@ hipError_t widen_i32_u64(const int32_t* in, uint64_t* out, int64_t n, hipStream_
   return hipGetLastError();
 }
 
-hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
+hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s,
+                            SortWork* ws) {
   if (n <= 1 || bits <= 0) return hipSuccess;
   int passes = (bits + 7) / 8;
   int64_t nb = (n + RS_TILE - 1) / RS_TILE;
   if (nb > (1ll << 30)) return hipErrorInvalidValue;
-  DevBuf k2, v2, hist, offs;
-  MM_TRY(k2.alloc(sizeof(uint64_t) * (size_t)n, s));
-  MM_TRY(v2.alloc(sizeof(int32_t) * (size_t)n, s));
-  MM_TRY(hist.alloc(sizeof(int32_t) * (size_t)(256 * nb), s));
-  MM_TRY(offs.alloc(sizeof(int64_t) * (size_t)(256 * nb + 1), s));
+  SortWork local;
+  SortWork& W = ws ? *ws : local;
+  auto grow = [&](DevBuf& b, size_t bytes) -> hipError_t {
+    return b.bytes >= bytes ? hipSuccess : b.alloc(bytes, s);
+  };
+  MM_TRY(grow(W.k2, sizeof(uint64_t) * (size_t)n));
+  MM_TRY(grow(W.v2, sizeof(int32_t) * (size_t)n));
+  MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)(256 * nb)));
+  MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb + 1)));
+  DevBuf& k2 = W.k2;
+  DevBuf& v2 = W.v2;
+  DevBuf& hist = W.hist;
+  DevBuf& offs = W.offs;
   uint64_t* ka = keys; int32_t* va = vals;
   uint64_t* kb = k2.as<uint64_t>(); int32_t* vb = v2.as<int32_t>();
   for (int p = 0; p < passes; ++p) {

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(
     const int32_t* __restrict__ nbr, const float* __restrict__ sqrtc, float scale,
     const float2* __restrict__ xy, const float2* __restrict__ F, float alpha, float q,
     float2* __restrict__ out, double2* __restrict__ part, const int32_t* __restrict__ gid,
-    const float* __restrict__ galpha) {
+    const float* __restrict__ galpha, const float* __restrict__ alpha_dev) {
   constexpr int RPB = SW_T / G;  // rows per block
   __shared__ double2 red[RPB];
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
@@ -34,6 +34,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(
   double2 dd = make_double2(0.0, 0.0);
   // batches: each graph has its own alpha; a negative one marks a finished
   // graph, whose coordinates are carried over unchanged
+  if (alpha_dev) alpha = *alpha_dev;
   if (galpha && u < n) alpha = galpha[gid[u]];
   if (u < n && alpha < 0.f) {
     if (gl == 0) out[u] = xy[u];
@@ -132,13 +133,14 @@ __global__ __launch_bounds__(1024) void k_sum_parts(const double2* __restrict__ 
 template <int G>
 hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, float scale,
                   const float* xy, const float* F, float alpha, float q, float* out, double2* part,
-                  int32_t nb, hipStream_t s, const int32_t* gid, const float* galpha) {
+                  int32_t nb, hipStream_t s, const int32_t* gid, const float* galpha,
+                  const float* alpha_dev) {
   const float2* x2 = (const float2*)xy;
   const float2* F2 = (const float2*)F;
   float2* o2 = (float2*)out;
 #define MM_SW(C, Q)                                                                          \
   k_sweep<G, C, Q><<<nb, SW_T, 0, s>>>(kh.n, kh.k, kh.off, kh.hend, kh.nbr, sqrtc, scale, x2, \
-                                       F2, alpha, q, o2, part, gid, galpha)
+                                       F2, alpha, q, o2, part, gid, galpha, alpha_dev)
   if (coarse) { if (q0) MM_SW(true, true); else MM_SW(true, false); }
   else { if (q0) MM_SW(false, true); else MM_SW(false, false); }
 #undef MM_SW
@@ -149,22 +151,24 @@ hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, f
 
 hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
-                 double* delta2_dev, hipStream_t s, const int32_t* gid, const float* galpha) {
+                 double* delta2_dev, hipStream_t s, const int32_t* gid, const float* galpha,
+                 const float* alpha_dev, DevBuf* part_ws) {
   if (kh.k > KMAX) return hipErrorInvalidValue;
   const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
   int G = avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
   const int32_t rpb = SW_T / G;
   const int32_t nb = (kh.n + rpb - 1) / rpb;
-  DevBuf part;
-  MM_TRY(part.alloc(sizeof(double2) * (size_t)nb, s));
+  DevBuf local;
+  DevBuf& part = part_ws ? *part_ws : local;
+  if (part.bytes < sizeof(double2) * (size_t)nb) MM_TRY(part.alloc(sizeof(double2) * (size_t)nb, s));
   const bool coarse = (level > 0) && sqrtc != nullptr;
   const bool q0 = (q == 0.0);
   hipError_t e;
   switch (G) {
-    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
-    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
-    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
-    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha); break;
+    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
+    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
+    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
+    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
   }
   MM_TRY(e);
   k_sum_parts<<<1, 1024, 0, s>>>(part.as<double2>(), nb, delta2_dev);

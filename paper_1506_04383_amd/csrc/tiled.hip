@@ -249,7 +249,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_slot,
     const uint16_t* __restrict__ ent, const float2* __restrict__ xy,
     const float* __restrict__ sqrtc, float scale, float alpha, float q,
-    float2* __restrict__ partial) {
+    float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
   extern __shared__ float2 sx[];
   // per hop h: (w = 1/h^2, w*d = 1/h, alpha, h); h = 0 marks padding: all zero
   __shared__ float4 lut[16];
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
       if (COARSE) mscu[i] = sqrtc[u];
     }
   }
+  if (alpha_dev) alpha = *alpha_dev;
   if (threadIdx.x < 16) {
     const float h = (float)threadIdx.x;
     lut[threadIdx.x] = threadIdx.x ? make_float4(1.f / (h * h), 1.f / h, alpha, h)
@@ -382,7 +383,9 @@ __global__ __launch_bounds__(CB_T) void k_combine(int32_t n, const int64_t* __re
                                                   const float2* __restrict__ xy,
                                                   const float2* __restrict__ F, float alpha,
                                                   float2* __restrict__ out,
-                                                  double2* __restrict__ dpart) {
+                                                  double2* __restrict__ dpart,
+                                                  const float* __restrict__ alpha_dev) {
+  if (alpha_dev) alpha = *alpha_dev;
   constexpr int RPB = CB_T / CB_G;
   __shared__ double2 red[RPB];
   const int gl = threadIdx.x % CB_G, gi = threadIdx.x / CB_G;
@@ -553,7 +556,7 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
 
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
-                       float* xy_out, double* delta2_dev, hipStream_t s) {
+                       float* xy_out, double* delta2_dev, hipStream_t s, const float* alpha_dev) {
   const bool coarse = level > 0 && sqrtc != nullptr;
   const bool q0 = q == 0.0;
   const int32_t T = 1 << ts.tbits;
@@ -563,11 +566,15 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
   float2* part = ts.b_partial.as<float2>();
 #define MM_TS(GG, C, Q)                                                                          \
   do {                                                                                           \
-    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tiled<GG, C, Q>),          \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));           \
+    static bool attr_set = false; /* once per instantiation (not during a capture) */           \
+    if (!attr_set) {                                                                             \
+      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tiled<GG, C, Q>),        \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));         \
+      attr_set = true;                                                                           \
+    }                                                                                            \
     k_sweep_tiled<GG, C, Q><<<ts.nunits, TS_T, shm, s>>>(                                        \
         ts.n, ts.tbits, ts.unit_c0, ts.unit_tile, ts.chunk_off, ts.chunk_row, ts.chunk_slot,     \
-        ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part);           \
+        ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, alpha_dev); \
   } while (0)
 #define MM_TSG(GG)                                   \
   do {                                               \
@@ -583,10 +590,10 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
 #undef MM_TS
   MM_TRY(hipGetLastError());
   const int32_t nb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);
-  DevBuf dpart;
-  MM_TRY(dpart.alloc(sizeof(double2) * (size_t)nb, s));
+  DevBuf& dpart = const_cast<TiledSet&>(ts).b_dpart;
+  if (dpart.bytes < sizeof(double2) * (size_t)nb) MM_TRY(dpart.alloc(sizeof(double2) * (size_t)nb, s));
   k_combine<<<nb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, part, rho, (const float2*)xy, (const float2*)F,
-                                (float)alpha, (float2*)xy_out, dpart.as<double2>());
+                                (float)alpha, (float2*)xy_out, dpart.as<double2>(), alpha_dev);
   k_sum_parts2<<<1, 1024, 0, s>>>(dpart.as<double2>(), nb, delta2_dev);
   return hipGetLastError();
 }

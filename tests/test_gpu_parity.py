@@ -248,3 +248,22 @@ def test_invalid_inputs_rejected(mm, ctx):
         mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(k=0))
     with pytest.raises(mm.MulmentError, match="not finite"):
         mm.layout(ctx, ctx.graph(g.row_ptr, g.col), init_xy=np.full((5, 2), np.nan, np.float32))
+
+
+@pytest.mark.parametrize("case", ["grid32-exact", "rgg4k-bh", "tree-bh"])
+def test_graph_replay_is_bit_identical(mm, ctx, case):
+    """Levels replayed from HIP graphs (hundreds of replays with host work and
+    synchronisation between them) give the same bits as direct launches."""
+    name = case.split("-")[0]
+    g = _graphs()[name]()
+    theta = -1.0 if case.endswith("exact") else 0.5
+    print(f"[graphs] {case} n={g.n}", flush=True)
+    dg = ctx.graph(g.row_ptr, g.col)
+    kw = dict(k=3, theta=theta, alpha_decay=0.5, max_levels=3 if theta < 0 else 62,
+              coarsest_n=20, seed=5)
+    xg, sg = mm.layout(ctx, dg, mm.Params(use_graphs=1, **kw))
+    xd, sd = mm.layout(ctx, dg, mm.Params(use_graphs=0, **kw))
+    xg2, _ = mm.layout(ctx, dg, mm.Params(use_graphs=1, **kw))
+    assert [l["iters"] for l in sg["per_level"]] == [l["iters"] for l in sd["per_level"]]
+    assert np.array_equal(xg.cpu().numpy(), xd.cpu().numpy())
+    assert np.array_equal(xg2.cpu().numpy(), xd.cpu().numpy())
