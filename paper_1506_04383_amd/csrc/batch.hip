@@ -37,8 +37,12 @@ __global__ void k_seg_max(const int32_t* __restrict__ goff, const int32_t* __res
 __global__ __launch_bounds__(256) void k_seg_delta(const int32_t* __restrict__ goff,
                                                    const float2* __restrict__ x,
                                                    const float2* __restrict__ xn,
-                                                   double2* __restrict__ out) {
+                                                   double2* __restrict__ out,
+                                                   int32_t* __restrict__ zero2) {
   const int32_t g = blockIdx.x;
+  // counters of the following schedule step start at zero (a kernel rather
+  // than a memset: this sequence is replayed from HIP graphs)
+  if (zero2 && g == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0;
   double a = 0.0, b = 0.0;
   for (int32_t v = goff[g] + threadIdx.x; v < goff[g + 1]; v += 256) {
     const float2 p = x[v], q = xn[v];
@@ -191,8 +195,8 @@ hipError_t batch_max_c(int32_t M, const int32_t* goff, const int32_t* c, int32_t
 }
 
 hipError_t batch_delta(int32_t M, const int32_t* goff, const float* x, const float* xn,
-                       double* out, hipStream_t s) {
-  k_seg_delta<<<M, 256, 0, s>>>(goff, (const float2*)x, (const float2*)xn, (double2*)out);
+                       double* out, hipStream_t s, int32_t* zero2) {
+  k_seg_delta<<<M, 256, 0, s>>>(goff, (const float2*)x, (const float2*)xn, (double2*)out, zero2);
   return hipGetLastError();
 }
 

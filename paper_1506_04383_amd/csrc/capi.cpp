@@ -960,7 +960,9 @@ mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, 
       if (graph_off[i + 1] - graph_off[i] < 2) return fail(MM_EINVAL, "graph %d has fewer than 2 vertices", i);
     if (g->nnz < 1 || g->nnz >= (1ll << 31)) return fail(MM_EINVAL, "nnz out of range");
     DeviceGuard dg(ctx->device);
-    hipStream_t s = ctx->stream;
+    hipStream_t s = ctx->work;
+    HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
+    HIPCHK(hipStreamWaitEvent(s, ctx->ev[3], 0));
     const int32_t n = g->n;
     const int64_t nnz = g->nnz;
     auto t_start = std::chrono::steady_clock::now();
@@ -1217,23 +1219,63 @@ mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, 
       bseg.gid = L.d_gid.as<int32_t>();
       bseg.goff = L.d_goff.as<int32_t>();
       int32_t iters = 0;
+      mm::DevBuf sweep_part;
+      float* bufA = xa.as<float>();
+      float* bufB = xb.as<float>();
+      int parity = 0;
+      int32_t* hc = reinterpret_cast<int32_t*>(ctx->pinned + 2);
+      // one iteration of every graph still running: far field, sweep with the
+      // graph's alpha, per-graph relative change, schedule step, counters
+      auto enqueue = [&](const float* xin, float* xout) -> hipError_t {
+        MM_TRY(mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
+                               nullptr, nullptr, 0, nullptr, s, &bseg));
+        MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q, xout,
+                         d2.as<double>(), s, L.d_gid.as<int32_t>(), galpha.as<float>(), nullptr,
+                         &sweep_part));
+        MM_TRY(mm::batch_delta(M, L.d_goff.as<int32_t>(), xin, xout, gd.as<double>(), s,
+                               cnt.as<int32_t>()));
+        MM_TRY(mm::batch_schedule(M, gd.as<double>(), prm, gst.as<mm::BatchState>(),
+                                  galpha.as<float>(), cnt.as<int32_t>(), s));
+        return hipMemcpyAsync(hc, cnt.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      };
+      // small union levels replay the iteration from HIP graphs (one per
+      // direction), captured after a direct iteration has sized the buffers
+      hipGraphExec_t gx[2] = {nullptr, nullptr};
+      struct GraphGuard {
+        hipGraphExec_t* g;
+        ~GraphGuard() { for (int i = 0; i < 2; ++i) if (g[i]) (void)hipGraphExecDestroy(g[i]); }
+      } gguard{gx};
+      bool gfail = !(p->use_graphs && nl <= kGraphMaxN);
       for (;;) {
-        HIPCHK(mm::farfield_bh(ctx->bh, nl, xa.as<float>(), p->q, p->theta, F.as<float>(), nullptr,
-                               nullptr, nullptr, nullptr, 0, nullptr, s, &bseg));
-        HIPCHK(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa.as<float>(), F.as<float>(), 0.0, p->q,
-                         xb.as<float>(), d2.as<double>(), s, L.d_gid.as<int32_t>(), galpha.as<float>()));
-        HIPCHK(mm::batch_delta(M, L.d_goff.as<int32_t>(), xa.as<float>(), xb.as<float>(), gd.as<double>(), s));
-        HIPCHK(hipMemsetAsync(cnt.p, 0, 2 * sizeof(int32_t), s));
-        HIPCHK(mm::batch_schedule(M, gd.as<double>(), prm, gst.as<mm::BatchState>(), galpha.as<float>(),
-                                  cnt.as<int32_t>(), s));
-        int32_t hc[2];
-        HIPCHK(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+        const float* xin = parity ? bufB : bufA;
+        float* xout = parity ? bufA : bufB;
+        if (iters >= 1 && !gx[0] && !gfail) {
+          for (int d = 0; d < 2 && !gfail; ++d) {
+            hipGraph_t gr = nullptr;
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) { gfail = true; break; }
+            const hipError_t e = enqueue(d ? bufB : bufA, d ? bufA : bufB);
+            const hipError_t e2 = hipStreamEndCapture(s, &gr);
+            if (e != hipSuccess || e2 != hipSuccess || !gr ||
+                hipGraphInstantiate(&gx[d], gr, nullptr, nullptr, 0) != hipSuccess) {
+              gfail = true;
+              gx[d] = nullptr;
+            }
+            if (gr) (void)hipGraphDestroy(gr);
+          }
+          if (gfail) {
+            (void)hipGetLastError();
+            for (auto& g2 : gx) if (g2) { (void)hipGraphExecDestroy(g2); g2 = nullptr; }
+          }
+        }
+        if (gx[parity]) HIPCHK(hipGraphLaunch(gx[parity], s));
+        else HIPCHK(enqueue(xin, xout));
         HIPCHK(hipStreamSynchronize(s));
-        std::swap(xa, xb);
+        parity ^= 1;
         iters++;
         if (hc[1] > 0) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
         if (hc[0] == 0) break;
       }
+      if (parity) std::swap(xa, xb);
       if (lvl < MM_MAX_LEVELS) {
         st.level_n[lvl] = nl;
         st.level_nnz[lvl] = L.g.nnz;

@@ -210,7 +210,7 @@ hipError_t batch_max_c(int32_t M, const int32_t* goff, const int32_t* c, int32_t
                        hipStream_t s);
 // out: 2 doubles per graph (sum |x'-x|^2, sum |x|^2)
 hipError_t batch_delta(int32_t M, const int32_t* goff, const float* x, const float* xn,
-                       double* out, hipStream_t s);
+                       double* out, hipStream_t s, int32_t* zero2 = nullptr);
 hipError_t batch_sched_init(int32_t M, const BatchSched& prm, double alpha_start, BatchState* st,
                             float* galpha, hipStream_t s);
 // counters[0] += graphs still iterating, counters[1] += graphs with a non-finite layout

@@ -78,15 +78,15 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
     int32_t* __restrict__ cm_tile, int32_t* __restrict__ cm_size, int32_t* __restrict__ cm_row,
     const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
     uint16_t* __restrict__ ent) {
-  __shared__ uint32_t tbm[TB_WAVES][TB_MAXW];
-  __shared__ int32_t pre[TB_WAVES][TB_MAXW];
-  __shared__ int32_t cnt[TB_WAVES][TB_MAXTILES];
+  // per wave, sized by the tile count: tile bitmap (ntw words), its popcount
+  // prefix (ntw), per-tile counters (ntiles)
+  extern __shared__ uint32_t tb_dyn[];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t u = blockIdx.x * TB_WAVES + w;
   if (u >= n) return;
-  uint32_t* bm = tbm[w];
-  int32_t* pf = pre[w];
-  int32_t* ct = cnt[w];
+  uint32_t* bm = tb_dyn + (size_t)w * (2 * ntw + ntiles);
+  int32_t* pf = reinterpret_cast<int32_t*>(bm + ntw);
+  int32_t* ct = pf + ntw;
   const int64_t beg = off[u];
   for (int i = l; i < ntw; i += 64) bm[i] = 0u;
   wave_sync();
@@ -480,7 +480,14 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(cm_tile.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(cm_size.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(cm_row.alloc(sizeof(int32_t) * (size_t)m, s));
-  k_row_chunks<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+  const size_t tb_shm = sizeof(uint32_t) * (size_t)TB_WAVES * (2 * (size_t)ntw + (size_t)ntiles);
+  if (tb_shm > 65536) {
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
+  }
+  k_row_chunks<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
       n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, cm_tile.as<int32_t>(),
       cm_size.as<int32_t>(), cm_row.as<int32_t>(), nullptr, nullptr, nullptr);
   MM_TRY(hipGetLastError());
@@ -520,7 +527,7 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(hipMemsetAsync(ts->ent, 0, sizeof(uint16_t) * (size_t)padded, s));
   ts->total = kh.total;
   ts->padded = padded;
-  k_row_chunks<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+  k_row_chunks<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
       n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr, nullptr,
       pos_of_slot, ts->chunk_off, ts->ent);
   MM_TRY(hipGetLastError());
