@@ -742,11 +742,14 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       // tile-major sets with LDS-staged coordinates when rows are long enough
       mm::TiledSet ts;
       mm::DevBuf rho;
-      if (mm::tiled_eligible(kh, mm::kTileBits)) {
+      // tile size: coarse levels stage sqrt c beside the coordinates (12 B per
+      // vertex), so smaller tiles keep two or more work-groups per CU
+      const int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 18) ? 12 : 11);
+      if (mm::tiled_eligible(kh, tbits_lvl)) {
         auto tt = std::chrono::steady_clock::now();
         HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
         HIPCHK(mm::compute_rho(kh, sqrtc, p->coarse_dist_scale, rho.as<float>(), s));
-        HIPCHK(mm::tiled_build(kh, mm::kTileBits, 8.0, &ts, s));
+        HIPCHK(mm::tiled_build(kh, tbits_lvl, 8.0, &ts, s));
         if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
         HIPCHK(hipStreamSynchronize(s));
         t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
