@@ -67,14 +67,19 @@ __global__ __launch_bounds__(BB_T) void k_bbox_partial(const float2* __restrict_
 
 __device__ void make_box(float4 r, BoxInfo* box);
 
+// One wave reduces the block partials (min / max are exact in any order).
 __global__ void k_bbox_final(const float4* __restrict__ part, int nb, BoxInfo* box) {
-  if (threadIdx.x != 0) return;
   float4 r = part[0];
-  for (int i = 1; i < nb; ++i) {
-    r.x = fminf(r.x, part[i].x); r.y = fminf(r.y, part[i].y);
-    r.z = fmaxf(r.z, part[i].z); r.w = fmaxf(r.w, part[i].w);
+  for (int i = threadIdx.x; i < nb; i += 64) {
+    const float4 p = part[i];
+    r.x = fminf(r.x, p.x); r.y = fminf(r.y, p.y);
+    r.z = fmaxf(r.z, p.z); r.w = fmaxf(r.w, p.w);
   }
-  make_box(r, box);
+  for (int o = 32; o > 0; o >>= 1) {
+    r.x = fminf(r.x, __shfl_xor(r.x, o, 64)); r.y = fminf(r.y, __shfl_xor(r.y, o, 64));
+    r.z = fmaxf(r.z, __shfl_xor(r.z, o, 64)); r.w = fmaxf(r.w, __shfl_xor(r.w, o, 64));
+  }
+  if (threadIdx.x == 0) make_box(r, box);
 }
 
 // One box per graph of a batch (block per graph).
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
   const bool valid = i < n;
   const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
-  const double qx2 = 2.0 * (double)qt.x + 1.0, qy2 = 2.0 * (double)qt.y + 1.0;
+  const int32_t qx2i = 2 * (int32_t)qt.x + 1, qy2i = 2 * (int32_t)qt.y + 1;
   float fx = 0.f, fy = 0.f;
   // nodes of this lane's tree: [root, end) (a batch holds one tree per graph,
   // graph g owning sorted points [goff[g], goff[g+1]))
@@ -358,16 +363,18 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     } else {
       bool opened = false;
       if (act) {
+        // opening test in exact integers: offsets of u's quantum-cell centre
+        // from the cell centre (doubled); |d| < S on both axes <=> u in C;
+        // d4 < 2^52 and 4 S^2 are exact doubles, so theta^2 d4 > 4 S^2 rounds
+        // exactly as the same test written with 64-bit integers
         const int sh = 24 - depth;
-        const bool contains = ((qt.x >> sh) == (nd.ox >> sh)) && ((qt.y >> sh) == (nd.oy >> sh));
-        bool accept = false;
-        if (!contains) {
-          const double S = (double)(1u << sh);
-          const double dx = qx2 - (2.0 * (double)nd.ox + S);
-          const double dy = qy2 - (2.0 * (double)nd.oy + S);
-          const double d4 = dx * dx + dy * dy;
-          accept = theta2 * d4 > 4.0 * S * S;
-        }
+        const int32_t S = 1 << sh;
+        const int32_t dxi = qx2i - (int32_t)(2u * nd.ox + (uint32_t)S);
+        const int32_t dyi = qy2i - (int32_t)(2u * nd.oy + (uint32_t)S);
+        const bool contains = abs(dxi) < S && abs(dyi) < S;
+        const double dxd = (double)dxi, dyd = (double)dyi;
+        const double d4 = fma(dxd, dxd, dyd * dyd);
+        const bool accept = !contains && theta2 * d4 > (double)((int64_t)S * S * 4);
         if (accept) {
           rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, nd.mass, fx, fy);
           if (STATS) acc++;

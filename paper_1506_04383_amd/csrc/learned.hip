@@ -226,17 +226,16 @@ __device__ inline bool cell_features(const BHNode& nd, const Cell& c, float xt, 
   return true;
 }
 
-// Exact opening test of the plain traversal (quantised geometry in FP64).
-__device__ inline bool open_test(const BHNode& nd, uint2 qt, double qx2, double qy2,
-                                 double theta2, bool* contains_out) {
+// Opening test of the plain traversal in exact integers (qx2i = 2 i_u + 1):
+// accept iff u is outside C and theta^2 |d|^2 > 4 S^2 (exact doubles).
+__device__ inline bool open_test(const BHNode& nd, int32_t qx2i, int32_t qy2i, double theta2) {
   const int sh = 24 - (nd.meta & 0xff);
-  const bool contains = ((qt.x >> sh) == (nd.ox >> sh)) && ((qt.y >> sh) == (nd.oy >> sh));
-  *contains_out = contains;
-  if (contains) return false;
-  const double S = (double)(1u << sh);
-  const double dx = qx2 - (2.0 * (double)nd.ox + S);
-  const double dy = qy2 - (2.0 * (double)nd.oy + S);
-  return theta2 * (dx * dx + dy * dy) > 4.0 * S * S;
+  const int32_t S = 1 << sh;
+  const int32_t dxi = qx2i - (int32_t)(2u * nd.ox + (uint32_t)S);
+  const int32_t dyi = qy2i - (int32_t)(2u * nd.oy + (uint32_t)S);
+  if (abs(dxi) < S && abs(dyi) < S) return false;
+  const double dxd = (double)dxi, dyd = (double)dyi;
+  return theta2 * fma(dxd, dxd, dyd * dyd) > (double)((int64_t)S * S * 4);
 }
 
 // ---------------------------------------------------------------- traversal
@@ -358,7 +357,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
   const bool valid = i < n;
   const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
-  const double qx2 = 2.0 * (double)qt.x + 1.0, qy2 = 2.0 * (double)qt.y + 1.0;
+  const int32_t qx2i = 2 * (int32_t)qt.x + 1, qy2i = 2 * (int32_t)qt.y + 1;
   float fx = 0.f, fy = 0.f, cfx = 0.f, cfy = 0.f;
   int32_t next = valid ? 0 : 0x7fffffff;
   int qh = 0, qt_ = 0;  // ring head / tail (wave-uniform, monotonic)
@@ -379,8 +378,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
       bool opened = false, push = false;
       Feat ft;
       if (act) {
-        bool contains;
-        if (open_test(nd, qt, qx2, qy2, theta2, &contains)) {
+        if (open_test(nd, qx2i, qy2i, theta2)) {
           rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), 0.f, nd.mass, fx, fy);
           push = cell_features(nd, cell[p], xt, yt, ft);
           next = nd.skip;
@@ -439,7 +437,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_far_samples(
   const bool valid = i < n;
   const float xt = valid ? xsx[i] : 0.f, yt = valid ? xsy[i] : 0.f;
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
-  const double qx2 = 2.0 * (double)qt.x + 1.0, qy2 = 2.0 * (double)qt.y + 1.0;
+  const int32_t qx2i = 2 * (int32_t)qt.x + 1, qy2i = 2 * (int32_t)qt.y + 1;
   int32_t next = valid ? 0 : 0x7fffffff;
   int32_t k = 0;
   const int64_t base = (!COUNT && valid) ? off[i] : 0;
@@ -457,8 +455,7 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_far_samples(
     bool opened = false, take = false;
     Feat ft;
     if (act) {
-      bool contains;
-      if (open_test(nd, qt, qx2, qy2, theta2, &contains)) {
+      if (open_test(nd, qx2i, qy2i, theta2)) {
         take = cell_features(nd, cell[p], xt, yt, ft);
         next = nd.skip;
       } else {

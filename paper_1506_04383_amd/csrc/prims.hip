@@ -69,18 +69,29 @@ __global__ void k_set_last(int64_t* out, int64_t n, const int64_t* part, int64_t
   out[n] = part[m];
 }
 
-// Small inputs: one workgroup walks the array in 1024-element steps.
+// Small inputs: one workgroup walks the array in steps of 1024 threads x 8
+// consecutive elements.
 template <typename Tin>
 __global__ __launch_bounds__(1024) void k_scan_small(const Tin* __restrict__ in, int64_t n,
                                                      int64_t* __restrict__ out) {
+  constexpr int E = 8;
   __shared__ int64_t sh[1024 / 64 + 1];
   int64_t carry = 0;
-  for (int64_t b = 0; b < n; b += 1024) {
-    const int64_t j = b + threadIdx.x;
-    const int64_t v = j < n ? (int64_t)in[j] : 0;
+  for (int64_t b = 0; b < n; b += 1024 * E) {
+    const int64_t j0 = b + (int64_t)threadIdx.x * E;
+    int64_t v[E], t = 0;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      v[i] = j0 + i < n ? (int64_t)in[j0 + i] : 0;
+      t += v[i];
+    }
     int64_t tot;
-    const int64_t ex = block_excl_scan<int64_t>(v, sh, &tot);
-    if (j < n) out[j] = carry + ex;
+    int64_t ex = carry + block_excl_scan<int64_t>(t, sh, &tot);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      if (j0 + i < n) out[j0 + i] = ex;
+      ex += v[i];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) out[n] = carry;

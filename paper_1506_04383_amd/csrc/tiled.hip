@@ -334,7 +334,9 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
 #pragma unroll
       for (int q2 = 0; q2 < 8; ++q2) {
         const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
-        const float D2 = fmaf(dx, dx, dy * dy);
+        // q = 0: a 1e-30 bias keeps 1/D finite for a coincident pair, whose
+        // r-terms then vanish through dx = dy = 0 (no select needed)
+        const float D2 = Q0 ? fmaf(dx, dx, fmaf(dy, dy, 1e-30f)) : fmaf(dx, dx, dy * dy);
         float w = lw[q2].x, wd = lw[q2].y;
         if (COARSE) {
           const float d = lw[q2].w * (scu + sc[q2]) * scale;
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
           w = r * r;
         }
         float inv = __builtin_amdgcn_rsqf(D2);
-        inv = D2 > 0.f ? inv : 0.f;
+        if (!Q0) inv = D2 > 0.f ? inv : 0.f;
         float rq;
         if (Q0) rq = inv * inv;
         else rq = D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f;
