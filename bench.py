@@ -338,6 +338,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: the sweep configuration of every level is timed and chosen during "
+                         "the first layout (the warm-up) and reused by the timed ones")
     ap.add_argument("--mode", default="layout",
                     choices=["layout", "learned", "batch", "snapshots"],
                     help="layout: the layout benchmark; learned: learned far field vs plain "
@@ -392,7 +395,7 @@ def main():
     dg = ctx.graph(g.row_ptr, g.col)
     p = mm.Params(k=wl["k"], theta=wl["theta"], alpha_decay=wl["alpha_decay"],
                   coarsest_n=wl.get("coarsest_n", 2), max_levels=wl.get("max_levels", 62),
-                  seed=args.seed, validate=0)
+                  seed=args.seed, validate=0, autotune=args.autotune)
 
     for i in range(args.warmup):
         t = time.time()
@@ -447,7 +450,8 @@ def main():
                           "khop": st["t_khop_ms"], "coarsen": st["t_coarsen_ms"],
                           "other": st["t_other_ms"]},
         "per_level": [[l["n"], l["khop_entries"], l["iters"], round(l["sweep_ms"], 1),
-                       round(l["far_ms"], 1)] for l in st["per_level"]],
+                       round(l["far_ms"], 1), l["tile_bits"], l["group"]] for l in st["per_level"]],
+        "autotune": {"enabled": args.autotune, "tuning_ms_in_timed_step": st["t_tune_ms"]},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_tiled + k_combine (finest-level sweep step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),

@@ -75,6 +75,11 @@ typedef struct {
                               (Barnes-Hut only, q = 0); NULL = plain Barnes-Hut (default) */
   int32_t use_graphs;      /* 1: replay the iterations of levels with <= 2^18 vertices from
                               HIP graphs (default; same results, fewer launches); 0: direct */
+  int32_t autotune;        /* 1: pick each level's sweep kernel, tile size and lanes per row
+                              or chunk by timing the candidates on the level itself, once per
+                              level shape, and keep the choice in the context (later layouts
+                              reuse it, so their results are reproducible); 0: fixed rules
+                              (default) */
 } mm_params;
 
 #define MM_MAX_LEVELS 64
@@ -93,6 +98,9 @@ typedef struct {
   double t_total_ms, t_coarsen_ms, t_khop_ms, t_farfield_ms, t_sweep_ms, t_other_ms;
   int64_t vertex_updates;                /* sum over levels of n * iterations */
   int64_t finest_updates;                /* n_0 * iterations on the input graph */
+  int32_t level_tile_bits[MM_MAX_LEVELS];/* sweep of the level: tile size 2^bits (0 = row kernel) */
+  int32_t level_group[MM_MAX_LEVELS];    /* lanes per chunk (tiled) or per row (row kernel) */
+  double t_tune_ms;                      /* time spent timing candidates (autotune) */
 } mm_stats;
 
 mm_status mm_params_default(mm_params* p);
@@ -100,6 +108,8 @@ mm_status mm_params_default(mm_params* p);
 /* device: HIP device ordinal; stream: hipStream_t or NULL (default stream). */
 mm_status mm_context_create(mm_context** out, int32_t device, void* stream);
 void mm_context_destroy(mm_context* ctx);
+/* Forgets the sweep configurations the autotuner chose in this context. */
+mm_status mm_tune_clear(mm_context* ctx);
 /* Waits for the context's stream; reports asynchronous device errors. */
 mm_status mm_sync(mm_context* ctx);
 const char* mm_last_error(void);

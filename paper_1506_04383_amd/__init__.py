@@ -43,7 +43,7 @@ class MMParams(C.Structure):
                 ("max_levels", C.c_int32), ("coarsest_n", C.c_int32), ("b", C.c_double),
                 ("f", C.c_double), ("lp_rounds", C.c_int32), ("coarse_dist_scale", C.c_double),
                 ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p),
-                ("use_graphs", C.c_int32)]
+                ("use_graphs", C.c_int32), ("autotune", C.c_int32)]
 
 
 class MMStats(C.Structure):
@@ -59,7 +59,8 @@ class MMStats(C.Structure):
                 ("t_coarsen_ms", C.c_double), ("t_khop_ms", C.c_double),
                 ("t_farfield_ms", C.c_double), ("t_sweep_ms", C.c_double),
                 ("t_other_ms", C.c_double), ("vertex_updates", C.c_int64),
-                ("finest_updates", C.c_int64)]
+                ("finest_updates", C.c_int64), ("level_tile_bits", C.c_int32 * MAX_LEVELS),
+                ("level_group", C.c_int32 * MAX_LEVELS), ("t_tune_ms", C.c_double)]
 
     def to_dict(self) -> dict:
         L = self.levels
@@ -70,12 +71,14 @@ class MMStats(C.Structure):
                  "khop_entries": self.level_khop[i], "iters": self.level_iters[i],
                  "final_iters": self.level_final_iters[i], "cap_hit": self.level_cap_hit[i],
                  "delta": self.level_delta[i], "sweep_ms": self.level_sweep_ms[i],
-                 "far_ms": self.level_far_ms[i], "khop_ms": self.level_khop_ms[i]}
+                 "far_ms": self.level_far_ms[i], "khop_ms": self.level_khop_ms[i],
+                 "tile_bits": self.level_tile_bits[i], "group": self.level_group[i]}
                 for i in range(L)],
             "t_total_ms": self.t_total_ms, "t_coarsen_ms": self.t_coarsen_ms,
             "t_khop_ms": self.t_khop_ms, "t_farfield_ms": self.t_farfield_ms,
             "t_sweep_ms": self.t_sweep_ms, "t_other_ms": self.t_other_ms,
             "vertex_updates": self.vertex_updates, "finest_updates": self.finest_updates,
+            "t_tune_ms": self.t_tune_ms,
         }
 
 
@@ -85,7 +88,8 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_coarsen",
            "mm_coarse_graph", "mm_coarse_export", "mm_coarse_free", "mm_init_layout",
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
-           "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch"]
+           "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
+           "mm_tune_clear"]
 
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
 
@@ -124,6 +128,7 @@ def lib():
         "mm_full_stress": [vp, P(MMGraph), vp, vp],
         "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
         "mm_layout_batch": [vp, i32, vp, P(MMGraph), P(MMParams), vp, vp, vp, P(MMStats)],
+        "mm_tune_clear": [vp],
         "mm_far_samples": [vp, i32, vp, f64, i64, vp, vp, vp, vp, vp, P(i64)],
         "mm_mlp_forward": [vp, i64, vp, vp, vp],
         "mm_mlp_grad": [vp, i64, vp, vp, vp, vp, vp],
@@ -182,6 +187,7 @@ class Params:
     validate: int = 1
     mlp_weights: object = None  # float32 device tensor of MLP_PARAMS (learned far field)
     use_graphs: int = 1  # replay small levels' iterations from HIP graphs
+    autotune: int = 0  # time each level's sweep configurations once per level shape
 
     def to_c(self) -> MMParams:
         p = MMParams()

@@ -12,7 +12,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -33,6 +35,9 @@ struct mm_context {
   float* alpha_pinned = nullptr; // alpha of the next replayed iteration
   float* alpha_dev = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // autotuner: sweep configuration per level shape (coarse?, n, sum |S|, k)
+  struct TuneChoice { int32_t tbits, group; };  // tbits 0: row kernel
+  std::map<std::tuple<int, int32_t, int64_t, int32_t>, TuneChoice> tune;
 };
 struct mm_khop {
   mm::KhopDev kh;
@@ -148,11 +153,82 @@ hipError_t make_sqrtc(int32_t n, const int32_t* c, mm::DevBuf& buf, hipStream_t 
   return mm::sqrt_weights(n, c, buf.as<float>(), s);
 }
 
+// Times `reps` launches of a sweep variant after one untimed launch; returns ms per launch.
+template <typename F>
+hipError_t time_variant(mm_context* ctx, hipStream_t s, int reps, F&& launch, float* ms) {
+  MM_TRY(launch());
+  MM_TRY(hipEventRecord(ctx->ev[0], s));
+  for (int r = 0; r < reps; ++r) MM_TRY(launch());
+  MM_TRY(hipEventRecord(ctx->ev[1], s));
+  MM_TRY(hipEventSynchronize(ctx->ev[1]));
+  float t = 0;
+  MM_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+  *ms = t / reps;
+  return hipSuccess;
+}
+
+// Autotuner of one level's sweep: every eligible configuration -- the row
+// kernel with 8/16/32/64 lanes per row, the tiled kernel with tiles of 2^11,
+// 2^12, 2^13 vertices and 4/8/16 lanes per chunk -- is run on the level's own
+// sets and coordinates (far field zero, alpha 1, output to scratch) and the
+// fastest is kept.  Row-kernel candidates are skipped on levels whose sets are
+// too large for that kernel to win (over 2^30 entries).
+mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float* sqrtc,
+                     const mm_params* p, const float* xa, float* F, float* xb, double* d2,
+                     hipStream_t s, mm_context::TuneChoice* out) {
+  const int32_t nl = kh.n;
+  HIPCHK(hipMemsetAsync(F, 0, sizeof(float) * 2 * (size_t)nl, s));
+  float best = INFINITY;
+  mm_context::TuneChoice bc{0, mm::row_group(kh)};
+  const int reps = kh.total > (1ll << 28) ? 1 : 3;
+  if (kh.total <= (1ll << 30)) {
+    mm::DevBuf part;
+    for (int32_t G : {8, 16, 32, 64}) {
+      float ms = 0;
+      HIPCHK(time_variant(ctx, s, reps, [&]() {
+        return mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa, F, 1.0, p->q, xb, d2, s, nullptr,
+                         nullptr, nullptr, &part, G);
+      }, &ms));
+      if (ms < best) { best = ms; bc = {0, G}; }
+    }
+  }
+  mm::DevBuf rho;
+  bool have_rho = false;
+  for (int32_t tb : {11, 12, 13}) {
+    if (!mm::tiled_eligible(kh, tb)) continue;
+    if (!have_rho) {
+      HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
+      HIPCHK(mm::compute_rho(kh, sqrtc, p->coarse_dist_scale, rho.as<float>(), s));
+      have_rho = true;
+    }
+    mm::TiledSet ts;
+    HIPCHK(mm::tiled_build(kh, tb, 0.0, &ts, s));
+    if (!ts.built) continue;
+    for (int32_t G : {4, 8, 16}) {
+      float ms = 0;
+      HIPCHK(time_variant(ctx, s, reps, [&]() {
+        return mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa, F, 1.0,
+                               p->q, xb, d2, s, nullptr, G);
+      }, &ms));
+      if (ms < best) { best = ms; bc = {tb, G}; }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  *out = bc;
+  return MM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* mm_last_error(void) { return g_err.c_str(); }
+
+mm_status mm_tune_clear(mm_context* ctx) {
+  if (!ctx) return fail(MM_EINVAL, "NULL context");
+  ctx->tune.clear();
+  return MM_OK;
+}
 
 mm_status mm_params_default(mm_params* p) {
   if (!p) return fail(MM_EINVAL, "params is NULL");
@@ -177,6 +253,7 @@ mm_status mm_params_default(mm_params* p) {
   p->validate = 1;
   p->mlp_weights = nullptr;
   p->use_graphs = 1;
+  p->autotune = 0;
   return MM_OK;
 }
 
@@ -641,7 +718,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
 
     mm_stats st;
     std::memset(&st, 0, sizeof(st));
-    double t_coarsen = 0, t_khop = 0, t_far = 0, t_sweep = 0;
+    double t_coarsen = 0, t_khop = 0, t_far = 0, t_sweep = 0, t_tune = 0;
 
     // ---- hierarchy (Section 3.1)
     std::vector<mm::DevBuf> clusters;
@@ -744,12 +821,29 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       mm::DevBuf rho;
       // tile size: coarse levels stage sqrt c beside the coordinates (12 B per
       // vertex), so smaller tiles keep two or more work-groups per CU
-      const int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 18) ? 12 : 11);
-      if (mm::tiled_eligible(kh, tbits_lvl)) {
+      int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 18) ? 12 : 11);
+      int32_t group_lvl = 0;  // 0: the kernels' own rule
+      double min_avg = 8.0;
+      if (p->autotune) {
+        const auto key = std::make_tuple(lvl > 0 ? 1 : 0, nl, kh.total, p->k);
+        auto it = ctx->tune.find(key);
+        if (it == ctx->tune.end()) {
+          auto tt = std::chrono::steady_clock::now();
+          mm_context::TuneChoice c;
+          STCHK(tune_level(ctx, kh, lvl, sqrtc, p, xa.as<float>(), F.as<float>(), xb.as<float>(),
+                           d2.as<double>(), s, &c));
+          it = ctx->tune.emplace(key, c).first;
+          t_tune += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
+        }
+        tbits_lvl = it->second.tbits;
+        group_lvl = it->second.group;
+        min_avg = 0.0;
+      }
+      if (tbits_lvl > 0 && mm::tiled_eligible(kh, tbits_lvl)) {
         auto tt = std::chrono::steady_clock::now();
         HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
         HIPCHK(mm::compute_rho(kh, sqrtc, p->coarse_dist_scale, rho.as<float>(), s));
-        HIPCHK(mm::tiled_build(kh, tbits_lvl, 8.0, &ts, s));
+        HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s));
         if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
         HIPCHK(hipStreamSynchronize(s));
         t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
@@ -771,10 +865,12 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         MM_TRY(hipEventRecord(ctx->ev[1], s));
         if (ts.built)
           MM_TRY(mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
-                                 F.as<float>(), alpha, p->q, xout, d2.as<double>(), s, adev));
+                                 F.as<float>(), alpha, p->q, xout, d2.as<double>(), s, adev,
+                                 group_lvl));
         else
           MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), alpha, p->q,
-                           xout, d2.as<double>(), s, nullptr, nullptr, adev, &sweep_part));
+                           xout, d2.as<double>(), s, nullptr, nullptr, adev, &sweep_part,
+                           group_lvl));
         return hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
       };
       // Small levels are launch-bound: after one direct iteration (which sizes
@@ -811,10 +907,12 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
           if (e == hipSuccess) {
             if (ts.built)
               e = mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
-                                  F.as<float>(), 0.0, p->q, xout, d2.as<double>(), s, ctx->alpha_dev);
+                                  F.as<float>(), 0.0, p->q, xout, d2.as<double>(), s, ctx->alpha_dev,
+                                  group_lvl);
             else
               e = mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
-                            xout, d2.as<double>(), s, nullptr, nullptr, ctx->alpha_dev, &sweep_part);
+                            xout, d2.as<double>(), s, nullptr, nullptr, ctx->alpha_dev, &sweep_part,
+                            group_lvl);
           }
           if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -897,6 +995,9 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         st.level_sweep_ms[lvl] = lvl_sweep;
         st.level_far_ms[lvl] = lvl_far;
         st.level_khop_ms[lvl] = khop_ms;
+        st.level_tile_bits[lvl] = ts.built ? ts.tbits : 0;
+        st.level_group[lvl] = group_lvl > 0 ? group_lvl : (ts.built ? mm::tiled_group(ts)
+                                                                    : mm::row_group(kh));
       }
       st.vertex_updates += (int64_t)nl * iters;
       if (lvl == 0) st.finest_updates = (int64_t)nl * iters;
@@ -909,7 +1010,8 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
     st.t_khop_ms = t_khop;
     st.t_farfield_ms = t_far;
     st.t_sweep_ms = t_sweep;
-    st.t_other_ms = st.t_total_ms - t_coarsen - t_khop - t_far - t_sweep;
+    st.t_tune_ms = t_tune;
+    st.t_other_ms = st.t_total_ms - t_coarsen - t_khop - t_far - t_sweep - t_tune;
     if (stats) *stats = st;
     return MM_OK;
   } catch (...) {

@@ -97,7 +97,11 @@ constexpr int32_t kTileBits = 13;
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
                        float* xy_out, double* delta2_dev, hipStream_t s,
-                       const float* alpha_dev = nullptr);
+                       const float* alpha_dev = nullptr, int32_t group = 0);
+// lanes per chunk (4, 8, 16) the heuristic picks; group = 0 above means this
+inline int32_t tiled_group(const TiledSet& ts) {
+  return ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
+}
 
 // ---- far field (farfield.hip)
 struct FarStats { int64_t accepted, leaf_pairs, coincident, nodes; };
@@ -147,7 +151,12 @@ hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double sc
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
                  double* delta2_dev, hipStream_t s, const int32_t* gid = nullptr,
                  const float* galpha = nullptr, const float* alpha_dev = nullptr,
-                 DevBuf* part_ws = nullptr);
+                 DevBuf* part_ws = nullptr, int32_t group = 0);
+// lanes per row (8, 16, 32, 64) the heuristic picks for the row kernel
+inline int32_t row_group(const KhopDev& kh) {
+  const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
+  return avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
+}
 
 // ---- coarsening (coarsen.hip)
 struct GraphDev {

@@ -152,10 +152,10 @@ hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, f
 hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
                  double* delta2_dev, hipStream_t s, const int32_t* gid, const float* galpha,
-                 const float* alpha_dev, DevBuf* part_ws) {
+                 const float* alpha_dev, DevBuf* part_ws, int32_t group) {
   if (kh.k > KMAX) return hipErrorInvalidValue;
   const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
-  int G = avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
+  int G = group > 0 ? group : avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
   const int32_t rpb = SW_T / G;
   const int32_t nb = (kh.n + rpb - 1) / rpb;
   DevBuf local;

@@ -565,13 +565,14 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
 
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
-                       float* xy_out, double* delta2_dev, hipStream_t s, const float* alpha_dev) {
+                       float* xy_out, double* delta2_dev, hipStream_t s, const float* alpha_dev,
+                       int32_t group) {
   const bool coarse = level > 0 && sqrtc != nullptr;
   const bool q0 = q == 0.0;
   const int32_t T = 1 << ts.tbits;
   const size_t shm = (size_t)T * (sizeof(float2) + (coarse ? sizeof(float) : 0));
   // a group of G lanes (one 8-entry block each per step) per chunk
-  const int G = ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
+  const int G = group > 0 ? group : ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
   float2* part = ts.b_partial.as<float2>();
 #define MM_TS(GG, C, Q)                                                                          \
   do {                                                                                           \
