@@ -37,6 +37,11 @@ WORKLOADS = {
                    desc="32x32 grid, k=3, exact far field, 3 coarsening levels"),
     "rgg22": dict(graph="rgg22", k=3, theta=0.5, alpha_decay=0.5, coarsest_n=100,
                   desc="RGG 2^22 points, mean degree ~8, LCC, k=3, theta=0.5"),
+    # the paper's configuration (S = E, decay 0.3, coarsening to 2 vertices) on a
+    # Delaunay triangulation of the shape of its del20 instance (context only)
+    "del20": dict(graph="del20", k=1, theta=0.5, alpha_decay=0.3, coarsest_n=2,
+                  desc="Delaunay triangulation of 2^20 uniform points, k=1 (S=E), theta=0.5, "
+                       "decay 0.3, hierarchy to 2 vertices"),
 }
 
 

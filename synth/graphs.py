@@ -225,6 +225,7 @@ def config_graph(name: str, seed: int = 1) -> Graph:
     rgg16    : RGG, 2^16 points, mean degree ~6, LCC (dynamic snapshots)
     rgg22    : RGG, 2^22 points, mean degree ~8, LCC
     rgg14    : RGG, 2^14 points, mean degree ~8, LCC
+    del20    : Delaunay triangulation of 2^20 uniform points (del16: 2^16)
     """
     if name == "grid32":
         return grid(32, 32)
@@ -238,6 +239,8 @@ def config_graph(name: str, seed: int = 1) -> Graph:
         return rgg(1 << 22, seed, 8.0)
     if name == "rmat20":
         return rmat(20, 8 * (1 << 20), seed)
+    if name.startswith("del"):
+        return delaunay(1 << int(name[3:]), seed)
     if name.startswith("rmat"):
         s = int(name[4:])
         return rmat(s, 8 * (1 << s), seed)
