@@ -314,6 +314,195 @@ __global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* _
   }
 }
 
+// ---- small trees: the whole build in one work-group (n <= BHS_MAX)
+// Same tree as the multi-kernel build: (code, id) sorted by one bitonic sort
+// of code << 12 | id in LDS, the same leaves and owner pairs, node keys
+// (first << 5 | depth code) sorted by a second bitonic sort, then the same
+// pre-order records.  Only the FP64 prefix sums run in a different order.
+constexpr int BHS_T = 1024;
+constexpr int BHS_MAX = 4096;
+
+__device__ inline void bitonic_sort_lds(uint64_t* a, int m) {  // m: power of two
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < m; i += BHS_T) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint64_t x = a[i], y = a[l];
+          const bool asc = (i & k) == 0;
+          if ((x > y) == asc) { a[i] = y; a[l] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(BHS_T) void k_bh_small(
+    const float2* __restrict__ xy, int32_t n, BoxInfo* __restrict__ boxo,
+    uint64_t* __restrict__ codes, int32_t* __restrict__ order, float* __restrict__ xsx,
+    float* __restrict__ xsy, uint2* __restrict__ ixy, double* __restrict__ px,
+    double* __restrict__ py, BHNode* __restrict__ nodes, int32_t* __restrict__ Np,
+    int64_t* __restrict__ export_nodes) {
+  // static LDS (112 KB for BHS_MAX = 4096; gfx950 work-groups may hold 160 KB)
+  __shared__ uint64_t sk[BHS_MAX];      // code << 12 | id, then codes
+  __shared__ uint64_t nk[2 * BHS_MAX];  // node keys
+  __shared__ int32_t fat[BHS_MAX];      // first node of each first point
+  int m = 1;
+  while (m < n) m <<= 1;
+  __shared__ float4 red[BHS_T / 64];
+  __shared__ BoxInfo sbox;
+  __shared__ int32_t ncount;
+  __shared__ double dsh[BHS_T / 64 + 1];
+  const int tid = threadIdx.x;
+  // 1. box
+  float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+  for (int i = tid; i < n; i += BHS_T) {
+    const float2 p = xy[i];
+    xmin = fminf(xmin, p.x); xmax = fmaxf(xmax, p.x);
+    ymin = fminf(ymin, p.y); ymax = fmaxf(ymax, p.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    xmin = fminf(xmin, __shfl_xor(xmin, o, 64)); xmax = fmaxf(xmax, __shfl_xor(xmax, o, 64));
+    ymin = fminf(ymin, __shfl_xor(ymin, o, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, o, 64));
+  }
+  if (lane_id() == 0) red[tid >> 6] = make_float4(xmin, ymin, xmax, ymax);
+  if (tid == 0) ncount = 0;
+  __syncthreads();
+  if (tid == 0) {
+    float4 r = red[0];
+    for (int i = 1; i < BHS_T / 64; ++i) {
+      r.x = fminf(r.x, red[i].x); r.y = fminf(r.y, red[i].y);
+      r.z = fmaxf(r.z, red[i].z); r.w = fmaxf(r.w, red[i].w);
+    }
+    make_box(r, &sbox);
+    *boxo = sbox;
+  }
+  __syncthreads();
+  // 2. codes, 3. sort (code, id)
+  const BoxInfo b = sbox;
+  for (int i = tid; i < m; i += BHS_T) {
+    if (i < n) {
+      const float2 p = xy[i];
+      double fx = floor(((double)p.x - b.xmin) * b.scale);
+      double fy = floor(((double)p.y - b.ymin) * b.scale);
+      fx = fmin(fmax(fx, 0.0), 16777215.0);
+      fy = fmin(fmax(fy, 0.0), 16777215.0);
+      const uint64_t c = spread24((uint32_t)fx) | (spread24((uint32_t)fy) << 1);
+      sk[i] = (c << 12) | (uint64_t)i;
+    } else {
+      sk[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  bitonic_sort_lds(sk, m);
+  // 4. sorted points
+  for (int i = tid; i < n; i += BHS_T) {
+    const uint64_t kv = sk[i];
+    const uint64_t c = kv >> 12;
+    const int32_t id = (int32_t)(kv & 0xFFFu);
+    const float2 p = xy[id];
+    codes[i] = c;
+    order[i] = id;
+    xsx[i] = p.x;
+    xsy[i] = p.y;
+    ixy[i] = make_uint2(compact24(c), compact24(c >> 1));
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += BHS_T) sk[i] = sk[i] >> 12;  // codes from here on
+  // 5. FP64 prefix sums of the sorted coordinates (4 consecutive points per thread)
+  {
+    const int i0 = tid * 4;
+    double vx[4], vy[4], tx = 0.0, ty = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + j;
+      vx[j] = vy[j] = 0.0;
+      if (i < n) {
+        const float2 p = xy[(int32_t)(order[i])];
+        vx[j] = p.x;
+        vy[j] = p.y;
+      }
+      tx += vx[j];
+      ty += vy[j];
+    }
+    double totx, toty;
+    double ex = block_excl_scan<double>(tx, dsh, &totx);
+    double ey = block_excl_scan<double>(ty, dsh, &toty);
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + j;
+      if (i < n) { px[i] = ex; py[i] = ey; }
+      ex += vx[j];
+      ey += vy[j];
+    }
+    if (tid == 0) { px[n] = totx; py[n] = toty; }
+  }
+  __syncthreads();
+  // 6. node keys: leaves at runs of equal codes, internal nodes at owner pairs
+  for (int i = tid; i < 2 * m; i += BHS_T) nk[i] = ~0ull;
+  __syncthreads();
+  for (int i = tid; i < n; i += BHS_T) {
+    const uint64_t ci = sk[i];
+    if (i == 0 || sk[i - 1] != ci) nk[atomicAdd(&ncount, 1)] = ((uint64_t)i << 5) | 31u;
+    if (i + 1 < n && sk[i + 1] != ci) {
+      const int t = lcp48(ci, sk[i + 1]) >> 1;
+      const int sh = 48 - 2 * t;
+      const uint64_t pre = ci >> sh;
+      int lo = 0, hi = i;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((sk[mid] >> sh) < pre) lo = mid + 1; else hi = mid;
+      }
+      if ((sk[lo] >> (sh - 2)) == (ci >> (sh - 2)))
+        nk[atomicAdd(&ncount, 1)] = ((uint64_t)lo << 5) | (uint32_t)t;
+    }
+  }
+  __syncthreads();
+  const int32_t N = ncount;
+  // 7. pre-order: sort by (first point, depth code)
+  bitonic_sort_lds(nk, 2 * m);
+  for (int p = tid; p < N; p += BHS_T) {
+    const int32_t f = (int32_t)(nk[p] >> 5);
+    if (p == 0 || (int32_t)(nk[p - 1] >> 5) != f) fat[f] = p;
+  }
+  __syncthreads();
+  // 8. node records
+  for (int p = tid; p < N; p += BHS_T) {
+    const uint64_t key = nk[p];
+    const int32_t first = (int32_t)(key >> 5);
+    const int dcode = (int)(key & 31u);
+    const bool leaf = dcode == 31;
+    const int depth = leaf ? 24 : dcode;
+    const uint64_t c0 = sk[first];
+    int lo = first + 1, hi = n;  // last point: end of the equal code run / prefix
+    if (leaf) {
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if (sk[mid] <= c0) lo = mid + 1; else hi = mid; }
+    } else {
+      const int sh = 48 - 2 * depth;
+      const uint64_t pre = c0 >> sh;
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if ((sk[mid] >> sh) <= pre) lo = mid + 1; else hi = mid; }
+    }
+    const int32_t last = lo - 1;
+    const int32_t cnt = last - first + 1;
+    BHNode nd;
+    nd.cx = (px[last + 1] - px[first]) / (double)cnt;
+    nd.cy = (py[last + 1] - py[first]) / (double)cnt;
+    nd.mass = (float)cnt;
+    nd.skip = (last + 1 < n) ? fat[last + 1] : N;
+    const uint32_t mask = depth >= 24 ? 0xFFFFFFu : ~((1u << (24 - depth)) - 1u) & 0xFFFFFFu;
+    nd.ox = compact24(c0) & mask;
+    nd.oy = compact24(c0 >> 1) & mask;
+    nd.meta = depth | ((leaf ? 1 : 0) << 8);
+    nd.first = first;
+    nodes[p] = nd;
+    if (export_nodes) {
+      int64_t* o = export_nodes + 5 * (int64_t)p;
+      o[0] = depth; o[1] = first; o[2] = cnt; o[3] = leaf ? 1 : 0;
+      o[4] = (int64_t)(c0 >> (2 * (24 - depth)));
+    }
+  }
+  if (tid == 0) *Np = N;
+}
+
 constexpr int TR_WAVES = 4;
 
 template <bool STATS>
@@ -443,6 +632,15 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   MM_TRY(ensure<int32_t>(w->counter, 1, s));
   const int32_t M = seg ? seg->M : 1;
   MM_TRY(ensure<BoxInfo>(w->box, (size_t)M, s));
+  MM_TRY(ensure<unsigned long long>(w->statc, 2, s));
+  if (!seg && n <= BHS_MAX) {
+    // small trees: one launch
+    k_bh_small<<<1, BHS_T, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(), w->codes.as<uint64_t>(),
+                                     w->order.as<int32_t>(), w->xsx.as<float>(), w->xsy.as<float>(),
+                                     w->ix.as<uint2>(), w->px.as<double>(), w->py.as<double>(),
+                                     w->nodes.as<BHNode>(), w->counter.as<int32_t>(), nodes_out);
+    return hipGetLastError();
+  }
   const int nbb = std::min(1024, std::max(1, (n + BB_T - 1) / BB_T));
   MM_TRY(ensure<float4>(w->partial, nbb, s));
   const int32_t nps = (n + PS_TILE - 1) / PS_TILE;

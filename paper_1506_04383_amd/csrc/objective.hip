@@ -95,12 +95,17 @@ __global__ __launch_bounds__(OB_T) void k_obj_all(int32_t n, const float2* __res
 constexpr int FS_T = 256;
 constexpr int FS_MAXW = 36864;  // LDS bitmap words (n <= 1179648); + 8 KB static < 160 KB
 
+// BIG: the visited bitmap is a static LDS array of FS_MAXW words (dynamic LDS
+// is limited to 64 KB per work-group); otherwise it is sized at launch.
+template <bool BIG>
 __global__ __launch_bounds__(FS_T) void k_full_stress(int32_t n, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col,
                                                       const float2* __restrict__ xy,
                                                       int32_t* __restrict__ gq, int32_t* __restrict__ ghop,
                                                       double* __restrict__ per) {
-  extern __shared__ uint32_t bm[];
+  extern __shared__ uint32_t bm_dyn[];
+  __shared__ uint32_t bm_big[BIG ? FS_MAXW : 1];
+  uint32_t* bm = BIG ? bm_big : bm_dyn;
   __shared__ int32_t tail;
   __shared__ double sh[4][FS_T];
   const int32_t W = (n + 31) >> 5;
@@ -210,10 +215,12 @@ hipError_t full_stress(const GraphDev& g, const float* xy, double* out_host, hip
   MM_TRY(hop.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
   MM_TRY(per.alloc(sizeof(double) * 4 * (size_t)n, s));
   const size_t shm = sizeof(uint32_t) * (size_t)W;
-  MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_full_stress),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  k_full_stress<<<slots, FS_T, shm, s>>>(n, g.row_ptr, g.col, (const float2*)xy, q.as<int32_t>(),
-                                         hop.as<int32_t>(), per.as<double>());
+  if (shm <= 65536)
+    k_full_stress<false><<<slots, FS_T, shm, s>>>(n, g.row_ptr, g.col, (const float2*)xy,
+                                                  q.as<int32_t>(), hop.as<int32_t>(), per.as<double>());
+  else
+    k_full_stress<true><<<slots, FS_T, 0, s>>>(n, g.row_ptr, g.col, (const float2*)xy,
+                                               q.as<int32_t>(), hop.as<int32_t>(), per.as<double>());
   MM_TRY(hipGetLastError());
   std::vector<double> h(4 * (size_t)n);
   MM_TRY(hipMemcpyAsync(h.data(), per.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
