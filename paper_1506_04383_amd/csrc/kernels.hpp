@@ -79,7 +79,7 @@ struct TiledSet {
   int32_t* chunk_row = nullptr;  // chunks by tile, largest first within a tile
   int64_t* chunk_off = nullptr;  // nchunks+1: entry offsets (multiples of 8)
   int32_t* chunk_slot = nullptr; // row-major slot of each chunk
-  uint16_t* ent = nullptr;       // (hop << tbits) | (v - tile * 2^tbits)
+  uint16_t* ent = nullptr;       // ((v - tile * 2^tbits) << 3) | hop
   int32_t* unit_c0 = nullptr;    // nunits+1: first chunk of each work unit
   int32_t* unit_tile = nullptr;  // tile of each work unit
   DevBuf b_rc_ptr, b_chunk_row, b_chunk_off, b_chunk_slot, b_ent, b_unit_c0, b_unit_tile, b_partial,
@@ -93,7 +93,7 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
 // min_avg_chunk it stops after counting (ts->built stays false).
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
                        hipStream_t s);
-constexpr int32_t kTileBits = 13;
+constexpr int32_t kTileBits = 13;  // tiled sets need k <= 7 and tbits <= 13
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
                        float* xy_out, double* delta2_dev, hipStream_t s,

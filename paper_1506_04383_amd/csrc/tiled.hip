@@ -6,7 +6,9 @@
 // into tiles of T = 2^tbits vertices; the coordinates (and sqrt c) of one
 // tile are staged in LDS and every (row, tile) chunk of the sets is swept
 // against them.  Entries are stored tile-major, 16 bits each:
-// (hop << tbits) | (v - tile * T), so hop <= 2^(16 - tbits) - 1.
+// ((v - tile * T) << 3) | hop, so hop <= 7 and T <= 2^13; the local id shifted
+// by 3 is the byte offset of x_v in the staged tile, and the hop indexes a
+// small per-level table (w = 1/d^2, w d, alpha; hop 0 marks padding).
 //
 // Per chunk the partial sum  P = sum w (x_v + d (x_u - x_v)/D) - alpha sum r_q(u,v)
 // is written to a row-major slot; the combine kernel adds a row's slots in
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
         const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
         const int32_t c = pos_of_slot[rbase + rank];
         const int64_t dst = chunk_off[c] + ct[t] + (l - rs);
-        ent[dst] = (uint16_t)((h << tbits) | (v & ((1 << tbits) - 1)));
+        ent[dst] = (uint16_t)(((v & ((1 << tbits) - 1)) << 3) | h);
       }
       wave_sync();
       if (end) ct[t] += l - rs + 1;
@@ -326,9 +328,9 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
 #pragma unroll
       for (int q2 = 0; q2 < 8; ++q2) {
         const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
-        const uint32_t vl = pk & (uint32_t)mask;
+        const uint32_t vl = pk >> 3;
         xv[q2] = sx[vl];
-        lw[q2] = lut[pk >> tbits];
+        lw[q2] = lut[pk & 7u];
         if (COARSE) sc[q2] = ssc[vl];
       }
 #pragma unroll
@@ -346,11 +348,9 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
         }
         float inv = __builtin_amdgcn_rsqf(D2);
         if (!Q0) inv = D2 > 0.f ? inv : 0.f;
-        float rq;
-        if (Q0) rq = inv * inv;
-        else rq = D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f;
+        const float rq = Q0 ? 0.f : (D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f);
         // w d / D - alpha / D^(q+2); zero for padding and coincident pairs
-        const float coef = fmaf(wd, inv, -lw[q2].z * rq);
+        const float coef = Q0 ? inv * fmaf(-lw[q2].z, inv, wd) : fmaf(wd, inv, -lw[q2].z * rq);
         px = fmaf(w, xv[q2].x, px);
         py = fmaf(w, xv[q2].y, py);
         px = fmaf(coef, dx, px);
@@ -447,7 +447,8 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 
 bool tiled_eligible(const KhopDev& kh, int32_t tbits) {
   const int64_t ntiles = ((int64_t)kh.n + (1 << tbits) - 1) >> tbits;
-  return kh.k <= ((1 << (16 - tbits)) - 1) && ntiles <= TB_MAXTILES && kh.total > 0;
+  // entries are (local id << 3) | hop: 3 hop bits, tbits + 3 <= 16
+  return kh.k <= 7 && tbits <= 13 && ntiles <= TB_MAXTILES && kh.total > 0;
 }
 
 hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, float* rho,
