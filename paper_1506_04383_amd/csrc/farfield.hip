@@ -286,6 +286,7 @@ __global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* _
                                  const int32_t* __restrict__ Np, int32_t n,
                                  const int32_t* __restrict__ first_at,
                                  const double* __restrict__ px, const double* __restrict__ py,
+                                 const float* __restrict__ xsx, const float* __restrict__ xsy,
                                  const uint2* __restrict__ ixy, BHNode* __restrict__ nodes,
                                  int64_t* __restrict__ export_nodes,
                                  const uint64_t* __restrict__ codes) {
@@ -296,8 +297,10 @@ __global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* _
   const int32_t first = t.x, last = t.y, depth = t.z, leaf = t.w;
   const int32_t cnt = last - first + 1;
   BHNode nd;
-  nd.cx = (px[last + 1] - px[first]) / (double)cnt;
-  nd.cy = (py[last + 1] - py[first]) / (double)cnt;
+  // a single point keeps its own coordinates exactly (the traversal reads
+  // them from here instead of the point arrays)
+  nd.cx = cnt == 1 ? (double)xsx[first] : (px[last + 1] - px[first]) / (double)cnt;
+  nd.cy = cnt == 1 ? (double)xsy[first] : (py[last + 1] - py[first]) / (double)cnt;
   nd.mass = (float)cnt;
   nd.skip = (last + 1 < n) ? first_at[last + 1] : N;
   const uint32_t mask = depth >= 24 ? 0xFFFFFFu : ~((1u << (24 - depth)) - 1u) & 0xFFFFFFu;
@@ -484,8 +487,8 @@ __global__ __launch_bounds__(BHS_T) void k_bh_small(
     const int32_t last = lo - 1;
     const int32_t cnt = last - first + 1;
     BHNode nd;
-    nd.cx = (px[last + 1] - px[first]) / (double)cnt;
-    nd.cy = (py[last + 1] - py[first]) / (double)cnt;
+    nd.cx = cnt == 1 ? (double)xsx[first] : (px[last + 1] - px[first]) / (double)cnt;
+    nd.cy = cnt == 1 ? (double)xsy[first] : (py[last + 1] - py[first]) / (double)cnt;
     nd.mass = (float)cnt;
     nd.skip = (last + 1 < n) ? fat[last + 1] : N;
     const uint32_t mask = depth >= 24 ? 0xFFFFFFu : ~((1u << (24 - depth)) - 1u) & 0xFFFFFFu;
@@ -538,13 +541,21 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     const bool act = (next == p);
     const int depth = nd.meta & 0xff;
     if (nd.meta >> 8) {
-      // leaf: exact terms for its points
+      // leaf: exact terms for its points (a single point's coordinates are
+      // in the node record)
       const int32_t cnt = (int32_t)nd.mass;
-      for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
-        const float sx = xsx[j], sy = xsy[j];
-        if (act && j != i) {
-          const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
+      if (cnt == 1) {
+        if (act && nd.first != i) {
+          const bool added = rq_add(xt - (float)nd.cx, yt - (float)nd.cy, q, 1.f, fx, fy);
           if (STATS && added) pairs++;
+        }
+      } else {
+        for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
+          const float sx = xsx[j], sy = xsy[j];
+          if (act && j != i) {
+            const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
+            if (STATS && added) pairs++;
+          }
         }
       }
       if (act) next = nd.skip >= end ? 0x7fffffff : nd.skip;
@@ -689,7 +700,8 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   k_first_at<<<(NMAX + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), Np, w->first_at.as<int32_t>());
   k_finalize_nodes<<<(NMAX + 255) / 256, 256, 0, s>>>(
       w->nvals.as<int32_t>(), w->ntmp.as<int4>(), Np, n, w->first_at.as<int32_t>(),
-      w->px.as<double>(), w->py.as<double>(), w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
+      w->px.as<double>(), w->py.as<double>(), w->xsx.as<float>(), w->xsy.as<float>(),
+      w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
       w->codes.as<uint64_t>());
   return hipGetLastError();
 }

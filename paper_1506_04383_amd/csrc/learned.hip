@@ -368,9 +368,13 @@ __global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
     const bool act = (next == p);
     if (nd.meta >> 8) {
       const int32_t cnt = (int32_t)nd.mass;
-      for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
-        const float sx = xsx[j], sy = xsy[j];
-        if (act && j != i) rq_add(xt - sx, yt - sy, 0.f, 1.f, fx, fy);
+      if (cnt == 1) {
+        if (act && nd.first != i) rq_add(xt - (float)nd.cx, yt - (float)nd.cy, 0.f, 1.f, fx, fy);
+      } else {
+        for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
+          const float sx = xsx[j], sy = xsy[j];
+          if (act && j != i) rq_add(xt - sx, yt - sy, 0.f, 1.f, fx, fy);
+        }
       }
       if (act) next = nd.skip;
       p = wave_min(next);
