@@ -286,12 +286,17 @@ def sweep_bytes(n: int, k: int, entries: int, coarse: bool) -> int:
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_tiled_rmat20_traffic.md")
+# Autotuner choices measured on MI355X for the bench workloads (written by
+# --save-tune-db); loading them makes the timed layouts use a fixed, known
+# sweep configuration per level.
+TUNE_DB = os.path.join(ROOT, "paper_1506_04383_amd", "tune_mi355x.json")
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, tile_bits: int, group: int):
     """HBM bytes per finest-level sweep step from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE passes (copy-calibrated), or None when the workload
-    differs or the kernel source changed since the counters were taken."""
+    or the sweep configuration (tile bits, lanes per chunk) differs or the
+    kernel source changed since the counters were taken."""
     import hashlib
 
     if workload != "rmat20" or not os.path.exists(TRAFFIC_PROFILE):
@@ -305,6 +310,8 @@ def measured_traffic(workload: str):
     if not os.path.exists(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("kernel_source_sha256"):
+        return None
+    if kv.get("sweep_config") != f"{tile_bits},{group}":
         return None
     return int(kv["traffic_bytes_per_launch"])
 
@@ -346,6 +353,11 @@ def main():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: the sweep configuration of every level is timed and chosen during "
                          "the first layout (the warm-up) and reused by the timed ones")
+    ap.add_argument("--tune-db", default=TUNE_DB,
+                    help="JSON file of autotuner choices (per level shape) loaded into the "
+                         "context before the first layout; levels it does not cover are tuned")
+    ap.add_argument("--save-tune-db", default="",
+                    help="write the context's autotuner choices here after the run")
     ap.add_argument("--mode", default="layout",
                     choices=["layout", "learned", "batch", "snapshots"],
                     help="layout: the layout benchmark; learned: learned far field vs plain "
@@ -402,6 +414,12 @@ def main():
                   coarsest_n=wl.get("coarsest_n", 2), max_levels=wl.get("max_levels", 62),
                   seed=args.seed, validate=0, autotune=args.autotune)
 
+    tune_loaded = 0
+    if args.autotune and args.tune_db and os.path.exists(args.tune_db):
+        recs = json.load(open(args.tune_db))["records"]
+        ctx.tune_import(np.array(recs, dtype=np.int64).reshape(-1, 6))
+        tune_loaded = len(recs)
+
     for i in range(args.warmup):
         t = time.time()
         mm.layout(ctx, dg, p)
@@ -456,10 +474,12 @@ def main():
                           "other": st["t_other_ms"]},
         "per_level": [[l["n"], l["khop_entries"], l["iters"], round(l["sweep_ms"], 1),
                        round(l["far_ms"], 1), l["tile_bits"], l["group"]] for l in st["per_level"]],
-        "autotune": {"enabled": args.autotune, "tuning_ms_in_timed_step": st["t_tune_ms"]},
+        "autotune": {"enabled": args.autotune, "tuning_ms_in_timed_step": st["t_tune_ms"],
+                     "records_loaded": tune_loaded},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_tiled + k_combine (finest-level sweep step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, L0["tile_bits"], L0["group"]),
                      "bytes_per_launch": bytes0, "avg_ms": sweep_avg_ms},
     }
     if not args.no_objective:
@@ -471,6 +491,17 @@ def main():
         x = xy.cpu().numpy().astype(np.float64)
         F = mm.repulsion(ctx, xy, p.q, p.theta)["F"].cpu().numpy().astype(np.float64)
         out["cpu_baseline"] = cpu_baseline(g, wl["k"], x, F, p.alpha_min)
+    if args.save_tune_db:
+        old = []
+        if os.path.exists(args.save_tune_db):
+            old = json.load(open(args.save_tune_db))["records"]
+        recs = {tuple(r[:4]): list(r) for r in old}
+        recs.update({tuple(int(v) for v in r[:4]): [int(v) for v in r]
+                     for r in ctx.tune_export()})
+        rows = ",\n".join("  " + json.dumps(r) for r in sorted(recs.values()))
+        with open(args.save_tune_db, "w") as fh:
+            fh.write('{"fields": ["coarse", "n", "stress_entries", "k", "tile_bits", "lanes"],\n'
+                     f' "records": [\n{rows}\n]}}\n')
     print(json.dumps(out))
     ctx.close()
 

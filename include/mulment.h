@@ -110,6 +110,17 @@ mm_status mm_context_create(mm_context** out, int32_t device, void* stream);
 void mm_context_destroy(mm_context* ctx);
 /* Forgets the sweep configurations the autotuner chose in this context. */
 mm_status mm_tune_clear(mm_context* ctx);
+/* The autotuner's choices as records of MM_TUNE_FIELDS int64 each:
+ * (coarse level?, n, sum |S(u)|, k, tile bits (0 = row kernel), lanes).
+ * mm_tune_export writes at most cap records to recs (host) and the number
+ * the context holds to *count (so cap = 0 asks for the size).
+ * mm_tune_import adds or replaces count records; a record whose tile bits
+ * are not 0 or 11..13, or whose lanes are not a power of two in 4..64, is
+ * rejected with MM_EINVAL and nothing is imported.  Used to keep a tuned
+ * configuration across processes. */
+#define MM_TUNE_FIELDS 6
+mm_status mm_tune_export(mm_context* ctx, int64_t* recs, int32_t cap, int32_t* count);
+mm_status mm_tune_import(mm_context* ctx, const int64_t* recs, int32_t count);
 /* Waits for the context's stream; reports asynchronous device errors. */
 mm_status mm_sync(mm_context* ctx);
 const char* mm_last_error(void);
@@ -236,6 +247,16 @@ enum { MM_SWEEP_AUTO = 0, MM_SWEEP_ROWS = 1, MM_SWEEP_TILED = 2 };
 mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
                       double scale, const float* xy_in, const float* F, double alpha, double q,
                       float* xy_out, double* delta, int32_t mode);
+/* As mm_sweep_ex with the configuration forced, the way the autotuner runs
+ * its candidates: tile_bits = 0 runs the row kernel with group lanes per row
+ * (8, 16, 32 or 64); tile_bits = 11, 12 or 13 runs the tiled kernel with tiles
+ * of 2^tile_bits vertices and group lanes per chunk (4, 8 or 16).  Any other
+ * pair is MM_EINVAL; tiled configurations the sets do not allow (k > 7, too
+ * many tiles) are MM_EUNSUPPORTED.  The update is the same for every
+ * configuration up to the order of FP32 summation. */
+mm_status mm_sweep_cfg(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
+                       double scale, const float* xy_in, const float* F, double alpha, double q,
+                       float* xy_out, double* delta, int32_t tile_bits, int32_t group);
 
 /* One coarsening step (Section 3.1): size-constrained label propagation with
  * bound U at hierarchy level level_h, then contraction.  cluster (device, n)

@@ -89,7 +89,7 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_coarse_graph", "mm_coarse_export", "mm_coarse_free", "mm_init_layout",
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
-           "mm_tune_clear"]
+           "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg"]
 
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
 
@@ -119,6 +119,7 @@ def lib():
         "mm_repulsion": [vp, i32, vp, f64, f64, vp, vp, vp, vp, vp],
         "mm_sweep": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp],
         "mm_sweep_ex": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32],
+        "mm_sweep_cfg": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32, i32],
         "mm_coarsen": [vp, P(MMGraph), f64, i32, u64, i32, vp, P(vp), vp, vp],
         "mm_coarse_graph": [vp, P(MMGraph)],
         "mm_coarse_export": [vp, vp, vp, vp, vp, vp, i32],
@@ -129,6 +130,8 @@ def lib():
         "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
         "mm_layout_batch": [vp, i32, vp, P(MMGraph), P(MMParams), vp, vp, vp, P(MMStats)],
         "mm_tune_clear": [vp],
+        "mm_tune_export": [vp, P(i64), i32, P(i32)],
+        "mm_tune_import": [vp, P(i64), i32],
         "mm_far_samples": [vp, i32, vp, f64, i64, vp, vp, vp, vp, vp, P(i64)],
         "mm_mlp_forward": [vp, i64, vp, vp, vp],
         "mm_mlp_grad": [vp, i64, vp, vp, vp, vp, vp],
@@ -238,6 +241,24 @@ class Context:
 
     def sync(self):
         _check(lib().mm_sync(self.h))
+
+    def tune_export(self):
+        """The autotuner's choices: int64 array (records, 6) of
+        (coarse?, n, sum |S|, k, tile bits (0 = row kernel), lanes)."""
+        cnt = C.c_int32(0)
+        _check(lib().mm_tune_export(self.h, None, 0, C.byref(cnt)))
+        recs = np.zeros((max(cnt.value, 1), 6), np.int64)
+        _check(lib().mm_tune_export(self.h, recs.ctypes.data_as(C.POINTER(C.c_int64)), cnt.value,
+                                    C.byref(cnt)))
+        return recs[: cnt.value]
+
+    def tune_import(self, recs):
+        recs = np.ascontiguousarray(recs, dtype=np.int64).reshape(-1, 6)
+        _check(lib().mm_tune_import(self.h, recs.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    recs.shape[0]))
+
+    def tune_clear(self):
+        _check(lib().mm_tune_clear(self.h))
 
     # -- helpers
     def _dev(self, a, dtype):
@@ -451,17 +472,23 @@ SWEEP_AUTO, SWEEP_ROWS, SWEEP_TILED = 0, 1, 2
 
 
 def sweep(ctx: Context, kh: KHop, xy, F, alpha: float, q: float = 0.0, level: int = 0,
-          node_w=None, scale: float = 1.0, mode: int = SWEEP_ROWS):
+          node_w=None, scale: float = 1.0, mode: int = SWEEP_ROWS, config=None):
     """One Jacobi iteration of Eq. 2; returns (xy_out, (|x'-x|^2, |x|^2)).
-    mode: SWEEP_ROWS (row-gather kernel), SWEEP_TILED (LDS-tiled), SWEEP_AUTO."""
+    mode: SWEEP_ROWS (row-gather kernel), SWEEP_TILED (LDS-tiled), SWEEP_AUTO.
+    config = (tile_bits, lanes) forces a configuration instead (mm_sweep_cfg)."""
     t = ctx.torch
     xy = ctx._dev(xy, t.float32)
     F = ctx._dev(F, t.float32)
     nw = None if node_w is None else ctx._dev(node_w, t.int32)
     out = t.empty_like(xy)
     d = np.zeros(2)
-    _check(lib().mm_sweep_ex(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha, q,
-                             _ptr(out), d.ctypes.data_as(C.c_void_p), mode))
+    if config is None:
+        _check(lib().mm_sweep_ex(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha, q,
+                                 _ptr(out), d.ctypes.data_as(C.c_void_p), mode))
+    else:
+        _check(lib().mm_sweep_cfg(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha,
+                                  q, _ptr(out), d.ctypes.data_as(C.c_void_p), int(config[0]),
+                                  int(config[1])))
     return out, (float(d[0]), float(d[1]))
 
 

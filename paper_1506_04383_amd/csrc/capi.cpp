@@ -218,6 +218,64 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
   return MM_OK;
 }
 
+// One sweep through the C-ABI: mode as mm_sweep_ex; tbits/group > 0 force the
+// tile size and lanes (a tile-major copy of another tile size is built for
+// the call and dropped).
+mm_status sweep_common(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
+                       double scale, const float* xy_in, const float* F, double alpha, double q,
+                       float* xy_out, double* delta, int32_t mode, int32_t tbits, int32_t group) {
+  try {
+    if (!ctx || !kh || !xy_in || !F || !xy_out) return fail(MM_EINVAL, "NULL argument");
+    if (xy_in == xy_out) return fail(MM_EINVAL, "Jacobi update needs separate in/out buffers");
+    if (level < 0 || !(scale > 0) || std::isnan(alpha) || std::isnan(q)) return fail(MM_EINVAL, "bad level/scale/alpha/q");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    mm::DevBuf sq, d2;
+    const float* sqrtc = nullptr;
+    if (level > 0) {
+      HIPCHK(make_sqrtc(kh->kh.n, node_w, sq, s));
+      sqrtc = sq.as<float>();
+    }
+    HIPCHK(d2.alloc(2 * sizeof(double), s));
+    const int32_t tb = tbits > 0 ? tbits : mm::kTileBits;
+    mm::TiledSet own;
+    const mm::TiledSet* ts = nullptr;
+    if (mode != MM_SWEEP_ROWS) {
+      const bool ok = mm::tiled_eligible(kh->kh, tb);
+      if (mode == MM_SWEEP_TILED && !ok) return fail(MM_EUNSUPPORTED, "tiled sweep needs k <= 7 and n <= 2^25");
+      if (ok && tb != mm::kTileBits) {
+        HIPCHK(mm::tiled_build(kh->kh, tb, 0.0, &own, s));
+        if (own.built) ts = &own;
+      } else if (ok) {
+        if (!kh->ts_tried) {
+          HIPCHK(mm::tiled_build(kh->kh, tb, mode == MM_SWEEP_TILED ? 0.0 : 8.0, &kh->ts, s));
+          kh->ts_tried = true;
+        }
+        if (!kh->ts.built && mode == MM_SWEEP_TILED) HIPCHK(mm::tiled_build(kh->kh, tb, 0.0, &kh->ts, s));
+        if (kh->ts.built) ts = &kh->ts;
+      }
+      if (!ts && mode == MM_SWEEP_TILED) return fail(MM_EUNSUPPORTED, "tile-major sets not built");
+    }
+    if (ts) {
+      mm::DevBuf rho;
+      HIPCHK(rho.alloc(sizeof(float) * (size_t)kh->kh.n, s));
+      HIPCHK(mm::compute_rho(kh->kh, sqrtc, scale, rho.as<float>(), s));
+      HIPCHK(mm::sweep_tiled(*ts, level, sqrtc, scale, rho.as<float>(), xy_in, F, alpha, q,
+                             xy_out, d2.as<double>(), s, nullptr, group));
+    } else {
+      mm::DevBuf part;
+      HIPCHK(mm::sweep(kh->kh, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2.as<double>(), s,
+                       nullptr, nullptr, nullptr, &part, group));
+    }
+    HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (delta) { delta[0] = ctx->pinned[0]; delta[1] = ctx->pinned[1]; }
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in the sweep");
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -227,6 +285,46 @@ const char* mm_last_error(void) { return g_err.c_str(); }
 mm_status mm_tune_clear(mm_context* ctx) {
   if (!ctx) return fail(MM_EINVAL, "NULL context");
   ctx->tune.clear();
+  return MM_OK;
+}
+
+mm_status mm_tune_export(mm_context* ctx, int64_t* recs, int32_t cap, int32_t* count) {
+  if (!ctx || !count) return fail(MM_EINVAL, "NULL context or count");
+  if (cap > 0 && !recs) return fail(MM_EINVAL, "NULL records with cap %d", cap);
+  int32_t i = 0;
+  for (const auto& [key, c] : ctx->tune) {
+    if (i < cap) {
+      int64_t* r = recs + (size_t)i * MM_TUNE_FIELDS;
+      r[0] = std::get<0>(key);
+      r[1] = std::get<1>(key);
+      r[2] = std::get<2>(key);
+      r[3] = std::get<3>(key);
+      r[4] = c.tbits;
+      r[5] = c.group;
+    }
+    ++i;
+  }
+  *count = i;
+  return MM_OK;
+}
+
+mm_status mm_tune_import(mm_context* ctx, const int64_t* recs, int32_t count) {
+  if (!ctx) return fail(MM_EINVAL, "NULL context");
+  if (count < 0 || (count > 0 && !recs)) return fail(MM_EINVAL, "bad record list (%d)", count);
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t* r = recs + (size_t)i * MM_TUNE_FIELDS;
+    const bool tb_ok = r[4] == 0 || (r[4] >= 11 && r[4] <= 13);
+    const bool g_ok = r[5] >= 4 && r[5] <= 64 && (r[5] & (r[5] - 1)) == 0 &&
+                      (r[4] == 0 ? r[5] >= 8 : r[5] <= 16);
+    if (!tb_ok || !g_ok || (r[0] != 0 && r[0] != 1) || r[1] < 0 || r[1] > INT32_MAX || r[2] < 0 ||
+        r[3] < 1 || r[3] > INT32_MAX)
+      return fail(MM_EINVAL, "tune record %d is invalid", i);
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t* r = recs + (size_t)i * MM_TUNE_FIELDS;
+    ctx->tune[std::make_tuple((int)r[0], (int32_t)r[1], r[2], (int32_t)r[3])] =
+        mm_context::TuneChoice{(int32_t)r[4], (int32_t)r[5]};
+  }
   return MM_OK;
 }
 
@@ -471,49 +569,18 @@ mm_status mm_mlp_train(mm_context* ctx, int64_t count, const float* feat, const 
 mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
                       double scale, const float* xy_in, const float* F, double alpha, double q,
                       float* xy_out, double* delta, int32_t mode) {
-  try {
-    if (!ctx || !kh || !xy_in || !F || !xy_out) return fail(MM_EINVAL, "NULL argument");
-    if (xy_in == xy_out) return fail(MM_EINVAL, "Jacobi update needs separate in/out buffers");
-    if (level < 0 || !(scale > 0) || std::isnan(alpha) || std::isnan(q)) return fail(MM_EINVAL, "bad level/scale/alpha/q");
-    if (mode < MM_SWEEP_AUTO || mode > MM_SWEEP_TILED) return fail(MM_EINVAL, "bad sweep mode");
-    DeviceGuard dg(ctx->device);
-    hipStream_t s = ctx->stream;
-    mm::DevBuf sq, d2;
-    const float* sqrtc = nullptr;
-    if (level > 0) {
-      HIPCHK(make_sqrtc(kh->kh.n, node_w, sq, s));
-      sqrtc = sq.as<float>();
-    }
-    HIPCHK(d2.alloc(2 * sizeof(double), s));
-    bool tiled = false;
-    if (mode != MM_SWEEP_ROWS) {
-      const bool ok = mm::tiled_eligible(kh->kh, mm::kTileBits);
-      if (mode == MM_SWEEP_TILED && !ok) return fail(MM_EUNSUPPORTED, "tiled sweep needs k <= 7 and n <= 2^25");
-      if (ok && !kh->ts_tried) {
-        HIPCHK(mm::tiled_build(kh->kh, mm::kTileBits, mode == MM_SWEEP_TILED ? 0.0 : 8.0, &kh->ts, s));
-        kh->ts_tried = true;
-      }
-      if (ok && !kh->ts.built && mode == MM_SWEEP_TILED) {
-        HIPCHK(mm::tiled_build(kh->kh, mm::kTileBits, 0.0, &kh->ts, s));
-      }
-      tiled = ok && kh->ts.built;
-    }
-    if (tiled) {
-      mm::DevBuf rho;
-      HIPCHK(rho.alloc(sizeof(float) * (size_t)kh->kh.n, s));
-      HIPCHK(mm::compute_rho(kh->kh, sqrtc, scale, rho.as<float>(), s));
-      HIPCHK(mm::sweep_tiled(kh->ts, level, sqrtc, scale, rho.as<float>(), xy_in, F, alpha, q,
-                             xy_out, d2.as<double>(), s));
-    } else {
-      HIPCHK(mm::sweep(kh->kh, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2.as<double>(), s));
-    }
-    HIPCHK(hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (delta) { delta[0] = ctx->pinned[0]; delta[1] = ctx->pinned[1]; }
-    return MM_OK;
-  } catch (...) {
-    return fail(MM_EINTERNAL, "exception in mm_sweep_ex");
-  }
+  if (mode < MM_SWEEP_AUTO || mode > MM_SWEEP_TILED) return fail(MM_EINVAL, "bad sweep mode");
+  return sweep_common(ctx, kh, level, node_w, scale, xy_in, F, alpha, q, xy_out, delta, mode, 0, 0);
+}
+
+mm_status mm_sweep_cfg(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
+                       double scale, const float* xy_in, const float* F, double alpha, double q,
+                       float* xy_out, double* delta, int32_t tile_bits, int32_t group) {
+  const bool rows_ok = tile_bits == 0 && (group == 8 || group == 16 || group == 32 || group == 64);
+  const bool tiled_ok = tile_bits >= 11 && tile_bits <= 13 && (group == 4 || group == 8 || group == 16);
+  if (!rows_ok && !tiled_ok) return fail(MM_EINVAL, "bad sweep configuration (%d, %d)", tile_bits, group);
+  return sweep_common(ctx, kh, level, node_w, scale, xy_in, F, alpha, q, xy_out, delta,
+                      tile_bits ? MM_SWEEP_TILED : MM_SWEEP_ROWS, tile_bits, group);
 }
 
 mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
