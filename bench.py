@@ -292,10 +292,10 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_tiled_rmat20_traffic.m
 TUNE_DB = os.path.join(ROOT, "paper_1506_04383_amd", "tune_mi355x.json")
 
 
-def measured_traffic(workload: str, tile_bits: int, group: int):
+def measured_traffic(workload: str, tile_bits: int, group: int, blocks: int):
     """HBM bytes per finest-level sweep step from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE passes (copy-calibrated), or None when the workload
-    or the sweep configuration (tile bits, lanes per chunk) differs or the
+    or the sweep configuration (tile bits, lanes per chunk, blocks per step) differs or the
     kernel source changed since the counters were taken."""
     import hashlib
 
@@ -311,7 +311,7 @@ def measured_traffic(workload: str, tile_bits: int, group: int):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("kernel_source_sha256"):
         return None
-    if kv.get("sweep_config") != f"{tile_bits},{group}":
+    if kv.get("sweep_config") != f"{tile_bits},{group},{blocks}":
         return None
     return int(kv["traffic_bytes_per_launch"])
 
@@ -353,6 +353,10 @@ def main():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: the sweep configuration of every level is timed and chosen during "
                          "the first layout (the warm-up) and reused by the timed ones")
+    ap.add_argument("--exact-below", type=int, default=49152,
+                    help="levels with at most this many vertices use the exact all-pairs far "
+                         "field (cheaper there than the tree on this GPU); 0 = Barnes-Hut on "
+                         "every level")
     ap.add_argument("--tune-db", default=TUNE_DB,
                     help="JSON file of autotuner choices (per level shape) loaded into the "
                          "context before the first layout; levels it does not cover are tuned")
@@ -412,12 +416,13 @@ def main():
     dg = ctx.graph(g.row_ptr, g.col)
     p = mm.Params(k=wl["k"], theta=wl["theta"], alpha_decay=wl["alpha_decay"],
                   coarsest_n=wl.get("coarsest_n", 2), max_levels=wl.get("max_levels", 62),
-                  seed=args.seed, validate=0, autotune=args.autotune)
+                  seed=args.seed, validate=0, autotune=args.autotune,
+                  exact_below=args.exact_below if wl["theta"] >= 0 else 0)
 
     tune_loaded = 0
     if args.autotune and args.tune_db and os.path.exists(args.tune_db):
         recs = json.load(open(args.tune_db))["records"]
-        ctx.tune_import(np.array(recs, dtype=np.int64).reshape(-1, 6))
+        ctx.tune_import(np.array(recs, dtype=np.int64).reshape(-1, mm.TUNE_FIELDS))
         tune_loaded = len(recs)
 
     for i in range(args.warmup):
@@ -463,6 +468,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": g.n, "m": g.m, "k": wl["k"],
                    "theta": wl["theta"], "alpha_decay": wl["alpha_decay"], "seed": args.seed,
+                   "exact_far_field_below_n": p.exact_below,
                    "levels": st["levels"]},
         "time_to_layout_s": T / args.steps,
         "finest_sweep_updates_per_s": n0 / (sweep_avg_ms * 1e-3),
@@ -473,13 +479,15 @@ def main():
                           "khop": st["t_khop_ms"], "coarsen": st["t_coarsen_ms"],
                           "other": st["t_other_ms"]},
         "per_level": [[l["n"], l["khop_entries"], l["iters"], round(l["sweep_ms"], 1),
-                       round(l["far_ms"], 1), l["tile_bits"], l["group"]] for l in st["per_level"]],
+                       round(l["far_ms"], 1), l["tile_bits"], l["group"], l["blocks"]]
+                      for l in st["per_level"]],
         "autotune": {"enabled": args.autotune, "tuning_ms_in_timed_step": st["t_tune_ms"],
                      "records_loaded": tune_loaded},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_tiled + k_combine (finest-level sweep step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, L0["tile_bits"], L0["group"]),
+                     "traffic": measured_traffic(args.workload, L0["tile_bits"], L0["group"],
+                                                 L0["blocks"]),
                      "bytes_per_launch": bytes0, "avg_ms": sweep_avg_ms},
     }
     if not args.no_objective:
@@ -500,7 +508,8 @@ def main():
                      for r in ctx.tune_export()})
         rows = ",\n".join("  " + json.dumps(r) for r in sorted(recs.values()))
         with open(args.save_tune_db, "w") as fh:
-            fh.write('{"fields": ["coarse", "n", "stress_entries", "k", "tile_bits", "lanes"],\n'
+            fh.write('{"fields": ["coarse", "n", "stress_entries", "k", "tile_bits", "lanes", '
+                     '"blocks"],\n'
                      f' "records": [\n{rows}\n]}}\n')
     print(json.dumps(out))
     ctx.close()

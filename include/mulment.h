@@ -80,6 +80,9 @@ typedef struct {
                               level shape, and keep the choice in the context (later layouts
                               reuse it, so their results are reproducible); 0: fixed rules
                               (default) */
+  int32_t exact_below;     /* levels with at most this many vertices use the exact all-pairs
+                              far field instead of Barnes-Hut (0 = none, default); mm_layout
+                              only (mm_layout_batch requires 0) */
 } mm_params;
 
 #define MM_MAX_LEVELS 64
@@ -101,6 +104,7 @@ typedef struct {
   int32_t level_tile_bits[MM_MAX_LEVELS];/* sweep of the level: tile size 2^bits (0 = row kernel) */
   int32_t level_group[MM_MAX_LEVELS];    /* lanes per chunk (tiled) or per row (row kernel) */
   double t_tune_ms;                      /* time spent timing candidates (autotune) */
+  int32_t level_blocks[MM_MAX_LEVELS];   /* tiled sweep: 16-byte entry blocks per lane and step */
 } mm_stats;
 
 mm_status mm_params_default(mm_params* p);
@@ -111,14 +115,17 @@ void mm_context_destroy(mm_context* ctx);
 /* Forgets the sweep configurations the autotuner chose in this context. */
 mm_status mm_tune_clear(mm_context* ctx);
 /* The autotuner's choices as records of MM_TUNE_FIELDS int64 each:
- * (coarse level?, n, sum |S(u)|, k, tile bits (0 = row kernel), lanes).
+ * (coarse level?, n, sum |S(u)|, k, tile bits (0 = row kernel), lanes,
+ * blocks per lane and step (tiled: 2 or 4; row kernel: 0)).
  * mm_tune_export writes at most cap records to recs (host) and the number
  * the context holds to *count (so cap = 0 asks for the size).
  * mm_tune_import adds or replaces count records; a record whose tile bits
- * are not 0 or 11..13, or whose lanes are not a power of two in 4..64, is
- * rejected with MM_EINVAL and nothing is imported.  Used to keep a tuned
+ * are not 0 or 11..13, whose lanes are not a power of two in 4..64 (8..64 for
+ * the row kernel, 4..16 tiled), or whose blocks are not 0 (row kernel) or
+ * 0, 2, 4 (tiled; 0 = the default rule) is rejected with MM_EINVAL and
+ * nothing is imported.  Used to keep a tuned
  * configuration across processes. */
-#define MM_TUNE_FIELDS 6
+#define MM_TUNE_FIELDS 7
 mm_status mm_tune_export(mm_context* ctx, int64_t* recs, int32_t cap, int32_t* count);
 mm_status mm_tune_import(mm_context* ctx, const int64_t* recs, int32_t count);
 /* Waits for the context's stream; reports asynchronous device errors. */
@@ -249,14 +256,16 @@ mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t
                       float* xy_out, double* delta, int32_t mode);
 /* As mm_sweep_ex with the configuration forced, the way the autotuner runs
  * its candidates: tile_bits = 0 runs the row kernel with group lanes per row
- * (8, 16, 32 or 64); tile_bits = 11, 12 or 13 runs the tiled kernel with tiles
- * of 2^tile_bits vertices and group lanes per chunk (4, 8 or 16).  Any other
- * pair is MM_EINVAL; tiled configurations the sets do not allow (k > 7, too
+ * (8, 16, 32 or 64; blocks must be 0); tile_bits = 11, 12 or 13 runs the
+ * tiled kernel with tiles of 2^tile_bits vertices, group lanes per chunk (4,
+ * 8 or 16) and blocks 16-byte entry blocks per lane and step (2 or 4; 0 = the
+ * default rule).  Any other combination is MM_EINVAL; tiled configurations the sets do not allow (k > 7, too
  * many tiles) are MM_EUNSUPPORTED.  The update is the same for every
  * configuration up to the order of FP32 summation. */
 mm_status mm_sweep_cfg(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
                        double scale, const float* xy_in, const float* F, double alpha, double q,
-                       float* xy_out, double* delta, int32_t tile_bits, int32_t group);
+                       float* xy_out, double* delta, int32_t tile_bits, int32_t group,
+                       int32_t blocks);
 
 /* One coarsening step (Section 3.1): size-constrained label propagation with
  * bound U at hierarchy level level_h, then contraction.  cluster (device, n)

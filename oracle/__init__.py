@@ -360,7 +360,8 @@ class Params:
     """Layout parameters; defaults are the paper's configuration.
 
     k: hop radius of the stress set (1 = edges only, the paper's default model).
-    theta < 0 selects the exact all-pairs far field, theta >= 0 Barnes-Hut.
+    theta < 0 selects the exact all-pairs far field, theta >= 0 Barnes-Hut;
+    levels with at most exact_below vertices use the exact far field either way.
     """
 
     k: int = 1
@@ -381,6 +382,8 @@ class Params:
     coarse_dist_scale: float = 1.0
     seed: int = 1
     mlp: np.ndarray | None = None  # far-field correction weights (q = 0, theta >= 0)
+    exact_below: int = 0
+
 
 
 def schedule(alpha0, alpha_decay, alpha_min):
@@ -436,7 +439,7 @@ def hierarchy(g0: Level, p: Params):
 
 
 def far_field(x, p: Params):
-    if p.theta < 0:
+    if p.theta < 0 or x.shape[0] <= p.exact_below:
         return farfield_exact(x, p.q)
     if p.mlp is not None:
         return barnes_hut_learned(x, p.theta, p.mlp)

@@ -43,7 +43,7 @@ class MMParams(C.Structure):
                 ("max_levels", C.c_int32), ("coarsest_n", C.c_int32), ("b", C.c_double),
                 ("f", C.c_double), ("lp_rounds", C.c_int32), ("coarse_dist_scale", C.c_double),
                 ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p),
-                ("use_graphs", C.c_int32), ("autotune", C.c_int32)]
+                ("use_graphs", C.c_int32), ("autotune", C.c_int32), ("exact_below", C.c_int32)]
 
 
 class MMStats(C.Structure):
@@ -60,7 +60,8 @@ class MMStats(C.Structure):
                 ("t_farfield_ms", C.c_double), ("t_sweep_ms", C.c_double),
                 ("t_other_ms", C.c_double), ("vertex_updates", C.c_int64),
                 ("finest_updates", C.c_int64), ("level_tile_bits", C.c_int32 * MAX_LEVELS),
-                ("level_group", C.c_int32 * MAX_LEVELS), ("t_tune_ms", C.c_double)]
+                ("level_group", C.c_int32 * MAX_LEVELS), ("t_tune_ms", C.c_double),
+                ("level_blocks", C.c_int32 * MAX_LEVELS)]
 
     def to_dict(self) -> dict:
         L = self.levels
@@ -72,7 +73,8 @@ class MMStats(C.Structure):
                  "final_iters": self.level_final_iters[i], "cap_hit": self.level_cap_hit[i],
                  "delta": self.level_delta[i], "sweep_ms": self.level_sweep_ms[i],
                  "far_ms": self.level_far_ms[i], "khop_ms": self.level_khop_ms[i],
-                 "tile_bits": self.level_tile_bits[i], "group": self.level_group[i]}
+                 "tile_bits": self.level_tile_bits[i], "group": self.level_group[i],
+                 "blocks": self.level_blocks[i]}
                 for i in range(L)],
             "t_total_ms": self.t_total_ms, "t_coarsen_ms": self.t_coarsen_ms,
             "t_khop_ms": self.t_khop_ms, "t_farfield_ms": self.t_farfield_ms,
@@ -91,6 +93,7 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
            "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg"]
 
+TUNE_FIELDS = 7  # coarse?, n, sum |S|, k, tile bits, lanes, blocks per step
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
 
 _lib = None
@@ -119,7 +122,7 @@ def lib():
         "mm_repulsion": [vp, i32, vp, f64, f64, vp, vp, vp, vp, vp],
         "mm_sweep": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp],
         "mm_sweep_ex": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32],
-        "mm_sweep_cfg": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32, i32],
+        "mm_sweep_cfg": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32, i32, i32],
         "mm_coarsen": [vp, P(MMGraph), f64, i32, u64, i32, vp, P(vp), vp, vp],
         "mm_coarse_graph": [vp, P(MMGraph)],
         "mm_coarse_export": [vp, vp, vp, vp, vp, vp, i32],
@@ -191,6 +194,7 @@ class Params:
     mlp_weights: object = None  # float32 device tensor of MLP_PARAMS (learned far field)
     use_graphs: int = 1  # replay small levels' iterations from HIP graphs
     autotune: int = 0  # time each level's sweep configurations once per level shape
+    exact_below: int = 0  # levels with <= this many vertices use the exact far field
 
     def to_c(self) -> MMParams:
         p = MMParams()
@@ -243,17 +247,17 @@ class Context:
         _check(lib().mm_sync(self.h))
 
     def tune_export(self):
-        """The autotuner's choices: int64 array (records, 6) of
-        (coarse?, n, sum |S|, k, tile bits (0 = row kernel), lanes)."""
+        """The autotuner's choices: int64 array (records, 7) of
+        (coarse?, n, sum |S|, k, tile bits (0 = row kernel), lanes, blocks)."""
         cnt = C.c_int32(0)
         _check(lib().mm_tune_export(self.h, None, 0, C.byref(cnt)))
-        recs = np.zeros((max(cnt.value, 1), 6), np.int64)
+        recs = np.zeros((max(cnt.value, 1), TUNE_FIELDS), np.int64)
         _check(lib().mm_tune_export(self.h, recs.ctypes.data_as(C.POINTER(C.c_int64)), cnt.value,
                                     C.byref(cnt)))
         return recs[: cnt.value]
 
     def tune_import(self, recs):
-        recs = np.ascontiguousarray(recs, dtype=np.int64).reshape(-1, 6)
+        recs = np.ascontiguousarray(recs, dtype=np.int64).reshape(-1, TUNE_FIELDS)
         _check(lib().mm_tune_import(self.h, recs.ctypes.data_as(C.POINTER(C.c_int64)),
                                     recs.shape[0]))
 
@@ -475,7 +479,7 @@ def sweep(ctx: Context, kh: KHop, xy, F, alpha: float, q: float = 0.0, level: in
           node_w=None, scale: float = 1.0, mode: int = SWEEP_ROWS, config=None):
     """One Jacobi iteration of Eq. 2; returns (xy_out, (|x'-x|^2, |x|^2)).
     mode: SWEEP_ROWS (row-gather kernel), SWEEP_TILED (LDS-tiled), SWEEP_AUTO.
-    config = (tile_bits, lanes) forces a configuration instead (mm_sweep_cfg)."""
+    config = (tile_bits, lanes[, blocks]) forces a configuration instead (mm_sweep_cfg)."""
     t = ctx.torch
     xy = ctx._dev(xy, t.float32)
     F = ctx._dev(F, t.float32)
@@ -486,9 +490,10 @@ def sweep(ctx: Context, kh: KHop, xy, F, alpha: float, q: float = 0.0, level: in
         _check(lib().mm_sweep_ex(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha, q,
                                  _ptr(out), d.ctypes.data_as(C.c_void_p), mode))
     else:
+        blocks = int(config[2]) if len(config) > 2 else 0
         _check(lib().mm_sweep_cfg(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha,
                                   q, _ptr(out), d.ctypes.data_as(C.c_void_p), int(config[0]),
-                                  int(config[1])))
+                                  int(config[1]), blocks))
     return out, (float(d[0]), float(d[1]))
 
 

@@ -36,6 +36,8 @@ struct BHWork {
   SortWork sort;
   // learned far field: per-node moments and cell records, sample offsets
   DevBuf mom, cell, ndepth, scount, soff;
+  // exact far field: per-slab partial sums
+  DevBuf expart;
 };
 
 template <typename T>
@@ -51,14 +53,16 @@ hipError_t ensure(DevBuf& b, size_t count, hipStream_t s) {
 hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_out,
                          hipStream_t s, const BHSeg* seg = nullptr);
 
-// Adds m * r_q for the offset (dx, dy); coincident points add nothing.
+// Adds m * r_q for the offset (dx, dy); coincident points add nothing.  The
+// fused forms are written out so that every kernel using this term rounds it
+// the same way, whatever the compiler's contraction choices.
 __device__ inline bool rq_add(float dx, float dy, float q, float m, float& fx, float& fy) {
-  float d2 = dx * dx + dy * dy;
+  const float d2 = fmaf(dx, dx, dy * dy);
   if (d2 > 0.f) {
     float f = (q == 0.f) ? __builtin_amdgcn_rcpf(d2) : powf(d2, -0.5f * (q + 2.f));
     f *= m;
-    fx += dx * f;
-    fy += dy * f;
+    fx = fmaf(dx, f, fx);
+    fy = fmaf(dy, f, fy);
     return true;
   }
   return false;

@@ -21,10 +21,12 @@
 #include "mulment.h"
 #include "kernels.hpp"
 
-// Levels up to this many vertices replay their iterations from HIP graphs
-// (their time is dominated by launches; the buffers of such levels keep the
-// single-launch scan paths, so no allocation happens inside a capture).
+// Batch levels up to this many vertices replay their iterations from HIP
+// graphs (their time is dominated by launches).
 constexpr int32_t kGraphMaxN = 1 << 18;
+// Single-graph levels replay far field and sweep from two graphs above this
+// many vertices, from one graph at or below it.
+constexpr int32_t kSplitMinN = 1 << 16;
 
 struct mm_context {
   int device = 0;
@@ -36,7 +38,7 @@ struct mm_context {
   float* alpha_dev = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // autotuner: sweep configuration per level shape (coarse?, n, sum |S|, k)
-  struct TuneChoice { int32_t tbits, group; };  // tbits 0: row kernel
+  struct TuneChoice { int32_t tbits, group, nb; };  // tbits 0: row kernel (nb 0)
   std::map<std::tuple<int, int32_t, int64_t, int32_t>, TuneChoice> tune;
 };
 struct mm_khop {
@@ -131,6 +133,7 @@ mm_status validate_params(const mm_params* p) {
   if (!(p->b > 1) || !(p->f > 0)) return fail(MM_EINVAL, "b > 1 and f > 0 required");
   if (p->lp_rounds < 0) return fail(MM_EINVAL, "lp_rounds < 0");
   if (!(p->coarse_dist_scale > 0)) return fail(MM_EINVAL, "coarse_dist_scale must be > 0");
+  if (p->exact_below < 0) return fail(MM_EINVAL, "exact_below must be >= 0");
   if (p->mlp_weights && (p->theta < 0 || p->q != 0.0))
     return fail(MM_EUNSUPPORTED, "the learned far field needs theta >= 0 and q == 0");
   return MM_OK;
@@ -169,7 +172,8 @@ hipError_t time_variant(mm_context* ctx, hipStream_t s, int reps, F&& launch, fl
 
 // Autotuner of one level's sweep: every eligible configuration -- the row
 // kernel with 8/16/32/64 lanes per row, the tiled kernel with tiles of 2^11,
-// 2^12, 2^13 vertices and 4/8/16 lanes per chunk -- is run on the level's own
+// 2^12, 2^13 vertices, 4/8/16 lanes per chunk and 2/4 blocks per lane and
+// step -- is run on the level's own
 // sets and coordinates (far field zero, alpha 1, output to scratch) and the
 // fastest is kept.  Row-kernel candidates are skipped on levels whose sets are
 // too large for that kernel to win (over 2^30 entries).
@@ -179,7 +183,7 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
   const int32_t nl = kh.n;
   HIPCHK(hipMemsetAsync(F, 0, sizeof(float) * 2 * (size_t)nl, s));
   float best = INFINITY;
-  mm_context::TuneChoice bc{0, mm::row_group(kh)};
+  mm_context::TuneChoice bc{0, mm::row_group(kh), 0};
   const int reps = kh.total > (1ll << 28) ? 1 : 3;
   if (kh.total <= (1ll << 30)) {
     mm::DevBuf part;
@@ -189,7 +193,7 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
         return mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa, F, 1.0, p->q, xb, d2, s, nullptr,
                          nullptr, nullptr, &part, G);
       }, &ms));
-      if (ms < best) { best = ms; bc = {0, G}; }
+      if (ms < best) { best = ms; bc = {0, G, 0}; }
     }
   }
   mm::DevBuf rho;
@@ -205,12 +209,14 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
     HIPCHK(mm::tiled_build(kh, tb, 0.0, &ts, s));
     if (!ts.built) continue;
     for (int32_t G : {4, 8, 16}) {
-      float ms = 0;
-      HIPCHK(time_variant(ctx, s, reps, [&]() {
-        return mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa, F, 1.0,
-                               p->q, xb, d2, s, nullptr, G);
-      }, &ms));
-      if (ms < best) { best = ms; bc = {tb, G}; }
+      for (int32_t NB : {2, 4}) {
+        float ms = 0;
+        HIPCHK(time_variant(ctx, s, reps, [&]() {
+          return mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa, F,
+                                 1.0, p->q, xb, d2, s, nullptr, G, NB);
+        }, &ms));
+        if (ms < best) { best = ms; bc = {tb, G, NB}; }
+      }
     }
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -218,12 +224,13 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
   return MM_OK;
 }
 
-// One sweep through the C-ABI: mode as mm_sweep_ex; tbits/group > 0 force the
-// tile size and lanes (a tile-major copy of another tile size is built for
-// the call and dropped).
+// One sweep through the C-ABI: mode as mm_sweep_ex; tbits/group/nb > 0 force
+// the tile size, lanes and blocks per step (a tile-major copy of another tile
+// size is built for the call and dropped).
 mm_status sweep_common(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
                        double scale, const float* xy_in, const float* F, double alpha, double q,
-                       float* xy_out, double* delta, int32_t mode, int32_t tbits, int32_t group) {
+                       float* xy_out, double* delta, int32_t mode, int32_t tbits, int32_t group,
+                       int32_t nb) {
   try {
     if (!ctx || !kh || !xy_in || !F || !xy_out) return fail(MM_EINVAL, "NULL argument");
     if (xy_in == xy_out) return fail(MM_EINVAL, "Jacobi update needs separate in/out buffers");
@@ -261,7 +268,7 @@ mm_status sweep_common(mm_context* ctx, mm_khop* kh, int32_t level, const int32_
       HIPCHK(rho.alloc(sizeof(float) * (size_t)kh->kh.n, s));
       HIPCHK(mm::compute_rho(kh->kh, sqrtc, scale, rho.as<float>(), s));
       HIPCHK(mm::sweep_tiled(*ts, level, sqrtc, scale, rho.as<float>(), xy_in, F, alpha, q,
-                             xy_out, d2.as<double>(), s, nullptr, group));
+                             xy_out, d2.as<double>(), s, nullptr, group, nb));
     } else {
       mm::DevBuf part;
       HIPCHK(mm::sweep(kh->kh, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2.as<double>(), s,
@@ -301,6 +308,7 @@ mm_status mm_tune_export(mm_context* ctx, int64_t* recs, int32_t cap, int32_t* c
       r[3] = std::get<3>(key);
       r[4] = c.tbits;
       r[5] = c.group;
+      r[6] = c.nb;
     }
     ++i;
   }
@@ -316,14 +324,15 @@ mm_status mm_tune_import(mm_context* ctx, const int64_t* recs, int32_t count) {
     const bool tb_ok = r[4] == 0 || (r[4] >= 11 && r[4] <= 13);
     const bool g_ok = r[5] >= 4 && r[5] <= 64 && (r[5] & (r[5] - 1)) == 0 &&
                       (r[4] == 0 ? r[5] >= 8 : r[5] <= 16);
-    if (!tb_ok || !g_ok || (r[0] != 0 && r[0] != 1) || r[1] < 0 || r[1] > INT32_MAX || r[2] < 0 ||
+    const bool nb_ok = r[4] == 0 ? r[6] == 0 : (r[6] == 0 || r[6] == 2 || r[6] == 4);
+    if (!tb_ok || !g_ok || !nb_ok || (r[0] != 0 && r[0] != 1) || r[1] < 0 || r[1] > INT32_MAX || r[2] < 0 ||
         r[3] < 1 || r[3] > INT32_MAX)
       return fail(MM_EINVAL, "tune record %d is invalid", i);
   }
   for (int32_t i = 0; i < count; ++i) {
     const int64_t* r = recs + (size_t)i * MM_TUNE_FIELDS;
     ctx->tune[std::make_tuple((int)r[0], (int32_t)r[1], r[2], (int32_t)r[3])] =
-        mm_context::TuneChoice{(int32_t)r[4], (int32_t)r[5]};
+        mm_context::TuneChoice{(int32_t)r[4], (int32_t)r[5], (int32_t)r[6]};
   }
   return MM_OK;
 }
@@ -352,6 +361,7 @@ mm_status mm_params_default(mm_params* p) {
   p->mlp_weights = nullptr;
   p->use_graphs = 1;
   p->autotune = 0;
+  p->exact_below = 0;
   return MM_OK;
 }
 
@@ -464,7 +474,7 @@ mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, do
     if (std::isnan(theta) || std::isnan(q)) return fail(MM_EINVAL, "theta/q NaN");
     DeviceGuard dg(ctx->device);
     if (theta < 0) {
-      HIPCHK(mm::farfield_exact(n, xy, q, F, ctx->stream));
+      HIPCHK(mm::farfield_exact(ctx->bh, n, xy, q, F, ctx->stream));
       if (counters) { counters[0] = 0; counters[1] = (int64_t)n * (n - 1); counters[2] = 0; counters[3] = 0; }
     } else {
       mm::FarStats st{};
@@ -570,17 +580,23 @@ mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t
                       double scale, const float* xy_in, const float* F, double alpha, double q,
                       float* xy_out, double* delta, int32_t mode) {
   if (mode < MM_SWEEP_AUTO || mode > MM_SWEEP_TILED) return fail(MM_EINVAL, "bad sweep mode");
-  return sweep_common(ctx, kh, level, node_w, scale, xy_in, F, alpha, q, xy_out, delta, mode, 0, 0);
+  return sweep_common(ctx, kh, level, node_w, scale, xy_in, F, alpha, q, xy_out, delta, mode, 0, 0,
+                      0);
 }
 
 mm_status mm_sweep_cfg(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t* node_w,
                        double scale, const float* xy_in, const float* F, double alpha, double q,
-                       float* xy_out, double* delta, int32_t tile_bits, int32_t group) {
-  const bool rows_ok = tile_bits == 0 && (group == 8 || group == 16 || group == 32 || group == 64);
-  const bool tiled_ok = tile_bits >= 11 && tile_bits <= 13 && (group == 4 || group == 8 || group == 16);
-  if (!rows_ok && !tiled_ok) return fail(MM_EINVAL, "bad sweep configuration (%d, %d)", tile_bits, group);
+                       float* xy_out, double* delta, int32_t tile_bits, int32_t group,
+                       int32_t blocks) {
+  const bool rows_ok = tile_bits == 0 && blocks == 0 &&
+                       (group == 8 || group == 16 || group == 32 || group == 64);
+  const bool tiled_ok = tile_bits >= 11 && tile_bits <= 13 &&
+                        (group == 4 || group == 8 || group == 16) &&
+                        (blocks == 0 || blocks == 2 || blocks == 4);
+  if (!rows_ok && !tiled_ok)
+    return fail(MM_EINVAL, "bad sweep configuration (%d, %d, %d)", tile_bits, group, blocks);
   return sweep_common(ctx, kh, level, node_w, scale, xy_in, F, alpha, q, xy_out, delta,
-                      tile_bits ? MM_SWEEP_TILED : MM_SWEEP_ROWS, tile_bits, group);
+                      tile_bits ? MM_SWEEP_TILED : MM_SWEEP_ROWS, tile_bits, group, blocks);
 }
 
 mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
@@ -890,6 +906,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       // vertex), so smaller tiles keep two or more work-groups per CU
       int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 18) ? 12 : 11);
       int32_t group_lvl = 0;  // 0: the kernels' own rule
+      int32_t nb_lvl = 0;
       double min_avg = 8.0;
       if (p->autotune) {
         const auto key = std::make_tuple(lvl > 0 ? 1 : 0, nl, kh.total, p->k);
@@ -904,6 +921,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         }
         tbits_lvl = it->second.tbits;
         group_lvl = it->second.group;
+        nb_lvl = it->second.nb;
         min_avg = 0.0;
       }
       if (tbits_lvl > 0 && mm::tiled_eligible(kh, tbits_lvl)) {
@@ -918,81 +936,93 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       int32_t iters = 0, final_iters = 0, cap_hit = 0;
       double delta = 0;
       mm::DevBuf sweep_part;
+      // far field of xin: exact all-pairs when theta < 0 or the level has at
+      // most exact_below vertices, else Barnes-Hut (with the learned
+      // correction when weights are given)
+      const bool exact_lvl = p->theta < 0 || nl <= p->exact_below;
+      auto far = [&](const float* xin) -> hipError_t {
+        if (exact_lvl) return mm::farfield_exact(ctx->bh, nl, xin, p->q, F.as<float>(), s);
+        if (p->mlp_weights)
+          return mm::farfield_learned(ctx->bh, nl, xin, p->theta, p->mlp_weights, F.as<float>(), s);
+        return mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
+                               nullptr, nullptr, 0, nullptr, s);
+      };
       // one iteration: far field of xin, sweep into xout (alpha from device
       // memory when replayed), relative-change partials to the pinned buffer
       auto enqueue = [&](double alpha, const float* xin, float* xout, const float* adev) -> hipError_t {
-        if (p->theta < 0) {
-          MM_TRY(mm::farfield_exact(nl, xin, p->q, F.as<float>(), s));
-        } else if (p->mlp_weights) {
-          MM_TRY(mm::farfield_learned(ctx->bh, nl, xin, p->theta, p->mlp_weights, F.as<float>(), s));
-        } else {
-          MM_TRY(mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
-                                 nullptr, nullptr, 0, nullptr, s));
-        }
+        MM_TRY(far(xin));
         MM_TRY(hipEventRecord(ctx->ev[1], s));
         if (ts.built)
           MM_TRY(mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
                                  F.as<float>(), alpha, p->q, xout, d2.as<double>(), s, adev,
-                                 group_lvl));
+                                 group_lvl, nb_lvl));
         else
           MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), alpha, p->q,
                            xout, d2.as<double>(), s, nullptr, nullptr, adev, &sweep_part,
                            group_lvl));
         return hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
       };
-      // Small levels are launch-bound: after one direct iteration (which sizes
-      // every buffer), the iteration is captured once per direction (A -> B,
-      // B -> A) and replayed.  Event records are not captured; a replay's time
-      // is split between far field and sweep in the ratio of the direct one.
+      // After one direct iteration (which sizes every buffer), the iteration
+      // is captured once per direction (A -> B, B -> A) and replayed.  Levels
+      // above kSplitMinN vertices keep the far field and the sweep in two
+      // graphs with event records between them (both parts stay timed by HIP
+      // events); smaller levels, where a second launch costs more than the
+      // work, use one graph and split its time in the ratio of the direct
+      // iteration.
       float* bufA = xa.as<float>();
       float* bufB = xb.as<float>();
       int parity = 0;  // 0: the current layout is in bufA
-      const bool want_graph = p->use_graphs && nl <= kGraphMaxN;
-      hipGraphExec_t gx[2] = {nullptr, nullptr};
+      const bool want_graph = p->use_graphs != 0;
+      const bool split_graphs = nl > kSplitMinN;
+      hipGraphExec_t gx[4] = {nullptr, nullptr, nullptr, nullptr};  // far A, far B, sweep A, sweep B
       bool graph_failed = false;
       double split = 0.5;
       struct GraphGuard {
         hipGraphExec_t* g;
-        ~GraphGuard() { for (int i = 0; i < 2; ++i) if (g[i]) (void)hipGraphExecDestroy(g[i]); }
+        ~GraphGuard() { for (int i = 0; i < 4; ++i) if (g[i]) (void)hipGraphExecDestroy(g[i]); }
       } gguard{gx};
+      auto capture_one = [&](hipGraphExec_t* out, auto&& body) -> bool {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+        const hipError_t e = body();
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(s, &gr);
+        if (e != hipSuccess || e2 != hipSuccess || !gr) {
+          if (gr) (void)hipGraphDestroy(gr);
+          (void)hipGetLastError();
+          return false;
+        }
+        const hipError_t e3 = hipGraphInstantiate(out, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e3 != hipSuccess) { *out = nullptr; (void)hipGetLastError(); return false; }
+        return true;
+      };
+      auto sweep_part_of = [&](const float* xin, float* xout) -> hipError_t {
+        MM_TRY(hipMemcpyAsync(ctx->alpha_dev, ctx->alpha_pinned, sizeof(float),
+                              hipMemcpyHostToDevice, s));
+        if (ts.built)
+          MM_TRY(mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
+                                 F.as<float>(), 0.0, p->q, xout, d2.as<double>(), s,
+                                 ctx->alpha_dev, group_lvl, nb_lvl));
+        else
+          MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
+                           xout, d2.as<double>(), s, nullptr, nullptr, ctx->alpha_dev,
+                           &sweep_part, group_lvl));
+        return hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+      };
       auto capture = [&]() -> bool {
         for (int d = 0; d < 2; ++d) {
           const float* xin = d ? bufB : bufA;
           float* xout = d ? bufA : bufB;
-          if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
-          hipError_t e = hipMemcpyAsync(ctx->alpha_dev, ctx->alpha_pinned, sizeof(float),
-                                        hipMemcpyHostToDevice, s);
-          if (e == hipSuccess) {
-            // no event records inside the capture
-            if (p->theta < 0) e = mm::farfield_exact(nl, xin, p->q, F.as<float>(), s);
-            else if (p->mlp_weights)
-              e = mm::farfield_learned(ctx->bh, nl, xin, p->theta, p->mlp_weights, F.as<float>(), s);
-            else
-              e = mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
-                                  nullptr, nullptr, 0, nullptr, s);
+          if (split_graphs) {
+            if (!capture_one(&gx[d], [&]() { return far(xin); })) return false;
+            if (!capture_one(&gx[2 + d], [&]() { return sweep_part_of(xin, xout); })) return false;
+          } else {
+            if (!capture_one(&gx[d], [&]() -> hipError_t {
+                  MM_TRY(far(xin));
+                  return sweep_part_of(xin, xout);
+                }))
+              return false;
           }
-          if (e == hipSuccess) {
-            if (ts.built)
-              e = mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xin,
-                                  F.as<float>(), 0.0, p->q, xout, d2.as<double>(), s, ctx->alpha_dev,
-                                  group_lvl);
-            else
-              e = mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
-                            xout, d2.as<double>(), s, nullptr, nullptr, ctx->alpha_dev, &sweep_part,
-                            group_lvl);
-          }
-          if (e == hipSuccess)
-            e = hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-          hipGraph_t gr = nullptr;
-          const hipError_t e2 = hipStreamEndCapture(s, &gr);
-          if (e != hipSuccess || e2 != hipSuccess || !gr) {
-            if (gr) (void)hipGraphDestroy(gr);
-            (void)hipGetLastError();
-            return false;
-          }
-          const hipError_t e3 = hipGraphInstantiate(&gx[d], gr, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(gr);
-          if (e3 != hipSuccess) { gx[d] = nullptr; (void)hipGetLastError(); return false; }
         }
         return true;
       };
@@ -1006,30 +1036,35 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
           }
         }
         HIPCHK(hipEventRecord(ctx->ev[0], s));
-        if (gx[parity]) {
+        float a = 0, b = 0;
+        if (gx[parity] && !split_graphs) {
           *ctx->alpha_pinned = (float)alpha;
           HIPCHK(hipGraphLaunch(gx[parity], s));
           HIPCHK(hipEventRecord(ctx->ev[2], s));
           HIPCHK(hipStreamSynchronize(s));
           float ab = 0;
           HIPCHK(hipEventElapsedTime(&ab, ctx->ev[0], ctx->ev[2]));
-          t_far += ab * split;
-          lvl_far += ab * split;
-          t_sweep += ab * (1.0 - split);
-          lvl_sweep += ab * (1.0 - split);
+          a = (float)(ab * split);
+          b = (float)(ab * (1.0 - split));
         } else {
-          HIPCHK(enqueue(alpha, xin, xout, nullptr));
+          if (gx[parity]) {
+            *ctx->alpha_pinned = (float)alpha;
+            HIPCHK(hipGraphLaunch(gx[parity], s));
+            HIPCHK(hipEventRecord(ctx->ev[1], s));
+            HIPCHK(hipGraphLaunch(gx[2 + parity], s));
+          } else {
+            HIPCHK(enqueue(alpha, xin, xout, nullptr));
+          }
           HIPCHK(hipEventRecord(ctx->ev[2], s));
           HIPCHK(hipStreamSynchronize(s));
-          float a = 0, b = 0;
           HIPCHK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
           HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
-          if (a + b > 0) split = a / (a + b);
-          t_far += a;
-          t_sweep += b;
-          lvl_far += a;
-          lvl_sweep += b;
+          if (!gx[parity] && a + b > 0) split = a / (a + b);
         }
+        t_far += a;
+        t_sweep += b;
+        lvl_far += a;
+        lvl_sweep += b;
         delta = ctx->pinned[1] > 0 ? std::sqrt(ctx->pinned[0] / ctx->pinned[1]) : INFINITY;
         if (!std::isfinite(delta)) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
         parity ^= 1;
@@ -1063,6 +1098,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         st.level_far_ms[lvl] = lvl_far;
         st.level_khop_ms[lvl] = khop_ms;
         st.level_tile_bits[lvl] = ts.built ? ts.tbits : 0;
+        st.level_blocks[lvl] = ts.built ? (nb_lvl > 0 ? nb_lvl : mm::tiled_blocks(ts)) : 0;
         st.level_group[lvl] = group_lvl > 0 ? group_lvl : (ts.built ? mm::tiled_group(ts)
                                                                     : mm::row_group(kh));
       }
@@ -1124,6 +1160,7 @@ mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, 
     if (!ctx || !g || !out_xy || !graph_off) return fail(MM_EINVAL, "NULL argument");
     STCHK(validate_params(p));
     if (p->theta < 0) return fail(MM_EUNSUPPORTED, "batches use the Barnes-Hut far field (theta >= 0)");
+    if (p->exact_below != 0) return fail(MM_EUNSUPPORTED, "batches use Barnes-Hut on every level (exact_below must be 0)");
     if (p->mlp_weights) return fail(MM_EUNSUPPORTED, "batches use the plain Barnes-Hut far field");
     if (G < 1) return fail(MM_EINVAL, "G < 1");
     if (g->mem != MM_HOST && g->mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");

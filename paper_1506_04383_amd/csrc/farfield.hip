@@ -230,48 +230,82 @@ __device__ inline int lcp48(uint64_t a, uint64_t b) {
 
 // Emit nodes: leaves at bucket starts, internal nodes at owner pairs.
 // key = first << 5 | depth (leaves use depth code 31); val = temp index.
+// Node keys at fixed slots: the leaf of the run of equal codes starting at i
+// in slot 2i, the internal node owned by the pair (i, i+1) in slot 2i+1;
+// slots without a node keep the all-ones key from k_fill_keys and sort last.
+// Range ends are found by galloping from i (steps 1, 2, 4, ... then a binary
+// search inside the last step), so a node spanning m points costs O(log m)
+// loads.  The node count is added once per wave.
+//
+// first index j in [lo, hi) at or after `from` whose key exceeds `key` under
+// the prefix shift sh (codes are sorted; the answer is > from)
+__device__ inline int32_t gallop_up(const uint64_t* __restrict__ codes, int32_t from, int32_t n,
+                                    uint64_t key, int sh) {
+  int32_t lo = from + 1, step = 1, hi = n;
+  while (lo < n) {
+    const int32_t probe = min(n - 1, from + step);
+    if ((codes[probe] >> sh) > key) { hi = probe; break; }
+    lo = probe + 1;
+    step <<= 1;
+  }
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((codes[mid] >> sh) <= key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+// first index j <= from with (codes[j] >> sh) == key (codes[from] >> sh == key)
+__device__ inline int32_t gallop_down(const uint64_t* __restrict__ codes, int32_t from,
+                                      uint64_t key, int sh) {
+  int32_t hi = from, step = 1, lo = 0;
+  while (hi > 0) {
+    const int32_t probe = max(0, from - step);
+    if ((codes[probe] >> sh) < key) { lo = probe + 1; break; }
+    hi = probe;
+    step <<= 1;
+  }
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((codes[mid] >> sh) < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
                              uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
                              int4* __restrict__ tmp, int32_t* __restrict__ counter) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t ci = codes[i];
-  if (i == 0 || codes[i - 1] != ci) {
-    // leaf: run of equal codes starting at i
-    int32_t lo = i, hi = n;  // first index with code > ci
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (codes[mid] <= ci) lo = mid + 1; else hi = mid;
-    }
-    int32_t slot = atomicAdd(counter, 1);
-    keys[slot] = ((uint64_t)i << 5) | 31u;
-    vals[slot] = slot;
-    tmp[slot] = make_int4(i, lo - 1, 24, 1);
-  }
-  if (i + 1 < n && codes[i + 1] != ci && (codes[i + 1] >> 48) == (ci >> 48)) {
-    const int t = lcp48(ci, codes[i + 1]) >> 1;
-    const int sh = 48 - 2 * t;
-    const uint64_t pre = ci >> sh;
-    // a: first index with the same 2t-bit prefix
-    int32_t lo = 0, hi = i;
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if ((codes[mid] >> sh) < pre) lo = mid + 1; else hi = mid;
-    }
-    const int32_t a = lo;
-    // owner iff points a..i lie in the same child (no split of depth t left of i)
-    if ((codes[a] >> (sh - 2)) == (ci >> (sh - 2))) {
-      lo = i + 1; hi = n;
-      while (lo < hi) {
-        int32_t mid = (lo + hi) >> 1;
-        if ((codes[mid] >> sh) <= pre) lo = mid + 1; else hi = mid;
-      }
-      int32_t slot = atomicAdd(counter, 1);
-      keys[slot] = ((uint64_t)a << 5) | (uint32_t)t;
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t made = 0;
+  if (i < n) {
+    const uint64_t ci = codes[i];
+    if (i == 0 || codes[i - 1] != ci) {
+      // leaf: run of equal codes starting at i
+      const int32_t end = gallop_up(codes, i, n, ci, 0);
+      const int32_t slot = 2 * i;
+      keys[slot] = ((uint64_t)i << 5) | 31u;
       vals[slot] = slot;
-      tmp[slot] = make_int4(a, lo - 1, t, 0);
+      tmp[slot] = make_int4(i, end - 1, 24, 1);
+      ++made;
+    }
+    if (i + 1 < n && codes[i + 1] != ci && (codes[i + 1] >> 48) == (ci >> 48)) {
+      const int t = lcp48(ci, codes[i + 1]) >> 1;
+      const int sh = 48 - 2 * t;
+      const uint64_t pre = ci >> sh;
+      // a: first index with the same 2t-bit prefix
+      const int32_t a = gallop_down(codes, i, pre, sh);
+      // owner iff points a..i lie in the same child (no split of depth t left of i)
+      if ((codes[a] >> (sh - 2)) == (ci >> (sh - 2))) {
+        const int32_t end = gallop_up(codes, i, n, pre, sh);
+        const int32_t slot = 2 * i + 1;
+        keys[slot] = ((uint64_t)a << 5) | (uint32_t)t;
+        vals[slot] = slot;
+        tmp[slot] = make_int4(a, end - 1, t, 0);
+        ++made;
+      }
     }
   }
+  made = wave_sum(made);
+  if (lane_id() == 0 && made) atomicAdd(counter, made);
 }
 
 __global__ void k_first_at(const uint64_t* __restrict__ keys, const int32_t* __restrict__ Np,
@@ -508,7 +542,65 @@ __global__ __launch_bounds__(BHS_T) void k_bh_small(
 
 constexpr int TR_WAVES = 4;
 
+// Interactions of one lane's target (xt, yt; quantum cell (qx2i, qy2i)
+// doubled) with node nd at index p: leaf terms, or the opening test and the
+// cell term.  Returns true when the lane opens the node.
 template <bool STATS>
+__device__ inline bool visit_node(const BHNode& nd, int32_t i, float xt, float yt, int32_t qx2i,
+                                  int32_t qy2i, float q, double theta2,
+                                  const float* __restrict__ xsx, const float* __restrict__ xsy,
+                                  float& fx, float& fy, unsigned long long& acc,
+                                  unsigned long long& pairs) {
+  if (nd.meta >> 8) {
+    // leaf: exact terms for its points (a single point's coordinates are in
+    // the node record)
+    const int32_t cnt = (int32_t)nd.mass;
+    if (cnt == 1) {
+      if (nd.first != i) {
+        const bool added = rq_add(xt - (float)nd.cx, yt - (float)nd.cy, q, 1.f, fx, fy);
+        if (STATS && added) pairs++;
+      }
+    } else {
+      for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
+        const float sx = xsx[j], sy = xsy[j];
+        if (j != i) {
+          const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
+          if (STATS && added) pairs++;
+        }
+      }
+    }
+    return false;
+  }
+  // opening test in exact integers: offsets of u's quantum-cell centre from
+  // the cell centre (doubled); |d| < S on both axes <=> u in C; d4 < 2^52 and
+  // 4 S^2 are exact doubles, so theta^2 d4 > 4 S^2 rounds exactly as the same
+  // test written with 64-bit integers
+  const int depth = nd.meta & 0xff;
+  const int sh = 24 - depth;
+  const int32_t S = 1 << sh;
+  const int32_t dxi = qx2i - (int32_t)(2u * nd.ox + (uint32_t)S);
+  const int32_t dyi = qy2i - (int32_t)(2u * nd.oy + (uint32_t)S);
+  const bool contains = abs(dxi) < S && abs(dyi) < S;
+  const double dxd = (double)dxi, dyd = (double)dyi;
+  const double d4 = fma(dxd, dxd, dyd * dyd);
+  const bool accept = !contains && theta2 * d4 > (double)((int64_t)S * S * 4);
+  if (accept) {
+    rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, nd.mass, fx, fy);
+    if (STATS) acc++;
+    return false;
+  }
+  return true;
+}
+
+// One wavefront walks the pre-order node array once for 64 Morton-consecutive
+// targets; a lane takes part at node p when its own walk is at p (next == p).
+// One tree (no batch): the wave's next node is p + 1 when some lane opens p,
+// else skip(p) -- a lane that is not at p waits at a node after p's subtree
+// (its walk never entered that subtree), i.e. at or after skip(p).  Both
+// candidate records are loaded as soon as p's record is there, so their
+// latency overlaps p's work.  Batches (one tree per graph, per-lane root and
+// end) take the minimum of the lanes' next nodes instead.
+template <bool STATS, bool SEG>
 __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np, const float* __restrict__ xsx,
     const float* __restrict__ xsy, const uint2* __restrict__ ixy, const int32_t* __restrict__ order,
@@ -524,65 +616,43 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
   const uint2 qt = valid ? ixy[i] : make_uint2(0, 0);
   const int32_t qx2i = 2 * (int32_t)qt.x + 1, qy2i = 2 * (int32_t)qt.y + 1;
   float fx = 0.f, fy = 0.f;
-  // nodes of this lane's tree: [root, end) (a batch holds one tree per graph,
-  // graph g owning sorted points [goff[g], goff[g+1]))
-  int32_t root = 0, end = N;
-  if (goff && valid) {
-    const int32_t g = (int32_t)(scodes[i] >> 48);
-    root = first_at[goff[g]];
-    end = goff[g + 1] < n ? first_at[goff[g + 1]] : N;
-  }
-  int32_t next = valid ? root : 0x7fffffff;
   unsigned long long acc = 0, pairs = 0;
-  int32_t p = wave_min(next);
-  while (p < N) {
-    p = __builtin_amdgcn_readfirstlane(p);
-    const BHNode nd = nodes[p];
-    const bool act = (next == p);
-    const int depth = nd.meta & 0xff;
-    if (nd.meta >> 8) {
-      // leaf: exact terms for its points (a single point's coordinates are
-      // in the node record)
-      const int32_t cnt = (int32_t)nd.mass;
-      if (cnt == 1) {
-        if (act && nd.first != i) {
-          const bool added = rq_add(xt - (float)nd.cx, yt - (float)nd.cy, q, 1.f, fx, fy);
-          if (STATS && added) pairs++;
-        }
-      } else {
-        for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
-          const float sx = xsx[j], sy = xsy[j];
-          if (act && j != i) {
-            const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
-            if (STATS && added) pairs++;
-          }
-        }
-      }
-      if (act) next = nd.skip >= end ? 0x7fffffff : nd.skip;
-      p = wave_min(next);
-    } else {
+  if (!SEG) {
+    int32_t next = valid ? 0 : 0x7fffffff;
+    int32_t p = 0;
+    BHNode nd = nodes[0];
+    while (p < N) {
+      const BHNode na = nodes[min(p + 1, N - 1)];
+      const BHNode nb = nodes[min(nd.skip, N - 1)];
       bool opened = false;
-      if (act) {
-        // opening test in exact integers: offsets of u's quantum-cell centre
-        // from the cell centre (doubled); |d| < S on both axes <=> u in C;
-        // d4 < 2^52 and 4 S^2 are exact doubles, so theta^2 d4 > 4 S^2 rounds
-        // exactly as the same test written with 64-bit integers
-        const int sh = 24 - depth;
-        const int32_t S = 1 << sh;
-        const int32_t dxi = qx2i - (int32_t)(2u * nd.ox + (uint32_t)S);
-        const int32_t dyi = qy2i - (int32_t)(2u * nd.oy + (uint32_t)S);
-        const bool contains = abs(dxi) < S && abs(dyi) < S;
-        const double dxd = (double)dxi, dyd = (double)dyi;
-        const double d4 = fma(dxd, dxd, dyd * dyd);
-        const bool accept = !contains && theta2 * d4 > (double)((int64_t)S * S * 4);
-        if (accept) {
-          rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, nd.mass, fx, fy);
-          if (STATS) acc++;
-          next = nd.skip >= end ? 0x7fffffff : nd.skip;
-        } else {
-          next = p + 1;
-          opened = true;
-        }
+      if (next == p) {
+        opened = visit_node<STATS>(nd, i, xt, yt, qx2i, qy2i, q, theta2, xsx, xsy, fx, fy, acc,
+                                   pairs);
+        next = opened ? p + 1 : (nd.skip >= N ? 0x7fffffff : nd.skip);
+      }
+      const bool down = __any(opened);
+      p = down ? p + 1 : nd.skip;
+      nd = down ? na : nb;
+    }
+  } else {
+    // nodes of this lane's tree: [root, end) (graph g owns sorted points
+    // [goff[g], goff[g+1]))
+    int32_t root = 0, end = N;
+    if (valid) {
+      const int32_t g = (int32_t)(scodes[i] >> 48);
+      root = first_at[goff[g]];
+      end = goff[g + 1] < n ? first_at[goff[g + 1]] : N;
+    }
+    int32_t next = valid ? root : 0x7fffffff;
+    int32_t p = wave_min(next);
+    while (p < N) {
+      p = __builtin_amdgcn_readfirstlane(p);
+      const BHNode nd = nodes[p];
+      bool opened = false;
+      if (next == p) {
+        opened = visit_node<STATS>(nd, i, xt, yt, qx2i, qy2i, q, theta2, xsx, xsy, fx, fy, acc,
+                                   pairs);
+        next = opened ? p + 1 : (nd.skip >= end ? 0x7fffffff : nd.skip);
       }
       if (__any(opened)) p = p + 1;
       else p = wave_min(next);
@@ -597,32 +667,91 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
 }
 
 // ---- exact all-pairs
+// Grid (target blocks) x (source slabs): a lane owns one target, the slab's
+// sources are read at wave-uniform addresses (scalar loads, broadcast to the
+// lanes), and each slab writes its partial sums; k_exact_sum adds the slabs
+// of a target in slab order, so the result does not depend on timing.  With
+// q = 0 the pair term is (dx, dy) / d^2; a bias of 1e-30 in d^2 makes the
+// self pair and coincident points contribute exactly 0 (0 * 1e30) and leaves
+// every d^2 above 1e-23 unchanged, as the skip of d^2 = 0 does for q != 0.
 constexpr int EX_T = 256;
-__global__ __launch_bounds__(EX_T) void k_exact(const float2* __restrict__ xy, int32_t n, float q,
-                                                float2* __restrict__ F) {
-  __shared__ float2 tile[EX_T];
+constexpr int EX_BLOCKS = 2048;  // target blocks x slabs to aim for (8 waves per SIMD)
+
+template <bool Q0>
+__global__ __launch_bounds__(EX_T) void k_exact(const float2* __restrict__ xy, int32_t n,
+                                                int32_t L, float q, float2* __restrict__ out) {
   const int32_t u = blockIdx.x * EX_T + threadIdx.x;
   const float2 xu = u < n ? xy[u] : make_float2(0.f, 0.f);
+  const int32_t j0 = blockIdx.y * L;
+  const int32_t j1 = min(n, j0 + L);
   float fx = 0.f, fy = 0.f;
-  for (int32_t b = 0; b < n; b += EX_T) {
-    __syncthreads();
-    if (b + threadIdx.x < n) tile[threadIdx.x] = xy[b + threadIdx.x];
-    __syncthreads();
-    const int32_t m = min(EX_T, n - b);
-    for (int32_t j = 0; j < m; ++j) {
-      if (b + j == u) continue;
-      const float2 p = tile[j];
+  if (Q0) {
+    int32_t j = j0;
+    for (; j + 8 <= j1; j += 8) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float2 p = xy[j + t];
+        const float dx = xu.x - p.x, dy = xu.y - p.y;
+        const float f = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
+        fx = fmaf(dx, f, fx);
+        fy = fmaf(dy, f, fy);
+      }
+    }
+    for (; j < j1; ++j) {
+      const float2 p = xy[j];
+      const float dx = xu.x - p.x, dy = xu.y - p.y;
+      const float f = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
+      fx = fmaf(dx, f, fx);
+      fy = fmaf(dy, f, fy);
+    }
+  } else {
+    for (int32_t j = j0; j < j1; ++j) {
+      const float2 p = xy[j];
       rq_add(xu.x - p.x, xu.y - p.y, q, 1.f, fx, fy);
     }
   }
-  if (u < n) F[u] = make_float2(fx, fy);
+  if (u < n) out[(size_t)blockIdx.y * n + u] = make_float2(fx, fy);
+}
+
+__global__ void k_exact_sum(const float2* __restrict__ part, int32_t n, int32_t S,
+                            float2* __restrict__ F) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  float fx = 0.f, fy = 0.f;
+  for (int32_t s = 0; s < S; ++s) {
+    const float2 v = part[(size_t)s * n + u];
+    fx += v.x;
+    fy += v.y;
+  }
+  F[u] = make_float2(fx, fy);
 }
 
 }  // namespace
 
-hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStream_t s) {
-  k_exact<<<(n + EX_T - 1) / EX_T, EX_T, 0, s>>>((const float2*)xy, n, (float)q, (float2*)F);
-  return hipGetLastError();
+hipError_t farfield_exact(BHWork* w, int32_t n, const float* xy, double q, float* F,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int32_t tb = (n + EX_T - 1) / EX_T;
+  // slabs: enough blocks to fill the chip, at least 64 sources per slab
+  int32_t S = std::max(1, std::min((EX_BLOCKS + tb - 1) / tb, (n + 63) / 64));
+  const int32_t L = (n + S - 1) / S;
+  S = (n + L - 1) / L;
+  float2* out = (float2*)F;
+  if (S > 1) {
+    MM_TRY(ensure<float2>(w->expart, (size_t)S * n, s));
+    out = w->expart.as<float2>();
+  }
+  const dim3 grid(tb, S);
+  if (q == 0.0)
+    k_exact<true><<<grid, EX_T, 0, s>>>((const float2*)xy, n, L, (float)q, out);
+  else
+    k_exact<false><<<grid, EX_T, 0, s>>>((const float2*)xy, n, L, (float)q, out);
+  MM_TRY(hipGetLastError());
+  if (S > 1) {
+    k_exact_sum<<<(n + 255) / 256, 256, 0, s>>>(out, n, S, (float2*)F);
+    MM_TRY(hipGetLastError());
+  }
+  return hipSuccess;
 }
 
 hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_out,
@@ -717,16 +846,14 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
   if (count_stats) MM_TRY(hipMemsetAsync(w->statc.p, 0, 2 * sizeof(unsigned long long), s));
   const int32_t nw = (n + 63) / 64;
   const int32_t nblk = (nw + TR_WAVES - 1) / TR_WAVES;
-  if (count_stats)
-    k_traverse<true><<<nblk, 64 * TR_WAVES, 0, s>>>(
-        w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
-        w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F,
-        w->statc.as<unsigned long long>(), sc, go, w->first_at.as<int32_t>());
-  else
-    k_traverse<false><<<nblk, 64 * TR_WAVES, 0, s>>>(
-        w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),
-        w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F, nullptr, sc, go,
-        w->first_at.as<int32_t>());
+#define MM_TR(ST, SG)                                                                            \
+  k_traverse<ST, SG><<<nblk, 64 * TR_WAVES, 0, s>>>(                                               \
+      w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),       \
+      w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F,                              \
+      ST ? w->statc.as<unsigned long long>() : nullptr, sc, go, w->first_at.as<int32_t>())
+  if (count_stats) { if (seg) MM_TR(true, true); else MM_TR(true, false); }
+  else { if (seg) MM_TR(false, true); else MM_TR(false, false); }
+#undef MM_TR
   MM_TRY(hipGetLastError());
   if (codes_out) {
     // codes in id order

@@ -50,7 +50,7 @@ hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t
 // iteration (no allocation after the first call: graph-capture safe as long
 // as the histogram scan stays on its single-launch path, <= 2^16 entries).
 struct SortWork {
-  DevBuf k2, v2, hist, offs;
+  DevBuf k2, v2, hist, offs, sparts;  // sparts: partial sums of the histogram scan
 };
 hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s,
                             SortWork* ws = nullptr);
@@ -97,19 +97,21 @@ constexpr int32_t kTileBits = 13;  // tiled sets need k <= 7 and tbits <= 13
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
                        float* xy_out, double* delta2_dev, hipStream_t s,
-                       const float* alpha_dev = nullptr, int32_t group = 0);
+                       const float* alpha_dev = nullptr, int32_t group = 0, int32_t nb = 0);
 // lanes per chunk (4, 8, 16) the heuristic picks; group = 0 above means this
 inline int32_t tiled_group(const TiledSet& ts) {
   return ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
 }
+// 16-byte blocks per lane and step (2, 4) the heuristic picks; nb = 0 above
+// means this
+inline int32_t tiled_blocks(const TiledSet& ts) { return ts.tbits >= 12 ? 4 : 2; }
 
 // ---- far field (farfield.hip)
 struct FarStats { int64_t accepted, leaf_pairs, coincident, nodes; };
-hipError_t farfield_exact(int32_t n, const float* xy, double q, float* F, hipStream_t s);
-// Barnes-Hut quadtree far field; optional exports (device pointers, may be null):
-// codes[n], order[n], nodes[5*(2n)] (depth, first, count, leaf, prefix per node in pre-order),
-// stats (host) receives counters (nodes always; interaction counters when count_stats).
 struct BHWork;  // persistent buffers, sized by n
+// Exact all-pairs far field; w holds the per-slab partial sums (sized here,
+// so a first direct call sizes it before any graph capture).
+hipError_t farfield_exact(BHWork* w, int32_t n, const float* xy, double q, float* F, hipStream_t s);
 // A batch of independent graphs laid out together: graph g owns points
 // [goff[g], goff[g+1]) (device arrays; gid[v] = graph of point v).  Each
 // graph gets its own box and its own tree.
@@ -120,6 +122,9 @@ struct BHSeg {
 };
 BHWork* bh_work_create();
 void bh_work_destroy(BHWork*);
+// Barnes-Hut quadtree far field; optional exports (device pointers, may be null):
+// codes[n], order[n], nodes[5*(2n)] (depth, first, count, leaf, prefix per node in pre-order),
+// stats (host) receives counters (nodes always; interaction counters when count_stats).
 hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double theta, float* F,
                        uint64_t* codes_out, int32_t* order_out, int64_t* nodes_out,
                        int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s,

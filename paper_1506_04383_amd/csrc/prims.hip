@@ -69,43 +69,52 @@ __global__ void k_set_last(int64_t* out, int64_t n, const int64_t* part, int64_t
   out[n] = part[m];
 }
 
-// Small inputs: one workgroup walks the array in steps of 1024 threads x 8
-// consecutive elements.
+// Small inputs (n <= 2^16): one workgroup of 16 waves, wave w owning the
+// contiguous segment [w*L, (w+1)*L).  Pass 1: each wave sums its segment in
+// coalesced 64-element steps; the 16 sums are scanned in LDS.  Pass 2: each
+// wave walks its segment again (from cache), a wave-wide inclusive scan per
+// step plus the running carry gives the exclusive prefixes.
 template <typename Tin>
 __global__ __launch_bounds__(1024) void k_scan_small(const Tin* __restrict__ in, int64_t n,
                                                      int64_t* __restrict__ out) {
-  constexpr int E = 8;
-  __shared__ int64_t sh[1024 / 64 + 1];
+  __shared__ int64_t wsum[16];
+  const int l = lane_id(), w = threadIdx.x >> 6;
+  const int64_t L = ((n + 15) / 16 + 63) & ~(int64_t)63;
+  const int64_t b0 = (int64_t)w * L;
+  const int64_t b1 = b0 + L < n ? b0 + L : n;
+  int64_t t = 0;
+  for (int64_t j = b0 + l; j < b1; j += 64) t += (int64_t)in[j];
+  t = wave_sum(t);
+  if (l == 0) wsum[w] = t;
+  __syncthreads();
   int64_t carry = 0;
-  for (int64_t b = 0; b < n; b += 1024 * E) {
-    const int64_t j0 = b + (int64_t)threadIdx.x * E;
-    int64_t v[E], t = 0;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      v[i] = j0 + i < n ? (int64_t)in[j0 + i] : 0;
-      t += v[i];
-    }
-    int64_t tot;
-    int64_t ex = carry + block_excl_scan<int64_t>(t, sh, &tot);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      if (j0 + i < n) out[j0 + i] = ex;
-      ex += v[i];
-    }
-    carry += tot;
+  for (int i = 0; i < w; ++i) carry += wsum[i];
+  for (int64_t j0 = b0; j0 < b1; j0 += 64) {
+    const int64_t j = j0 + l;
+    const int64_t v = j < b1 ? (int64_t)in[j] : 0;
+    const int64_t inc = wave_incl_scan(v);
+    if (j < b1) out[j] = carry + inc - v;
+    carry += __shfl(inc, 63, 64);
   }
-  if (threadIdx.x == 0) out[n] = carry;
+  if (threadIdx.x == 1023) {
+    int64_t tot = 0;
+    for (int i = 0; i < 16; ++i) tot += wsum[i];
+    out[n] = tot;
+  }
 }
 
 template <typename Tin>
-hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s) {
+hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s,
+                          DevBuf* ws = nullptr) {
   if (n <= (1 << 16)) {
     k_scan_small<Tin><<<1, 1024, 0, s>>>(in, n, out);
     return hipGetLastError();
   }
   int64_t m = (n + SCAN_TILE - 1) / SCAN_TILE;
-  DevBuf part;
-  MM_TRY(part.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  DevBuf local;
+  DevBuf& part = ws ? *ws : local;
+  if (part.bytes < sizeof(int64_t) * (size_t)(m + 1))
+    MM_TRY(part.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
   if (m > 0) {
     k_tile_sums<Tin><<<(unsigned)m, SCAN_T, 0, s>>>(in, n, part.as<int64_t>());
   }
@@ -230,6 +239,8 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
   MM_TRY(grow(W.v2, sizeof(int32_t) * (size_t)n));
   MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)(256 * nb)));
   MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb + 1)));
+  if (256 * nb > (1 << 16))
+    MM_TRY(grow(W.sparts, sizeof(int64_t) * (size_t)((256 * nb + SCAN_TILE - 1) / SCAN_TILE + 1)));
   DevBuf& k2 = W.k2;
   DevBuf& v2 = W.v2;
   DevBuf& hist = W.hist;
@@ -239,7 +250,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
   for (int p = 0; p < passes; ++p) {
     int shift = 8 * p;
     k_rs_hist<<<(unsigned)nb, RS_T, 0, s>>>(ka, n, shift, (int)nb, hist.as<int32_t>());
-    MM_TRY(scan_excl_i32(hist.as<int32_t>(), offs.as<int64_t>(), 256 * nb, s));
+    MM_TRY(scan_excl_impl<int32_t>(hist.as<int32_t>(), offs.as<int64_t>(), 256 * nb, s, &W.sparts));
     k_rs_scatter<<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, shift, (int)nb, offs.as<int64_t>(), kb, vb);
     MM_TRY(hipGetLastError());
     uint64_t* tk = ka; ka = kb; kb = tk;

@@ -240,11 +240,14 @@ __global__ void k_rho(int32_t n, int32_t k, const int64_t* __restrict__ off,
 // One workgroup per work unit (<= UNIT_CH chunks of one tile).  Prologue:
 // the tile's coordinates (and sqrt c) and the unit's chunk metadata (first
 // block, slot, x_u) are staged in LDS.  Then each group of G lanes streams
-// chunks gi, gi + NG, ... one 16-byte block (8 entries) per lane per step.
-// The only global load in the loop is the entry block for the lane's next
-// step, issued unconditionally (clamped address) before the current block is
-// computed, so its latency overlaps one step of work.
-template <int G, bool COARSE, bool Q0>
+// chunks gi, gi + NG, ...: per step a lane takes NB 16-byte blocks (8
+// entries each) G blocks apart, so the group covers NB * G consecutive
+// blocks of its chunk.  The only global loads in the loop are the entry
+// blocks of the lane's next step, issued unconditionally (clamped address)
+// before the current blocks are computed, so their latency overlaps one step
+// of work.  A lane visits its blocks in the same order for every NB, so NB
+// changes only how many bytes are in flight, not the result.
+template <int G, int NB, bool COARSE, bool Q0>
 __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     int32_t n, int32_t tbits, const int32_t* __restrict__ unit_c0,
     const int32_t* __restrict__ unit_tile, const int64_t* __restrict__ chunk_off,
@@ -288,75 +291,88 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   __syncthreads();
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
   constexpr int NG = TS_T / G;
-  const int32_t mask = T - 1;
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const u32x4* __restrict__ ent4 = reinterpret_cast<const u32x4*>(ent);
   int32_t ci = gi;                      // chunk (relative to the unit)
   int32_t ae = ci < nch ? mblk[ci + 1] : 0;
   int32_t a = ci < nch ? mblk[ci] + gl : 0;
-  bool valid = ci < nch && a < ae;
-  u32x4 blk = ent4[valid ? a : 0];
+  u32x4 blk[NB];
+  bool vb[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    vb[b] = ci < nch && a + b * G < ae;
+    blk[b] = ent4[vb[b] ? a + b * G : 0];
+  }
   float2 xu = ci < nch ? mxu[ci] : make_float2(0.f, 0.f);
   float scu = (COARSE && ci < nch) ? mscu[ci] : 0.f;
   float px = 0.f, py = 0.f;
+  // one 16-byte block: decode the 8 entries, issue their LDS reads, then
+  // compute (branch-free)
+  auto run = [&](const u32x4 bk) {
+    const uint32_t wv[4] = {bk.x, bk.y, bk.z, bk.w};
+    float2 xv[8];
+    float4 lw[8];
+    float sc[8];
+#pragma unroll
+    for (int q2 = 0; q2 < 8; ++q2) {
+      const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
+      const uint32_t vl = pk >> 3;
+      xv[q2] = sx[vl];
+      lw[q2] = lut[pk & 7u];
+      if (COARSE) sc[q2] = ssc[vl];
+    }
+#pragma unroll
+    for (int q2 = 0; q2 < 8; ++q2) {
+      const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
+      // q = 0: a 1e-30 bias keeps 1/D finite for a coincident pair, whose
+      // r-terms then vanish through dx = dy = 0 (no select needed)
+      const float D2 = Q0 ? fmaf(dx, dx, fmaf(dy, dy, 1e-30f)) : fmaf(dx, dx, dy * dy);
+      float w = lw[q2].x, wd = lw[q2].y;
+      if (COARSE) {
+        const float d = lw[q2].w * (scu + sc[q2]) * scale;
+        const float r = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
+        wd = r;
+        w = r * r;
+      }
+      float inv = __builtin_amdgcn_rsqf(D2);
+      if (!Q0) inv = D2 > 0.f ? inv : 0.f;
+      const float rq = Q0 ? 0.f : (D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f);
+      // w d / D - alpha / D^(q+2); zero for padding and coincident pairs
+      const float coef = Q0 ? inv * fmaf(-lw[q2].z, inv, wd) : fmaf(wd, inv, -lw[q2].z * rq);
+      px = fmaf(w, xv[q2].x, px);
+      py = fmaf(w, xv[q2].y, py);
+      px = fmaf(coef, dx, px);
+      py = fmaf(coef, dy, py);
+    }
+  };
   for (;;) {
     const bool active = ci < nch;
     if (!__any(active)) break;
     // the group's next position: same chunk, or its next chunk if this step
     // finishes the current one (same decision for all lanes of the group)
-    const bool sw = active && (a - gl + G >= ae);
-    int32_t a_nx = a + G;
-    bool v_nx = active && a_nx < ae;
+    const bool sw = active && (a - gl + NB * G >= ae);
+    int32_t a_nx = a + NB * G;
     int32_t ae_nx = ae;
+    bool act_nx = active;
     if (sw) {
       const int32_t cn = ci + NG;
       if (cn < nch) {
         a_nx = mblk[cn] + gl;
         ae_nx = mblk[cn + 1];
-        v_nx = a_nx < ae_nx;
       } else {
-        v_nx = false;
+        act_nx = false;
       }
     }
-    const u32x4 nblk = __builtin_nontemporal_load(&ent4[v_nx ? a_nx : 0]);
-    if (valid) {
-      const uint32_t wv[4] = {blk.x, blk.y, blk.z, blk.w};
-      // branch-free: decode the 8 entries, issue their LDS reads, then compute
-      float2 xv[8];
-      float4 lw[8];
-      float sc[8];
+    u32x4 nblk[NB];
+    bool nvb[NB];
 #pragma unroll
-      for (int q2 = 0; q2 < 8; ++q2) {
-        const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
-        const uint32_t vl = pk >> 3;
-        xv[q2] = sx[vl];
-        lw[q2] = lut[pk & 7u];
-        if (COARSE) sc[q2] = ssc[vl];
-      }
-#pragma unroll
-      for (int q2 = 0; q2 < 8; ++q2) {
-        const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
-        // q = 0: a 1e-30 bias keeps 1/D finite for a coincident pair, whose
-        // r-terms then vanish through dx = dy = 0 (no select needed)
-        const float D2 = Q0 ? fmaf(dx, dx, fmaf(dy, dy, 1e-30f)) : fmaf(dx, dx, dy * dy);
-        float w = lw[q2].x, wd = lw[q2].y;
-        if (COARSE) {
-          const float d = lw[q2].w * (scu + sc[q2]) * scale;
-          const float r = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
-          wd = r;
-          w = r * r;
-        }
-        float inv = __builtin_amdgcn_rsqf(D2);
-        if (!Q0) inv = D2 > 0.f ? inv : 0.f;
-        const float rq = Q0 ? 0.f : (D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f);
-        // w d / D - alpha / D^(q+2); zero for padding and coincident pairs
-        const float coef = Q0 ? inv * fmaf(-lw[q2].z, inv, wd) : fmaf(wd, inv, -lw[q2].z * rq);
-        px = fmaf(w, xv[q2].x, px);
-        py = fmaf(w, xv[q2].y, py);
-        px = fmaf(coef, dx, px);
-        py = fmaf(coef, dy, py);
-      }
+    for (int b = 0; b < NB; ++b) {
+      nvb[b] = act_nx && a_nx + b * G < ae_nx;
+      nblk[b] = __builtin_nontemporal_load(&ent4[nvb[b] ? a_nx + b * G : 0]);
     }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (vb[b]) run(blk[b]);
     if (__any(sw)) {
       const float rx = group_sum(px, G), ry = group_sum(py, G);
       if (sw) {
@@ -372,8 +388,11 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     }
     a = a_nx;
     ae = ae_nx;
-    valid = v_nx;
-    blk = nblk;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      vb[b] = nvb[b];
+      blk[b] = nblk[b];
+    }
   }
 }
 
@@ -567,30 +586,35 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
                        float* xy_out, double* delta2_dev, hipStream_t s, const float* alpha_dev,
-                       int32_t group) {
+                       int32_t group, int32_t nb) {
   const bool coarse = level > 0 && sqrtc != nullptr;
   const bool q0 = q == 0.0;
   const int32_t T = 1 << ts.tbits;
   const size_t shm = (size_t)T * (sizeof(float2) + (coarse ? sizeof(float) : 0));
   // a group of G lanes (one 8-entry block each per step) per chunk
-  const int G = group > 0 ? group : ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
+  const int G = group > 0 ? group : tiled_group(ts);
+  const int NB = nb > 0 ? nb : tiled_blocks(ts);
   float2* part = ts.b_partial.as<float2>();
-#define MM_TS(GG, C, Q)                                                                          \
+#define MM_TS(GG, NBV, C, Q)                                                                     \
   do {                                                                                           \
     static bool attr_set = false; /* once per instantiation (not during a capture) */           \
     if (!attr_set) {                                                                             \
-      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tiled<GG, C, Q>),        \
+      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tiled<GG, NBV, C, Q>), \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));         \
       attr_set = true;                                                                           \
     }                                                                                            \
-    k_sweep_tiled<GG, C, Q><<<ts.nunits, TS_T, shm, s>>>(                                        \
+    k_sweep_tiled<GG, NBV, C, Q><<<ts.nunits, TS_T, shm, s>>>(                                   \
         ts.n, ts.tbits, ts.unit_c0, ts.unit_tile, ts.chunk_off, ts.chunk_row, ts.chunk_slot,     \
         ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, alpha_dev); \
   } while (0)
+#define MM_TSN(GG, NBV)                                                                  \
+  do {                                                                                   \
+    if (coarse) { if (q0) MM_TS(GG, NBV, true, true); else MM_TS(GG, NBV, true, false); } \
+    else { if (q0) MM_TS(GG, NBV, false, true); else MM_TS(GG, NBV, false, false); }      \
+  } while (0)
 #define MM_TSG(GG)                                   \
   do {                                               \
-    if (coarse) { if (q0) MM_TS(GG, true, true); else MM_TS(GG, true, false); } \
-    else { if (q0) MM_TS(GG, false, true); else MM_TS(GG, false, false); }      \
+    if (NB == 4) MM_TSN(GG, 4); else MM_TSN(GG, 2);  \
   } while (0)
   switch (G) {
     case 16: MM_TSG(16); break;
@@ -598,14 +622,15 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
     default: MM_TSG(4); break;
   }
 #undef MM_TSG
+#undef MM_TSN
 #undef MM_TS
   MM_TRY(hipGetLastError());
-  const int32_t nb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);
+  const int32_t ncb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);
   DevBuf& dpart = const_cast<TiledSet&>(ts).b_dpart;
-  if (dpart.bytes < sizeof(double2) * (size_t)nb) MM_TRY(dpart.alloc(sizeof(double2) * (size_t)nb, s));
-  k_combine<<<nb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, part, rho, (const float2*)xy, (const float2*)F,
+  if (dpart.bytes < sizeof(double2) * (size_t)ncb) MM_TRY(dpart.alloc(sizeof(double2) * (size_t)ncb, s));
+  k_combine<<<ncb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, part, rho, (const float2*)xy, (const float2*)F,
                                 (float)alpha, (float2*)xy_out, dpart.as<double2>(), alpha_dev);
-  k_sum_parts2<<<1, 1024, 0, s>>>(dpart.as<double2>(), nb, delta2_dev);
+  k_sum_parts2<<<1, 1024, 0, s>>>(dpart.as<double2>(), ncb, delta2_dev);
   return hipGetLastError();
 }
 

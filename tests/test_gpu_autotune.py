@@ -3,7 +3,8 @@ kept across contexts, through the C-ABI.
 
 Bars:
 * each configuration (row kernel with 8/16/32/64 lanes per row, tiled kernel
-  with tiles of 2^11/2^12/2^13 vertices and 4/8/16 lanes per chunk) gives one
+  with tiles of 2^11/2^12/2^13 vertices, 4/8/16 lanes per chunk and 2/4
+  blocks per lane and step) gives one
   Jacobi iteration of Eq. 2 within 1e-4 relative (floor 1) of the FP64 oracle
   on the same FP32 inputs, finest and coarse level, with a ragged last tile;
 * an autotuned layout is reproducible in its context, and a second context
@@ -19,7 +20,8 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = [(0, 8), (0, 16), (0, 32), (0, 64)] + [(tb, g) for tb in (11, 12, 13) for g in (4, 8, 16)]
+CONFIGS = [(0, 8, 0), (0, 16, 0), (0, 32, 0), (0, 64, 0)] + \
+    [(tb, g, nb) for tb in (11, 12, 13) for g in (4, 8, 16) for nb in (2, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -41,7 +43,7 @@ def ctx(mm):
 
 
 def _cfg_id(c):
-    return f"rows-{c[1]}" if c[0] == 0 else f"tile{c[0]}-{c[1]}"
+    return f"rows-{c[1]}" if c[0] == 0 else f"tile{c[0]}-{c[1]}x{c[2]}"
 
 
 @pytest.fixture(scope="module")
@@ -78,7 +80,8 @@ def test_every_sweep_configuration_matches_oracle(mm, ctx, case, config, level):
 
 def test_bad_configuration_rejected(mm, ctx, case):
     g, x, c, kh, F, _ = case
-    for cfg in [(0, 4), (0, 128), (10, 8), (13, 32), (14, 8), (12, 6)]:
+    for cfg in [(0, 4, 0), (0, 128, 0), (10, 8, 2), (13, 32, 2), (14, 8, 2), (12, 6, 2),
+                (0, 8, 2), (12, 8, 3), (12, 8, 8)]:
         with pytest.raises(mm.MulmentError, match="EINVAL"):
             mm.sweep(ctx, kh, x, F, 0.37, config=cfg)
 
@@ -113,9 +116,9 @@ def test_tuned_layout_export_import(mm, ctx):
 
 
 def test_bad_tune_records_rejected(mm, ctx):
-    good = np.array([[0, 1000, 50000, 2, 13, 8]], np.int64)
+    good = np.array([[0, 1000, 50000, 2, 13, 8, 4]], np.int64)
     ctx.tune_import(good)
-    for col, val in [(4, 10), (4, 14), (5, 3), (5, 32), (0, 2), (1, -1), (3, 0)]:
+    for col, val in [(4, 10), (4, 14), (5, 3), (5, 32), (0, 2), (1, -1), (3, 0), (6, 3), (6, 8)]:
         bad = good.copy()
         bad[0, col] = val
         with pytest.raises(mm.MulmentError, match="EINVAL"):

@@ -101,11 +101,17 @@ def test_barnes_hut_parity(orc, mm, ctx, n, theta):
     assert _far_err(r["F"].cpu().numpy(), ref.F) < 1e-4
 
 
-@pytest.mark.parametrize("q", [0.0, 1.0])
-def test_exact_far_field(orc, mm, ctx, q):
-    x = _layout_points(2048, 9)
+@pytest.mark.parametrize("n,q", [(2048, 0.0), (2048, 1.0), (1, 0.0), (2, 0.0), (63, 1.0),
+                                 (5001, 0.0), (5001, 1.0), (40000, 0.0)])
+def test_exact_far_field(orc, mm, ctx, n, q):
+    """All pairs, split into source slabs (ragged last slab and target block)."""
+    print(f"[exact] n={n} q={q}", flush=True)
+    x = _layout_points(n, 9) if n >= 8 else np.random.default_rng(n).random((n, 2)).astype(np.float32)
     F = mm.repulsion(ctx, x, q, -1.0)["F"].cpu().numpy()
     Fr = orc.farfield_exact(x.astype(np.float64), q)
+    if n == 1:
+        assert np.array_equal(F, np.zeros((1, 2), np.float32))
+        return
     assert _far_err(F, Fr) < 1e-4
 
 
@@ -233,6 +239,26 @@ def test_layout_small_config_end_to_end(orc, mm, ctx):
     assert np.array_equal(x2.cpu().numpy().astype(np.float64), xg)
 
 
+def test_layout_exact_below_hybrid(orc, mm, ctx):
+    """Levels with at most exact_below vertices take the exact far field, the
+    rest Barnes-Hut: maxent-stress within 1% of the oracle doing the same;
+    exact_below above every level gives the theta < 0 layout bit for bit."""
+    g = _graphs()["rgg4k"]()
+    kw = dict(k=3, alpha_decay=0.5, coarsest_n=20, seed=3)
+    xg, st = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(theta=0.5, exact_below=1000, **kw))
+    xo, sto = orc.layout(g, orc.Params(theta=0.5, exact_below=1000, **kw))
+    assert [l["n"] for l in st["per_level"]][::-1] == [l["n"] for l in sto["levels"]]
+    assert st["per_level"][0]["n"] > 1000 and st["per_level"][-1]["n"] <= 1000
+    kh = orc.khop_build(g.row_ptr, g.col, 3)
+    mg = orc.objective(kh, xg.cpu().numpy().astype(np.float64), 0.008)["M"]
+    mo = orc.objective(kh, xo, 0.008)["M"]
+    print(f"  M gpu {mg:.6g} orc {mo:.6g}")
+    assert abs(mg - mo) <= 0.01 * abs(mo)
+    xa, _ = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(theta=0.5, exact_below=g.n, **kw))
+    xe, _ = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(theta=-1.0, **kw))
+    assert np.array_equal(xa.cpu().numpy(), xe.cpu().numpy())
+
+
 def test_invalid_inputs_rejected(mm, ctx):
     g = synth.path(5)
     rp, col = g.row_ptr.copy(), g.col.copy()
@@ -246,6 +272,8 @@ def test_invalid_inputs_rejected(mm, ctx):
         mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(alpha0=0.001))
     with pytest.raises(mm.MulmentError, match="k must"):
         mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(k=0))
+    with pytest.raises(mm.MulmentError, match="exact_below"):
+        mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(exact_below=-1))
     with pytest.raises(mm.MulmentError, match="not finite"):
         mm.layout(ctx, ctx.graph(g.row_ptr, g.col), init_xy=np.full((5, 2), np.nan, np.float32))
 

@@ -217,6 +217,19 @@ def test_grid_converges_to_isometry_as_alpha_vanishes(orc):
     assert orc.objective(kh, x, 0)["stress"] < 1e-4
 
 
+def test_exact_below_selects_the_exact_far_field(orc):
+    """exact_below >= n on every level reproduces the exact-far-field layout
+    (theta < 0) bit for bit; exact_below = 0 is plain Barnes-Hut, which at
+    theta = 0.5 moves the result."""
+    g = synth.grid(16, 16)
+    kw = dict(k=2, alpha_decay=0.5, coarsest_n=10, max_final_iters=30)
+    xe, _ = orc.layout(g, orc.Params(theta=-1, **kw))
+    xa, _ = orc.layout(g, orc.Params(theta=0.5, exact_below=g.n, **kw))
+    xb, _ = orc.layout(g, orc.Params(theta=0.5, **kw))
+    assert np.array_equal(xe, xa)
+    assert not np.array_equal(xe, xb)
+
+
 def test_translation_rotation_invariance(orc):
     g = synth.grid(7, 6)
     kh = orc.khop_build(g.row_ptr, g.col, 2)
