@@ -6,9 +6,10 @@
 // into tiles of T = 2^tbits vertices; the coordinates (and sqrt c) of one
 // tile are staged in LDS and every (row, tile) chunk of the sets is swept
 // against them.  Entries are stored tile-major, 16 bits each:
-// ((v - tile * T) << 3) | hop, so hop <= 7 and T <= 2^13; the local id shifted
-// by 3 is the byte offset of x_v in the staged tile, and the hop indexes a
-// small per-level table (w = 1/d^2, w d, alpha; hop 0 marks padding).
+// ((v - tile * T) << 3) | hop, so hop <= 7 and T <= 2^13; the local id
+// indexes the staged tile, and the hop a small table of 1/hop and the bias
+// added to D^2 (hop 0 marks padding: bias +inf makes 1/D = 0, so all of a
+// padding entry's terms are exactly 0).
 //
 // Per chunk the partial sum  P = sum w (x_v + d (x_u - x_v)/D) - alpha sum r_q(u,v)
 // is written to a row-major slot; the combine kernel adds a row's slots in
@@ -256,8 +257,9 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     const float* __restrict__ sqrtc, float scale, float alpha, float q,
     float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
   extern __shared__ float2 sx[];
-  // per hop h: (w = 1/h^2, w*d = 1/h, alpha, h); h = 0 marks padding: all zero
-  __shared__ float4 lut[16];
+  // per hop h: (1/h, bias added to D^2); h = 0 marks padding: (0, +inf), so a
+  // padding entry gets 1/D = 0 and every one of its terms is exactly 0
+  __shared__ float2 lut[16];
   __shared__ int32_t mblk[UNIT_CH + 1];   // first block of each chunk (absolute)
   __shared__ int32_t mslot[UNIT_CH];
   __shared__ float2 mxu[UNIT_CH];
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   const int32_t nv = min(T, n - v0);
   for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
     sx[i] = xy[v0 + i];
-    if (COARSE) ssc[i] = sqrtc[v0 + i];
+    if (COARSE) ssc[i] = sqrtc[v0 + i] * scale;
   }
   for (int32_t i = threadIdx.x; i <= nch; i += TS_T) {
     mblk[i] = (int32_t)(chunk_off[c0 + i] >> 3);
@@ -279,14 +281,16 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
       const int32_t u = chunk_row[c0 + i];
       mslot[i] = chunk_slot[c0 + i];
       mxu[i] = xy[u];
-      if (COARSE) mscu[i] = sqrtc[u];
+      if (COARSE) mscu[i] = sqrtc[u] * scale;
     }
   }
   if (alpha_dev) alpha = *alpha_dev;
   if (threadIdx.x < 16) {
+    // q = 0: a 1e-30 bias keeps 1/D finite for a coincident pair, whose
+    // r-terms then vanish through dx = dy = 0; q != 0 tests D^2 > 0 instead
     const float h = (float)threadIdx.x;
-    lut[threadIdx.x] = threadIdx.x ? make_float4(1.f / (h * h), 1.f / h, alpha, h)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    lut[threadIdx.x] = threadIdx.x ? make_float2(1.f / h, Q0 ? 1e-30f : 0.f)
+                                   : make_float2(0.f, INFINITY);
   }
   __syncthreads();
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   auto run = [&](const u32x4 bk) {
     const uint32_t wv[4] = {bk.x, bk.y, bk.z, bk.w};
     float2 xv[8];
-    float4 lw[8];
+    float2 lw[8];
     float sc[8];
 #pragma unroll
     for (int q2 = 0; q2 < 8; ++q2) {
@@ -324,21 +328,17 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
 #pragma unroll
     for (int q2 = 0; q2 < 8; ++q2) {
       const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
-      // q = 0: a 1e-30 bias keeps 1/D finite for a coincident pair, whose
-      // r-terms then vanish through dx = dy = 0 (no select needed)
-      const float D2 = Q0 ? fmaf(dx, dx, fmaf(dy, dy, 1e-30f)) : fmaf(dx, dx, dy * dy);
-      float w = lw[q2].x, wd = lw[q2].y;
-      if (COARSE) {
-        const float d = lw[q2].w * (scu + sc[q2]) * scale;
-        const float r = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
-        wd = r;
-        w = r * r;
-      }
+      const float D2 = fmaf(dx, dx, fmaf(dy, dy, lw[q2].y));
+      // w d = 1/d with d = hop (finest level) or hop (sqrt c_u + sqrt c_v)
+      // scale (coarse levels; the staged roots are pre-scaled), w = (w d)^2
+      float wd = lw[q2].x;
+      if (COARSE) wd *= __builtin_amdgcn_rcpf(scu + sc[q2]);
+      const float w = wd * wd;
       float inv = __builtin_amdgcn_rsqf(D2);
       if (!Q0) inv = D2 > 0.f ? inv : 0.f;
       const float rq = Q0 ? 0.f : (D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f);
       // w d / D - alpha / D^(q+2); zero for padding and coincident pairs
-      const float coef = Q0 ? inv * fmaf(-lw[q2].z, inv, wd) : fmaf(wd, inv, -lw[q2].z * rq);
+      const float coef = Q0 ? inv * fmaf(-alpha, inv, wd) : fmaf(wd, inv, -alpha * rq);
       px = fmaf(w, xv[q2].x, px);
       py = fmaf(w, xv[q2].y, py);
       px = fmaf(coef, dx, px);
