@@ -83,6 +83,11 @@ typedef struct {
   int32_t exact_below;     /* levels with at most this many vertices use the exact all-pairs
                               far field instead of Barnes-Hut (0 = none, default); mm_layout
                               only (mm_layout_batch requires 0) */
+  int32_t approx_h;        /* h > 0: MulMent_h, the cluster far field of Eq. 3 with the graph
+                              h levels beneath (else the coarsest) on every level that has a
+                              coarser one, replacing theta / exact_below / mlp_weights there
+                              (the coarsest level keeps those); 0 = off (default).  Needs the
+                              hierarchy: ignored with init_xy; mm_layout only */
 } mm_params;
 
 #define MM_MAX_LEVELS 64
@@ -185,6 +190,22 @@ mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32
 mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, double theta,
                        float* F, uint64_t* codes, int32_t* order, int64_t* nodes,
                        int64_t* counters);
+
+/* Cluster far field, the first two sums of Eq. 3 (Section 3.2, "Faster Local
+ * Improvement"; MulMent_h): for each u,
+ *   F_u = sum_{v != u, cluster1[v] == cluster1[u]} r_q(u,v)
+ *       + sum_{j != cluster_h[u]} nu_j r_q(x_u, xp_j),
+ * nu_j = #{v : cluster_h[v] == j}, xp_j = node-weighted midpoint of those v
+ * (node_w NULL: weights 1).  cluster1 (n values in [0, n1)) maps to the next
+ * coarser level, cluster_h (n values in [0, nh)) to the level used for the
+ * approximation; vertices sharing u's cluster_h value but not its cluster1
+ * value contribute nothing (the merged-vertex error of that section).  With
+ * both maps the identity this is the exact sum.  All arrays are device
+ * arrays; xy, F are n*2 FP32.  Out-of-range cluster ids are MM_EINVAL.
+ * Synchronous on the context's stream. */
+mm_status mm_repulsion_cluster(mm_context* ctx, int32_t n, const float* xy, const int32_t* node_w,
+                               const int32_t* cluster1, int32_t n1, const int32_t* cluster_h,
+                               int32_t nh, double q, float* F);
 
 /* ---- learned far-field correction (an extension; the paper has none) ----
  * Barnes-Hut as in mm_repulsion (q = 0) where every accepted cell C adds,

@@ -50,6 +50,8 @@ def lib():
         L.orc_validate.argtypes = [C.c_int32, i32p, i32p, vp, vp]
         L.orc_khop_build.argtypes = [C.c_int32, i32p, i32p, C.c_int32, i64p, vp, vp]
         L.orc_farfield_exact.argtypes = [C.c_int32, f64p, C.c_double, f64p]
+        L.orc_cluster_far.argtypes = [C.c_int32, f64p, vp, i32p, C.c_int32, i32p, C.c_int32,
+                                      C.c_double, f64p]
         L.orc_bh.argtypes = [C.c_int32, f64p, C.c_double, C.c_double, f64p, vp, vp, vp,
                              C.c_int64, i64p]
         L.orc_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, i64p, i32p, i32p, vp,
@@ -146,6 +148,24 @@ def farfield_exact(xy, q: float = 0.0) -> np.ndarray:
     n = xy.size // 2
     F = np.zeros(2 * n)
     lib().orc_farfield_exact(n, xy, q, F)
+    return F.reshape(n, 2)
+
+
+def cluster_far_field(xy, c, cl1, n1: int, clh, nh: int, q: float = 0.0) -> np.ndarray:
+    """First two sums of Eq. 3 (Section 3.2): exact r-values within the own
+    cluster of the next coarser level (cl1) plus, for every other vertex j of
+    the approximation level (clh), nu_j r(x_u, xp_j) with nu_j the number of
+    vertices j represents here and xp_j their node-weighted midpoint."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    n = xy.size // 2
+    cl1 = _i32(cl1)
+    clh = _i32(clh)
+    cw = _i32(c)
+    F = np.zeros(2 * n)
+    rc = lib().orc_cluster_far(n, xy, None if cw is None else cw.ctypes.data_as(C.c_void_p),
+                               cl1, int(n1), clh, int(nh), q, F)
+    if rc != 0:
+        raise ValueError(f"orc_cluster_far failed ({rc})")
     return F.reshape(n, 2)
 
 
@@ -362,6 +382,9 @@ class Params:
     k: hop radius of the stress set (1 = edges only, the paper's default model).
     theta < 0 selects the exact all-pairs far field, theta >= 0 Barnes-Hut;
     levels with at most exact_below vertices use the exact far field either way.
+    approx_h > 0 selects the cluster far field of Eq. 3 with the graph h levels
+    beneath (or the coarsest) on every level that has a coarser one (MulMent_h);
+    the coarsest level then uses the exact far field.
     """
 
     k: int = 1
@@ -383,6 +406,7 @@ class Params:
     seed: int = 1
     mlp: np.ndarray | None = None  # far-field correction weights (q = 0, theta >= 0)
     exact_below: int = 0
+    approx_h: int = 0
 
 
 
@@ -446,8 +470,10 @@ def far_field(x, p: Params):
     return barnes_hut(x, p.theta, p.q).F
 
 
-def refine(lv: Level, level: int, x, p: Params, kh: KHop | None = None, start_alpha=None):
-    """Local improvement on one level (Section 3.2)."""
+def refine(lv: Level, level: int, x, p: Params, kh: KHop | None = None, start_alpha=None,
+           far=None):
+    """Local improvement on one level (Section 3.2).  far(x) -> F overrides the
+    far field chosen by p (the cluster far field of Eq. 3)."""
     if kh is None:
         kh = khop_build(lv.row_ptr, lv.col, p.k)
     alpha = p.alpha0 if start_alpha is None else start_alpha
@@ -455,7 +481,7 @@ def refine(lv: Level, level: int, x, p: Params, kh: KHop | None = None, start_al
     hist = []
 
     def T(x, a):
-        F = far_field(x, p)
+        F = far(x) if far is not None else far_field(x, p)
         return sweep(kh, x, F, a, p.q, level, lv.c, p.coarse_dist_scale)
 
     while alpha > p.alpha_min:
@@ -513,6 +539,16 @@ def layout(g, p: Params, init_xy=None):
     for lvl in range(L, -1, -1):
         if lvl < L:
             x = prolong(clusters[lvl], levels[lvl + 1].c, x, p.seed, lvl)
-        x, st = refine(levels[lvl], lvl, x, p)
+        far = None
+        if p.approx_h > 0 and lvl < L:
+            # Eq. 3: own cluster one level down, representatives h levels
+            # down (or on the coarsest level)
+            lh = min(lvl + p.approx_h, L)
+            clh = clusters[lvl]
+            for j in range(lvl + 1, lh):
+                clh = clusters[j][clh]
+            args = (levels[lvl].c, clusters[lvl], levels[lvl + 1].n, clh, levels[lh].n, p.q)
+            far = lambda xx, a=args: cluster_far_field(xx, *a)
+        x, st = refine(levels[lvl], lvl, x, p, far=far)
         stats["levels"].append({"level": lvl, "n": levels[lvl].n, **st})
     return x, stats

@@ -191,6 +191,69 @@ void orc_farfield_exact(int32_t n, const double* xy, double q, double* F) {
     }
 }
 
+/* ------------------------------------------------ cluster far field (Eq. 3)
+ * The first two sums of Eq. 3 for every u of one level, in the reading that
+ * Section 3.2 gives for an approximation level h > 1 beneath:
+ *   sum over v != u with cl1[v] == cl1[u] of r_q(u, v)          (exact, own
+ *       cluster of the next coarser level)
+ * + sum over coarse vertices j != clh[u] of nu_j r_q(x_u, xp_j)  (level used
+ *       for approximation),
+ * where nu_j = #{v : clh[v] == j} and xp_j is the c-weighted midpoint of
+ * those v.  Vertices whose clh equals clh[u] but whose cl1 differs from
+ * cl1[u] contribute nothing (the merged-vertex error of Section 3.2).  With
+ * cl1 = clh = identity this is the exact all-pairs sum. */
+int orc_cluster_far(int32_t n, const double* xy, const int32_t* c, const int32_t* cl1,
+                    int32_t n1, const int32_t* clh, int32_t nh, double q, double* F) {
+    for (int32_t v = 0; v < n; ++v)
+        if (cl1[v] < 0 || cl1[v] >= n1 || clh[v] < 0 || clh[v] >= nh) return -1;
+    double* mid = (double*)calloc(3 * (size_t)(nh > 0 ? nh : 1), sizeof(double));
+    int64_t* nu = (int64_t*)calloc((size_t)(nh > 0 ? nh : 1), sizeof(int64_t));
+    int64_t* start = (int64_t*)calloc((size_t)n1 + 1, sizeof(int64_t));
+    int32_t* memb = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!mid || !nu || !start || !memb) { free(mid); free(nu); free(start); free(memb); return -2; }
+    /* weighted midpoints, in ascending v */
+    for (int32_t v = 0; v < n; ++v) {
+        const double w = c ? (double)c[v] : 1.0;
+        const int32_t j = clh[v];
+        mid[3 * j] += w * xy[2 * v];
+        mid[3 * j + 1] += w * xy[2 * v + 1];
+        mid[3 * j + 2] += w;
+        nu[j]++;
+    }
+    for (int32_t j = 0; j < nh; ++j)
+        if (nu[j] > 0) { mid[3 * j] /= mid[3 * j + 2]; mid[3 * j + 1] /= mid[3 * j + 2]; }
+    /* members of each next-level cluster, ascending */
+    for (int32_t v = 0; v < n; ++v) start[cl1[v] + 1]++;
+    for (int32_t j = 0; j < n1; ++j) start[j + 1] += start[j];
+    {
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n1 + 1));
+        if (!fill) { free(mid); free(nu); free(start); free(memb); return -2; }
+        memcpy(fill, start, sizeof(int64_t) * ((size_t)n1 + 1));
+        for (int32_t v = 0; v < n; ++v) memb[fill[cl1[v]]++] = v;
+        free(fill);
+    }
+#pragma omp parallel for schedule(static)
+    for (int32_t u = 0; u < n; ++u) {
+        double fx = 0.0, fy = 0.0, rx, ry;
+        const int32_t a = cl1[u];
+        for (int64_t i = start[a]; i < start[a + 1]; ++i) {
+            const int32_t v = memb[i];
+            if (v == u) continue;
+            rq(xy[2 * u] - xy[2 * v], xy[2 * u + 1] - xy[2 * v + 1], q, &rx, &ry);
+            fx += rx; fy += ry;
+        }
+        for (int32_t j = 0; j < nh; ++j) {
+            if (j == clh[u] || nu[j] == 0) continue;
+            rq(xy[2 * u] - mid[3 * j], xy[2 * u + 1] - mid[3 * j + 1], q, &rx, &ry);
+            fx += (double)nu[j] * rx;
+            fy += (double)nu[j] * ry;
+        }
+        F[2 * u] = fx; F[2 * u + 1] = fy;
+    }
+    free(mid); free(nu); free(start); free(memb);
+    return 0;
+}
+
 /* ------------------------------------------------------------ Barnes-Hut */
 
 typedef struct {

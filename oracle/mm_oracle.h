@@ -51,6 +51,15 @@ int orc_khop_build(int32_t n, const int32_t* row_ptr, const int32_t* col,
  * Exact all-pairs sum in ascending v; coincident pairs contribute 0. */
 void orc_farfield_exact(int32_t n, const double* xy, double q, double* F);
 
+/* Cluster far field, the first two sums of Eq. 3 (Section 3.2): exact terms
+ * within the own cluster of the next coarser level (cl1, values < n1), plus
+ * each other vertex j of the approximation level (clh, values < nh) as
+ * nu_j r_q(x_u, xp_j), nu_j = number of level vertices it represents, xp_j
+ * their node-weighted midpoint (c may be NULL: weights 1).  Returns -1 on
+ * an out-of-range cluster id, -2 on allocation failure. */
+int orc_cluster_far(int32_t n, const double* xy, const int32_t* c, const int32_t* cl1,
+                    int32_t n1, const int32_t* clh, int32_t nh, double q, double* F);
+
 /* Barnes-Hut quadtree approximation (the quadtree far field the paper cites
  * as related work and as the method of the solver it compares against).
  * Box: origin (min x, min y), side 2^e >= extent; point cell index

@@ -43,7 +43,8 @@ class MMParams(C.Structure):
                 ("max_levels", C.c_int32), ("coarsest_n", C.c_int32), ("b", C.c_double),
                 ("f", C.c_double), ("lp_rounds", C.c_int32), ("coarse_dist_scale", C.c_double),
                 ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p),
-                ("use_graphs", C.c_int32), ("autotune", C.c_int32), ("exact_below", C.c_int32)]
+                ("use_graphs", C.c_int32), ("autotune", C.c_int32), ("exact_below", C.c_int32),
+                ("approx_h", C.c_int32)]
 
 
 class MMStats(C.Structure):
@@ -91,7 +92,8 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_coarse_graph", "mm_coarse_export", "mm_coarse_free", "mm_init_layout",
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
-           "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg"]
+           "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg",
+           "mm_repulsion_cluster"]
 
 TUNE_FIELDS = 7  # coarse?, n, sum |S|, k, tile bits, lanes, blocks per step
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
@@ -133,6 +135,7 @@ def lib():
         "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
         "mm_layout_batch": [vp, i32, vp, P(MMGraph), P(MMParams), vp, vp, vp, P(MMStats)],
         "mm_tune_clear": [vp],
+        "mm_repulsion_cluster": [vp, i32, vp, vp, vp, i32, vp, i32, f64, vp],
         "mm_tune_export": [vp, P(i64), i32, P(i32)],
         "mm_tune_import": [vp, P(i64), i32],
         "mm_far_samples": [vp, i32, vp, f64, i64, vp, vp, vp, vp, vp, P(i64)],
@@ -195,6 +198,7 @@ class Params:
     use_graphs: int = 1  # replay small levels' iterations from HIP graphs
     autotune: int = 0  # time each level's sweep configurations once per level shape
     exact_below: int = 0  # levels with <= this many vertices use the exact far field
+    approx_h: int = 0  # MulMent_h: cluster far field of Eq. 3, h levels beneath
 
     def to_c(self) -> MMParams:
         p = MMParams()
@@ -394,6 +398,21 @@ def repulsion(ctx: Context, xy, q: float = 0.0, theta: float = 0.5, export: bool
     if counters or export:
         out.update(accepted=int(cnt[0]), leaf_pairs=int(cnt[1]), n_nodes=int(cnt[3]))
     return out
+
+
+def repulsion_cluster(ctx: Context, xy, cluster1, n1: int, cluster_h, nh: int, node_w=None,
+                      q: float = 0.0):
+    """Cluster far field of Eq. 3 (mm_repulsion_cluster): float32 [n,2]."""
+    t = ctx.torch
+    xy = ctx._dev(xy, t.float32)
+    n = xy.shape[0]
+    c1 = ctx._dev(cluster1, t.int32)
+    ch = ctx._dev(cluster_h, t.int32)
+    nw = None if node_w is None else ctx._dev(node_w, t.int32)
+    F = t.empty((n, 2), dtype=t.float32, device=xy.device)
+    _check(lib().mm_repulsion_cluster(ctx.h, n, _ptr(xy), _ptr(nw), _ptr(c1), int(n1), _ptr(ch),
+                                      int(nh), q, _ptr(F)))
+    return F
 
 
 def mlp_init(seed: int, out_scale: float = 0.1, device: str = "cuda"):

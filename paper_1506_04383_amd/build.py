@@ -18,8 +18,8 @@ INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmulment.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["prims.hip", "khop.hip", "farfield.hip", "learned.hip", "sweep.hip", "tiled.hip", "coarsen.hip",
-           "layout.hip", "batch.hip", "objective.hip", "capi.cpp"]
+SOURCES = ["prims.hip", "khop.hip", "farfield.hip", "clusterfar.hip", "learned.hip", "sweep.hip",
+           "tiled.hip", "coarsen.hip", "layout.hip", "batch.hip", "objective.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MM_OFFLOAD_ARCH", "gfx950")

@@ -134,6 +134,7 @@ mm_status validate_params(const mm_params* p) {
   if (p->lp_rounds < 0) return fail(MM_EINVAL, "lp_rounds < 0");
   if (!(p->coarse_dist_scale > 0)) return fail(MM_EINVAL, "coarse_dist_scale must be > 0");
   if (p->exact_below < 0) return fail(MM_EINVAL, "exact_below must be >= 0");
+  if (p->approx_h < 0) return fail(MM_EINVAL, "approx_h must be >= 0");
   if (p->mlp_weights && (p->theta < 0 || p->q != 0.0))
     return fail(MM_EUNSUPPORTED, "the learned far field needs theta >= 0 and q == 0");
   return MM_OK;
@@ -362,6 +363,7 @@ mm_status mm_params_default(mm_params* p) {
   p->use_graphs = 1;
   p->autotune = 0;
   p->exact_below = 0;
+  p->approx_h = 0;
   return MM_OK;
 }
 
@@ -487,6 +489,28 @@ mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, do
     return MM_OK;
   } catch (...) {
     return fail(MM_EINTERNAL, "exception in mm_repulsion");
+  }
+}
+
+mm_status mm_repulsion_cluster(mm_context* ctx, int32_t n, const float* xy, const int32_t* node_w,
+                               const int32_t* cluster1, int32_t n1, const int32_t* cluster_h,
+                               int32_t nh, double q, float* F) {
+  try {
+    if (!ctx || !xy || !F || !cluster1 || !cluster_h) return fail(MM_EINVAL, "NULL argument");
+    if (n < 1 || n1 < 1 || nh < 1) return fail(MM_EINVAL, "n, n1 and nh must be >= 1");
+    if (std::isnan(q)) return fail(MM_EINVAL, "q NaN");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    bool ok = false;
+    HIPCHK(mm::cluster_far_check(n, cluster1, n1, cluster_h, nh, &ok, s));
+    if (!ok) return fail(MM_EINVAL, "cluster id out of range");
+    mm::ClusterFar cf;
+    HIPCHK(mm::cluster_far_setup(n, cluster1, n1, cluster_h, nh, &cf, s));
+    HIPCHK(mm::cluster_far(cf, xy, node_w, q, F, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_repulsion_cluster");
   }
 }
 
@@ -936,11 +960,31 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       int32_t iters = 0, final_iters = 0, cap_hit = 0;
       double delta = 0;
       mm::DevBuf sweep_part;
-      // far field of xin: exact all-pairs when theta < 0 or the level has at
-      // most exact_below vertices, else Barnes-Hut (with the learned
-      // correction when weights are given)
+      // far field of xin: the cluster far field of Eq. 3 (approx_h > 0, a
+      // coarser level exists), else exact all-pairs when theta < 0 or the
+      // level has at most exact_below vertices, else Barnes-Hut (with the
+      // learned correction when weights are given)
+      const bool cf_lvl = p->approx_h > 0 && lvl < Lmax;
       const bool exact_lvl = p->theta < 0 || nl <= p->exact_below;
+      mm::ClusterFar cf;
+      if (cf_lvl) {
+        const int32_t lh = std::min(lvl + p->approx_h, Lmax);
+        mm::DevBuf mh, tmp;
+        HIPCHK(mh.alloc(sizeof(int32_t) * (size_t)nl, s));
+        HIPCHK(hipMemcpyAsync(mh.p, clusters[lvl].p, sizeof(int32_t) * (size_t)nl,
+                              hipMemcpyDeviceToDevice, s));
+        for (int32_t j = lvl + 1; j < lh; ++j) {
+          HIPCHK(tmp.alloc(sizeof(int32_t) * (size_t)nl, s));
+          HIPCHK(mm::cluster_compose(nl, mh.as<int32_t>(), clusters[j].as<int32_t>(),
+                                     tmp.as<int32_t>(), s));
+          std::swap(mh, tmp);
+        }
+        HIPCHK(mm::cluster_far_setup(nl, clusters[lvl].as<int32_t>(), levels[lvl + 1]->g.n,
+                                     mh.as<int32_t>(), levels[lh]->g.n, &cf, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
       auto far = [&](const float* xin) -> hipError_t {
+        if (cf_lvl) return mm::cluster_far(cf, xin, G.c, p->q, F.as<float>(), s);
         if (exact_lvl) return mm::farfield_exact(ctx->bh, nl, xin, p->q, F.as<float>(), s);
         if (p->mlp_weights)
           return mm::farfield_learned(ctx->bh, nl, xin, p->theta, p->mlp_weights, F.as<float>(), s);

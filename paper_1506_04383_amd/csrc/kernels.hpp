@@ -130,6 +130,27 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
                        int64_t* n_nodes_out, int count_stats, FarStats* st, hipStream_t s,
                        const BHSeg* seg = nullptr);
 
+// ---- cluster far field of Eq. 3 (clusterfar.hip)
+struct ClusterFar {
+  int32_t n = 0, n1 = 0, nh = 0;  // level size, next coarser level, approximation level
+  int32_t S = 1, L = 1;           // source slabs and representatives per slab
+  DevBuf cl1, clh;                // cluster maps (copies)
+  DevBuf ord1, off1, ordh, offh;  // members sorted by cluster, cluster start offsets
+  DevBuf rep;                     // float4 (midpoint x, y, nu, 0) per representative
+  DevBuf part;                    // slab partial sums
+};
+// true in *ok when every cl1 value is in [0, n1) and every clh value in [0, nh)
+hipError_t cluster_far_check(int32_t n, const int32_t* cl1, int32_t n1, const int32_t* clh,
+                             int32_t nh, bool* ok, hipStream_t s);
+// out[v] = cl[in[v]]
+hipError_t cluster_compose(int32_t n, const int32_t* in, const int32_t* cl, int32_t* out,
+                           hipStream_t s);
+hipError_t cluster_far_setup(int32_t n, const int32_t* cl1, int32_t n1, const int32_t* clh,
+                             int32_t nh, ClusterFar* cf, hipStream_t s);
+// allocation-free after the setup (capturable)
+hipError_t cluster_far(ClusterFar& cf, const float* xy, const int32_t* c, double q, float* F,
+                       hipStream_t s);
+
 // ---- learned far-field correction (learned.hip), q = 0
 constexpr int32_t kMlpParams = 4866;  // W1 64x8, b1, W2 64x64, b2, W3 2x64, b3
 hipError_t farfield_learned(BHWork* w, int32_t n, const float* xy, double theta, const float* wts,

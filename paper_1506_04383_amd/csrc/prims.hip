@@ -69,44 +69,35 @@ __global__ void k_set_last(int64_t* out, int64_t n, const int64_t* part, int64_t
   out[n] = part[m];
 }
 
-// Small inputs (n <= 2^16): one workgroup of 16 waves, wave w owning the
-// contiguous segment [w*L, (w+1)*L).  Pass 1: each wave sums its segment in
-// coalesced 64-element steps; the 16 sums are scanned in LDS.  Pass 2: each
-// wave walks its segment again (from cache), a wave-wide inclusive scan per
-// step plus the running carry gives the exclusive prefixes.
+// Small inputs (n <= 8192): one workgroup, one step of 1024 threads x 8
+// consecutive elements.
+constexpr int64_t SCAN_SMALL_MAX = 8192;
 template <typename Tin>
 __global__ __launch_bounds__(1024) void k_scan_small(const Tin* __restrict__ in, int64_t n,
                                                      int64_t* __restrict__ out) {
-  __shared__ int64_t wsum[16];
-  const int l = lane_id(), w = threadIdx.x >> 6;
-  const int64_t L = ((n + 15) / 16 + 63) & ~(int64_t)63;
-  const int64_t b0 = (int64_t)w * L;
-  const int64_t b1 = b0 + L < n ? b0 + L : n;
-  int64_t t = 0;
-  for (int64_t j = b0 + l; j < b1; j += 64) t += (int64_t)in[j];
-  t = wave_sum(t);
-  if (l == 0) wsum[w] = t;
-  __syncthreads();
-  int64_t carry = 0;
-  for (int i = 0; i < w; ++i) carry += wsum[i];
-  for (int64_t j0 = b0; j0 < b1; j0 += 64) {
-    const int64_t j = j0 + l;
-    const int64_t v = j < b1 ? (int64_t)in[j] : 0;
-    const int64_t inc = wave_incl_scan(v);
-    if (j < b1) out[j] = carry + inc - v;
-    carry += __shfl(inc, 63, 64);
+  constexpr int E = 8;
+  __shared__ int64_t sh[1024 / 64 + 1];
+  const int64_t j0 = (int64_t)threadIdx.x * E;
+  int64_t v[E], t = 0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    v[i] = j0 + i < n ? (int64_t)in[j0 + i] : 0;
+    t += v[i];
   }
-  if (threadIdx.x == 1023) {
-    int64_t tot = 0;
-    for (int i = 0; i < 16; ++i) tot += wsum[i];
-    out[n] = tot;
+  int64_t tot;
+  int64_t ex = block_excl_scan<int64_t>(t, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    if (j0 + i < n) out[j0 + i] = ex;
+    ex += v[i];
   }
+  if (threadIdx.x == 0) out[n] = tot;
 }
 
 template <typename Tin>
 hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s,
                           DevBuf* ws = nullptr) {
-  if (n <= (1 << 16)) {
+  if (n <= SCAN_SMALL_MAX) {
     k_scan_small<Tin><<<1, 1024, 0, s>>>(in, n, out);
     return hipGetLastError();
   }
@@ -239,7 +230,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
   MM_TRY(grow(W.v2, sizeof(int32_t) * (size_t)n));
   MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)(256 * nb)));
   MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb + 1)));
-  if (256 * nb > (1 << 16))
+  if (256 * nb > SCAN_SMALL_MAX)
     MM_TRY(grow(W.sparts, sizeof(int64_t) * (size_t)((256 * nb + SCAN_TILE - 1) / SCAN_TILE + 1)));
   DevBuf& k2 = W.k2;
   DevBuf& v2 = W.v2;
