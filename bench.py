@@ -357,6 +357,9 @@ def main():
                     help="levels with at most this many vertices use the exact all-pairs far "
                          "field (cheaper there than the tree on this GPU); 0 = Barnes-Hut on "
                          "every level")
+    ap.add_argument("--approx-h", type=int, default=0,
+                    help="h > 0: MulMent_h, the paper's cluster far field (Eq. 3) with the "
+                         "graph h levels beneath, on every level with a coarser one")
     ap.add_argument("--tune-db", default=TUNE_DB,
                     help="JSON file of autotuner choices (per level shape) loaded into the "
                          "context before the first layout; levels it does not cover are tuned")
@@ -417,7 +420,8 @@ def main():
     p = mm.Params(k=wl["k"], theta=wl["theta"], alpha_decay=wl["alpha_decay"],
                   coarsest_n=wl.get("coarsest_n", 2), max_levels=wl.get("max_levels", 62),
                   seed=args.seed, validate=0, autotune=args.autotune,
-                  exact_below=args.exact_below if wl["theta"] >= 0 else 0)
+                  exact_below=args.exact_below if wl["theta"] >= 0 else 0,
+                  approx_h=args.approx_h)
 
     tune_loaded = 0
     if args.autotune and args.tune_db and os.path.exists(args.tune_db):
@@ -469,6 +473,8 @@ def main():
         "config": {"workload": wl["desc"], "n": g.n, "m": g.m, "k": wl["k"],
                    "theta": wl["theta"], "alpha_decay": wl["alpha_decay"], "seed": args.seed,
                    "exact_far_field_below_n": p.exact_below,
+                   "far_field": (f"MulMent_{p.approx_h} (Eq. 3)" if p.approx_h > 0
+                                 else "Barnes-Hut" if wl["theta"] >= 0 else "exact"),
                    "levels": st["levels"]},
         "time_to_layout_s": T / args.steps,
         "finest_sweep_updates_per_s": n0 / (sweep_avg_ms * 1e-3),
