@@ -13,7 +13,9 @@
 // the GPU result equals the sequential definition bit for bit.
 //
 // Scoring uses one wavefront per active vertex with an open-addressing hash
-// table (label -> score) in LDS for degree <= 128, in global memory otherwise.
+// table (label -> score) in LDS for degree <= 128, in global memory otherwise;
+// vertices of degree > 2048 (hubs) get a whole work-group each, so their
+// neighbour lists do not leave one wave running long after the others.
 // Admission: proposals compacted in v order, stably radix-sorted by target,
 // then an int64 prefix sum of c gives every proposal its running sum.
 // Contraction: labels are ranked, cut edges keyed (C(u), C(v)) and radix
@@ -29,6 +31,8 @@ namespace {
 constexpr int LP_WAVES = 4;
 constexpr int LP_SLOTS = 256;  // LDS hash slots per wave (degree <= 128)
 constexpr int LP_SMALL = 128;
+constexpr int LP_BIG = 2048;   // degree above which a whole work-group scores the vertex
+constexpr int LP_BT = 1024;    // threads of that work-group
 
 __global__ void k_weights(int32_t n, const int32_t* __restrict__ label, const int32_t* __restrict__ c,
                           unsigned long long* __restrict__ W) {
@@ -70,6 +74,11 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     long long* __restrict__ gsc, const int32_t* __restrict__ gid, const int32_t* __restrict__ goff,
     const double* __restrict__ Ug, const int32_t* __restrict__ gstop) {
   __shared__ int32_t skey[LP_WAVES][LP_SLOTS];
+  // hubs are scored by k_lp_propose_big
+  {
+    const int32_t vv = blockIdx.x * LP_WAVES + (threadIdx.x >> 6);
+    if (vv < n && rp[vv + 1] - rp[vv] > LP_BIG) return;
+  }
   __shared__ long long ssc[LP_WAVES][LP_SLOTS];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t v = blockIdx.x * LP_WAVES + w;
@@ -141,6 +150,89 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
   }
   best = wave_best(best);
   if (l == 0) prop[v] = (best.lab != own) ? best.lab : -1;
+}
+
+// One work-group per hub vertex (degree > LP_BIG): the same scoring as
+// k_lp_propose over the vertex's global table, with the block's threads
+// sharing the neighbour list and the table scan.
+__global__ __launch_bounds__(LP_BT) void k_lp_propose_big(
+    const int32_t* __restrict__ bigv, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ col, const int32_t* __restrict__ c,
+    const int32_t* __restrict__ ew, const int32_t* __restrict__ label,
+    const unsigned long long* __restrict__ W, double U, uint64_t stream, int colour,
+    int32_t* __restrict__ prop, const int64_t* __restrict__ hoff, int32_t* __restrict__ gkeys,
+    long long* __restrict__ gsc, const int32_t* __restrict__ gid, const int32_t* __restrict__ goff,
+    const double* __restrict__ Ug, const int32_t* __restrict__ gstop) {
+  __shared__ Cand wb[LP_BT / 64];
+  const int t = threadIdx.x, w = t >> 6, l = lane_id();
+  const int32_t v = bigv[blockIdx.x];
+  uint64_t vid = (uint64_t)v;
+  if (gid) {
+    const int32_t g = gid[v];
+    if (gstop[g]) { if (t == 0) prop[v] = -1; return; }
+    U = Ug[g];
+    vid = (uint64_t)(v - goff[g]);
+  }
+  const bool active = (int)(sm64_at(stream, vid) & 1ull) == colour;
+  if (!active) { if (t == 0) prop[v] = -1; return; }
+  const int32_t beg = rp[v], deg = rp[v + 1] - beg;
+  const int32_t own = label[v];
+  const long long cv = c ? c[v] : 1;
+  int32_t* keys = gkeys + hoff[v];
+  long long* sc = gsc + hoff[v];
+  const uint32_t mask = (uint32_t)(hoff[v + 1] - hoff[v]) - 1u;
+  for (uint32_t i = t; i <= mask; i += LP_BT) { keys[i] = -1; sc[i] = 0; }
+  __threadfence();
+  __syncthreads();
+  for (int32_t e = t; e < deg; e += LP_BT) {
+    const int32_t lab = label[col[beg + e]];
+    const long long wt = ew ? ew[beg + e] : 1;
+    uint32_t sl = hslot(lab, mask);
+    for (;;) {
+      int32_t prev = atomicCAS(&keys[sl], -1, lab);
+      if (prev == -1 || prev == lab) break;
+      sl = (sl + 1) & mask;
+    }
+    atomicAdd((unsigned long long*)&sc[sl], (unsigned long long)wt);
+  }
+  __threadfence();
+  __syncthreads();
+  Cand best;
+  best.sc = -1; best.lab = 0x7fffffff; best.own = 0;
+  for (uint32_t i = t; i <= mask; i += LP_BT) {
+    const int32_t lab = keys[i];
+    if (lab < 0) continue;
+    Cand cd;
+    cd.sc = sc[i];
+    cd.lab = lab;
+    cd.own = (lab == own);
+    if (!cd.own) {
+      if (cd.sc <= 0) continue;
+      if ((double)((long long)W[lab] + cv) > U) continue;  // infeasible
+    }
+    if (better(cd, best)) best = cd;
+  }
+  best = wave_best(best);
+  if (l == 0) wb[w] = best;
+  __syncthreads();
+  if (t == 0) {
+    Cand b = wb[0];
+    for (int i = 1; i < LP_BT / 64; ++i) if (better(wb[i], b)) b = wb[i];
+    // own label always competes (score 0 when no neighbour carries it)
+    Cand o; o.sc = 0; o.lab = own; o.own = 1;
+    if (better(o, b)) b = o;
+    prop[v] = (b.lab != own) ? b.lab : -1;
+  }
+}
+
+__global__ void k_big_flags(int32_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ flag) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = rp[v + 1] - rp[v] > LP_BIG ? 1 : 0;
+}
+__global__ void k_big_list(int32_t n, const int32_t* __restrict__ flag,
+                           const int64_t* __restrict__ pos, int32_t* __restrict__ bigv) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && flag[v]) bigv[pos[v]] = v;
 }
 
 __global__ void k_prop_flags(int32_t n, const int32_t* __restrict__ prop, int32_t* __restrict__ flag) {
@@ -299,6 +391,17 @@ hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed
   MM_TRY(hipStreamSynchronize(s));
   MM_TRY(gk.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(hslots, 1), s));
   MM_TRY(gsc.alloc(sizeof(long long) * (size_t)std::max<int64_t>(hslots, 1), s));
+  // hub vertices, scored one work-group each
+  DevBuf bigv;
+  int64_t nbig = 0;
+  k_big_flags<<<nblk(n), 256, 0, s>>>(n, g.row_ptr, flag.as<int32_t>());
+  MM_TRY(scan_excl_i32(flag.as<int32_t>(), pos.as<int64_t>(), n, s));
+  MM_TRY(hipMemcpyAsync(&nbig, pos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  if (nbig > 0) {
+    MM_TRY(bigv.alloc(sizeof(int32_t) * (size_t)nbig, s));
+    k_big_list<<<nblk(n), 256, 0, s>>>(n, flag.as<int32_t>(), pos.as<int64_t>(), bigv.as<int32_t>());
+  }
   MM_TRY(iota_i32(label, n, s));
   int lbits = 1;
   while ((1ll << lbits) < (int64_t)n) lbits++;
@@ -313,6 +416,11 @@ hipError_t lp_cluster(const GraphDev& g, double U, int32_t rounds, uint64_t seed
           n, g.row_ptr, g.col, g.c, g.w, label, W.as<unsigned long long>(), U, st, colour,
           prop.as<int32_t>(), hoff.as<int64_t>(), gk.as<int32_t>(), gsc.as<long long>(), gid, goff,
           Ug, gstop);
+      if (nbig > 0)
+        k_lp_propose_big<<<(unsigned)nbig, LP_BT, 0, s>>>(
+            bigv.as<int32_t>(), g.row_ptr, g.col, g.c, g.w, label, W.as<unsigned long long>(), U, st,
+            colour, prop.as<int32_t>(), hoff.as<int64_t>(), gk.as<int32_t>(), gsc.as<long long>(),
+            gid, goff, Ug, gstop);
       k_prop_flags<<<nblk(n), 256, 0, s>>>(n, prop.as<int32_t>(), flag.as<int32_t>());
       MM_TRY(scan_excl_i32(flag.as<int32_t>(), pos.as<int64_t>(), n, s));
       int64_t m = 0;
