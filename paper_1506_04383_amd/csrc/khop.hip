@@ -150,12 +150,18 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
 // ONE (k == 2): a single bitmap; the hop-2 candidates are marked without a
 // visited test and u and N(u) are cleared afterwards, which halves the LDS
 // footprint (two workgroups per CU for n up to ~650K).
-template <bool FILL, bool LDSBM, bool ONE>
+// KEEP (with ONE, when device memory allows): the counting pass stores each
+// row's final hop-2 bitmap (n bits per big row, row r at bmkeep + r * W) and
+// the filling pass extracts from it instead of marking again.
+template <bool FILL, bool LDSBM, bool ONE, bool KEEP>
 __global__ __launch_bounds__(KB_T) void k_khop_big(
     int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t k,
     const int32_t* __restrict__ rows, int32_t nrows, const int64_t* __restrict__ off,
     int32_t* __restrict__ hend, int32_t* __restrict__ nbr, int32_t* __restrict__ cnt,
-    uint32_t* __restrict__ gbm, int32_t* __restrict__ gscratch) {
+    uint32_t* __restrict__ gbm, int32_t* __restrict__ gscratch, uint32_t* __restrict__ bmkeep) {
+  static_assert(!KEEP || ONE, "kept bitmaps hold hop 2 only");
+  constexpr bool LOAD = KEEP && FILL;   // extract from the kept bitmap
+  constexpr bool STORE = KEEP && !FILL; // keep the bitmap
   extern __shared__ uint32_t dyn[];
   __shared__ int32_t wtot[KB_NW + 1];
   const int32_t W = (n + 31) >> 5;
@@ -186,9 +192,10 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     const int32_t* F = col + beg;
     int32_t flen = deg;
     __syncthreads();
+    const uint32_t* kept = LOAD ? bmkeep + (size_t)r * (size_t)W : nullptr;
     for (int h = 2; h <= k; ++h) {
       // mark neighbours of the frontier not yet visited
-      for (int32_t i = wv; i < flen; i += KB_NW) {
+      for (int32_t i = wv; i < flen && !LOAD; i += KB_NW) {
         int32_t x = F[i];
         int32_t b0 = rp[x], b1 = rp[x + 1];
         for (int32_t e = b0 + l; e < b1; e += 64) {
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
         }
       }
       __syncthreads();
-      if (ONE) {
+      if (ONE && !LOAD) {
         // drop hop 0 and hop 1 from the candidates
         if (t == 0) atomicAnd(&NEW[u >> 5], ~(1u << (u & 31)));
         for (int32_t i = t; i < deg; i += KB_T) {
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
       int32_t c = 0;
       for (int32_t b = wlo; b < whi; b += 64) {
         int32_t wi = b + l;
-        if (wi < whi) c += __popc(NEW[wi]);
+        if (wi < whi) c += __popc(LOAD ? kept[wi] : NEW[wi]);
       }
       c = wave_sum(c);
       if (l == 0) wtot[wv] = c;
@@ -232,7 +239,8 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
       int32_t run = wtot[wv];
       for (int32_t b = wlo; b < whi; b += 64) {
         int32_t wi = b + l;
-        uint32_t bits = wi < whi ? NEW[wi] : 0u;
+        uint32_t bits = wi < whi ? (LOAD ? kept[wi] : NEW[wi]) : 0u;
+        if (STORE && wi < whi) bmkeep[(size_t)r * (size_t)W + wi] = bits;
         int32_t pc = __popc(bits);
         int32_t inc = wave_incl_scan(pc);
         int32_t pos = run + inc - pc;
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
               dst[pos++] = (wi << 5) + j;
             }
           }
-          NEW[wi] = 0u;
+          if (!LOAD) NEW[wi] = 0u;
           if (!ONE && !last) VIS[wi] |= bits;
         }
         run += __shfl(inc, 63, 64);
@@ -328,22 +336,37 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   const size_t shm = lds_bm ? sizeof(uint32_t) * (size_t)nbw : 0;
   const int per_cu = lds_bm ? (int)std::max<size_t>(1, (160 * 1024 - 256) / std::max<size_t>(shm, 1)) : 2;
   const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * std::min(per_cu, 4));
-  DevBuf gbm, gscr;
-#define MM_BIG(FILLV, LDSV, ONEV, ...)                                                          \
+  DevBuf gbm, gscr, bmk;
+  // keep the counting pass's hop-2 bitmaps for the filling pass when they
+  // take at most a third of the free device memory
+  bool keep = false;
+  if (one && nbig > 0) {
+    size_t freeb = 0, totb = 0;
+    MM_TRY(hipMemGetInfo(&freeb, &totb));
+    const size_t kb = sizeof(uint32_t) * (size_t)W * (size_t)nbig;
+    if (kb <= freeb / 3) {
+      MM_TRY(bmk.alloc(kb, s));
+      keep = true;
+    }
+  }
+#define MM_BIG(FILLV, LDSV, ONEV, KEEPV, ...)                                                   \
   do {                                                                                         \
     if (LDSV)                                                                                  \
-      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_khop_big<FILLV, LDSV, ONEV>), \
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));       \
-    k_khop_big<FILLV, LDSV, ONEV><<<slots, KB_T, LDSV ? shm : 0, s>>>(__VA_ARGS__);           \
+      MM_TRY(hipFuncSetAttribute(                                                              \
+          reinterpret_cast<const void*>(&k_khop_big<FILLV, LDSV, ONEV, KEEPV>),                \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));                              \
+    k_khop_big<FILLV, LDSV, ONEV, KEEPV><<<slots, KB_T, LDSV ? shm : 0, s>>>(__VA_ARGS__);    \
   } while (0)
 #define MM_BIG_ANY(FILLV, ...)                                                          \
   do {                                                                                 \
     if (lds_bm) {                                                                      \
-      if (one) MM_BIG(FILLV, true, true, __VA_ARGS__);                                 \
-      else MM_BIG(FILLV, true, false, __VA_ARGS__);                                    \
+      if (one && keep) MM_BIG(FILLV, true, true, true, __VA_ARGS__);                   \
+      else if (one) MM_BIG(FILLV, true, true, false, __VA_ARGS__);                     \
+      else MM_BIG(FILLV, true, false, false, __VA_ARGS__);                             \
     } else {                                                                           \
-      if (one) MM_BIG(FILLV, false, true, __VA_ARGS__);                                \
-      else MM_BIG(FILLV, false, false, __VA_ARGS__);                                   \
+      if (one && keep) MM_BIG(FILLV, false, true, true, __VA_ARGS__);                  \
+      else if (one) MM_BIG(FILLV, false, true, false, __VA_ARGS__);                    \
+      else MM_BIG(FILLV, false, false, false, __VA_ARGS__);                            \
     }                                                                                  \
   } while (0)
   if (nbig > 0) {
@@ -353,7 +376,8 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
     if (!lds_bm) MM_TRY(gbm.alloc(sizeof(uint32_t) * (size_t)nbw * (size_t)slots, s));
     if (k >= 3) MM_TRY(gscr.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
     MM_BIG_ANY(false, n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig, nullptr, out->hend,
-               nullptr, cnt.as<int32_t>(), gbm.as<uint32_t>(), gscr.as<int32_t>());
+               nullptr, cnt.as<int32_t>(), gbm.as<uint32_t>(), gscr.as<int32_t>(),
+               bmk.as<uint32_t>());
     MM_TRY(hipGetLastError());
   }
   MM_TRY(scan_excl_i32(cnt.as<int32_t>(), out->off, n, s));
@@ -366,7 +390,7 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   MM_TRY(hipGetLastError());
   if (nbig > 0) {
     MM_BIG_ANY(true, n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig, out->off, out->hend,
-               out->nbr, nullptr, gbm.as<uint32_t>(), nullptr);
+               out->nbr, nullptr, gbm.as<uint32_t>(), nullptr, bmk.as<uint32_t>());
     MM_TRY(hipGetLastError());
   }
 #undef MM_BIG_ANY
