@@ -72,8 +72,11 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(int32_t n, int32_t 
 }
 
 // K3 / K6: per row, per tile runs.  FILL=false: chunk sizes (row-major
-// slots).  FILL=true: write the 16-bit entries.
-template <bool FILL>
+// slots).  FILL=true: write the 16-bit entries; with BASE the start of every
+// touched tile's chunk is looked up once per row (an LDS table of int64) so
+// that the entry loop has no dependent global loads.  The row's entries are
+// loaded one 64-entry step ahead.
+template <bool FILL, bool BASE>
 __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
     int32_t n, int32_t k, int32_t tbits, int32_t ntiles, int32_t ntw,
     const int64_t* __restrict__ off, const int32_t* __restrict__ hend,
@@ -82,21 +85,32 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
     const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
     uint16_t* __restrict__ ent) {
   // per wave, sized by the tile count: tile bitmap (ntw words), its popcount
-  // prefix (ntw), per-tile counters (ntiles)
+  // prefix (ntw), per-tile counters (ntiles), with BASE the chunk starts
+  // (ntiles int64, 8-byte aligned)
   extern __shared__ uint32_t tb_dyn[];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t u = blockIdx.x * TB_WAVES + w;
   if (u >= n) return;
-  uint32_t* bm = tb_dyn + (size_t)w * (2 * ntw + ntiles);
+  const size_t per = ((2 * (size_t)ntw + (size_t)ntiles + 1) & ~(size_t)1) +
+                     (BASE ? 2 * (size_t)ntiles : 0);
+  uint32_t* bm = tb_dyn + (size_t)w * per;
   int32_t* pf = reinterpret_cast<int32_t*>(bm + ntw);
   int32_t* ct = pf + ntw;
-  const int64_t beg = off[u];
+  int64_t* base = BASE ? reinterpret_cast<int64_t*>(bm + ((2 * (size_t)ntw + (size_t)ntiles + 1) &
+                                                          ~(size_t)1))
+                       : nullptr;
+  const int64_t beg = off[u], endr = off[u + 1];
   for (int i = l; i < ntw; i += 64) bm[i] = 0u;
   wave_sync();
-  for (int64_t e = beg + l; e < off[u + 1]; e += 64) {
-    const int32_t t = nbr[e] >> tbits;
-    const uint32_t bit = 1u << (t & 31);
-    if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+  {
+    int32_t vn = beg + l < endr ? nbr[beg + l] : 0;
+    for (int64_t e = beg + l; e < endr; e += 64) {
+      const int32_t v = vn;
+      if (e + 64 < endr) vn = nbr[e + 64];
+      const int32_t t = v >> tbits;
+      const uint32_t bit = 1u << (t & 31);
+      if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+    }
   }
   wave_sync();
   // zero the counters of touched tiles; popcount prefix over words
@@ -110,13 +124,28 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
   }
   wave_sync();
   const int64_t rbase = rc_ptr[u];
+  if (FILL && BASE) {
+    for (int i = l; i < ntw; i += 64) {
+      uint32_t b = bm[i];
+      int32_t rank = pf[i];
+      while (b) {
+        const int j = __ffs(b) - 1;
+        b &= b - 1;
+        base[(i << 5) + j] = chunk_off[pos_of_slot[rbase + rank]];
+        rank++;
+      }
+    }
+    wave_sync();
+  }
   int32_t seg0 = 0;
   for (int h = 1; h <= k; ++h) {
     const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    int32_t vn = seg0 + l < seg1 ? nbr[beg + seg0 + l] : 0;
     for (int32_t b = seg0; b < seg1; b += 64) {
       const int32_t i = b + l;
       const bool valid = i < seg1;
-      const int32_t v = valid ? nbr[beg + i] : 0;
+      const int32_t v = vn;
+      if (i + 64 < seg1) vn = nbr[beg + i + 64];
       const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
       const int32_t tprev = __shfl_up(t, 1, 64);
       const bool start = valid && (l == 0 || tprev != t);
@@ -124,9 +153,14 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
       const int32_t tnext = __shfl_down(t, 1, 64);
       const bool end = valid && (l == 63 || i + 1 >= seg1 || tnext != t);
       if (FILL && valid) {
-        const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
-        const int32_t c = pos_of_slot[rbase + rank];
-        const int64_t dst = chunk_off[c] + ct[t] + (l - rs);
+        int64_t cbase;
+        if (BASE) {
+          cbase = base[t];
+        } else {
+          const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
+          cbase = chunk_off[pos_of_slot[rbase + rank]];
+        }
+        const int64_t dst = cbase + ct[t] + (l - rs);
         ent[dst] = (uint16_t)(((v & ((1 << tbits) - 1)) << 3) | h);
       }
       wave_sync();
@@ -502,14 +536,18 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(cm_tile.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(cm_size.alloc(sizeof(int32_t) * (size_t)m, s));
   MM_TRY(cm_row.alloc(sizeof(int32_t) * (size_t)m, s));
-  const size_t tb_shm = sizeof(uint32_t) * (size_t)TB_WAVES * (2 * (size_t)ntw + (size_t)ntiles);
+  const size_t per_wave = (2 * (size_t)ntw + (size_t)ntiles + 1) & ~(size_t)1;
+  const size_t tb_shm = sizeof(uint32_t) * (size_t)TB_WAVES * per_wave;
+  // the fill pass keeps the chunk starts of a row's tiles in LDS when they fit
+  const size_t tb_shm_base = sizeof(uint32_t) * (size_t)TB_WAVES * (per_wave + 2 * (size_t)ntiles);
+  const bool use_base = tb_shm_base <= 65536;
   if (tb_shm > 65536) {
-    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<false>),
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<false, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
-    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<true>),
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<true, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
   }
-  k_row_chunks<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
+  k_row_chunks<false, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
       n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, cm_tile.as<int32_t>(),
       cm_size.as<int32_t>(), cm_row.as<int32_t>(), nullptr, nullptr, nullptr);
   MM_TRY(hipGetLastError());
@@ -549,9 +587,14 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(hipMemsetAsync(ts->ent, 0, sizeof(uint16_t) * (size_t)padded, s));
   ts->total = kh.total;
   ts->padded = padded;
-  k_row_chunks<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
-      n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr, nullptr,
-      pos_of_slot, ts->chunk_off, ts->ent);
+  if (use_base)
+    k_row_chunks<true, true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm_base, s>>>(
+        n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
+        nullptr, pos_of_slot, ts->chunk_off, ts->ent);
+  else
+    k_row_chunks<true, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
+        n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
+        nullptr, pos_of_slot, ts->chunk_off, ts->ent);
   MM_TRY(hipGetLastError());
   // work units
   MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)m, s));
