@@ -951,8 +951,8 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       if (tbits_lvl > 0 && mm::tiled_eligible(kh, tbits_lvl)) {
         auto tt = std::chrono::steady_clock::now();
         HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
-        HIPCHK(mm::compute_rho(kh, sqrtc, p->coarse_dist_scale, rho.as<float>(), s));
-        HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s));
+        HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s, sqrtc, p->coarse_dist_scale,
+                               rho.as<float>()));
         if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
         HIPCHK(hipStreamSynchronize(s));
         t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();

@@ -90,9 +90,12 @@ bool tiled_eligible(const KhopDev& kh, int32_t tbits);
 hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, float* rho,
                        hipStream_t s);
 // Builds the tile-major copy of kh; when the mean chunk length is below
-// min_avg_chunk it stops after counting (ts->built stays false).
+// min_avg_chunk it stops after counting (ts->built stays false).  With rho
+// non-null it also computes compute_rho's result (same bits) in its first
+// pass over the sets, built or not.
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
-                       hipStream_t s);
+                       hipStream_t s, const float* sqrtc = nullptr, double scale = 1.0,
+                       float* rho = nullptr);
 constexpr int32_t kTileBits = 13;  // tiled sets need k <= 7 and tbits <= 13
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,

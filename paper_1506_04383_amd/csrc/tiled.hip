@@ -48,10 +48,15 @@ __device__ inline int32_t wave_incl_max(int32_t v) {
 }
 
 // K1: number of distinct tiles per row
-__global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(int32_t n, int32_t tbits, int32_t ntw,
-                                                            const int64_t* __restrict__ off,
-                                                            const int32_t* __restrict__ nbr,
-                                                            int32_t* __restrict__ nch) {
+// Distinct tiles per row (the row's chunk count); with RHO also
+// rho_u = sum over S(u) of w_uv in exactly k_rho's order (per hop segment,
+// lane-strided, then a wave sum), so both give the same bits.
+template <bool RHO>
+__global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(
+    int32_t n, int32_t k, int32_t tbits, int32_t ntw, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ hend, const int32_t* __restrict__ nbr,
+    const float* __restrict__ sqrtc, float scale, int32_t* __restrict__ nch,
+    float* __restrict__ rho) {
   __shared__ uint32_t tbm[TB_WAVES][TB_MAXW];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t u = blockIdx.x * TB_WAVES + w;
@@ -59,16 +64,44 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(int32_t n, int32_t 
   uint32_t* bm = tbm[w];
   for (int i = l; i < ntw; i += 64) bm[i] = 0u;
   wave_sync();
-  for (int64_t e = off[u] + l; e < off[u + 1]; e += 64) {
-    const int32_t t = nbr[e] >> tbits;
-    const uint32_t bit = 1u << (t & 31);
-    if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+  const int64_t beg = off[u];
+  const float su = (RHO && sqrtc) ? sqrtc[u] : 0.f;
+  float r = 0.f;
+  int32_t seg0 = 0;
+  for (int h = 1; h <= k; ++h) {
+    const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    for (int32_t i = seg0 + l; i < seg1; i += 64) {
+      const int32_t v = nbr[beg + i];
+      const int32_t t = v >> tbits;
+      const uint32_t bit = 1u << (t & 31);
+      if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+      if (RHO && sqrtc) {
+        const float d = (float)h * (su + sqrtc[v]) * scale;
+        r += 1.f / (d * d);
+      }
+    }
+    seg0 = seg1;
   }
   wave_sync();
   int32_t c = 0;
   for (int i = l; i < ntw; i += 64) c += __popc(bm[i]);
   c = wave_sum(c);
   if (l == 0) nch[u] = c;
+  if (RHO) {
+    if (sqrtc) {
+      r = wave_sum(r);
+      if (l == 0) rho[u] = r;
+    } else if (l == 0) {
+      int32_t prev = 0;
+      float rr = 0.f;
+      for (int h = 1; h <= k; ++h) {
+        const int32_t e = hend[(int64_t)u * k + h - 1];
+        rr += (float)(e - prev) / (float)(h * h);
+        prev = e;
+      }
+      rho[u] = rr;
+    }
+  }
 }
 
 // K3 / K6: per row, per tile runs.  FILL=false: chunk sizes (row-major
@@ -511,7 +544,7 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
 }
 
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
-                       hipStream_t s) {
+                       hipStream_t s, const float* sqrtc, double scale, float* rho) {
   const int32_t n = kh.n;
   const int32_t ntiles = (int32_t)(((int64_t)n + (1 << tbits) - 1) >> tbits);
   const int32_t ntw = (ntiles + 31) >> 5;
@@ -522,7 +555,12 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(nch.alloc(sizeof(int32_t) * (size_t)n, s));
   MM_TRY(ts->b_rc_ptr.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
   ts->rc_ptr = ts->b_rc_ptr.as<int64_t>();
-  k_row_tiles<<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(n, tbits, ntw, kh.off, kh.nbr, nch.as<int32_t>());
+  if (rho)
+    k_row_tiles<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+        n, kh.k, tbits, ntw, kh.off, kh.hend, kh.nbr, sqrtc, (float)scale, nch.as<int32_t>(), rho);
+  else
+    k_row_tiles<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+        n, kh.k, tbits, ntw, kh.off, kh.hend, kh.nbr, nullptr, 1.f, nch.as<int32_t>(), nullptr);
   MM_TRY(hipGetLastError());
   MM_TRY(scan_excl_i32(nch.as<int32_t>(), ts->rc_ptr, n, s));
   int64_t m = 0;
