@@ -194,6 +194,81 @@ def snapshot_comparison(args):
     ctx.close()
 
 
+def dynamic_comparison(args):
+    """The update algorithm of Sec. 4.3 against layouts from scratch, on the
+    paper's grid: x in {1, 5} % of the edges replaced, new edges to vertices
+    1 < d <= D hops away with D in {2, 16}, MulMent_h with h in {0, 7} (h = 0:
+    exact far field; h = 7: Eq. 3 with the graph 7 levels beneath, the update
+    cutting the hierarchy after 7 levels).  Graphs: RGG 2^16 and a Delaunay
+    triangulation of 2^16 points, the paper's configuration otherwise (S = E,
+    decay 0.3).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1506_04383_amd as mm
+    import synth
+
+    ctx = mm.Context(0)
+    base = dict(k=1, alpha_decay=0.3, coarsest_n=2, seed=args.seed, validate=0)
+    graphs = [("rgg16", synth.config_graph("rgg16", args.seed)),
+              ("del16", synth.delaunay(1 << 16, args.seed))]
+    rows = []
+    for gname, g in graphs:
+        dg = ctx.graph(g.row_ptr, g.col)
+        churned = {}
+        for x in (1, 5):
+            for D in (2, 16):
+                t0 = time.perf_counter()
+                churned[(x, D)] = synth.churn_snapshot(g, args.seed * 100 + x * 10 + D, x / 100.0, D)
+                print(f"[dyn] {gname} churn x={x}% D={D} in {time.perf_counter() - t0:.1f}s",
+                      file=sys.stderr, flush=True)
+        for h in (0, 7):
+            P = dict(base, theta=-1.0) if h == 0 else dict(base, theta=0.5, approx_h=h)
+            xg, _ = mm.layout(ctx, dg, mm.Params(**P))
+            for (x, D), q in churned.items():
+                dq = ctx.graph(q.row_ptr, q.col)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xd, _ = mm.layout(ctx, dq, mm.Params(**P), init_xy=xg)
+                torch.cuda.synchronize()
+                t_dyn = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                xs, _ = mm.layout(ctx, dq, mm.Params(**P))
+                torch.cuda.synchronize()
+                t_scr = time.perf_counter() - t0
+                kh = mm.khop_build(ctx, dq, 1)
+                Md = mm.objective(ctx, kh, xd, 0.008)["M"]
+                Ms = mm.objective(ctx, kh, xs, 0.008)["M"]
+                kh.free()
+                Fd = mm.full_stress(ctx, dq, xd)["F"]
+                Fs = mm.full_stress(ctx, dq, xs)["F"]
+                rows.append({"graph": gname, "x_pct": x, "D": D, "h": h, "t_dyn_s": t_dyn,
+                             "t_scratch_s": t_scr, "speedup": t_scr / t_dyn,
+                             "F_dyn_over_scratch": Fd / Fs, "M_dyn": Md, "M_scratch": Ms})
+                print(f"[dyn] {gname} x={x} D={D} h={h}: dyn {t_dyn:.3f}s scratch {t_scr:.3f}s "
+                      f"F ratio {Fd / Fs:.3f} M dyn {Md:.6g} scratch {Ms:.6g}", file=sys.stderr,
+                      flush=True)
+
+    def gmean(v):
+        return float(np.exp(np.mean(np.log(v))))
+
+    by_h = {h: [r for r in rows if r["h"] == h] for h in (0, 7)}
+    out = {"metric": "time of the update algorithm vs scratch on the paper's dynamic protocol "
+                     "(Sec. 4.3)",
+           "value": gmean([r["speedup"] for r in rows]), "unit": "speedup (x, geometric mean)",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "RGG 2^16 and Delaunay 2^16; x in {1,5}%, D in {2,16}, "
+                                  "h in {0,7}; k=1, decay 0.3", "seed": args.seed},
+           "speedup_by_h": {str(h): gmean([r["speedup"] for r in v]) for h, v in by_h.items()},
+           "F_ratio_mean": float(np.mean([r["F_dyn_over_scratch"] for r in rows])),
+           # M can change sign (k = 1 has few stress pairs), so no ratio: the
+           # share of runs where the update ends at no higher maxent-stress
+           "M_dyn_not_above_scratch": float(np.mean([r["M_dyn"] <= r["M_scratch"] for r in rows])),
+           "runs": rows}
+    print(json.dumps(out))
+    ctx.close()
+
+
 def learned_comparison(args):
     """Learned far field vs plain Barnes-Hut on RGG 2^22 (k = 3): the network is
     trained on the GPU on exact residuals of cells accepted at theta = 1 in
@@ -366,10 +441,11 @@ def main():
     ap.add_argument("--save-tune-db", default="",
                     help="write the context's autotuner choices here after the run")
     ap.add_argument("--mode", default="layout",
-                    choices=["layout", "learned", "batch", "snapshots"],
+                    choices=["layout", "learned", "batch", "snapshots", "dynamic"],
                     help="layout: the layout benchmark; learned: learned far field vs plain "
                          "Barnes-Hut on RGG 2^22; batch: 4096 graphs batched vs one at a "
-                         "time; snapshots: warm-started dynamic snapshots vs scratch")
+                         "time; snapshots: warm-started dynamic snapshots vs scratch; dynamic: "
+                         "the paper's update protocol (x, D, h grid) vs scratch")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-sample", type=int, default=96)
     ap.add_argument("--snapshots", type=int, default=64)
@@ -405,6 +481,9 @@ def main():
         return
     if args.mode == "snapshots":
         snapshot_comparison(args)
+        return
+    if args.mode == "dynamic":
+        dynamic_comparison(args)
         return
 
     import paper_1506_04383_amd as mm

@@ -524,15 +524,30 @@ def layout(g, p: Params, init_xy=None):
     edge_w).  Returns (x[n,2] FP64, stats)."""
     g0 = Level(_i32(g.row_ptr), _i32(g.col), _i32(getattr(g, "node_w", None)),
                _i32(getattr(g, "edge_w", None)))
+    if init_xy is not None:
+        # warm start on the finest level only (the update algorithm of Sec.
+        # 4.3); with approx_h > 0 the coarsening stops after h levels, whose
+        # last graph serves the cluster far field of Eq. 3
+        far = None
+        info = []
+        if p.approx_h > 0:
+            levels, clusters, info = hierarchy(g0, replace(p, max_levels=min(p.max_levels,
+                                                                             p.approx_h)))
+            L = len(levels) - 1
+            if L > 0:
+                clh = clusters[0]
+                for j in range(1, L):
+                    clh = clusters[j][clh]
+                args = (g0.c, clusters[0], levels[1].n, clh, levels[L].n, p.q)
+                far = lambda xx, a=args: cluster_far_field(xx, *a)
+        stats = {"levels": [], "hierarchy": info}
+        x, st = refine(g0, 0, np.asarray(init_xy, dtype=np.float64), p,
+                       start_alpha=p.alpha_min, far=far)
+        stats["levels"].append({"level": 0, "n": g0.n, **st})
+        return x, stats
     levels, clusters, info = hierarchy(g0, p)
     L = len(levels) - 1
     stats = {"levels": [], "hierarchy": info}
-    if init_xy is not None:
-        # warm start on the finest level only (dynamic update)
-        x, st = refine(levels[0], 0, np.asarray(init_xy, dtype=np.float64), p,
-                       start_alpha=p.alpha_min)
-        stats["levels"].append({"level": 0, "n": levels[0].n, **st})
-        return x, stats
     x = init_layout(levels[L].n, p.seed, L)
     if levels[L].n == 2:
         x = place_pair(x, levels[L], L, p)

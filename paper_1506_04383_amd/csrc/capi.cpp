@@ -830,13 +830,18 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
     // ---- hierarchy (Section 3.1)
     std::vector<mm::DevBuf> clusters;
     auto t0 = std::chrono::steady_clock::now();
-    if (!init_xy) {
+    // a warm start refines only the finest level; with approx_h > 0 it still
+    // needs the graphs h levels beneath for the cluster far field, so the
+    // coarsening stops after h levels (the update protocol of Sec. 4.3)
+    const bool cut = init_xy && p->approx_h > 0;
+    const int32_t max_lv = cut ? std::min(p->max_levels, p->approx_h) : p->max_levels;
+    if (!init_xy || cut) {
       double cV = 0;
       if (h_c.empty()) cV = (double)n;
       else for (int32_t v = 0; v < n; ++v) cV += h_c[v];
       double f = p->f;
       int32_t h = 1, redo = 0;
-      while ((int32_t)levels.size() - 1 < p->max_levels &&
+      while ((int32_t)levels.size() - 1 < max_lv &&
              levels.back()->g.n > std::max(p->coarsest_n, 2)) {
         LevelGraph& L = *levels.back();
         const double W = std::min(std::pow(p->b, (double)h), cV / f);
@@ -868,11 +873,12 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
     }
     t_coarsen = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     const int32_t Lmax = (int32_t)levels.size() - 1;
-    st.levels = Lmax + 1;
+    const int32_t top = init_xy ? 0 : Lmax;  // finest-only refinement for a warm start
+    st.levels = top + 1;
 
     // ---- placement of the coarsest level
     mm::DevBuf xa, xb, F, d2;
-    const int32_t nL = levels[Lmax]->g.n;
+    const int32_t nL = levels[top]->g.n;
     HIPCHK(xa.alloc(sizeof(float) * 2 * (size_t)nL, s));
     if (init_xy) {
       HIPCHK(hipMemcpyAsync(xa.p, init_xy, sizeof(float) * 2 * (size_t)n,
@@ -899,10 +905,10 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
     HIPCHK(d2.alloc(2 * sizeof(double), s));
 
     // ---- level loop (Section 3.2)
-    for (int32_t lvl = Lmax; lvl >= 0; --lvl) {
+    for (int32_t lvl = top; lvl >= 0; --lvl) {
       mm::GraphDev& G = levels[lvl]->g;
       const int32_t nl = G.n;
-      if (lvl < Lmax) {
+      if (lvl < top) {
         HIPCHK(xb.alloc(sizeof(float) * 2 * (size_t)nl, s));
         HIPCHK(mm::prolong(nl, clusters[lvl].as<int32_t>(), levels[lvl + 1]->g.c, xa.as<float>(),
                            p->seed, lvl, xb.as<float>(), s));

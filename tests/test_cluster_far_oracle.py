@@ -102,3 +102,22 @@ def test_mulment_h_layout_close_to_exact(orc):
     Me, Ma = orc.objective(kh, xe, 0.008)["M"], orc.objective(kh, xa, 0.008)["M"]
     assert not np.array_equal(xe, xa)
     assert abs(Ma - Me) <= 0.05 * abs(Me), (Ma, Me)
+
+
+def test_update_protocol_cuts_the_hierarchy(orc):
+    """Sec. 4.3 update algorithm: a warm start refines the finest level at
+    alpha_min only; with approx_h = h the coarsening stops after h levels and
+    the last of them gives the representatives.  On an unchanged graph the
+    update continues the optimisation at alpha_min, so the maxent-stress does
+    not rise."""
+    g = synth.grid(16, 16)
+    kw = dict(k=2, alpha_decay=0.5, coarsest_n=4, max_final_iters=40)
+    x0, _ = orc.layout(g, orc.Params(theta=-1, approx_h=2, **kw))
+    x1, st = orc.layout(g, orc.Params(theta=-1, approx_h=2, **kw), init_xy=x0)
+    assert len(st["hierarchy"]) == 2 and len(st["levels"]) == 1
+    x2, st2 = orc.layout(g, orc.Params(theta=-1, **kw), init_xy=x0)
+    assert len(st2["hierarchy"]) == 0
+    assert not np.array_equal(x1, x2)  # Eq. 3 vs the exact far field
+    kh = orc.khop_build(g.row_ptr, g.col, 2)
+    m0, m1 = orc.objective(kh, x0, 0.008)["M"], orc.objective(kh, x1, 0.008)["M"]
+    assert m1 <= m0, (m0, m1)

@@ -124,3 +124,26 @@ def test_mulment_h_layout_matches_oracle(orc, mm, ctx, name, h):
     mo = orc.objective(kh, xo, 0.008)["M"]
     print(f"  M gpu {mg:.6g} oracle {mo:.6g}", flush=True)
     assert abs(mg - mo) <= 0.01 * abs(mo)
+
+
+@pytest.mark.parametrize("h", [2, 7])
+def test_update_protocol_matches_oracle(orc, mm, ctx, h):
+    """Warm start of a churned RGG at alpha_min with the hierarchy cut at h
+    levels (Sec. 4.3): maxent-stress within 1% of the oracle's update."""
+    g = synth.rgg(3000, 11)
+    q = synth.churn_snapshot(g, 12, 0.05, 2)
+    kw = dict(k=3, theta=0.5, alpha_decay=0.5, coarsest_n=20, seed=4, approx_h=h)
+    xg0, _ = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(**kw))
+    x0 = xg0.cpu().numpy()
+    dq = ctx.graph(q.row_ptr, q.col)
+    xu, st = mm.layout(ctx, dq, mm.Params(**kw), init_xy=x0)
+    xu2, _ = mm.layout(ctx, dq, mm.Params(**kw), init_xy=x0)
+    assert st["levels"] == 1
+    assert np.array_equal(xu.cpu().numpy(), xu2.cpu().numpy())
+    xo, sto = orc.layout(q, orc.Params(**kw), init_xy=x0.astype(np.float64))
+    assert len(sto["hierarchy"]) <= h
+    kh = orc.khop_build(q.row_ptr, q.col, 3)
+    mg = orc.objective(kh, xu.cpu().numpy().astype(np.float64), 0.008)["M"]
+    mo = orc.objective(kh, xo, 0.008)["M"]
+    print(f"  h={h} M gpu {mg:.6g} oracle {mo:.6g}", flush=True)
+    assert abs(mg - mo) <= 0.01 * abs(mo)
