@@ -425,6 +425,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
+    ap.add_argument("--full-stress", action="store_true",
+                    help="also compute the full stress F(x) over all pairs (one BFS per vertex "
+                         "on the GPU) at the optimal scale")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: the sweep configuration of every level is timed and chosen during "
                          "the first layout (the warm-up) and reused by the timed ones")
@@ -576,10 +579,17 @@ def main():
                      "bytes_per_launch": bytes0, "avg_ms": sweep_avg_ms},
     }
     if not args.no_objective:
+        t1 = time.perf_counter()
         kh = mm.khop_build(ctx, dg, wl["k"])
         o = mm.objective(ctx, kh, xy, p.alpha_min, p.q)
         kh.free()
         out["final_maxent_stress"] = o["M"]
+        out["objective_s"] = time.perf_counter() - t1
+    if args.full_stress:
+        t1 = time.perf_counter()
+        fs = mm.full_stress(ctx, dg, xy)
+        out["full_stress"] = {"F": fs["F"], "s_opt": fs["s_opt"], "pairs": g.n * (g.n - 1) // 2,
+                              "seconds": time.perf_counter() - t1}
     if not args.no_cpu_baseline:
         x = xy.cpu().numpy().astype(np.float64)
         F = mm.repulsion(ctx, xy, p.q, p.theta)["F"].cpu().numpy().astype(np.float64)

@@ -152,6 +152,51 @@ def test_sweep_replay(orc, mm, ctx, name, k, level, mode):
 
 
 @pytest.mark.parametrize("mode", [1, 2], ids=["rows", "tiled"])
+@pytest.mark.parametrize("name,k,level,q", [("rgg4k", 3, 0, 1.0), ("rmat12", 2, 1, 0.5)])
+def test_sweep_q_nonzero(orc, mm, ctx, name, k, level, q, mode):
+    """Eq. 2 with the power entropies of the general model (q != 0)."""
+    g = _graphs()[name]()
+    print(f"[sweep q] {name} k={k} level={level} q={q} mode={mode}", flush=True)
+    rng = np.random.default_rng(17)
+    x = (rng.random((g.n, 2)) * math.sqrt(g.n)).astype(np.float32)
+    c = rng.integers(1, 9, g.n).astype(np.int32) if level > 0 else None
+    kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), k)
+    F = mm.repulsion(ctx, x, q, 0.5)["F"]
+    xo, d = mm.sweep(ctx, kh, x, F, 0.37, q, level, c, 1.0, mode=mode)
+    ref = orc.khop_build(g.row_ptr, g.col, k)
+    xr, dr = orc.sweep(ref, x.astype(np.float64), F.cpu().numpy().astype(np.float64), 0.37, q,
+                       level, c, 1.0)
+    err = np.abs(xo.cpu().numpy() - xr) / np.maximum(np.abs(xr), 1.0)
+    print(f"  max err {err.max():.3e}", flush=True)
+    assert err.max() < 1e-4
+    assert abs(math.sqrt(d[0] / d[1]) - dr) <= 1e-3 * dr + 1e-7
+
+
+def test_barnes_hut_q_nonzero(orc, mm, ctx):
+    x = _layout_points(3000, 21)
+    r = mm.repulsion(ctx, x, 1.0, 0.5, export=True)
+    ref = orc.barnes_hut(x.astype(np.float64), 0.5, 1.0)
+    assert np.array_equal(r["nodes"].cpu().numpy(), ref.nodes)
+    assert r["accepted"] == ref.accepted and r["leaf_pairs"] == ref.leaf_pairs
+    assert _far_err(r["F"].cpu().numpy(), ref.F) < 1e-4
+
+
+@pytest.mark.parametrize("theta", [-1.0, 0.5])
+def test_layout_q_nonzero_matches_oracle(orc, mm, ctx, theta):
+    """General model, q = 1: 32x32 grid, k = 3; maxent-stress (E_1 entropy)
+    within 1% of the oracle."""
+    g = synth.grid(32, 32)
+    kw = dict(k=3, q=1.0, theta=theta, alpha_decay=0.5, max_levels=3, seed=6)
+    xg, _ = mm.layout(ctx, ctx.graph(g.row_ptr, g.col), mm.Params(**kw))
+    xo, _ = orc.layout(g, orc.Params(**kw))
+    kh = orc.khop_build(g.row_ptr, g.col, 3)
+    mg = orc.objective(kh, xg.cpu().numpy().astype(np.float64), 0.008, 1.0)["M"]
+    mo = orc.objective(kh, xo, 0.008, 1.0)["M"]
+    print(f"  q=1 theta={theta}: M gpu {mg:.6g} oracle {mo:.6g}", flush=True)
+    assert abs(mg - mo) <= 0.01 * abs(mo)
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["rows", "tiled"])
 def test_sweep_deterministic(mm, ctx, mode):
     g = synth.rmat(14, 8 * (1 << 14), 3)
     kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), 2)

@@ -243,28 +243,31 @@ def test_translation_rotation_invariance(orc):
     assert np.max(np.abs(T(x @ R.T) - base @ R.T)) < 1e-12 * 20
 
 
-def _fd_grad(orc, kh, x, alpha, h=1e-6):
+def _fd_grad(orc, kh, x, alpha, h=1e-6, q=0.0):
     g = np.zeros_like(x)
     for i in range(x.shape[0]):
         for j in range(2):
             xp = x.copy(); xp[i, j] += h
             xm = x.copy(); xm[i, j] -= h
-            g[i, j] = (orc.objective(kh, xp, alpha)["M"] - orc.objective(kh, xm, alpha)["M"]) / (2 * h)
+            g[i, j] = (orc.objective(kh, xp, alpha, q)["M"] -
+                       orc.objective(kh, xm, alpha, q)["M"]) / (2 * h)
     return g
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_update_is_gradient_step_of_objective(orc, k):
+@pytest.mark.parametrize("k,q", [(1, 0.0), (2, 0.0), (2, 1.0), (1, 0.5)])
+def test_update_is_gradient_step_of_objective(orc, k, q):
     """Eq. 1 vs Eq. 2: grad_u M_{2 alpha}(x) = 2 rho_u (x_u - T_alpha(x)_u) at any
-    layout; the update and the objective are independent code paths."""
+    layout, for the logarithmic entropy (q = 0) and the power entropies
+    E_q = -D^-q / q of the general model (their gradient is r_q); the update
+    and the objective are independent code paths."""
     g = synth.grid(4, 5)
     kh = orc.khop_build(g.row_ptr, g.col, k)
     x = orc.init_layout(g.n, 9, 0) * 4
     alpha = 0.2
-    Tx, _ = orc.sweep(kh, x, orc.farfield_exact(x), alpha)
+    Tx, _ = orc.sweep(kh, x, orc.farfield_exact(x, q), alpha, q)
     rho = np.array([np.sum(1.0 / kh.hops(u).astype(float) ** 2) for u in range(g.n)])
     grad = 2 * rho[:, None] * (x - Tx)
-    fd = _fd_grad(orc, kh, x, 2 * alpha)
+    fd = _fd_grad(orc, kh, x, 2 * alpha, q=q)
     assert np.max(np.abs(grad)) > 1.0
     assert np.max(np.abs(fd - grad)) < 1e-5 * np.max(np.abs(grad))
 
