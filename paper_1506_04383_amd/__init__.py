@@ -93,7 +93,7 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
            "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg",
-           "mm_repulsion_cluster"]
+           "mm_repulsion_cluster", "mm_full_stress_ex"]
 
 TUNE_FIELDS = 7  # coarse?, n, sum |S|, k, tile bits, lanes, blocks per step
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
@@ -132,6 +132,7 @@ def lib():
         "mm_prolong": [vp, i32, vp, vp, vp, u64, i32, vp],
         "mm_objective": [vp, vp, i32, vp, f64, vp, f64, vp],
         "mm_full_stress": [vp, P(MMGraph), vp, vp],
+        "mm_full_stress_ex": [vp, P(MMGraph), vp, i32, vp],
         "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
         "mm_layout_batch": [vp, i32, vp, P(MMGraph), P(MMParams), vp, vp, vp, P(MMStats)],
         "mm_tune_clear": [vp],
@@ -572,10 +573,13 @@ def objective(ctx: Context, kh: KHop, xy, alpha: float, q: float = 0.0, level: i
             "M": out[0] - alpha * out[1]}
 
 
-def full_stress(ctx: Context, g: DeviceGraph, xy) -> dict:
+def full_stress(ctx: Context, g: DeviceGraph, xy, method: int = 0) -> dict:
+    """Full stress at the optimal scale; method 0 auto, 1 multi-source BFS,
+    2 one BFS per source (mm_full_stress_ex)."""
     t = ctx.torch
     xy = ctx._dev(xy, t.float32)
     out = np.zeros(3)
     gc = g.c()
-    _check(lib().mm_full_stress(ctx.h, C.byref(gc), _ptr(xy), out.ctypes.data_as(C.c_void_p)))
+    _check(lib().mm_full_stress_ex(ctx.h, C.byref(gc), _ptr(xy), int(method),
+                                   out.ctypes.data_as(C.c_void_p)))
     return {"F_unscaled": out[0], "s_opt": out[1], "F": out[2]}

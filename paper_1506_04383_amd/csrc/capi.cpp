@@ -734,21 +734,33 @@ mm_status mm_objective(mm_context* ctx, const mm_khop* kh, int32_t level, const 
   }
 }
 
-mm_status mm_full_stress(mm_context* ctx, const mm_graph* g, const float* xy, double* out) {
+mm_status mm_full_stress_ex(mm_context* ctx, const mm_graph* g, const float* xy, int32_t method,
+                            double* out) {
   try {
     if (!ctx || !g || !xy || !out) return fail(MM_EINVAL, "NULL argument");
     if (g->mem != MM_DEVICE) return fail(MM_EINVAL, "mm_full_stress needs a device graph");
-    if (g->n > 1179648) return fail(MM_EUNSUPPORTED, "full stress limited to n <= 1179648");
+    if (method < 0 || method > 2) return fail(MM_EINVAL, "method must be 0, 1 or 2");
+    if (g->n < 1) return fail(MM_EINVAL, "n < 1");
+    if (method == 2 && g->n > 1179648)
+      return fail(MM_EUNSUPPORTED, "one BFS per source is limited to n <= 1179648");
     DeviceGuard dg(ctx->device);
     mm::GraphDev G;
     G.n = g->n; G.nnz = g->nnz;
     G.row_ptr = const_cast<int32_t*>(g->row_ptr);
     G.col = const_cast<int32_t*>(g->col);
-    HIPCHK(mm::full_stress(G, xy, out, ctx->stream));
+    const hipError_t e = mm::full_stress(G, xy, out, ctx->stream, method);
+    if (e == hipErrorInvalidValue)
+      return fail(MM_EUNSUPPORTED, "graph too large for one BFS per source and of too high a "
+                                   "diameter for the multi-source BFS");
+    HIPCHK(e);
     return MM_OK;
   } catch (...) {
     return fail(MM_EINTERNAL, "exception in mm_full_stress");
   }
+}
+
+mm_status mm_full_stress(mm_context* ctx, const mm_graph* g, const float* xy, double* out) {
+  return mm_full_stress_ex(ctx, g, xy, 0, out);
 }
 
 // ---------------------------------------------------------------- layout

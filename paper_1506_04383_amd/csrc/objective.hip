@@ -174,7 +174,137 @@ __global__ __launch_bounds__(FS_T) void k_full_stress(int32_t n, const int32_t* 
   }
 }
 
+// ---- full stress by bit-parallel multi-source BFS (low-diameter graphs)
+// A batch of MS_B = 256 sources advances one level per launch: vertex v's
+// sources-reached mask (4 x 64 bits) grows by the OR of its neighbours'
+// frontier masks; each newly reached (source, v) pair at level h adds its
+// terms with d = h to v's own FP64 accumulators (one wave per vertex, so each
+// accumulator has one writer and a fixed order).  Ordered pairs: every
+// unordered pair is counted from both ends and the sums are halved.
+constexpr int MS_W = 4;           // 64-bit words per vertex mask
+constexpr int MS_B = 64 * MS_W;   // sources per batch
+
+__global__ void k_ms_init(int32_t n, int32_t s0, uint64_t* __restrict__ vis,
+                          uint64_t* __restrict__ fr) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t b = v - s0;
+#pragma unroll
+  for (int w = 0; w < MS_W; ++w) {
+    const uint64_t m = (b >= 0 && b < MS_B && (b >> 6) == w) ? (1ull << (b & 63)) : 0ull;
+    vis[(size_t)v * MS_W + w] = m;
+    fr[(size_t)v * MS_W + w] = m;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ms_step(
+    int32_t n, int32_t s0, int32_t h, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ col, const float2* __restrict__ xy,
+    const uint64_t* __restrict__ fr, uint64_t* __restrict__ nx, uint64_t* __restrict__ vis,
+    double* __restrict__ acc, int32_t* __restrict__ more) {
+  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = lane_id();
+  if (v >= n) return;
+  uint64_t a[MS_W] = {0ull, 0ull, 0ull, 0ull};
+  for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 64) {
+    const uint64_t* f = fr + (size_t)col[e] * MS_W;
+#pragma unroll
+    for (int w = 0; w < MS_W; ++w) a[w] |= f[w];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int w = 0; w < MS_W; ++w) a[w] |= __shfl_xor(a[w], o, 64);
+  uint64_t nw[MS_W];
+  bool any = false;
+#pragma unroll
+  for (int w = 0; w < MS_W; ++w) {
+    nw[w] = a[w] & ~vis[(size_t)v * MS_W + w];
+    any |= nw[w] != 0ull;
+  }
+  if (l < MS_W) {
+    nx[(size_t)v * MS_W + l] = nw[l];
+    vis[(size_t)v * MS_W + l] |= nw[l];
+  }
+  if (!any) return;
+  if (l == 0) *more = 1;
+  // pair terms: lane l takes source bit l of every word
+  const float2 xv = xy[v];
+  const double d = (double)h;
+  double a1 = 0.0, a2 = 0.0, a0 = 0.0, np = 0.0;
+#pragma unroll
+  for (int w = 0; w < MS_W; ++w) {
+    if ((nw[w] >> l) & 1ull) {
+      const float2 xs = xy[s0 + 64 * w + l];
+      const double dx = (double)xs.x - (double)xv.x, dy = (double)xs.y - (double)xv.y;
+      const double D = sqrt(dx * dx + dy * dy);
+      a1 += D / d;
+      a2 += (D / d) * (D / d);
+      a0 += (D - d) * (D - d) / (d * d);
+      np += 1.0;
+    }
+  }
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  a0 = wave_sum(a0);
+  np = wave_sum(np);
+  if (l == 0) {
+    acc[4 * (size_t)v] += a1;
+    acc[4 * (size_t)v + 1] += a2;
+    acc[4 * (size_t)v + 2] += a0;
+    acc[4 * (size_t)v + 3] += np;
+  }
+}
+
 }  // namespace
+
+// Returns false in *done (and leaves out_host alone) when the first batch
+// needs more than max_levels levels: a high-diameter graph, for which the
+// per-source kernel is the better choice.
+hipError_t full_stress_msbfs(const GraphDev& g, const float* xy, int32_t max_levels,
+                             double* out_host, bool* done, hipStream_t s) {
+  const int32_t n = g.n;
+  *done = false;
+  DevBuf vis, fr, nx, acc, more;
+  MM_TRY(vis.alloc(sizeof(uint64_t) * MS_W * (size_t)n, s));
+  MM_TRY(fr.alloc(sizeof(uint64_t) * MS_W * (size_t)n, s));
+  MM_TRY(nx.alloc(sizeof(uint64_t) * MS_W * (size_t)n, s));
+  MM_TRY(acc.alloc(sizeof(double) * 4 * (size_t)n, s));
+  MM_TRY(more.alloc(sizeof(int32_t), s));
+  MM_TRY(hipMemsetAsync(acc.p, 0, sizeof(double) * 4 * (size_t)n, s));
+  const unsigned nb = (unsigned)((n + 255) / 256), nw = (unsigned)((n + 3) / 4);
+  for (int32_t s0 = 0; s0 < n; s0 += MS_B) {
+    k_ms_init<<<nb, 256, 0, s>>>(n, s0, vis.as<uint64_t>(), fr.as<uint64_t>());
+    MM_TRY(hipGetLastError());
+    for (int32_t h = 1;; ++h) {
+      if (s0 == 0 && h > max_levels) return hipStreamSynchronize(s);  // *done stays false
+      MM_TRY(hipMemsetAsync(more.p, 0, sizeof(int32_t), s));
+      k_ms_step<<<nw, 256, 0, s>>>(n, s0, h, g.row_ptr, g.col, (const float2*)xy,
+                                   fr.as<uint64_t>(), nx.as<uint64_t>(), vis.as<uint64_t>(),
+                                   acc.as<double>(), more.as<int32_t>());
+      MM_TRY(hipGetLastError());
+      std::swap(fr, nx);
+      int32_t hm = 0;
+      MM_TRY(hipMemcpyAsync(&hm, more.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      MM_TRY(hipStreamSynchronize(s));
+      if (!hm) break;
+    }
+  }
+  std::vector<double> h(4 * (size_t)n);
+  MM_TRY(hipMemcpyAsync(h.data(), acc.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  double s1 = 0, s2 = 0, s0s = 0, np = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    s1 += h[4 * u]; s2 += h[4 * u + 1]; s0s += h[4 * u + 2]; np += h[4 * u + 3];
+  }
+  s1 *= 0.5; s2 *= 0.5; s0s *= 0.5; np *= 0.5;  // ordered -> unordered pairs
+  const double sstar = s2 > 0 ? s1 / s2 : 1.0;
+  out_host[0] = s0s;
+  out_host[1] = sstar;
+  out_host[2] = sstar * sstar * s2 - 2.0 * sstar * s1 + np;
+  *done = true;
+  return hipSuccess;
+}
 
 hipError_t objective(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                      const float* xy, double q, double* out_host, hipStream_t s) {
@@ -202,9 +332,17 @@ hipError_t objective(const KhopDev& kh, int32_t level, const float* sqrtc, doubl
   return hipSuccess;
 }
 
-hipError_t full_stress(const GraphDev& g, const float* xy, double* out_host, hipStream_t s) {
+hipError_t full_stress(const GraphDev& g, const float* xy, double* out_host, hipStream_t s,
+                       int32_t method) {
   const int32_t n = g.n;
   const int32_t W = (n + 31) >> 5;
+  // large graphs of low diameter: the multi-source BFS (tried first, given up
+  // after 64 levels of its first batch)
+  if (method == 1 || (method == 0 && n > 65536)) {
+    bool done = false;
+    MM_TRY(full_stress_msbfs(g, xy, method == 1 ? INT32_MAX : 64, out_host, &done, s));
+    if (done) return hipSuccess;
+  }
   if (W > FS_MAXW) return hipErrorInvalidValue;
   int dev = 0, ncu = 0;
   MM_TRY(hipGetDevice(&dev));

@@ -254,13 +254,29 @@ def test_objective_parity(orc, mm, ctx, k, level):
         assert abs(o[key] - r[key]) <= 1e-5 * abs(r[key]), key
 
 
-def test_full_stress_parity(orc, mm, ctx):
-    g = synth.rgg(2500, 4)
+@pytest.mark.parametrize("name,method", [("rgg2500", 2), ("rgg2500", 1), ("rmat12", 1),
+                                         ("rmat12", 2), ("tree", 1)])
+def test_full_stress_parity(orc, mm, ctx, name, method):
+    """One BFS per source (method 2) and the bit-parallel multi-source BFS
+    (method 1, 256 sources per pass, ragged last pass) vs the oracle."""
+    g = synth.rgg(2500, 4) if name == "rgg2500" else _graphs()[name]()
     x = _layout_points(g.n, 5)
-    o = mm.full_stress(ctx, ctx.graph(g.row_ptr, g.col), x)
+    o = mm.full_stress(ctx, ctx.graph(g.row_ptr, g.col), x, method=method)
     r = orc.full_stress(g.row_ptr, g.col, x.astype(np.float64))
     for key in ("F_unscaled", "s_opt", "F"):
         assert abs(o[key] - r[key]) <= 1e-6 * abs(r[key]), key
+
+
+def test_full_stress_msbfs_large(mm, ctx):
+    """Auto method on R-MAT 2^16 (low diameter: the multi-source BFS) equals
+    one BFS per source up to the order of the FP64 sums."""
+    g = synth.rmat(16, 8 * (1 << 16), 2)
+    x = _layout_points(g.n, 8)
+    dg = ctx.graph(g.row_ptr, g.col)
+    a = mm.full_stress(ctx, dg, x, method=0)
+    b = mm.full_stress(ctx, dg, x, method=2)
+    for key in ("F_unscaled", "s_opt", "F"):
+        assert abs(a[key] - b[key]) <= 1e-9 * abs(b[key]), key
 
 
 def test_layout_small_config_end_to_end(orc, mm, ctx):
