@@ -360,7 +360,10 @@ def sweep_bytes(n: int, k: int, entries: int, coarse: bool) -> int:
     return 4 * entries + n * per_v + 8 * n
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_tiled_rmat20_traffic.md")
+# copy-calibrated HBM traffic of the finest-level sweep step, per sweep kernel
+TRAFFIC_PROFILES = {"sliced": os.path.join(ROOT, "profiles", "k_sweep_sliced_rmat20_traffic.md"),
+                    "tiled": os.path.join(ROOT, "profiles", "k_sweep_tiled_rmat20_traffic.md")}
+SLICED_GROUP = 64  # lanes code of the sliced layout in the per-level statistics
 # Autotuner choices measured on MI355X for the bench workloads (written by
 # --save-tune-db); loading them makes the timed layouts use a fixed, known
 # sweep configuration per level.
@@ -374,10 +377,11 @@ def measured_traffic(workload: str, tile_bits: int, group: int, blocks: int):
     kernel source changed since the counters were taken."""
     import hashlib
 
-    if workload != "rmat20" or not os.path.exists(TRAFFIC_PROFILE):
+    prof = TRAFFIC_PROFILES["sliced" if group == SLICED_GROUP else "tiled"]
+    if workload != "rmat20" or not os.path.exists(prof):
         return None
     kv = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(prof):
         if ":" in line and not line.startswith(("|", "#", " ", "`")):
             key, _, val = line.partition(":")
             kv[key.strip()] = val.strip()
@@ -571,7 +575,11 @@ def main():
                       for l in st["per_level"]],
         "autotune": {"enabled": args.autotune, "tuning_ms_in_timed_step": st["t_tune_ms"],
                      "records_loaded": tune_loaded},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep_tiled + k_combine (finest-level sweep step)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_sweep_sliced" if L0["group"] == SLICED_GROUP and L0["tile_bits"]
+                                else "k_sweep_tiled" if L0["tile_bits"] else "k_sweep")
+                               + (" + k_combine" if L0["tile_bits"] else "")
+                               + " (finest-level sweep step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, L0["tile_bits"], L0["group"],

@@ -125,8 +125,8 @@ mm_status mm_tune_clear(mm_context* ctx);
  * mm_tune_export writes at most cap records to recs (host) and the number
  * the context holds to *count (so cap = 0 asks for the size).
  * mm_tune_import adds or replaces count records; a record whose tile bits
- * are not 0 or 11..13, whose lanes are not a power of two in 4..64 (8..64 for
- * the row kernel, 4..16 tiled), or whose blocks are not 0 (row kernel) or
+ * are not 0 or 11..13, whose lanes are not a power of two in 1..64 (8..64 for
+ * the row kernel, 1..16 tiled), or whose blocks are not 0 (row kernel) or
  * 0, 2, 4 (tiled; 0 = the default rule) is rejected with MM_EINVAL and
  * nothing is imported.  Used to keep a tuned
  * configuration across processes. */
@@ -278,8 +278,8 @@ mm_status mm_sweep_ex(mm_context* ctx, mm_khop* kh, int32_t level, const int32_t
 /* As mm_sweep_ex with the configuration forced, the way the autotuner runs
  * its candidates: tile_bits = 0 runs the row kernel with group lanes per row
  * (8, 16, 32 or 64; blocks must be 0); tile_bits = 11, 12 or 13 runs the
- * tiled kernel with tiles of 2^tile_bits vertices, group lanes per chunk (4,
- * 8 or 16) and blocks 16-byte entry blocks per lane and step (2 or 4; 0 = the
+ * tiled kernel with tiles of 2^tile_bits vertices, group lanes per chunk (1,
+ * 2, 4, 8 or 16) and blocks 16-byte entry blocks per lane and step (2 or 4; 0 = the
  * default rule).  Any other combination is MM_EINVAL; tiled configurations the sets do not allow (k > 7, too
  * many tiles) are MM_EUNSUPPORTED.  The update is the same for every
  * configuration up to the order of FP32 summation. */

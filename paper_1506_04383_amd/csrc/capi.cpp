@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -173,7 +174,7 @@ hipError_t time_variant(mm_context* ctx, hipStream_t s, int reps, F&& launch, fl
 
 // Autotuner of one level's sweep: every eligible configuration -- the row
 // kernel with 8/16/32/64 lanes per row, the tiled kernel with tiles of 2^11,
-// 2^12, 2^13 vertices, 4/8/16 lanes per chunk and 2/4 blocks per lane and
+// 2^12, 2^13 vertices, 1/2/4/8/16 lanes per chunk and 2/4 blocks per lane and
 // step -- is run on the level's own
 // sets and coordinates (far field zero, alpha 1, output to scratch) and the
 // fastest is kept.  Row-kernel candidates are skipped on levels whose sets are
@@ -186,6 +187,9 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
   float best = INFINITY;
   mm_context::TuneChoice bc{0, mm::row_group(kh), 0};
   const int reps = kh.total > (1ll << 28) ? 1 : 3;
+  // MM_TUNE_VERBOSE=1 prints every candidate's time to stderr
+  const char* ev = std::getenv("MM_TUNE_VERBOSE");
+  const bool verbose = ev && ev[0] == '1';
   if (kh.total <= (1ll << 30)) {
     mm::DevBuf part;
     for (int32_t G : {8, 16, 32, 64}) {
@@ -194,6 +198,9 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
         return mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xa, F, 1.0, p->q, xb, d2, s, nullptr,
                          nullptr, nullptr, &part, G);
       }, &ms));
+      if (verbose)
+        std::fprintf(stderr, "[tune] level %d n %d sets %lld rows lanes %d: %.4f ms\n", lvl, nl,
+                     (long long)kh.total, G, ms);
       if (ms < best) { best = ms; bc = {0, G, 0}; }
     }
   }
@@ -209,15 +216,34 @@ mm_status tune_level(mm_context* ctx, mm::KhopDev& kh, int32_t lvl, const float*
     mm::TiledSet ts;
     HIPCHK(mm::tiled_build(kh, tb, 0.0, &ts, s));
     if (!ts.built) continue;
-    for (int32_t G : {4, 8, 16}) {
+    for (int32_t G : {1, 2, 4, 8, 16}) {
       for (int32_t NB : {2, 4}) {
         float ms = 0;
         HIPCHK(time_variant(ctx, s, reps, [&]() {
           return mm::sweep_tiled(ts, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa, F,
                                  1.0, p->q, xb, d2, s, nullptr, G, NB);
         }, &ms));
+        if (verbose)
+          std::fprintf(stderr, "[tune] level %d n %d sets %lld tiled tbits %d lanes %d blocks %d: %.4f ms\n",
+                       lvl, nl, (long long)kh.total, tb, G, NB, ms);
         if (ms < best) { best = ms; bc = {tb, G, NB}; }
       }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    // the sliced layout of the same tiles
+    mm::TiledSet tsl;
+    HIPCHK(mm::tiled_build(kh, tb, 0.0, &tsl, s, nullptr, 1.0, nullptr, true));
+    if (!tsl.built) continue;
+    for (int32_t NB : {2, 4}) {
+      float ms = 0;
+      HIPCHK(time_variant(ctx, s, reps, [&]() {
+        return mm::sweep_tiled(tsl, lvl, sqrtc, p->coarse_dist_scale, rho.as<float>(), xa, F,
+                               1.0, p->q, xb, d2, s, nullptr, mm::kSlicedGroup, NB);
+      }, &ms));
+      if (verbose)
+        std::fprintf(stderr, "[tune] level %d n %d sets %lld sliced tbits %d blocks %d: %.4f ms\n",
+                     lvl, nl, (long long)kh.total, tb, NB, ms);
+      if (ms < best) { best = ms; bc = {tb, mm::kSlicedGroup, NB}; }
     }
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -251,7 +277,10 @@ mm_status sweep_common(mm_context* ctx, mm_khop* kh, int32_t level, const int32_
     if (mode != MM_SWEEP_ROWS) {
       const bool ok = mm::tiled_eligible(kh->kh, tb);
       if (mode == MM_SWEEP_TILED && !ok) return fail(MM_EUNSUPPORTED, "tiled sweep needs k <= 7 and n <= 2^25");
-      if (ok && tb != mm::kTileBits) {
+      if (ok && group == mm::kSlicedGroup) {
+        HIPCHK(mm::tiled_build(kh->kh, tb, 0.0, &own, s, nullptr, 1.0, nullptr, true));
+        if (own.built) ts = &own;
+      } else if (ok && tb != mm::kTileBits) {
         HIPCHK(mm::tiled_build(kh->kh, tb, 0.0, &own, s));
         if (own.built) ts = &own;
       } else if (ok) {
@@ -323,8 +352,8 @@ mm_status mm_tune_import(mm_context* ctx, const int64_t* recs, int32_t count) {
   for (int32_t i = 0; i < count; ++i) {
     const int64_t* r = recs + (size_t)i * MM_TUNE_FIELDS;
     const bool tb_ok = r[4] == 0 || (r[4] >= 11 && r[4] <= 13);
-    const bool g_ok = r[5] >= 4 && r[5] <= 64 && (r[5] & (r[5] - 1)) == 0 &&
-                      (r[4] == 0 ? r[5] >= 8 : r[5] <= 16);
+    const bool g_ok = r[5] >= 1 && r[5] <= 64 && (r[5] & (r[5] - 1)) == 0 &&
+                      (r[4] == 0 ? r[5] >= 8 : (r[5] <= 16 || r[5] == mm::kSlicedGroup));
     const bool nb_ok = r[4] == 0 ? r[6] == 0 : (r[6] == 0 || r[6] == 2 || r[6] == 4);
     if (!tb_ok || !g_ok || !nb_ok || (r[0] != 0 && r[0] != 1) || r[1] < 0 || r[1] > INT32_MAX || r[2] < 0 ||
         r[3] < 1 || r[3] > INT32_MAX)
@@ -615,7 +644,8 @@ mm_status mm_sweep_cfg(mm_context* ctx, mm_khop* kh, int32_t level, const int32_
   const bool rows_ok = tile_bits == 0 && blocks == 0 &&
                        (group == 8 || group == 16 || group == 32 || group == 64);
   const bool tiled_ok = tile_bits >= 11 && tile_bits <= 13 &&
-                        (group == 4 || group == 8 || group == 16) &&
+                        (group == 1 || group == 2 || group == 4 || group == 8 || group == 16 ||
+                         group == mm::kSlicedGroup) &&
                         (blocks == 0 || blocks == 2 || blocks == 4);
   if (!rows_ok && !tiled_ok)
     return fail(MM_EINVAL, "bad sweep configuration (%d, %d, %d)", tile_bits, group, blocks);
@@ -946,8 +976,8 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       mm::DevBuf rho;
       // tile size: coarse levels stage sqrt c beside the coordinates (12 B per
       // vertex), so smaller tiles keep two or more work-groups per CU
-      int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 18) ? 12 : 11);
-      int32_t group_lvl = 0;  // 0: the kernels' own rule
+      int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 17) ? 12 : 11);
+      int32_t group_lvl = 0;  // 0: the sliced layout where tiled, else the row kernel's rule
       int32_t nb_lvl = 0;
       double min_avg = 8.0;
       if (p->autotune) {
@@ -970,7 +1000,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         auto tt = std::chrono::steady_clock::now();
         HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
         HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s, sqrtc, p->coarse_dist_scale,
-                               rho.as<float>()));
+                               rho.as<float>(), group_lvl == 0 || group_lvl == mm::kSlicedGroup));
         if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
         HIPCHK(hipStreamSynchronize(s));
         t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
@@ -1161,8 +1191,9 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         st.level_khop_ms[lvl] = khop_ms;
         st.level_tile_bits[lvl] = ts.built ? ts.tbits : 0;
         st.level_blocks[lvl] = ts.built ? (nb_lvl > 0 ? nb_lvl : mm::tiled_blocks(ts)) : 0;
-        st.level_group[lvl] = group_lvl > 0 ? group_lvl : (ts.built ? mm::tiled_group(ts)
-                                                                    : mm::row_group(kh));
+        st.level_group[lvl] = group_lvl > 0 ? group_lvl
+                                            : (ts.built ? (ts.sliced ? mm::kSlicedGroup : mm::tiled_group(ts))
+                                                        : mm::row_group(kh));
       }
       st.vertex_updates += (int64_t)nl * iters;
       if (lvl == 0) st.finest_updates = (int64_t)nl * iters;

@@ -80,10 +80,18 @@ struct TiledSet {
   int64_t* chunk_off = nullptr;  // nchunks+1: entry offsets (multiples of 8)
   int32_t* chunk_slot = nullptr; // row-major slot of each chunk
   uint16_t* ent = nullptr;       // ((v - tile * 2^tbits) << 3) | hop
-  int32_t* unit_c0 = nullptr;    // nunits+1: first chunk of each work unit
+  int32_t* unit_c0 = nullptr;    // nunits+1: first chunk (sliced: slice) of each work unit
   int32_t* unit_tile = nullptr;  // tile of each work unit
+  // sliced layout: the chunks of a tile in slices of 64; block j of the
+  // slice's chunk i at block slice_base + 64 j + i (chunk_off = the entry
+  // offset of its block 0)
+  bool sliced = false;
+  int64_t nslices = 0;
+  int32_t* slice_c0 = nullptr;   // nslices+1: first chunk of each slice
+  int32_t* slice_h = nullptr;    // blocks per chunk of the slice (its first chunk's)
+  int64_t* slice_base = nullptr; // nslices+1: first block of each slice
   DevBuf b_rc_ptr, b_chunk_row, b_chunk_off, b_chunk_slot, b_ent, b_unit_c0, b_unit_tile, b_partial,
-      b_dpart;
+      b_dpart, b_slice_c0, b_slice_h, b_slice_base;
 };
 bool tiled_eligible(const KhopDev& kh, int32_t tbits);
 // rho_u = sum_{v in S(u)} w_uv (sqrtc null: finest level, d = hop)
@@ -93,9 +101,13 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
 // min_avg_chunk it stops after counting (ts->built stays false).  With rho
 // non-null it also computes compute_rho's result (same bits) in its first
 // pass over the sets, built or not.
+// sliced: the sliced layout (k_sweep_sliced) instead of consecutive chunks.
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
                        hipStream_t s, const float* sqrtc = nullptr, double scale = 1.0,
-                       float* rho = nullptr);
+                       float* rho = nullptr, bool sliced = false);
+// lanes-per-chunk code of the sliced layout in tuner records and forced
+// configurations (one lane per chunk, 64 chunks per wave)
+constexpr int32_t kSlicedGroup = 64;
 constexpr int32_t kTileBits = 13;  // tiled sets need k <= 7 and tbits <= 13
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,

@@ -30,6 +30,7 @@ constexpr int TB_MAXTILES = 4096;    // conversion keeps per-tile counters in LD
 constexpr int TB_MAXW = TB_MAXTILES / 32;
 constexpr int TS_T = 512;            // sweep block
 constexpr int32_t UNIT_CH = 768;      // chunks per work unit (metadata staged in LDS)
+constexpr int32_t UNIT_S = 64;        // slices per work unit of the sliced layout
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -268,6 +269,72 @@ __global__ void k_unit_fill(int64_t m, const int32_t* __restrict__ flag, const i
 }
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 
+// Sliced layout.  Sorted chunk c has rank r = c - tile_first[tile] within its
+// tile; slices are the runs of 64 ranks.  flag[c] = 1 where a slice starts.
+__global__ void k_slice_flags(int64_t m, const uint64_t* __restrict__ skey,
+                              const int32_t* __restrict__ tile_first, int32_t* __restrict__ flag) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int64_t r = c - tile_first[skey[c] >> 32];
+  flag[c] = (r & 63) == 0 ? 1 : 0;
+}
+// slice s (= spos[c] at its first chunk): first chunk, height in blocks (its
+// first chunk is its longest) and the 64 h blocks it occupies
+__global__ void k_slice_fill(int64_t m, const int32_t* __restrict__ flag,
+                             const int64_t* __restrict__ spos, const int32_t* __restrict__ ssize,
+                             int32_t* __restrict__ slice_c0, int32_t* __restrict__ slice_h,
+                             int32_t* __restrict__ slice_blocks) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m || !flag[c]) return;
+  const int64_t sl = spos[c];
+  slice_c0[sl] = (int32_t)c;
+  slice_h[sl] = ssize[c] >> 3;
+  slice_blocks[sl] = (ssize[c] >> 3) * 64;
+}
+// Consecutive layout -> sliced layout: one wave per slice; lane i copies
+// the blocks of the slice's chunk i (consecutive from chunk_off[c]) to
+// slice_base + 64 j + i and writes zero blocks past its chunk's end (and for
+// lanes without a chunk), so every block of the slice is written.
+__global__ __launch_bounds__(256) void k_slice_transpose(
+    int64_t nsl, const int32_t* __restrict__ slice_c0, const int32_t* __restrict__ slice_h,
+    const int64_t* __restrict__ slice_base, const int64_t* __restrict__ chunk_off,
+    const uint4* __restrict__ src, uint4* __restrict__ dst) {
+  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sl >= nsl) return;
+  const int l = lane_id();
+  const int32_t c0 = slice_c0[sl], nc = slice_c0[sl + 1] - c0, h = slice_h[sl];
+  const bool lv = l < nc;
+  const int64_t b0 = lv ? chunk_off[c0 + l] >> 3 : 0;
+  const int32_t nb = lv ? (int32_t)((chunk_off[c0 + l + 1] >> 3) - b0) : 0;
+  uint4* __restrict__ d = dst + slice_base[sl] + l;
+  for (int32_t j = 0; j < h; ++j)
+    d[(int64_t)j * 64] = j < nb ? src[b0 + j] : make_uint4(0u, 0u, 0u, 0u);
+}
+// unit starts over slices: the first slice of a tile, every UNIT_S-th slice
+// after it, and every slice that begins a new span of emax blocks
+__global__ void k_slice_unit_flags(int32_t S, const int32_t* __restrict__ slice_c0,
+                                   const uint64_t* __restrict__ skey,
+                                   const int32_t* __restrict__ tile_first,
+                                   const int64_t* __restrict__ slice_base, int64_t emax,
+                                   int32_t* __restrict__ flag) {
+  const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= S) return;
+  const int32_t c = slice_c0[sl];
+  const int32_t rs = (c - tile_first[skey[c] >> 32]) >> 6;  // slice rank within the tile
+  flag[sl] = (rs % UNIT_S == 0 || (rs > 0 && slice_base[sl] / emax != slice_base[sl - 1] / emax))
+                 ? 1 : 0;
+}
+__global__ void k_slice_unit_fill(int32_t S, const int32_t* __restrict__ flag,
+                                  const int64_t* __restrict__ pos,
+                                  const int32_t* __restrict__ slice_c0,
+                                  const uint64_t* __restrict__ skey, int32_t* __restrict__ unit_s0,
+                                  int32_t* __restrict__ unit_tile) {
+  const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= S || !flag[sl]) return;
+  unit_s0[pos[sl]] = sl;
+  unit_tile[pos[sl]] = (int32_t)(skey[slice_c0[sl]] >> 32);
+}
+
 // rho_u = sum over S(u) of w_uv (canonical sets)
 __global__ void k_rho(int32_t n, int32_t k, const int64_t* __restrict__ off,
                       const int32_t* __restrict__ hend, const int32_t* __restrict__ nbr,
@@ -303,6 +370,54 @@ __global__ void k_rho(int32_t n, int32_t k, const int64_t* __restrict__ off,
   if (l == 0) rho[u] = r;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte block of 8 entries of one chunk (row u, one tile): decode the
+// entries, issue their LDS reads, then accumulate (branch-free) into (px, py)
+// the sum over the entries of c (x_u - x_v) with
+//   c = w d / D - alpha / D^(q+2) - w,   w = d^-2,
+// i.e. Eq. 2's numerator minus rho_u x_u (the combine adds rho_u x_u back).
+// sx: the tile's coordinates; ssc: sqrt c of the tile's vertices times the
+// distance scale (coarse levels); lut: per hop (1/hop, bias added to D^2).
+template <bool COARSE, bool Q0>
+__device__ __forceinline__ void sweep_block(const u32x4 bk, const float2* __restrict__ sx,
+                                            const float* __restrict__ ssc,
+                                            const float2* __restrict__ lut, const float2 xu,
+                                            const float scu, const float alpha, const float q,
+                                            float& px, float& py) {
+  const uint32_t wv[4] = {bk.x, bk.y, bk.z, bk.w};
+  float2 xv[8];
+  float2 lw[8];
+  float sc[8];
+#pragma unroll
+  for (int q2 = 0; q2 < 8; ++q2) {
+    const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
+    const uint32_t vl = pk >> 3;
+    xv[q2] = sx[vl];
+    lw[q2] = lut[pk & 7u];
+    if (COARSE) sc[q2] = ssc[vl];
+  }
+#pragma unroll
+  for (int q2 = 0; q2 < 8; ++q2) {
+    const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
+    const float D2 = fmaf(dx, dx, fmaf(dy, dy, lw[q2].y));
+    // w d = 1/d with d = hop (finest level) or hop (sqrt c_u + sqrt c_v)
+    // scale (coarse levels; the staged roots are pre-scaled), w = (w d)^2
+    float wd = lw[q2].x;
+    if (COARSE) wd *= __builtin_amdgcn_rcpf(scu + sc[q2]);
+    const float w = wd * wd;
+    float inv = __builtin_amdgcn_rsqf(D2);
+    if (!Q0) inv = D2 > 0.f ? inv : 0.f;
+    const float rq = Q0 ? 0.f : (D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f);
+    // w x_v = w x_u - w (x_u - x_v): the sums are taken relative to x_u, so
+    // one coefficient multiplies the offset.  It is 0 for padding; for a
+    // coincident pair it is finite and the offset is 0.
+    const float coef = Q0 ? fmaf(inv, fmaf(-alpha, inv, wd), -w) : fmaf(wd, inv, fmaf(-alpha, rq, -w));
+    px = fmaf(coef, dx, px);
+    py = fmaf(coef, dy, py);
+  }
+}
+
 // ---- the tiled sweep
 //
 // One workgroup per work unit (<= UNIT_CH chunks of one tile).  Prologue:
@@ -315,24 +430,29 @@ __global__ void k_rho(int32_t n, int32_t k, const int64_t* __restrict__ off,
 // before the current blocks are computed, so their latency overlaps one step
 // of work.  A lane visits its blocks in the same order for every NB, so NB
 // changes only how many bytes are in flight, not the result.
-template <int G, int NB, bool COARSE, bool Q0>
+template <int G, int NB, int TB, bool COARSE, bool Q0>
 __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
-    int32_t n, int32_t tbits, const int32_t* __restrict__ unit_c0,
+    int32_t n, const int32_t* __restrict__ unit_c0,
     const int32_t* __restrict__ unit_tile, const int64_t* __restrict__ chunk_off,
     const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_slot,
     const uint16_t* __restrict__ ent, const float2* __restrict__ xy,
     const float* __restrict__ sqrtc, float scale, float alpha, float q,
     float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
-  extern __shared__ float2 sx[];
+  // the tile's coordinates (and pre-scaled roots on coarse levels) in static
+  // LDS at a fixed address, so an entry's high 13 bits address them directly
   // per hop h: (1/h, bias added to D^2); h = 0 marks padding: (0, +inf), so a
-  // padding entry gets 1/D = 0 and every one of its terms is exactly 0
-  __shared__ float2 lut[16];
+  // padding entry gets 1/D = 0 and every one of its terms is exactly 0.  The
+  // table sits at the start of the coordinate array so that both lookups use
+  // the instruction's immediate offset.
+  constexpr int32_t T = 1 << TB;
+  __shared__ float2 slx[16 + T];
+  float2* const lut = slx;
+  float2* const sx = slx + 16;
+  __shared__ float ssc[COARSE ? T : 1];
   __shared__ int32_t mblk[UNIT_CH + 1];   // first block of each chunk (absolute)
   __shared__ int32_t mslot[UNIT_CH];
   __shared__ float2 mxu[UNIT_CH];
   __shared__ float mscu[COARSE ? UNIT_CH : 1];
-  const int32_t T = 1 << tbits;
-  float* ssc = reinterpret_cast<float*>(sx + T);
   const int32_t tile = unit_tile[blockIdx.x];
   const int32_t c0 = unit_c0[blockIdx.x], c1 = unit_c0[blockIdx.x + 1];
   const int32_t nch = c1 - c0;
@@ -362,7 +482,6 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   __syncthreads();
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
   constexpr int NG = TS_T / G;
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const u32x4* __restrict__ ent4 = reinterpret_cast<const u32x4*>(ent);
   int32_t ci = gi;                      // chunk (relative to the unit)
   int32_t ae = ci < nch ? mblk[ci + 1] : 0;
@@ -377,40 +496,8 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   float2 xu = ci < nch ? mxu[ci] : make_float2(0.f, 0.f);
   float scu = (COARSE && ci < nch) ? mscu[ci] : 0.f;
   float px = 0.f, py = 0.f;
-  // one 16-byte block: decode the 8 entries, issue their LDS reads, then
-  // compute (branch-free)
   auto run = [&](const u32x4 bk) {
-    const uint32_t wv[4] = {bk.x, bk.y, bk.z, bk.w};
-    float2 xv[8];
-    float2 lw[8];
-    float sc[8];
-#pragma unroll
-    for (int q2 = 0; q2 < 8; ++q2) {
-      const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
-      const uint32_t vl = pk >> 3;
-      xv[q2] = sx[vl];
-      lw[q2] = lut[pk & 7u];
-      if (COARSE) sc[q2] = ssc[vl];
-    }
-#pragma unroll
-    for (int q2 = 0; q2 < 8; ++q2) {
-      const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
-      const float D2 = fmaf(dx, dx, fmaf(dy, dy, lw[q2].y));
-      // w d = 1/d with d = hop (finest level) or hop (sqrt c_u + sqrt c_v)
-      // scale (coarse levels; the staged roots are pre-scaled), w = (w d)^2
-      float wd = lw[q2].x;
-      if (COARSE) wd *= __builtin_amdgcn_rcpf(scu + sc[q2]);
-      const float w = wd * wd;
-      float inv = __builtin_amdgcn_rsqf(D2);
-      if (!Q0) inv = D2 > 0.f ? inv : 0.f;
-      const float rq = Q0 ? 0.f : (D2 > 0.f ? powf(D2, -0.5f * (q + 2.f)) : 0.f);
-      // w d / D - alpha / D^(q+2); zero for padding and coincident pairs
-      const float coef = Q0 ? inv * fmaf(-alpha, inv, wd) : fmaf(wd, inv, -alpha * rq);
-      px = fmaf(w, xv[q2].x, px);
-      py = fmaf(w, xv[q2].y, py);
-      px = fmaf(coef, dx, px);
-      py = fmaf(coef, dy, py);
-    }
+    sweep_block<COARSE, Q0>(bk, sx, ssc, lut, xu, scu, alpha, q, px, py);
   };
   for (;;) {
     const bool active = ci < nch;
@@ -463,6 +550,90 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   }
 }
 
+// ---- the sliced sweep
+//
+// Sliced layout: the chunks of a tile (sorted by decreasing length) are cut
+// into slices of 64; block j of the slice's chunk i is stored at
+// slice_base + 64 j + i (chunks shorter than the slice's first are padded
+// with zero entries, which contribute 0).  One wave sweeps one slice with
+// one lane per chunk: every load of the wave reads 64 consecutive blocks, a
+// lane's partial sum is its chunk's, and no lane is idle except on padding
+// (the chunks of a slice have nearly equal lengths).  One workgroup per work
+// unit (up to UNIT_S slices of one tile) stages the tile's coordinates once;
+// its waves take the unit's slices in turn.  Blocks are loaded NB at a time,
+// one step ahead.
+template <int NB, int TB, bool COARSE, bool Q0>
+__global__ __launch_bounds__(TS_T) void k_sweep_sliced(
+    int32_t n, const int32_t* __restrict__ unit_s0, const int32_t* __restrict__ unit_tile,
+    const int64_t* __restrict__ slice_base, const int32_t* __restrict__ slice_h,
+    const int32_t* __restrict__ slice_c0, const int32_t* __restrict__ chunk_row,
+    const int32_t* __restrict__ chunk_slot, const uint16_t* __restrict__ ent,
+    const float2* __restrict__ xy, const float* __restrict__ sqrtc, float scale, float alpha,
+    float q, float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
+  constexpr int32_t T = 1 << TB;
+  __shared__ float2 slx[16 + T];  // hop table, then the tile's coordinates
+  float2* const lut = slx;
+  float2* const sx = slx + 16;
+  __shared__ float ssc[COARSE ? T : 1];
+  const int32_t tile = unit_tile[blockIdx.x];
+  const int32_t s0 = unit_s0[blockIdx.x], s1 = unit_s0[blockIdx.x + 1];
+  const int32_t v0 = tile * T;
+  const int32_t nv = min(T, n - v0);
+  for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
+    sx[i] = xy[v0 + i];
+    if (COARSE) ssc[i] = sqrtc[v0 + i] * scale;
+  }
+  if (alpha_dev) alpha = *alpha_dev;
+  if (threadIdx.x < 16) {
+    const float h = (float)threadIdx.x;
+    lut[threadIdx.x] = threadIdx.x ? make_float2(1.f / h, Q0 ? 1e-30f : 0.f)
+                                   : make_float2(0.f, INFINITY);
+  }
+  __syncthreads();
+  const int l = lane_id();
+  const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  for (int32_t sl = s0 + wv; sl < s1; sl += TS_T / 64) {
+    // slice parameters are wave-uniform (scalar registers, scalar branches)
+    const int32_t c0 = __builtin_amdgcn_readfirstlane(slice_c0[sl]);
+    const int32_t nc = __builtin_amdgcn_readfirstlane(slice_c0[sl + 1]) - c0;
+    const int32_t h = __builtin_amdgcn_readfirstlane(slice_h[sl]);
+    const int64_t sb = slice_base[sl];
+    const bool lv = l < nc;
+    const int32_t c = c0 + (lv ? l : 0);
+    const int32_t row = chunk_row[c];
+    const float2 xu = xy[row];
+    const float scu = COARSE ? sqrtc[row] * scale : 0.f;
+    // the slice's blocks from a wave-uniform base; a lane's block j sits
+    // 64 j + l blocks beyond it (32-bit byte offsets within the slice).  Loads
+    // past the slice's last row re-read that row (in bounds, never used), so
+    // every load is unconditional.
+    const char* __restrict__ eb = reinterpret_cast<const char*>(ent) + sb * 16;
+    auto ld = [&](int32_t j) {
+      const uint32_t jj = (uint32_t)min(j, h - 1);
+      return __builtin_nontemporal_load(
+          reinterpret_cast<const u32x4*>(eb + (jj * 64u + (uint32_t)l) * 16u));
+    };
+    float px = 0.f, py = 0.f;
+    u32x4 ba[NB], bb[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) ba[b] = ld(b);
+    for (int32_t j = 0; j < h; j += 2 * NB) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bb[b] = ld(j + NB + b);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (j + b < h) sweep_block<COARSE, Q0>(ba[b], sx, ssc, lut, xu, scu, alpha, q, px, py);
+      if (j + NB >= h) break;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) ba[b] = ld(j + 2 * NB + b);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (j + NB + b < h) sweep_block<COARSE, Q0>(bb[b], sx, ssc, lut, xu, scu, alpha, q, px, py);
+    }
+    if (lv) partial[chunk_slot[c]] = make_float2(px, py);
+  }
+}
+
 constexpr int CB_T = 256;
 constexpr int CB_G = 16;  // lanes per row in the combine
 __global__ __launch_bounds__(CB_T) void k_combine(int32_t n, const int64_t* __restrict__ rc_ptr,
@@ -491,9 +662,10 @@ __global__ __launch_bounds__(CB_T) void k_combine(int32_t n, const int64_t* __re
     if (gl == 0) {
       const float2 fu = F[u], xu = xy[u];
       const float r = rho[u];
+      // the partial sums are relative to x_u (see the sweep)
       float2 xn;
-      xn.x = (px + alpha * fu.x) / r;
-      xn.y = (py + alpha * fu.y) / r;
+      xn.x = xu.x + (px + alpha * fu.x) / r;
+      xn.y = xu.y + (py + alpha * fu.y) / r;
       out[u] = xn;
       const double ex = (double)xn.x - (double)xu.x, ey = (double)xn.y - (double)xu.y;
       dd.x = ex * ex + ey * ey;
@@ -544,7 +716,7 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
 }
 
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
-                       hipStream_t s, const float* sqrtc, double scale, float* rho) {
+                       hipStream_t s, const float* sqrtc, double scale, float* rho, bool sliced) {
   const int32_t n = kh.n;
   const int32_t ntiles = (int32_t)(((int64_t)n + (1 << tbits) - 1) >> tbits);
   const int32_t ntw = (ntiles + 31) >> 5;
@@ -610,7 +782,37 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   k_gather_sorted_chunks<<<nblk(m), 256, 0, s>>>(m, svals.as<int32_t>(), cm_size.as<int32_t>(),
                                                  cm_row.as<int32_t>(), ssize.as<int32_t>(),
                                                  ts->chunk_row, pos_of_slot);
+  DevBuf tfirst;
+  MM_TRY(tfirst.alloc(sizeof(int32_t) * (size_t)ntiles, s));
+  k_tile_first<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>());
+  int64_t nsl = 0;
+  DevBuf sflag, spos;
+  // consecutive chunks (the sliced layout is built from them)
   MM_TRY(scan_excl_i32(ssize.as<int32_t>(), ts->chunk_off, m, s));
+  if (sliced) {
+    // slices of 64 chunks of one tile; block j of the slice's chunk i at
+    // slice_base + 64 j + i
+    MM_TRY(sflag.alloc(sizeof(int32_t) * (size_t)m, s));
+    MM_TRY(spos.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+    k_slice_flags<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>(),
+                                          sflag.as<int32_t>());
+    MM_TRY(scan_excl_i32(sflag.as<int32_t>(), spos.as<int64_t>(), m, s));
+    MM_TRY(hipMemcpyAsync(&nsl, spos.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MM_TRY(hipStreamSynchronize(s));
+    DevBuf sblocks;
+    MM_TRY(ts->b_slice_c0.alloc(sizeof(int32_t) * (size_t)(nsl + 1), s));
+    MM_TRY(ts->b_slice_h.alloc(sizeof(int32_t) * (size_t)nsl, s));
+    MM_TRY(ts->b_slice_base.alloc(sizeof(int64_t) * (size_t)(nsl + 1), s));
+    MM_TRY(sblocks.alloc(sizeof(int32_t) * (size_t)nsl, s));
+    ts->slice_c0 = ts->b_slice_c0.as<int32_t>();
+    ts->slice_h = ts->b_slice_h.as<int32_t>();
+    ts->slice_base = ts->b_slice_base.as<int64_t>();
+    k_slice_fill<<<nblk(m), 256, 0, s>>>(m, sflag.as<int32_t>(), spos.as<int64_t>(),
+                                         ssize.as<int32_t>(), ts->slice_c0, ts->slice_h,
+                                         sblocks.as<int32_t>());
+    k_set_i32<<<1, 1, 0, s>>>(ts->slice_c0 + nsl, (int32_t)m);
+    MM_TRY(scan_excl_i32(sblocks.as<int32_t>(), ts->slice_base, nsl, s));
+  }
   // chunk -> row-major slot
   MM_TRY(ts->b_chunk_slot.alloc(sizeof(int32_t) * (size_t)m, s));
   ts->chunk_slot = ts->b_chunk_slot.as<int32_t>();
@@ -618,47 +820,70 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
                         hipMemcpyDeviceToDevice, s));
   int64_t padded = 0;
   MM_TRY(hipMemcpyAsync(&padded, ts->chunk_off + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  int64_t sl_blocks = 0;
+  if (sliced)
+    MM_TRY(hipMemcpyAsync(&sl_blocks, ts->slice_base + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
-  if ((padded >> 3) >= (1ll << 31)) return hipSuccess;  // block ids are int32 in the sweep
-  MM_TRY(ts->b_ent.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
-  ts->ent = ts->b_ent.as<uint16_t>();
-  MM_TRY(hipMemsetAsync(ts->ent, 0, sizeof(uint16_t) * (size_t)padded, s));
-  ts->total = kh.total;
-  ts->padded = padded;
+  if ((padded >> 3) >= (1ll << 31) || sl_blocks >= (1ll << 31)) return hipSuccess;  // int32 block ids
+  // the consecutive layout: the sets themselves, or the staging copy of the
+  // sliced layout
+  DevBuf stage;
+  DevBuf& cons = sliced ? stage : ts->b_ent;
+  MM_TRY(cons.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
+  MM_TRY(hipMemsetAsync(cons.p, 0, sizeof(uint16_t) * (size_t)padded, s));
   if (use_base)
     k_row_chunks<true, true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm_base, s>>>(
         n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
-        nullptr, pos_of_slot, ts->chunk_off, ts->ent);
+        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
   else
     k_row_chunks<true, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
         n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
-        nullptr, pos_of_slot, ts->chunk_off, ts->ent);
+        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
   MM_TRY(hipGetLastError());
-  // work units
-  MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)m, s));
-  MM_TRY(upos.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
-  {
-    DevBuf tfirst;
-    MM_TRY(tfirst.alloc(sizeof(int32_t) * (size_t)ntiles, s));
-    k_tile_first<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>());
-    // at least ~8 work units per CU when the level is small; never fewer
-    // than 64K entries per unit (the tile staging is amortised over them)
-    const int64_t emax = std::max<int64_t>(65536, padded / 2048);
+  if (sliced) {
+    padded = sl_blocks * 8;
+    MM_TRY(ts->b_ent.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
+    k_slice_transpose<<<nblk(nsl, 4), 256, 0, s>>>(nsl, ts->slice_c0, ts->slice_h, ts->slice_base,
+                                                   ts->chunk_off, cons.as<uint4>(),
+                                                   ts->b_ent.as<uint4>());
+    MM_TRY(hipGetLastError());
+  }  // the staging copy is freed (stream-ordered) on return
+  ts->ent = ts->b_ent.as<uint16_t>();
+  ts->total = kh.total;
+  ts->padded = padded;
+  // work units: chunks (tiled) or slices (sliced) of one tile
+  const int64_t mu = sliced ? nsl : m;
+  MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(mu, 1), s));
+  MM_TRY(upos.alloc(sizeof(int64_t) * (size_t)(mu + 1), s));
+  // at least ~8 work units per CU when the level is small; never fewer
+  // than 64K entries per unit (the tile staging is amortised over them)
+  const int64_t emax = std::max<int64_t>(65536, padded / 2048);
+  if (sliced)
+    k_slice_unit_flags<<<nblk(mu), 256, 0, s>>>((int32_t)mu, ts->slice_c0, skeys.as<uint64_t>(),
+                                                tfirst.as<int32_t>(), ts->slice_base, emax / 8,
+                                                flag.as<int32_t>());
+  else
     k_unit_flags<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>(),
                                          ts->chunk_off, emax, flag.as<int32_t>());
-  }
-  MM_TRY(scan_excl_i32(flag.as<int32_t>(), upos.as<int64_t>(), m, s));
+  MM_TRY(scan_excl_i32(flag.as<int32_t>(), upos.as<int64_t>(), mu, s));
   int64_t nu = 0;
-  MM_TRY(hipMemcpyAsync(&nu, upos.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipMemcpyAsync(&nu, upos.as<int64_t>() + mu, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
   ts->nunits = (int32_t)nu;
   MM_TRY(ts->b_unit_c0.alloc(sizeof(int32_t) * (size_t)(nu + 1), s));
   MM_TRY(ts->b_unit_tile.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1), s));
   ts->unit_c0 = ts->b_unit_c0.as<int32_t>();
   ts->unit_tile = ts->b_unit_tile.as<int32_t>();
-  k_unit_fill<<<nblk(m), 256, 0, s>>>(m, flag.as<int32_t>(), upos.as<int64_t>(), skeys.as<uint64_t>(),
-                                      ts->unit_c0, ts->unit_tile);
-  k_set_i32<<<1, 1, 0, s>>>(ts->unit_c0 + nu, (int32_t)m);
+  if (sliced)
+    k_slice_unit_fill<<<nblk(mu), 256, 0, s>>>((int32_t)mu, flag.as<int32_t>(), upos.as<int64_t>(),
+                                               ts->slice_c0, skeys.as<uint64_t>(), ts->unit_c0,
+                                               ts->unit_tile);
+  else
+    k_unit_fill<<<nblk(m), 256, 0, s>>>(m, flag.as<int32_t>(), upos.as<int64_t>(),
+                                        skeys.as<uint64_t>(), ts->unit_c0, ts->unit_tile);
+  k_set_i32<<<1, 1, 0, s>>>(ts->unit_c0 + nu, (int32_t)mu);
+  ts->sliced = sliced;
+  ts->nslices = nsl;
   MM_TRY(ts->b_partial.alloc(sizeof(float2) * (size_t)m, s));
   ts->built = true;
   return hipGetLastError();
@@ -670,40 +895,64 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
                        int32_t group, int32_t nb) {
   const bool coarse = level > 0 && sqrtc != nullptr;
   const bool q0 = q == 0.0;
-  const int32_t T = 1 << ts.tbits;
-  const size_t shm = (size_t)T * (sizeof(float2) + (coarse ? sizeof(float) : 0));
+  if (ts.tbits < 11 || ts.tbits > 13) return hipErrorInvalidValue;
   // a group of G lanes (one 8-entry block each per step) per chunk
   const int G = group > 0 ? group : tiled_group(ts);
   const int NB = nb > 0 ? nb : tiled_blocks(ts);
   float2* part = ts.b_partial.as<float2>();
-#define MM_TS(GG, NBV, C, Q)                                                                     \
-  do {                                                                                           \
-    static bool attr_set = false; /* once per instantiation (not during a capture) */           \
-    if (!attr_set) {                                                                             \
-      MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tiled<GG, NBV, C, Q>), \
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));         \
-      attr_set = true;                                                                           \
-    }                                                                                            \
-    k_sweep_tiled<GG, NBV, C, Q><<<ts.nunits, TS_T, shm, s>>>(                                   \
-        ts.n, ts.tbits, ts.unit_c0, ts.unit_tile, ts.chunk_off, ts.chunk_row, ts.chunk_slot,     \
-        ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, alpha_dev); \
+#define MM_TS(GG, NBV, TBV, C, Q)                                                               \
+  k_sweep_tiled<GG, NBV, TBV, C, Q><<<ts.nunits, TS_T, 0, s>>>(                                 \
+      ts.n, ts.unit_c0, ts.unit_tile, ts.chunk_off, ts.chunk_row, ts.chunk_slot, ts.ent,         \
+      (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, alpha_dev)
+#define MM_TST(GG, NBV, TBV)                                                                   \
+  do {                                                                                         \
+    if (coarse) { if (q0) MM_TS(GG, NBV, TBV, true, true); else MM_TS(GG, NBV, TBV, true, false); } \
+    else { if (q0) MM_TS(GG, NBV, TBV, false, true); else MM_TS(GG, NBV, TBV, false, false); }      \
   } while (0)
-#define MM_TSN(GG, NBV)                                                                  \
-  do {                                                                                   \
-    if (coarse) { if (q0) MM_TS(GG, NBV, true, true); else MM_TS(GG, NBV, true, false); } \
-    else { if (q0) MM_TS(GG, NBV, false, true); else MM_TS(GG, NBV, false, false); }      \
+#define MM_TSN(GG, NBV)                                            \
+  do {                                                             \
+    if (ts.tbits == 13) MM_TST(GG, NBV, 13);                       \
+    else if (ts.tbits == 12) MM_TST(GG, NBV, 12);                  \
+    else MM_TST(GG, NBV, 11);                                      \
   } while (0)
 #define MM_TSG(GG)                                   \
   do {                                               \
     if (NB == 4) MM_TSN(GG, 4); else MM_TSN(GG, 2);  \
   } while (0)
-  switch (G) {
-    case 16: MM_TSG(16); break;
-    case 8: MM_TSG(8); break;
-    default: MM_TSG(4); break;
+#define MM_SL(NBV, TBV, C, Q)                                                                   \
+  k_sweep_sliced<NBV, TBV, C, Q><<<ts.nunits, TS_T, 0, s>>>(                                     \
+      ts.n, ts.unit_c0, ts.unit_tile, ts.slice_base, ts.slice_h, ts.slice_c0, ts.chunk_row,      \
+      ts.chunk_slot, ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, \
+      alpha_dev)
+#define MM_SLT(NBV, TBV)                                                                       \
+  do {                                                                                         \
+    if (coarse) { if (q0) MM_SL(NBV, TBV, true, true); else MM_SL(NBV, TBV, true, false); }    \
+    else { if (q0) MM_SL(NBV, TBV, false, true); else MM_SL(NBV, TBV, false, false); }         \
+  } while (0)
+#define MM_SLN(NBV)                                                \
+  do {                                                             \
+    if (ts.tbits == 13) MM_SLT(NBV, 13);                           \
+    else if (ts.tbits == 12) MM_SLT(NBV, 12);                      \
+    else MM_SLT(NBV, 11);                                          \
+  } while (0)
+  if (ts.sliced) {
+    if (NB == 4) MM_SLN(4); else MM_SLN(2);
+  } else {
+    switch (G) {
+      case 16: MM_TSG(16); break;
+      case 8: MM_TSG(8); break;
+      case 4: MM_TSG(4); break;
+      case 2: MM_TSG(2); break;
+      case 1: MM_TSG(1); break;
+      default: return hipErrorInvalidValue;
+    }
   }
+#undef MM_SLN
+#undef MM_SLT
+#undef MM_SL
 #undef MM_TSG
 #undef MM_TSN
+#undef MM_TST
 #undef MM_TS
   MM_TRY(hipGetLastError());
   const int32_t ncb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);

@@ -3,7 +3,8 @@ kept across contexts, through the C-ABI.
 
 Bars:
 * each configuration (row kernel with 8/16/32/64 lanes per row, tiled kernel
-  with tiles of 2^11/2^12/2^13 vertices, 4/8/16 lanes per chunk and 2/4
+  with tiles of 2^11/2^12/2^13 vertices, 1/2/4/8/16 lanes per chunk or the
+  sliced layout (lanes code 64), and 2/4
   blocks per lane and step) gives one
   Jacobi iteration of Eq. 2 within 1e-4 relative (floor 1) of the FP64 oracle
   on the same FP32 inputs, finest and coarse level, with a ragged last tile;
@@ -21,7 +22,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 CONFIGS = [(0, 8, 0), (0, 16, 0), (0, 32, 0), (0, 64, 0)] + \
-    [(tb, g, nb) for tb in (11, 12, 13) for g in (4, 8, 16) for nb in (2, 4)]
+    [(tb, g, nb) for tb in (11, 12, 13) for g in (1, 2, 4, 8, 16, 64) for nb in (2, 4)]
 
 
 @pytest.fixture(scope="module")
