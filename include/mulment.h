@@ -114,7 +114,10 @@ typedef struct {
 
 mm_status mm_params_default(mm_params* p);
 
-/* device: HIP device ordinal; stream: hipStream_t or NULL (default stream). */
+/* device: HIP device ordinal; stream: hipStream_t or NULL (default stream).
+ * The library allocates its buffers stream-ordered from the device's default
+ * memory pool and raises that pool's release threshold, so memory it frees
+ * stays mapped for its next allocations; mm_context_destroy trims the pool. */
 mm_status mm_context_create(mm_context** out, int32_t device, void* stream);
 void mm_context_destroy(mm_context* ctx);
 /* Forgets the sweep configurations the autotuner chose in this context. */

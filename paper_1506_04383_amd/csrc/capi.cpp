@@ -412,6 +412,17 @@ mm_status mm_context_create(mm_context** out, int32_t device, void* stream) {
     HIPCHK(hipMalloc((void**)&c->alpha_dev, sizeof(float)));
     HIPCHK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    mm::big_register(c->stream);
+    mm::big_register(c->work);
+    // the library's buffers come from the device's default pool
+    // (stream-ordered); keep freed memory in the pool instead of returning it
+    // at every synchronisation, since each level frees and re-allocates sets
+    // of tens of GB (mm_context_destroy trims the pool)
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
     *out = c.release();
     return MM_OK;
   } catch (...) {
@@ -426,11 +437,16 @@ void mm_context_destroy(mm_context* ctx) {
   mm::bh_work_destroy(ctx->bh);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->work) (void)hipStreamSynchronize(ctx->work);
+  mm::big_unregister(ctx->stream);
+  if (ctx->work) mm::big_unregister(ctx->work);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->alpha_pinned) (void)hipHostFree(ctx->alpha_pinned);
   if (ctx->alpha_dev) (void)hipFree(ctx->alpha_dev);
   if (ctx->work) (void)hipStreamDestroy(ctx->work);
   for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
+  (void)hipDeviceSynchronize();
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
   delete ctx;
 }
 
@@ -1003,7 +1019,12 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
                                rho.as<float>(), group_lvl == 0 || group_lvl == mm::kSlicedGroup));
         if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
         HIPCHK(hipStreamSynchronize(s));
-        t_khop += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
+        const double tiled_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
+        t_khop += tiled_ms;
+        const char* ev = std::getenv("MM_VERBOSE");
+        if (ev && ev[0] == '1')
+          std::fprintf(stderr, "[level %d] n %d sets %lld: k-hop build %.1f ms, tile-major copy %.1f ms\n",
+                       lvl, nl, (long long)kh.total, khop_ms, tiled_ms);
       }
       int32_t iters = 0, final_iters = 0, cap_hit = 0;
       double delta = 0;

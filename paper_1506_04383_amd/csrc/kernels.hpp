@@ -1,35 +1,71 @@
 // Host-side launchers of the HIP kernels (internal to libmulment).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <stdint.h>
 
 namespace mm {
+
+// Blocks of kBigBlock bytes and more are kept for reuse, per device and
+// stream: the levels of a layout free and allocate blocks of tens of GB, and
+// the device memory pool occasionally takes seconds to provide a fresh one.
+// big_alloc hands out the smallest cached block of the caller's device and
+// stream that holds b bytes and is at most twice b (else a new block; *cap
+// receives the block's size); big_free returns a block to the cache, which
+// frees (stream-ordered) its largest blocks beyond 40% of device memory.
+// Reuse on the same stream keeps the stream order of the frees.
+constexpr size_t kBigBlock = size_t(1) << 30;
+hipError_t big_alloc(void** p, size_t b, size_t* cap, hipStream_t s);
+void big_free(void* p, size_t cap, hipStream_t s);
+size_t big_cached_bytes(int device);
+void big_flush(int device);  // frees every cached block of the device
+// Blocks are cached only for registered streams (those of live contexts);
+// unregistering (reference-counted) frees the stream's cached blocks, so it
+// must precede the stream's destruction.
+void big_register(hipStream_t s);
+void big_unregister(hipStream_t s);
 
 // Stream-ordered temporary device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  size_t cap = 0;  // size of the block behind p (>= bytes for cached blocks)
   hipStream_t s = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap), s(o.s) {
+    o.p = nullptr;
+    o.bytes = o.cap = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; s = o.s; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; cap = o.cap; s = o.s;
+      o.p = nullptr;
+      o.bytes = o.cap = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   hipError_t alloc(size_t b, hipStream_t st) {
     release();
     s = st;
-    bytes = b;
+    bytes = cap = b;
     if (b == 0) return hipSuccess;
+    if (b >= kBigBlock) return big_alloc(&p, b, &cap, st);
     return hipMallocAsync(&p, b, st);
   }
   void release() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) {
+      if (cap >= kBigBlock) big_free(p, cap, s);
+      else (void)hipFreeAsync(p, s);
+    }
     p = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };

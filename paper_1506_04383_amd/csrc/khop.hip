@@ -13,6 +13,9 @@
 //    new) in LDS when they fit, otherwise in global memory per workgroup
 //    slot; the hop-h set is extracted in ascending order by scanning the new
 //    bitmap with wave-level prefix sums.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -344,10 +347,23 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
     size_t freeb = 0, totb = 0;
     MM_TRY(hipMemGetInfo(&freeb, &totb));
     const size_t kb = sizeof(uint32_t) * (size_t)W * (size_t)nbig;
+    if (kb > freeb / 3) {
+      // memory freed by earlier stream-ordered frees may still be held by the
+      // device's default pool (not reported as free): release it and look again
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && hipMemPoolTrimTo(pool, 0) == hipSuccess)
+        MM_TRY(hipMemGetInfo(&freeb, &totb));
+    }
+    freeb += big_cached_bytes(dev);  // cached blocks are available too
     if (kb <= freeb / 3) {
       MM_TRY(bmk.alloc(kb, s));
       keep = true;
     }
+    // MM_VERBOSE=1 reports the decision on stderr
+    const char* ev = std::getenv("MM_VERBOSE");
+    if (ev && ev[0] == '1')
+      std::fprintf(stderr, "[khop] n %d rows with bitmaps %lld (%.2f GB), free %.2f GB: %s\n", n,
+                   (long long)nbig, kb / 1e9, freeb / 1e9, keep ? "kept" : "rebuilt");
   }
 #define MM_BIG(FILLV, LDSV, ONEV, KEEPV, ...)                                                   \
   do {                                                                                         \

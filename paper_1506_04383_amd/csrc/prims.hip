@@ -1,4 +1,10 @@
 // Scan and radix-sort primitives (deterministic: fixed tiles, fixed order).
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -252,6 +258,145 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
     MM_TRY(hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
   }
   return hipGetLastError();
+}
+
+// ---- cache of big device blocks (see kernels.hpp)
+namespace {
+struct BigBlock {
+  void* p;
+  size_t cap;
+  hipStream_t s;
+  int dev;
+};
+std::mutex g_big_mu;
+std::vector<BigBlock> g_big;
+std::vector<std::pair<hipStream_t, int>> g_big_streams;  // registered streams, counts
+bool verbose_allocs() {
+  static const bool v = [] { const char* e = std::getenv("MM_VERBOSE"); return e && e[0] == '1'; }();
+  return v;
+}
+void big_flush_locked(int dev) {
+  for (size_t i = 0; i < g_big.size();) {
+    if (g_big[i].dev == dev) {
+      (void)hipFreeAsync(g_big[i].p, g_big[i].s);
+      g_big[i] = g_big.back();
+      g_big.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+}  // namespace
+
+hipError_t big_alloc(void** p, size_t b, size_t* cap, hipStream_t s) {
+  int dev = 0;
+  MM_TRY(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_big_mu);
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < g_big.size(); ++i) {
+      const BigBlock& k = g_big[i];
+      if (k.dev == dev && k.s == s && k.cap >= b && k.cap / 2 <= b &&
+          (best == SIZE_MAX || k.cap < g_big[best].cap))
+        best = i;
+    }
+    if (best != SIZE_MAX) {
+      *p = g_big[best].p;
+      *cap = g_big[best].cap;
+      g_big[best] = g_big.back();
+      g_big.pop_back();
+      return hipSuccess;
+    }
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipMallocAsync(p, b, s);
+  if (e == hipErrorOutOfMemory) {
+    // give the cached blocks back and try once more
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(g_big_mu);
+      big_flush_locked(dev);
+    }
+    MM_TRY(hipDeviceSynchronize());
+    e = hipMallocAsync(p, b, s);
+  }
+  *cap = b;
+  if (verbose_allocs())
+    std::fprintf(stderr, "[alloc] %.2f GB in %.1f ms\n", b / 1e9,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+  return e;
+}
+
+void big_free(void* p, size_t cap, hipStream_t s) {
+  int dev = 0;
+  bool reg = false;
+  {
+    std::lock_guard<std::mutex> lk(g_big_mu);
+    for (const auto& r : g_big_streams) reg = reg || r.first == s;
+  }
+  // blocks are kept only for streams of live contexts
+  if (!reg || hipGetDevice(&dev) != hipSuccess) {
+    (void)hipFreeAsync(p, s);
+    return;
+  }
+  size_t freeb = 0, totb = 0;
+  (void)hipMemGetInfo(&freeb, &totb);
+  const size_t limit = totb / 10 * 4;
+  std::lock_guard<std::mutex> lk(g_big_mu);
+  g_big.push_back({p, cap, s, dev});
+  for (;;) {
+    size_t total = 0, big = SIZE_MAX;
+    for (size_t i = 0; i < g_big.size(); ++i) {
+      if (g_big[i].dev != dev) continue;
+      total += g_big[i].cap;
+      if (big == SIZE_MAX || g_big[i].cap > g_big[big].cap) big = i;
+    }
+    if (total <= limit || big == SIZE_MAX) break;
+    (void)hipFreeAsync(g_big[big].p, g_big[big].s);
+    g_big[big] = g_big.back();
+    g_big.pop_back();
+  }
+}
+
+size_t big_cached_bytes(int device) {
+  std::lock_guard<std::mutex> lk(g_big_mu);
+  size_t t = 0;
+  for (const BigBlock& k : g_big)
+    if (k.dev == device) t += k.cap;
+  return t;
+}
+
+void big_flush(int device) {
+  std::lock_guard<std::mutex> lk(g_big_mu);
+  big_flush_locked(device);
+}
+
+void big_register(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_big_mu);
+  for (auto& r : g_big_streams)
+    if (r.first == s) { r.second++; return; }
+  g_big_streams.push_back({s, 1});
+}
+
+void big_unregister(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_big_mu);
+  for (size_t i = 0; i < g_big_streams.size(); ++i) {
+    if (g_big_streams[i].first != s) continue;
+    if (--g_big_streams[i].second > 0) return;
+    g_big_streams[i] = g_big_streams.back();
+    g_big_streams.pop_back();
+    break;
+  }
+  // the stream may be destroyed next: free its blocks while it is valid
+  for (size_t i = 0; i < g_big.size();) {
+    if (g_big[i].s == s) {
+      (void)hipFreeAsync(g_big[i].p, g_big[i].s);
+      g_big[i] = g_big.back();
+      g_big.pop_back();
+    } else {
+      ++i;
+    }
+  }
 }
 
 }  // namespace mm

@@ -378,7 +378,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 //   c = w d / D - alpha / D^(q+2) - w,   w = d^-2,
 // i.e. Eq. 2's numerator minus rho_u x_u (the combine adds rho_u x_u back).
 // sx: the tile's coordinates; ssc: sqrt c of the tile's vertices times the
-// distance scale (coarse levels); lut: per hop (1/hop, bias added to D^2).
+// distance scale (coarse levels); lut: the per-hop table (hop_entry).
 template <bool COARSE, bool Q0>
 __device__ __forceinline__ void sweep_block(const u32x4 bk, const float2* __restrict__ sx,
                                             const float* __restrict__ ssc,
@@ -392,10 +392,32 @@ __device__ __forceinline__ void sweep_block(const u32x4 bk, const float2* __rest
 #pragma unroll
   for (int q2 = 0; q2 < 8; ++q2) {
     const uint32_t pk = (wv[q2 >> 1] >> (16 * (q2 & 1))) & 0xFFFFu;
-    const uint32_t vl = pk >> 3;
-    xv[q2] = sx[vl];
+    // byte offsets: id * 8 is the entry with its hop bits cleared, and
+    // id * 4 half of that
+    const uint32_t xo = pk & 0xFFF8u;
+    xv[q2] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(sx) + xo);
     lw[q2] = lut[pk & 7u];
-    if (COARSE) sc[q2] = ssc[vl];
+    if (COARSE) sc[q2] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(ssc) + (xo >> 1));
+  }
+  if (COARSE && Q0) {
+    // coarse levels, q = 0: with g = h (sqrt c_u + sqrt c_v) scale = 1/wd and
+    // r = 1/(g D) = wd/D, the coefficient is  r - r^2 (alpha g^2 + D^2)
+    // (= wd/D - alpha/D^2 - wd^2): one reciprocal square root per entry.
+    // The table holds (h, bias added to g^2 D^2): a tiny bias keeps r finite
+    // for a coincident pair (whose offset is 0); +inf for padding gives
+    // r = 0 and a zero coefficient.
+#pragma unroll
+    for (int q2 = 0; q2 < 8; ++q2) {
+      const float dx = xu.x - xv[q2].x, dy = xu.y - xv[q2].y;
+      const float D2 = fmaf(dx, dx, dy * dy);
+      const float g = lw[q2].x * (scu + sc[q2]);
+      const float g2 = g * g;
+      const float r = __builtin_amdgcn_rsqf(fmaf(D2, g2, lw[q2].y));
+      const float coef = fmaf(-(r * r), fmaf(alpha, g2, D2), r);
+      px = fmaf(coef, dx, px);
+      py = fmaf(coef, dy, py);
+    }
+    return;
   }
 #pragma unroll
   for (int q2 = 0; q2 < 8; ++q2) {
@@ -416,6 +438,18 @@ __device__ __forceinline__ void sweep_block(const u32x4 bk, const float2* __rest
     px = fmaf(coef, dx, px);
     py = fmaf(coef, dy, py);
   }
+}
+
+// The per-hop table of the sweeps (index = hop; hop 0 marks padding).
+// Finest level, or q != 0: (1/h, bias added to D^2), padding (0, +inf) so that
+// 1/D = 0 and every term of a padding entry is exactly 0; at q = 0 a 1e-30
+// bias keeps 1/D finite for a coincident pair, whose r-terms then vanish
+// through dx = dy = 0 (q != 0 tests D^2 > 0 instead).  Coarse levels at
+// q = 0: (h, bias added to g^2 D^2) as sweep_block describes.
+template <bool COARSE, bool Q0>
+__device__ inline float2 hop_entry(uint32_t h) {
+  if (COARSE && Q0) return h ? make_float2((float)h, 1e-20f) : make_float2(1.f, INFINITY);
+  return h ? make_float2(1.f / (float)h, Q0 ? 1e-30f : 0.f) : make_float2(0.f, INFINITY);
 }
 
 // ---- the tiled sweep
@@ -440,10 +474,8 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
   // the tile's coordinates (and pre-scaled roots on coarse levels) in static
   // LDS at a fixed address, so an entry's high 13 bits address them directly
-  // per hop h: (1/h, bias added to D^2); h = 0 marks padding: (0, +inf), so a
-  // padding entry gets 1/D = 0 and every one of its terms is exactly 0.  The
-  // table sits at the start of the coordinate array so that both lookups use
-  // the instruction's immediate offset.
+  // the per-hop table (hop_entry) sits at the start of the coordinate array
+  // so that both lookups of an entry use the instruction's immediate offset
   constexpr int32_t T = 1 << TB;
   __shared__ float2 slx[16 + T];
   float2* const lut = slx;
@@ -473,11 +505,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   }
   if (alpha_dev) alpha = *alpha_dev;
   if (threadIdx.x < 16) {
-    // q = 0: a 1e-30 bias keeps 1/D finite for a coincident pair, whose
-    // r-terms then vanish through dx = dy = 0; q != 0 tests D^2 > 0 instead
-    const float h = (float)threadIdx.x;
-    lut[threadIdx.x] = threadIdx.x ? make_float2(1.f / h, Q0 ? 1e-30f : 0.f)
-                                   : make_float2(0.f, INFINITY);
+    lut[threadIdx.x] = hop_entry<COARSE, Q0>(threadIdx.x);
   }
   __syncthreads();
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
@@ -585,9 +613,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_sliced(
   }
   if (alpha_dev) alpha = *alpha_dev;
   if (threadIdx.x < 16) {
-    const float h = (float)threadIdx.x;
-    lut[threadIdx.x] = threadIdx.x ? make_float2(1.f / h, Q0 ? 1e-30f : 0.f)
-                                   : make_float2(0.f, INFINITY);
+    lut[threadIdx.x] = hop_entry<COARSE, Q0>(threadIdx.x);
   }
   __syncthreads();
   const int l = lane_id();
