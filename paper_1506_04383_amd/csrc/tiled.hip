@@ -28,6 +28,7 @@ namespace {
 constexpr int TB_WAVES = 4;          // waves per block of the conversion kernels
 constexpr int TB_MAXTILES = 4096;    // conversion keeps per-tile counters in LDS
 constexpr int TB_MAXW = TB_MAXTILES / 32;
+constexpr int RU = 4;                // 64-entry steps loaded at once per wave (conversion)
 constexpr int TS_T = 512;            // sweep block
 constexpr int32_t UNIT_CH = 768;      // chunks per work unit (metadata staged in LDS)
 constexpr int32_t UNIT_S = 64;        // slices per work unit of the sliced layout
@@ -71,14 +72,30 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(
   int32_t seg0 = 0;
   for (int h = 1; h <= k; ++h) {
     const int32_t seg1 = hend[(int64_t)u * k + h - 1];
-    for (int32_t i = seg0 + l; i < seg1; i += 64) {
-      const int32_t v = nbr[beg + i];
-      const int32_t t = v >> tbits;
-      const uint32_t bit = 1u << (t & 31);
-      if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
-      if (RHO && sqrtc) {
-        const float d = (float)h * (su + sqrtc[v]) * scale;
-        r += 1.f / (d * d);
+    // RU 64-entry steps per pass, their loads (and sqrt c gathers) issued
+    // before any is used; each lane still takes its entries in order
+    for (int32_t i0 = seg0; i0 < seg1; i0 += 64 * RU) {
+      int32_t vv[RU];
+      float sv[RU];
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        const int32_t i = i0 + 64 * uu + l;
+        vv[uu] = i < seg1 ? nbr[beg + i] : 0;
+      }
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu)
+        sv[uu] = (RHO && sqrtc && i0 + 64 * uu + l < seg1) ? sqrtc[vv[uu]] : 0.f;
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        if (i0 + 64 * uu + l >= seg1) break;
+        const int32_t v = vv[uu];
+        const int32_t t = v >> tbits;
+        const uint32_t bit = 1u << (t & 31);
+        if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+        if (RHO && sqrtc) {
+          const float d = (float)h * (su + sv[uu]) * scale;
+          r += 1.f / (d * d);
+        }
       }
     }
     seg0 = seg1;
@@ -109,7 +126,7 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(
 // slots).  FILL=true: write the 16-bit entries; with BASE the start of every
 // touched tile's chunk is looked up once per row (an LDS table of int64) so
 // that the entry loop has no dependent global loads.  The row's entries are
-// loaded one 64-entry step ahead.
+// loaded RU 64-entry steps at a time.
 template <bool FILL, bool BASE>
 __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
     int32_t n, int32_t k, int32_t tbits, int32_t ntiles, int32_t ntw,
@@ -136,12 +153,17 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
   const int64_t beg = off[u], endr = off[u + 1];
   for (int i = l; i < ntw; i += 64) bm[i] = 0u;
   wave_sync();
-  {
-    int32_t vn = beg + l < endr ? nbr[beg + l] : 0;
-    for (int64_t e = beg + l; e < endr; e += 64) {
-      const int32_t v = vn;
-      if (e + 64 < endr) vn = nbr[e + 64];
-      const int32_t t = v >> tbits;
+  for (int64_t e0 = beg; e0 < endr; e0 += 64 * RU) {
+    int32_t vv[RU];
+#pragma unroll
+    for (int uu = 0; uu < RU; ++uu) {
+      const int64_t e = e0 + 64 * uu + l;
+      vv[uu] = e < endr ? nbr[e] : 0;
+    }
+#pragma unroll
+    for (int uu = 0; uu < RU; ++uu) {
+      if (e0 + 64 * uu + l >= endr) break;
+      const int32_t t = vv[uu] >> tbits;
       const uint32_t bit = 1u << (t & 31);
       if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
     }
@@ -174,32 +196,41 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
   int32_t seg0 = 0;
   for (int h = 1; h <= k; ++h) {
     const int32_t seg1 = hend[(int64_t)u * k + h - 1];
-    int32_t vn = seg0 + l < seg1 ? nbr[beg + seg0 + l] : 0;
-    for (int32_t b = seg0; b < seg1; b += 64) {
-      const int32_t i = b + l;
-      const bool valid = i < seg1;
-      const int32_t v = vn;
-      if (i + 64 < seg1) vn = nbr[beg + i + 64];
-      const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
-      const int32_t tprev = __shfl_up(t, 1, 64);
-      const bool start = valid && (l == 0 || tprev != t);
-      const int32_t rs = wave_incl_max(start ? l : -1);
-      const int32_t tnext = __shfl_down(t, 1, 64);
-      const bool end = valid && (l == 63 || i + 1 >= seg1 || tnext != t);
-      if (FILL && valid) {
-        int64_t cbase;
-        if (BASE) {
-          cbase = base[t];
-        } else {
-          const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
-          cbase = chunk_off[pos_of_slot[rbase + rank]];
-        }
-        const int64_t dst = cbase + ct[t] + (l - rs);
-        ent[dst] = (uint16_t)(((v & ((1 << tbits) - 1)) << 3) | h);
+    for (int32_t b0 = seg0; b0 < seg1; b0 += 64 * RU) {
+      int32_t vv[RU];
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        const int32_t i = b0 + 64 * uu + l;
+        vv[uu] = i < seg1 ? nbr[beg + i] : 0;
       }
-      wave_sync();
-      if (end) ct[t] += l - rs + 1;
-      wave_sync();
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        const int32_t b = b0 + 64 * uu;
+        if (b >= seg1) break;  // wave-uniform
+        const int32_t i = b + l;
+        const bool valid = i < seg1;
+        const int32_t v = vv[uu];
+        const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
+        const int32_t tprev = __shfl_up(t, 1, 64);
+        const bool start = valid && (l == 0 || tprev != t);
+        const int32_t rs = wave_incl_max(start ? l : -1);
+        const int32_t tnext = __shfl_down(t, 1, 64);
+        const bool end = valid && (l == 63 || i + 1 >= seg1 || tnext != t);
+        if (FILL && valid) {
+          int64_t cbase;
+          if (BASE) {
+            cbase = base[t];
+          } else {
+            const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
+            cbase = chunk_off[pos_of_slot[rbase + rank]];
+          }
+          const int64_t dst = cbase + ct[t] + (l - rs);
+          ent[dst] = (uint16_t)(((v & ((1 << tbits) - 1)) << 3) | h);
+        }
+        wave_sync();
+        if (end) ct[t] += l - rs + 1;
+        wave_sync();
+      }
     }
     seg0 = seg1;
   }
