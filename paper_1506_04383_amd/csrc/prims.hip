@@ -125,7 +125,7 @@ hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s,
 
 // ---------------------------------------------------------------- radix sort
 constexpr int RS_T = 256;
-constexpr int RS_TILE = 4096;  // elements per block
+constexpr int RS_TILE = 1024;  // elements per block (4 steps of RS_T; >= 2 blocks per CU from 2^19 keys)
 constexpr int RS_NW = RS_T / 64;
 
 __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
