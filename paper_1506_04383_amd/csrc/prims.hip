@@ -71,6 +71,39 @@ __global__ __launch_bounds__(SCAN_T) void k_tile_scan(const Tin* __restrict__ in
   }
 }
 
+// As k_tile_scan, for few tiles (m <= SCAN_FUSE_MAX): each block adds the
+// sums of the tiles before it itself (so no separate scan of the sums), and
+// the last block also writes the total to out[n].
+constexpr int64_t SCAN_FUSE_MAX = 512;
+template <typename Tin>
+__global__ __launch_bounds__(SCAN_T) void k_tile_scan_fused(const Tin* __restrict__ in, int64_t n,
+                                                            const int64_t* __restrict__ part,
+                                                            int64_t m, int64_t* __restrict__ out) {
+  __shared__ int64_t sh[SCAN_T / 64 + 1];
+  int64_t c = 0;
+  for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += SCAN_T) c += part[j];
+  int64_t carry;
+  block_excl_scan<int64_t>(c, sh, &carry);
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+  int64_t v[SCAN_I];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    int64_t j = base + i;
+    v[i] = j < n ? (int64_t)in[j] : 0;
+    s += v[i];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan<int64_t>(s, sh, &tot) + carry;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    int64_t j = base + i;
+    if (j < n) out[j] = ex;
+    ex += v[i];
+  }
+  if ((int64_t)blockIdx.x == m - 1 && threadIdx.x == 0) out[n] = carry + tot;
+}
+
 __global__ void k_set_last(int64_t* out, int64_t n, const int64_t* part, int64_t m) {
   out[n] = part[m];
 }
@@ -112,6 +145,11 @@ hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s,
   DevBuf& part = ws ? *ws : local;
   if (part.bytes < sizeof(int64_t) * (size_t)(m + 1))
     MM_TRY(part.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  if (m <= SCAN_FUSE_MAX) {  // two launches instead of four (n > SCAN_SMALL_MAX, so m >= 1)
+    k_tile_sums<Tin><<<(unsigned)m, SCAN_T, 0, s>>>(in, n, part.as<int64_t>());
+    k_tile_scan_fused<Tin><<<(unsigned)m, SCAN_T, 0, s>>>(in, n, part.as<int64_t>(), m, out);
+    return hipGetLastError();
+  }
   if (m > 0) {
     k_tile_sums<Tin><<<(unsigned)m, SCAN_T, 0, s>>>(in, n, part.as<int64_t>());
   }
