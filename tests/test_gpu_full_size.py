@@ -1,0 +1,153 @@
+"""Parity at the full size of the workload bench.py times: R-MAT scale 20
+(8 * 2^20 draws, a = .57, b = c = .19, seed 1; 546,036 vertices after the
+largest component, 9.7e9 k-hop entries at k = 2), in the bench's launch
+configuration, on outputs the FP64 oracle computes one by one.
+
+Bars:
+* k-hop rows of 64 sampled vertices bit-exact to their definition (the
+  sorted 1-hop neighbours, then the sorted 2-hop ones), with the hop ends,
+  and their sizes equal to the oracle's breadth-first search;
+* Barnes-Hut (theta = 0.5) over all 546,036 points: Morton codes, order,
+  node table and interaction counts bit-exact to the oracle's, F within
+  1e-4 relative to max(|F_u|, mean |F|);
+* one sweep of the finest level in the bench's configuration (sliced layout,
+  tiles of 2^13 vertices, 2 blocks per lane and step) within
+  1e-4 * max(|x_orc|, 1) of the oracle's FP64 update of 512 sampled rows fed
+  the same FP32 inputs;
+* the first coarsening step (label propagation at h = 1, contraction)
+  bit-exact to the oracle's, and one sweep of that coarse level (406K
+  vertices, 8.8e9 entries) in the bench's level-1 configuration (sliced,
+  tiles of 2^12, 4 blocks) within the same bar on 512 sampled rows.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SLICED = 64  # lanes code of the sliced layout in forced configurations
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1506_04383_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def full(mm):
+    print("[full] generating R-MAT scale 20", flush=True)
+    g = synth.rmat(20, 8 << 20, 1)
+    ctx = mm.Context(0)
+    dg = ctx.graph(g.row_ptr, g.col)
+    rng = np.random.default_rng(11)
+    x = (rng.random((g.n, 2)) * math.sqrt(g.n)).astype(np.float32)
+    yield g, ctx, dg, x
+    ctx.close()
+
+
+def _rel_err(xo, xr):
+    return float(np.max(np.abs(xo - xr) / np.maximum(np.abs(xr), 1.0)))
+
+
+def test_full_khop_rows(orc, mm, full):
+    import torch
+
+    g, ctx, dg, x = full
+    print(f"[full khop] n={g.n}", flush=True)
+    kh = mm.khop_build(ctx, dg, 2)
+    try:
+        assert kh.n == g.n and kh.k == 2 and kh.total > 9_000_000_000
+        dev = torch.device("cuda", 0)
+        off = torch.empty(kh.n + 1, dtype=torch.int64, device=dev)
+        hend = torch.empty(kh.n * kh.k, dtype=torch.int32, device=dev)
+        nbr = torch.empty(kh.total, dtype=torch.int32, device=dev)
+        mm._check(mm.lib().mm_khop_export(ctx.h, kh.h, mm._ptr(off), mm._ptr(hend), mm._ptr(nbr),
+                                          mm.MM_DEVICE))
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(5)
+        deg = np.diff(g.row_ptr)
+        # the highest-degree vertex and random ones
+        rows = np.unique(np.concatenate([[int(np.argmax(deg))], rng.choice(g.n, 63, replace=False)]))
+        offh = off.cpu().numpy()
+        _, sizes = orc.sweep_rows(g.row_ptr, g.col, 2, x, np.zeros_like(x), 0.5, rows)
+        for u, sz in zip(rows, sizes):
+            n1 = np.sort(g.col[g.row_ptr[u]:g.row_ptr[u + 1]])
+            two = np.unique(np.concatenate([g.col[g.row_ptr[w]:g.row_ptr[w + 1]] for w in n1]))
+            n2 = np.setdiff1d(two, np.append(n1, u))
+            want = np.concatenate([n1, n2]).astype(np.int32)
+            got = nbr[offh[u]:offh[u + 1]].cpu().numpy()
+            assert np.array_equal(got, want), f"row {u}"
+            assert list(hend[2 * u:2 * u + 2].cpu().numpy()) == [n1.size, want.size]
+            assert sz == want.size
+    finally:
+        kh.free()
+
+
+def test_full_barnes_hut(orc, mm, full):
+    g, ctx, dg, x = full
+    print(f"[full bh] n={g.n}", flush=True)
+    r = mm.repulsion(ctx, x, 0.0, 0.5, export=True)
+    ref = orc.barnes_hut(x.astype(np.float64), 0.5)
+    assert np.array_equal(r["codes"], ref.codes)
+    assert np.array_equal(r["order"].cpu().numpy(), ref.order)
+    assert np.array_equal(r["nodes"].cpu().numpy(), ref.nodes)
+    assert r["accepted"] == ref.accepted and r["leaf_pairs"] == ref.leaf_pairs
+    F, Fr = r["F"].cpu().numpy(), ref.F
+    nr = np.linalg.norm(Fr, axis=1)
+    err = float(np.max(np.linalg.norm(F - Fr, axis=1) / np.maximum(nr, nr.mean())))
+    print(f"  max err {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
+def _sweep_rows_check(orc, mm, ctx, rp, col, x, c, level, config):
+    """One sweep in `config` vs the oracle on 512 sampled rows."""
+    dg = ctx.graph(rp, col, c, None) if c is not None else ctx.graph(rp, col)
+    kh = mm.khop_build(ctx, dg, 2)
+    try:
+        F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
+        alpha = 0.37
+        xo, _ = mm.sweep(ctx, kh, x, F, alpha, 0.0, level, c, 1.0, config=config)
+        xo = xo.cpu().numpy()
+    finally:
+        kh.free()
+    rng = np.random.default_rng(3 + level)
+    rows = rng.choice(rp.size - 1, 512, replace=False).astype(np.int32)
+    xr, sizes = orc.sweep_rows(rp, col, 2, x.astype(np.float64),
+                               F.cpu().numpy().astype(np.float64), alpha, rows, 0.0, level, c, 1.0)
+    err = _rel_err(xo[rows], xr)
+    print(f"  level {level}: {rows.size} rows (mean |S| {sizes.mean():.0f}), max err {err:.3e}",
+          flush=True)
+    assert err < 1e-4
+
+
+def test_full_sweep_finest(orc, mm, full):
+    g, ctx, dg, x = full
+    print(f"[full sweep] level 0, config (13, sliced, 2)", flush=True)
+    _sweep_rows_check(orc, mm, ctx, g.row_ptr, g.col, x, None, 0, (13, SLICED, 2))
+
+
+def test_full_coarsen_and_coarse_sweep(orc, mm, full):
+    g, ctx, dg, x = full
+    print(f"[full coarsen] h=1", flush=True)
+    lv = orc.Level(g.row_ptr, g.col)
+    U = 2.0  # max(max c, min(b^h, |V|/f)) at h = 1 with b = 2, unit weights
+    cl, (rp, col, cw, ew), rounds, moves = mm.coarsen(ctx, dg, U, 10, 1, 1)
+    lab, mv = orc.lp(lv.row_ptr, lv.col, U, 10, 1, 1, lv.c, lv.w)
+    rcl, G = orc.contract(lv, lab)
+    assert rounds == mv.size and np.array_equal(moves, mv)
+    assert np.array_equal(cl.cpu().numpy(), rcl)
+    assert np.array_equal(rp, G.row_ptr) and np.array_equal(col, G.col)
+    assert np.array_equal(cw, G.c) and np.array_equal(ew, G.w)
+    print(f"[full sweep] level 1 (n={G.n}), config (12, sliced, 4)", flush=True)
+    rng = np.random.default_rng(13)
+    xc = (rng.random((G.n, 2)) * math.sqrt(G.n)).astype(np.float32)
+    _sweep_rows_check(orc, mm, ctx, G.row_ptr, G.col, xc, G.c, 1, (12, SLICED, 4))
