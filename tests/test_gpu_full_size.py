@@ -18,6 +18,10 @@ Bars:
   bit-exact to the oracle's, and one sweep of that coarse level (406K
   vertices, 8.8e9 entries) in the bench's level-1 configuration (sliced,
   tiles of 2^12, 4 blocks) within the same bar on 512 sampled rows.
+
+The learned-far-field workload's graph (RGG 2^22, k = 3) and the batched
+workload (4096 graphs, 6.7M vertices) are covered at full size as well (see
+their tests).
 """
 import math
 
@@ -151,3 +155,105 @@ def test_full_coarsen_and_coarse_sweep(orc, mm, full):
     rng = np.random.default_rng(13)
     xc = (rng.random((G.n, 2)) * math.sqrt(G.n)).astype(np.float32)
     _sweep_rows_check(orc, mm, ctx, G.row_ptr, G.col, xc, G.c, 1, (12, SLICED, 4))
+
+
+def _bfs_row(rp, col, u, k):
+    """S_k(u) by definition: vertices at hop 1..k from u, sorted by (hop, id)."""
+    seen = {int(u)}
+    frontier = [int(u)]
+    out, ends = [], []
+    for _ in range(k):
+        nxt = set()
+        for w in frontier:
+            nxt.update(int(v) for v in col[rp[w]:rp[w + 1]])
+        nxt -= seen
+        seen |= nxt
+        frontier = sorted(nxt)
+        out += frontier
+        ends.append(len(out))
+    return np.array(out, np.int32), ends
+
+
+def test_full_rgg22(orc, mm):
+    """The learned-far-field workload's graph (RGG 2^22, mean degree 8, k = 3)
+    at full size: sampled k-hop rows, Barnes-Hut at theta = 1 (the learned
+    configuration's tree) and 0.5 (the plain one) over all points, and one
+    finest-level sweep on 512 sampled rows in the default configuration."""
+    import torch
+
+    g = synth.config_graph("rgg22", 1)
+    print(f"[full rgg22] n={g.n} m={g.m}", flush=True)
+    ctx = mm.Context(0)
+    try:
+        dg = ctx.graph(g.row_ptr, g.col)
+        rng = np.random.default_rng(21)
+        x = (rng.random((g.n, 2)) * math.sqrt(g.n)).astype(np.float32)
+        kh = mm.khop_build(ctx, dg, 3)
+        dev = torch.device("cuda", 0)
+        off = torch.empty(kh.n + 1, dtype=torch.int64, device=dev)
+        hend = torch.empty(kh.n * kh.k, dtype=torch.int32, device=dev)
+        nbr = torch.empty(kh.total, dtype=torch.int32, device=dev)
+        mm._check(mm.lib().mm_khop_export(ctx.h, kh.h, mm._ptr(off), mm._ptr(hend), mm._ptr(nbr),
+                                          mm.MM_DEVICE))
+        offh = off.cpu().numpy()
+        for u in rng.choice(g.n, 64, replace=False):
+            want, ends = _bfs_row(g.row_ptr, g.col, u, 3)
+            assert np.array_equal(nbr[offh[u]:offh[u + 1]].cpu().numpy(), want), f"row {u}"
+            assert list(hend[3 * u:3 * u + 3].cpu().numpy()) == ends
+        del off, hend, nbr
+        for theta in (1.0, 0.5):
+            r = mm.repulsion(ctx, x, 0.0, theta, export=True)
+            ref = orc.barnes_hut(x.astype(np.float64), theta)
+            assert np.array_equal(r["nodes"].cpu().numpy(), ref.nodes)
+            assert r["accepted"] == ref.accepted and r["leaf_pairs"] == ref.leaf_pairs
+            F, Fr = r["F"].cpu().numpy(), ref.F
+            nr = np.linalg.norm(Fr, axis=1)
+            err = float(np.max(np.linalg.norm(F - Fr, axis=1) / np.maximum(nr, nr.mean())))
+            print(f"  theta {theta}: max far-field err {err:.3e}", flush=True)
+            assert err < 1e-4
+        F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
+        xo, _ = mm.sweep(ctx, kh, x, F, 0.37, mode=mm.SWEEP_AUTO)
+        kh.free()
+        rows = rng.choice(g.n, 512, replace=False).astype(np.int32)
+        xr, _ = orc.sweep_rows(g.row_ptr, g.col, 3, x.astype(np.float64),
+                               F.cpu().numpy().astype(np.float64), 0.37, rows)
+        err = _rel_err(xo.cpu().numpy()[rows], xr)
+        print(f"  sweep: max err {err:.3e}", flush=True)
+        assert err < 1e-4
+    finally:
+        ctx.close()
+
+
+def test_full_batch_4096(orc, mm):
+    """The batched workload at full size (4096 graphs of 64..8192 vertices,
+    6.7M vertices in one union, the bench's parameters): per-graph hierarchy
+    depth equal to the oracle's on 64 sampled graphs, and the final
+    maxent-stress of 4 sampled graphs (and the largest) within 1% of the
+    oracle's layout of the same graph."""
+    P = dict(k=3, theta=0.5, alpha_decay=0.5, coarsest_n=100, seed=1, validate=0)
+    gs = synth.batch_graphs(4096, 1)
+    rp, col, offs = synth.concat(gs)
+    print(f"[full batch] {len(gs)} graphs, n={int(offs[-1])}", flush=True)
+    ctx = mm.Context(0)
+    try:
+        xy, lev, st = mm.layout_batch(ctx, ctx.graph(rp, col), None, offs, mm.Params(**P))
+        op = orc.Params(**{k: v for k, v in P.items() if k != "validate"})
+        rng = np.random.default_rng(4)
+        for i in rng.choice(len(gs), 64, replace=False):
+            levels, _, _ = orc.hierarchy(orc.Level(gs[i].row_ptr, gs[i].col), op)
+            assert lev[i] == len(levels), i
+        sizes = np.diff(offs)
+        pick = list(rng.choice(len(gs), 4, replace=False)) + [int(np.argmax(sizes))]
+        for i in pick:
+            g = gs[int(i)]
+            xo, _ = orc.layout(g, op)
+            Mo = orc.objective(orc.khop_build(g.row_ptr, g.col, 3), xo, 0.008)["M"]
+            kh = mm.khop_build(ctx, ctx.graph(g.row_ptr, g.col), 3)
+            Mb = mm.objective(ctx, kh, xy[int(offs[i]):int(offs[i + 1])], 0.008)["M"]
+            kh.free()
+            rel = abs(Mb - Mo) / abs(Mo)
+            print(f"  graph {int(i)} (n={g.n}): M_S batch {Mb:.6e} oracle {Mo:.6e} rel {rel:.2e}",
+                  flush=True)
+            assert rel <= 0.01
+    finally:
+        ctx.close()
