@@ -66,6 +66,13 @@ __device__ inline uint32_t hslot(int32_t lab, uint32_t mask) {
 }
 
 // big: nonzero => use global tables; gkeys/gsc sized by hoff (per-vertex table offsets).
+// Orders a work-group's own hash-table writes and atomics before its reads.
+__device__ inline void lp_table_fence(bool global_table) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (global_table) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const int32_t* __restrict__ c, const int32_t* __restrict__ ew, const int32_t* __restrict__ label,
@@ -107,10 +114,11 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     mask = (uint32_t)(hoff[v + 1] - hoff[v]) - 1u;
   }
   for (uint32_t i = l; i <= mask; i += 64) { keys[i] = -1; sc[i] = 0; }
-  // the wave's own table writes/atomics before its reads: LDS tables need
-  // only the work-group fence; global tables the device-scope one
-  if (deg <= LP_SMALL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  else __threadfence();
+  // the wave's own table writes/atomics before its reads: only this wave
+  // touches the table, so a work-group-scope release orders them (a
+  // device-scope release would also write back the L2); a global table's
+  // reads also take a device-scope acquire, which drops this CU's L1 copies
+  lp_table_fence(deg > LP_SMALL);
   __builtin_amdgcn_wave_barrier();
   for (int32_t e = l; e < deg; e += 64) {
     const int32_t lab = label[col[beg + e]];
@@ -123,10 +131,11 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
     }
     atomicAdd((unsigned long long*)&sc[s], (unsigned long long)wt);
   }
-  // the wave's own table writes/atomics before its reads: LDS tables need
-  // only the work-group fence; global tables the device-scope one
-  if (deg <= LP_SMALL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  else __threadfence();
+  // the wave's own table writes/atomics before its reads: only this wave
+  // touches the table, so a work-group-scope release orders them (a
+  // device-scope release would also write back the L2); a global table's
+  // reads also take a device-scope acquire, which drops this CU's L1 copies
+  lp_table_fence(deg > LP_SMALL);
   __builtin_amdgcn_wave_barrier();
   Cand best;
   best.sc = -1; best.lab = 0x7fffffff; best.own = 0;
@@ -182,8 +191,10 @@ __global__ __launch_bounds__(LP_BT) void k_lp_propose_big(
   long long* sc = gsc + hoff[v];
   const uint32_t mask = (uint32_t)(hoff[v + 1] - hoff[v]) - 1u;
   for (uint32_t i = t; i <= mask; i += LP_BT) { keys[i] = -1; sc[i] = 0; }
-  __threadfence();
+  // the table is this work-group's: the barrier (work-group-scope fences)
+  // orders its global writes and atomics, the acquire drops stale L1 lines
   __syncthreads();
+  lp_table_fence(true);
   for (int32_t e = t; e < deg; e += LP_BT) {
     const int32_t lab = label[col[beg + e]];
     const long long wt = ew ? ew[beg + e] : 1;
@@ -195,8 +206,8 @@ __global__ __launch_bounds__(LP_BT) void k_lp_propose_big(
     }
     atomicAdd((unsigned long long*)&sc[sl], (unsigned long long)wt);
   }
-  __threadfence();
   __syncthreads();
+  lp_table_fence(true);
   Cand best;
   best.sc = -1; best.lab = 0x7fffffff; best.own = 0;
   for (uint32_t i = t; i <= mask; i += LP_BT) {
