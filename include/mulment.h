@@ -183,6 +183,28 @@ mm_status mm_khop_arrays(const mm_khop* kh, const int64_t** off, const int32_t**
 mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32_t* hend,
                          int32_t* nbr, int32_t mem);
 
+/* General stress sets (the footnote to Eq. 1: any S ⊇ E, each pair with its
+ * target distance d_uv).  The caller's arrays use the layout of the k-hop
+ * sets above: row offsets off[n+1] (off[0] = 0, non-decreasing, total =
+ * off[n]); hend[u*k + h-1] = entries of row u with d_uv <= h, for integer
+ * distances h in 1..k (k in [1, 8]); nbr[total] ids, strictly increasing
+ * inside each distance group.  S is a set of unordered pairs: an entry v at
+ * distance h in row u needs u at distance h in row v.  No id repeats in a
+ * row, none equals its row, all lie in [0, n).  That S contains E is the
+ * caller's model choice and is not checked (no graph is passed).
+ *
+ * mm_khop_validate checks host arrays only (no device work, no context):
+ * MM_OK, or MM_EINVAL naming the first violation (mm_last_error).
+ * mm_khop_import copies the arrays (kind mem: MM_HOST or MM_DEVICE; device
+ * arrays are read back to the host for the same checks) into a new set that
+ * mm_sweep, mm_sweep_ex, mm_sweep_cfg, mm_objective and the mm_khop_*
+ * queries accept like a built one; the caller keeps ownership of its
+ * arrays.  Errors: MM_EINVAL as above, MM_ENOMEM. */
+mm_status mm_khop_validate(int32_t n, int32_t k, const int64_t* off, const int32_t* hend,
+                           const int32_t* nbr);
+mm_status mm_khop_import(mm_context* ctx, int32_t n, int32_t k, const int64_t* off,
+                         const int32_t* hend, const int32_t* nbr, int32_t mem, mm_khop** out);
+
 /* Far field F_u = sum_{v != u} r_q(u,v) (the entropy term of Eq. 2 before
  * removing S).  theta < 0: exact all-pairs; theta >= 0: Barnes-Hut quadtree.
  * xy, F: n*2 FP32 device.  codes (n, Morton codes in id order), order (n,

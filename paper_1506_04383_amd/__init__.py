@@ -93,7 +93,7 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
            "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg",
-           "mm_repulsion_cluster", "mm_full_stress_ex"]
+           "mm_repulsion_cluster", "mm_full_stress_ex", "mm_khop_validate", "mm_khop_import"]
 
 TUNE_FIELDS = 7  # coarse?, n, sum |S|, k, tile bits, lanes, blocks per step
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
@@ -121,6 +121,8 @@ def lib():
         "mm_khop_info": [vp, P(i32), P(i32), P(i64)],
         "mm_khop_arrays": [vp, P(vp), P(vp), P(vp)],
         "mm_khop_export": [vp, vp, vp, vp, vp, i32],
+        "mm_khop_validate": [i32, i32, vp, vp, vp],
+        "mm_khop_import": [vp, i32, i32, vp, vp, vp, i32, P(vp)],
         "mm_repulsion": [vp, i32, vp, f64, f64, vp, vp, vp, vp, vp],
         "mm_sweep": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp],
         "mm_sweep_ex": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32],
@@ -372,6 +374,53 @@ def khop_build(ctx: Context, g: DeviceGraph, k: int) -> KHop:
     h = C.c_void_p()
     gc = g.c()
     _check(lib().mm_khop_build(ctx.h, C.byref(gc), k, C.byref(h)))
+    return KHop(ctx, h)
+
+
+def _set_arrays(off, hend, nbr):
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    hend = np.ascontiguousarray(hend, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    return off, hend, nbr
+
+
+def khop_validate(n: int, k: int, off, hend, nbr) -> None:
+    """Host check of a general stress set S (raises MMError naming the first
+    violation); no device work."""
+    off, hend, nbr = _set_arrays(off, hend, nbr)
+    if off.size != n + 1 or hend.size != n * k or nbr.size < (off[-1] if off.size else 0):
+        raise ValueError("array sizes do not match n, k and off[n]")
+    _check(lib().mm_khop_validate(n, k, off.ctypes.data_as(C.c_void_p),
+                                  hend.ctypes.data_as(C.c_void_p),
+                                  nbr.ctypes.data_as(C.c_void_p)))
+
+
+def khop_import(ctx: Context, n: int, k: int, off, hend, nbr) -> KHop:
+    """A general stress set S ⊇ E with integer target distances 1..k, in the
+    layout of the k-hop sets (host numpy arrays or CUDA tensors); usable by
+    every sweep configuration and the objective."""
+    t = ctx.torch
+    h = C.c_void_p()
+    dev = [isinstance(a, t.Tensor) and a.is_cuda for a in (off, hend, nbr)]
+    if all(dev):
+        if off.dtype != t.int64 or hend.dtype != t.int32 or nbr.dtype != t.int32:
+            raise TypeError("device arrays must be int64 off, int32 hend and nbr")
+        if off.numel() != n + 1 or hend.numel() != n * k:
+            raise ValueError("array sizes do not match n and k")
+        off, hend, nbr = off.contiguous(), hend.contiguous(), nbr.contiguous()
+        if nbr.numel() < int(off[-1].item()):
+            raise ValueError("nbr shorter than off[n]")
+        _check(lib().mm_khop_import(ctx.h, n, k, _ptr(off), _ptr(hend), _ptr(nbr), MM_DEVICE,
+                                    C.byref(h)))
+    elif any(dev):
+        raise TypeError("off, hend and nbr must all live on the host or all on the device")
+    else:
+        off, hend, nbr = _set_arrays(off, hend, nbr)
+        if off.size != n + 1 or hend.size != n * k or nbr.size < (off[-1] if off.size else 0):
+            raise ValueError("array sizes do not match n, k and off[n]")
+        _check(lib().mm_khop_import(ctx.h, n, k, off.ctypes.data_as(C.c_void_p),
+                                    hend.ctypes.data_as(C.c_void_p),
+                                    nbr.ctypes.data_as(C.c_void_p), MM_HOST, C.byref(h)))
     return KHop(ctx, h)
 
 

@@ -510,6 +510,130 @@ mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32
   return MM_OK;
 }
 
+// A general stress set S ⊇ E (footnote to Eq. 1) handed in by the caller, in
+// the layout of the k-hop sets: per row the entries are grouped by their
+// target distance d_uv = h in 1..k (hend cumulative), ids strictly increasing
+// inside a group.  S is a set of unordered pairs: (u, v, h) in row u needs
+// (v, u, h) in row v.
+mm_status mm_khop_validate(int32_t n, int32_t k, const int64_t* off, const int32_t* hend,
+                           const int32_t* nbr) {
+  if (!off || !hend) return fail(MM_EINVAL, "NULL argument");
+  if (n < 2) return fail(MM_EINVAL, "n < 2");
+  if (k < 1 || k > 8) return fail(MM_EINVAL, "k must be in [1, 8]");
+  if (off[0] != 0) return fail(MM_EINVAL, "off[0] = %lld, must be 0", (long long)off[0]);
+  for (int32_t u = 0; u < n; ++u) {
+    const int64_t len = off[u + 1] - off[u];
+    if (len < 0) return fail(MM_EINVAL, "off decreases at row %d", u);
+    if (len >= n) return fail(MM_EINVAL, "row %d has %lld entries (at most n-1)", u, (long long)len);
+    int32_t prev = 0;
+    for (int32_t h = 0; h < k; ++h) {
+      const int32_t e = hend[(size_t)u * k + h];
+      if (e < prev) return fail(MM_EINVAL, "hend of row %d decreases at distance %d", u, h + 1);
+      prev = e;
+    }
+    if (prev != len)
+      return fail(MM_EINVAL, "hend of row %d ends at %d, row has %lld entries", u, prev, (long long)len);
+  }
+  const int64_t total = off[n];
+  if (total > 0 && !nbr) return fail(MM_EINVAL, "nbr is NULL");
+  std::vector<int32_t> seen((size_t)n, -1);
+  for (int32_t u = 0; u < n; ++u) {
+    const int32_t* row = nbr + off[u];
+    int32_t s0 = 0;
+    for (int32_t h = 0; h < k; ++h) {
+      const int32_t s1 = hend[(size_t)u * k + h];
+      for (int32_t i = s0; i < s1; ++i) {
+        const int32_t v = row[i];
+        if (v < 0 || v >= n) return fail(MM_EINVAL, "row %d: id %d out of range", u, v);
+        if (v == u) return fail(MM_EINVAL, "row %d holds itself", u);
+        if (i > s0 && row[i - 1] >= v)
+          return fail(MM_EINVAL, "row %d: ids at distance %d not strictly increasing", u, h + 1);
+        if (seen[(size_t)v] == u) return fail(MM_EINVAL, "row %d holds %d twice", u, v);
+        seen[(size_t)v] = u;
+      }
+      s0 = s1;
+    }
+  }
+  // every row is well formed now: look up the mirror of each pair, u in the
+  // group of row v with the same distance
+  for (int32_t u = 0; u < n; ++u) {
+    const int32_t* row = nbr + off[u];
+    int32_t s0 = 0;
+    for (int32_t h = 0; h < k; ++h) {
+      const int32_t s1 = hend[(size_t)u * k + h];
+      for (int32_t i = s0; i < s1; ++i) {
+        const int32_t v = row[i];
+        const int32_t* vr = nbr + off[v];
+        const int32_t* b = vr + (h ? hend[(size_t)v * k + h - 1] : 0);
+        const int32_t* e = vr + hend[(size_t)v * k + h];
+        const int32_t* f = std::lower_bound(b, e, u);
+        if (f == e || *f != u)
+          return fail(MM_EINVAL, "pair (%d, %d) at distance %d has no mirror (%d, %d)", u, v, h + 1, v, u);
+      }
+      s0 = s1;
+    }
+  }
+  return MM_OK;
+}
+
+mm_status mm_khop_import(mm_context* ctx, int32_t n, int32_t k, const int64_t* off,
+                         const int32_t* hend, const int32_t* nbr, int32_t mem, mm_khop** out) {
+  try {
+    if (!ctx || !off || !hend || !out) return fail(MM_EINVAL, "NULL argument");
+    if (mem != MM_HOST && mem != MM_DEVICE) return fail(MM_EINVAL, "bad mem kind");
+    if (n < 2) return fail(MM_EINVAL, "n < 2");
+    if (k < 1 || k > 8) return fail(MM_EINVAL, "k must be in [1, 8]");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    // host copies for the checks when the caller's arrays live on the device
+    std::vector<int64_t> h_off;
+    std::vector<int32_t> h_hend, h_nbr;
+    const int64_t* ho = off;
+    const int32_t* hh = hend;
+    const int32_t* hn = nbr;
+    if (mem == MM_DEVICE) {
+      h_off.resize((size_t)n + 1);
+      h_hend.resize((size_t)n * k);
+      HIPCHK(hipMemcpyAsync(h_off.data(), off, sizeof(int64_t) * h_off.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(h_hend.data(), hend, sizeof(int32_t) * h_hend.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const int64_t tot = h_off[(size_t)n];
+      if (tot < 0 || h_off[0] != 0) return fail(MM_EINVAL, "off[0] must be 0 and off[n] >= 0");
+      if (tot > 0) {
+        if (!nbr) return fail(MM_EINVAL, "nbr is NULL");
+        h_nbr.resize((size_t)tot);
+        HIPCHK(hipMemcpyAsync(h_nbr.data(), nbr, sizeof(int32_t) * h_nbr.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+      ho = h_off.data();
+      hh = h_hend.data();
+      hn = h_nbr.data();
+    }
+    STCHK(mm_khop_validate(n, k, ho, hh, hn));
+    const int64_t total = ho[n];
+    std::unique_ptr<mm_khop> kh(new mm_khop());
+    mm::KhopDev& K = kh->kh;
+    K.n = n;
+    K.k = k;
+    K.total = total;
+    HIPCHK(K.b_off.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+    HIPCHK(K.b_hend.alloc(sizeof(int32_t) * (size_t)n * k, s));
+    HIPCHK(K.b_nbr.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), s));
+    K.off = K.b_off.as<int64_t>();
+    K.hend = K.b_hend.as<int32_t>();
+    K.nbr = K.b_nbr.as<int32_t>();
+    const hipMemcpyKind kd = mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(K.off, off, sizeof(int64_t) * (size_t)(n + 1), kd, s));
+    HIPCHK(hipMemcpyAsync(K.hend, hend, sizeof(int32_t) * (size_t)n * k, kd, s));
+    if (total > 0) HIPCHK(hipMemcpyAsync(K.nbr, nbr, sizeof(int32_t) * (size_t)total, kd, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = kh.release();
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_khop_import");
+  }
+}
+
 // ------------------------------------------------------------- far field
 
 mm_status mm_repulsion(mm_context* ctx, int32_t n, const float* xy, double q, double theta,
