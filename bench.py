@@ -430,8 +430,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
     ap.add_argument("--full-stress", action="store_true",
-                    help="also compute the full stress F(x) over all pairs (one BFS per vertex "
-                         "on the GPU) at the optimal scale")
+                    help="also compute the full stress F(x) over all pairs at the optimal scale "
+                         "(breadth-first searches on the GPU: bit-parallel over all vertices for "
+                         "low diameters, banded otherwise)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: the sweep configuration of every level is timed and chosen during "
                          "the first layout (the warm-up) and reused by the timed ones")

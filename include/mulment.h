@@ -343,14 +343,20 @@ mm_status mm_objective(mm_context* ctx, const mm_khop* kh, int32_t level, const 
 
 /* Full stress over all connected pairs with hop distances (Section 4):
  * out (host, 3) = {F(x), s*, F(s* x)}; the graph in device memory.  Hop
- * distances come from breadth-first searches on the GPU: for n > 65536 a
- * bit-parallel search of 256 sources at a time when the graph's diameter is
- * low (the first 256 sources finish within 64 levels), otherwise one search
- * per source (n <= 1179648, else MM_EUNSUPPORTED). */
+ * distances come from breadth-first searches on the GPU: one search per
+ * source for n <= 65536; above, a bit-parallel search of 256 sources at a
+ * time over all vertices when the graph's diameter is low (the first 256
+ * sources finish within 64 levels), otherwise the banded search: vertices
+ * renumbered in Morton order of xy, 64 neighbouring sources per search, each
+ * level visiting only the 64-vertex tiles next to the vertices reached at
+ * the level before (n <= 2^23, else MM_EUNSUPPORTED).  Fast when the layout
+ * roughly follows graph distances; correct for any xy.  Every method sums in
+ * a fixed order (bit-identical reruns). */
 mm_status mm_full_stress(mm_context* ctx, const mm_graph* g, const float* xy, double* out);
 /* As mm_full_stress with the method chosen: 0 as above, 1 the multi-source
- * search (any n and diameter), 2 one search per source (n <= 1179648).  The
- * results agree up to the order of the FP64 sums. */
+ * search over all vertices (any n and diameter), 2 one search per source
+ * (n <= 1179648), 3 the banded search (n <= 2^23).  The results agree up to
+ * the order of the FP64 sums. */
 mm_status mm_full_stress_ex(mm_context* ctx, const mm_graph* g, const float* xy, int32_t method,
                             double* out);
 

@@ -624,7 +624,7 @@ def objective(ctx: Context, kh: KHop, xy, alpha: float, q: float = 0.0, level: i
 
 def full_stress(ctx: Context, g: DeviceGraph, xy, method: int = 0) -> dict:
     """Full stress at the optimal scale; method 0 auto, 1 multi-source BFS,
-    2 one BFS per source (mm_full_stress_ex)."""
+    2 one BFS per source, 3 banded multi-source search (mm_full_stress_ex)."""
     t = ctx.torch
     xy = ctx._dev(xy, t.float32)
     out = np.zeros(3)

@@ -909,10 +909,12 @@ mm_status mm_full_stress_ex(mm_context* ctx, const mm_graph* g, const float* xy,
   try {
     if (!ctx || !g || !xy || !out) return fail(MM_EINVAL, "NULL argument");
     if (g->mem != MM_DEVICE) return fail(MM_EINVAL, "mm_full_stress needs a device graph");
-    if (method < 0 || method > 2) return fail(MM_EINVAL, "method must be 0, 1 or 2");
+    if (method < 0 || method > 3) return fail(MM_EINVAL, "method must be 0, 1, 2 or 3");
     if (g->n < 1) return fail(MM_EINVAL, "n < 1");
     if (method == 2 && g->n > 1179648)
       return fail(MM_EUNSUPPORTED, "one BFS per source is limited to n <= 1179648");
+    if (method == 3 && g->n > (1 << 23))
+      return fail(MM_EUNSUPPORTED, "the banded search is limited to n <= 2^23");
     DeviceGuard dg(ctx->device);
     mm::GraphDev G;
     G.n = g->n; G.nnz = g->nnz;

@@ -315,9 +315,10 @@ hipError_t batch_cl_map(int32_t n, const int32_t* cluster, const int32_t* cflag,
 hipError_t objective(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                      const float* xy, double q, double* out_host, hipStream_t s);
 // out (host, 3 doubles): F unscaled, s*, F(s* x).
-// method 0: multi-source BFS for n > 65536 when the graph's diameter is low
-// (at most 64 levels from the first 256 sources), else one BFS per source;
-// 1: multi-source BFS; 2: one BFS per source (n <= 1179648)
+// method 0: n <= 65536 one BFS per source; larger graphs the multi-source BFS
+// when the diameter is low (at most 64 levels from the first 256 sources),
+// else the banded search; 1: multi-source BFS; 2: one BFS per source
+// (n <= 1179648); 3: banded search (n <= 2^23)
 hipError_t full_stress(const GraphDev& g, const float* xy, double* out_host, hipStream_t s,
                        int32_t method = 0);
 

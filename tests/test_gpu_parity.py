@@ -255,7 +255,8 @@ def test_objective_parity(orc, mm, ctx, k, level):
 
 
 @pytest.mark.parametrize("name,method", [("rgg2500", 2), ("rgg2500", 1), ("rmat12", 1),
-                                         ("rmat12", 2), ("tree", 1)])
+                                         ("rmat12", 2), ("tree", 1), ("rgg2500", 3),
+                                         ("rmat12", 3), ("tree", 3), ("tri", 3)])
 def test_full_stress_parity(orc, mm, ctx, name, method):
     """One BFS per source (method 2) and the bit-parallel multi-source BFS
     (method 1, 256 sources per pass, ragged last pass) vs the oracle."""
@@ -277,6 +278,68 @@ def test_full_stress_msbfs_large(mm, ctx):
     b = mm.full_stress(ctx, dg, x, method=2)
     for key in ("F_unscaled", "s_opt", "F"):
         assert abs(a[key] - b[key]) <= 1e-9 * abs(b[key]), key
+
+
+def _two_paths(n):
+    """Two paths of n // 2 vertices each, ids interleaved (a disconnected,
+    high-diameter graph)."""
+    a = np.arange(0, n - 2, 2)
+    b = np.arange(1, n - 2, 2)
+    return synth.csr_from_edges(n, np.concatenate([a, b]), np.concatenate([a + 2, b + 2]))
+
+
+@pytest.mark.parametrize("name", ["path3000", "del4000", "two_paths", "grid70x40", "single"])
+@pytest.mark.parametrize("layout", ["generator", "random"])
+def test_full_stress_banded_parity(orc, mm, ctx, name, layout):
+    """The banded search (method 3) against the oracle on high-diameter and
+    disconnected graphs, with a layout that follows the graph (thin bands)
+    and a random one (every tile visited often); ragged last tiles."""
+    g = {"path3000": lambda: synth.path(3000), "del4000": lambda: synth.delaunay(4000, 3),
+         "two_paths": lambda: _two_paths(2999), "grid70x40": lambda: synth.grid(70, 40),
+         "single": lambda: synth.path(1)}[name]()
+    if layout == "generator" and g.points is not None:
+        x = (g.points * 60).astype(np.float32)
+    elif layout == "generator":  # paths and grids: vertex ids along the graph
+        cols = 40 if name == "grid70x40" else 1
+        v = np.arange(g.n)
+        x = np.stack([v // cols, v % cols], 1).astype(np.float32)
+    elif g.n >= 8:
+        x = _layout_points(g.n, 6)
+    else:
+        x = np.random.default_rng(6).random((g.n, 2)).astype(np.float32)
+    print(f"[full stress banded] {name} n={g.n} layout={layout}", flush=True)
+    o = mm.full_stress(ctx, ctx.graph(g.row_ptr, g.col), x, method=3)
+    r = orc.full_stress(g.row_ptr, g.col, x.astype(np.float64))
+    for key in ("F_unscaled", "s_opt", "F"):
+        assert abs(o[key] - r[key]) <= 1e-6 * abs(r[key]) + 1e-12, key
+
+
+def test_full_stress_banded_large(mm, ctx):
+    """Delaunay 2^16 with its generator layout: the banded search equals one
+    search per source up to the order of the FP64 sums, reruns are
+    bit-identical, and the automatic choice (n > 65536 would pick it; here
+    n = 65536 picks per-source) agrees."""
+    g = synth.delaunay(1 << 16, 5)
+    x = (g.points * 256).astype(np.float32)
+    dg = ctx.graph(g.row_ptr, g.col)
+    a = mm.full_stress(ctx, dg, x, method=3)
+    b = mm.full_stress(ctx, dg, x, method=2)
+    c = mm.full_stress(ctx, dg, x, method=3)
+    assert a == c
+    for key in ("F_unscaled", "s_opt", "F"):
+        assert abs(a[key] - b[key]) <= 1e-9 * abs(b[key]), key
+
+
+def test_full_stress_auto_picks_banded_for_high_diameter(mm, ctx):
+    """n > 65536 and a diameter above 64: the automatic method gives the
+    banded search's result bit for bit."""
+    g = synth.grid(400, 180)  # 72,000 vertices, diameter 578
+    v = np.arange(g.n)
+    x = np.stack([v // 180, v % 180], 1).astype(np.float32) * 1.3
+    dg = ctx.graph(g.row_ptr, g.col)
+    a = mm.full_stress(ctx, dg, x, method=0)
+    b = mm.full_stress(ctx, dg, x, method=3)
+    assert a == b
 
 
 def test_layout_small_config_end_to_end(orc, mm, ctx):
