@@ -74,6 +74,8 @@ def lib():
         L.orc_far_samples.argtypes = [C.c_int32, f64p, C.c_double, C.c_int64, i32p, i64p, f64p,
                                       f64p, f64p, i64p]
         L.orc_bh_learned.argtypes = [C.c_int32, f64p, C.c_double, f64p, f64p]
+        L.orc_bh_learned_rows.argtypes = [C.c_int32, f64p, C.c_double, f64p, i32p, C.c_int32,
+                                          f64p]
         L.orc_mlp_forward.argtypes = [f64p, C.c_int64, f64p, f64p]
         _lib = L
     return _lib
@@ -237,6 +239,18 @@ def barnes_hut_learned(xy, theta: float, weights) -> np.ndarray:
     if lib().orc_bh_learned(n, xy, theta, w, F) != 0:
         raise MemoryError("bh_learned")
     return F.reshape(n, 2)
+
+
+def barnes_hut_learned_rows(xy, theta: float, weights, rows) -> np.ndarray:
+    """barnes_hut_learned for the given points only (same tree, same visit)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    rows = _i32(rows)
+    n = xy.size // 2
+    F = np.zeros(2 * rows.size)
+    if lib().orc_bh_learned_rows(n, xy, theta, w, rows, rows.size, F) != 0:
+        raise MemoryError("bh_learned_rows")
+    return F.reshape(-1, 2)
 
 
 def mlp_forward_c(weights, feat) -> np.ndarray:

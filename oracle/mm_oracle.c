@@ -695,6 +695,21 @@ int orc_bh_learned(int32_t n, const double* xy, double theta, const double* weig
     return 0;
 }
 
+int orc_bh_learned_rows(int32_t n, const double* xy, double theta, const double* weights,
+                        const int32_t* rows, int32_t nrows, double* F) {
+    bh_setup b;
+    if (bh_setup_build(n, xy, NULL, NULL, &b) != 0) return -1;
+    bh_ctx c = {&b.t, b.pts, b.ix, b.iy, xy, 0.0, theta * theta, b.xmin, b.ymin, b.scale};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t i = 0; i < nrows; ++i) {
+        double fx = 0.0, fy = 0.0;
+        bh_visit_learned(&c, b.root, rows[i], weights, NULL, &fx, &fy);
+        F[2 * i] = fx; F[2 * i + 1] = fy;
+    }
+    bh_setup_free(&b);
+    return 0;
+}
+
 void orc_mlp_forward(const double* weights, int64_t count, const double* feat, double* out) {
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < count; ++j) mlp_forward(weights, feat + MLP_IN * j, out + 2 * j);

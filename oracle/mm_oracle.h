@@ -101,6 +101,10 @@ int orc_far_samples(int32_t n, const double* xy, double theta, int64_t cap, int3
                     int64_t* count);
 int orc_bh_learned(int32_t n, const double* xy, double theta, const double* weights,
                    double* F);
+/* The same field for the listed points only (F: nrows x 2), for checks of
+ * large inputs on a sample. */
+int orc_bh_learned_rows(int32_t n, const double* xy, double theta, const double* weights,
+                        const int32_t* rows, int32_t nrows, double* F);
 void orc_mlp_forward(const double* weights, int64_t count, const double* feat, double* out);
 
 /* ---- one Jacobi iteration of the local update (Eq. 2) ----------------

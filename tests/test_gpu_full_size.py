@@ -174,11 +174,27 @@ def _bfs_row(rp, col, u, k):
     return np.array(out, np.int32), ends
 
 
+def _bf16_weights(mlp, w):
+    """The network the GPU evaluates: BF16 matrices (round to nearest even),
+    FP32 biases."""
+    w = np.asarray(w, dtype=np.float32).copy()
+    o = 0
+    for name, shp in mlp.SHAPES:
+        k = int(np.prod(shp))
+        if name.startswith("W"):
+            u = w[o:o + k].view(np.uint32).astype(np.uint64)
+            u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+            w[o:o + k] = u.astype(np.uint32).view(np.float32)
+        o += k
+    return w.astype(np.float64)
+
+
 def test_full_rgg22(orc, mm):
     """The learned-far-field workload's graph (RGG 2^22, mean degree 8, k = 3)
     at full size: sampled k-hop rows, Barnes-Hut at theta = 1 (the learned
-    configuration's tree) and 0.5 (the plain one) over all points, and one
-    finest-level sweep on 512 sampled rows in the default configuration."""
+    configuration's tree) and 0.5 (the plain one) over all points, the learned
+    correction at theta = 1 on 4096 sampled points, and one finest-level
+    sweep on 512 sampled rows in the default configuration."""
     import torch
 
     g = synth.config_graph("rgg22", 1)
@@ -211,6 +227,18 @@ def test_full_rgg22(orc, mm):
             err = float(np.max(np.linalg.norm(F - Fr, axis=1) / np.maximum(nr, nr.mean())))
             print(f"  theta {theta}: max far-field err {err:.3e}", flush=True)
             assert err < 1e-4
+        # learned correction at theta = 1 (a random network: the check is of
+        # the evaluation, not of a trained one) on 4096 sampled points
+        from oracle import mlp
+        w = mlp.init(7, out_scale=0.3).astype(np.float32)
+        Fl = mm.repulsion_learned(ctx, x, 1.0, w).cpu().numpy()
+        lrows = rng.choice(g.n, 4096, replace=False).astype(np.int32)
+        ref = orc.barnes_hut_learned_rows(x.astype(np.float64), 1.0, _bf16_weights(mlp, w), lrows)
+        nr = np.linalg.norm(ref, axis=1)
+        err = float(np.max(np.linalg.norm(Fl[lrows] - ref, axis=1) / np.maximum(nr, nr.mean())))
+        print(f"  learned theta 1: max err {err:.3e}", flush=True)
+        assert err < 2e-3
+        del Fl
         F = mm.repulsion(ctx, x, 0.0, 0.5)["F"]
         xo, _ = mm.sweep(ctx, kh, x, F, 0.37, mode=mm.SWEEP_AUTO)
         kh.free()

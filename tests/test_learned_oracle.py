@@ -153,3 +153,16 @@ def test_learned_field_composition():
     assert np.abs(FL - F).max() < 1e-12 * np.abs(F0).max()
     # samples are recorded in ascending target order
     assert np.all(np.diff(S.u) >= 0)
+
+
+def test_bh_learned_rows_is_the_full_field_at_those_rows(orc):
+    """The sampled variant used for large checks visits the same tree."""
+    from oracle import mlp
+
+    rng = np.random.default_rng(3)
+    x = rng.random((3000, 2)) * 55
+    w = mlp.init(5, out_scale=0.3)
+    rows = rng.choice(3000, 200, replace=False)
+    full = orc.barnes_hut_learned(x, 1.0, w)
+    part = orc.barnes_hut_learned_rows(x, 1.0, w, rows)
+    assert np.array_equal(full[rows], part)
