@@ -205,6 +205,15 @@ __global__ __launch_bounds__(256) void k_ms_step(
   const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = lane_id();
   if (v >= n) return;
+  // every source already reached v: nothing new can arrive (late levels of
+  // low-diameter graphs, where most vertices are done)
+  uint64_t all = ~0ull;
+#pragma unroll
+  for (int w = 0; w < MS_W; ++w) all &= vis[(size_t)v * MS_W + w];
+  if (all == ~0ull) {
+    if (l < MS_W) nx[(size_t)v * MS_W + l] = 0ull;
+    return;
+  }
   uint64_t a[MS_W] = {0ull, 0ull, 0ull, 0ull};
   for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 64) {
     const uint64_t* f = fr + (size_t)col[e] * MS_W;
