@@ -426,6 +426,7 @@ __global__ __launch_bounds__(BS_T, 8) void k_bs_search(int32_t n, int32_t tiles,
     for (int32_t i = threadIdx.x; i < 2 * words; i += BS_T) bs_bm[i] = 0ull;
     const int32_t s0 = 64 * b;
     const int ns = min(64, n - s0);
+    const uint64_t full = ns == 64 ? ~0ull : (1ull << ns) - 1ull;
     if (threadIdx.x < 64) sx[threadIdx.x] = threadIdx.x < ns ? xy[s0 + threadIdx.x] : make_float2(0.f, 0.f);
     if (threadIdx.x < 2) s_any[threadIdx.x] = 0;
 #pragma unroll
@@ -472,11 +473,13 @@ __global__ __launch_bounds__(BS_T, 8) void k_bs_search(int32_t n, int32_t tiles,
               for (int k = 0; k < BS_U; ++k) cu[k] = k < K ? ce[64 * k] : -1;
               const uint64_t vv = vis[v];
               uint64_t a = 0ull;
+              if (vv != full) {  // a vertex every source has reached gains nothing
 #pragma unroll
-              for (int k = 0; k < BS_U; ++k) a |= cu[k] >= 0 ? R[cu[k]] : 0ull;
-              for (int32_t k = BS_U; k < K; ++k) {
-                const int32_t u = ce[64 * k];
-                if (u >= 0) a |= R[u];
+                for (int k = 0; k < BS_U; ++k) a |= cu[k] >= 0 ? R[cu[k]] : 0ull;
+                for (int32_t k = BS_U; k < K; ++k) {
+                  const int32_t u = ce[64 * k];
+                  if (u >= 0) a |= R[u];
+                }
               }
               const uint64_t nw = a & ~vv;
               Wm[v] = nw;
