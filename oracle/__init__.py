@@ -434,8 +434,12 @@ def schedule(alpha0, alpha_decay, alpha_min):
     return out
 
 
-def hierarchy(g0: Level, p: Params):
+def hierarchy(g0: Level, p: Params, trace: list | None = None):
     """Coarsening (Section 3.1).  Returns (levels, clusters, info).
+    trace (optional list) receives one record per contraction attempt: the
+    level index h, f, W and U of the attempt, the contracted size n, whether
+    the 10% rule fired (then also f_next, the f it leaves), and the
+    attempt's rebuild counter.
 
     Reading: |V| in W = min(b^h, |V|/f) is the total node weight; h is the
     index of the level being built (1 for the first contraction).  When the
@@ -460,9 +464,14 @@ def hierarchy(g0: Level, p: Params):
         U = max(float(maxc), W)
         label, moves = lp(G.row_ptr, G.col, U, p.lp_rounds, p.seed, h, G.c, G.w)
         cluster, Gc = contract(G, label)
+        if trace is not None:
+            trace.append({"h": h, "f": f, "W": W, "U": U, "n": Gc.n,
+                          "fired": bool(Gc.n > 0.9 * G.n), "redo": redo})
         if Gc.n > 0.9 * G.n:
             bounded_by_f = (cV / f) < p.b ** h
             f = 0.7 * f
+            if trace is not None:
+                trace[-1]["f_next"] = f
             if bounded_by_f and redo < 10:
                 redo += 1
                 continue

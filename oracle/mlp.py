@@ -4,6 +4,14 @@ h = W3 relu(W2 relu(W1 f + b1) + b2) + b3, W1: 64x8, W2: 64x64, W3: 2x64,
 parameters packed as W1, b1, W2, b2, W3, b3 (row-major, 4866 values).
 Loss of a batch (f_b, y_b): L = 1/(2B) sum_b |h(f_b) - y_b|^2.
 The gradient is the chain rule written out layer by layer.
+
+Training is Adam (Kingma and Ba, "Adam: A Method for Stochastic
+Optimization", ICLR 2015, Algorithm 1) with its default moment decays
+beta1 = 0.9, beta2 = 0.999 and epsilon = 1e-8, bias-corrected, on
+minibatches drawn with replacement: row b of the minibatch of step t is
+draw b of the SplitMix64 stream (seed, t, 64) modulo the sample count (the
+stream state 0 is replaced by 1).  The network is not part of the paper; its
+training is an extension of the method.
 """
 from __future__ import annotations
 
@@ -70,3 +78,56 @@ def loss_grad(w, X, Y):
     g["W1"] = dz1.T @ X
     g["b1"] = dz1.sum(0)
     return L, pack(g)
+
+
+# ------------------------------------------------------------------ Adam
+
+ADAM_BETA1, ADAM_BETA2, ADAM_EPS = 0.9, 0.999, 1e-8
+MINIBATCH_TAG = 64
+
+
+def adam_step(w, g, m, v, t, lr, beta1=ADAM_BETA1, beta2=ADAM_BETA2, eps=ADAM_EPS):
+    """One Adam update at step number t >= 1 (Kingma and Ba 2015, Alg. 1):
+    first and second raw moment estimates decayed by beta1 and beta2, each
+    divided by (1 - beta^t) to remove the bias of their zero start, and the
+    parameters moved by lr * m_hat / (sqrt(v_hat) + eps).
+    Returns new (w, m, v); the inputs are not modified."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * (g * g)
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def minibatch_rows(n_samples: int, batch: int, seed: int, t: int) -> np.ndarray:
+    """Rows of the minibatch of step t: SplitMix64 draws 0..batch-1 of the
+    stream (seed, level t, tag 64), each modulo n_samples."""
+    from . import draws, splitmix64_at
+
+    state = (int(seed) ^ (int(t) << 48) ^ (MINIBATCH_TAG << 32)) & 0xFFFFFFFFFFFFFFFF
+    if state == 0:
+        r = np.array([splitmix64_at(1, b) for b in range(batch)], dtype=np.uint64)
+    else:
+        r = draws(seed, t, MINIBATCH_TAG, 0, batch)
+    return (r % np.uint64(n_samples)).astype(np.int64)
+
+
+def train(w, m, v, X, Y, steps: int, batch: int, lr: float, seed: int, step0: int = 0):
+    """`steps` Adam steps on minibatches of the samples (X, Y), step numbers
+    step0+1 ... step0+steps.  Returns (w, m, v, losses) with the minibatch
+    loss before each step."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, N_IN)
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, N_OUT)
+    w = np.array(w, dtype=np.float64)
+    m = np.array(m, dtype=np.float64)
+    v = np.array(v, dtype=np.float64)
+    losses = []
+    for it in range(steps):
+        t = step0 + it + 1
+        rows = minibatch_rows(X.shape[0], batch, seed, t)
+        L, g = loss_grad(w, X[rows], Y[rows])
+        losses.append(L)
+        w, m, v = adam_step(w, g, m, v, t, lr)
+    return w, m, v, np.array(losses)

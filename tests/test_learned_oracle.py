@@ -166,3 +166,92 @@ def test_bh_learned_rows_is_the_full_field_at_those_rows(orc):
     full = orc.barnes_hut_learned(x, 1.0, w)
     part = orc.barnes_hut_learned_rows(x, 1.0, w, rows)
     assert np.array_equal(full[rows], part)
+
+
+# ------------------------------------------------------------------ Adam
+
+def test_adam_two_steps_hand_worked():
+    """Adam (Kingma and Ba 2015, Alg. 1) by hand, one scalar, lr = 0.1,
+    eps = 0, w0 = 1, gradients 1 then 3.
+    t = 1: m = 0.1, v = 0.001; m_hat = 0.1/(1-0.9) = 1, v_hat = 0.001/(1-0.999)
+    = 1; w1 = 1 - 0.1 * 1/1 = 0.9.
+    t = 2: m = 0.9*0.1 + 0.1*3 = 0.39, v = 0.999*0.001 + 0.001*9 = 0.009999;
+    m_hat = 0.39/(1-0.81) = 39/19, v_hat = 0.009999/(1-0.998001) = 9999/1999;
+    w2 = 0.9 - 0.1 * (39/19) / sqrt(9999/1999) = 0.808221888..."""
+    w, m, v = mlp.adam_step(np.array([1.0]), np.array([1.0]), np.zeros(1), np.zeros(1), 1, 0.1,
+                            eps=0.0)
+    assert abs(w[0] - 0.9) < 1e-15 and abs(m[0] - 0.1) < 1e-15 and abs(v[0] - 0.001) < 1e-15
+    w, m, v = mlp.adam_step(w, np.array([3.0]), m, v, 2, 0.1, eps=0.0)
+    assert abs(m[0] - 0.39) < 1e-15 and abs(v[0] - 0.009999) < 1e-15
+    expect = 0.9 - 0.1 * (39.0 / 19.0) / np.sqrt(9999.0 / 1999.0)
+    assert abs(expect - 0.808221888) < 1e-9
+    assert abs(w[0] - expect) < 1e-14
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient g from zero moments the bias-corrected
+    estimates are exactly g and g^2 at every step (that is what the
+    correction is for), so each step moves every parameter by
+    lr g / (|g| + eps): a wrong correction power or decay fails this."""
+    rng = np.random.default_rng(5)
+    g = rng.normal(0, 1, 50) * 10.0 ** rng.integers(-3, 3, 50)
+    w0 = rng.normal(0, 1, 50)
+    w, m, v = w0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 41):
+        w_prev = w
+        w, m, v = mlp.adam_step(w, g, m, v, t, 1e-3)
+        np.testing.assert_allclose(w_prev - w, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+    np.testing.assert_allclose(w, w0 - 40e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+
+
+def test_adam_is_invariant_to_gradient_scale_and_eps_sits_outside_the_root():
+    """Scaling every gradient by c > 0 leaves the steps unchanged (up to
+    eps); a gradient of 1e-8 at t = 1 moves by lr/2, which holds only with
+    eps added to sqrt(v_hat)."""
+    rng = np.random.default_rng(6)
+    G = rng.normal(0, 1, (6, 30))
+    wa = wb = np.zeros(30)
+    ma = mb = va = vb = np.zeros(30)
+    for t in range(1, 7):
+        wa, ma, va = mlp.adam_step(wa, G[t - 1], ma, va, t, 0.01)
+        wb, mb, vb = mlp.adam_step(wb, 1000.0 * G[t - 1], mb, vb, t, 0.01)
+    np.testing.assert_allclose(wa, wb, rtol=1e-6, atol=1e-12)
+    w, _, _ = mlp.adam_step(np.zeros(1), np.array([1e-8]), np.zeros(1), np.zeros(1), 1, 0.01)
+    assert abs(w[0] + 0.005) < 1e-12
+
+
+def test_minibatch_rows_follow_splitmix64_known_answers():
+    """Step t's rows are draws 0, 1, ... of the SplitMix64 stream
+    seed ^ (t << 48) ^ (64 << 32) modulo the sample count; the stream state
+    1234567 has the published outputs in tests/golden/splitmix64.json."""
+    import json
+    import os
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "splitmix64.json")))
+    outs = [v for v in gold["vectors"] if v["state"] == 1234567][0]["outputs"]
+    for t in (1, 7):
+        seed = 1234567 ^ (t << 48) ^ (64 << 32)
+        for N in (1000, 4099, 2 ** 31 - 1):
+            rows = mlp.minibatch_rows(N, 3, seed, t)
+            assert rows.tolist() == [o % N for o in outs]
+
+
+def test_adam_training_fits_a_teacher_network():
+    """train(): a student from another initialisation fits targets made by a
+    teacher network (the loss falls by more than 20x in 600 steps) and the
+    run is a deterministic function of its inputs."""
+    rng = np.random.default_rng(8)
+    X = rng.normal(0, 0.7, (4000, 8))
+    X[:, 7] = 0
+    teacher = mlp.init(11, out_scale=1.0)
+    Y, _ = mlp.forward(teacher, X)
+    w0 = mlp.init(12, out_scale=0.1)
+    z = np.zeros_like(w0)
+    w, m, v, L = mlp.train(w0, z, z, X, Y, 600, 256, 3e-3, 5)
+    assert L[-20:].mean() < L[:5].mean() / 20
+    w2, _, _, L2 = mlp.train(w0, z, z, X, Y, 600, 256, 3e-3, 5)
+    assert np.array_equal(w, w2) and np.array_equal(L, L2)
+    # resuming at step0 continues the same sequence of steps
+    wa, ma, va, _ = mlp.train(w0, z, z, X, Y, 300, 256, 3e-3, 5)
+    wb, _, _, _ = mlp.train(wa, ma, va, X, Y, 300, 256, 3e-3, 5, step0=300)
+    assert np.array_equal(wb, w)

@@ -159,6 +159,68 @@ def test_bh_tree_geometry(orc):
             assert len(digits) >= 2
 
 
+def test_bh_opening_threshold_hand_worked(orc):
+    """Three points A = (0, 0), B = (0.25, 0), T = (63, 0).  Box side 64 =
+    2^6, so a quantum is 2^-18: A, B, T sit in cells (0, 0), (2^16, 0),
+    (63 * 2^18, 0).  The tight cell of {A, B} is the aligned cell of side
+    2^17 quanta (0.5) at the origin (side 2^16 would split them), centre
+    (0.25, 0.25); T's quantum-cell centre is (63 + 2^-19, 2^-19).  T accepts
+    {A, B} iff side < theta * distance of the two centres, i.e. iff
+    theta > 2^18 / |(2 (63 * 2^18) + 1 - 2^17, 1 - 2^17)| = 0.0079680640...
+    (distances to the centroid (0.125, 0) would put the threshold at
+    0.5/62.875 = 0.0079523).  A and B open everything (they lie in the cell):
+    4 exact pairs.  Accepted: F_T = 2 r(T - (0.125, 0)); opened: the two
+    exact terms."""
+    x = np.array([[0.0, 0.0], [0.25, 0.0], [63.0, 0.0]])
+    th = 2.0 ** 18 / math.hypot(2 * 63 * 2 ** 18 + 1 - 2 ** 17, 1 - 2 ** 17)
+    assert abs(th - 0.0079680640) < 1e-10
+    for t, acc in [(th * (1 + 1e-7), 1), (th * (1 - 1e-7), 0), (0.5 / 62.875 * (1 + 5e-4), 0)]:
+        bh = orc.barnes_hut(x, t)
+        assert (bh.accepted, bh.leaf_pairs) == (acc, 6 - 2 * acc)
+        assert bh.nodes[1].tolist()[:3] == [7, 0, 2]  # depth 24 - 17, first, count
+        if acc:
+            assert abs(bh.F[2, 0] - 2 / 62.875) < 1e-15 and bh.F[2, 1] == 0.0
+        else:
+            assert abs(bh.F[2, 0] - (1 / 63.0 + 1 / 62.75)) < 1e-15
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_bh_error_is_the_sum_of_cell_remainders(orc, theta):
+    """Every target of a clustered instance: the exact field minus the
+    Barnes-Hut field equals the sum over the cells the target accepts of
+    (exact cell sum - m r(x_u - centroid)), computed here from the cell's
+    points, so accepted cells act exactly through their centroids and all
+    other points are summed exactly.  Each such remainder obeys the
+    multipole bound: with w = x_u - c, delta_v = x_v - c in complex form,
+    1/conj(w - delta) - 1/conj(w) - conj(delta)/conj(w)^2 =
+    conj(delta)^2 / (conj(w)^2 conj(w - delta)), and the dipole terms cancel
+    (sum of delta_v = 0), so |R| <= sum_v |delta_v|^2 / (|w|^2 |x_u - x_v|)."""
+    x = _points(700, 4)
+    bh = orc.barnes_hut(x, theta)
+    S = orc.far_samples(x, theta)
+    assert S.u.size == bh.accepted > 0
+    F = orc.farfield_exact(x)
+    acc = np.zeros_like(F)
+    worst = 0.0
+    for u, nd in zip(S.u, S.node):
+        depth, first, count, leaf, _ = bh.nodes[nd]
+        pts = x[bh.order[first:first + count]]
+        assert not leaf or count > 1
+        c = pts.mean(0)
+        d = x[u] - pts
+        w = x[u] - c
+        R = (d / (d ** 2).sum(1)[:, None]).sum(0) - count * w / (w @ w)
+        acc[u] += R
+        delta2 = ((pts - c) ** 2).sum(1)
+        bound = (delta2 / ((w @ w) * np.sqrt((d ** 2).sum(1)))).sum()
+        # (R is a difference of sums of size count/|w|: allow its rounding)
+        assert np.hypot(*R) <= bound * (1 + 1e-9) + 1e-13 * count / np.sqrt(w @ w)
+        worst = max(worst, np.hypot(*R) / bound)
+    scale = np.maximum(np.linalg.norm(F, axis=1), np.linalg.norm(F, axis=1).mean())
+    assert np.max(np.linalg.norm(F - bh.F - acc, axis=1) / scale) < 1e-11
+    assert worst > 0.05  # the bound is not vacuous
+
+
 # ------------------------------------------------------------- Eq. 2 (P1-P6)
 
 def test_sweep_subtraction_equals_direct_sum(orc):
@@ -417,3 +479,93 @@ def test_thread_count_independence(orc, tmp_path):
         subprocess.run([sys.executable, "-c", code, f], check=True, env=env)
         outs.append(np.load(f))
     assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------- hierarchy driver (P8)
+
+def _attempts(trace):
+    return [(t["h"], round(t["f"], 9), round(t["W"], 9), round(t["U"], 9), t["n"], t["fired"],
+             t["redo"], round(t.get("f_next", t["f"]), 9)) for t in trace]
+
+
+def test_hierarchy_rules_on_a_matching(orc):
+    """Ten disjoint edges (0-1, 2-3, ..., 18-19), unit weights, |V| = 20,
+    b = 2, f = 20, seed 1 (Section 3.1).  Worked by hand:
+    h = 1 (first contraction): W = min(2, 20/20) = 1, U = max(1, W) = 1: no
+    vertex fits next to another (1 + 1 > 1), n stays 20 > 0.9 * 20, the rule
+    fires; W was bounded by |V|/f (1 < 2), so f := 14 and the level is
+    rebuilt: W = min(2, 20/14) = 1.43 = U, still nothing fits, f := 9.8,
+    rebuilt: W = min(2, 20/9.8 = 2.04) = 2 = U.  Now a pair merges in the
+    first round its endpoints draw different colours (the first active
+    endpoint joins the other's label; equal colours swap the labels); with
+    seed 1 every pair has differing colours by round 3 (bits below), so
+    n = 10 <= 18: level 1 is kept (two rebuilds).
+    h = 2: ten isolated vertices of weight 2.  W = min(4, 20/9.8) = 2.04 (|V|
+    is the total weight 20, not the 10 vertices), U = max(2, W) = 2.04; no
+    edges, n stays 10, fires, bounded (2.04 < 4): f := 6.86, rebuild
+    (W = U = 20/6.86 = 2.92), fires, bounded: f := 4.802, rebuild:
+    W = min(4, 4.16) = 4 = U, fires, not bounded by |V|/f (4.16 >= 4): f :=
+    3.3614 without a rebuild; no progress, coarsening stops."""
+    n = 20
+    g = synth.csr_from_edges(n, np.arange(0, n, 2), np.arange(1, n, 2))
+    bits = [[int(b) & 1 for b in orc.draws(1, 1, 16 + r, 0, n)] for r in range(4)]
+    first_diff = [min(r for r in range(4) if bits[r][2 * i] != bits[r][2 * i + 1])
+                  for i in range(10)]
+    assert first_diff == [0, 0, 3, 0, 3, 1, 0, 2, 0, 0]
+    tr = []
+    levels, clusters, info = orc.hierarchy(orc.Level(g.row_ptr, g.col), orc.Params(seed=1), tr)
+    assert [lv.n for lv in levels] == [20, 10]
+    assert clusters[0].tolist() == [i // 2 for i in range(n)]
+    assert levels[1].c.tolist() == [2] * 10 and levels[1].col.size == 0
+    assert _attempts(tr) == [
+        (1, 20.0, 1.0, 1.0, 20, True, 0, 14.0),
+        (1, 14.0, round(20 / 14, 9), round(20 / 14, 9), 20, True, 1, 9.8),
+        (1, 9.8, 2.0, 2.0, 10, False, 2, 9.8),
+        (2, 9.8, round(20 / 9.8, 9), round(20 / 9.8, 9), 10, True, 0, 6.86),
+        (2, 6.86, round(20 / 6.86, 9), round(20 / 6.86, 9), 10, True, 1, 4.802),
+        (2, 4.802, 4.0, 4.0, 10, True, 2, 3.3614)]
+    assert info == [{"h": 1, "U": 2.0, "n": 10, "lp_rounds": 5, "redo": 2}]
+
+
+def test_hierarchy_rule_fires_without_rebuild_and_keeps_the_level(orc):
+    """Star with centre 0 and 29 leaves, |V| = 30, seed 1, stop at <= 29
+    vertices.  h = 1: W = min(2, 30/20 = 1.5) = U: nothing fits, fires,
+    bounded (1.5 < 2): f := 14, rebuild: W = min(2, 30/14 = 2.14) = 2 = U.
+    Round 0, colour 0: the centre (bit 1) waits, the active leaves all
+    propose the centre's label and admission in ascending id takes leaf 1
+    only (1 + 1 <= 2); colour 1: the centre's best label is its own (tie);
+    round 1 moves nothing.  n = 29 > 0.9 * 30: fires, but W was not bounded
+    by |V|/f (2.14 >= 2), so f := 9.8 with no rebuild, and the level is kept
+    (progress); 29 vertices end the coarsening."""
+    g = synth.star(29)
+    b0 = [int(b) & 1 for b in orc.draws(1, 1, 16, 0, 30)]
+    assert b0[0] == 1 and b0[1] == 0
+    tr = []
+    levels, clusters, info = orc.hierarchy(orc.Level(g.row_ptr, g.col),
+                                           orc.Params(seed=1, coarsest_n=29), tr)
+    assert [lv.n for lv in levels] == [30, 29]
+    assert clusters[0].tolist() == [0, 0] + list(range(1, 29))
+    assert levels[1].c.tolist() == [2] + [1] * 28
+    assert _attempts(tr) == [(1, 20.0, 1.5, 1.5, 30, True, 0, 14.0),
+                             (1, 14.0, 2.0, 2.0, 29, True, 1, 9.8)]
+    assert info == [{"h": 1, "U": 2.0, "n": 29, "lp_rounds": 2, "redo": 1}]
+
+
+def test_hierarchy_rebuild_limit(orc):
+    """Five isolated vertices, b = 1e6 so W = |V|/f always: every attempt
+    fires and is rebuilt with f := 0.7 f (U = max(1, W) = 1 while W < 1)
+    until the tenth rebuild; the eleventh attempt fires without a rebuild
+    and, with no progress, ends the coarsening at the input graph."""
+    rp = np.zeros(6, np.int32)
+    tr = []
+    levels, _, info = orc.hierarchy(orc.Level(rp, np.zeros(0, np.int32)),
+                                    orc.Params(seed=1, b=1e6), tr)
+    assert [lv.n for lv in levels] == [5] and info == []
+    f = 20.0
+    exp = []
+    for r in range(11):
+        W = 5 / f
+        exp.append((1, round(f, 9), round(W, 9), round(max(1.0, W), 9), 5, True, r,
+                    round(0.7 * f, 9)))
+        f *= 0.7
+    assert _attempts(tr) == exp
