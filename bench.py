@@ -269,6 +269,56 @@ def dynamic_comparison(args):
     ctx.close()
 
 
+def caps_comparison(args):
+    """Time against stress: the RGG 2^17 (k = 3) and R-MAT 2^20 (k = 2)
+    layouts with the cap on the iterations at alpha_min set to 25, 50, 100 and
+    200 (the paper stops at a relative change below 1e-4 and names no cap).
+    Per cap: layout time, maxent-stress M_S, full stress F at the optimal
+    scale, levels stopped by the cap.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1506_04383_amd as mm
+    import synth
+
+    ctx = mm.Context(0)
+    if args.tune_db and os.path.exists(args.tune_db):
+        recs = json.load(open(args.tune_db))["records"]
+        ctx.tune_import(np.array(recs, dtype=np.int64).reshape(-1, mm.TUNE_FIELDS))
+    rows = []
+    for wname in ("rgg17", "rmat20"):
+        wl = WORKLOADS[wname]
+        g = synth.config_graph(wl["graph"], args.seed)
+        dg = ctx.graph(g.row_ptr, g.col)
+        kh = mm.khop_build(ctx, dg, wl["k"])
+        for cap in (25, 50, 100, 200):
+            p = mm.Params(k=wl["k"], theta=wl["theta"], alpha_decay=wl["alpha_decay"],
+                          coarsest_n=wl["coarsest_n"], seed=args.seed, validate=0,
+                          autotune=1, exact_below=args.exact_below, max_final_iters=cap)
+            mm.layout(ctx, dg, p)  # warm-up (tunes levels the table lacks)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xy, st = mm.layout(ctx, dg, p)
+            torch.cuda.synchronize()
+            T = time.perf_counter() - t0
+            M = mm.objective(ctx, kh, xy, p.alpha_min, p.q)["M"]
+            F = mm.full_stress(ctx, dg, xy)["F"]
+            caps = [l["cap_hit"] for l in st["per_level"]]
+            rows.append({"workload": wname, "cap": cap, "time_s": T, "M_S": M, "F": F,
+                         "levels_stopped_by_cap": int(sum(caps)), "levels": len(caps),
+                         "vertex_updates": st["vertex_updates"]})
+            print(f"[caps] {wname} cap {cap}: {T:.2f} s, M_S {M:.6e}, F {F:.6e}, "
+                  f"{sum(caps)}/{len(caps)} levels at the cap", file=sys.stderr, flush=True)
+        kh.free()
+    print(json.dumps({"metric": "time-to-layout and final stress vs the cap on final iterations",
+                      "unit": "s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "RGG 2^17 (k=3) and R-MAT 2^20 (k=2), theta=0.5, "
+                                 "decay 0.5, hierarchy to <=100 vertices, exact far field "
+                                 f"at <= {args.exact_below} vertices", "seed": args.seed},
+                      "rows": rows}))
+    ctx.close()
+
+
 def learned_comparison(args):
     """Learned far field vs plain Barnes-Hut on RGG 2^22 (k = 3): the network is
     trained on the GPU on exact residuals of cells accepted at theta = 1 in
@@ -295,7 +345,7 @@ def learned_comparison(args):
     feat, tgt = torch.cat(feats), torch.cat(tgts)
     torch.cuda.synchronize()
     t_samples = time.perf_counter() - t0
-    w = mm.mlp_init(11, out_scale=0.1)
+    w = mm.mlp_init(ctx, 11, out_scale=0.1)
     adam = torch.zeros(2 * mm.MLP_PARAMS, dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
     losses = mm.mlp_train(ctx, feat, tgt, w, adam, args.train_steps, 4096, 2e-3, 5)
@@ -395,29 +445,57 @@ def measured_traffic(workload: str, tile_bits: int, group: int, blocks: int):
     return int(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(g, k, x, F, alpha, seconds=15.0, seed=0):
+def host_cpu() -> dict:
+    """Model, sockets and logical CPUs of the host (lscpu), as far as readable."""
+    import subprocess
+
+    info = {"model": None, "sockets": None, "logical_cpus": os.cpu_count()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "Model name":
+                info["model"] = val
+            elif key == "Socket(s)":
+                info["sockets"] = int(val) if val.isdigit() else val
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(g, k, x, F, alpha, seconds=15.0, seed=0, seconds_1t=6.0):
     """The FP64 oracle's update of sampled rows (each row's stress set found by
-    BFS, then Eq. 2), timed on the host cores."""
+    BFS, then Eq. 2), timed on the host cores: all threads, then one thread."""
     import numpy as np
 
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rng = np.random.default_rng(seed)
-    rows = rng.choice(g.n, size=min(g.n, 256), replace=False).astype(np.int32)
-    t0 = time.perf_counter()
-    oracle.sweep_rows(g.row_ptr, g.col, k, x, F, alpha, rows)
-    dt = time.perf_counter() - t0
-    target = max(256, min(g.n, int(256 * seconds / max(dt, 1e-3))))
-    rows = rng.choice(g.n, size=target, replace=False).astype(np.int32)
-    t0 = time.perf_counter()
-    _, sizes = oracle.sweep_rows(g.row_ptr, g.col, k, x, F, alpha, rows)
-    dt = time.perf_counter() - t0
-    return {"value": rows.size / dt, "unit": "vertex-updates/s", "cores": threads,
+
+    def timed(nrows):
+        rows = rng.choice(g.n, size=nrows, replace=False).astype(np.int32)
+        t0 = time.perf_counter()
+        _, sizes = oracle.sweep_rows(g.row_ptr, g.col, k, x, F, alpha, rows)
+        return rows.size, time.perf_counter() - t0, sizes
+
+    prev = oracle.set_threads(threads)
+    n1, dt, _ = timed(min(g.n, 256))
+    target = max(256, min(g.n, int(n1 * seconds / max(dt, 1e-3))))
+    nrows, dt, sizes = timed(target)
+    oracle.set_threads(1)
+    n1, dt1, _ = timed(min(g.n, 64))
+    target1 = max(64, min(g.n, int(n1 * seconds_1t / max(dt1, 1e-3))))
+    nrows1, dt1, sizes1 = timed(target1)
+    oracle.set_threads(prev)
+    return {"value": nrows / dt, "unit": "vertex-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{rows.size} random rows of the finest level (mean |S| "
+            "sample": f"{nrows} random rows of the finest level (mean |S| "
                       f"{float(sizes.mean()):.0f}), FP64 update of Eq. 2 with each row's "
-                      f"k-hop set found by BFS, far field given, {dt:.1f} s"}
+                      f"k-hop set found by BFS, far field given, {dt:.1f} s; the same "
+                      f"on 1 thread: {nrows1} rows in {dt1:.1f} s",
+            "value_1_thread": nrows1 / dt1, "host": host_cpu()}
 
 
 def main():
@@ -449,11 +527,12 @@ def main():
     ap.add_argument("--save-tune-db", default="",
                     help="write the context's autotuner choices here after the run")
     ap.add_argument("--mode", default="layout",
-                    choices=["layout", "learned", "batch", "snapshots", "dynamic"],
+                    choices=["layout", "learned", "batch", "snapshots", "dynamic", "caps"],
                     help="layout: the layout benchmark; learned: learned far field vs plain "
                          "Barnes-Hut on RGG 2^22; batch: 4096 graphs batched vs one at a "
                          "time; snapshots: warm-started dynamic snapshots vs scratch; dynamic: "
-                         "the paper's update protocol (x, D, h grid) vs scratch")
+                         "the paper's update protocol (x, D, h grid) vs scratch; caps: time "
+                         "and stress against the cap on the final iterations")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-sample", type=int, default=96)
     ap.add_argument("--snapshots", type=int, default=64)
@@ -492,6 +571,9 @@ def main():
         return
     if args.mode == "dynamic":
         dynamic_comparison(args)
+        return
+    if args.mode == "caps":
+        caps_comparison(args)
         return
 
     import paper_1506_04383_amd as mm
@@ -543,6 +625,8 @@ def main():
     far_avg_ms = L0["far_ms"] / max(L0["iters"], 1)
     total_sweep_ms = sum(l["sweep_ms"] for l in st["per_level"])
     total_far_ms = sum(l["far_ms"] for l in st["per_level"])
+    traffic = measured_traffic(args.workload, L0["tile_bits"], L0["group"], L0["blocks"])
+    caps = [l["cap_hit"] for l in st["per_level"]]
 
     out = {
         "metric": METRIC,
@@ -565,15 +649,27 @@ def main():
                    "levels": st["levels"]},
         "time_to_layout_s": T / args.steps,
         "finest_sweep_updates_per_s": n0 / (sweep_avg_ms * 1e-3),
-        "finest_iteration_updates_per_s": n0 / ((sweep_avg_ms + far_avg_ms) * 1e-3),
+        "finest_iteration_updates_per_s": n0 / (L0["wall_ms"] / max(L0["iters"], 1) * 1e-3),
         "finest_iters": L0["iters"],
         "vertex_updates_per_step": updates // args.steps,
-        "time_split_ms": {"sweep": total_sweep_ms, "far_field": total_far_ms,
-                          "khop": st["t_khop_ms"], "coarsen": st["t_coarsen_ms"],
-                          "other": st["t_other_ms"]},
-        "per_level": [[l["n"], l["khop_entries"], l["iters"], round(l["sweep_ms"], 1),
-                       round(l["far_ms"], 1), l["tile_bits"], l["group"], l["blocks"]]
-                      for l in st["per_level"]],
+        # iterations: elapsed time of all Jacobi iterations; sweep and
+        # far_field are the kernel times inside them, which overlap (the far
+        # field runs on a second stream beside the sweep's stress sums)
+        "time_split_ms": {"iterations": st["t_iterate_ms"], "sweep": total_sweep_ms,
+                          "far_field": total_far_ms, "khop": st["t_khop_ms"],
+                          "coarsen": st["t_coarsen_ms"], "other": st["t_other_ms"]},
+        "per_level_fields": ["n", "stress_entries", "iters", "final_iters", "cap_hit",
+                             "final_rel_change", "iterations_ms", "sweep_ms", "far_ms",
+                             "tile_bits", "lanes", "blocks"],
+        "per_level": [[l["n"], l["khop_entries"], l["iters"], l["final_iters"], l["cap_hit"],
+                       float(f"{l['delta']:.3e}"), round(l["wall_ms"], 1),
+                       round(l["sweep_ms"], 1), round(l["far_ms"], 1), l["tile_bits"],
+                       l["group"], l["blocks"]] for l in st["per_level"]],
+        # stopping rule at alpha_min: relative change < eps_final, or the cap
+        "convergence": {"eps_final": p.eps_final, "max_final_iters": p.max_final_iters,
+                        "levels_stopped_by_cap": int(sum(caps)), "levels": len(caps),
+                        "finest_final_rel_change": L0["delta"],
+                        "finest_stopped_by_cap": bool(L0["cap_hit"])},
         "autotune": {"enabled": args.autotune, "tuning_ms_in_timed_step": st["t_tune_ms"],
                      "records_loaded": tune_loaded},
         "roofline": {"bound": "hbm",
@@ -583,9 +679,16 @@ def main():
                                + " (finest-level sweep step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, L0["tile_bits"], L0["group"],
-                                                 L0["blocks"]),
-                     "bytes_per_launch": bytes0, "avg_ms": sweep_avg_ms},
+                     "traffic": traffic,
+                     "bytes_per_launch": bytes0, "avg_ms": sweep_avg_ms,
+                     # achieved/frac count the algorithmic bytes (4 B per stress-set
+                     # id); the kernel reads 16-bit tile-major ids, so the bytes HBM
+                     # actually moves (traffic, from the counters) are fewer
+                     "measured_GBps": (traffic / (sweep_avg_ms * 1e-3) / 1e9
+                                       if traffic else None),
+                     "measured_frac": (traffic / (sweep_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                       if traffic else None),
+                     "limiter": "vector-instruction issue (SQ counters)"},
     }
     if not args.no_objective:
         t1 = time.perf_counter()

@@ -110,6 +110,11 @@ typedef struct {
   int32_t level_group[MM_MAX_LEVELS];    /* lanes per chunk (tiled) or per row (row kernel) */
   double t_tune_ms;                      /* time spent timing candidates (autotune) */
   int32_t level_blocks[MM_MAX_LEVELS];   /* tiled sweep: 16-byte entry blocks per lane and step */
+  /* The far field runs on a second stream, concurrently with the part of the
+   * sweep that does not read it, so the far-field and sweep times above
+   * overlap; these are the elapsed times of the iterations themselves. */
+  double t_iterate_ms;                   /* all iterations of all levels */
+  double level_wall_ms[MM_MAX_LEVELS];   /* iterations of the level */
 } mm_stats;
 
 mm_status mm_params_default(mm_params* p);
@@ -188,7 +193,8 @@ mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32
  * sets above: row offsets off[n+1] (off[0] = 0, non-decreasing, total =
  * off[n]); hend[u*k + h-1] = entries of row u with d_uv <= h, for integer
  * distances h in 1..k (k in [1, 8]); nbr[total] ids, strictly increasing
- * inside each distance group.  S is a set of unordered pairs: an entry v at
+ * inside each distance group; no row is empty (Eq. 2 divides by rho_u, the
+ * sum of its weights).  S is a set of unordered pairs: an entry v at
  * distance h in row u needs u at distance h in row v.  No id repeats in a
  * row, none equals its row, all lie in [0, n).  That S contains E is the
  * caller's model choice and is not checked (no graph is passed).
@@ -261,6 +267,12 @@ mm_status mm_far_samples(mm_context* ctx, int32_t n, const float* xy, double the
                          int32_t* u_out, int32_t* node_out, float* feat, float* target,
                          float* coef, int64_t* count);
 
+/* Initial weights for mm_mlp_train: W1 ~ N(0, 2/8) and W2 ~ N(0, 2/64)
+ * (He), W3 ~ N(0, (out_scale/8)^2), zero biases; normal draws by the
+ * Box-Muller transform of SplitMix64 draws 2p and 2p+1 of stream (seed, level
+ * 0, tag 65) for parameter p.  weights: MM_MLP_PARAMS floats (device). */
+mm_status mm_mlp_init(mm_context* ctx, uint64_t seed, double out_scale, float* weights);
+
 /* h = MLP(feat) for count rows (feat count*8, out count*2). */
 mm_status mm_mlp_forward(mm_context* ctx, int64_t count, const float* feat, const float* weights,
                          float* out);
@@ -327,7 +339,12 @@ mm_status mm_coarse_export(mm_context* ctx, const mm_coarse* cg, int32_t* row_pt
                            int32_t* node_w, int32_t* edge_w, int32_t mem);
 void mm_coarse_free(mm_coarse* cg);
 
-/* Initial layout of the coarsest graph: uniform [0,1)^2 from the seed. */
+/* Initial layout of the coarsest graph (replaces the placement of Section
+ * 3.1, "Initial Layout", whose coarsest graph has two vertices at their
+ * optimal distance): x_v uniform in [0,1)^2, coordinate j of vertex v from
+ * the top 24 bits of SplitMix64 draw 2v+j of stream (seed, level, tag 1), so
+ * every value is exact in FP32.  mm_layout applies the two-vertex optimum
+ * itself when the coarsest graph has exactly two vertices.  xy: n*2 device. */
 mm_status mm_init_layout(mm_context* ctx, int32_t n, uint64_t seed, int32_t level, float* xy);
 
 /* Prolongation (Section 3.2): fine v placed uniformly in angle and radius
@@ -336,10 +353,16 @@ mm_status mm_prolong(mm_context* ctx, int32_t n_fine, const int32_t* cluster,
                      const int32_t* coarse_w, const float* coarse_xy, uint64_t seed,
                      int32_t level, float* fine_xy);
 
-/* Maxent-stress parts over S (Eq. 1): out (host, 3) = {stress over S,
- * entropy sum over pairs not in S, coincident pairs}; M = out[0] - alpha*out[1]. */
+/* Maxent-stress of Eq. 1 over the stress set S of kh at entropy weight
+ * alpha: out (host, 4) = {M_S = stress - alpha * entropy, stress = sum over
+ * unordered pairs of S of w (|x_u - x_v| - d_uv)^2, entropy = sum over the
+ * other pairs u < v of ln |x_u - x_v| (q = 0; -|x_u - x_v|^-q / q otherwise),
+ * coincident pairs (distance 0, left out of the entropy sum)}.  Target
+ * distances as in mm_sweep (level, node_w, scale).  The paper's metric M_E is
+ * the same call on the k = 1 sets (S = E); the full stress at the optimal
+ * scale s* (Section 4, "Methodology") is mm_full_stress.  Sums in FP64. */
 mm_status mm_objective(mm_context* ctx, const mm_khop* kh, int32_t level, const int32_t* node_w,
-                       double scale, const float* xy, double q, double* out);
+                       double scale, const float* xy, double alpha, double q, double* out);
 
 /* Full stress over all connected pairs with hop distances (Section 4):
  * out (host, 3) = {F(x), s*, F(s* x)}; the graph in device memory.  Hop

@@ -44,6 +44,8 @@ def lib():
         u64p = np.ctypeslib.ndpointer(np.uint64, flags="C")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
         vp = C.c_void_p
+        L.orc_set_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_splitmix64_at.restype = C.c_uint64
         L.orc_splitmix64_at.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_draws.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_int64, u64p]
@@ -90,6 +92,12 @@ def _i32(a):
 
 
 # ------------------------------------------------------------------ primitives
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the previous
+    maximum (results do not depend on it)."""
+    return int(lib().orc_set_threads(int(n)))
+
 
 def splitmix64_at(state: int, i: int) -> int:
     return int(lib().orc_splitmix64_at(state, i))

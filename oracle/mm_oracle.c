@@ -20,6 +20,12 @@ static uint64_t sm_mix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+int orc_set_threads(int n) {
+    const int prev = omp_get_max_threads();
+    if (n >= 1) omp_set_num_threads(n);
+    return prev;
+}
+
 uint64_t orc_splitmix64_at(uint64_t state, uint64_t i) {
     return sm_mix(state + (i + 1) * 0x9E3779B97F4A7C15ULL);
 }

@@ -32,6 +32,11 @@ uint64_t orc_stream(uint64_t seed, uint32_t level, uint32_t tag);
 void orc_draws(uint64_t seed, uint32_t level, uint32_t tag, uint64_t i0,
                int64_t count, uint64_t* out);
 
+/* ---- execution ----------------------------------------------------------
+ * Threads of the oracle's OpenMP loops from now on (n >= 1); returns the
+ * previous maximum.  Results do not depend on it (fixed-order sums). */
+int orc_set_threads(int n);
+
 /* ---- input validation (Preliminaries: undirected simple graph, c, w) --
  * 0 ok, 1 n < 2, 2 bad row_ptr, 3 column out of range, 4 self-loop,
  * 5 row not strictly ascending (duplicate), 6 asymmetric edge or weight,

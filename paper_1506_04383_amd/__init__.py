@@ -62,7 +62,8 @@ class MMStats(C.Structure):
                 ("t_other_ms", C.c_double), ("vertex_updates", C.c_int64),
                 ("finest_updates", C.c_int64), ("level_tile_bits", C.c_int32 * MAX_LEVELS),
                 ("level_group", C.c_int32 * MAX_LEVELS), ("t_tune_ms", C.c_double),
-                ("level_blocks", C.c_int32 * MAX_LEVELS)]
+                ("level_blocks", C.c_int32 * MAX_LEVELS), ("t_iterate_ms", C.c_double),
+                ("level_wall_ms", C.c_double * MAX_LEVELS)]
 
     def to_dict(self) -> dict:
         L = self.levels
@@ -75,13 +76,13 @@ class MMStats(C.Structure):
                  "delta": self.level_delta[i], "sweep_ms": self.level_sweep_ms[i],
                  "far_ms": self.level_far_ms[i], "khop_ms": self.level_khop_ms[i],
                  "tile_bits": self.level_tile_bits[i], "group": self.level_group[i],
-                 "blocks": self.level_blocks[i]}
+                 "blocks": self.level_blocks[i], "wall_ms": self.level_wall_ms[i]}
                 for i in range(L)],
             "t_total_ms": self.t_total_ms, "t_coarsen_ms": self.t_coarsen_ms,
             "t_khop_ms": self.t_khop_ms, "t_farfield_ms": self.t_farfield_ms,
             "t_sweep_ms": self.t_sweep_ms, "t_other_ms": self.t_other_ms,
             "vertex_updates": self.vertex_updates, "finest_updates": self.finest_updates,
-            "t_tune_ms": self.t_tune_ms,
+            "t_tune_ms": self.t_tune_ms, "t_iterate_ms": self.t_iterate_ms,
         }
 
 
@@ -93,7 +94,8 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_prolong", "mm_objective", "mm_full_stress", "mm_repulsion_learned",
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
            "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg",
-           "mm_repulsion_cluster", "mm_full_stress_ex", "mm_khop_validate", "mm_khop_import"]
+           "mm_repulsion_cluster", "mm_full_stress_ex", "mm_khop_validate", "mm_khop_import",
+           "mm_mlp_init"]
 
 TUNE_FIELDS = 7  # coarse?, n, sum |S|, k, tile bits, lanes, blocks per step
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
@@ -132,7 +134,8 @@ def lib():
         "mm_coarse_export": [vp, vp, vp, vp, vp, vp, i32],
         "mm_init_layout": [vp, i32, u64, i32, vp],
         "mm_prolong": [vp, i32, vp, vp, vp, u64, i32, vp],
-        "mm_objective": [vp, vp, i32, vp, f64, vp, f64, vp],
+        "mm_objective": [vp, vp, i32, vp, f64, vp, f64, f64, vp],
+        "mm_mlp_init": [vp, u64, f64, vp],
         "mm_full_stress": [vp, P(MMGraph), vp, vp],
         "mm_full_stress_ex": [vp, P(MMGraph), vp, i32, vp],
         "mm_repulsion_learned": [vp, i32, vp, f64, vp, vp],
@@ -465,16 +468,14 @@ def repulsion_cluster(ctx: Context, xy, cluster1, n1: int, cluster_h, nh: int, n
     return F
 
 
-def mlp_init(seed: int, out_scale: float = 0.1, device: str = "cuda"):
-    """Initial network weights (float32 device tensor of MLP_PARAMS): He-normal
-    hidden layers, output layer scaled by out_scale, zero biases."""
-    import torch
-
-    rng = np.random.default_rng(seed)
-    parts = [rng.normal(0, np.sqrt(2.0 / 8), 64 * 8), np.zeros(64),
-             rng.normal(0, np.sqrt(2.0 / 64), 64 * 64), np.zeros(64),
-             rng.normal(0, out_scale / 8.0, 2 * 64), np.zeros(2)]
-    return torch.as_tensor(np.concatenate(parts).astype(np.float32), device=device)
+def mlp_init(ctx: Context, seed: int, out_scale: float = 0.1):
+    """Initial network weights (float32 device tensor of MLP_PARAMS) from
+    mm_mlp_init: He-normal hidden layers, output layer scaled by out_scale,
+    zero biases."""
+    t = ctx.torch
+    w = t.empty(MLP_PARAMS, dtype=t.float32, device=f"cuda:{ctx.device}")
+    _check(lib().mm_mlp_init(ctx.h, int(seed), float(out_scale), _ptr(w)))
+    return w
 
 
 def repulsion_learned(ctx: Context, xy, theta: float, weights):
@@ -615,11 +616,10 @@ def objective(ctx: Context, kh: KHop, xy, alpha: float, q: float = 0.0, level: i
     t = ctx.torch
     xy = ctx._dev(xy, t.float32)
     nw = None if node_w is None else ctx._dev(node_w, t.int32)
-    out = np.zeros(3)
-    _check(lib().mm_objective(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), q,
+    out = np.zeros(4)
+    _check(lib().mm_objective(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), alpha, q,
                               out.ctypes.data_as(C.c_void_p)))
-    return {"stress": out[0], "ent": out[1], "coincident": int(out[2]),
-            "M": out[0] - alpha * out[1]}
+    return {"M": out[0], "stress": out[1], "ent": out[2], "coincident": int(out[3])}
 
 
 def full_stress(ctx: Context, g: DeviceGraph, xy, method: int = 0) -> dict:

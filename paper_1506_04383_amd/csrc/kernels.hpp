@@ -149,6 +149,16 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
                        const float* rho, const float* xy, const float* F, double alpha, double q,
                        float* xy_out, double* delta2_dev, hipStream_t s,
                        const float* alpha_dev = nullptr, int32_t group = 0, int32_t nb = 0);
+// The two halves of sweep_tiled: the stress sums of every chunk (reads xy
+// only, into the set's partial slots), then the combine of each row with the
+// far field F (x' and the relative-change sums).  Only the second needs F, so
+// the far field of the same iteration may run concurrently with the first.
+hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
+                               const float* xy, double alpha, double q, hipStream_t s,
+                               const float* alpha_dev = nullptr, int32_t group = 0, int32_t nb = 0);
+hipError_t sweep_tiled_combine(const TiledSet& ts, const float* rho, const float* xy,
+                               const float* F, double alpha, float* xy_out, double* delta2_dev,
+                               hipStream_t s, const float* alpha_dev = nullptr);
 // lanes per chunk (4, 8, 16) the heuristic picks; group = 0 above means this
 inline int32_t tiled_group(const TiledSet& ts) {
   return ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;
@@ -213,6 +223,10 @@ hipError_t mlp_forward(int64_t count, const float* feat, const float* wts, float
                        hipStream_t s);
 hipError_t mlp_grad(int64_t count, const float* feat, const float* tgt, const float* wts,
                     float* grad, float* loss_dev, hipStream_t s);
+// Initial weights: W1 ~ N(0, 2/8), W2 ~ N(0, 2/64) (He), W3 ~ N(0,
+// (out_scale/8)^2), zero biases; normal draws by Box-Muller from SplitMix64
+// stream (seed, level 0, tag 65), draws 2p and 2p+1 for parameter p.
+hipError_t mlp_init(uint64_t seed, double out_scale, float* wts, hipStream_t s);
 hipError_t mlp_train(int64_t N, const float* feat, const float* tgt, float* wts, float* adam,
                      int32_t steps, int32_t batch, double lr, uint64_t seed, int32_t step0,
                      float* losses, hipStream_t s);

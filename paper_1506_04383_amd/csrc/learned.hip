@@ -721,9 +721,12 @@ __global__ __launch_bounds__(64 * MW) void k_mlp_grad(
 
 // Sums the per-wave partials in wave order; optionally applies one Adam step
 // (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) to the FP32 weights.
+// The step is evaluated in FP64 (0.999 has no FP32 value: 0.999f would make
+// the second moment's weight 1 - beta2 off by 1.3e-5 relative) and the
+// moments and weights are stored in FP32.
 __global__ void k_mlp_reduce(const float* __restrict__ part, int32_t nw, float* __restrict__ grad,
                              float* __restrict__ loss_out, float* __restrict__ w,
-                             float* __restrict__ am, float* __restrict__ av, int32_t t, float lr,
+                             float* __restrict__ am, float* __restrict__ av, int32_t t, double lr,
                              float invB) {
   const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > NPARAM) return;
@@ -736,14 +739,29 @@ __global__ void k_mlp_reduce(const float* __restrict__ part, int32_t nw, float* 
   const float gp = (float)s;
   if (grad) grad[p] = gp;
   if (w) {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float m = b1 * am[p] + (1.f - b1) * gp;
-    const float v = b2 * av[p] + (1.f - b2) * gp * gp;
-    am[p] = m;
-    av[p] = v;
-    const float mh = m / (1.f - powf(b1, (float)t)), vh = v / (1.f - powf(b2, (float)t));
-    w[p] -= lr * mh / (sqrtf(vh) + 1e-8f);
+    const double b1 = 0.9, b2 = 0.999, g = (double)gp;
+    const double m = b1 * (double)am[p] + (1.0 - b1) * g;
+    const double v = b2 * (double)av[p] + (1.0 - b2) * g * g;
+    am[p] = (float)m;
+    av[p] = (float)v;
+    const double mh = m / (1.0 - pow(b1, (double)t)), vh = v / (1.0 - pow(b2, (double)t));
+    w[p] = (float)((double)w[p] - lr * mh / (sqrt(vh) + 1e-8));
   }
+}
+
+// Initial weights (one thread per parameter), as mlp_init describes.
+__global__ void k_mlp_init(uint64_t state, float out_scale, float* __restrict__ w) {
+  const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  float sd = 0.f;  // biases stay 0
+  if (p >= OFF_W1 && p < OFF_B1) sd = sqrtf(2.f / (float)NIN);
+  else if (p >= OFF_W2 && p < OFF_B2) sd = sqrtf(2.f / (float)NH);
+  else if (p >= OFF_W3 && p < OFF_B3) sd = out_scale / sqrtf((float)NH);
+  // Box-Muller: u1 in (0, 1] from the top 24 bits, u2 in [0, 1)
+  const float u1 = (float)((sm64_at(state, 2 * (uint64_t)p) >> 40) + 1) * 0x1p-24f;
+  const float u2 = (float)(sm64_at(state, 2 * (uint64_t)p + 1) >> 40) * 0x1p-24f;
+  const float z = sqrtf(-2.f * logf(u1)) * cospif(2.f * u2);
+  w[p] = sd * z;
 }
 
 inline int32_t grad_waves(int64_t B) { return (int32_t)((B + 16 * RB - 1) / (16 * RB)); }
@@ -825,8 +843,13 @@ hipError_t mlp_grad(int64_t count, const float* feat, const float* tgt, const fl
   k_mlp_grad<<<nwp / MW, 64 * MW, 0, s>>>(feat, tgt, count, count, 0, wts, part.as<float>());
   MM_TRY(hipGetLastError());
   k_mlp_reduce<<<(NPARAM + 256) / 256, 256, 0, s>>>(part.as<float>(), nwp, grad, loss_dev,
-                                                    nullptr, nullptr, nullptr, 0, 0.f,
+                                                    nullptr, nullptr, nullptr, 0, 0.0,
                                                     1.f / (float)count);
+  return hipGetLastError();
+}
+
+hipError_t mlp_init(uint64_t seed, double out_scale, float* wts, hipStream_t s) {
+  k_mlp_init<<<(NPARAM + 255) / 256, 256, 0, s>>>(rng_stream(seed, 0, 65), (float)out_scale, wts);
   return hipGetLastError();
 }
 
@@ -844,7 +867,7 @@ hipError_t mlp_train(int64_t N, const float* feat, const float* tgt, float* wts,
     k_mlp_grad<<<nwp / MW, 64 * MW, 0, s>>>(feat, tgt, N, batch, state, wts, part.as<float>());
     k_mlp_reduce<<<(NPARAM + 256) / 256, 256, 0, s>>>(part.as<float>(), nwp, nullptr,
                                                       losses ? losses + it : nullptr, wts, adam,
-                                                      adam + NPARAM, t, (float)lr,
+                                                      adam + NPARAM, t, lr,
                                                       1.f / (float)batch);
   }
   return hipGetLastError();

@@ -946,10 +946,9 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   return hipGetLastError();
 }
 
-hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
-                       const float* rho, const float* xy, const float* F, double alpha, double q,
-                       float* xy_out, double* delta2_dev, hipStream_t s, const float* alpha_dev,
-                       int32_t group, int32_t nb) {
+hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
+                               const float* xy, double alpha, double q, hipStream_t s,
+                               const float* alpha_dev, int32_t group, int32_t nb) {
   const bool coarse = level > 0 && sqrtc != nullptr;
   const bool q0 = q == 0.0;
   if (ts.tbits < 11 || ts.tbits > 13) return hipErrorInvalidValue;
@@ -1011,14 +1010,28 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
 #undef MM_TSN
 #undef MM_TST
 #undef MM_TS
-  MM_TRY(hipGetLastError());
+  return hipGetLastError();
+}
+
+hipError_t sweep_tiled_combine(const TiledSet& ts, const float* rho, const float* xy,
+                               const float* F, double alpha, float* xy_out, double* delta2_dev,
+                               hipStream_t s, const float* alpha_dev) {
   const int32_t ncb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);
   DevBuf& dpart = const_cast<TiledSet&>(ts).b_dpart;
   if (dpart.bytes < sizeof(double2) * (size_t)ncb) MM_TRY(dpart.alloc(sizeof(double2) * (size_t)ncb, s));
-  k_combine<<<ncb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, part, rho, (const float2*)xy, (const float2*)F,
-                                (float)alpha, (float2*)xy_out, dpart.as<double2>(), alpha_dev);
+  k_combine<<<ncb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, ts.b_partial.as<float2>(), rho,
+                                (const float2*)xy, (const float2*)F, (float)alpha,
+                                (float2*)xy_out, dpart.as<double2>(), alpha_dev);
   k_sum_parts2<<<1, 1024, 0, s>>>(dpart.as<double2>(), ncb, delta2_dev);
   return hipGetLastError();
+}
+
+hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
+                       const float* rho, const float* xy, const float* F, double alpha, double q,
+                       float* xy_out, double* delta2_dev, hipStream_t s, const float* alpha_dev,
+                       int32_t group, int32_t nb) {
+  MM_TRY(sweep_tiled_partial(ts, level, sqrtc, scale, xy, alpha, q, s, alpha_dev, group, nb));
+  return sweep_tiled_combine(ts, rho, xy, F, alpha, xy_out, delta2_dev, s, alpha_dev);
 }
 
 }  // namespace mm

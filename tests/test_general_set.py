@@ -74,8 +74,16 @@ def test_validate_accepts_general_sets():
     g = synth.rgg(500, 2)
     mm.khop_validate(g.n, 3, *gs.thresholded(g, g.points, 3, 0.08))
     mm.khop_validate(g.n, 2, *gs.sampled(g, 2, 0.3, seed=1))
-    # a row with no entries (vertex 2 of a 3-vertex graph with one edge)
-    mm.khop_validate(3, 1, np.array([0, 1, 2, 2]), np.array([1, 1, 0]), np.array([1, 0]))
+
+
+def test_validate_rejects_empty_row():
+    """A row with no entries has rho_u = 0, the divisor of Eq. 2 (vertex 2 of
+    a 3-vertex set holding only the pair (0, 1))."""
+    import paper_1506_04383_amd as mm
+
+    with pytest.raises(mm.MulmentError, match="row 2 is empty") as e:
+        mm.khop_validate(3, 1, np.array([0, 1, 2, 2]), np.array([1, 1, 0]), np.array([1, 0]))
+    assert e.value.status == 1  # MM_EINVAL
 
 
 def _corrupt(which):

@@ -122,6 +122,131 @@ def test_mlp_grad_matches_oracle(orc, mm, ctx, count):
         o += k
 
 
+def test_mlp_init_is_box_muller_of_splitmix64(orc, mm, ctx):
+    """mm_mlp_init: parameter p is sd_p * sqrt(-2 ln u1) cos(2 pi u2) with
+    u1 = (top 24 bits of draw 2p, plus 1) / 2^24 and u2 = (top 24 bits of
+    draw 2p + 1) / 2^24 of SplitMix64 stream (seed, 0, tag 65) (draws from
+    the oracle's generator), sd = sqrt(2/8), sqrt(2/64), out_scale/8, 0 by
+    block; FP32 logf/cospif against FP64: within 1e-5 relative of max |w|.
+    Same seed, same bits."""
+    seed, scale = 17, 0.3
+    w = mm.mlp_init(ctx, seed, scale).cpu().numpy().astype(np.float64)
+    w2 = mm.mlp_init(ctx, seed, scale).cpu().numpy()
+    assert np.array_equal(w.astype(np.float32), w2)
+    r = orc.draws(seed, 0, 65, 0, 2 * mm.MLP_PARAMS)
+    u1 = ((r[0::2] >> np.uint64(40)).astype(np.float64) + 1.0) * 2.0 ** -24
+    u2 = (r[1::2] >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    sd = np.concatenate([np.full(512, np.sqrt(2 / 8)), np.zeros(64), np.full(4096, np.sqrt(2 / 64)),
+                         np.zeros(64), np.full(128, scale / 8), np.zeros(2)])
+    ref = sd * z
+    err = np.abs(w - ref).max() / np.abs(ref).max()
+    print(f"  max err {err:.2e}; W2 std {w[576:4672].std():.4f} (He {np.sqrt(2 / 64):.4f})")
+    assert err < 1e-5
+    assert np.all(w[sd == 0] == 0)
+
+
+def _adam_data(count, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 0.7, (count, 8)).astype(np.float32)
+    X[:, 7] = 0
+    Y = (0.3 * np.tanh(X[:, :2] * X[:, 2:4]) + rng.normal(0, 0.05, (count, 2))).astype(np.float32)
+    from oracle import mlp
+
+    w = mlp.init(5, out_scale=1.0)
+    w = (w + rng.normal(0, 0.1, w.size)).astype(np.float32)  # biases away from 0 too
+    return X, Y, w
+
+
+def test_adam_steps_match_oracle(orc, mm, ctx):
+    """mm_mlp_train one step at a time (steps 1..5, bias correction of each
+    step number) against the oracle's Adam step (Kingma and Ba 2015, Alg. 1)
+    fed the gradient the GPU computes on the same minibatch: the oracle's
+    minibatch rows, gathered on the host and passed to mm_mlp_grad in order,
+    give the GPU training step's gradient bit for bit (the same kernel sees
+    the same rows in the same order).  Moments within 1e-6 relative (FP32
+    storage of an FP64 step), weight updates within 3e-4 of the largest
+    update: storing a weight below 4 in FP32 rounds it by at most 2^-23 ~
+    1.2e-7, against updates of up to lr = 1e-3."""
+    import torch
+
+    from oracle import mlp
+
+    count, B, lr, seed = 3000, 512, 1e-3, 9
+    X, Y, w0 = _adam_data(count, 31)
+    Xd, Yd = _dev(mm, X), _dev(mm, Y)
+    w = _dev(mm, w0)
+    adam = torch.zeros(2 * mm.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    P = mm.MLP_PARAMS
+    for t in range(1, 6):
+        w_prev = w.cpu().numpy().astype(np.float64)
+        m_prev = adam[:P].cpu().numpy().astype(np.float64)
+        v_prev = adam[P:].cpu().numpy().astype(np.float64)
+        rows = mlp.minibatch_rows(count, B, seed, t)
+        loss_g, g = mm.mlp_grad(ctx, _dev(mm, X[rows]), _dev(mm, Y[rows]), w)
+        loss_t = mm.mlp_train(ctx, Xd, Yd, w, adam, 1, B, lr, seed, step0=t - 1).cpu().numpy()
+        w_ref, m_ref, v_ref = mlp.adam_step(w_prev, g.cpu().numpy().astype(np.float64), m_prev,
+                                            v_prev, t, lr)
+        m_gpu = adam[:P].cpu().numpy().astype(np.float64)
+        v_gpu = adam[P:].cpu().numpy().astype(np.float64)
+        dw_gpu = w.cpu().numpy().astype(np.float64) - w_prev
+        dw_ref = w_ref - w_prev
+        em = (np.abs(m_gpu - m_ref) / np.abs(m_ref).max()).max()
+        ev = (np.abs(v_gpu - v_ref) / np.abs(v_ref).max()).max()
+        ew = (np.abs(dw_gpu - dw_ref) / np.abs(dw_ref).max()).max()
+        print(f"  step {t}: loss {loss_t[0]:.4e} (grad call {loss_g:.4e}); "
+              f"m err {em:.1e} v err {ev:.1e} update err {ew:.1e}", flush=True)
+        assert loss_t[0] == np.float32(loss_g)
+        assert em < 1e-6 and ev < 1e-6 and ew < 3e-4
+
+
+def test_adam_training_matches_oracle(orc, mm, ctx):
+    """Ten GPU Adam steps (mm_mlp_train, minibatches of 1024 drawn from 5000
+    samples) against the oracle's ten steps from the same start on the same
+    draws, its gradient taken with the network the GPU evaluates (BF16
+    matrices and inputs): minibatch losses within 2e-2 relative, weights
+    within 2e-2 per tensor (norm of the difference over the oracle tensor's
+    norm), moments within 5e-2 per tensor."""
+    import torch
+
+    from oracle import mlp
+
+    count, B, lr, seed, steps = 5000, 1024, 2e-3, 13, 10
+    X, Y, w0 = _adam_data(count, 32)
+    w = _dev(mm, w0)
+    adam = torch.zeros(2 * mm.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    losses = mm.mlp_train(ctx, _dev(mm, X), _dev(mm, Y), w, adam, steps, B, lr, seed)
+    losses = losses.cpu().numpy().astype(np.float64)
+    wr = w0.astype(np.float64)
+    mr = np.zeros_like(wr)
+    vr = np.zeros_like(wr)
+    lr_ref = []
+    Xb = bf16(X)
+    for t in range(1, steps + 1):
+        rows = mlp.minibatch_rows(count, B, seed, t)
+        L, g = mlp.loss_grad(bf16_weights(wr), Xb[rows], Y[rows].astype(np.float64))
+        lr_ref.append(L)
+        wr, mr, vr = mlp.adam_step(wr, g, mr, vr, t, lr)
+    el = np.abs(losses - lr_ref) / np.array(lr_ref)
+    print(f"  losses gpu {losses[0]:.4e} .. {losses[-1]:.4e}, oracle {lr_ref[0]:.4e} .. "
+          f"{lr_ref[-1]:.4e}; max rel err {el.max():.2e}", flush=True)
+    assert el.max() < 2e-2
+    wg = w.cpu().numpy().astype(np.float64)
+    P = mm.MLP_PARAMS
+    mg = adam[:P].cpu().numpy().astype(np.float64)
+    o = 0
+    for name, shp in BLOCKS:
+        k = int(np.prod(shp))
+        sl = slice(o, o + k)
+        e_w = np.linalg.norm(wg[sl] - wr[sl]) / np.linalg.norm(wr[sl])
+        e_m = np.linalg.norm(mg[sl] - mr[sl]) / np.linalg.norm(mr[sl])
+        e_dw = np.linalg.norm((wg[sl] - w0[sl]) - (wr[sl] - w0[sl])) / np.linalg.norm(wr[sl] - w0[sl])
+        print(f"  {name}: weights {e_w:.2e}, first moment {e_m:.2e}, "
+              f"change of the weights {e_dw:.2e}", flush=True)
+        assert e_w < 2e-2 and e_m < 5e-2, name
+        o += k
+
+
 @pytest.mark.parametrize("n,seed,theta", [(700, 1, 1.0), (3000, 2, 1.0), (3000, 3, 0.5),
                                           (20000, 4, 1.0)])
 def test_samples_match_oracle(orc, mm, ctx, n, seed, theta):
