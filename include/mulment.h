@@ -300,6 +300,24 @@ mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int3
                    double scale, const float* xy_in, const float* F, double alpha, double q,
                    float* xy_out, double* delta);
 
+/* mm_sweep without any device allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernel and result (bit
+ * for bit) as mm_sweep.  Its temporaries -- the per-work-group partial sums,
+ * the two relative-change sums and, on levels > 0, sqrt of the node weights
+ * -- live in a fixed device array of the library (about 8 MiB), one copy per
+ * device, held until the process ends; nothing in it needs to start at zero,
+ * since every call writes what it reads.  The sets must have at most
+ * MM_SWEEP_NOALLOC_MAX_N vertices, else MM_EINVAL (nothing is launched).
+ * All calls on one device share that device's array: calls that overlap on
+ * one device (several streams, contexts or host threads) race and must be
+ * serialised by the caller.  MM_EDEVICE if the array's address could not be
+ * looked up when the context was created. */
+#define MM_SWEEP_NOALLOC_MAX_N (1 << 20)
+mm_status mm_sweep_noalloc(mm_context* ctx, const mm_khop* kh, int32_t level,
+                           const int32_t* node_w, double scale, const float* xy_in,
+                           const float* F, double alpha, double q, float* xy_out, double* delta);
+
 /* Kernel choice for mm_sweep_ex.  Both compute the same update.
  * MM_SWEEP_ROWS: a group of lanes per row gathers x_v from HBM/L2.
  * MM_SWEEP_TILED: the sets are re-laid tile-major (tiles of 8192 vertices,

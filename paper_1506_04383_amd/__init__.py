@@ -95,10 +95,11 @@ EXPORTS = ["mm_params_default", "mm_context_create", "mm_context_destroy", "mm_s
            "mm_far_samples", "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_layout_batch",
            "mm_tune_clear", "mm_tune_export", "mm_tune_import", "mm_sweep_cfg",
            "mm_repulsion_cluster", "mm_full_stress_ex", "mm_khop_validate", "mm_khop_import",
-           "mm_mlp_init"]
+           "mm_sweep_noalloc", "mm_mlp_init"]
 
 TUNE_FIELDS = 7  # coarse?, n, sum |S|, k, tile bits, lanes, blocks per step
 MLP_PARAMS = 4866  # W1 64x8, b1 64, W2 64x64, b2 64, W3 2x64, b3 2 (FP32, packed)
+SWEEP_NOALLOC_MAX_N = 1 << 20  # vertex limit of mm_sweep_noalloc's fixed scratch
 
 _lib = None
 
@@ -128,6 +129,7 @@ def lib():
         "mm_repulsion": [vp, i32, vp, f64, f64, vp, vp, vp, vp, vp],
         "mm_sweep": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp],
         "mm_sweep_ex": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32],
+        "mm_sweep_noalloc": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp],
         "mm_sweep_cfg": [vp, vp, i32, vp, f64, vp, vp, f64, f64, vp, vp, i32, i32, i32],
         "mm_coarsen": [vp, P(MMGraph), f64, i32, u64, i32, vp, P(vp), vp, vp],
         "mm_coarse_graph": [vp, P(MMGraph)],
@@ -564,6 +566,23 @@ def sweep(ctx: Context, kh: KHop, xy, F, alpha: float, q: float = 0.0, level: in
         _check(lib().mm_sweep_cfg(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha,
                                   q, _ptr(out), d.ctypes.data_as(C.c_void_p), int(config[0]),
                                   int(config[1]), blocks))
+    return out, (float(d[0]), float(d[1]))
+
+
+def sweep_noalloc(ctx: Context, kh: KHop, xy, F, alpha: float, q: float = 0.0, level: int = 0,
+                  node_w=None, scale: float = 1.0, out=None):
+    """mm_sweep_noalloc: the row-kernel Jacobi iteration with the library's
+    fixed scratch (no device allocation by the library); out (optional) is
+    the caller's output tensor.  Returns (xy_out, (|x'-x|^2, |x|^2))."""
+    t = ctx.torch
+    xy = ctx._dev(xy, t.float32)
+    F = ctx._dev(F, t.float32)
+    nw = None if node_w is None else ctx._dev(node_w, t.int32)
+    if out is None:
+        out = t.empty_like(xy)
+    d = np.zeros(2)
+    _check(lib().mm_sweep_noalloc(ctx.h, kh.h, level, _ptr(nw), scale, _ptr(xy), _ptr(F), alpha,
+                                  q, _ptr(out), d.ctypes.data_as(C.c_void_p)))
     return out, (float(d[0]), float(d[1]))
 
 

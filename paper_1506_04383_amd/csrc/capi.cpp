@@ -39,6 +39,10 @@ struct mm_context {
   float* alpha_dev = nullptr;
   hipStream_t far = nullptr;     // far field of mm_layout, beside the sweep on `work`
   hipEvent_t ev[8] = {};
+  // this device's copy of the fixed scratch of mm_sweep_noalloc (null if its
+  // lookup failed; scratch_err then holds the HIP error)
+  void* scratch = nullptr;
+  hipError_t scratch_err = hipSuccess;
   // autotuner: sweep configuration per level shape (coarse?, n, sum |S|, k)
   struct TuneChoice { int32_t tbits, group, nb; };  // tbits 0: row kernel (nb 0)
   std::map<std::tuple<int, int32_t, int64_t, int32_t>, TuneChoice> tune;
@@ -414,6 +418,9 @@ mm_status mm_context_create(mm_context** out, int32_t device, void* stream) {
     HIPCHK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->far, hipStreamNonBlocking));
     for (auto& e : c->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDefault));
+    // device address of the no-allocation sweep's scratch (looked up once per
+    // device, with the device current); a failure is reported by that call
+    c->scratch_err = mm::noalloc_scratch_setup(device, &c->scratch);
     mm::big_register(c->stream);
     mm::big_register(c->work);
     mm::big_register(c->far);
@@ -819,6 +826,45 @@ mm_status mm_sweep(mm_context* ctx, const mm_khop* kh, int32_t level, const int3
                    float* xy_out, double* delta) {
   return mm_sweep_ex(ctx, const_cast<mm_khop*>(kh), level, node_w, scale, xy_in, F, alpha, q,
                      xy_out, delta, MM_SWEEP_ROWS);
+}
+
+static_assert(MM_SWEEP_NOALLOC_MAX_N == mm::kNoallocMaxN, "scratch limit");
+
+mm_status mm_sweep_noalloc(mm_context* ctx, const mm_khop* kh, int32_t level,
+                           const int32_t* node_w, double scale, const float* xy_in,
+                           const float* F, double alpha, double q, float* xy_out, double* delta) {
+  try {
+    if (!ctx || !kh || !xy_in || !F || !xy_out) return fail(MM_EINVAL, "NULL argument");
+    if (xy_in == xy_out) return fail(MM_EINVAL, "Jacobi update needs separate in/out buffers");
+    if (level < 0 || !(scale > 0) || std::isnan(alpha) || std::isnan(q)) return fail(MM_EINVAL, "bad level/scale/alpha/q");
+    const mm::KhopDev& K = kh->kh;
+    if (K.n > MM_SWEEP_NOALLOC_MAX_N)
+      return fail(MM_EINVAL, "mm_sweep_noalloc: %d vertices exceed its scratch limit of %d", K.n,
+                  MM_SWEEP_NOALLOC_MAX_N);
+    if (K.k > 8) return fail(MM_EINVAL, "k must be <= 8");
+    if (K.n > 0 && !K.nbr && K.total > 0) return fail(MM_EINVAL, "the sets hold no ids");
+    if (!ctx->scratch)
+      return fail(MM_EDEVICE, "scratch of device %d unavailable: %s", ctx->device,
+                  hipGetErrorString(ctx->scratch_err));
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    unsigned char* base = static_cast<unsigned char*>(ctx->scratch);
+    double* d2 = reinterpret_cast<double*>(base);
+    double2* part = reinterpret_cast<double2*>(base + mm::kNoallocPartOff);
+    float* sqrtc = nullptr;
+    if (level > 0) {
+      sqrtc = reinterpret_cast<float*>(base + mm::kNoallocSqrtcOff);
+      HIPCHK(mm::sqrt_weights(K.n, node_w, sqrtc, s));
+    }
+    HIPCHK(mm::sweep_into(K, level, sqrtc, scale, xy_in, F, alpha, q, xy_out, d2, part,
+                          mm::kNoallocPartBytes, s));
+    HIPCHK(hipMemcpyAsync(ctx->pinned, d2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (delta) { delta[0] = ctx->pinned[0]; delta[1] = ctx->pinned[1]; }
+    return MM_OK;
+  } catch (...) {
+    return fail(MM_EINTERNAL, "exception in mm_sweep_noalloc");
+  }
 }
 
 // ------------------------------------------------------------- coarsening

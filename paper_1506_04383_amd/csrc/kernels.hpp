@@ -248,6 +248,34 @@ inline int32_t row_group(const KhopDev& kh) {
   const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
   return avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
 }
+// work-groups of the row kernel (256 threads, 256/G rows each) = entries of
+// its reduction buffer (one double2 per work-group)
+inline int32_t sweep_blocks(int32_t n, int32_t G) {
+  const int32_t rpb = 256 / G;
+  return (n + rpb - 1) / rpb;
+}
+// The row kernel with a caller-provided reduction buffer (part: part_bytes,
+// at least sweep_blocks(n, G) double2) and no allocation; group 0 = the
+// heuristic.  hipErrorInvalidValue if the buffer is too small or k > 8.
+hipError_t sweep_into(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
+                      const float* xy, const float* F, double alpha, double q, float* xy_out,
+                      double* delta2_dev, double2* part, size_t part_bytes, hipStream_t s,
+                      const int32_t* gid = nullptr, const float* galpha = nullptr,
+                      const float* alpha_dev = nullptr, int32_t group = 0);
+
+// ---- fixed scratch of the no-allocation sweep (noalloc.hip)
+// Layout: [0, 16) the two FP64 relative-change sums; [kNoallocPartOff, +
+// kNoallocPartBytes) the row kernel's per-work-group partials (at most
+// sweep_blocks(n, 64) = n/4 double2); [kNoallocSqrtcOff, + 4n) sqrt of the
+// node weights on coarse levels.
+constexpr int32_t kNoallocMaxN = 1 << 20;
+constexpr size_t kNoallocPartOff = 256;
+constexpr size_t kNoallocPartBytes = 16 * (size_t)(kNoallocMaxN / 4);
+constexpr size_t kNoallocSqrtcOff = kNoallocPartOff + kNoallocPartBytes;
+constexpr size_t kNoallocScratchBytes = kNoallocSqrtcOff + 4 * (size_t)kNoallocMaxN;
+// Device address of the scratch copy of `device`, which must be the current
+// device; looked up once per device (later calls return the first result).
+hipError_t noalloc_scratch_setup(int device, void** out);
 
 // ---- coarsening (coarsen.hip)
 struct GraphDev {

@@ -149,30 +149,42 @@ hipError_t launch(const KhopDev& kh, bool coarse, bool q0, const float* sqrtc, f
 
 }  // namespace
 
+hipError_t sweep_into(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
+                      const float* xy, const float* F, double alpha, double q, float* xy_out,
+                      double* delta2_dev, double2* part, size_t part_bytes, hipStream_t s,
+                      const int32_t* gid, const float* galpha, const float* alpha_dev,
+                      int32_t group) {
+  if (kh.k > KMAX) return hipErrorInvalidValue;
+  const int G = group > 0 ? group : row_group(kh);
+  if (G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+  const int32_t nb = sweep_blocks(kh.n, G);
+  if (!part || part_bytes < sizeof(double2) * (size_t)nb) return hipErrorInvalidValue;
+  const bool coarse = (level > 0) && sqrtc != nullptr;
+  const bool q0 = (q == 0.0);
+  hipError_t e;
+  switch (G) {
+    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part, nb, s, gid, galpha, alpha_dev); break;
+    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part, nb, s, gid, galpha, alpha_dev); break;
+    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part, nb, s, gid, galpha, alpha_dev); break;
+    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part, nb, s, gid, galpha, alpha_dev); break;
+  }
+  MM_TRY(e);
+  k_sum_parts<<<1, 1024, 0, s>>>(part, nb, delta2_dev);
+  return hipGetLastError();
+}
+
 hipError_t sweep(const KhopDev& kh, int32_t level, const float* sqrtc, double scale,
                  const float* xy, const float* F, double alpha, double q, float* xy_out,
                  double* delta2_dev, hipStream_t s, const int32_t* gid, const float* galpha,
                  const float* alpha_dev, DevBuf* part_ws, int32_t group) {
   if (kh.k > KMAX) return hipErrorInvalidValue;
-  const double avg = kh.n > 0 ? (double)kh.total / (double)kh.n : 0.0;
-  int G = group > 0 ? group : avg >= 96 ? 64 : avg >= 40 ? 32 : avg >= 16 ? 16 : 8;
-  const int32_t rpb = SW_T / G;
-  const int32_t nb = (kh.n + rpb - 1) / rpb;
+  const int G = group > 0 ? group : row_group(kh);
+  const int32_t nb = sweep_blocks(kh.n, G);
   DevBuf local;
   DevBuf& part = part_ws ? *part_ws : local;
   if (part.bytes < sizeof(double2) * (size_t)nb) MM_TRY(part.alloc(sizeof(double2) * (size_t)nb, s));
-  const bool coarse = (level > 0) && sqrtc != nullptr;
-  const bool q0 = (q == 0.0);
-  hipError_t e;
-  switch (G) {
-    case 64: e = launch<64>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
-    case 32: e = launch<32>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
-    case 16: e = launch<16>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
-    default: e = launch<8>(kh, coarse, q0, sqrtc, (float)scale, xy, F, (float)alpha, (float)q, xy_out, part.as<double2>(), nb, s, gid, galpha, alpha_dev); break;
-  }
-  MM_TRY(e);
-  k_sum_parts<<<1, 1024, 0, s>>>(part.as<double2>(), nb, delta2_dev);
-  return hipGetLastError();
+  return sweep_into(kh, level, sqrtc, scale, xy, F, alpha, q, xy_out, delta2_dev,
+                    part.as<double2>(), part.bytes, s, gid, galpha, alpha_dev, G);
 }
 
 }  // namespace mm
