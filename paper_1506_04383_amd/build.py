@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["prims.hip", "khop.hip", "farfield.hip", "clusterfar.hip", "learned.hip", "sweep.hip",
            "tiled.hip", "coarsen.hip", "layout.hip", "batch.hip", "objective.hip", "noalloc.hip",
-           "capi.cpp"]
+           "validate.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MM_OFFLOAD_ARCH", "gfx950")

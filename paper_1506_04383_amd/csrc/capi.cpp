@@ -21,6 +21,7 @@
 
 #include "mulment.h"
 #include "kernels.hpp"
+#include "validate.hpp"
 
 // Batch levels up to this many vertices replay their iterations from HIP
 // graphs (their time is dominated by launches).
@@ -98,31 +99,8 @@ struct DeviceGuard {
 // Host-side structural validation (undirected simple graph, weights >= 1).
 mm_status validate_graph(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
                          const int32_t* c, const int32_t* w) {
-  if (n < 2) return fail(MM_EINVAL, "graph needs at least 2 vertices (n=%d)", n);
-  if (rp[0] != 0 || (int64_t)rp[n] != nnz) return fail(MM_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
-  for (int32_t u = 0; u < n; ++u)
-    if (rp[u + 1] < rp[u]) return fail(MM_EINVAL, "row_ptr not monotone at %d", u);
-  for (int32_t u = 0; u < n; ++u) {
-    if (rp[u + 1] == rp[u]) return fail(MM_EINVAL, "vertex %d is isolated (rho_u = 0)", u);
-    if (c && c[u] < 1) return fail(MM_EINVAL, "node weight of %d < 1", u);
-    for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
-      const int32_t v = col[e];
-      if (v < 0 || v >= n) return fail(MM_EINVAL, "column %d out of range in row %d", v, u);
-      if (v == u) return fail(MM_EINVAL, "self-loop at %d", u);
-      if (e > rp[u] && col[e - 1] >= v) return fail(MM_EINVAL, "row %d not strictly ascending", u);
-      if (w && w[e] < 1) return fail(MM_EINVAL, "edge weight < 1 in row %d", u);
-    }
-  }
-  for (int32_t u = 0; u < n; ++u) {
-    for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
-      const int32_t v = col[e];
-      const int32_t* b = col + rp[v];
-      const int32_t* en = col + rp[v + 1];
-      const int32_t* it = std::lower_bound(b, en, u);
-      if (it == en || *it != u) return fail(MM_EINVAL, "edge %d-%d has no reverse", u, v);
-      if (w && w[it - col] != w[e]) return fail(MM_EINVAL, "edge weights of %d-%d differ", u, v);
-    }
-  }
+  char msg[256];
+  if (!mm::check_graph(n, nnz, rp, col, c, w, msg, sizeof(msg))) return fail(MM_EINVAL, "%s", msg);
   return MM_OK;
 }
 
@@ -355,13 +333,7 @@ mm_status mm_tune_import(mm_context* ctx, const int64_t* recs, int32_t count) {
   if (!ctx) return fail(MM_EINVAL, "NULL context");
   if (count < 0 || (count > 0 && !recs)) return fail(MM_EINVAL, "bad record list (%d)", count);
   for (int32_t i = 0; i < count; ++i) {
-    const int64_t* r = recs + (size_t)i * MM_TUNE_FIELDS;
-    const bool tb_ok = r[4] == 0 || (r[4] >= 11 && r[4] <= 13);
-    const bool g_ok = r[5] >= 1 && r[5] <= 64 && (r[5] & (r[5] - 1)) == 0 &&
-                      (r[4] == 0 ? r[5] >= 8 : (r[5] <= 16 || r[5] == mm::kSlicedGroup));
-    const bool nb_ok = r[4] == 0 ? r[6] == 0 : (r[6] == 0 || r[6] == 2 || r[6] == 4);
-    if (!tb_ok || !g_ok || !nb_ok || (r[0] != 0 && r[0] != 1) || r[1] < 0 || r[1] > INT32_MAX || r[2] < 0 ||
-        r[3] < 1 || r[3] > INT32_MAX)
+    if (!mm::check_tune_record(recs + (size_t)i * MM_TUNE_FIELDS, mm::kSlicedGroup))
       return fail(MM_EINVAL, "tune record %d is invalid", i);
   }
   for (int32_t i = 0; i < count; ++i) {
@@ -530,64 +502,8 @@ mm_status mm_khop_export(mm_context* ctx, const mm_khop* kh, int64_t* off, int32
 // (v, u, h) in row v.
 mm_status mm_khop_validate(int32_t n, int32_t k, const int64_t* off, const int32_t* hend,
                            const int32_t* nbr) {
-  if (!off || !hend) return fail(MM_EINVAL, "NULL argument");
-  if (n < 2) return fail(MM_EINVAL, "n < 2");
-  if (k < 1 || k > 8) return fail(MM_EINVAL, "k must be in [1, 8]");
-  if (off[0] != 0) return fail(MM_EINVAL, "off[0] = %lld, must be 0", (long long)off[0]);
-  for (int32_t u = 0; u < n; ++u) {
-    const int64_t len = off[u + 1] - off[u];
-    if (len < 0) return fail(MM_EINVAL, "off decreases at row %d", u);
-    // Eq. 2 divides by rho_u = sum of w_uv over S(u): an empty row has none
-    if (len == 0) return fail(MM_EINVAL, "row %d is empty (rho_u = 0 in Eq. 2)", u);
-    if (len >= n) return fail(MM_EINVAL, "row %d has %lld entries (at most n-1)", u, (long long)len);
-    int32_t prev = 0;
-    for (int32_t h = 0; h < k; ++h) {
-      const int32_t e = hend[(size_t)u * k + h];
-      if (e < prev) return fail(MM_EINVAL, "hend of row %d decreases at distance %d", u, h + 1);
-      prev = e;
-    }
-    if (prev != len)
-      return fail(MM_EINVAL, "hend of row %d ends at %d, row has %lld entries", u, prev, (long long)len);
-  }
-  const int64_t total = off[n];
-  if (total > 0 && !nbr) return fail(MM_EINVAL, "nbr is NULL");
-  std::vector<int32_t> seen((size_t)n, -1);
-  for (int32_t u = 0; u < n; ++u) {
-    const int32_t* row = nbr + off[u];
-    int32_t s0 = 0;
-    for (int32_t h = 0; h < k; ++h) {
-      const int32_t s1 = hend[(size_t)u * k + h];
-      for (int32_t i = s0; i < s1; ++i) {
-        const int32_t v = row[i];
-        if (v < 0 || v >= n) return fail(MM_EINVAL, "row %d: id %d out of range", u, v);
-        if (v == u) return fail(MM_EINVAL, "row %d holds itself", u);
-        if (i > s0 && row[i - 1] >= v)
-          return fail(MM_EINVAL, "row %d: ids at distance %d not strictly increasing", u, h + 1);
-        if (seen[(size_t)v] == u) return fail(MM_EINVAL, "row %d holds %d twice", u, v);
-        seen[(size_t)v] = u;
-      }
-      s0 = s1;
-    }
-  }
-  // every row is well formed now: look up the mirror of each pair, u in the
-  // group of row v with the same distance
-  for (int32_t u = 0; u < n; ++u) {
-    const int32_t* row = nbr + off[u];
-    int32_t s0 = 0;
-    for (int32_t h = 0; h < k; ++h) {
-      const int32_t s1 = hend[(size_t)u * k + h];
-      for (int32_t i = s0; i < s1; ++i) {
-        const int32_t v = row[i];
-        const int32_t* vr = nbr + off[v];
-        const int32_t* b = vr + (h ? hend[(size_t)v * k + h - 1] : 0);
-        const int32_t* e = vr + hend[(size_t)v * k + h];
-        const int32_t* f = std::lower_bound(b, e, u);
-        if (f == e || *f != u)
-          return fail(MM_EINVAL, "pair (%d, %d) at distance %d has no mirror (%d, %d)", u, v, h + 1, v, u);
-      }
-      s0 = s1;
-    }
-  }
+  char msg[256];
+  if (!mm::check_stress_set(n, k, off, hend, nbr, msg, sizeof(msg))) return fail(MM_EINVAL, "%s", msg);
   return MM_OK;
 }
 
