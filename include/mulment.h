@@ -165,8 +165,13 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
  * far field.  init_xy (n*2 or NULL): warm start of every graph as in
  * mm_layout.  out_xy: n*2 in the graph's memory kind.  graph_levels (host,
  * G, may be NULL): levels of each graph's hierarchy.  stats: per union
- * level sizes and iteration counts (the union iterates until its last
- * graph is done), totals. */
+ * level sizes, the iterations of its longest-running graph
+ * (level_iters, level_final_iters), the number of its graphs stopped by
+ * max_final_iters (level_cap_hit), the sweep configuration, and totals
+ * (vertex_updates counts each graph's own iterations).  Each graph's alpha
+ * schedule and stop run on the device; the host checks the number of
+ * running graphs once per replay of several captured iterations (iterations
+ * after a graph's stop leave its coordinates unchanged). */
 mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, const mm_graph* g,
                           const mm_params* p, const float* init_xy, float* out_xy,
                           int32_t* graph_levels, mm_stats* stats);

@@ -23,9 +23,10 @@
 #include "kernels.hpp"
 #include "validate.hpp"
 
-// Batch levels up to this many vertices replay their iterations from HIP
-// graphs (their time is dominated by launches).
-constexpr int32_t kGraphMaxN = 1 << 18;
+// Iterations of a batch level captured into one HIP graph and replayed
+// between two host checks of the running-graph count (even: a replay keeps
+// the parity of the coordinate buffers).
+constexpr int32_t kBatchReplay = 4;
 // Single-graph levels replay far field and sweep from two graphs above this
 // many vertices, from one graph at or below it.
 constexpr int32_t kSplitMinN = 1 << 16;
@@ -1696,76 +1697,143 @@ mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, 
       HIPCHK(galpha.alloc(sizeof(float) * (size_t)M, s));
       HIPCHK(mm::batch_sched_init(M, prm, init_xy ? p->alpha_min : p->alpha0, gst.as<mm::BatchState>(),
                                   galpha.as<float>(), s));
+      // sweep configuration of the union level, as in mm_layout: the tuner's
+      // choice for the level's shape (autotune), else the tile-major sliced
+      // sweep when the mean (row, tile) chunk has at least 8 entries
+      int32_t tbits_lvl = lvl == 0 ? mm::kTileBits : (nl >= (1 << 17) ? 12 : 11);
+      int32_t group_lvl = 0, nb_lvl = 0;
+      double min_avg = 8.0;
+      if (p->autotune) {
+        const auto key = std::make_tuple(lvl > 0 ? 1 : 0, nl, kh.total, p->k);
+        auto it = ctx->tune.find(key);
+        if (it == ctx->tune.end()) {
+          mm_context::TuneChoice c;
+          STCHK(tune_level(ctx, kh, lvl, sqrtc, p, xa.as<float>(), F.as<float>(), xb.as<float>(),
+                           d2.as<double>(), s, &c));
+          it = ctx->tune.emplace(key, c).first;
+        }
+        tbits_lvl = it->second.tbits;
+        group_lvl = it->second.group;
+        nb_lvl = it->second.nb;
+        min_avg = 0.0;
+      }
+      mm::TiledSet ts;
+      mm::DevBuf rho;
+      if (tbits_lvl > 0 && mm::tiled_eligible(kh, tbits_lvl)) {
+        HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
+        HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s, sqrtc, p->coarse_dist_scale,
+                               rho.as<float>(), group_lvl == 0 || group_lvl == mm::kSlicedGroup));
+        if (ts.built) kh.b_nbr.release();
+        HIPCHK(hipStreamSynchronize(s));
+      }
       mm::BHSeg bseg;
       bseg.M = M;
       bseg.gid = L.d_gid.as<int32_t>();
       bseg.goff = L.d_goff.as<int32_t>();
-      int32_t iters = 0;
+      int32_t launched = 0;  // iterations launched (finished graphs only copy)
       mm::DevBuf sweep_part;
       float* bufA = xa.as<float>();
       float* bufB = xb.as<float>();
       int parity = 0;
       int32_t* hc = reinterpret_cast<int32_t*>(ctx->pinned + 2);
+      const int32_t* gidp = L.d_gid.as<int32_t>();
       // one iteration of every graph still running: far field, sweep with the
-      // graph's alpha, per-graph relative change, schedule step, counters
+      // graph's alpha, per-graph relative change, schedule step (counters:
+      // graphs still running, graphs with a non-finite layout)
       auto enqueue = [&](const float* xin, float* xout) -> hipError_t {
         MM_TRY(mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
                                nullptr, nullptr, 0, nullptr, s, &bseg));
-        MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q, xout,
-                         d2.as<double>(), s, L.d_gid.as<int32_t>(), galpha.as<float>(), nullptr,
-                         &sweep_part));
+        if (ts.built) {
+          MM_TRY(mm::sweep_tiled_partial(ts, lvl, sqrtc, p->coarse_dist_scale, xin, 0.0, p->q, s,
+                                         nullptr, group_lvl, nb_lvl, gidp, galpha.as<float>()));
+          MM_TRY(mm::sweep_tiled_combine(ts, rho.as<float>(), xin, F.as<float>(), 0.0, xout,
+                                         d2.as<double>(), s, nullptr, gidp, galpha.as<float>()));
+        } else {
+          MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
+                           xout, d2.as<double>(), s, gidp, galpha.as<float>(), nullptr,
+                           &sweep_part, group_lvl));
+        }
         MM_TRY(mm::batch_delta(M, L.d_goff.as<int32_t>(), xin, xout, gd.as<double>(), s,
                                cnt.as<int32_t>()));
-        MM_TRY(mm::batch_schedule(M, gd.as<double>(), prm, gst.as<mm::BatchState>(),
-                                  galpha.as<float>(), cnt.as<int32_t>(), s));
+        return mm::batch_schedule(M, gd.as<double>(), prm, gst.as<mm::BatchState>(),
+                                  galpha.as<float>(), cnt.as<int32_t>(), s);
+      };
+      auto readback = [&]() -> hipError_t {
         return hipMemcpyAsync(hc, cnt.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
       };
-      // small union levels replay the iteration from HIP graphs (one per
-      // direction), captured after a direct iteration has sized the buffers
-      hipGraphExec_t gx[2] = {nullptr, nullptr};
+      // The union iterates until its last graph is done; the device-side
+      // schedule decides each graph's alpha and stop, so the host only needs
+      // the count of running graphs.  After two direct iterations (the first
+      // sizes every buffer; two keep the parity), kBatchReplay iterations are
+      // captured into one HIP graph and replayed with one host check per
+      // replay; iterations past the last graph's stop copy the coordinates
+      // of the finished graphs and leave the layout unchanged.
+      hipGraphExec_t gxr = nullptr;
       struct GraphGuard {
         hipGraphExec_t* g;
-        ~GraphGuard() { for (int i = 0; i < 2; ++i) if (g[i]) (void)hipGraphExecDestroy(g[i]); }
-      } gguard{gx};
-      bool gfail = !(p->use_graphs && nl <= kGraphMaxN);
+        ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
+      } gguard{&gxr};
+      bool gfail = !p->use_graphs;
       for (;;) {
-        const float* xin = parity ? bufB : bufA;
-        float* xout = parity ? bufA : bufB;
-        if (iters >= 1 && !gx[0] && !gfail) {
-          for (int d = 0; d < 2 && !gfail; ++d) {
-            hipGraph_t gr = nullptr;
-            if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) { gfail = true; break; }
-            const hipError_t e = enqueue(d ? bufB : bufA, d ? bufA : bufB);
+        if (launched >= 2 && !gxr && !gfail) {
+          hipGraph_t gr = nullptr;
+          if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            gfail = true;
+          } else {
+            hipError_t e = hipSuccess;
+            for (int32_t r = 0; r < kBatchReplay && e == hipSuccess; ++r)
+              e = enqueue((r & 1) ? bufB : bufA, (r & 1) ? bufA : bufB);
+            if (e == hipSuccess) e = readback();
             const hipError_t e2 = hipStreamEndCapture(s, &gr);
             if (e != hipSuccess || e2 != hipSuccess || !gr ||
-                hipGraphInstantiate(&gx[d], gr, nullptr, nullptr, 0) != hipSuccess) {
+                hipGraphInstantiate(&gxr, gr, nullptr, nullptr, 0) != hipSuccess) {
               gfail = true;
-              gx[d] = nullptr;
+              gxr = nullptr;
             }
             if (gr) (void)hipGraphDestroy(gr);
-          }
-          if (gfail) {
-            (void)hipGetLastError();
-            for (auto& g2 : gx) if (g2) { (void)hipGraphExecDestroy(g2); g2 = nullptr; }
+            if (gfail) (void)hipGetLastError();
           }
         }
-        if (gx[parity]) HIPCHK(hipGraphLaunch(gx[parity], s));
-        else HIPCHK(enqueue(xin, xout));
+        if (gxr && parity == 0) {
+          HIPCHK(hipGraphLaunch(gxr, s));
+          launched += kBatchReplay;
+        } else {
+          HIPCHK(enqueue(parity ? bufB : bufA, parity ? bufA : bufB));
+          HIPCHK(readback());
+          parity ^= 1;
+          launched++;
+        }
         HIPCHK(hipStreamSynchronize(s));
-        parity ^= 1;
-        iters++;
         if (hc[1] > 0) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
         if (hc[0] == 0) break;
       }
       if (parity) std::swap(xa, xb);
+      // per-graph iteration counts from the device-side schedule
+      std::vector<mm::BatchState> hs((size_t)M);
+      HIPCHK(hipMemcpy(hs.data(), gst.p, sizeof(mm::BatchState) * (size_t)M, hipMemcpyDeviceToHost));
+      int32_t iters = 0, final_iters = 0, caps = 0;
+      int64_t updates = 0;
+      for (int32_t m = 0; m < M; ++m) {
+        iters = std::max(iters, hs[m].iters);
+        final_iters = std::max(final_iters, hs[m].final_iters);
+        caps += hs[m].cap_hit;
+        updates += (int64_t)(L.goff_h[m + 1] - L.goff_h[m]) * hs[m].iters;
+      }
       if (lvl < MM_MAX_LEVELS) {
         st.level_n[lvl] = nl;
         st.level_nnz[lvl] = L.g.nnz;
         st.level_khop[lvl] = kh.total;
         st.level_iters[lvl] = iters;
+        st.level_final_iters[lvl] = final_iters;
+        st.level_cap_hit[lvl] = caps;
+        st.level_tile_bits[lvl] = ts.built ? ts.tbits : 0;
+        st.level_group[lvl] = group_lvl > 0 ? group_lvl
+                                            : (ts.built ? (ts.sliced ? mm::kSlicedGroup : mm::tiled_group(ts))
+                                                        : mm::row_group(kh));
+        st.level_blocks[lvl] = ts.built ? (nb_lvl > 0 ? nb_lvl : mm::tiled_blocks(ts)) : 0;
       }
-      st.vertex_updates += (int64_t)nl * iters;
-      if (lvl == 0) st.finest_updates = (int64_t)nl * iters;
+      st.vertex_updates += updates;
+      if (lvl == 0) st.finest_updates = updates;
     }
     HIPCHK(hipMemcpyAsync(out_xy, xa.p, sizeof(float) * 2 * (size_t)n,
                           g->mem == MM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));

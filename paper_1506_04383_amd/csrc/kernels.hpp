@@ -153,12 +153,16 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
 // only, into the set's partial slots), then the combine of each row with the
 // far field F (x' and the relative-change sums).  Only the second needs F, so
 // the far field of the same iteration may run concurrently with the first.
+// gid/galpha (batches, may be null): alpha of each row's graph, < 0 for a
+// finished graph (its rows are copied by the combine).
 hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                                const float* xy, double alpha, double q, hipStream_t s,
-                               const float* alpha_dev = nullptr, int32_t group = 0, int32_t nb = 0);
+                               const float* alpha_dev = nullptr, int32_t group = 0, int32_t nb = 0,
+                               const int32_t* gid = nullptr, const float* galpha = nullptr);
 hipError_t sweep_tiled_combine(const TiledSet& ts, const float* rho, const float* xy,
                                const float* F, double alpha, float* xy_out, double* delta2_dev,
-                               hipStream_t s, const float* alpha_dev = nullptr);
+                               hipStream_t s, const float* alpha_dev = nullptr,
+                               const int32_t* gid = nullptr, const float* galpha = nullptr);
 // lanes per chunk (4, 8, 16) the heuristic picks; group = 0 above means this
 inline int32_t tiled_group(const TiledSet& ts) {
   return ts.avg_chunk >= 512 ? 16 : ts.avg_chunk >= 128 ? 8 : 4;

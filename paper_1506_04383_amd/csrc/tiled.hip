@@ -412,7 +412,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // distance scale (coarse levels); lut: the per-hop table (hop_entry).
 template <bool COARSE, bool Q0>
 __device__ __forceinline__ void sweep_block(const u32x4 bk, const float2* __restrict__ sx,
-                                            const float* __restrict__ ssc,
+                                            const float2* __restrict__ ssc,
                                             const float2* __restrict__ lut, const float2 xu,
                                             const float scu, const float alpha, const float q,
                                             float& px, float& py) {
@@ -428,7 +428,9 @@ __device__ __forceinline__ void sweep_block(const u32x4 bk, const float2* __rest
     const uint32_t xo = pk & 0xFFF8u;
     xv[q2] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(sx) + xo);
     lw[q2] = lut[pk & 7u];
-    if (COARSE) sc[q2] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(ssc) + (xo >> 1));
+    // sqrt c sits at the same 8-byte stride as the coordinates, so one
+    // address register serves both reads (different immediate offsets)
+    if (COARSE) sc[q2] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(ssc) + xo);
   }
   if (COARSE && Q0) {
     // coarse levels, q = 0: with g = h (sqrt c_u + sqrt c_v) scale = 1/wd and
@@ -502,7 +504,8 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_slot,
     const uint16_t* __restrict__ ent, const float2* __restrict__ xy,
     const float* __restrict__ sqrtc, float scale, float alpha, float q,
-    float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
+    float2* __restrict__ partial, const float* __restrict__ alpha_dev,
+    const int32_t* __restrict__ gid, const float* __restrict__ galpha) {
   // the tile's coordinates (and pre-scaled roots on coarse levels) in static
   // LDS at a fixed address, so an entry's high 13 bits address them directly
   // the per-hop table (hop_entry) sits at the start of the coordinate array
@@ -511,11 +514,12 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   __shared__ float2 slx[16 + T];
   float2* const lut = slx;
   float2* const sx = slx + 16;
-  __shared__ float ssc[COARSE ? T : 1];
+  __shared__ float2 ssc[COARSE ? T : 1];  // (sqrt c * scale, unused)
   __shared__ int32_t mblk[UNIT_CH + 1];   // first block of each chunk (absolute)
   __shared__ int32_t mslot[UNIT_CH];
   __shared__ float2 mxu[UNIT_CH];
   __shared__ float mscu[COARSE ? UNIT_CH : 1];
+  __shared__ float malpha[UNIT_CH];       // per-graph alpha of each chunk's row (batches)
   const int32_t tile = unit_tile[blockIdx.x];
   const int32_t c0 = unit_c0[blockIdx.x], c1 = unit_c0[blockIdx.x + 1];
   const int32_t nch = c1 - c0;
@@ -523,7 +527,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   const int32_t nv = min(T, n - v0);
   for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
     sx[i] = xy[v0 + i];
-    if (COARSE) ssc[i] = sqrtc[v0 + i] * scale;
+    if (COARSE) ssc[i] = make_float2(sqrtc[v0 + i] * scale, 0.f);
   }
   for (int32_t i = threadIdx.x; i <= nch; i += TS_T) {
     mblk[i] = (int32_t)(chunk_off[c0 + i] >> 3);
@@ -532,6 +536,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
       mslot[i] = chunk_slot[c0 + i];
       mxu[i] = xy[u];
       if (COARSE) mscu[i] = sqrtc[u] * scale;
+      if (galpha) malpha[i] = galpha[gid[u]];
     }
   }
   if (alpha_dev) alpha = *alpha_dev;
@@ -539,6 +544,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
     lut[threadIdx.x] = hop_entry<COARSE, Q0>(threadIdx.x);
   }
   __syncthreads();
+  const float alpha0 = alpha;
   const int gl = threadIdx.x % G, gi = threadIdx.x / G;
   constexpr int NG = TS_T / G;
   const u32x4* __restrict__ ent4 = reinterpret_cast<const u32x4*>(ent);
@@ -554,6 +560,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
   }
   float2 xu = ci < nch ? mxu[ci] : make_float2(0.f, 0.f);
   float scu = (COARSE && ci < nch) ? mscu[ci] : 0.f;
+  if (galpha) alpha = ci < nch ? malpha[ci] : alpha0;
   float px = 0.f, py = 0.f;
   auto run = [&](const u32x4 bk) {
     sweep_block<COARSE, Q0>(bk, sx, ssc, lut, xu, scu, alpha, q, px, py);
@@ -596,6 +603,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_tiled(
         if (ci < nch) {
           xu = mxu[ci];
           if (COARSE) scu = mscu[ci];
+          if (galpha) alpha = malpha[ci];
         }
       }
     }
@@ -628,19 +636,20 @@ __global__ __launch_bounds__(TS_T) void k_sweep_sliced(
     const int32_t* __restrict__ slice_c0, const int32_t* __restrict__ chunk_row,
     const int32_t* __restrict__ chunk_slot, const uint16_t* __restrict__ ent,
     const float2* __restrict__ xy, const float* __restrict__ sqrtc, float scale, float alpha,
-    float q, float2* __restrict__ partial, const float* __restrict__ alpha_dev) {
+    float q, float2* __restrict__ partial, const float* __restrict__ alpha_dev,
+    const int32_t* __restrict__ gid, const float* __restrict__ galpha) {
   constexpr int32_t T = 1 << TB;
   __shared__ float2 slx[16 + T];  // hop table, then the tile's coordinates
   float2* const lut = slx;
   float2* const sx = slx + 16;
-  __shared__ float ssc[COARSE ? T : 1];
+  __shared__ float2 ssc[COARSE ? T : 1];  // (sqrt c * scale, unused)
   const int32_t tile = unit_tile[blockIdx.x];
   const int32_t s0 = unit_s0[blockIdx.x], s1 = unit_s0[blockIdx.x + 1];
   const int32_t v0 = tile * T;
   const int32_t nv = min(T, n - v0);
   for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
     sx[i] = xy[v0 + i];
-    if (COARSE) ssc[i] = sqrtc[v0 + i] * scale;
+    if (COARSE) ssc[i] = make_float2(sqrtc[v0 + i] * scale, 0.f);
   }
   if (alpha_dev) alpha = *alpha_dev;
   if (threadIdx.x < 16) {
@@ -660,6 +669,8 @@ __global__ __launch_bounds__(TS_T) void k_sweep_sliced(
     const int32_t row = chunk_row[c];
     const float2 xu = xy[row];
     const float scu = COARSE ? sqrtc[row] * scale : 0.f;
+    // batches: the alpha of the row's graph (a lane-varying value)
+    const float al = galpha ? galpha[gid[row]] : alpha;
     // the slice's blocks from a wave-uniform base; a lane's block j sits
     // 64 j + l blocks beyond it (32-bit byte offsets within the slice).  Loads
     // past the slice's last row re-read that row (in bounds, never used), so
@@ -679,13 +690,13 @@ __global__ __launch_bounds__(TS_T) void k_sweep_sliced(
       for (int b = 0; b < NB; ++b) bb[b] = ld(j + NB + b);
 #pragma unroll
       for (int b = 0; b < NB; ++b)
-        if (j + b < h) sweep_block<COARSE, Q0>(ba[b], sx, ssc, lut, xu, scu, alpha, q, px, py);
+        if (j + b < h) sweep_block<COARSE, Q0>(ba[b], sx, ssc, lut, xu, scu, al, q, px, py);
       if (j + NB >= h) break;
 #pragma unroll
       for (int b = 0; b < NB; ++b) ba[b] = ld(j + 2 * NB + b);
 #pragma unroll
       for (int b = 0; b < NB; ++b)
-        if (j + NB + b < h) sweep_block<COARSE, Q0>(bb[b], sx, ssc, lut, xu, scu, alpha, q, px, py);
+        if (j + NB + b < h) sweep_block<COARSE, Q0>(bb[b], sx, ssc, lut, xu, scu, al, q, px, py);
     }
     if (lv) partial[chunk_slot[c]] = make_float2(px, py);
   }
@@ -700,14 +711,21 @@ __global__ __launch_bounds__(CB_T) void k_combine(int32_t n, const int64_t* __re
                                                   const float2* __restrict__ F, float alpha,
                                                   float2* __restrict__ out,
                                                   double2* __restrict__ dpart,
-                                                  const float* __restrict__ alpha_dev) {
+                                                  const float* __restrict__ alpha_dev,
+                                                  const int32_t* __restrict__ gid,
+                                                  const float* __restrict__ galpha) {
   if (alpha_dev) alpha = *alpha_dev;
   constexpr int RPB = CB_T / CB_G;
   __shared__ double2 red[RPB];
   const int gl = threadIdx.x % CB_G, gi = threadIdx.x / CB_G;
   const int32_t u = blockIdx.x * RPB + gi;
   double2 dd = make_double2(0.0, 0.0);
-  if (u < n) {
+  // batches: each graph has its own alpha; a negative one marks a finished
+  // graph, whose coordinates are carried over unchanged
+  const float al = (galpha && u < n) ? galpha[gid[u]] : alpha;
+  if (u < n && al < 0.f) {
+    if (gl == 0) out[u] = xy[u];
+  } else if (u < n) {
     float px = 0.f, py = 0.f;
     for (int64_t s = rc_ptr[u] + gl; s < rc_ptr[u + 1]; s += CB_G) {
       const float2 p = partial[s];
@@ -721,8 +739,8 @@ __global__ __launch_bounds__(CB_T) void k_combine(int32_t n, const int64_t* __re
       const float r = rho[u];
       // the partial sums are relative to x_u (see the sweep)
       float2 xn;
-      xn.x = xu.x + (px + alpha * fu.x) / r;
-      xn.y = xu.y + (py + alpha * fu.y) / r;
+      xn.x = xu.x + (px + al * fu.x) / r;
+      xn.y = xu.y + (py + al * fu.y) / r;
       out[u] = xn;
       const double ex = (double)xn.x - (double)xu.x, ey = (double)xn.y - (double)xu.y;
       dd.x = ex * ex + ey * ey;
@@ -948,7 +966,8 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
 
 hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                                const float* xy, double alpha, double q, hipStream_t s,
-                               const float* alpha_dev, int32_t group, int32_t nb) {
+                               const float* alpha_dev, int32_t group, int32_t nb,
+                               const int32_t* gid, const float* galpha) {
   const bool coarse = level > 0 && sqrtc != nullptr;
   const bool q0 = q == 0.0;
   if (ts.tbits < 11 || ts.tbits > 13) return hipErrorInvalidValue;
@@ -959,7 +978,7 @@ hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* s
 #define MM_TS(GG, NBV, TBV, C, Q)                                                               \
   k_sweep_tiled<GG, NBV, TBV, C, Q><<<ts.nunits, TS_T, 0, s>>>(                                 \
       ts.n, ts.unit_c0, ts.unit_tile, ts.chunk_off, ts.chunk_row, ts.chunk_slot, ts.ent,         \
-      (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, alpha_dev)
+      (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, alpha_dev, gid, galpha)
 #define MM_TST(GG, NBV, TBV)                                                                   \
   do {                                                                                         \
     if (coarse) { if (q0) MM_TS(GG, NBV, TBV, true, true); else MM_TS(GG, NBV, TBV, true, false); } \
@@ -979,7 +998,7 @@ hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* s
   k_sweep_sliced<NBV, TBV, C, Q><<<ts.nunits, TS_T, 0, s>>>(                                     \
       ts.n, ts.unit_c0, ts.unit_tile, ts.slice_base, ts.slice_h, ts.slice_c0, ts.chunk_row,      \
       ts.chunk_slot, ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, \
-      alpha_dev)
+      alpha_dev, gid, galpha)
 #define MM_SLT(NBV, TBV)                                                                       \
   do {                                                                                         \
     if (coarse) { if (q0) MM_SL(NBV, TBV, true, true); else MM_SL(NBV, TBV, true, false); }    \
@@ -1015,13 +1034,14 @@ hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* s
 
 hipError_t sweep_tiled_combine(const TiledSet& ts, const float* rho, const float* xy,
                                const float* F, double alpha, float* xy_out, double* delta2_dev,
-                               hipStream_t s, const float* alpha_dev) {
+                               hipStream_t s, const float* alpha_dev, const int32_t* gid,
+                               const float* galpha) {
   const int32_t ncb = (ts.n + CB_T / CB_G - 1) / (CB_T / CB_G);
   DevBuf& dpart = const_cast<TiledSet&>(ts).b_dpart;
   if (dpart.bytes < sizeof(double2) * (size_t)ncb) MM_TRY(dpart.alloc(sizeof(double2) * (size_t)ncb, s));
   k_combine<<<ncb, CB_T, 0, s>>>(ts.n, ts.rc_ptr, ts.b_partial.as<float2>(), rho,
                                 (const float2*)xy, (const float2*)F, (float)alpha,
-                                (float2*)xy_out, dpart.as<double2>(), alpha_dev);
+                                (float2*)xy_out, dpart.as<double2>(), alpha_dev, gid, galpha);
   k_sum_parts2<<<1, 1024, 0, s>>>(dpart.as<double2>(), ncb, delta2_dev);
   return hipGetLastError();
 }
