@@ -14,11 +14,13 @@
 // expansion of sum_v 1/conj(z - w_v).
 //
 // MLP 8 -> 64 -> 64 -> 2, ReLU, weights rounded to BF16, FP32 accumulation
-// on the matrix cores (v_mfma_f32_16x16x16_bf16).  Rows are evaluated 16 at
-// a time in transposed form: layer l computes H_l^T = W_l H_{l-1}^T, so the
-// accumulator layout of one layer (lane: unit 4(l/16)+j of a 16-unit block,
-// row l%16) is exactly the B-operand layout of the next and activations
-// never leave registers.
+// on the matrix cores.  Rows are evaluated 16 at a time in transposed form:
+// layer l computes H_l^T = W_l H_{l-1}^T, so the accumulator layout of one
+// layer (lane: unit 4(l/16)+j of a 16-unit block, row l%16) is the B-operand
+// layout of the next and activations never leave registers.  Inference (the
+// traversal, mlp_forward) uses gfx950's 16x16x32 BF16 product on pairs of
+// such blocks (mlp_blocks32); training keeps the 16x16x16 form, whose
+// operand layouts its backward products share.
 //
 // Parameters (FP32, packed): W1[64][8], b1[64], W2[64][64], b2[64], W3[2][64],
 // b3[2] -- 4866 values.
@@ -40,11 +42,17 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIN, OFF_W2 = OFF_B1 + NH,
               NPARAM = OFF_B3 + NOUT;
 static_assert(NPARAM == kMlpParams, "parameter count");
 
-// FP32 -> BF16, round to nearest even (inputs are finite).
-__device__ inline uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// FP32 -> BF16, round to nearest even (inputs are finite): gfx950's
+// v_cvt_pk_bf16_f32, two values per instruction in the packed form.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ inline uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+// four values as one BF16 operand fragment
+__device__ inline v4s f2bf4(float a, float b, float c, float d) {
+  return __builtin_bit_cast(v4s, (uint2){f2bf2(a, b), f2bf2(c, d)});
 }
 
 __device__ inline v4f mfma(v4s a, v4s b, v4f c) {
@@ -83,6 +91,95 @@ __device__ void stage_weights(const float* __restrict__ w, MlpLds& L) {
 
 __device__ inline v4s ld4(const uint16_t* p) { return *reinterpret_cast<const v4s*>(p); }
 
+// gfx950's 16x16x32 BF16 product: A lane l = row l%16, K 8(l/16)..+7; B lane
+// l = column l%16, the same K; C/D as in the 16x16x16 form.  Used for
+// inference.  K is taken in a permuted order: K slot 8g+j (j < 4) is input
+// unit 32p + 4g + j and slot 8g+4+j is unit 32p + 16 + 4g + j, so a pair of
+// accumulator blocks of the previous layer (lane: units 4g..4g+3 of each) is
+// the B fragment as it is, and the A fragment is two 4-value loads of the
+// weight row.
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ inline v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ inline v8s cat8(v4s lo, v4s hi) {
+  return v8s{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+// writes the low (hi = 0) or high half of a fragment
+__device__ inline void set_half(v8s& v, int hi, v4s h) {
+  if (hi) { v[4] = h[0]; v[5] = h[1]; v[6] = h[2]; v[7] = h[3]; }
+  else { v[0] = h[0]; v[1] = h[1]; v[2] = h[2]; v[3] = h[3]; }
+}
+
+// Forward pass of up to four 16-row blocks on the 16x16x32 product,
+// interleaved layer by layer (their matrix-core chains are independent).
+// x[b]: lane l < 16 holds the 8 features of row l of block b (others zero).
+// Lanes 0-15 return h of row l of block b in o[b] (.x, .y).
+__device__ inline void mlp_blocks32(const MlpLds& L, const v8s* x, int nb, v4f* o) {
+  const int l = lane_id(), r = l & 15, g = l >> 4;
+  // activations held directly as B fragments: a1[b][p] = blocks 2p, 2p+1
+  v8s a1[4][2], a2[4][2];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    // layer 1: K = the 8 features (slots of lane group 0), zero elsewhere
+    const v8s w = g == 0 ? *reinterpret_cast<const v8s*>(&L.w1[(ob * 16 + r) * 16])
+                         : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+    float bias[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias[j] = L.b1[ob * 16 + 4 * g + j];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b < nb) {
+        const v4f c = mfma32(w, x[b], v4f{0.f, 0.f, 0.f, 0.f});
+        const v4s h = f2bf4(fmaxf(c[0] + bias[0], 0.f), fmaxf(c[1] + bias[1], 0.f),
+                            fmaxf(c[2] + bias[2], 0.f), fmaxf(c[3] + bias[3], 0.f));
+        set_half(a1[b][ob >> 1], ob & 1, h);
+      }
+    }
+  }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    v4f c[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kp = 0; kp < 2; ++kp) {
+      const uint16_t* wr = &L.w2[(ob * 16 + r) * NH + kp * 32 + 4 * g];
+      const v8s w = cat8(ld4(wr), ld4(wr + 16));
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (b < nb) c[b] = mfma32(w, a1[b][kp], c[b]);
+    }
+    float bias[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias[j] = L.b2[ob * 16 + 4 * g + j];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < nb)
+        set_half(a2[b][ob >> 1], ob & 1,
+                 f2bf4(fmaxf(c[b][0] + bias[0], 0.f), fmaxf(c[b][1] + bias[1], 0.f),
+                       fmaxf(c[b][2] + bias[2], 0.f), fmaxf(c[b][3] + bias[3], 0.f)));
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) o[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kp = 0; kp < 2; ++kp) {
+    const uint16_t* wr = &L.w3[r * NH + kp * 32 + 4 * g];
+    const v8s w = cat8(ld4(wr), ld4(wr + 16));
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < nb) o[b] = mfma32(w, a2[b][kp], o[b]);
+  }
+  const float b30 = L.b3[0], b31 = L.b3[1];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    o[b][0] += b30;
+    o[b][1] += b31;
+  }
+}
+
 // Forward pass of 16 rows.  x: B operand of the features (lane l < 32: row
 // l%16, features 4(l/16)..+3; other lanes zero).  Lanes 0-15 return h of row
 // l in (.x, .y).  KEEP stores the pre-activations and BF16 activations in
@@ -95,13 +192,9 @@ __device__ inline v4f mlp16(const MlpLds& L, v4s x, v4f* z1, v4s* h1, v4f* z2, v
   for (int ob = 0; ob < 4; ++ob) {
     v4f c = {0.f, 0.f, 0.f, 0.f};
     c = mfma(ld4(&L.w1[(ob * 16 + r) * 16 + 4 * g]), x, c);
-    v4s hb;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float z = c[j] + L.b1[ob * 16 + 4 * g + j];
-      c[j] = z;
-      hb[j] = (short)f2bf(fmaxf(z, 0.f));
-    }
+    for (int j = 0; j < 4; ++j) c[j] += L.b1[ob * 16 + 4 * g + j];
+    const v4s hb = f2bf4(fmaxf(c[0], 0.f), fmaxf(c[1], 0.f), fmaxf(c[2], 0.f), fmaxf(c[3], 0.f));
     a1[ob] = hb;
     if (KEEP) { z1[ob] = c; h1[ob] = hb; }
   }
@@ -110,13 +203,9 @@ __device__ inline v4f mlp16(const MlpLds& L, v4s x, v4f* z1, v4s* h1, v4f* z2, v
     v4f c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) c = mfma(ld4(&L.w2[(ob * 16 + r) * NH + kb * 16 + 4 * g]), a1[kb], c);
-    v4s hb;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float z = c[j] + L.b2[ob * 16 + 4 * g + j];
-      c[j] = z;
-      hb[j] = (short)f2bf(fmaxf(z, 0.f));
-    }
+    for (int j = 0; j < 4; ++j) c[j] += L.b2[ob * 16 + 4 * g + j];
+    const v4s hb = f2bf4(fmaxf(c[0], 0.f), fmaxf(c[1], 0.f), fmaxf(c[2], 0.f), fmaxf(c[3], 0.f));
     a2[ob] = hb;
     if (KEEP) { z2[ob] = c; h2[ob] = hb; }
   }
@@ -258,65 +347,17 @@ __device__ inline void flush_rows(const MlpLds& L, const QRow* ring, int qh, int
   asm volatile("" ::: "memory");
   const int l = lane_id(), r = l & 15, g = l >> 4;
   const int nb = (rows + 15) >> 4;
-  v4s x[4];
+  v8s x[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    x[b] = v4s{0, 0, 0, 0};
-    if (b < nb && g < 2 && 16 * b + r < rows) {
+    x[b] = v8s{0, 0, 0, 0, 0, 0, 0, 0};
+    if (b < nb && g == 0 && 16 * b + r < rows) {
       const QRow& e = ring[(qh + 16 * b + r) & (QCAP - 1)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) x[b][j] = (short)f2bf(e.f[4 * g + j]);
+      x[b] = cat8(f2bf4(e.f[0], e.f[1], e.f[2], e.f[3]), f2bf4(e.f[4], e.f[5], e.f[6], e.f[7]));
     }
-  }
-  v4s a1[4][4], a2[4][4];
-#pragma unroll
-  for (int ob = 0; ob < 4; ++ob) {
-    const v4s w = ld4(&L.w1[(ob * 16 + r) * 16 + 4 * g]);
-    float bias[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bias[j] = L.b1[ob * 16 + 4 * g + j];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      if (b < nb) {
-        const v4f c = mfma(w, x[b], v4f{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a1[b][ob][j] = (short)f2bf(fmaxf(c[j] + bias[j], 0.f));
-      }
-    }
-  }
-#pragma unroll
-  for (int ob = 0; ob < 4; ++ob) {
-    v4f c[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) c[b] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const v4s w = ld4(&L.w2[(ob * 16 + r) * NH + kb * 16 + 4 * g]);
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (b < nb) c[b] = mfma(w, a1[b][kb], c[b]);
-    }
-    float bias[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bias[j] = L.b2[ob * 16 + 4 * g + j];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (b < nb) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a2[b][ob][j] = (short)f2bf(fmaxf(c[b][j] + bias[j], 0.f));
-      }
   }
   v4f o[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) o[b] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) {
-    const v4s w = ld4(&L.w3[r * NH + kb * 16 + 4 * g]);
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (b < nb) o[b] = mfma(w, a2[b][kb], o[b]);
-  }
-  const float b30 = L.b3[0], b31 = L.b3[1];
+  mlp_blocks32(L, x, nb, o);
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     if (b >= nb) break;
@@ -324,7 +365,7 @@ __device__ inline void flush_rows(const MlpLds& L, const QRow* ring, int qh, int
     int32_t tl = -1;
     if (g == 0 && 16 * b + r < rows) {
       const QRow& e = ring[(qh + 16 * b + r) & (QCAP - 1)];
-      const float h0 = o[b][0] + b30, h1 = o[b][1] + b31;
+      const float h0 = o[b][0], h1 = o[b][1];
       ax = h0 * e.kex - h1 * e.key;
       ay = h0 * e.key + h1 * e.kex;
       tl = e.lane;
@@ -339,7 +380,7 @@ __device__ inline void flush_rows(const MlpLds& L, const QRow* ring, int qh, int
   }
 }
 
-__global__ __launch_bounds__(64 * TL_WAVES) void k_traverse_learned(
+__global__ __launch_bounds__(64 * TL_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_traverse_learned(
     const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np,
     const Cell* __restrict__ cell, const float* __restrict__ xsx, const float* __restrict__ xsy,
     const uint2* __restrict__ ixy, const int32_t* __restrict__ order, int32_t n, double theta2,
@@ -527,11 +568,16 @@ __global__ __launch_bounds__(64 * MW) void k_mlp_forward(const float* __restrict
   for (int64_t b = (int64_t)blockIdx.x * MW + (threadIdx.x >> 6); b < nblk;
        b += (int64_t)gridDim.x * MW) {
     const int64_t row = b * 16 + r;
-    const v4f o = mlp16<false>(L, feat_frag(feat, row, row < count), nullptr, nullptr, nullptr,
-                               nullptr);
+    v8s x = v8s{0, 0, 0, 0, 0, 0, 0, 0};
     if (l < 16 && row < count) {
-      out[2 * row] = o[0];
-      out[2 * row + 1] = o[1];
+      const float* f = feat + 8 * row;
+      x = cat8(f2bf4(f[0], f[1], f[2], f[3]), f2bf4(f[4], f[5], f[6], f[7]));
+    }
+    v4f o[4];
+    mlp_blocks32(L, &x, 1, o);
+    if (l < 16 && row < count) {
+      out[2 * row] = o[0][0];
+      out[2 * row + 1] = o[0][1];
     }
   }
 }

@@ -157,6 +157,47 @@ def test_full_coarsen_and_coarse_sweep(orc, mm, full):
     _sweep_rows_check(orc, mm, ctx, G.row_ptr, G.col, xc, G.c, 1, (12, SLICED, 4))
 
 
+def test_full_hierarchy_every_level(orc, mm, full):
+    """The whole hierarchy of the bench workload (Sec. 3.1, b = 2, f = 20,
+    down to <= 100 vertices): every contraction attempt of the oracle's
+    driver repeated on the GPU from the same fine graph with the same U and
+    h -- cluster ids, coarse CSR, node and edge weights bit-exact for every
+    accepted level, coarse sizes equal for attempts the 10% rule rejected --
+    and the library's own driver (mm_layout) building the same level sizes."""
+    g, ctx, dg, x = full
+    print("[full hierarchy] oracle driver", flush=True)
+    p = orc.Params(k=2, theta=0.5, alpha_decay=0.5, coarsest_n=100, seed=1)
+    trace = []
+    levels, clusters, info = orc.hierarchy(orc.Level(g.row_ptr, g.col), p, trace)
+    print(f"  {len(levels) - 1} contractions, {len(trace)} attempts: "
+          f"{[lv.n for lv in levels]}", flush=True)
+    assert len(levels) - 1 >= 10
+    accepted = 0
+    last = {t["h"]: i for i, t in enumerate(trace)}
+    for i, t in enumerate(trace):
+        h = t["h"]
+        fine = levels[h - 1]
+        dfine = ctx.graph(fine.row_ptr, fine.col, fine.c, fine.w)
+        cl, (rp, col, cw, ew), rounds, moves = mm.coarsen(ctx, dfine, t["U"], p.lp_rounds,
+                                                          p.seed, h)
+        assert rp.size - 1 == t["n"], (h, t)
+        is_final = i == last[h] and h <= len(levels) - 1  # the attempt the driver kept
+        if is_final:
+            G = levels[h]
+            assert np.array_equal(cl.cpu().numpy(), clusters[h - 1]), h
+            assert np.array_equal(rp, G.row_ptr) and np.array_equal(col, G.col), h
+            assert np.array_equal(cw, G.c) and np.array_equal(ew, G.w), h
+            accepted += 1
+        print(f"  h={h} U={t['U']:.1f} n={t['n']} rounds={rounds} "
+              f"{'bit-exact' if is_final else 'rejected attempt, size equal'}", flush=True)
+    assert accepted == len(levels) - 1
+    print("[full hierarchy] library driver (one layout)", flush=True)
+    _, st = mm.layout(ctx, dg, mm.Params(k=2, theta=0.5, alpha_decay=0.5, coarsest_n=100,
+                                         seed=1, validate=0, max_final_iters=2))
+    lib_n = [l["n"] for l in sorted(st["per_level"], key=lambda r: r["level"])]
+    assert lib_n == [lv.n for lv in levels]
+
+
 def _bfs_row(rp, col, u, k):
     """S_k(u) by definition: vertices at hop 1..k from u, sorted by (hop, id)."""
     seen = {int(u)}
