@@ -1747,7 +1747,7 @@ mm_status mm_layout_batch(mm_context* ctx, int32_t G, const int64_t* graph_off, 
           MM_TRY(mm::sweep_tiled_partial(ts, lvl, sqrtc, p->coarse_dist_scale, xin, 0.0, p->q, s,
                                          nullptr, group_lvl, nb_lvl, gidp, galpha.as<float>()));
           MM_TRY(mm::sweep_tiled_combine(ts, rho.as<float>(), xin, F.as<float>(), 0.0, xout,
-                                         d2.as<double>(), s, nullptr, gidp, galpha.as<float>()));
+                                         nullptr, s, nullptr, gidp, galpha.as<float>()));
         } else {
           MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
                            xout, d2.as<double>(), s, gidp, galpha.as<float>(), nullptr,

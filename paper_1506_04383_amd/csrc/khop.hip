@@ -26,6 +26,7 @@ constexpr int KS_CAP = 1024;     // list capacity per wave (entries)
 constexpr int KS_WAVES = 2;      // waves per block
 constexpr int KB_T = 512;        // threads per big-row block
 constexpr int KB_NW = KB_T / 64;
+constexpr int KB_U = 4;          // frontier vertices per wave step in the bitmap kernel
 constexpr int KB_LDS_WORDS = 19968;  // 2 x this many bitmap words fit in a CU's LDS
 
 __device__ inline void wave_sync() {
@@ -197,19 +198,35 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     __syncthreads();
     const uint32_t* kept = LOAD ? bmkeep + (size_t)r * (size_t)W : nullptr;
     for (int h = 2; h <= k; ++h) {
-      // mark neighbours of the frontier not yet visited
-      for (int32_t i = wv; i < flen && !LOAD; i += KB_NW) {
-        int32_t x = F[i];
-        int32_t b0 = rp[x], b1 = rp[x + 1];
-        for (int32_t e = b0 + l; e < b1; e += 64) {
-          int32_t v = col[e];
-          uint32_t bit = 1u << (v & 31);
-          if (ONE) {
-            if (!(NEW[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
-          } else {
-            if (!(VIS[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
-          }
+      // mark neighbours of the frontier not yet visited.  A wave takes KB_U
+      // frontier vertices at a time and issues their row bounds and first 64
+      // neighbour loads before marking any, so KB_U dependent load chains are
+      // in flight per wave instead of one (most frontier vertices have fewer
+      // than 64 neighbours)
+      auto mark = [&](int32_t v) {
+        const uint32_t bit = 1u << (v & 31);
+        if (ONE) {
+          if (!(NEW[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
+        } else {
+          if (!(VIS[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
         }
+      };
+      for (int32_t i0 = wv * KB_U; i0 < flen && !LOAD; i0 += KB_NW * KB_U) {
+        int32_t b0[KB_U], b1[KB_U], v0[KB_U];
+#pragma unroll
+        for (int uu = 0; uu < KB_U; ++uu) {
+          const int32_t x = i0 + uu < flen ? F[i0 + uu] : -1;
+          b0[uu] = x >= 0 ? rp[x] : 0;
+          b1[uu] = x >= 0 ? rp[x + 1] : 0;
+        }
+#pragma unroll
+        for (int uu = 0; uu < KB_U; ++uu) v0[uu] = b0[uu] + l < b1[uu] ? col[b0[uu] + l] : -1;
+#pragma unroll
+        for (int uu = 0; uu < KB_U; ++uu)
+          if (v0[uu] >= 0) mark(v0[uu]);
+#pragma unroll
+        for (int uu = 0; uu < KB_U; ++uu)
+          for (int32_t e = b0[uu] + 64 + l; e < b1[uu]; e += 64) mark(col[e]);
       }
       __syncthreads();
       if (ONE && !LOAD) {
