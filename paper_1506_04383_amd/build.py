@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmulment.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["prims.hip", "khop.hip", "farfield.hip", "clusterfar.hip", "learned.hip", "sweep.hip",
-           "tiled.hip", "coarsen.hip", "layout.hip", "batch.hip", "objective.hip", "noalloc.hip",
+           "tiled.hip", "tilemajor.hip", "coarsen.hip", "layout.hip", "batch.hip", "objective.hip", "noalloc.hip",
            "validate.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -145,6 +145,9 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
 // configurations (one lane per chunk, 64 chunks per wave)
 constexpr int32_t kSlicedGroup = 64;
 constexpr int32_t kTileBits = 13;  // tiled sets need k <= 7 and tbits <= 13
+constexpr int32_t kTiledMaxTiles = 4096;  // tiles per level (per-tile counters in LDS)
+constexpr int32_t kUnitChunks = 768;      // chunks per work unit (consecutive layout)
+constexpr int32_t kUnitSlices = 64;       // slices per work unit (sliced layout)
 hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                        const float* rho, const float* xy, const float* F, double alpha, double q,
                        float* xy_out, double* delta2_dev, hipStream_t s,

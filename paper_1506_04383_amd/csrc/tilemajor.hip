@@ -1,0 +1,581 @@
+// Tile-major copy of the stress sets for the LDS-tiled sweep (tiled.hip):
+// the canonical k-hop sets (sorted by (hop, v) per row) are re-laid per
+// (row, tile) chunk, 16 bits per entry ((v - tile * T) << 3 | hop), chunks
+// ordered by tile and, within a tile, by decreasing length; either
+// consecutively (work units of <= kUnitChunks chunks) or in the sliced
+// layout (slices of 64 chunks, block j of chunk i at slice_base + 64 j + i;
+// work units of <= kUnitSlices slices).  Also rho_u = sum over S(u) of w_uv.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace {
+
+constexpr int TB_WAVES = 4;          // waves per block of the conversion kernels
+constexpr int TB_MAXW = kTiledMaxTiles / 32;
+constexpr int RU = 4;                // 64-entry steps loaded at once per wave (conversion)
+constexpr int32_t UNIT_CH = kUnitChunks;
+constexpr int32_t UNIT_S = kUnitSlices;
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// wave inclusive max-scan
+__device__ inline int32_t wave_incl_max(int32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t w = __shfl_up(v, o, 64);
+    if (l >= o) v = max(v, w);
+  }
+  return v;
+}
+
+// K1: number of distinct tiles per row
+// Distinct tiles per row (the row's chunk count); with RHO also
+// rho_u = sum over S(u) of w_uv in exactly k_rho's order (per hop segment,
+// lane-strided, then a wave sum), so both give the same bits.
+template <bool RHO>
+__global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(
+    int32_t n, int32_t k, int32_t tbits, int32_t ntw, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ hend, const int32_t* __restrict__ nbr,
+    const float* __restrict__ sqrtc, float scale, int32_t* __restrict__ nch,
+    float* __restrict__ rho) {
+  __shared__ uint32_t tbm[TB_WAVES][TB_MAXW];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t u = blockIdx.x * TB_WAVES + w;
+  if (u >= n) return;
+  uint32_t* bm = tbm[w];
+  for (int i = l; i < ntw; i += 64) bm[i] = 0u;
+  wave_sync();
+  const int64_t beg = off[u];
+  const float su = (RHO && sqrtc) ? sqrtc[u] : 0.f;
+  float r = 0.f;
+  int32_t seg0 = 0;
+  for (int h = 1; h <= k; ++h) {
+    const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    // RU 64-entry steps per pass, their loads (and sqrt c gathers) issued
+    // before any is used; each lane still takes its entries in order
+    for (int32_t i0 = seg0; i0 < seg1; i0 += 64 * RU) {
+      int32_t vv[RU];
+      float sv[RU];
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        const int32_t i = i0 + 64 * uu + l;
+        vv[uu] = i < seg1 ? nbr[beg + i] : 0;
+      }
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu)
+        sv[uu] = (RHO && sqrtc && i0 + 64 * uu + l < seg1) ? sqrtc[vv[uu]] : 0.f;
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        if (i0 + 64 * uu + l >= seg1) break;
+        const int32_t v = vv[uu];
+        const int32_t t = v >> tbits;
+        const uint32_t bit = 1u << (t & 31);
+        if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+        if (RHO && sqrtc) {
+          const float d = (float)h * (su + sv[uu]) * scale;
+          r += 1.f / (d * d);
+        }
+      }
+    }
+    seg0 = seg1;
+  }
+  wave_sync();
+  int32_t c = 0;
+  for (int i = l; i < ntw; i += 64) c += __popc(bm[i]);
+  c = wave_sum(c);
+  if (l == 0) nch[u] = c;
+  if (RHO) {
+    if (sqrtc) {
+      r = wave_sum(r);
+      if (l == 0) rho[u] = r;
+    } else if (l == 0) {
+      int32_t prev = 0;
+      float rr = 0.f;
+      for (int h = 1; h <= k; ++h) {
+        const int32_t e = hend[(int64_t)u * k + h - 1];
+        rr += (float)(e - prev) / (float)(h * h);
+        prev = e;
+      }
+      rho[u] = rr;
+    }
+  }
+}
+
+// K3 / K6: per row, per tile runs.  FILL=false: chunk sizes (row-major
+// slots).  FILL=true: write the 16-bit entries; with BASE the start of every
+// touched tile's chunk is looked up once per row (an LDS table of int64) so
+// that the entry loop has no dependent global loads.  The row's entries are
+// loaded RU 64-entry steps at a time.
+template <bool FILL, bool BASE>
+__global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
+    int32_t n, int32_t k, int32_t tbits, int32_t ntiles, int32_t ntw,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ hend,
+    const int32_t* __restrict__ nbr, const int64_t* __restrict__ rc_ptr,
+    int32_t* __restrict__ cm_tile, int32_t* __restrict__ cm_size, int32_t* __restrict__ cm_row,
+    const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
+    uint16_t* __restrict__ ent) {
+  // per wave, sized by the tile count: tile bitmap (ntw words), its popcount
+  // prefix (ntw), per-tile counters (ntiles), with BASE the chunk starts
+  // (ntiles int64, 8-byte aligned)
+  extern __shared__ uint32_t tb_dyn[];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t u = blockIdx.x * TB_WAVES + w;
+  if (u >= n) return;
+  const size_t per = ((2 * (size_t)ntw + (size_t)ntiles + 1) & ~(size_t)1) +
+                     (BASE ? 2 * (size_t)ntiles : 0);
+  uint32_t* bm = tb_dyn + (size_t)w * per;
+  int32_t* pf = reinterpret_cast<int32_t*>(bm + ntw);
+  int32_t* ct = pf + ntw;
+  int64_t* base = BASE ? reinterpret_cast<int64_t*>(bm + ((2 * (size_t)ntw + (size_t)ntiles + 1) &
+                                                          ~(size_t)1))
+                       : nullptr;
+  const int64_t beg = off[u], endr = off[u + 1];
+  for (int i = l; i < ntw; i += 64) bm[i] = 0u;
+  wave_sync();
+  for (int64_t e0 = beg; e0 < endr; e0 += 64 * RU) {
+    int32_t vv[RU];
+#pragma unroll
+    for (int uu = 0; uu < RU; ++uu) {
+      const int64_t e = e0 + 64 * uu + l;
+      vv[uu] = e < endr ? nbr[e] : 0;
+    }
+#pragma unroll
+    for (int uu = 0; uu < RU; ++uu) {
+      if (e0 + 64 * uu + l >= endr) break;
+      const int32_t t = vv[uu] >> tbits;
+      const uint32_t bit = 1u << (t & 31);
+      if (!(bm[t >> 5] & bit)) atomicOr(&bm[t >> 5], bit);
+    }
+  }
+  wave_sync();
+  // zero the counters of touched tiles; popcount prefix over words
+  for (int i = l; i < ntw; i += 64) {
+    uint32_t b = bm[i];
+    while (b) { int j = __ffs(b) - 1; b &= b - 1; ct[(i << 5) + j] = 0; }
+  }
+  if (l == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < ntw; ++i) { pf[i] = run; run += __popc(bm[i]); }
+  }
+  wave_sync();
+  const int64_t rbase = rc_ptr[u];
+  if (FILL && BASE) {
+    for (int i = l; i < ntw; i += 64) {
+      uint32_t b = bm[i];
+      int32_t rank = pf[i];
+      while (b) {
+        const int j = __ffs(b) - 1;
+        b &= b - 1;
+        base[(i << 5) + j] = chunk_off[pos_of_slot[rbase + rank]];
+        rank++;
+      }
+    }
+    wave_sync();
+  }
+  int32_t seg0 = 0;
+  for (int h = 1; h <= k; ++h) {
+    const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    for (int32_t b0 = seg0; b0 < seg1; b0 += 64 * RU) {
+      int32_t vv[RU];
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        const int32_t i = b0 + 64 * uu + l;
+        vv[uu] = i < seg1 ? nbr[beg + i] : 0;
+      }
+#pragma unroll
+      for (int uu = 0; uu < RU; ++uu) {
+        const int32_t b = b0 + 64 * uu;
+        if (b >= seg1) break;  // wave-uniform
+        const int32_t i = b + l;
+        const bool valid = i < seg1;
+        const int32_t v = vv[uu];
+        const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
+        const int32_t tprev = __shfl_up(t, 1, 64);
+        const bool start = valid && (l == 0 || tprev != t);
+        const int32_t rs = wave_incl_max(start ? l : -1);
+        const int32_t tnext = __shfl_down(t, 1, 64);
+        const bool end = valid && (l == 63 || i + 1 >= seg1 || tnext != t);
+        if (FILL && valid) {
+          int64_t cbase;
+          if (BASE) {
+            cbase = base[t];
+          } else {
+            const int32_t rank = pf[t >> 5] + __popc(bm[t >> 5] & ((1u << (t & 31)) - 1u));
+            cbase = chunk_off[pos_of_slot[rbase + rank]];
+          }
+          const int64_t dst = cbase + ct[t] + (l - rs);
+          ent[dst] = (uint16_t)(((v & ((1 << tbits) - 1)) << 3) | h);
+        }
+        wave_sync();
+        if (end) ct[t] += l - rs + 1;
+        wave_sync();
+      }
+    }
+    seg0 = seg1;
+  }
+  if (!FILL) {
+    for (int i = l; i < ntw; i += 64) {
+      uint32_t bb = bm[i];
+      int32_t r = pf[i];
+      while (bb) {
+        int j = __ffs(bb) - 1;
+        bb &= bb - 1;
+        const int32_t t = (i << 5) + j;
+        cm_tile[rbase + r] = t;
+        cm_size[rbase + r] = ct[t];
+        cm_row[rbase + r] = u;
+        r++;
+      }
+    }
+  }
+}
+
+__global__ void k_gather_sorted_chunks(int64_t m, const int32_t* __restrict__ svals,
+                                       const int32_t* __restrict__ cm_size,
+                                       const int32_t* __restrict__ cm_row,
+                                       int32_t* __restrict__ ssize, int32_t* __restrict__ chunk_row,
+                                       int32_t* __restrict__ pos_of_slot) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int32_t s = svals[c];
+  ssize[c] = (cm_size[s] + 7) & ~7;  // chunks padded to 16-byte blocks (hop 0 = padding)
+  chunk_row[c] = cm_row[s];
+  pos_of_slot[s] = (int32_t)c;
+}
+
+__global__ void k_chunk_keys(int64_t m, const int32_t* __restrict__ cm_tile,
+                             const int32_t* __restrict__ cm_size, uint64_t* __restrict__ keys) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  keys[c] = ((uint64_t)(uint32_t)cm_tile[c] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)cm_size[c]);
+}
+__global__ void k_tile_first(int64_t m, const uint64_t* __restrict__ skey,
+                             int32_t* __restrict__ tile_first) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const uint32_t t = (uint32_t)(skey[c] >> 32);
+  if (c == 0 || (uint32_t)(skey[c - 1] >> 32) != t) tile_first[t] = (int32_t)c;
+}
+// unit starts: the first chunk of a tile, every UNIT_CH-th chunk after it,
+// and every chunk that begins a new span of emax entries (so that levels with
+// few, long chunks still give enough work units to fill the chip)
+__global__ void k_unit_flags(int64_t m, const uint64_t* __restrict__ skey,
+                             const int32_t* __restrict__ tile_first,
+                             const int64_t* __restrict__ chunk_off, int64_t emax,
+                             int32_t* __restrict__ flag) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int64_t tf = tile_first[skey[c] >> 32];
+  flag[c] = ((c - tf) % UNIT_CH == 0 || (c > tf && chunk_off[c] / emax != chunk_off[c - 1] / emax))
+                ? 1 : 0;
+}
+__global__ void k_unit_fill(int64_t m, const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                           const uint64_t* __restrict__ skey, int32_t* __restrict__ unit_c0,
+                           int32_t* __restrict__ unit_tile) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m || !flag[c]) return;
+  unit_c0[pos[c]] = (int32_t)c;
+  unit_tile[pos[c]] = (int32_t)(skey[c] >> 32);
+}
+__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+
+// Sliced layout.  Sorted chunk c has rank r = c - tile_first[tile] within its
+// tile; slices are the runs of 64 ranks.  flag[c] = 1 where a slice starts.
+__global__ void k_slice_flags(int64_t m, const uint64_t* __restrict__ skey,
+                              const int32_t* __restrict__ tile_first, int32_t* __restrict__ flag) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int64_t r = c - tile_first[skey[c] >> 32];
+  flag[c] = (r & 63) == 0 ? 1 : 0;
+}
+// slice s (= spos[c] at its first chunk): first chunk, height in blocks (its
+// first chunk is its longest) and the 64 h blocks it occupies
+__global__ void k_slice_fill(int64_t m, const int32_t* __restrict__ flag,
+                             const int64_t* __restrict__ spos, const int32_t* __restrict__ ssize,
+                             int32_t* __restrict__ slice_c0, int32_t* __restrict__ slice_h,
+                             int32_t* __restrict__ slice_blocks) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m || !flag[c]) return;
+  const int64_t sl = spos[c];
+  slice_c0[sl] = (int32_t)c;
+  slice_h[sl] = ssize[c] >> 3;
+  slice_blocks[sl] = (ssize[c] >> 3) * 64;
+}
+// Consecutive layout -> sliced layout: one wave per slice; lane i copies
+// the blocks of the slice's chunk i (consecutive from chunk_off[c]) to
+// slice_base + 64 j + i and writes zero blocks past its chunk's end (and for
+// lanes without a chunk), so every block of the slice is written.
+__global__ __launch_bounds__(256) void k_slice_transpose(
+    int64_t nsl, const int32_t* __restrict__ slice_c0, const int32_t* __restrict__ slice_h,
+    const int64_t* __restrict__ slice_base, const int64_t* __restrict__ chunk_off,
+    const uint4* __restrict__ src, uint4* __restrict__ dst) {
+  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sl >= nsl) return;
+  const int l = lane_id();
+  const int32_t c0 = slice_c0[sl], nc = slice_c0[sl + 1] - c0, h = slice_h[sl];
+  const bool lv = l < nc;
+  const int64_t b0 = lv ? chunk_off[c0 + l] >> 3 : 0;
+  const int32_t nb = lv ? (int32_t)((chunk_off[c0 + l + 1] >> 3) - b0) : 0;
+  uint4* __restrict__ d = dst + slice_base[sl] + l;
+  for (int32_t j = 0; j < h; ++j)
+    d[(int64_t)j * 64] = j < nb ? src[b0 + j] : make_uint4(0u, 0u, 0u, 0u);
+}
+// unit starts over slices: the first slice of a tile, every UNIT_S-th slice
+// after it, and every slice that begins a new span of emax blocks
+__global__ void k_slice_unit_flags(int32_t S, const int32_t* __restrict__ slice_c0,
+                                   const uint64_t* __restrict__ skey,
+                                   const int32_t* __restrict__ tile_first,
+                                   const int64_t* __restrict__ slice_base, int64_t emax,
+                                   int32_t* __restrict__ flag) {
+  const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= S) return;
+  const int32_t c = slice_c0[sl];
+  const int32_t rs = (c - tile_first[skey[c] >> 32]) >> 6;  // slice rank within the tile
+  flag[sl] = (rs % UNIT_S == 0 || (rs > 0 && slice_base[sl] / emax != slice_base[sl - 1] / emax))
+                 ? 1 : 0;
+}
+__global__ void k_slice_unit_fill(int32_t S, const int32_t* __restrict__ flag,
+                                  const int64_t* __restrict__ pos,
+                                  const int32_t* __restrict__ slice_c0,
+                                  const uint64_t* __restrict__ skey, int32_t* __restrict__ unit_s0,
+                                  int32_t* __restrict__ unit_tile) {
+  const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= S || !flag[sl]) return;
+  unit_s0[pos[sl]] = sl;
+  unit_tile[pos[sl]] = (int32_t)(skey[slice_c0[sl]] >> 32);
+}
+
+// rho_u = sum over S(u) of w_uv (canonical sets)
+__global__ void k_rho(int32_t n, int32_t k, const int64_t* __restrict__ off,
+                      const int32_t* __restrict__ hend, const int32_t* __restrict__ nbr,
+                      const float* __restrict__ sqrtc, float scale, float* __restrict__ rho) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int32_t u = blockIdx.x * (blockDim.x >> 6) + w;
+  if (u >= n) return;
+  float r = 0.f;
+  if (!sqrtc) {
+    if (l == 0) {
+      int32_t prev = 0;
+      for (int h = 1; h <= k; ++h) {
+        const int32_t e = hend[(int64_t)u * k + h - 1];
+        r += (float)(e - prev) / (float)(h * h);
+        prev = e;
+      }
+      rho[u] = r;
+    }
+    return;
+  }
+  const int64_t beg = off[u];
+  const float su = sqrtc[u];
+  int32_t seg0 = 0;
+  for (int h = 1; h <= k; ++h) {
+    const int32_t seg1 = hend[(int64_t)u * k + h - 1];
+    for (int32_t i = seg0 + l; i < seg1; i += 64) {
+      const float d = (float)h * (su + sqrtc[nbr[beg + i]]) * scale;
+      r += 1.f / (d * d);
+    }
+    seg0 = seg1;
+  }
+  r = wave_sum(r);
+  if (l == 0) rho[u] = r;
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+bool tiled_eligible(const KhopDev& kh, int32_t tbits) {
+  const int64_t ntiles = ((int64_t)kh.n + (1 << tbits) - 1) >> tbits;
+  // entries are (local id << 3) | hop: 3 hop bits, tbits + 3 <= 16
+  return kh.k <= 7 && tbits <= 13 && ntiles <= kTiledMaxTiles && kh.total > 0;
+}
+
+hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, float* rho,
+                       hipStream_t s) {
+  k_rho<<<nblk(kh.n, 4), 256, 0, s>>>(kh.n, kh.k, kh.off, kh.hend, kh.nbr, sqrtc, (float)scale, rho);
+  return hipGetLastError();
+}
+
+hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
+                       hipStream_t s, const float* sqrtc, double scale, float* rho, bool sliced) {
+  const int32_t n = kh.n;
+  const int32_t ntiles = (int32_t)(((int64_t)n + (1 << tbits) - 1) >> tbits);
+  const int32_t ntw = (ntiles + 31) >> 5;
+  ts->n = n;
+  ts->tbits = tbits;
+  ts->ntiles = ntiles;
+  DevBuf nch, cm_tile, cm_size, cm_row, skeys, svals, ssize, flag, upos;
+  MM_TRY(nch.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(ts->b_rc_ptr.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  ts->rc_ptr = ts->b_rc_ptr.as<int64_t>();
+  if (rho)
+    k_row_tiles<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+        n, kh.k, tbits, ntw, kh.off, kh.hend, kh.nbr, sqrtc, (float)scale, nch.as<int32_t>(), rho);
+  else
+    k_row_tiles<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
+        n, kh.k, tbits, ntw, kh.off, kh.hend, kh.nbr, nullptr, 1.f, nch.as<int32_t>(), nullptr);
+  MM_TRY(hipGetLastError());
+  MM_TRY(scan_excl_i32(nch.as<int32_t>(), ts->rc_ptr, n, s));
+  int64_t m = 0;
+  MM_TRY(hipMemcpyAsync(&m, ts->rc_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  if (m >= (1ll << 31)) return hipErrorInvalidValue;
+  ts->nchunks = m;
+  ts->avg_chunk = (double)kh.total / (double)std::max<int64_t>(m, 1);
+  ts->built = false;
+  if (ts->avg_chunk < min_avg_chunk) return hipSuccess;  // chunks too short to pay off
+  MM_TRY(cm_tile.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(cm_size.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(cm_row.alloc(sizeof(int32_t) * (size_t)m, s));
+  const size_t per_wave = (2 * (size_t)ntw + (size_t)ntiles + 1) & ~(size_t)1;
+  const size_t tb_shm = sizeof(uint32_t) * (size_t)TB_WAVES * per_wave;
+  // the fill pass keeps the chunk starts of a row's tiles in LDS when they fit
+  const size_t tb_shm_base = sizeof(uint32_t) * (size_t)TB_WAVES * (per_wave + 2 * (size_t)ntiles);
+  const bool use_base = tb_shm_base <= 65536;
+  if (tb_shm > 65536) {
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<false, false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
+    MM_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_chunks<true, false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
+  }
+  k_row_chunks<false, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
+      n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, cm_tile.as<int32_t>(),
+      cm_size.as<int32_t>(), cm_row.as<int32_t>(), nullptr, nullptr, nullptr);
+  MM_TRY(hipGetLastError());
+  // order chunks by (tile, row): stable sort of row-major slots by tile
+  MM_TRY(skeys.alloc(sizeof(uint64_t) * (size_t)m, s));
+  MM_TRY(svals.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(iota_i32(svals.as<int32_t>(), m, s));
+  // chunks of a tile in descending size (stable: ties keep row order), so the
+  // chunks of a work unit have similar sizes and its lane groups stay balanced
+  k_chunk_keys<<<nblk(m), 256, 0, s>>>(m, cm_tile.as<int32_t>(), cm_size.as<int32_t>(),
+                                       skeys.as<uint64_t>());
+  int kbits = 1;
+  while ((1 << kbits) < ntiles) kbits++;
+  MM_TRY(radix_sort_pairs(skeys.as<uint64_t>(), svals.as<int32_t>(), m, 32 + kbits, s));
+  MM_TRY(ssize.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(ts->b_chunk_row.alloc(sizeof(int32_t) * (size_t)m, s));
+  MM_TRY(ts->b_chunk_off.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+  ts->chunk_row = ts->b_chunk_row.as<int32_t>();
+  ts->chunk_off = ts->b_chunk_off.as<int64_t>();
+  // pos_of_slot reuses cm_tile's storage after the sort
+  int32_t* pos_of_slot = cm_tile.as<int32_t>();
+  k_gather_sorted_chunks<<<nblk(m), 256, 0, s>>>(m, svals.as<int32_t>(), cm_size.as<int32_t>(),
+                                                 cm_row.as<int32_t>(), ssize.as<int32_t>(),
+                                                 ts->chunk_row, pos_of_slot);
+  DevBuf tfirst;
+  MM_TRY(tfirst.alloc(sizeof(int32_t) * (size_t)ntiles, s));
+  k_tile_first<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>());
+  int64_t nsl = 0;
+  DevBuf sflag, spos;
+  // consecutive chunks (the sliced layout is built from them)
+  MM_TRY(scan_excl_i32(ssize.as<int32_t>(), ts->chunk_off, m, s));
+  if (sliced) {
+    // slices of 64 chunks of one tile; block j of the slice's chunk i at
+    // slice_base + 64 j + i
+    MM_TRY(sflag.alloc(sizeof(int32_t) * (size_t)m, s));
+    MM_TRY(spos.alloc(sizeof(int64_t) * (size_t)(m + 1), s));
+    k_slice_flags<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>(),
+                                          sflag.as<int32_t>());
+    MM_TRY(scan_excl_i32(sflag.as<int32_t>(), spos.as<int64_t>(), m, s));
+    MM_TRY(hipMemcpyAsync(&nsl, spos.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MM_TRY(hipStreamSynchronize(s));
+    DevBuf sblocks;
+    MM_TRY(ts->b_slice_c0.alloc(sizeof(int32_t) * (size_t)(nsl + 1), s));
+    MM_TRY(ts->b_slice_h.alloc(sizeof(int32_t) * (size_t)nsl, s));
+    MM_TRY(ts->b_slice_base.alloc(sizeof(int64_t) * (size_t)(nsl + 1), s));
+    MM_TRY(sblocks.alloc(sizeof(int32_t) * (size_t)nsl, s));
+    ts->slice_c0 = ts->b_slice_c0.as<int32_t>();
+    ts->slice_h = ts->b_slice_h.as<int32_t>();
+    ts->slice_base = ts->b_slice_base.as<int64_t>();
+    k_slice_fill<<<nblk(m), 256, 0, s>>>(m, sflag.as<int32_t>(), spos.as<int64_t>(),
+                                         ssize.as<int32_t>(), ts->slice_c0, ts->slice_h,
+                                         sblocks.as<int32_t>());
+    k_set_i32<<<1, 1, 0, s>>>(ts->slice_c0 + nsl, (int32_t)m);
+    MM_TRY(scan_excl_i32(sblocks.as<int32_t>(), ts->slice_base, nsl, s));
+  }
+  // chunk -> row-major slot
+  MM_TRY(ts->b_chunk_slot.alloc(sizeof(int32_t) * (size_t)m, s));
+  ts->chunk_slot = ts->b_chunk_slot.as<int32_t>();
+  MM_TRY(hipMemcpyAsync(ts->chunk_slot, svals.p, sizeof(int32_t) * (size_t)m,
+                        hipMemcpyDeviceToDevice, s));
+  int64_t padded = 0;
+  MM_TRY(hipMemcpyAsync(&padded, ts->chunk_off + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  int64_t sl_blocks = 0;
+  if (sliced)
+    MM_TRY(hipMemcpyAsync(&sl_blocks, ts->slice_base + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  if ((padded >> 3) >= (1ll << 31) || sl_blocks >= (1ll << 31)) return hipSuccess;  // int32 block ids
+  // the consecutive layout: the sets themselves, or the staging copy of the
+  // sliced layout
+  DevBuf stage;
+  DevBuf& cons = sliced ? stage : ts->b_ent;
+  MM_TRY(cons.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
+  MM_TRY(hipMemsetAsync(cons.p, 0, sizeof(uint16_t) * (size_t)padded, s));
+  if (use_base)
+    k_row_chunks<true, true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm_base, s>>>(
+        n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
+        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
+  else
+    k_row_chunks<true, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
+        n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
+        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
+  MM_TRY(hipGetLastError());
+  if (sliced) {
+    padded = sl_blocks * 8;
+    MM_TRY(ts->b_ent.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
+    k_slice_transpose<<<nblk(nsl, 4), 256, 0, s>>>(nsl, ts->slice_c0, ts->slice_h, ts->slice_base,
+                                                   ts->chunk_off, cons.as<uint4>(),
+                                                   ts->b_ent.as<uint4>());
+    MM_TRY(hipGetLastError());
+  }  // the staging copy is freed (stream-ordered) on return
+  ts->ent = ts->b_ent.as<uint16_t>();
+  ts->total = kh.total;
+  ts->padded = padded;
+  // work units: chunks (tiled) or slices (sliced) of one tile
+  const int64_t mu = sliced ? nsl : m;
+  MM_TRY(flag.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(mu, 1), s));
+  MM_TRY(upos.alloc(sizeof(int64_t) * (size_t)(mu + 1), s));
+  // at least ~8 work units per CU when the level is small; never fewer
+  // than 64K entries per unit (the tile staging is amortised over them)
+  const int64_t emax = std::max<int64_t>(65536, padded / 2048);
+  if (sliced)
+    k_slice_unit_flags<<<nblk(mu), 256, 0, s>>>((int32_t)mu, ts->slice_c0, skeys.as<uint64_t>(),
+                                                tfirst.as<int32_t>(), ts->slice_base, emax / 8,
+                                                flag.as<int32_t>());
+  else
+    k_unit_flags<<<nblk(m), 256, 0, s>>>(m, skeys.as<uint64_t>(), tfirst.as<int32_t>(),
+                                         ts->chunk_off, emax, flag.as<int32_t>());
+  MM_TRY(scan_excl_i32(flag.as<int32_t>(), upos.as<int64_t>(), mu, s));
+  int64_t nu = 0;
+  MM_TRY(hipMemcpyAsync(&nu, upos.as<int64_t>() + mu, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  ts->nunits = (int32_t)nu;
+  MM_TRY(ts->b_unit_c0.alloc(sizeof(int32_t) * (size_t)(nu + 1), s));
+  MM_TRY(ts->b_unit_tile.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1), s));
+  ts->unit_c0 = ts->b_unit_c0.as<int32_t>();
+  ts->unit_tile = ts->b_unit_tile.as<int32_t>();
+  if (sliced)
+    k_slice_unit_fill<<<nblk(mu), 256, 0, s>>>((int32_t)mu, flag.as<int32_t>(), upos.as<int64_t>(),
+                                               ts->slice_c0, skeys.as<uint64_t>(), ts->unit_c0,
+                                               ts->unit_tile);
+  else
+    k_unit_fill<<<nblk(m), 256, 0, s>>>(m, flag.as<int32_t>(), upos.as<int64_t>(),
+                                        skeys.as<uint64_t>(), ts->unit_c0, ts->unit_tile);
+  k_set_i32<<<1, 1, 0, s>>>(ts->unit_c0 + nu, (int32_t)mu);
+  ts->sliced = sliced;
+  ts->nslices = nsl;
+  MM_TRY(ts->b_partial.alloc(sizeof(float2) * (size_t)m, s));
+  ts->built = true;
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -11,7 +11,7 @@ Bars:
   node table and interaction counts bit-exact to the oracle's, F within
   1e-4 relative to max(|F_u|, mean |F|);
 * one sweep of the finest level in the bench's configuration (sliced layout,
-  tiles of 2^13 vertices, 2 blocks per lane and step) within
+  tiles of 2^13 vertices, 4 blocks per lane and step; also 2 blocks) within
   1e-4 * max(|x_orc|, 1) of the oracle's FP64 update of 512 sampled rows fed
   the same FP32 inputs;
 * the first coarsening step (label propagation at h = 1, contraction)
@@ -133,10 +133,11 @@ def _sweep_rows_check(orc, mm, ctx, rp, col, x, c, level, config):
     assert err < 1e-4
 
 
-def test_full_sweep_finest(orc, mm, full):
+@pytest.mark.parametrize("blocks", [4, 2])
+def test_full_sweep_finest(orc, mm, full, blocks):
     g, ctx, dg, x = full
-    print(f"[full sweep] level 0, config (13, sliced, 2)", flush=True)
-    _sweep_rows_check(orc, mm, ctx, g.row_ptr, g.col, x, None, 0, (13, SLICED, 2))
+    print(f"[full sweep] level 0, config (13, sliced, {blocks})", flush=True)
+    _sweep_rows_check(orc, mm, ctx, g.row_ptr, g.col, x, None, 0, (13, SLICED, blocks))
 
 
 def test_full_coarsen_and_coarse_sweep(orc, mm, full):
