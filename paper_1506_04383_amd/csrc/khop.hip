@@ -27,6 +27,9 @@ constexpr int KS_WAVES = 2;      // waves per block
 constexpr int KB_T = 512;        // threads per big-row block
 constexpr int KB_NW = KB_T / 64;
 constexpr int KB_U = 4;          // frontier vertices per wave step in the bitmap kernel
+constexpr int KB_V = 8;          // neighbour loads in flight per lane while marking
+constexpr int32_t KB_HUB = 512;  // longer neighbour lists are marked by the whole workgroup
+constexpr int KB_HUBCAP = 256;   // hubs deferred per frontier (more: marked by their wave)
 constexpr int KB_LDS_WORDS = 19968;  // 2 x this many bitmap words fit in a CU's LDS
 
 __device__ inline void wave_sync() {
@@ -168,6 +171,8 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
   constexpr bool STORE = KEEP && !FILL; // keep the bitmap
   extern __shared__ uint32_t dyn[];
   __shared__ int32_t wtot[KB_NW + 1];
+  __shared__ int32_t hubs[KB_HUBCAP];
+  __shared__ int32_t nhub;
   const int32_t W = (n + 31) >> 5;
   const int32_t NB = ONE ? 1 : 2;
   uint32_t* VIS = LDSBM ? dyn : gbm + (size_t)blockIdx.x * NB * (size_t)W;
@@ -175,6 +180,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
   int32_t* scratch = gscratch ? gscratch + (size_t)blockIdx.x * (size_t)n : nullptr;
   const int t = threadIdx.x, wv = t >> 6, l = lane_id();
   for (int32_t i = t; i < NB * W; i += KB_T) VIS[i] = 0;
+  if (t == 0) nhub = 0;
   __syncthreads();
   // word chunk per wave for the ordered extraction
   const int32_t CW = ((W + KB_NW - 1) / KB_NW + 63) & ~63;
@@ -198,11 +204,17 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     __syncthreads();
     const uint32_t* kept = LOAD ? bmkeep + (size_t)r * (size_t)W : nullptr;
     for (int h = 2; h <= k; ++h) {
-      // mark neighbours of the frontier not yet visited.  A wave takes KB_U
-      // frontier vertices at a time and issues their row bounds and first 64
-      // neighbour loads before marking any, so KB_U dependent load chains are
-      // in flight per wave instead of one (most frontier vertices have fewer
-      // than 64 neighbours)
+      // mark neighbours of the frontier not yet visited.  The marks are
+      // bound by the latency of the neighbour loads, and most of them come
+      // from the few long lists of high-degree vertices (a vertex of degree
+      // d lies in d rows' frontiers and costs d marks in each), so:
+      //  * a wave takes KB_U frontier vertices at a time and issues their row
+      //    bounds and first 64 neighbour loads before marking any;
+      //  * the rest of a list is loaded KB_V steps of 64 at a time;
+      //  * lists longer than KB_HUB are set aside and marked afterwards by
+      //    the whole workgroup, KB_T * KB_V entries per round, so that one
+      //    long list does not hold the row on one wave.
+      // Bits are only ever set, so the order of the marks does not matter.
       auto mark = [&](int32_t v) {
         const uint32_t bit = 1u << (v & 31);
         if (ONE) {
@@ -218,6 +230,16 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
           const int32_t x = i0 + uu < flen ? F[i0 + uu] : -1;
           b0[uu] = x >= 0 ? rp[x] : 0;
           b1[uu] = x >= 0 ? rp[x + 1] : 0;
+          if (b1[uu] - b0[uu] > KB_HUB) {
+            // wave-uniform: defer to the workgroup unless the list is full
+            int32_t slot = 0;
+            if (l == 0) slot = atomicAdd(&nhub, 1);
+            slot = __shfl(slot, 0, 64);
+            if (slot < KB_HUBCAP) {
+              if (l == 0) hubs[slot] = x;
+              b1[uu] = b0[uu];
+            }
+          }
         }
 #pragma unroll
         for (int uu = 0; uu < KB_U; ++uu) v0[uu] = b0[uu] + l < b1[uu] ? col[b0[uu] + l] : -1;
@@ -225,10 +247,41 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
         for (int uu = 0; uu < KB_U; ++uu)
           if (v0[uu] >= 0) mark(v0[uu]);
 #pragma unroll
-        for (int uu = 0; uu < KB_U; ++uu)
-          for (int32_t e = b0[uu] + 64 + l; e < b1[uu]; e += 64) mark(col[e]);
+        for (int uu = 0; uu < KB_U; ++uu) {
+          for (int32_t e0 = b0[uu] + 64; e0 < b1[uu]; e0 += 64 * KB_V) {
+            int32_t vv[KB_V];
+#pragma unroll
+            for (int j = 0; j < KB_V; ++j) {
+              const int32_t e = e0 + 64 * j + l;
+              vv[j] = e < b1[uu] ? col[e] : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < KB_V; ++j)
+              if (vv[j] >= 0) mark(vv[j]);
+          }
+        }
       }
       __syncthreads();
+      if (!LOAD) {
+        const int32_t nh = min(nhub, KB_HUBCAP);
+        for (int32_t j = 0; j < nh; ++j) {
+          const int32_t x = hubs[j];
+          const int32_t e1 = rp[x + 1];
+          for (int32_t e0 = rp[x]; e0 < e1; e0 += KB_T * KB_V) {
+            int32_t vv[KB_V];
+#pragma unroll
+            for (int jj = 0; jj < KB_V; ++jj) {
+              const int32_t e = e0 + KB_T * jj + t;
+              vv[jj] = e < e1 ? col[e] : -1;
+            }
+#pragma unroll
+            for (int jj = 0; jj < KB_V; ++jj)
+              if (vv[jj] >= 0) mark(vv[jj]);
+          }
+        }
+        __syncthreads();
+        if (t == 0) nhub = 0;
+      }
       if (ONE && !LOAD) {
         // drop hop 0 and hop 1 from the candidates
         if (t == 0) atomicAnd(&NEW[u >> 5], ~(1u << (u & 31)));

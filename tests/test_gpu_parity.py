@@ -41,7 +41,15 @@ def _graphs():
     hub_nb = np.arange(0, n - 1, 350)[:2000]
     src = np.concatenate([v, np.full(hub_nb.size, n - 1)])
     dst = np.concatenate([v + 1, hub_nb])
+    # vertex 0 joined to 300 hubs of 600 leaves each (shared among hubs):
+    # frontiers with more long lists than the kernel sets aside per row
+    L = 4000
+    hubs = np.arange(1, 301)
+    lv = 301 + (13 * (hubs[:, None] - 1) + np.arange(600)[None, :]) % L
+    hs = np.concatenate([np.zeros(300, np.int64), np.repeat(hubs, 600)])
+    hd = np.concatenate([hubs, lv.ravel()])
     return {
+        "hubs300": lambda: synth.csr_from_edges(301 + L, hs, hd),
         "grid32": lambda: synth.grid(32, 32),
         "rgg4k": lambda: synth.rgg(4000, 3),
         "rmat12": lambda: synth.rmat(12, 8 * 4096, 5),
@@ -55,7 +63,8 @@ def _graphs():
 
 
 KHOP_CASES = [("grid32", 3), ("grid32", 1), ("rgg4k", 3), ("rgg4k", 5), ("rmat12", 2),
-              ("rmat12", 3), ("star3k", 2), ("tree", 4), ("tri", 2), ("hubpath700k", 2)]
+              ("rmat12", 3), ("star3k", 2), ("star3k", 3), ("tree", 4), ("tri", 2),
+              ("hubpath700k", 2), ("hubs300", 2), ("hubs300", 3)]
 
 
 @pytest.mark.parametrize("name,k", KHOP_CASES)
