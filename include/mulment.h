@@ -88,6 +88,11 @@ typedef struct {
                               coarser one, replacing theta / exact_below / mlp_weights there
                               (the coarsest level keeps those); 0 = off (default).  Needs the
                               hierarchy: ignored with init_xy; mm_layout only */
+  int32_t khop_direct;     /* 1 (default): on levels swept tile-major with k = 2, rows whose
+                              2-hop search used a bitmap are copied to the tile-major layout
+                              straight from that bitmap, without writing their canonical ids
+                              (same layout, bit for bit); 0: always via the canonical ids.
+                              mm_layout only */
 } mm_params;
 
 #define MM_MAX_LEVELS 64

@@ -44,7 +44,7 @@ class MMParams(C.Structure):
                 ("f", C.c_double), ("lp_rounds", C.c_int32), ("coarse_dist_scale", C.c_double),
                 ("seed", C.c_uint64), ("validate", C.c_int32), ("mlp_weights", C.c_void_p),
                 ("use_graphs", C.c_int32), ("autotune", C.c_int32), ("exact_below", C.c_int32),
-                ("approx_h", C.c_int32)]
+                ("approx_h", C.c_int32), ("khop_direct", C.c_int32)]
 
 
 class MMStats(C.Structure):
@@ -207,6 +207,7 @@ class Params:
     autotune: int = 0  # time each level's sweep configurations once per level shape
     exact_below: int = 0  # levels with <= this many vertices use the exact far field
     approx_h: int = 0  # MulMent_h: cluster far field of Eq. 3, h levels beneath
+    khop_direct: int = 1  # tile-major sets of bitmap rows straight from the 2-hop search
 
     def to_c(self) -> MMParams:
         p = MMParams()

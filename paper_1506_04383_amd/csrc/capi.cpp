@@ -371,6 +371,7 @@ mm_status mm_params_default(mm_params* p) {
   p->autotune = 0;
   p->exact_below = 0;
   p->approx_h = 0;
+  p->khop_direct = 1;
   return MM_OK;
 }
 
@@ -1094,9 +1095,26 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       HIPCHK(F.alloc(sizeof(float) * 2 * (size_t)nl, s));
       auto tk = std::chrono::steady_clock::now();
       mm::KhopDev kh;
-      HIPCHK(mm::khop_build(nl, G.row_ptr, G.col, p->k, &kh, s));
+      mm::KhopCount kc;
+      HIPCHK(mm::khop_count(nl, G.row_ptr, G.col, p->k, &kh, &kc, s));
+      // the canonical ids are written only when something reads them: the
+      // tuner, the row kernel, or a tile-major copy that cannot be built
+      // straight from the search's kept bitmaps
+      bool canon = false;
+      double khop_ms = 0;
+      auto fill_canon = [&]() -> hipError_t {
+        if (canon) return hipSuccess;
+        canon = true;
+        auto tf = std::chrono::steady_clock::now();
+        MM_TRY(mm::khop_fill(nl, G.row_ptr, G.col, &kh, &kc, s));
+        MM_TRY(hipStreamSynchronize(s));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
+        khop_ms += ms;
+        t_khop += ms;
+        return hipSuccess;
+      };
       HIPCHK(hipStreamSynchronize(s));
-      const double khop_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
+      khop_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
       t_khop += khop_ms;
       double lvl_far = 0, lvl_sweep = 0, lvl_wall = 0;
       mm::DevBuf sq;
@@ -1118,6 +1136,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         const auto key = std::make_tuple(lvl > 0 ? 1 : 0, nl, kh.total, p->k);
         auto it = ctx->tune.find(key);
         if (it == ctx->tune.end()) {
+          HIPCHK(fill_canon());
           auto tt = std::chrono::steady_clock::now();
           mm_context::TuneChoice c;
           STCHK(tune_level(ctx, kh, lvl, sqrtc, p, xa.as<float>(), F.as<float>(), xb.as<float>(),
@@ -1133,17 +1152,35 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       if (tbits_lvl > 0 && mm::tiled_eligible(kh, tbits_lvl)) {
         auto tt = std::chrono::steady_clock::now();
         HIPCHK(rho.alloc(sizeof(float) * (size_t)nl, s));
-        HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s, sqrtc, p->coarse_dist_scale,
-                               rho.as<float>(), group_lvl == 0 || group_lvl == mm::kSlicedGroup));
+        const bool sliced_lvl = group_lvl == 0 || group_lvl == mm::kSlicedGroup;
+        const bool direct = !canon && p->khop_direct && mm::tiled_direct_ok(kh, kc, tbits_lvl);
+        if (direct) {
+          // big rows straight from their kept bitmaps, the rest from a
+          // compact copy of their canonical ids
+          mm::DevBuf off_small, nbr_small;
+          HIPCHK(mm::khop_fill_small(nl, G.row_ptr, G.col, kh, &kc, &off_small, &nbr_small, s));
+          HIPCHK(mm::tiled_build_direct(kh, kc, G.row_ptr, G.col, off_small.as<int64_t>(),
+                                        nbr_small.as<int32_t>(), tbits_lvl, min_avg, &ts, s, sqrtc,
+                                        p->coarse_dist_scale, rho.as<float>(), sliced_lvl));
+        } else {
+          HIPCHK(fill_canon());
+          tt = std::chrono::steady_clock::now();
+          HIPCHK(mm::tiled_build(kh, tbits_lvl, min_avg, &ts, s, sqrtc, p->coarse_dist_scale,
+                                 rho.as<float>(), sliced_lvl));
+        }
         if (ts.built) kh.b_nbr.release();  // ids now live in the tile-major copy
         HIPCHK(hipStreamSynchronize(s));
         const double tiled_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt).count();
         t_khop += tiled_ms;
         const char* ev = std::getenv("MM_VERBOSE");
         if (ev && ev[0] == '1')
-          std::fprintf(stderr, "[level %d] n %d sets %lld: k-hop build %.1f ms, tile-major copy %.1f ms\n",
-                       lvl, nl, (long long)kh.total, khop_ms, tiled_ms);
+          std::fprintf(stderr, "[level %d] n %d sets %lld: k-hop build %.1f ms, tile-major copy %.1f ms%s\n",
+                       lvl, nl, (long long)kh.total, khop_ms, tiled_ms,
+                       direct ? " (straight from the search)" : "");
       }
+      // the row kernel reads the canonical ids
+      if (!ts.built) HIPCHK(fill_canon());
+      kc = mm::KhopCount();  // kept bitmaps no longer needed
       int32_t iters = 0, final_iters = 0, cap_hit = 0;
       double delta = 0;
       mm::DevBuf sweep_part;

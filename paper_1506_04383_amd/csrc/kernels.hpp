@@ -104,6 +104,27 @@ struct KhopDev {
 };
 hipError_t khop_build(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
                       KhopDev* out, hipStream_t s);
+// The build in two steps.  khop_count fills off, hend and total; rows whose
+// breadth-first search outgrows the per-wave lists ("big" rows, ids in rows)
+// are searched with n-bit bitmaps, and for k = 2 their hop-2 bitmaps are
+// kept (bmk: row r of rows at bmk + r * W, W = ceil(n / 32) words) when
+// device memory allows.  khop_fill writes the canonical ids (nbr) from that
+// state; khop_fill_small writes only the other rows' ids, into a compact
+// array with its own offsets (off_small: n + 1 values, 0-length for big rows).
+struct KhopCount {
+  int32_t k = 0, W = 0, slots = 0;
+  int64_t nbig = 0;
+  size_t shm = 0;
+  bool lds_bm = false, one = false, keep = false;
+  DevBuf cnt, big, bigpos, rows, bmk, gbm, gscr;
+};
+hipError_t khop_count(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
+                      KhopDev* out, KhopCount* st, hipStream_t s);
+hipError_t khop_fill(int32_t n, const int32_t* row_ptr, const int32_t* col, KhopDev* out,
+                     KhopCount* st, hipStream_t s);
+hipError_t khop_fill_small(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                           const KhopDev& kh, KhopCount* st, DevBuf* off_small,
+                           DevBuf* nbr_small, hipStream_t s);
 
 // ---- tile-major stress sets and the LDS-tiled sweep (tiled.hip)
 struct TiledSet {
@@ -141,6 +162,17 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
                        hipStream_t s, const float* sqrtc = nullptr, double scale = 1.0,
                        float* rho = nullptr, bool sliced = false);
+// The same tile-major copy built without the canonical ids of the big rows
+// (k = 2 with kept hop-2 bitmaps): those rows are read from their CSR row
+// and bitmap, the others from off_small / nbr_small (khop_fill_small).  The
+// result (entries, chunk order, rho) is identical to tiled_build's on the
+// canonical sets.  tiled_direct_ok says whether the state allows it.
+bool tiled_direct_ok(const KhopDev& kh, const KhopCount& st, int32_t tbits);
+hipError_t tiled_build_direct(const KhopDev& kh, const KhopCount& st, const int32_t* row_ptr,
+                              const int32_t* col, const int64_t* off_small,
+                              const int32_t* nbr_small, int32_t tbits, double min_avg_chunk,
+                              TiledSet* ts, hipStream_t s, const float* sqrtc = nullptr,
+                              double scale = 1.0, float* rho = nullptr, bool sliced = false);
 // lanes-per-chunk code of the sliced layout in tuner records and forced
 // configurations (one lane per chunk, 64 chunks per wave)
 constexpr int32_t kSlicedGroup = 64;

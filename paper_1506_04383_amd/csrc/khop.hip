@@ -362,54 +362,59 @@ __global__ void k_hop1(int32_t n, const int32_t* rp, int32_t* hend, int32_t* cnt
   if (u < n) { int32_t d = rp[u + 1] - rp[u]; hend[u] = d; cnt[u] = d; }
 }
 
+// counts of the rows the small-row kernel filled (0 for bitmap rows)
+__global__ void k_small_counts(int32_t n, const int32_t* cnt, const int32_t* big, int32_t* out) {
+  int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) out[u] = big[u] ? 0 : cnt[u];
+}
+
 }  // namespace
 
-hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, KhopDev* out,
-                      hipStream_t s) {
+hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, KhopDev* out,
+                      KhopCount* st, hipStream_t s) {
   out->n = n;
   out->k = k;
+  st->k = k;
   MM_TRY(out->b_off.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
   MM_TRY(out->b_hend.alloc(sizeof(int32_t) * (size_t)n * (size_t)k, s));
   out->off = out->b_off.as<int64_t>();
   out->hend = out->b_hend.as<int32_t>();
+  MM_TRY(st->cnt.alloc(sizeof(int32_t) * (size_t)n, s));
   if (k == 1) {
     // S_1(u) = N(u): the CSR row itself
-    DevBuf cnt;
-    MM_TRY(cnt.alloc(sizeof(int32_t) * (size_t)n, s));
-    k_hop1<<<(n + 255) / 256, 256, 0, s>>>(n, rp, out->hend, cnt.as<int32_t>());
-    MM_TRY(scan_excl_i32(cnt.as<int32_t>(), out->off, n, s));
+    k_hop1<<<(n + 255) / 256, 256, 0, s>>>(n, rp, out->hend, st->cnt.as<int32_t>());
+    MM_TRY(scan_excl_i32(st->cnt.as<int32_t>(), out->off, n, s));
     MM_TRY(hipMemcpyAsync(&out->total, out->off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MM_TRY(hipStreamSynchronize(s));
-    MM_TRY(out->b_nbr.alloc(sizeof(int32_t) * (size_t)out->total, s));
-    out->nbr = out->b_nbr.as<int32_t>();
-    MM_TRY(hipMemcpyAsync(out->nbr, col, sizeof(int32_t) * (size_t)out->total,
-                          hipMemcpyDeviceToDevice, s));
     return hipGetLastError();
   }
-  DevBuf cnt, big, bigpos, rows;
-  MM_TRY(cnt.alloc(sizeof(int32_t) * (size_t)n, s));
-  MM_TRY(big.alloc(sizeof(int32_t) * (size_t)n, s));
-  MM_TRY(bigpos.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
-  MM_TRY(hipMemsetAsync(big.p, 0, sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(st->big.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(st->bigpos.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  MM_TRY(hipMemsetAsync(st->big.p, 0, sizeof(int32_t) * (size_t)n, s));
   const unsigned gs = (unsigned)((n + KS_WAVES - 1) / KS_WAVES);
   k_khop_small<false><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, nullptr, out->hend, nullptr,
-                                                  cnt.as<int32_t>(), big.as<int32_t>());
+                                                  st->cnt.as<int32_t>(), st->big.as<int32_t>());
   MM_TRY(hipGetLastError());
-  MM_TRY(scan_excl_i32(big.as<int32_t>(), bigpos.as<int64_t>(), n, s));
+  MM_TRY(scan_excl_i32(st->big.as<int32_t>(), st->bigpos.as<int64_t>(), n, s));
   int64_t nbig = 0;
-  MM_TRY(hipMemcpyAsync(&nbig, bigpos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipMemcpyAsync(&nbig, st->bigpos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
+  st->nbig = nbig;
   const int32_t W = (n + 31) >> 5;
+  st->W = W;
   const bool one = (k == 2);
+  st->one = one;
   const int32_t nbw = (one ? 1 : 2) * W;  // bitmap words per workgroup
   const bool lds_bm = nbw <= 2 * KB_LDS_WORDS;
+  st->lds_bm = lds_bm;
   int dev = 0, ncu = 0;
   MM_TRY(hipGetDevice(&dev));
   MM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const size_t shm = lds_bm ? sizeof(uint32_t) * (size_t)nbw : 0;
+  st->shm = shm;
   const int per_cu = lds_bm ? (int)std::max<size_t>(1, (160 * 1024 - 256) / std::max<size_t>(shm, 1)) : 2;
   const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * std::min(per_cu, 4));
-  DevBuf gbm, gscr, bmk;
+  st->slots = slots;
   // keep the counting pass's hop-2 bitmaps for the filling pass when they
   // take at most a third of the free device memory
   bool keep = false;
@@ -426,7 +431,7 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
     }
     freeb += big_cached_bytes(dev);  // cached blocks are available too
     if (kb <= freeb / 3) {
-      MM_TRY(bmk.alloc(kb, s));
+      MM_TRY(st->bmk.alloc(kb, s));
       keep = true;
     }
     // MM_VERBOSE=1 reports the decision on stderr
@@ -435,53 +440,94 @@ hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
       std::fprintf(stderr, "[khop] n %d rows with bitmaps %lld (%.2f GB), free %.2f GB: %s\n", n,
                    (long long)nbig, kb / 1e9, freeb / 1e9, keep ? "kept" : "rebuilt");
   }
+  st->keep = keep;
 #define MM_BIG(FILLV, LDSV, ONEV, KEEPV, ...)                                                   \
   do {                                                                                         \
     if (LDSV)                                                                                  \
       MM_TRY(hipFuncSetAttribute(                                                              \
           reinterpret_cast<const void*>(&k_khop_big<FILLV, LDSV, ONEV, KEEPV>),                \
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));                              \
-    k_khop_big<FILLV, LDSV, ONEV, KEEPV><<<slots, KB_T, LDSV ? shm : 0, s>>>(__VA_ARGS__);    \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->shm));                          \
+    k_khop_big<FILLV, LDSV, ONEV, KEEPV><<<st->slots, KB_T, LDSV ? st->shm : 0, s>>>(__VA_ARGS__); \
   } while (0)
 #define MM_BIG_ANY(FILLV, ...)                                                          \
   do {                                                                                 \
-    if (lds_bm) {                                                                      \
-      if (one && keep) MM_BIG(FILLV, true, true, true, __VA_ARGS__);                   \
-      else if (one) MM_BIG(FILLV, true, true, false, __VA_ARGS__);                     \
+    if (st->lds_bm) {                                                                  \
+      if (st->one && st->keep) MM_BIG(FILLV, true, true, true, __VA_ARGS__);           \
+      else if (st->one) MM_BIG(FILLV, true, true, false, __VA_ARGS__);                 \
       else MM_BIG(FILLV, true, false, false, __VA_ARGS__);                             \
     } else {                                                                           \
-      if (one && keep) MM_BIG(FILLV, false, true, true, __VA_ARGS__);                  \
-      else if (one) MM_BIG(FILLV, false, true, false, __VA_ARGS__);                    \
+      if (st->one && st->keep) MM_BIG(FILLV, false, true, true, __VA_ARGS__);          \
+      else if (st->one) MM_BIG(FILLV, false, true, false, __VA_ARGS__);                \
       else MM_BIG(FILLV, false, false, false, __VA_ARGS__);                            \
     }                                                                                  \
   } while (0)
   if (nbig > 0) {
-    MM_TRY(rows.alloc(sizeof(int32_t) * (size_t)nbig, s));
-    k_collect_big<<<(n + 255) / 256, 256, 0, s>>>(big.as<int32_t>(), n, bigpos.as<int64_t>(),
-                                                  rows.as<int32_t>());
-    if (!lds_bm) MM_TRY(gbm.alloc(sizeof(uint32_t) * (size_t)nbw * (size_t)slots, s));
-    if (k >= 3) MM_TRY(gscr.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
-    MM_BIG_ANY(false, n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig, nullptr, out->hend,
-               nullptr, cnt.as<int32_t>(), gbm.as<uint32_t>(), gscr.as<int32_t>(),
-               bmk.as<uint32_t>());
+    MM_TRY(st->rows.alloc(sizeof(int32_t) * (size_t)nbig, s));
+    k_collect_big<<<(n + 255) / 256, 256, 0, s>>>(st->big.as<int32_t>(), n, st->bigpos.as<int64_t>(),
+                                                  st->rows.as<int32_t>());
+    if (!lds_bm) MM_TRY(st->gbm.alloc(sizeof(uint32_t) * (size_t)nbw * (size_t)slots, s));
+    if (k >= 3) MM_TRY(st->gscr.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
+    MM_BIG_ANY(false, n, rp, col, k, st->rows.as<int32_t>(), (int32_t)nbig, nullptr, out->hend,
+               nullptr, st->cnt.as<int32_t>(), st->gbm.as<uint32_t>(), st->gscr.as<int32_t>(),
+               st->bmk.as<uint32_t>());
     MM_TRY(hipGetLastError());
   }
-  MM_TRY(scan_excl_i32(cnt.as<int32_t>(), out->off, n, s));
+  MM_TRY(scan_excl_i32(st->cnt.as<int32_t>(), out->off, n, s));
   MM_TRY(hipMemcpyAsync(&out->total, out->off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
+  return hipGetLastError();
+}
+
+hipError_t khop_fill(int32_t n, const int32_t* rp, const int32_t* col, KhopDev* out, KhopCount* st,
+                     hipStream_t s) {
+  const int32_t k = st->k;
   MM_TRY(out->b_nbr.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(out->total, 1), s));
   out->nbr = out->b_nbr.as<int32_t>();
+  if (k == 1) {
+    if (out->total > 0)
+      MM_TRY(hipMemcpyAsync(out->nbr, col, sizeof(int32_t) * (size_t)out->total,
+                            hipMemcpyDeviceToDevice, s));
+    return hipGetLastError();
+  }
+  const unsigned gs = (unsigned)((n + KS_WAVES - 1) / KS_WAVES);
   k_khop_small<true><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, out->off, out->hend, out->nbr,
-                                                 nullptr, big.as<int32_t>());
+                                                 nullptr, st->big.as<int32_t>());
   MM_TRY(hipGetLastError());
-  if (nbig > 0) {
-    MM_BIG_ANY(true, n, rp, col, k, rows.as<int32_t>(), (int32_t)nbig, out->off, out->hend,
-               out->nbr, nullptr, gbm.as<uint32_t>(), nullptr, bmk.as<uint32_t>());
+  if (st->nbig > 0) {
+    MM_BIG_ANY(true, n, rp, col, k, st->rows.as<int32_t>(), (int32_t)st->nbig, out->off, out->hend,
+               out->nbr, nullptr, st->gbm.as<uint32_t>(), nullptr, st->bmk.as<uint32_t>());
     MM_TRY(hipGetLastError());
   }
+  return hipGetLastError();
+}
 #undef MM_BIG_ANY
 #undef MM_BIG
+
+hipError_t khop_fill_small(int32_t n, const int32_t* rp, const int32_t* col, const KhopDev& kh,
+                           KhopCount* st, DevBuf* off_small, DevBuf* nbr_small, hipStream_t s) {
+  if (st->k < 2) return hipErrorInvalidValue;
+  DevBuf c;
+  MM_TRY(c.alloc(sizeof(int32_t) * (size_t)n, s));
+  MM_TRY(off_small->alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  k_small_counts<<<(n + 255) / 256, 256, 0, s>>>(n, st->cnt.as<int32_t>(), st->big.as<int32_t>(),
+                                                 c.as<int32_t>());
+  MM_TRY(scan_excl_i32(c.as<int32_t>(), off_small->as<int64_t>(), n, s));
+  int64_t tot = 0;
+  MM_TRY(hipMemcpyAsync(&tot, off_small->as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipStreamSynchronize(s));
+  MM_TRY(nbr_small->alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1), s));
+  const unsigned gs = (unsigned)((n + KS_WAVES - 1) / KS_WAVES);
+  k_khop_small<true><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, st->k, off_small->as<int64_t>(),
+                                                 kh.hend, nbr_small->as<int32_t>(), nullptr,
+                                                 st->big.as<int32_t>());
   return hipGetLastError();
+}
+
+hipError_t khop_build(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, KhopDev* out,
+                      hipStream_t s) {
+  KhopCount st;
+  MM_TRY(khop_count(n, rp, col, k, out, &st, s));
+  return khop_fill(n, rp, col, out, &st, s);
 }
 
 }  // namespace mm

@@ -45,11 +45,11 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_tiles(
     int32_t n, int32_t k, int32_t tbits, int32_t ntw, const int64_t* __restrict__ off,
     const int32_t* __restrict__ hend, const int32_t* __restrict__ nbr,
     const float* __restrict__ sqrtc, float scale, int32_t* __restrict__ nch,
-    float* __restrict__ rho) {
+    float* __restrict__ rho, const int32_t* __restrict__ skip) {
   __shared__ uint32_t tbm[TB_WAVES][TB_MAXW];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t u = blockIdx.x * TB_WAVES + w;
-  if (u >= n) return;
+  if (u >= n || (skip && skip[u])) return;
   uint32_t* bm = tbm[w];
   for (int i = l; i < ntw; i += 64) bm[i] = 0u;
   wave_sync();
@@ -121,14 +121,14 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
     const int32_t* __restrict__ nbr, const int64_t* __restrict__ rc_ptr,
     int32_t* __restrict__ cm_tile, int32_t* __restrict__ cm_size, int32_t* __restrict__ cm_row,
     const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
-    uint16_t* __restrict__ ent) {
+    uint16_t* __restrict__ ent, const int32_t* __restrict__ skip) {
   // per wave, sized by the tile count: tile bitmap (ntw words), its popcount
   // prefix (ntw), per-tile counters (ntiles), with BASE the chunk starts
   // (ntiles int64, 8-byte aligned)
   extern __shared__ uint32_t tb_dyn[];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int32_t u = blockIdx.x * TB_WAVES + w;
-  if (u >= n) return;
+  if (u >= n || (skip && skip[u])) return;
   const size_t per = ((2 * (size_t)ntw + (size_t)ntiles + 1) & ~(size_t)1) +
                      (BASE ? 2 * (size_t)ntiles : 0);
   uint32_t* bm = tb_dyn + (size_t)w * per;
@@ -234,6 +234,248 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
         cm_row[rbase + r] = u;
         r++;
       }
+    }
+  }
+}
+
+// ---- rows read straight from the breadth-first search (direct build, k = 2)
+// A big row u = rows[r] has hop 1 = its CSR row (ascending) and hop 2 = the
+// set bits of its kept bitmap (bm + r * W, ascending), which is exactly its
+// canonical set; these kernels produce what the three passes above produce
+// for it from the canonical set, with the same results.
+
+constexpr int BT_STAGE = 2048;  // hop-2 ids of one 64-word step (at most 64 * 32)
+constexpr int32_t kDirectMaxTiles = 1024;  // LDS per wave: 12 B per tile
+
+// K1 for big rows: the row's entries per tile (dense, tcnt[r * ntiles + t]),
+// its tile count and, with RHO, rho_u.  With SQ (coarse levels) rho_u is
+// summed in k_row_tiles' order: lane l adds the entries at positions l,
+// l + 64, ... of each hop segment in turn, then a wave sum; the hop-2 ids of
+// each 64-word step are staged in LDS so that each reaches the lane of its
+// position.  Without SQ rho_u follows from the hop counts (same formula).
+template <bool RHO, bool SQ>
+__global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
+    int64_t nbig, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W,
+    const int32_t* __restrict__ hend, int32_t tbits, int32_t ntiles,
+    const float* __restrict__ sqrtc, float scale, int32_t* __restrict__ tcnt,
+    int32_t* __restrict__ nch, float* __restrict__ rho) {
+  extern __shared__ int32_t bt_dyn[];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int64_t r = (int64_t)blockIdx.x * TB_WAVES + w;
+  if (r >= nbig) return;
+  int32_t* ct = bt_dyn + (size_t)w * ((size_t)ntiles + (SQ ? BT_STAGE : 0));
+  int32_t* stage = ct + ntiles;
+  const int32_t u = rows[r];
+  for (int32_t t = l; t < ntiles; t += 64) ct[t] = 0;
+  wave_sync();
+  const int32_t b = rp[u], d = rp[u + 1] - b;
+  const float su = SQ ? sqrtc[u] : 0.f;
+  float acc = 0.f;
+  // hop 1: in a 64-entry step of the ascending row a tile's entries are one run
+  for (int32_t i0 = 0; i0 < d; i0 += 64) {
+    const int32_t i = i0 + l;
+    const bool valid = i < d;
+    const int32_t v = valid ? col[b + i] : 0;
+    if (SQ && valid) {
+      const float dd = (float)1 * (su + sqrtc[v]) * scale;
+      acc += 1.f / (dd * dd);
+    }
+    const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
+    const int32_t tprev = __shfl_up(t, 1, 64);
+    const bool start = valid && (l == 0 || tprev != t);
+    const int32_t rs = wave_incl_max(start ? l : -1);
+    const int32_t tnext = __shfl_down(t, 1, 64);
+    const bool end = valid && (l == 63 || i + 1 >= d || tnext != t);
+    if (end) ct[t] += l - rs + 1;
+    wave_sync();
+  }
+  // hop 2: 64-word steps (each inside one tile: a tile has >= 64 words),
+  // four steps loaded at a time
+  const uint32_t* __restrict__ brow = bm + (size_t)r * (size_t)W;
+  const int32_t tsh = tbits - 5;
+  int32_t P = 0;  // hop-2 entries before the step
+  for (int32_t w0 = 0; w0 < W; w0 += 256) {
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int32_t wi = w0 + 64 * j + l;
+      x[j] = wi < W ? brow[wi] : 0u;
+    }
+    if (!SQ) {
+      int32_t cur = 0, curt = w0 >> tsh;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t wj = w0 + 64 * j;
+        if (wj >= W) break;
+        if ((wj >> tsh) != curt) {
+          const int32_t c = wave_sum(cur);
+          if (l == 0) ct[curt] += c;
+          cur = 0;
+          curt = wj >> tsh;
+        }
+        cur += __popc(x[j]);
+      }
+      const int32_t c = wave_sum(cur);
+      if (l == 0) ct[curt] += c;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t wj = w0 + 64 * j;
+        if (wj >= W) break;
+        const int32_t pc = __popc(x[j]);
+        const int32_t inc = wave_incl_scan(pc);
+        const int32_t tot = __shfl(inc, 63, 64);
+        if (tot == 0) continue;
+        int32_t pos = inc - pc;
+        uint32_t xx = x[j];
+        while (xx) {
+          const int bit = __ffs(xx) - 1;
+          xx &= xx - 1;
+          stage[pos++] = ((wj + l) << 5) + bit;
+        }
+        wave_sync();
+        for (int32_t q = (l - P) & 63; q < tot; q += 64) {
+          const float dd = (float)2 * (su + sqrtc[stage[q]]) * scale;
+          acc += 1.f / (dd * dd);
+        }
+        if (l == 0) ct[wj >> tsh] += tot;
+        P += tot;
+        wave_sync();
+      }
+    }
+  }
+  wave_sync();
+  int32_t nt = 0;
+  int32_t* __restrict__ trow = tcnt + (size_t)r * (size_t)ntiles;
+  for (int32_t t = l; t < ntiles; t += 64) {
+    const int32_t c = ct[t];
+    trow[t] = c;
+    nt += c > 0 ? 1 : 0;
+  }
+  nt = wave_sum(nt);
+  if (l == 0) nch[u] = nt;
+  if (RHO) {
+    if (SQ) {
+      acc = wave_sum(acc);
+      if (l == 0) rho[u] = acc;
+    } else if (l == 0) {
+      int32_t prev = 0;
+      float rr = 0.f;
+      for (int h = 1; h <= 2; ++h) {
+        const int32_t e = hend[(int64_t)u * 2 + h - 1];
+        rr += (float)(e - prev) / (float)(h * h);
+        prev = e;
+      }
+      rho[u] = rr;
+    }
+  }
+}
+
+// K3 for big rows: the row-major chunk slots (tile, size, row) in tile order
+__global__ __launch_bounds__(64 * TB_WAVES) void k_big_slots(
+    int64_t nbig, const int32_t* __restrict__ rows, int32_t ntiles,
+    const int32_t* __restrict__ tcnt, const int64_t* __restrict__ rc_ptr,
+    int32_t* __restrict__ cm_tile, int32_t* __restrict__ cm_size, int32_t* __restrict__ cm_row) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int64_t r = (int64_t)blockIdx.x * TB_WAVES + w;
+  if (r >= nbig) return;
+  const int32_t u = rows[r];
+  const int64_t rbase = rc_ptr[u];
+  const int32_t* __restrict__ trow = tcnt + (size_t)r * (size_t)ntiles;
+  int32_t run = 0;
+  for (int32_t t0 = 0; t0 < ntiles; t0 += 64) {
+    const int32_t t = t0 + l;
+    const int32_t c = t < ntiles ? trow[t] : 0;
+    const uint64_t m = __ballot(c > 0);
+    const int32_t rank = run + __popcll(m & lanemask_lt());
+    if (c > 0) {
+      cm_tile[rbase + rank] = t;
+      cm_size[rbase + rank] = c;
+      cm_row[rbase + rank] = u;
+    }
+    run += __popcll(m);
+  }
+}
+
+// K6 for big rows: the 16-bit entries, per chunk hop 1 then hop 2, each
+// ascending (the canonical order restricted to the tile).  Per wave in LDS:
+// the start of each touched tile's chunk (int64) and its fill count.
+__global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
+    int64_t nbig, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W, int32_t tbits,
+    int32_t ntiles, const int32_t* __restrict__ tcnt, const int64_t* __restrict__ rc_ptr,
+    const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
+    uint16_t* __restrict__ ent) {
+  extern __shared__ int64_t bf_dyn[];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int64_t r = (int64_t)blockIdx.x * TB_WAVES + w;
+  if (r >= nbig) return;
+  const size_t per = (size_t)ntiles + (((size_t)ntiles + 1) >> 1);  // int64 units
+  int64_t* base = bf_dyn + (size_t)w * per;
+  int32_t* ct = reinterpret_cast<int32_t*>(base + ntiles);
+  const int32_t u = rows[r];
+  const int64_t rbase = rc_ptr[u];
+  const int32_t* __restrict__ trow = tcnt + (size_t)r * (size_t)ntiles;
+  int32_t run = 0;
+  for (int32_t t0 = 0; t0 < ntiles; t0 += 64) {
+    const int32_t t = t0 + l;
+    const int32_t c = t < ntiles ? trow[t] : 0;
+    const uint64_t m = __ballot(c > 0);
+    const int32_t rank = run + __popcll(m & lanemask_lt());
+    if (t < ntiles) {
+      ct[t] = 0;
+      if (c > 0) base[t] = chunk_off[pos_of_slot[rbase + rank]];
+    }
+    run += __popcll(m);
+  }
+  wave_sync();
+  const int32_t lo = (1 << tbits) - 1;
+  const int32_t b = rp[u], d = rp[u + 1] - b;
+  for (int32_t i0 = 0; i0 < d; i0 += 64) {
+    const int32_t i = i0 + l;
+    const bool valid = i < d;
+    const int32_t v = valid ? col[b + i] : 0;
+    const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
+    const int32_t tprev = __shfl_up(t, 1, 64);
+    const bool start = valid && (l == 0 || tprev != t);
+    const int32_t rs = wave_incl_max(start ? l : -1);
+    const int32_t tnext = __shfl_down(t, 1, 64);
+    const bool end = valid && (l == 63 || i + 1 >= d || tnext != t);
+    if (valid) ent[base[t] + ct[t] + (l - rs)] = (uint16_t)(((v & lo) << 3) | 1);
+    wave_sync();
+    if (end) ct[t] += l - rs + 1;
+    wave_sync();
+  }
+  const uint32_t* __restrict__ brow = bm + (size_t)r * (size_t)W;
+  const int32_t tsh = tbits - 5;
+  for (int32_t w0 = 0; w0 < W; w0 += 256) {
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int32_t wi = w0 + 64 * j + l;
+      x[j] = wi < W ? brow[wi] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int32_t wj = w0 + 64 * j;
+      if (wj >= W) break;
+      const int32_t pc = __popc(x[j]);
+      const int32_t inc = wave_incl_scan(pc);
+      const int32_t tot = __shfl(inc, 63, 64);
+      if (tot == 0) continue;
+      const int32_t t = wj >> tsh;
+      int64_t pos = base[t] + ct[t] + (inc - pc);
+      uint32_t xx = x[j];
+      while (xx) {
+        const int bit = __ffs(xx) - 1;
+        xx &= xx - 1;
+        const int32_t v = ((wj + l) << 5) + bit;
+        ent[pos++] = (uint16_t)(((v & lo) << 3) | 2);
+      }
+      wave_sync();
+      if (l == 0) ct[t] += tot;
+      wave_sync();
     }
   }
 }
@@ -404,9 +646,29 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
   return hipGetLastError();
 }
 
-hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
-                       hipStream_t s, const float* sqrtc, double scale, float* rho, bool sliced) {
-  const int32_t n = kh.n;
+namespace {
+
+// Where the rows' entries come from: the canonical lists (off, nbr) for
+// every row not flagged in skip; the flagged ("big") rows, listed in rows,
+// from their CSR row (hop 1) and kept hop-2 bitmap (bm + r * W).
+struct TileSrc {
+  int32_t n = 0, k = 0;
+  int64_t total = 0;
+  const int64_t* off = nullptr;
+  const int32_t* hend = nullptr;
+  const int32_t* nbr = nullptr;
+  const int32_t* skip = nullptr;
+  int64_t nbig = 0;
+  const int32_t* rows = nullptr;
+  const uint32_t* bm = nullptr;
+  int32_t W = 0;
+  const int32_t* rp = nullptr;
+  const int32_t* col = nullptr;
+};
+
+hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chunk, TiledSet* ts,
+                           hipStream_t s, const float* sqrtc, double scale, float* rho, bool sliced) {
+  const int32_t n = src.n;
   const int32_t ntiles = (int32_t)(((int64_t)n + (1 << tbits) - 1) >> tbits);
   const int32_t ntw = (ntiles + 31) >> 5;
   ts->n = n;
@@ -418,18 +680,37 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   ts->rc_ptr = ts->b_rc_ptr.as<int64_t>();
   if (rho)
     k_row_tiles<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
-        n, kh.k, tbits, ntw, kh.off, kh.hend, kh.nbr, sqrtc, (float)scale, nch.as<int32_t>(), rho);
+        n, src.k, tbits, ntw, src.off, src.hend, src.nbr, sqrtc, (float)scale, nch.as<int32_t>(), rho,
+        src.skip);
   else
     k_row_tiles<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
-        n, kh.k, tbits, ntw, kh.off, kh.hend, kh.nbr, nullptr, 1.f, nch.as<int32_t>(), nullptr);
+        n, src.k, tbits, ntw, src.off, src.hend, src.nbr, nullptr, 1.f, nch.as<int32_t>(), nullptr,
+        src.skip);
   MM_TRY(hipGetLastError());
+  // big rows: entries per tile (dense, kept for the slot and fill passes)
+  DevBuf tcnt;
+  const unsigned gbig = (unsigned)((src.nbig + TB_WAVES - 1) / TB_WAVES);
+  if (src.nbig > 0) {
+    MM_TRY(tcnt.alloc(sizeof(int32_t) * (size_t)src.nbig * (size_t)ntiles, s));
+    const bool sq = rho && sqrtc;
+    const size_t shm = sizeof(int32_t) * TB_WAVES * ((size_t)ntiles + (sq ? BT_STAGE : 0));
+#define MM_BT(R, Q)                                                                            \
+  k_big_tiles<R, Q><<<gbig, 64 * TB_WAVES, shm, s>>>(                                          \
+      src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.hend, tbits, ntiles, sqrtc,      \
+      (float)scale, tcnt.as<int32_t>(), nch.as<int32_t>(), rho)
+    if (sq) MM_BT(true, true);
+    else if (rho) MM_BT(true, false);
+    else MM_BT(false, false);
+#undef MM_BT
+    MM_TRY(hipGetLastError());
+  }
   MM_TRY(scan_excl_i32(nch.as<int32_t>(), ts->rc_ptr, n, s));
   int64_t m = 0;
   MM_TRY(hipMemcpyAsync(&m, ts->rc_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
   if (m >= (1ll << 31)) return hipErrorInvalidValue;
   ts->nchunks = m;
-  ts->avg_chunk = (double)kh.total / (double)std::max<int64_t>(m, 1);
+  ts->avg_chunk = (double)src.total / (double)std::max<int64_t>(m, 1);
   ts->built = false;
   if (ts->avg_chunk < min_avg_chunk) return hipSuccess;  // chunks too short to pay off
   MM_TRY(cm_tile.alloc(sizeof(int32_t) * (size_t)m, s));
@@ -447,9 +728,15 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tb_shm));
   }
   k_row_chunks<false, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
-      n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, cm_tile.as<int32_t>(),
-      cm_size.as<int32_t>(), cm_row.as<int32_t>(), nullptr, nullptr, nullptr);
+      n, src.k, tbits, ntiles, ntw, src.off, src.hend, src.nbr, ts->rc_ptr, cm_tile.as<int32_t>(),
+      cm_size.as<int32_t>(), cm_row.as<int32_t>(), nullptr, nullptr, nullptr, src.skip);
   MM_TRY(hipGetLastError());
+  if (src.nbig > 0) {
+    k_big_slots<<<gbig, 64 * TB_WAVES, 0, s>>>(src.nbig, src.rows, ntiles, tcnt.as<int32_t>(),
+                                               ts->rc_ptr, cm_tile.as<int32_t>(),
+                                               cm_size.as<int32_t>(), cm_row.as<int32_t>());
+    MM_TRY(hipGetLastError());
+  }
   // order chunks by (tile, row): stable sort of row-major slots by tile
   MM_TRY(skeys.alloc(sizeof(uint64_t) * (size_t)m, s));
   MM_TRY(svals.alloc(sizeof(int32_t) * (size_t)m, s));
@@ -522,13 +809,20 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(hipMemsetAsync(cons.p, 0, sizeof(uint16_t) * (size_t)padded, s));
   if (use_base)
     k_row_chunks<true, true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm_base, s>>>(
-        n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
-        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
+        n, src.k, tbits, ntiles, ntw, src.off, src.hend, src.nbr, ts->rc_ptr, nullptr, nullptr,
+        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>(), src.skip);
   else
     k_row_chunks<true, false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm, s>>>(
-        n, kh.k, tbits, ntiles, ntw, kh.off, kh.hend, kh.nbr, ts->rc_ptr, nullptr, nullptr,
-        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
+        n, src.k, tbits, ntiles, ntw, src.off, src.hend, src.nbr, ts->rc_ptr, nullptr, nullptr,
+        nullptr, pos_of_slot, ts->chunk_off, cons.as<uint16_t>(), src.skip);
   MM_TRY(hipGetLastError());
+  if (src.nbig > 0) {
+    const size_t shm = sizeof(int64_t) * TB_WAVES * ((size_t)ntiles + (((size_t)ntiles + 1) >> 1));
+    k_big_fill<<<gbig, 64 * TB_WAVES, shm, s>>>(src.nbig, src.rows, src.rp, src.col, src.bm, src.W,
+                                               tbits, ntiles, tcnt.as<int32_t>(), ts->rc_ptr,
+                                               pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
+    MM_TRY(hipGetLastError());
+  }
   if (sliced) {
     padded = sl_blocks * 8;
     MM_TRY(ts->b_ent.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
@@ -538,7 +832,7 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
     MM_TRY(hipGetLastError());
   }  // the staging copy is freed (stream-ordered) on return
   ts->ent = ts->b_ent.as<uint16_t>();
-  ts->total = kh.total;
+  ts->total = src.total;
   ts->padded = padded;
   // work units: chunks (tiled) or slices (sliced) of one tile
   const int64_t mu = sliced ? nsl : m;
@@ -576,6 +870,50 @@ hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, T
   MM_TRY(ts->b_partial.alloc(sizeof(float2) * (size_t)m, s));
   ts->built = true;
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
+                       hipStream_t s, const float* sqrtc, double scale, float* rho, bool sliced) {
+  TileSrc src;
+  src.n = kh.n;
+  src.k = kh.k;
+  src.total = kh.total;
+  src.off = kh.off;
+  src.hend = kh.hend;
+  src.nbr = kh.nbr;
+  return tiled_build_src(src, tbits, min_avg_chunk, ts, s, sqrtc, scale, rho, sliced);
+}
+
+bool tiled_direct_ok(const KhopDev& kh, const KhopCount& st, int32_t tbits) {
+  const int64_t ntiles = ((int64_t)kh.n + (1 << tbits) - 1) >> tbits;
+  // dense per-tile counts of the big rows: at most 2 GB
+  return kh.k == 2 && st.k == 2 && st.keep && st.nbig > 0 && tiled_eligible(kh, tbits) &&
+         ntiles <= kDirectMaxTiles && st.nbig * ntiles * 4 <= (int64_t)2 << 30;
+}
+
+hipError_t tiled_build_direct(const KhopDev& kh, const KhopCount& st, const int32_t* row_ptr,
+                              const int32_t* col, const int64_t* off_small,
+                              const int32_t* nbr_small, int32_t tbits, double min_avg_chunk,
+                              TiledSet* ts, hipStream_t s, const float* sqrtc, double scale,
+                              float* rho, bool sliced) {
+  if (!tiled_direct_ok(kh, st, tbits)) return hipErrorInvalidValue;
+  TileSrc src;
+  src.n = kh.n;
+  src.k = kh.k;
+  src.total = kh.total;
+  src.off = off_small;
+  src.hend = kh.hend;
+  src.nbr = nbr_small;
+  src.skip = st.big.as<int32_t>();
+  src.nbig = st.nbig;
+  src.rows = st.rows.as<int32_t>();
+  src.bm = st.bmk.as<uint32_t>();
+  src.W = st.W;
+  src.rp = row_ptr;
+  src.col = col;
+  return tiled_build_src(src, tbits, min_avg_chunk, ts, s, sqrtc, scale, rho, sliced);
 }
 
 }  // namespace mm
