@@ -115,7 +115,7 @@ struct KhopCount {
   int32_t k = 0, W = 0, slots = 0;
   int64_t nbig = 0;
   size_t shm = 0;
-  bool lds_bm = false, one = false, keep = false;
+  bool lds_bm = false, one = false, keep = false, test = false;
   DevBuf cnt, big, bigpos, rows, bmk, gbm, gscr;
 };
 hipError_t khop_count(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,

@@ -160,7 +160,9 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
 // KEEP (with ONE, when device memory allows): the counting pass stores each
 // row's final hop-2 bitmap (n bits per big row, row r at bmkeep + r * W) and
 // the filling pass extracts from it instead of marking again.
-template <bool FILL, bool LDSBM, bool ONE, bool KEEP>
+// TEST (with ONE): read a candidate's bit before setting it; pays on dense
+// graphs, where most candidates of a row are marked many times.
+template <bool FILL, bool LDSBM, bool ONE, bool KEEP, bool TEST>
 __global__ __launch_bounds__(KB_T) void k_khop_big(
     int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t k,
     const int32_t* __restrict__ rows, int32_t nrows, const int64_t* __restrict__ off,
@@ -205,79 +207,85 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     const uint32_t* kept = LOAD ? bmkeep + (size_t)r * (size_t)W : nullptr;
     for (int h = 2; h <= k; ++h) {
       // mark neighbours of the frontier not yet visited.  The marks are
-      // bound by the latency of the neighbour loads, and most of them come
-      // from the few long lists of high-degree vertices (a vertex of degree
-      // d lies in d rows' frontiers and costs d marks in each), so:
+      // bound by the latency of the neighbour loads and by the instructions
+      // around each mark, and most of them come from the few long lists of
+      // high-degree vertices (a vertex of degree d lies in d rows'
+      // frontiers and costs d marks in each), so:
       //  * a wave takes KB_U frontier vertices at a time and issues their row
       //    bounds and first 64 neighbour loads before marking any;
       //  * the rest of a list is loaded KB_V steps of 64 at a time;
       //  * lists longer than KB_HUB are set aside and marked afterwards by
       //    the whole workgroup, KB_T * KB_V entries per round, so that one
-      //    long list does not hold the row on one wave.
+      //    long list does not hold the row on one wave;
+      //  * list bounds are wave-uniform; loads past a list's end read its
+      //    last entry instead, so loads need no lane masks, and only the
+      //    marks of a list's last, partial step are masked (marking the
+      //    clamped copies would send many lanes' atomics to one LDS word,
+      //    which serialises them).
       // Bits are only ever set, so the order of the marks does not matter.
       auto mark = [&](int32_t v) {
         const uint32_t bit = 1u << (v & 31);
         if (ONE) {
-          if (!(NEW[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
+          if (!TEST || !(NEW[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
         } else {
           if (!(VIS[v >> 5] & bit)) atomicOr(&NEW[v >> 5], bit);
         }
       };
-      for (int32_t i0 = wv * KB_U; i0 < flen && !LOAD; i0 += KB_NW * KB_U) {
-        int32_t b0[KB_U], b1[KB_U], v0[KB_U];
+      // entries [e0, len) of the list cb, stride S, this thread's offset me
+      auto mark_list = [&](const int32_t* __restrict__ cb, int32_t e0, int32_t len, int32_t S,
+                           int32_t me) {
+        for (; e0 + S * KB_V <= len; e0 += S * KB_V) {
+          int32_t vv[KB_V];
+#pragma unroll
+          for (int j = 0; j < KB_V; ++j) vv[j] = cb[e0 + S * j + me];
+#pragma unroll
+          for (int j = 0; j < KB_V; ++j) mark(vv[j]);
+        }
+        if (e0 < len) {
+          int32_t vv[KB_V];
+#pragma unroll
+          for (int j = 0; j < KB_V; ++j) vv[j] = cb[min(e0 + S * j + me, len - 1)];
+#pragma unroll
+          for (int j = 0; j < KB_V; ++j)
+            if (e0 + S * j + me < len) mark(vv[j]);
+        }
+      };
+      const int32_t wvu = __builtin_amdgcn_readfirstlane(wv);
+      for (int32_t i0 = wvu * KB_U; i0 < flen && !LOAD; i0 += KB_NW * KB_U) {
+        int32_t b0[KB_U], len[KB_U], v0[KB_U];
 #pragma unroll
         for (int uu = 0; uu < KB_U; ++uu) {
-          const int32_t x = i0 + uu < flen ? F[i0 + uu] : -1;
-          b0[uu] = x >= 0 ? rp[x] : 0;
-          b1[uu] = x >= 0 ? rp[x + 1] : 0;
-          if (b1[uu] - b0[uu] > KB_HUB) {
-            // wave-uniform: defer to the workgroup unless the list is full
+          const int32_t x = i0 + uu < flen ? __builtin_amdgcn_readfirstlane(F[i0 + uu]) : -1;
+          b0[uu] = x >= 0 ? __builtin_amdgcn_readfirstlane(rp[x]) : 0;
+          len[uu] = x >= 0 ? __builtin_amdgcn_readfirstlane(rp[x + 1]) - b0[uu] : 0;
+          if (len[uu] > KB_HUB) {
+            // defer to the workgroup unless the list is full
             int32_t slot = 0;
             if (l == 0) slot = atomicAdd(&nhub, 1);
-            slot = __shfl(slot, 0, 64);
+            slot = __builtin_amdgcn_readfirstlane(__shfl(slot, 0, 64));
             if (slot < KB_HUBCAP) {
               if (l == 0) hubs[slot] = x;
-              b1[uu] = b0[uu];
+              len[uu] = 0;
             }
           }
         }
-#pragma unroll
-        for (int uu = 0; uu < KB_U; ++uu) v0[uu] = b0[uu] + l < b1[uu] ? col[b0[uu] + l] : -1;
 #pragma unroll
         for (int uu = 0; uu < KB_U; ++uu)
-          if (v0[uu] >= 0) mark(v0[uu]);
+          if (len[uu] > 0) v0[uu] = col[b0[uu] + min(l, len[uu] - 1)];
 #pragma unroll
-        for (int uu = 0; uu < KB_U; ++uu) {
-          for (int32_t e0 = b0[uu] + 64; e0 < b1[uu]; e0 += 64 * KB_V) {
-            int32_t vv[KB_V];
+        for (int uu = 0; uu < KB_U; ++uu)
+          if (l < len[uu]) mark(v0[uu]);
 #pragma unroll
-            for (int j = 0; j < KB_V; ++j) {
-              const int32_t e = e0 + 64 * j + l;
-              vv[j] = e < b1[uu] ? col[e] : -1;
-            }
-#pragma unroll
-            for (int j = 0; j < KB_V; ++j)
-              if (vv[j] >= 0) mark(vv[j]);
-          }
-        }
+        for (int uu = 0; uu < KB_U; ++uu)
+          if (len[uu] > 64) mark_list(col + b0[uu], 64, len[uu], 64, l);
       }
       __syncthreads();
       if (!LOAD) {
         const int32_t nh = min(nhub, KB_HUBCAP);
         for (int32_t j = 0; j < nh; ++j) {
-          const int32_t x = hubs[j];
-          const int32_t e1 = rp[x + 1];
-          for (int32_t e0 = rp[x]; e0 < e1; e0 += KB_T * KB_V) {
-            int32_t vv[KB_V];
-#pragma unroll
-            for (int jj = 0; jj < KB_V; ++jj) {
-              const int32_t e = e0 + KB_T * jj + t;
-              vv[jj] = e < e1 ? col[e] : -1;
-            }
-#pragma unroll
-            for (int jj = 0; jj < KB_V; ++jj)
-              if (vv[jj] >= 0) mark(vv[jj]);
-          }
+          const int32_t x = __builtin_amdgcn_readfirstlane(hubs[j]);
+          const int32_t e0 = __builtin_amdgcn_readfirstlane(rp[x]);
+          mark_list(col + e0, 0, __builtin_amdgcn_readfirstlane(rp[x + 1]) - e0, KB_T, t);
         }
         __syncthreads();
         if (t == 0) nhub = 0;
@@ -362,6 +370,21 @@ __global__ void k_hop1(int32_t n, const int32_t* rp, int32_t* hend, int32_t* cnt
   if (u < n) { int32_t d = rp[u + 1] - rp[u]; hend[u] = d; cnt[u] = d; }
 }
 
+// sum over vertices of deg^2 (the candidate marks of all rows' 2-hop searches)
+__global__ __launch_bounds__(256) void k_sum_deg2(int32_t n, const int32_t* rp,
+                                                  unsigned long long* out) {
+  __shared__ unsigned long long part[4];
+  unsigned long long a = 0;
+  for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
+    const unsigned long long d = (unsigned long long)(rp[u + 1] - rp[u]);
+    a += d * d;
+  }
+  a = wave_sum(a);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
 // counts of the rows the small-row kernel filled (0 for bitmap rows)
 __global__ void k_small_counts(int32_t n, const int32_t* cnt, const int32_t* big, int32_t* out) {
   int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,10 +419,21 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
                                                   st->cnt.as<int32_t>(), st->big.as<int32_t>());
   MM_TRY(hipGetLastError());
   MM_TRY(scan_excl_i32(st->big.as<int32_t>(), st->bigpos.as<int64_t>(), n, s));
+  DevBuf d2;
+  MM_TRY(d2.alloc(sizeof(unsigned long long), s));
+  MM_TRY(hipMemsetAsync(d2.p, 0, sizeof(unsigned long long), s));
+  k_sum_deg2<<<(unsigned)std::min<int64_t>(1024, ((int64_t)n + 255) / 256), 256, 0, s>>>(
+      n, rp, d2.as<unsigned long long>());
+  MM_TRY(hipGetLastError());
   int64_t nbig = 0;
+  unsigned long long sdeg2 = 0;
   MM_TRY(hipMemcpyAsync(&nbig, st->bigpos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_TRY(hipMemcpyAsync(&sdeg2, d2.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   MM_TRY(hipStreamSynchronize(s));
   st->nbig = nbig;
+  // candidate marks per row (sum deg^2 / n) of at least n: most candidates
+  // repeat, and reading the bit first saves their atomics
+  st->test = (double)sdeg2 >= (double)n * (double)n;
   const int32_t W = (n + 31) >> 5;
   st->W = W;
   const bool one = (k == 2);
@@ -441,24 +475,32 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
                    (long long)nbig, kb / 1e9, freeb / 1e9, keep ? "kept" : "rebuilt");
   }
   st->keep = keep;
-#define MM_BIG(FILLV, LDSV, ONEV, KEEPV, ...)                                                   \
+#define MM_BIG(FILLV, LDSV, ONEV, KEEPV, TESTV, ...)                                            \
   do {                                                                                         \
     if (LDSV)                                                                                  \
       MM_TRY(hipFuncSetAttribute(                                                              \
-          reinterpret_cast<const void*>(&k_khop_big<FILLV, LDSV, ONEV, KEEPV>),                \
+          reinterpret_cast<const void*>(&k_khop_big<FILLV, LDSV, ONEV, KEEPV, TESTV>),         \
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->shm));                          \
-    k_khop_big<FILLV, LDSV, ONEV, KEEPV><<<st->slots, KB_T, LDSV ? st->shm : 0, s>>>(__VA_ARGS__); \
+    k_khop_big<FILLV, LDSV, ONEV, KEEPV, TESTV><<<st->slots, KB_T, LDSV ? st->shm : 0, s>>>(   \
+        __VA_ARGS__);                                                                          \
+  } while (0)
+// the filling passes either extract kept bitmaps or mark again (then TEST
+// changes nothing but the speed: always on there)
+#define MM_BIG_ONE(FILLV, LDSV, KEEPV, ...)                                             \
+  do {                                                                                 \
+    if (!FILLV && !st->test) MM_BIG(FILLV, LDSV, true, KEEPV, false, __VA_ARGS__);     \
+    else MM_BIG(FILLV, LDSV, true, KEEPV, true, __VA_ARGS__);                          \
   } while (0)
 #define MM_BIG_ANY(FILLV, ...)                                                          \
   do {                                                                                 \
     if (st->lds_bm) {                                                                  \
-      if (st->one && st->keep) MM_BIG(FILLV, true, true, true, __VA_ARGS__);           \
-      else if (st->one) MM_BIG(FILLV, true, true, false, __VA_ARGS__);                 \
-      else MM_BIG(FILLV, true, false, false, __VA_ARGS__);                             \
+      if (st->one && st->keep) MM_BIG_ONE(FILLV, true, true, __VA_ARGS__);             \
+      else if (st->one) MM_BIG_ONE(FILLV, true, false, __VA_ARGS__);                   \
+      else MM_BIG(FILLV, true, false, false, true, __VA_ARGS__);                       \
     } else {                                                                           \
-      if (st->one && st->keep) MM_BIG(FILLV, false, true, true, __VA_ARGS__);          \
-      else if (st->one) MM_BIG(FILLV, false, true, false, __VA_ARGS__);                \
-      else MM_BIG(FILLV, false, false, false, __VA_ARGS__);                            \
+      if (st->one && st->keep) MM_BIG_ONE(FILLV, false, true, __VA_ARGS__);            \
+      else if (st->one) MM_BIG_ONE(FILLV, false, false, __VA_ARGS__);                  \
+      else MM_BIG(FILLV, false, false, false, true, __VA_ARGS__);                      \
     }                                                                                  \
   } while (0)
   if (nbig > 0) {
@@ -501,6 +543,7 @@ hipError_t khop_fill(int32_t n, const int32_t* rp, const int32_t* col, KhopDev* 
   return hipGetLastError();
 }
 #undef MM_BIG_ANY
+#undef MM_BIG_ONE
 #undef MM_BIG
 
 hipError_t khop_fill_small(int32_t n, const int32_t* rp, const int32_t* col, const KhopDev& kh,
