@@ -156,8 +156,10 @@ hipError_t compute_rho(const KhopDev& kh, const float* sqrtc, double scale, floa
                        hipStream_t s);
 // Builds the tile-major copy of kh; when the mean chunk length is below
 // min_avg_chunk it stops after counting (ts->built stays false).  With rho
-// non-null it also computes compute_rho's result (same bits) in its first
-// pass over the sets, built or not.
+// non-null and the copy built it also fills rho_u: on the finest level
+// (sqrtc null) from the hop counts (compute_rho's bits), on coarse levels
+// as per-chunk sums added per row in slot order (the same value up to
+// rounding order).
 // sliced: the sliced layout (k_sweep_sliced) instead of consecutive chunks.
 hipError_t tiled_build(const KhopDev& kh, int32_t tbits, double min_avg_chunk, TiledSet* ts,
                        hipStream_t s, const float* sqrtc = nullptr, double scale = 1.0,

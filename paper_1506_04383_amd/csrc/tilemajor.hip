@@ -244,43 +244,31 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
 // canonical set; these kernels produce what the three passes above produce
 // for it from the canonical set, with the same results.
 
-constexpr int BT_STAGE = 2048;  // hop-2 ids of one 64-word step (at most 64 * 32)
 constexpr int32_t kDirectMaxTiles = 1024;  // LDS per wave: 12 B per tile
 
-// K1 for big rows: the row's entries per tile (dense, tcnt[r * ntiles + t]),
-// its tile count and, with RHO, rho_u.  With SQ (coarse levels) rho_u is
-// summed in k_row_tiles' order: lane l adds the entries at positions l,
-// l + 64, ... of each hop segment in turn, then a wave sum; the hop-2 ids of
-// each 64-word step are staged in LDS so that each reaches the lane of its
-// position.  Without SQ rho_u follows from the hop counts (same formula).
-template <bool RHO, bool SQ>
+// K1 for big rows: the row's entries per tile (dense, tcnt[r * ntiles + t])
+// and its tile count; with RHO (finest level) also rho_u from the hop counts
+// (k_row_tiles' formula).
+template <bool RHO>
 __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
     int64_t nbig, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W,
-    const int32_t* __restrict__ hend, int32_t tbits, int32_t ntiles,
-    const float* __restrict__ sqrtc, float scale, int32_t* __restrict__ tcnt,
+    const int32_t* __restrict__ hend, int32_t tbits, int32_t ntiles, int32_t* __restrict__ tcnt,
     int32_t* __restrict__ nch, float* __restrict__ rho) {
   extern __shared__ int32_t bt_dyn[];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int64_t r = (int64_t)blockIdx.x * TB_WAVES + w;
   if (r >= nbig) return;
-  int32_t* ct = bt_dyn + (size_t)w * ((size_t)ntiles + (SQ ? BT_STAGE : 0));
-  int32_t* stage = ct + ntiles;
+  int32_t* ct = bt_dyn + (size_t)w * (size_t)ntiles;
   const int32_t u = rows[r];
   for (int32_t t = l; t < ntiles; t += 64) ct[t] = 0;
   wave_sync();
   const int32_t b = rp[u], d = rp[u + 1] - b;
-  const float su = SQ ? sqrtc[u] : 0.f;
-  float acc = 0.f;
   // hop 1: in a 64-entry step of the ascending row a tile's entries are one run
   for (int32_t i0 = 0; i0 < d; i0 += 64) {
     const int32_t i = i0 + l;
     const bool valid = i < d;
     const int32_t v = valid ? col[b + i] : 0;
-    if (SQ && valid) {
-      const float dd = (float)1 * (su + sqrtc[v]) * scale;
-      acc += 1.f / (dd * dd);
-    }
     const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
     const int32_t tprev = __shfl_up(t, 1, 64);
     const bool start = valid && (l == 0 || tprev != t);
@@ -291,10 +279,9 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
     wave_sync();
   }
   // hop 2: 64-word steps (each inside one tile: a tile has >= 64 words),
-  // four steps loaded at a time
+  // four steps loaded at a time, one wave sum per tile and group of steps
   const uint32_t* __restrict__ brow = bm + (size_t)r * (size_t)W;
   const int32_t tsh = tbits - 5;
-  int32_t P = 0;  // hop-2 entries before the step
   for (int32_t w0 = 0; w0 < W; w0 += 256) {
     uint32_t x[4];
 #pragma unroll
@@ -302,48 +289,21 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
       const int32_t wi = w0 + 64 * j + l;
       x[j] = wi < W ? brow[wi] : 0u;
     }
-    if (!SQ) {
-      int32_t cur = 0, curt = w0 >> tsh;
+    int32_t cur = 0, curt = w0 >> tsh;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int32_t wj = w0 + 64 * j;
-        if (wj >= W) break;
-        if ((wj >> tsh) != curt) {
-          const int32_t c = wave_sum(cur);
-          if (l == 0) ct[curt] += c;
-          cur = 0;
-          curt = wj >> tsh;
-        }
-        cur += __popc(x[j]);
+    for (int j = 0; j < 4; ++j) {
+      const int32_t wj = w0 + 64 * j;
+      if (wj >= W) break;
+      if ((wj >> tsh) != curt) {
+        const int32_t c = wave_sum(cur);
+        if (l == 0) ct[curt] += c;
+        cur = 0;
+        curt = wj >> tsh;
       }
-      const int32_t c = wave_sum(cur);
-      if (l == 0) ct[curt] += c;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int32_t wj = w0 + 64 * j;
-        if (wj >= W) break;
-        const int32_t pc = __popc(x[j]);
-        const int32_t inc = wave_incl_scan(pc);
-        const int32_t tot = __shfl(inc, 63, 64);
-        if (tot == 0) continue;
-        int32_t pos = inc - pc;
-        uint32_t xx = x[j];
-        while (xx) {
-          const int bit = __ffs(xx) - 1;
-          xx &= xx - 1;
-          stage[pos++] = ((wj + l) << 5) + bit;
-        }
-        wave_sync();
-        for (int32_t q = (l - P) & 63; q < tot; q += 64) {
-          const float dd = (float)2 * (su + sqrtc[stage[q]]) * scale;
-          acc += 1.f / (dd * dd);
-        }
-        if (l == 0) ct[wj >> tsh] += tot;
-        P += tot;
-        wave_sync();
-      }
+      cur += __popc(x[j]);
     }
+    const int32_t c = wave_sum(cur);
+    if (l == 0) ct[curt] += c;
   }
   wave_sync();
   int32_t nt = 0;
@@ -355,20 +315,15 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
   }
   nt = wave_sum(nt);
   if (l == 0) nch[u] = nt;
-  if (RHO) {
-    if (SQ) {
-      acc = wave_sum(acc);
-      if (l == 0) rho[u] = acc;
-    } else if (l == 0) {
-      int32_t prev = 0;
-      float rr = 0.f;
-      for (int h = 1; h <= 2; ++h) {
-        const int32_t e = hend[(int64_t)u * 2 + h - 1];
-        rr += (float)(e - prev) / (float)(h * h);
-        prev = e;
-      }
-      rho[u] = rr;
+  if (RHO && l == 0) {
+    int32_t prev = 0;
+    float rr = 0.f;
+    for (int h = 1; h <= 2; ++h) {
+      const int32_t e = hend[(int64_t)u * 2 + h - 1];
+      rr += (float)(e - prev) / (float)(h * h);
+      prev = e;
     }
+    rho[u] = rr;
   }
 }
 
@@ -478,6 +433,63 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
       wave_sync();
     }
   }
+}
+
+// rho_u on coarse levels (w_uv = 1 / (hop (sqrt c_u + sqrt c_v) scale)^2)
+// from the consecutive tile-major chunks: a wave sums one chunk at a time
+// (16-byte blocks of 8 entries, padding entries have hop 0) into the chunk's
+// row-major slot, with sqrt c of the block's first chunk's tile staged in LDS
+// (chunks are sorted by tile, so a block rarely straddles two tiles; other
+// tiles' values are read from memory); k_rho_rows adds a row's slots in slot
+// order.  Per entry this reads 2 bytes and one LDS word instead of
+// gathering sqrt c_v from memory for every entry of every row.
+constexpr int32_t RH_CH = 256;  // chunks per workgroup
+template <int TB>
+__global__ __launch_bounds__(256) void k_rho_chunks(
+    int64_t m, const uint64_t* __restrict__ skey, const int64_t* __restrict__ chunk_off,
+    const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_slot,
+    const uint4* __restrict__ ent, int32_t n, const float* __restrict__ sqrtc, float scale,
+    float* __restrict__ part) {
+  constexpr int32_t T = 1 << TB;
+  __shared__ float ssc[T];
+  const int64_t c0 = (int64_t)blockIdx.x * RH_CH;
+  const int32_t t0 = (int32_t)(skey[c0] >> 32);
+  const int32_t v0 = t0 * T, nv = min(T, n - v0);
+  for (int32_t i = threadIdx.x; i < nv; i += 256) ssc[i] = sqrtc[v0 + i];
+  __syncthreads();
+  const int l = lane_id();
+  const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  const int64_t c1 = min<int64_t>(c0 + RH_CH, m);
+  for (int64_t c = c0 + wv; c < c1; c += 4) {
+    const int32_t t = __builtin_amdgcn_readfirstlane((int32_t)(skey[c] >> 32));
+    const int64_t b0 = chunk_off[c] >> 3, b1 = chunk_off[c + 1] >> 3;
+    const float su = sqrtc[chunk_row[c]];
+    const float* __restrict__ sv = t == t0 ? ssc : sqrtc + (size_t)t * T;
+    float r = 0.f;
+    for (int64_t b = b0 + l; b < b1; b += 64) {
+      const uint4 q = ent[b];
+      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+        const uint32_t h = e & 7u;
+        if (h) {
+          const float d = (float)h * (su + sv[e >> 3]) * scale;
+          r += 1.f / (d * d);
+        }
+      }
+    }
+    r = wave_sum(r);
+    if (l == 0) part[chunk_slot[c]] = r;
+  }
+}
+__global__ void k_rho_rows(int32_t n, const int64_t* __restrict__ rc_ptr,
+                           const float* __restrict__ part, float* __restrict__ rho) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  float r = 0.f;
+  for (int64_t s = rc_ptr[u]; s < rc_ptr[u + 1]; ++s) r += part[s];
+  rho[u] = r;
 }
 
 __global__ void k_gather_sorted_chunks(int64_t m, const int32_t* __restrict__ svals,
@@ -678,9 +690,12 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
   MM_TRY(nch.alloc(sizeof(int32_t) * (size_t)n, s));
   MM_TRY(ts->b_rc_ptr.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
   ts->rc_ptr = ts->b_rc_ptr.as<int64_t>();
-  if (rho)
+  // coarse levels: rho from the built chunks (below); finest level: from
+  // the hop counts in the first pass
+  const bool rho_first = rho && !sqrtc;
+  if (rho_first)
     k_row_tiles<true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
-        n, src.k, tbits, ntw, src.off, src.hend, src.nbr, sqrtc, (float)scale, nch.as<int32_t>(), rho,
+        n, src.k, tbits, ntw, src.off, src.hend, src.nbr, nullptr, 1.f, nch.as<int32_t>(), rho,
         src.skip);
   else
     k_row_tiles<false><<<nblk(n, TB_WAVES), 64 * TB_WAVES, 0, s>>>(
@@ -692,16 +707,15 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
   const unsigned gbig = (unsigned)((src.nbig + TB_WAVES - 1) / TB_WAVES);
   if (src.nbig > 0) {
     MM_TRY(tcnt.alloc(sizeof(int32_t) * (size_t)src.nbig * (size_t)ntiles, s));
-    const bool sq = rho && sqrtc;
-    const size_t shm = sizeof(int32_t) * TB_WAVES * ((size_t)ntiles + (sq ? BT_STAGE : 0));
-#define MM_BT(R, Q)                                                                            \
-  k_big_tiles<R, Q><<<gbig, 64 * TB_WAVES, shm, s>>>(                                          \
-      src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.hend, tbits, ntiles, sqrtc,      \
-      (float)scale, tcnt.as<int32_t>(), nch.as<int32_t>(), rho)
-    if (sq) MM_BT(true, true);
-    else if (rho) MM_BT(true, false);
-    else MM_BT(false, false);
-#undef MM_BT
+    const size_t shm = sizeof(int32_t) * TB_WAVES * (size_t)ntiles;
+    if (rho_first)
+      k_big_tiles<true><<<gbig, 64 * TB_WAVES, shm, s>>>(
+          src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.hend, tbits, ntiles,
+          tcnt.as<int32_t>(), nch.as<int32_t>(), rho);
+    else
+      k_big_tiles<false><<<gbig, 64 * TB_WAVES, shm, s>>>(
+          src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.hend, tbits, ntiles,
+          tcnt.as<int32_t>(), nch.as<int32_t>(), nullptr);
     MM_TRY(hipGetLastError());
   }
   MM_TRY(scan_excl_i32(nch.as<int32_t>(), ts->rc_ptr, n, s));
@@ -821,6 +835,22 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
     k_big_fill<<<gbig, 64 * TB_WAVES, shm, s>>>(src.nbig, src.rows, src.rp, src.col, src.bm, src.W,
                                                tbits, ntiles, tcnt.as<int32_t>(), ts->rc_ptr,
                                                pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
+    MM_TRY(hipGetLastError());
+  }
+  if (rho && sqrtc) {
+    DevBuf part;
+    MM_TRY(part.alloc(sizeof(float) * (size_t)m, s));
+    const unsigned gr = (unsigned)((m + RH_CH - 1) / RH_CH);
+#define MM_RH(TBV)                                                                             \
+  k_rho_chunks<TBV><<<gr, 256, 0, s>>>(m, skeys.as<uint64_t>(), ts->chunk_off, ts->chunk_row,   \
+                                       svals.as<int32_t>(), cons.as<uint4>(), n, sqrtc,         \
+                                       (float)scale, part.as<float>())
+    if (tbits == 13) MM_RH(13);
+    else if (tbits == 12) MM_RH(12);
+    else MM_RH(11);
+#undef MM_RH
+    MM_TRY(hipGetLastError());
+    k_rho_rows<<<nblk(n), 256, 0, s>>>(n, ts->rc_ptr, part.as<float>(), rho);
     MM_TRY(hipGetLastError());
   }
   if (sliced) {
