@@ -299,6 +299,29 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
         }
         __syncthreads();
       }
+      if (ONE && !FILL) {
+        // counting pass of a 2-hop search: the row's hop-2 bits are final;
+        // count them, keep them (KEEP) and clear the bitmap for the next row
+        // (no positions are needed, so no scans)
+        int32_t c = 0;
+        uint32_t* __restrict__ keep_row = STORE ? bmkeep + (size_t)r * (size_t)W : nullptr;
+        for (int32_t wi = wlo + l; wi < whi; wi += 64) {
+          const uint32_t bits = NEW[wi];
+          if (STORE) keep_row[wi] = bits;
+          c += __popc(bits);
+          NEW[wi] = 0u;
+        }
+        c = wave_sum(c);
+        if (l == 0) wtot[wv] = c;
+        __syncthreads();
+        int32_t cnt_h = 0;
+        for (int i = 0; i < KB_NW; ++i) cnt_h += wtot[i];
+        total += cnt_h;
+        if (t == 0) hend[(int64_t)u * k + (h - 1)] = (int32_t)total;
+        __syncthreads();
+        flen = cnt_h;
+        continue;
+      }
       // count per wave chunk
       int32_t c = 0;
       for (int32_t b = wlo; b < whi; b += 64) {
