@@ -107,12 +107,13 @@ hipError_t khop_build(int32_t n, const int32_t* row_ptr, const int32_t* col, int
 // The build in two steps.  khop_count fills off, hend and total; rows whose
 // breadth-first search outgrows the per-wave lists ("big" rows, ids in rows)
 // are searched with n-bit bitmaps, and for k = 2 their hop-2 bitmaps are
-// kept (bmk: row r of rows at bmk + r * W, W = ceil(n / 32) words) when
-// device memory allows.  khop_fill writes the canonical ids (nbr) from that
+// kept (bmk: row r of rows at bmk + r * Wp, W = ceil(n / 32) words) when
+// device memory allows (row pitch Wp = W rounded up to 4 words, so rows
+// start 16-byte aligned).  khop_fill writes the canonical ids (nbr) from that
 // state; khop_fill_small writes only the other rows' ids, into a compact
 // array with its own offsets (off_small: n + 1 values, 0-length for big rows).
 struct KhopCount {
-  int32_t k = 0, W = 0, slots = 0;
+  int32_t k = 0, W = 0, Wp = 0, slots = 0;
   int64_t nbig = 0;
   size_t shm = 0;
   bool lds_bm = false, one = false, keep = false, test = false;

@@ -158,7 +158,8 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
 // visited test and u and N(u) are cleared afterwards, which halves the LDS
 // footprint (two workgroups per CU for n up to ~650K).
 // KEEP (with ONE, when device memory allows): the counting pass stores each
-// row's final hop-2 bitmap (n bits per big row, row r at bmkeep + r * W) and
+// row's final hop-2 bitmap (n bits per big row, row r at bmkeep + r * Wp,
+// Wp = W rounded up to 4 words so that rows start 16-byte aligned) and
 // the filling pass extracts from it instead of marking again.
 // TEST (with ONE): read a candidate's bit before setting it; pays on dense
 // graphs, where most candidates of a row are marked many times.
@@ -176,6 +177,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
   __shared__ int32_t hubs[KB_HUBCAP];
   __shared__ int32_t nhub;
   const int32_t W = (n + 31) >> 5;
+  const size_t Wp = (size_t)((W + 3) & ~3);
   const int32_t NB = ONE ? 1 : 2;
   uint32_t* VIS = LDSBM ? dyn : gbm + (size_t)blockIdx.x * NB * (size_t)W;
   uint32_t* NEW = ONE ? VIS : VIS + W;
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     const int32_t* F = col + beg;
     int32_t flen = deg;
     __syncthreads();
-    const uint32_t* kept = LOAD ? bmkeep + (size_t)r * (size_t)W : nullptr;
+    const uint32_t* kept = LOAD ? bmkeep + (size_t)r * Wp : nullptr;
     for (int h = 2; h <= k; ++h) {
       // mark neighbours of the frontier not yet visited.  The marks are
       // bound by the latency of the neighbour loads and by the instructions
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
         // count them, keep them (KEEP) and clear the bitmap for the next row
         // (no positions are needed, so no scans)
         int32_t c = 0;
-        uint32_t* __restrict__ keep_row = STORE ? bmkeep + (size_t)r * (size_t)W : nullptr;
+        uint32_t* __restrict__ keep_row = STORE ? bmkeep + (size_t)r * Wp : nullptr;
         for (int32_t wi = wlo + l; wi < whi; wi += 64) {
           const uint32_t bits = NEW[wi];
           if (STORE) keep_row[wi] = bits;
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
       for (int32_t b = wlo; b < whi; b += 64) {
         int32_t wi = b + l;
         uint32_t bits = wi < whi ? (LOAD ? kept[wi] : NEW[wi]) : 0u;
-        if (STORE && wi < whi) bmkeep[(size_t)r * (size_t)W + wi] = bits;
+        if (STORE && wi < whi) bmkeep[(size_t)r * Wp + wi] = bits;
         int32_t pc = __popc(bits);
         int32_t inc = wave_incl_scan(pc);
         int32_t pos = run + inc - pc;
@@ -459,6 +461,7 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   st->test = (double)sdeg2 >= (double)n * (double)n;
   const int32_t W = (n + 31) >> 5;
   st->W = W;
+  st->Wp = (W + 3) & ~3;
   const bool one = (k == 2);
   st->one = one;
   const int32_t nbw = (one ? 1 : 2) * W;  // bitmap words per workgroup
@@ -478,7 +481,7 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   if (one && nbig > 0) {
     size_t freeb = 0, totb = 0;
     MM_TRY(hipMemGetInfo(&freeb, &totb));
-    const size_t kb = sizeof(uint32_t) * (size_t)W * (size_t)nbig;
+    const size_t kb = sizeof(uint32_t) * (size_t)st->Wp * (size_t)nbig;
     if (kb > freeb / 3) {
       // memory freed by earlier stream-ordered frees may still be held by the
       // device's default pool (not reported as free): release it and look again

@@ -221,7 +221,22 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
     }
     seg0 = seg1;
   }
-  if (!FILL) {
+  if (FILL) {
+    // each chunk's padding to a whole 8-entry block: hop 0
+    wave_sync();
+    for (int i = l; i < ntw; i += 64) {
+      uint32_t bb = bm[i];
+      int32_t rank = pf[i];
+      while (bb) {
+        const int j = __ffs(bb) - 1;
+        bb &= bb - 1;
+        const int32_t t = (i << 5) + j;
+        const int64_t cb = BASE ? base[t] : chunk_off[pos_of_slot[rbase + rank]];
+        for (int32_t p = ct[t]; p & 7; ++p) ent[cb + p] = 0;
+        rank++;
+      }
+    }
+  } else {
     for (int i = l; i < ntw; i += 64) {
       uint32_t bb = bm[i];
       int32_t r = pf[i];
@@ -246,13 +261,26 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
 
 constexpr int32_t kDirectMaxTiles = 1024;  // LDS per wave: 12 B per tile
 
+// words wb .. wb + 3 of a kept bitmap row (16-byte aligned; wb a multiple of
+// 4); words at or past W (the row's padding) read as 0
+__device__ __forceinline__ uint4 load_words4(const uint4* __restrict__ row, int32_t wb, int32_t W) {
+  if (wb >= W) return make_uint4(0u, 0u, 0u, 0u);
+  uint4 q = row[wb >> 2];
+  if (wb + 3 >= W) {
+    if (wb + 1 >= W) q.y = 0u;
+    if (wb + 2 >= W) q.z = 0u;
+    q.w = 0u;
+  }
+  return q;
+}
+
 // K1 for big rows: the row's entries per tile (dense, tcnt[r * ntiles + t])
 // and its tile count; with RHO (finest level) also rho_u from the hop counts
 // (k_row_tiles' formula).
 template <bool RHO>
 __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
     int64_t nbig, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W,
+    const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W, int32_t Wp,
     const int32_t* __restrict__ hend, int32_t tbits, int32_t ntiles, int32_t* __restrict__ tcnt,
     int32_t* __restrict__ nch, float* __restrict__ rho) {
   extern __shared__ int32_t bt_dyn[];
@@ -278,32 +306,22 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
     if (end) ct[t] += l - rs + 1;
     wave_sync();
   }
-  // hop 2: 64-word steps (each inside one tile: a tile has >= 64 words),
-  // four steps loaded at a time, one wave sum per tile and group of steps
-  const uint32_t* __restrict__ brow = bm + (size_t)r * (size_t)W;
+  // hop 2: 256-word steps, four words per lane (a tile's words are a run of
+  // G >= 16 lanes), two steps loaded at a time; per tile a group sum
+  const uint4* __restrict__ brow = reinterpret_cast<const uint4*>(bm + (size_t)r * (size_t)Wp);
   const int32_t tsh = tbits - 5;
-  for (int32_t w0 = 0; w0 < W; w0 += 256) {
-    uint32_t x[4];
+  const int32_t G = min(64, (1 << tsh) >> 2);
+  for (int32_t w0 = 0; w0 < W; w0 += 512) {
+    uint4 x[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int32_t wi = w0 + 64 * j + l;
-      x[j] = wi < W ? brow[wi] : 0u;
-    }
-    int32_t cur = 0, curt = w0 >> tsh;
+    for (int j = 0; j < 2; ++j) x[j] = load_words4(brow, w0 + 256 * j + 4 * l, W);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int32_t wj = w0 + 64 * j;
-      if (wj >= W) break;
-      if ((wj >> tsh) != curt) {
-        const int32_t c = wave_sum(cur);
-        if (l == 0) ct[curt] += c;
-        cur = 0;
-        curt = wj >> tsh;
-      }
-      cur += __popc(x[j]);
+    for (int j = 0; j < 2; ++j) {
+      const int32_t wb = w0 + 256 * j + 4 * l;
+      int32_t c = __popc(x[j].x) + __popc(x[j].y) + __popc(x[j].z) + __popc(x[j].w);
+      c = group_sum(c, G);
+      if ((l & (G - 1)) == 0 && wb < W) ct[wb >> tsh] += c;
     }
-    const int32_t c = wave_sum(cur);
-    if (l == 0) ct[curt] += c;
   }
   wave_sync();
   int32_t nt = 0;
@@ -358,10 +376,10 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_slots(
 // the start of each touched tile's chunk (int64) and its fill count.
 __global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
     int64_t nbig, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W, int32_t tbits,
-    int32_t ntiles, const int32_t* __restrict__ tcnt, const int64_t* __restrict__ rc_ptr,
-    const int32_t* __restrict__ pos_of_slot, const int64_t* __restrict__ chunk_off,
-    uint16_t* __restrict__ ent) {
+    const int32_t* __restrict__ col, const uint32_t* __restrict__ bm, int32_t W, int32_t Wp,
+    int32_t tbits, int32_t ntiles, const int32_t* __restrict__ tcnt,
+    const int64_t* __restrict__ rc_ptr, const int32_t* __restrict__ pos_of_slot,
+    const int64_t* __restrict__ chunk_off, uint16_t* __restrict__ ent) {
   extern __shared__ int64_t bf_dyn[];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int64_t r = (int64_t)blockIdx.x * TB_WAVES + w;
@@ -380,7 +398,12 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
     const int32_t rank = run + __popcll(m & lanemask_lt());
     if (t < ntiles) {
       ct[t] = 0;
-      if (c > 0) base[t] = chunk_off[pos_of_slot[rbase + rank]];
+      if (c > 0) {
+        const int64_t cb = chunk_off[pos_of_slot[rbase + rank]];
+        base[t] = cb;
+        // the chunk's padding to a whole 8-entry block: hop 0
+        for (int32_t p = c; p & 7; ++p) ent[cb + p] = 0;
+      }
     }
     run += __popcll(m);
   }
@@ -402,7 +425,11 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
     if (end) ct[t] += l - rs + 1;
     wave_sync();
   }
-  const uint32_t* __restrict__ brow = bm + (size_t)r * (size_t)W;
+  // hop 2: 64-word steps, one word per lane (consecutive lanes then write
+  // consecutive entries: four words per lane spread each store over four
+  // times the addresses and ran slower), four steps loaded at a time; a
+  // 64-word step lies inside one tile
+  const uint32_t* __restrict__ brow = bm + (size_t)r * (size_t)Wp;
   const int32_t tsh = tbits - 5;
   for (int32_t w0 = 0; w0 < W; w0 += 256) {
     uint32_t x[4];
@@ -673,7 +700,7 @@ struct TileSrc {
   int64_t nbig = 0;
   const int32_t* rows = nullptr;
   const uint32_t* bm = nullptr;
-  int32_t W = 0;
+  int32_t W = 0, Wp = 0;
   const int32_t* rp = nullptr;
   const int32_t* col = nullptr;
 };
@@ -710,11 +737,11 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
     const size_t shm = sizeof(int32_t) * TB_WAVES * (size_t)ntiles;
     if (rho_first)
       k_big_tiles<true><<<gbig, 64 * TB_WAVES, shm, s>>>(
-          src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.hend, tbits, ntiles,
+          src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.Wp, src.hend, tbits, ntiles,
           tcnt.as<int32_t>(), nch.as<int32_t>(), rho);
     else
       k_big_tiles<false><<<gbig, 64 * TB_WAVES, shm, s>>>(
-          src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.hend, tbits, ntiles,
+          src.nbig, src.rows, src.rp, src.col, src.bm, src.W, src.Wp, src.hend, tbits, ntiles,
           tcnt.as<int32_t>(), nch.as<int32_t>(), nullptr);
     MM_TRY(hipGetLastError());
   }
@@ -820,7 +847,7 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
   DevBuf stage;
   DevBuf& cons = sliced ? stage : ts->b_ent;
   MM_TRY(cons.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
-  MM_TRY(hipMemsetAsync(cons.p, 0, sizeof(uint16_t) * (size_t)padded, s));
+  // (every chunk's padding is written by the filling kernels)
   if (use_base)
     k_row_chunks<true, true><<<nblk(n, TB_WAVES), 64 * TB_WAVES, tb_shm_base, s>>>(
         n, src.k, tbits, ntiles, ntw, src.off, src.hend, src.nbr, ts->rc_ptr, nullptr, nullptr,
@@ -833,7 +860,7 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
   if (src.nbig > 0) {
     const size_t shm = sizeof(int64_t) * TB_WAVES * ((size_t)ntiles + (((size_t)ntiles + 1) >> 1));
     k_big_fill<<<gbig, 64 * TB_WAVES, shm, s>>>(src.nbig, src.rows, src.rp, src.col, src.bm, src.W,
-                                               tbits, ntiles, tcnt.as<int32_t>(), ts->rc_ptr,
+                                               src.Wp, tbits, ntiles, tcnt.as<int32_t>(), ts->rc_ptr,
                                                pos_of_slot, ts->chunk_off, cons.as<uint16_t>());
     MM_TRY(hipGetLastError());
   }
@@ -941,6 +968,7 @@ hipError_t tiled_build_direct(const KhopDev& kh, const KhopCount& st, const int3
   src.rows = st.rows.as<int32_t>();
   src.bm = st.bmk.as<uint32_t>();
   src.W = st.W;
+  src.Wp = st.Wp;
   src.rp = row_ptr;
   src.col = col;
   return tiled_build_src(src, tbits, min_avg_chunk, ts, s, sqrtc, scale, rho, sliced);
