@@ -61,6 +61,31 @@ __device__ inline T wave_incl_scan(T v) {
   }
   return v;
 }
+// int32: the same inclusive sum from DPP row shifts (1, 2, 4, 8 within rows
+// of 16 lanes) and row broadcasts (lane 15 into rows 1 and 3, lane 31 into
+// rows 2 and 3): VALU data movement instead of six LDS-crossbar shuffles.
+// Lanes whose source lies outside their row keep the identity 0.
+template <>
+__device__ inline int32_t wave_incl_scan<int32_t>(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+// Inclusive max over the wave (int32, DPP as above; identity INT32_MIN).
+__device__ inline int32_t wave_incl_max(int32_t v) {
+  constexpr int32_t lo = -2147483647 - 1;
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false));
+  return v;
+}
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 // Exclusive block scan (blockDim multiple of 64, <= 1024). Returns the

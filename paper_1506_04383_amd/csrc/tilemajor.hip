@@ -20,20 +20,18 @@ constexpr int RU = 4;                // 64-entry steps loaded at once per wave (
 constexpr int32_t UNIT_CH = kUnitChunks;
 constexpr int32_t UNIT_S = kUnitSlices;
 
+// the value of lane l - 1 (lane 0: its own) and of lane l + 1 (lane 63:
+// its own), by DPP wave shifts
+__device__ inline int32_t lane_prev(int32_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ inline int32_t lane_next(int32_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-}
-
-// wave inclusive max-scan
-__device__ inline int32_t wave_incl_max(int32_t v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int32_t w = __shfl_up(v, o, 64);
-    if (l >= o) v = max(v, w);
-  }
-  return v;
 }
 
 // K1: number of distinct tiles per row
@@ -198,10 +196,10 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
         const bool valid = i < seg1;
         const int32_t v = vv[uu];
         const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
-        const int32_t tprev = __shfl_up(t, 1, 64);
+        const int32_t tprev = lane_prev(t);
         const bool start = valid && (l == 0 || tprev != t);
         const int32_t rs = wave_incl_max(start ? l : -1);
-        const int32_t tnext = __shfl_down(t, 1, 64);
+        const int32_t tnext = lane_next(t);
         const bool end = valid && (l == 63 || i + 1 >= seg1 || tnext != t);
         if (FILL && valid) {
           int64_t cbase;
@@ -298,10 +296,10 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_tiles(
     const bool valid = i < d;
     const int32_t v = valid ? col[b + i] : 0;
     const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
-    const int32_t tprev = __shfl_up(t, 1, 64);
+    const int32_t tprev = lane_prev(t);
     const bool start = valid && (l == 0 || tprev != t);
     const int32_t rs = wave_incl_max(start ? l : -1);
-    const int32_t tnext = __shfl_down(t, 1, 64);
+    const int32_t tnext = lane_next(t);
     const bool end = valid && (l == 63 || i + 1 >= d || tnext != t);
     if (end) ct[t] += l - rs + 1;
     wave_sync();
@@ -415,10 +413,10 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
     const bool valid = i < d;
     const int32_t v = valid ? col[b + i] : 0;
     const int32_t t = valid ? (v >> tbits) : 0x7fffffff;
-    const int32_t tprev = __shfl_up(t, 1, 64);
+    const int32_t tprev = lane_prev(t);
     const bool start = valid && (l == 0 || tprev != t);
     const int32_t rs = wave_incl_max(start ? l : -1);
-    const int32_t tnext = __shfl_down(t, 1, 64);
+    const int32_t tnext = lane_next(t);
     const bool end = valid && (l == 63 || i + 1 >= d || tnext != t);
     if (valid) ent[base[t] + ct[t] + (l - rs)] = (uint16_t)(((v & lo) << 3) | 1);
     wave_sync();
@@ -444,7 +442,7 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_big_fill(
       if (wj >= W) break;
       const int32_t pc = __popc(x[j]);
       const int32_t inc = wave_incl_scan(pc);
-      const int32_t tot = __shfl(inc, 63, 64);
+      const int32_t tot = __builtin_amdgcn_readlane(inc, 63);
       if (tot == 0) continue;
       const int32_t t = wj >> tsh;
       int64_t pos = base[t] + ct[t] + (inc - pc);
@@ -500,10 +498,9 @@ __global__ __launch_bounds__(256) void k_rho_chunks(
       for (int k = 0; k < 8; ++k) {
         const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
         const uint32_t h = e & 7u;
-        if (h) {
-          const float d = (float)h * (su + sv[e >> 3]) * scale;
-          r += 1.f / (d * d);
-        }
+        // hardware reciprocal (within 1 ulp); padding (hop 0) adds 0
+        const float d = (float)h * (su + sv[e >> 3]) * scale;
+        r += h ? __builtin_amdgcn_rcpf(d * d) : 0.f;
       }
     }
     r = wave_sum(r);
@@ -590,24 +587,48 @@ __global__ void k_slice_fill(int64_t m, const int32_t* __restrict__ flag,
   slice_h[sl] = ssize[c] >> 3;
   slice_blocks[sl] = (ssize[c] >> 3) * 64;
 }
-// Consecutive layout -> sliced layout: one wave per slice; lane i copies
-// the blocks of the slice's chunk i (consecutive from chunk_off[c]) to
-// slice_base + 64 j + i and writes zero blocks past its chunk's end (and for
-// lanes without a chunk), so every block of the slice is written.
+// Consecutive layout -> sliced layout through LDS, a workgroup per slice
+// (grid-stride over slices), in windows of TJ block rows: the waves read
+// runs of TJ consecutive blocks of a chunk (half a wave per chunk, so each
+// read instruction covers two chunks' contiguous runs) into an LDS tile
+// [chunk][row], then write block rows, lane i taking chunk i (1 KB per
+// row).  Blocks past a chunk's end, and the rows of lanes without a chunk,
+// are written as zero blocks, so every block of the slice is written.  The
+// tile's row stride (TJ + 1 blocks) keeps both phases free of bank conflicts.
+constexpr int TJ = 32;
 __global__ __launch_bounds__(256) void k_slice_transpose(
     int64_t nsl, const int32_t* __restrict__ slice_c0, const int32_t* __restrict__ slice_h,
     const int64_t* __restrict__ slice_base, const int64_t* __restrict__ chunk_off,
     const uint4* __restrict__ src, uint4* __restrict__ dst) {
-  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (sl >= nsl) return;
-  const int l = lane_id();
-  const int32_t c0 = slice_c0[sl], nc = slice_c0[sl + 1] - c0, h = slice_h[sl];
-  const bool lv = l < nc;
-  const int64_t b0 = lv ? chunk_off[c0 + l] >> 3 : 0;
-  const int32_t nb = lv ? (int32_t)((chunk_off[c0 + l + 1] >> 3) - b0) : 0;
-  uint4* __restrict__ d = dst + slice_base[sl] + l;
-  for (int32_t j = 0; j < h; ++j)
-    d[(int64_t)j * 64] = j < nb ? src[b0 + j] : make_uint4(0u, 0u, 0u, 0u);
+  __shared__ uint4 tl[64][TJ + 1];
+  __shared__ int64_t cb[64];
+  __shared__ int32_t cn[64];
+  const int t = threadIdx.x, w = t >> 6, l = lane_id();
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
+    const int32_t c0 = slice_c0[sl], nc = slice_c0[sl + 1] - c0, h = slice_h[sl];
+    if (t < 64) {
+      const bool v = t < nc;
+      const int64_t b0 = v ? chunk_off[c0 + t] >> 3 : 0;
+      cb[t] = b0;
+      cn[t] = v ? (int32_t)((chunk_off[c0 + t + 1] >> 3) - b0) : 0;
+    }
+    __syncthreads();
+    uint4* __restrict__ d = dst + slice_base[sl];
+    for (int32_t j0 = 0; j0 < h; j0 += TJ) {
+      // chunks 2p and 2p + 1 per wave instruction, p = w, w + 4, ...
+      const int32_t jj = l & (TJ - 1);
+      for (int32_t p = w; p < 32; p += 4) {
+        const int32_t i = 2 * p + (l >> 5);
+        const int32_t b = j0 + jj;
+        tl[i][jj] = b < cn[i] ? src[cb[i] + b] : zero;
+      }
+      __syncthreads();
+      const int32_t rows = min(TJ, h - j0);
+      for (int32_t j = w; j < rows; j += 4) d[(int64_t)(j0 + j) * 64 + l] = tl[l][j];
+      __syncthreads();
+    }
+  }
 }
 // unit starts over slices: the first slice of a tile, every UNIT_S-th slice
 // after it, and every slice that begins a new span of emax blocks
@@ -883,9 +904,9 @@ hipError_t tiled_build_src(const TileSrc& src, int32_t tbits, double min_avg_chu
   if (sliced) {
     padded = sl_blocks * 8;
     MM_TRY(ts->b_ent.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(padded, 8), s));
-    k_slice_transpose<<<nblk(nsl, 4), 256, 0, s>>>(nsl, ts->slice_c0, ts->slice_h, ts->slice_base,
-                                                   ts->chunk_off, cons.as<uint4>(),
-                                                   ts->b_ent.as<uint4>());
+    k_slice_transpose<<<(unsigned)std::min<int64_t>(nsl, 16384), 256, 0, s>>>(
+        nsl, ts->slice_c0, ts->slice_h, ts->slice_base, ts->chunk_off, cons.as<uint4>(),
+        ts->b_ent.as<uint4>());
     MM_TRY(hipGetLastError());
   }  // the staging copy is freed (stream-ordered) on return
   ts->ent = ts->b_ent.as<uint16_t>();
