@@ -117,7 +117,9 @@ struct KhopCount {
   int64_t nbig = 0;
   size_t shm = 0;
   bool lds_bm = false, one = false, keep = false, test = false;
-  DevBuf cnt, big, bigpos, rows, bmk, gbm, gscr;
+  int32_t hthr = 0x7fffffff;  // k = 2: vertices with more neighbours have bitmaps in hb
+  int32_t orcap = 0;          // hub bitmaps a row may OR (LDS list length)
+  DevBuf cnt, big, bigpos, rows, bmk, gbm, gscr, hubidx, hb;
 };
 hipError_t khop_count(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
                       KhopDev* out, KhopCount* st, hipStream_t s);

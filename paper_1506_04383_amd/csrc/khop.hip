@@ -30,7 +30,12 @@ constexpr int KB_U = 4;          // frontier vertices per wave step in the bitma
 constexpr int KB_V = 8;          // neighbour loads in flight per lane while marking
 constexpr int32_t KB_HUB = 512;  // longer neighbour lists are marked by the whole workgroup
 constexpr int KB_HUBCAP = 256;   // hubs deferred per frontier (more: marked by their wave)
-constexpr int KB_LDS_WORDS = 19968;  // 2 x this many bitmap words fit in a CU's LDS
+constexpr int KB_ORCAP = 4096;   // adjacency bitmaps ORed per row (more: marked)
+// the bitmap kernel's static LDS (bytes, rounded up)
+constexpr int KB_STATIC_LDS = 4 * (KB_NW + 1 + KB_HUBCAP + 2) + 64;
+// 2 x this many bitmap words fit in a CU's 160 KB of LDS beside them
+constexpr int KB_LDS_WORDS = (160 * 1024 - KB_STATIC_LDS) / 8;
+
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -87,7 +92,7 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
       if (i < len1) { int32_t x = L1[i]; d = rp[x + 1] - rp[x]; }
       int32_t inc = wave_incl_scan(d);
       if (i < len1) PF[i] = run + inc - d;
-      run += __shfl(inc, 63, 64);
+      run += __builtin_amdgcn_readlane(inc, 63);
     }
     const int32_t ncand = run;
     if (ncand > KS_CAP) {
@@ -168,23 +173,29 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
     int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t k,
     const int32_t* __restrict__ rows, int32_t nrows, const int64_t* __restrict__ off,
     int32_t* __restrict__ hend, int32_t* __restrict__ nbr, int32_t* __restrict__ cnt,
-    uint32_t* __restrict__ gbm, int32_t* __restrict__ gscratch, uint32_t* __restrict__ bmkeep) {
+    uint32_t* __restrict__ gbm, int32_t* __restrict__ gscratch, uint32_t* __restrict__ bmkeep,
+    int32_t hthr, const int32_t* __restrict__ hubidx, const uint32_t* __restrict__ hb,
+    int32_t orcap) {
   static_assert(!KEEP || ONE, "kept bitmaps hold hop 2 only");
   constexpr bool LOAD = KEEP && FILL;   // extract from the kept bitmap
   constexpr bool STORE = KEEP && !FILL; // keep the bitmap
-  extern __shared__ uint32_t dyn[];
+  extern __shared__ uint4 dyn4[];  // 16-byte aligned: the OR phase reads it as uint4
   __shared__ int32_t wtot[KB_NW + 1];
   __shared__ int32_t hubs[KB_HUBCAP];
-  __shared__ int32_t nhub;
+  __shared__ int32_t nhub, norl;
   const int32_t W = (n + 31) >> 5;
   const size_t Wp = (size_t)((W + 3) & ~3);
   const int32_t NB = ONE ? 1 : 2;
-  uint32_t* VIS = LDSBM ? dyn : gbm + (size_t)blockIdx.x * NB * (size_t)W;
-  uint32_t* NEW = ONE ? VIS : VIS + W;
+  // bitmaps at pitch Wp (the words past W stay 0)
+  uint32_t* VIS = LDSBM ? reinterpret_cast<uint32_t*>(dyn4) : gbm + (size_t)blockIdx.x * NB * Wp;
+  uint32_t* NEW = ONE ? VIS : VIS + Wp;
+  // hub indices to OR (orcap entries, in LDS after the bitmaps; orcap is 0
+  // unless hthr is set, which needs the LDS bitmaps)
+  int32_t* orl = reinterpret_cast<int32_t*>(dyn4) + NB * Wp;
   int32_t* scratch = gscratch ? gscratch + (size_t)blockIdx.x * (size_t)n : nullptr;
   const int t = threadIdx.x, wv = t >> 6, l = lane_id();
-  for (int32_t i = t; i < NB * W; i += KB_T) VIS[i] = 0;
-  if (t == 0) nhub = 0;
+  for (size_t i = t; i < NB * Wp; i += KB_T) VIS[i] = 0;
+  if (t == 0) { nhub = 0; norl = 0; }
   __syncthreads();
   // word chunk per wave for the ordered extraction
   const int32_t CW = ((W + KB_NW - 1) / KB_NW + 63) & ~63;
@@ -219,6 +230,10 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
       //  * lists longer than KB_HUB are set aside and marked afterwards by
       //    the whole workgroup, KB_T * KB_V entries per round, so that one
       //    long list does not hold the row on one wave;
+      //  * (k = 2) vertices with more than hthr neighbours have their
+      //    adjacency bitmap precomputed (hb, row hubidx[x] at pitch Wp): a row
+      //    ORs it into its own, 16 bytes per thread and load, instead of
+      //    marking the neighbours one by one;
       //  * list bounds are wave-uniform; loads past a list's end read its
       //    last entry instead, so loads need no lane masks, and only the
       //    marks of a list's last, partial step are masked (marking the
@@ -260,6 +275,16 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
           const int32_t x = i0 + uu < flen ? __builtin_amdgcn_readfirstlane(F[i0 + uu]) : -1;
           b0[uu] = x >= 0 ? __builtin_amdgcn_readfirstlane(rp[x]) : 0;
           len[uu] = x >= 0 ? __builtin_amdgcn_readfirstlane(rp[x + 1]) - b0[uu] : 0;
+          if (ONE && len[uu] > hthr) {
+            // OR its adjacency bitmap after the marks, unless the list is full
+            int32_t slot = 0;
+            if (l == 0) slot = atomicAdd(&norl, 1);
+            slot = __builtin_amdgcn_readfirstlane(__shfl(slot, 0, 64));
+            if (slot < orcap) {
+              if (l == 0) orl[slot] = hubidx[x];
+              len[uu] = 0;
+            }
+          }
           if (len[uu] > KB_HUB) {
             // defer to the workgroup unless the list is full
             int32_t slot = 0;
@@ -290,7 +315,37 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
           mark_list(col + e0, 0, __builtin_amdgcn_readfirstlane(rp[x + 1]) - e0, KB_T, t);
         }
         __syncthreads();
-        if (t == 0) nhub = 0;
+        if (ONE) {
+          // each thread owns 16-byte words of the bitmap: no atomics here
+          const int32_t no = min(norl, orcap);
+          if (no > 0) {
+            const size_t W4 = Wp >> 2;
+            uint4* __restrict__ N4 = reinterpret_cast<uint4*>(NEW);
+            const uint4* __restrict__ H4 = reinterpret_cast<const uint4*>(hb);
+            for (size_t w4 = t; w4 < W4; w4 += KB_T) {
+              uint4 a = N4[w4];
+              int32_t j = 0;
+              for (; j + 4 <= no; j += 4) {
+                const uint4 h0 = H4[(size_t)orl[j] * W4 + w4], h1 = H4[(size_t)orl[j + 1] * W4 + w4];
+                const uint4 h2 = H4[(size_t)orl[j + 2] * W4 + w4], h3 = H4[(size_t)orl[j + 3] * W4 + w4];
+                a.x |= h0.x | h1.x | h2.x | h3.x;
+                a.y |= h0.y | h1.y | h2.y | h3.y;
+                a.z |= h0.z | h1.z | h2.z | h3.z;
+                a.w |= h0.w | h1.w | h2.w | h3.w;
+              }
+              for (; j < no; ++j) {
+                const uint4 h0 = H4[(size_t)orl[j] * W4 + w4];
+                a.x |= h0.x;
+                a.y |= h0.y;
+                a.z |= h0.z;
+                a.w |= h0.w;
+              }
+              N4[w4] = a;
+            }
+          }
+          __syncthreads();
+        }
+        if (t == 0) { nhub = 0; norl = 0; }
       }
       if (ONE && !LOAD) {
         // drop hop 0 and hop 1 from the candidates
@@ -362,7 +417,7 @@ __global__ __launch_bounds__(KB_T) void k_khop_big(
           if (!LOAD) NEW[wi] = 0u;
           if (!ONE && !last) VIS[wi] |= bits;
         }
-        run += __shfl(inc, 63, 64);
+        run += __builtin_amdgcn_readlane(inc, 63);
       }
       total += cnt_h;
       if (!FILL && t == 0) hend[(int64_t)u * k + (h - 1)] = (int32_t)total;
@@ -408,6 +463,29 @@ __global__ __launch_bounds__(256) void k_sum_deg2(int32_t n, const int32_t* rp,
   if (lane_id() == 0) part[threadIdx.x >> 6] = a;
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+// vertices with more than thr neighbours: their index among them (or -1)
+// and their adjacency bitmaps (row h at hb + h * Wp, zeroed beforehand)
+__global__ void k_hub_flags(int32_t n, const int32_t* rp, int32_t thr, int32_t* flag) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) flag[u] = rp[u + 1] - rp[u] > thr ? 1 : 0;
+}
+__global__ void k_hub_index(int32_t n, const int32_t* flag, const int64_t* pos, int32_t* hubidx,
+                            int32_t* hubv) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  hubidx[u] = flag[u] ? (int32_t)pos[u] : -1;
+  if (flag[u]) hubv[pos[u]] = u;
+}
+__global__ __launch_bounds__(256) void k_hub_bitmaps(const int32_t* hubv, const int32_t* rp,
+                                                     const int32_t* col, int64_t Wp, uint32_t* hb) {
+  const int32_t u = hubv[blockIdx.x];
+  uint32_t* row = hb + (size_t)blockIdx.x * (size_t)Wp;
+  for (int32_t e = rp[u] + threadIdx.x; e < rp[u + 1]; e += 256) {
+    const int32_t v = col[e];
+    atomicOr(&row[v >> 5], 1u << (v & 31));
+  }
 }
 
 // counts of the rows the small-row kernel filled (0 for bitmap rows)
@@ -464,17 +542,14 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   st->Wp = (W + 3) & ~3;
   const bool one = (k == 2);
   st->one = one;
-  const int32_t nbw = (one ? 1 : 2) * W;  // bitmap words per workgroup
+  const int32_t nbw = (one ? 1 : 2) * st->Wp;  // bitmap words per workgroup
   const bool lds_bm = nbw <= 2 * KB_LDS_WORDS;
   st->lds_bm = lds_bm;
   int dev = 0, ncu = 0;
   MM_TRY(hipGetDevice(&dev));
   MM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const size_t shm = lds_bm ? sizeof(uint32_t) * (size_t)nbw : 0;
-  st->shm = shm;
-  const int per_cu = lds_bm ? (int)std::max<size_t>(1, (160 * 1024 - 256) / std::max<size_t>(shm, 1)) : 2;
-  const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * std::min(per_cu, 4));
-  st->slots = slots;
+  size_t shm = lds_bm ? sizeof(uint32_t) * (size_t)nbw : 0;
+
   // keep the counting pass's hop-2 bitmaps for the filling pass when they
   // take at most a third of the free device memory
   bool keep = false;
@@ -501,6 +576,48 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
                    (long long)nbig, kb / 1e9, freeb / 1e9, keep ? "kept" : "rebuilt");
   }
   st->keep = keep;
+  // adjacency bitmaps of the vertices with more than W / 4 neighbours (an
+  // OR of W / 4 16-byte words replaces > W / 4 random marks), at most 1 GB.
+  // Measured on R-MAT 2^20: they pay on levels whose bitmap rows have at
+  // most ~9000 words (levels 2-9: 15-40% less time); on larger levels
+  // streaming the hubs' 50-70 KB rows for every row cost more than the marks
+  // they replace (+7% and +25% on levels 0 and 1)
+  st->hthr = 0x7fffffff;
+  st->orcap = 0;
+  if (one && lds_bm && nbig > 0 && W <= 9000) {
+    int32_t thr = std::max(W / 4, 64);
+    DevBuf hf, hpos;
+    MM_TRY(hf.alloc(sizeof(int32_t) * (size_t)n, s));
+    MM_TRY(hpos.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+    int64_t nh = 0;
+    for (;;) {
+      k_hub_flags<<<(n + 255) / 256, 256, 0, s>>>(n, rp, thr, hf.as<int32_t>());
+      MM_TRY(scan_excl_i32(hf.as<int32_t>(), hpos.as<int64_t>(), n, s));
+      MM_TRY(hipMemcpyAsync(&nh, hpos.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      MM_TRY(hipStreamSynchronize(s));
+      if (nh * (int64_t)st->Wp * 4 <= ((int64_t)1 << 30) || thr >= n) break;
+      thr *= 2;
+    }
+    if (nh > 0 && nh * (int64_t)st->Wp * 4 <= ((int64_t)1 << 30)) {
+      DevBuf hv;
+      MM_TRY(st->hubidx.alloc(sizeof(int32_t) * (size_t)n, s));
+      MM_TRY(hv.alloc(sizeof(int32_t) * (size_t)nh, s));
+      k_hub_index<<<(n + 255) / 256, 256, 0, s>>>(n, hf.as<int32_t>(), hpos.as<int64_t>(),
+                                                  st->hubidx.as<int32_t>(), hv.as<int32_t>());
+      MM_TRY(st->hb.alloc(sizeof(uint32_t) * (size_t)nh * (size_t)st->Wp, s));
+      MM_TRY(hipMemsetAsync(st->hb.p, 0, sizeof(uint32_t) * (size_t)nh * (size_t)st->Wp, s));
+      k_hub_bitmaps<<<(unsigned)nh, 256, 0, s>>>(hv.as<int32_t>(), rp, col, st->Wp,
+                                                 st->hb.as<uint32_t>());
+      MM_TRY(hipGetLastError());
+      st->hthr = thr;
+      st->orcap = (int32_t)std::min<int64_t>(nh, KB_ORCAP);
+      shm += sizeof(int32_t) * (size_t)st->orcap;
+    }
+  }
+  st->shm = shm;
+  const int per_cu = lds_bm ? (int)std::max<size_t>(1, (160 * 1024) / (shm + KB_STATIC_LDS)) : 2;
+  const int32_t slots = (int32_t)std::min<int64_t>(nbig, (int64_t)ncu * std::min(per_cu, 4));
+  st->slots = slots;
 #define MM_BIG(FILLV, LDSV, ONEV, KEEPV, TESTV, ...)                                            \
   do {                                                                                         \
     if (LDSV)                                                                                  \
@@ -537,7 +654,8 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
     if (k >= 3) MM_TRY(st->gscr.alloc(sizeof(int32_t) * (size_t)n * (size_t)slots, s));
     MM_BIG_ANY(false, n, rp, col, k, st->rows.as<int32_t>(), (int32_t)nbig, nullptr, out->hend,
                nullptr, st->cnt.as<int32_t>(), st->gbm.as<uint32_t>(), st->gscr.as<int32_t>(),
-               st->bmk.as<uint32_t>());
+               st->bmk.as<uint32_t>(), st->hthr, st->hubidx.as<int32_t>(), st->hb.as<uint32_t>(),
+               st->orcap);
     MM_TRY(hipGetLastError());
   }
   MM_TRY(scan_excl_i32(st->cnt.as<int32_t>(), out->off, n, s));
@@ -563,7 +681,8 @@ hipError_t khop_fill(int32_t n, const int32_t* rp, const int32_t* col, KhopDev* 
   MM_TRY(hipGetLastError());
   if (st->nbig > 0) {
     MM_BIG_ANY(true, n, rp, col, k, st->rows.as<int32_t>(), (int32_t)st->nbig, out->off, out->hend,
-               out->nbr, nullptr, st->gbm.as<uint32_t>(), nullptr, st->bmk.as<uint32_t>());
+               out->nbr, nullptr, st->gbm.as<uint32_t>(), nullptr, st->bmk.as<uint32_t>(),
+               st->hthr, st->hubidx.as<int32_t>(), st->hb.as<uint32_t>(), st->orcap);
     MM_TRY(hipGetLastError());
   }
   return hipGetLastError();
