@@ -1096,7 +1096,8 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       auto tk = std::chrono::steady_clock::now();
       mm::KhopDev kh;
       mm::KhopCount kc;
-      HIPCHK(mm::khop_count(nl, G.row_ptr, G.col, p->k, &kh, &kc, s));
+      HIPCHK(mm::khop_count(nl, G.row_ptr, G.col, p->k, &kh, &kc, s,
+                            p->khop_direct != 0 && p->k == 2));
       // the canonical ids are written only when something reads them: the
       // tuner, the row kernel, or a tile-major copy that cannot be built
       // straight from the search's kept bitmaps

@@ -110,8 +110,10 @@ hipError_t khop_build(int32_t n, const int32_t* row_ptr, const int32_t* col, int
 // kept (bmk: row r of rows at bmk + r * Wp, W = ceil(n / 32) words) when
 // device memory allows (row pitch Wp = W rounded up to 4 words, so rows
 // start 16-byte aligned).  khop_fill writes the canonical ids (nbr) from that
-// state; khop_fill_small writes only the other rows' ids, into a compact
-// array with its own offsets (off_small: n + 1 values, 0-length for big rows).
+// state; khop_fill_small gives only the other rows' ids, with their own
+// offsets (off_small: n + 1 values; the rows' lengths are their last hop
+// ends): the fixed slots the counting pass kept (keep_short, k = 2), else a
+// compact array.
 struct KhopCount {
   int32_t k = 0, W = 0, Wp = 0, slots = 0;
   int64_t nbig = 0;
@@ -120,9 +122,10 @@ struct KhopCount {
   int32_t hthr = 0x7fffffff;  // k = 2: vertices with more neighbours have bitmaps in hb
   int32_t orcap = 0;          // hub bitmaps a row may OR (LDS list length)
   DevBuf cnt, big, bigpos, rows, bmk, gbm, gscr, hubidx, hb;
+  DevBuf slots_short;  // keep_short, k = 2: short row u's ids at u * 2048 (n * 2048 ids)
 };
 hipError_t khop_count(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
-                      KhopDev* out, KhopCount* st, hipStream_t s);
+                      KhopDev* out, KhopCount* st, hipStream_t s, bool keep_short = false);
 hipError_t khop_fill(int32_t n, const int32_t* row_ptr, const int32_t* col, KhopDev* out,
                      KhopCount* st, hipStream_t s);
 hipError_t khop_fill_small(int32_t n, const int32_t* row_ptr, const int32_t* col,

@@ -23,6 +23,7 @@ namespace mm {
 namespace {
 
 constexpr int KS_CAP = 1024;     // list capacity per wave (entries)
+constexpr int64_t KS_SLOT = 2 * KS_CAP;  // k = 2: a short row has at most this many entries
 constexpr int KS_WAVES = 2;      // waves per block
 constexpr int KB_T = 512;        // threads per big-row block
 constexpr int KB_NW = KB_T / 64;
@@ -68,7 +69,10 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
   int32_t* CA = lds[w][3];  // candidates
   int32_t* PF = lds[w][4];  // frontier degree prefix
   const int32_t beg = rp[u], deg = rp[u + 1] - beg;
-  int64_t o = FILL ? off[u] : 0;
+  // the filling pass writes the row at off[u]; a counting pass given nbr
+  // (k = 2) writes it to the fixed slot u * KS_SLOT as well
+  const bool put = FILL || nbr != nullptr;
+  int64_t o = FILL ? off[u] : (int64_t)u * KS_SLOT;
   if (deg > KS_CAP) {
     if (!FILL) { if (l == 0) big[u] = 1; }
     return;
@@ -77,7 +81,7 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
   for (int i = l; i < deg; i += 64) {
     int32_t v = col[beg + i];
     L1[i] = v;
-    if (FILL) nbr[o + i] = v;
+    if (put) nbr[o + i] = v;
   }
   int len0 = 0, len1 = deg;   // L0 holds {u} implicitly for h = 2
   int32_t total = deg;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(64 * KS_WAVES) void k_khop_small(
       int pos = cnt_h + __popcll(m & lanemask_lt());
       if (keep) {
         NW[pos] = v;
-        if (FILL) nbr[o + total + pos] = v;
+        if (put) nbr[o + total + pos] = v;
       }
       cnt_h += __popcll(m);
     }
@@ -497,7 +501,7 @@ __global__ void k_small_counts(int32_t n, const int32_t* cnt, const int32_t* big
 }  // namespace
 
 hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, KhopDev* out,
-                      KhopCount* st, hipStream_t s) {
+                      KhopCount* st, hipStream_t s, bool keep_short) {
   out->n = n;
   out->k = k;
   st->k = k;
@@ -518,7 +522,18 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   MM_TRY(st->bigpos.alloc(sizeof(int64_t) * (size_t)(n + 1), s));
   MM_TRY(hipMemsetAsync(st->big.p, 0, sizeof(int32_t) * (size_t)n, s));
   const unsigned gs = (unsigned)((n + KS_WAVES - 1) / KS_WAVES);
-  k_khop_small<false><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, nullptr, out->hend, nullptr,
+  // k = 2: keep the short rows' lists (fixed slots of KS_SLOT ids) so that a
+  // compact copy needs no second search
+  if (keep_short && k == 2) {
+    size_t freeb = 0, totb = 0;
+    int cur = 0;
+    MM_TRY(hipGetDevice(&cur));
+    MM_TRY(hipMemGetInfo(&freeb, &totb));
+    const size_t sb = sizeof(int32_t) * (size_t)n * KS_SLOT;
+    if (sb <= (freeb + big_cached_bytes(cur)) / 8) MM_TRY(st->slots_short.alloc(sb, s));
+  }
+  k_khop_small<false><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, nullptr, out->hend,
+                                                  st->slots_short.as<int32_t>(),
                                                   st->cnt.as<int32_t>(), st->big.as<int32_t>());
   MM_TRY(hipGetLastError());
   MM_TRY(scan_excl_i32(st->big.as<int32_t>(), st->bigpos.as<int64_t>(), n, s));
@@ -691,12 +706,25 @@ hipError_t khop_fill(int32_t n, const int32_t* rp, const int32_t* col, KhopDev* 
 #undef MM_BIG_ONE
 #undef MM_BIG
 
+// off_small[u] = u * KS_SLOT (the short rows' fixed slots)
+__global__ void k_slot_offsets(int32_t n, int64_t* off) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u <= n) off[u] = (int64_t)u * KS_SLOT;
+}
+
 hipError_t khop_fill_small(int32_t n, const int32_t* rp, const int32_t* col, const KhopDev& kh,
                            KhopCount* st, DevBuf* off_small, DevBuf* nbr_small, hipStream_t s) {
   if (st->k < 2) return hipErrorInvalidValue;
+  MM_TRY(off_small->alloc(sizeof(int64_t) * (size_t)(n + 1), s));
+  if (st->slots_short.p) {
+    // the counting pass kept them: row u at u * KS_SLOT (its length is its
+    // last hop end)
+    k_slot_offsets<<<(n + 256) / 256, 256, 0, s>>>(n, off_small->as<int64_t>());
+    *nbr_small = std::move(st->slots_short);
+    return hipGetLastError();
+  }
   DevBuf c;
   MM_TRY(c.alloc(sizeof(int32_t) * (size_t)n, s));
-  MM_TRY(off_small->alloc(sizeof(int64_t) * (size_t)(n + 1), s));
   k_small_counts<<<(n + 255) / 256, 256, 0, s>>>(n, st->cnt.as<int32_t>(), st->big.as<int32_t>(),
                                                  c.as<int32_t>());
   MM_TRY(scan_excl_i32(c.as<int32_t>(), off_small->as<int64_t>(), n, s));

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * TB_WAVES) void k_row_chunks(
   int64_t* base = BASE ? reinterpret_cast<int64_t*>(bm + ((2 * (size_t)ntw + (size_t)ntiles + 1) &
                                                           ~(size_t)1))
                        : nullptr;
-  const int64_t beg = off[u], endr = off[u + 1];
+  const int64_t beg = off[u], endr = beg + hend[(int64_t)u * k + k - 1];
   for (int i = l; i < ntw; i += 64) bm[i] = 0u;
   wave_sync();
   for (int64_t e0 = beg; e0 < endr; e0 += 64 * RU) {
