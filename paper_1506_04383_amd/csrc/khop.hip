@@ -530,7 +530,10 @@ hipError_t khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
     MM_TRY(hipGetDevice(&cur));
     MM_TRY(hipMemGetInfo(&freeb, &totb));
     const size_t sb = sizeof(int32_t) * (size_t)n * KS_SLOT;
-    if (sb <= (freeb + big_cached_bytes(cur)) / 8) MM_TRY(st->slots_short.alloc(sb, s));
+    // (at most 8 GB, n <= 2^20: every short row's slot is written whether
+    // or not the level's tile-major copy ends up reading it)
+    if (sb <= std::min<size_t>((freeb + big_cached_bytes(cur)) / 8, (size_t)8 << 30))
+      MM_TRY(st->slots_short.alloc(sb, s));
   }
   k_khop_small<false><<<gs, 64 * KS_WAVES, 0, s>>>(n, rp, col, k, nullptr, out->hend,
                                                   st->slots_short.as<int32_t>(),
