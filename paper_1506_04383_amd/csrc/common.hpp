@@ -75,6 +75,19 @@ __device__ inline int32_t wave_incl_scan<int32_t>(int32_t v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
+// Minimum over the wave (int32, every lane active): DPP min-scan as above
+// (identity INT32_MAX), then lane 63's value, uniform across the wave.
+template <>
+__device__ inline int32_t wave_min<int32_t>(int32_t v) {
+  constexpr int32_t hi = 0x7fffffff;
+  v = min(v, __builtin_amdgcn_update_dpp(hi, v, 0x111, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(hi, v, 0x112, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(hi, v, 0x114, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(hi, v, 0x118, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(hi, v, 0x142, 0xa, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(hi, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
 // Inclusive max over the wave (int32, DPP as above; identity INT32_MIN).
 __device__ inline int32_t wave_incl_max(int32_t v) {
   constexpr int32_t lo = -2147483647 - 1;
