@@ -50,16 +50,39 @@ __device__ inline bool better(const Cand& a, const Cand& b) {
   if (a.own != b.own) return a.own > b.own;
   return a.lab < b.lab;
 }
+// one step of the wave reduction: compare with the candidate of the lane
+// the DPP control CTRL selects (rows outside RM, and lanes whose source lies
+// outside their row, compare with themselves)
+template <int CTRL, int RM>
+__device__ inline void best_step(Cand& c) {
+  const int32_t lo = (int32_t)(uint32_t)(unsigned long long)c.sc;
+  const int32_t hi = (int32_t)((unsigned long long)c.sc >> 32);
+  Cand d;
+  const uint32_t dlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, RM, 0xf, false);
+  const uint32_t dhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, RM, 0xf, false);
+  d.sc = (long long)(((unsigned long long)dhi << 32) | dlo);
+  d.lab = __builtin_amdgcn_update_dpp(c.lab, c.lab, CTRL, RM, 0xf, false);
+  d.own = __builtin_amdgcn_update_dpp(c.own, c.own, CTRL, RM, 0xf, false);
+  if (better(d, c)) c = d;
+}
+// The best candidate of the wave (every lane active; `better` is a total
+// order, so the result does not depend on the order of the comparisons):
+// DPP row shifts then row broadcasts leave it in lane 63, which every lane
+// reads.
 __device__ inline Cand wave_best(Cand c) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    Cand d;
-    d.sc = __shfl_xor(c.sc, o, 64);
-    d.lab = __shfl_xor(c.lab, o, 64);
-    d.own = __shfl_xor(c.own, o, 64);
-    if (better(d, c)) c = d;
-  }
-  return c;
+  best_step<0x111, 0xf>(c);  // row_shr:1
+  best_step<0x112, 0xf>(c);  // row_shr:2
+  best_step<0x114, 0xf>(c);  // row_shr:4
+  best_step<0x118, 0xf>(c);  // row_shr:8
+  best_step<0x142, 0xa>(c);  // row_bcast:15
+  best_step<0x143, 0xc>(c);  // row_bcast:31
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(unsigned long long)c.sc, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)((unsigned long long)c.sc >> 32), 63);
+  Cand r;
+  r.sc = (long long)(((unsigned long long)hi << 32) | lo);
+  r.lab = __builtin_amdgcn_readlane(c.lab, 63);
+  r.own = __builtin_amdgcn_readlane(c.own, 63);
+  return r;
 }
 __device__ inline uint32_t hslot(int32_t lab, uint32_t mask) {
   return ((uint32_t)lab * 2654435761u) & mask;
