@@ -2,17 +2,23 @@
 // the stress superset of the general maxent-stress model (footnote to Eq. 1),
 // found by a frontier BFS per source vertex.
 //
-// Two kernels, each run once to count (row lengths and per-hop ends) and once
-// to fill (after an int64 scan of the counts gives the row offsets):
+// Two kernels, each with a counting pass (row lengths and per-hop ends) and
+// a filling pass (after an int64 scan of the counts gives the row offsets):
 //  * small rows: one wavefront per source; the hop-h frontier lives in LDS;
 //    candidates (neighbours of the hop-(h-1) frontier) are bitonic-sorted in
 //    LDS, deduplicated, and filtered against hops h-1 and h-2 (a neighbour of
 //    a hop-(h-1) vertex has hop h-2, h-1 or h).  Rows whose candidates exceed
-//    the LDS capacity are flagged for the big-row kernel.
+//    the LDS capacity are flagged for the big-row kernel.  For k = 2 the
+//    counting pass can also keep each row's list in a fixed slot.
 //  * big rows: one workgroup per source with two n-bit bitmaps (visited and
-//    new) in LDS when they fit, otherwise in global memory per workgroup
-//    slot; the hop-h set is extracted in ascending order by scanning the new
-//    bitmap with wave-level prefix sums.
+//    new; one for k = 2) in LDS when they fit, otherwise in global memory per
+//    workgroup slot; the hop-h set is extracted in ascending order by
+//    scanning the new bitmap with wave-level prefix sums.  For k = 2 the
+//    counting pass keeps each row's hop-2 bitmap for the filling pass, and
+//    vertices with long neighbour lists contribute precomputed adjacency
+//    bitmaps by OR instead of one mark per neighbour.
+// The tile-major copy of the sweep can be built straight from the counting
+// pass's state (tilemajor.hip), without the filling pass.
 #include <cstdio>
 #include <cstdlib>
 
