@@ -15,8 +15,7 @@
 // is written to a row-major slot; the combine kernel adds a row's slots in
 // tile order and forms x'_u = (P + alpha F_u) / rho_u (fixed order: the
 // result is run-to-run identical).  rho_u = sum_{S(u)} w_uv is computed once
-// per level from the canonical sets.  The tile-major copy itself is built in
-// tilemajor.hip.
+// per level, with the tile-major copy itself, in tilemajor.hip.
 #include <algorithm>
 #include <vector>
 

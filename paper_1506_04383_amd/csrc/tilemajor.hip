@@ -1,5 +1,6 @@
 // Tile-major copy of the stress sets for the LDS-tiled sweep (tiled.hip):
-// the canonical k-hop sets (sorted by (hop, v) per row) are re-laid per
+// the k-hop sets (sorted by (hop, v) per row; canonical ids, or for k = 2
+// the bitmaps the search kept for its long rows) are re-laid per
 // (row, tile) chunk, 16 bits per entry ((v - tile * T) << 3 | hop), chunks
 // ordered by tile and, within a tile, by decreasing length; either
 // consecutively (work units of <= kUnitChunks chunks) or in the sliced
