@@ -69,15 +69,13 @@ __global__ __launch_bounds__(256) void k_seg_delta(const int32_t* __restrict__ g
 //   rounds (alpha > alpha_min): after `a` iterations or when delta < eps_round,
 //     alpha := max(decay * alpha, alpha_min);
 //   final phase (alpha_min): until delta < eps_final or max_final iterations.
-// galpha receives the alpha of the next iteration (-1 once finished).
-__global__ void k_schedule(int32_t M, const double2* __restrict__ gd, BatchSched prm,
-                           BatchState* __restrict__ st, float* __restrict__ galpha,
-                           int32_t* __restrict__ counters) {
-  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= M) return;
-  BatchState S = st[g];
-  if (S.phase >= 2) { galpha[g] = -1.f; return; }
-  const double2 d = gd[g];
+// Returns the alpha of the next iteration (-1 once finished); counters[0]
+// counts the graphs still iterating, counters[1] those with a non-finite
+// layout.
+__device__ float sched_step(const double2 d, const BatchSched& prm, BatchState* __restrict__ sp,
+                            int32_t* __restrict__ counters) {
+  BatchState S = *sp;
+  if (S.phase >= 2) return -1.f;
   const double delta = d.y > 0.0 ? sqrt(d.x / d.y) : INFINITY;
   S.delta = delta;
   S.iters++;
@@ -101,9 +99,25 @@ __global__ void k_schedule(int32_t M, const double2* __restrict__ gd, BatchSched
       S.cap_hit = 1;
     }
   }
-  st[g] = S;
-  galpha[g] = S.phase == 0 ? (float)S.alpha : S.phase == 1 ? (float)prm.alpha_min : -1.f;
+  *sp = S;
   if (S.phase < 2) atomicAdd(&counters[0], 1);
+  return S.phase == 0 ? (float)S.alpha : S.phase == 1 ? (float)prm.alpha_min : -1.f;
+}
+__global__ void k_schedule(int32_t M, const double2* __restrict__ gd, BatchSched prm,
+                           BatchState* __restrict__ st, float* __restrict__ galpha,
+                           int32_t* __restrict__ counters) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M) return;
+  galpha[g] = sched_step(gd[g], prm, &st[g], counters);
+}
+// One graph (single layouts): the counters start at zero here (a kernel, not
+// a memset: the step is replayed from HIP graphs).
+__global__ void k_schedule_one(const double2* __restrict__ d, BatchSched prm,
+                               BatchState* __restrict__ st, float* __restrict__ alpha,
+                               int32_t* __restrict__ counters) {
+  counters[0] = 0;
+  counters[1] = 0;
+  alpha[0] = sched_step(d[0], prm, st, counters);
 }
 
 __global__ void k_sched_init(int32_t M, BatchSched prm, double alpha_start,
@@ -209,6 +223,12 @@ hipError_t batch_sched_init(int32_t M, const BatchSched& prm, double alpha_start
 hipError_t batch_schedule(int32_t M, const double* gd, const BatchSched& prm, BatchState* st,
                           float* galpha, int32_t* counters, hipStream_t s) {
   k_schedule<<<nb256(M), 256, 0, s>>>(M, (const double2*)gd, prm, st, galpha, counters);
+  return hipGetLastError();
+}
+
+hipError_t schedule_one(const double* d2, const BatchSched& prm, BatchState* st, float* alpha,
+                        int32_t* counters, hipStream_t s) {
+  k_schedule_one<<<1, 1, 0, s>>>(reinterpret_cast<const double2*>(d2), prm, st, alpha, counters);
   return hipGetLastError();
 }
 

@@ -27,6 +27,9 @@
 // between two host checks of the running-graph count (even: a replay keeps
 // the parity of the coordinate buffers).
 constexpr int32_t kBatchReplay = 4;
+// iterations a single layout enqueues between two reads of its device-side
+// schedule state
+constexpr int32_t kIterChunk = 8;
 // Single-graph levels replay far field and sweep from two graphs above this
 // many vertices, from one graph at or below it.
 constexpr int32_t kSplitMinN = 1 << 16;
@@ -36,8 +39,7 @@ struct mm_context {
   hipStream_t stream = nullptr;  // the caller's stream
   hipStream_t work = nullptr;    // the layout drivers' own stream (capturable)
   mm::BHWork* bh = nullptr;
-  double* pinned = nullptr;      // 4 doubles for small read-backs
-  float* alpha_pinned = nullptr; // alpha of the next replayed iteration
+  double* pinned = nullptr;      // 16 doubles for small read-backs
   float* alpha_dev = nullptr;
   hipStream_t far = nullptr;     // far field of mm_layout, beside the sweep on `work`
   hipEvent_t ev[8] = {};
@@ -386,8 +388,7 @@ mm_status mm_context_create(mm_context** out, int32_t device, void* stream) {
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->bh = mm::bh_work_create();
-    HIPCHK(hipHostMalloc((void**)&c->pinned, 4 * sizeof(double), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&c->alpha_pinned, sizeof(float), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->pinned, 16 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipMalloc((void**)&c->alpha_dev, sizeof(float)));
     HIPCHK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->far, hipStreamNonBlocking));
@@ -426,7 +427,6 @@ void mm_context_destroy(mm_context* ctx) {
   if (ctx->work) mm::big_unregister(ctx->work);
   if (ctx->far) mm::big_unregister(ctx->far);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-  if (ctx->alpha_pinned) (void)hipHostFree(ctx->alpha_pinned);
   if (ctx->alpha_dev) (void)hipFree(ctx->alpha_dev);
   if (ctx->work) (void)hipStreamDestroy(ctx->work);
   if (ctx->far) (void)hipStreamDestroy(ctx->far);
@@ -1224,25 +1224,49 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         return mm::farfield_bh(ctx->bh, nl, xin, p->q, p->theta, F.as<float>(), nullptr, nullptr,
                                nullptr, nullptr, 0, nullptr, s2);
       };
+      // The alpha schedule of Section 3.2 runs on the device (the state
+      // machine of a batch's graphs, for one graph): after each iteration a
+      // one-thread kernel takes the relative change from the combine's sums
+      // and writes the alpha of the next iteration, or -1 once the level is
+      // done (the sweep then carries x over unchanged).  The host launches
+      // up to kIterChunk iterations at a time and reads the state once per
+      // chunk, so no iteration waits for a host round trip; a chunk never
+      // exceeds the level's largest possible iteration count, so iterations
+      // past the stop happen only when the relative change ends it early.
+      mm::BatchSched prm;
+      prm.alpha_min = p->alpha_min;
+      prm.decay = p->alpha_decay;
+      prm.eps_round = p->eps_round;
+      prm.eps_final = p->eps_final;
+      prm.a = p->iters_per_round;
+      prm.max_final = p->max_final_iters;
+      mm::DevBuf sst, scnt;
+      HIPCHK(sst.alloc(sizeof(mm::BatchState), s));
+      HIPCHK(scnt.alloc(2 * sizeof(int32_t), s));
+      const double alpha_start = init_xy ? p->alpha_min : p->alpha0;
+      HIPCHK(mm::batch_sched_init(1, prm, alpha_start, sst.as<mm::BatchState>(), ctx->alpha_dev, s));
+      int32_t max_iters = p->max_final_iters;  // every round at full length, then the cap
+      for (double a0 = alpha_start; a0 > p->alpha_min; a0 = std::max(a0 * p->alpha_decay, p->alpha_min))
+        max_iters += p->iters_per_round;
       // the part of the sweep that does not read F (tiled levels)
-      auto sweep_sums = [&](double alpha, const float* xin, const float* adev) -> hipError_t {
+      auto sweep_sums = [&](const float* xin) -> hipError_t {
         if (!ts.built) return hipSuccess;
-        return mm::sweep_tiled_partial(ts, lvl, sqrtc, p->coarse_dist_scale, xin, alpha, p->q, s,
-                                       adev, group_lvl, nb_lvl);
+        return mm::sweep_tiled_partial(ts, lvl, sqrtc, p->coarse_dist_scale, xin, 0.0, p->q, s,
+                                       ctx->alpha_dev, group_lvl, nb_lvl);
       };
-      // the part that reads F, and the relative-change sums to pinned memory
-      auto sweep_finish = [&](double alpha, const float* xin, float* xout,
-                              const float* adev) -> hipError_t {
+      // the part that reads F, the relative-change sums and the schedule step
+      auto sweep_finish = [&](const float* xin, float* xout) -> hipError_t {
         if (ts.built)
-          MM_TRY(mm::sweep_tiled_combine(ts, rho.as<float>(), xin, F.as<float>(), alpha, xout,
-                                         d2.as<double>(), s, adev));
+          MM_TRY(mm::sweep_tiled_combine(ts, rho.as<float>(), xin, F.as<float>(), 0.0, xout,
+                                         d2.as<double>(), s, ctx->alpha_dev));
         else
-          MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), alpha, p->q,
-                           xout, d2.as<double>(), s, nullptr, nullptr, adev, &sweep_part,
-                           group_lvl));
-        return hipMemcpyAsync(ctx->pinned, d2.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+          MM_TRY(mm::sweep(kh, lvl, sqrtc, p->coarse_dist_scale, xin, F.as<float>(), 0.0, p->q,
+                           xout, d2.as<double>(), s, nullptr, nullptr, ctx->alpha_dev,
+                           &sweep_part, group_lvl));
+        return mm::schedule_one(d2.as<double>(), prm, sst.as<mm::BatchState>(), ctx->alpha_dev,
+                                scnt.as<int32_t>(), s);
       };
-      hipEvent_t ex = ctx->ev[4], ej = ctx->ev[5], ef0 = ctx->ev[6], ej_t = ctx->ev[7];
+      hipEvent_t ex = ctx->ev[4];
       // After one direct iteration per level (which sizes every buffer), the
       // iteration is captured once per direction (A -> B, B -> A) and
       // replayed.  Levels above kSplitMinN vertices keep three graphs -- far
@@ -1264,6 +1288,15 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         hipGraphExec_t* g;
         ~GraphGuard() { for (int i = 0; i < 6; ++i) if (g[i]) (void)hipGraphExecDestroy(g[i]); }
       } gguard{gx};
+      // six timing events per iteration of a chunk: s before and after the
+      // stress sums, before and after the combine; s2 before and after the
+      // far field (the last is also the join)
+      struct EventSet {
+        std::vector<hipEvent_t> e;
+        ~EventSet() { for (hipEvent_t x : e) (void)hipEventDestroy(x); }
+      } evs;
+      evs.e.resize(6 * kIterChunk, nullptr);
+      for (auto& x : evs.e) HIPCHK(hipEventCreate(&x));
       struct FarJoin {  // no far-field work outlives the level's graphs and buffers
         hipStream_t s2;
         ~FarJoin() { (void)hipStreamSynchronize(s2); }
@@ -1283,116 +1316,127 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
         if (e3 != hipSuccess) { *out = nullptr; (void)hipGetLastError(); return false; }
         return true;
       };
-      auto alpha_upload = [&]() -> hipError_t {
-        return hipMemcpyAsync(ctx->alpha_dev, ctx->alpha_pinned, sizeof(float),
-                              hipMemcpyHostToDevice, s);
-      };
       auto capture = [&]() -> bool {
+        hipEvent_t ej = ctx->ev[5];
         for (int d = 0; d < 2; ++d) {
           const float* xin = d ? bufB : bufA;
           float* xout = d ? bufA : bufB;
           if (split_graphs) {
             if (!capture_one(s2, &gx[d], [&]() { return far(xin); })) return false;
-            if (!capture_one(s, &gx[2 + d], [&]() -> hipError_t {
-                  MM_TRY(alpha_upload());
-                  return sweep_sums(0.0, xin, ctx->alpha_dev);
-                }))
-              return false;
-            if (!capture_one(s, &gx[4 + d],
-                             [&]() { return sweep_finish(0.0, xin, xout, ctx->alpha_dev); }))
-              return false;
+            if (!capture_one(s, &gx[2 + d], [&]() { return sweep_sums(xin); })) return false;
+            if (!capture_one(s, &gx[4 + d], [&]() { return sweep_finish(xin, xout); })) return false;
           } else {
             if (!capture_one(s, &gx[d], [&]() -> hipError_t {
-                  MM_TRY(alpha_upload());
                   MM_TRY(hipEventRecord(ex, s));
                   MM_TRY(hipStreamWaitEvent(s2, ex, 0));
                   MM_TRY(far(xin));
                   MM_TRY(hipEventRecord(ej, s2));
-                  MM_TRY(sweep_sums(0.0, xin, ctx->alpha_dev));
+                  MM_TRY(sweep_sums(xin));
                   MM_TRY(hipStreamWaitEvent(s, ej, 0));
-                  return sweep_finish(0.0, xin, xout, ctx->alpha_dev);
+                  return sweep_finish(xin, xout);
                 }))
               return false;
           }
         }
         return true;
       };
-      auto iterate = [&](double alpha) -> mm_status {
-        const float* xin = parity ? bufB : bufA;
-        float* xout = parity ? bufA : bufB;
-        if (want_graph && iters >= 1 && !gx[0] && !graph_failed) {
+      // enqueue one iteration (no host wait) with the events of chunk slot r
+      int32_t launched = 0;
+      auto launch = [&](int r) -> mm_status {
+        if (want_graph && launched >= 1 && !gx[0] && !graph_failed) {
           if (!capture()) {
             graph_failed = true;
             for (auto& g2 : gx) if (g2) { (void)hipGraphExecDestroy(g2); g2 = nullptr; }
           }
         }
-        float a = 0, b = 0;
+        const float* xin = parity ? bufB : bufA;
+        float* xout = parity ? bufA : bufB;
+        hipEvent_t* E = &evs.e[6 * r];
         if (gx[parity] && !split_graphs) {
-          *ctx->alpha_pinned = (float)alpha;
-          HIPCHK(hipEventRecord(ctx->ev[0], s));
+          HIPCHK(hipEventRecord(E[0], s));
           HIPCHK(hipGraphLaunch(gx[parity], s));
-          HIPCHK(hipEventRecord(ctx->ev[2], s));
-          HIPCHK(hipStreamSynchronize(s));
-          float ab = 0;
-          HIPCHK(hipEventElapsedTime(&ab, ctx->ev[0], ctx->ev[2]));
-          a = (float)(ab * split);
-          b = (float)(ab * (1.0 - split));
-          lvl_wall += ab;
+          HIPCHK(hipEventRecord(E[3], s));
         } else {
           // fork: the far field of xin on s2
           HIPCHK(hipEventRecord(ex, s));
           HIPCHK(hipStreamWaitEvent(s2, ex, 0));
-          HIPCHK(hipEventRecord(ef0, s2));
+          HIPCHK(hipEventRecord(E[4], s2));
           if (gx[parity]) HIPCHK(hipGraphLaunch(gx[parity], s2));
           else HIPCHK(far(xin));
-          HIPCHK(hipEventRecord(ej_t, s2));
+          HIPCHK(hipEventRecord(E[5], s2));
           // the stress sums on s, then join and combine
-          HIPCHK(hipEventRecord(ctx->ev[0], s));
-          if (gx[parity]) {
-            *ctx->alpha_pinned = (float)alpha;
-            HIPCHK(hipGraphLaunch(gx[2 + parity], s));
-          } else {
-            HIPCHK(sweep_sums(alpha, xin, nullptr));
-          }
-          HIPCHK(hipEventRecord(ctx->ev[1], s));
-          HIPCHK(hipStreamWaitEvent(s, ej_t, 0));
-          HIPCHK(hipEventRecord(ctx->ev[3], s));
+          HIPCHK(hipEventRecord(E[0], s));
+          if (gx[parity]) HIPCHK(hipGraphLaunch(gx[2 + parity], s));
+          else HIPCHK(sweep_sums(xin));
+          HIPCHK(hipEventRecord(E[1], s));
+          HIPCHK(hipStreamWaitEvent(s, E[5], 0));
+          HIPCHK(hipEventRecord(E[2], s));
           if (gx[parity]) HIPCHK(hipGraphLaunch(gx[4 + parity], s));
-          else HIPCHK(sweep_finish(alpha, xin, xout, nullptr));
-          HIPCHK(hipEventRecord(ctx->ev[2], s));
-          HIPCHK(hipStreamSynchronize(s));
-          float b1 = 0, b2 = 0, wall = 0;
-          HIPCHK(hipEventElapsedTime(&a, ef0, ej_t));
-          HIPCHK(hipEventElapsedTime(&b1, ctx->ev[0], ctx->ev[1]));
-          HIPCHK(hipEventElapsedTime(&b2, ctx->ev[3], ctx->ev[2]));
-          HIPCHK(hipEventElapsedTime(&wall, ctx->ev[0], ctx->ev[2]));
+          else HIPCHK(sweep_finish(xin, xout));
+          HIPCHK(hipEventRecord(E[3], s));
+        }
+        parity ^= 1;
+        launched++;
+        return MM_OK;
+      };
+      // the times of an iteration of the chunk (after the chunk's wait)
+      auto account = [&](int r, bool direct_split) -> mm_status {
+        hipEvent_t* E = &evs.e[6 * r];
+        float a = 0, b = 0, wall = 0;
+        if (!direct_split) {
+          HIPCHK(hipEventElapsedTime(&wall, E[0], E[3]));
+          a = (float)(wall * split);
+          b = (float)(wall * (1.0 - split));
+        } else {
+          float b1 = 0, b2 = 0;
+          HIPCHK(hipEventElapsedTime(&a, E[4], E[5]));
+          HIPCHK(hipEventElapsedTime(&b1, E[0], E[1]));
+          HIPCHK(hipEventElapsedTime(&b2, E[2], E[3]));
+          HIPCHK(hipEventElapsedTime(&wall, E[0], E[3]));
           b = b1 + b2;
-          lvl_wall += wall;
-          if (!gx[parity] && a + b > 0) split = a / (a + b);
         }
         t_far += a;
         t_sweep += b;
         lvl_far += a;
         lvl_sweep += b;
-        delta = ctx->pinned[1] > 0 ? std::sqrt(ctx->pinned[0] / ctx->pinned[1]) : INFINITY;
-        if (!std::isfinite(delta)) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
-        parity ^= 1;
-        iters++;
+        lvl_wall += wall;
         return MM_OK;
       };
-      double alpha = init_xy ? p->alpha_min : p->alpha0;
-      while (alpha > p->alpha_min) {
-        for (int32_t it = 0; it < p->iters_per_round; ++it) {
-          STCHK(iterate(alpha));
-          if (delta < p->eps_round) break;
+      mm::BatchState* hstate = reinterpret_cast<mm::BatchState*>(ctx->pinned + 8);
+      int32_t* hcnt = reinterpret_cast<int32_t*>(ctx->pinned + 14);
+      for (;;) {
+        const int32_t chunk = std::max<int32_t>(1, std::min<int32_t>(
+            launched == 0 ? 1 : kIterChunk, max_iters - launched));
+        const int32_t first = launched;
+        bool single_graph[kIterChunk];
+        for (int32_t r = 0; r < chunk; ++r) {
+          STCHK(launch(r));
+          single_graph[r] = gx[(parity ^ 1)] != nullptr && !split_graphs;
         }
-        alpha = std::max(alpha * p->alpha_decay, p->alpha_min);
-      }
-      for (int32_t it = 0; it < p->max_final_iters; ++it) {
-        STCHK(iterate(p->alpha_min));
-        final_iters++;
-        if (delta < p->eps_final) break;
-        if (it == p->max_final_iters - 1) cap_hit = 1;
+        HIPCHK(hipMemcpyAsync(hstate, sst.p, sizeof(mm::BatchState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hcnt, scnt.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const mm::BatchState S = *hstate;
+        // (the counters describe the chunk's last step; a non-finite layout
+        // also leaves the state in phase 3)
+        if (hcnt[1] > 0 || S.phase == 3) return fail(MM_EINTERNAL, "non-finite layout at level %d", lvl);
+        for (int32_t r = 0; r < chunk; ++r) {
+          if (first + r >= S.iters) break;  // past the level's stop: copies only
+          STCHK(account(r, !single_graph[r]));
+          // the direct iteration sets the far / sweep ratio of single graphs
+          if (first + r == 0 && !split_graphs) {
+            float a = 0, b1 = 0, b2 = 0;
+            HIPCHK(hipEventElapsedTime(&a, evs.e[6 * r + 4], evs.e[6 * r + 5]));
+            HIPCHK(hipEventElapsedTime(&b1, evs.e[6 * r], evs.e[6 * r + 1]));
+            HIPCHK(hipEventElapsedTime(&b2, evs.e[6 * r + 2], evs.e[6 * r + 3]));
+            if (a + b1 + b2 > 0) split = a / (a + b1 + b2);
+          }
+        }
+        iters = S.iters;
+        final_iters = S.final_iters;
+        cap_hit = S.cap_hit;
+        delta = S.delta;
+        if (hcnt[0] == 0 || launched >= max_iters) break;
       }
       if (parity) std::swap(xa, xb);  // the level's result in xa
       if (lvl < MM_MAX_LEVELS) {

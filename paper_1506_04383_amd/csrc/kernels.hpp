@@ -391,6 +391,10 @@ hipError_t batch_sched_init(int32_t M, const BatchSched& prm, double alpha_start
 // counters[0] += graphs still iterating, counters[1] += graphs with a non-finite layout
 hipError_t batch_schedule(int32_t M, const double* gd, const BatchSched& prm, BatchState* st,
                           float* galpha, int32_t* counters, hipStream_t s);
+// The same step for a single layout (d2: sum |x'-x|^2, sum |x|^2; counters
+// zeroed first; alpha: the next iteration's alpha, -1 once finished).
+hipError_t schedule_one(const double* d2, const BatchSched& prm, BatchState* st, float* alpha,
+                        int32_t* counters, hipStream_t s);
 hipError_t batch_coarse_offsets(int32_t n, int32_t M, int32_t nc, const int32_t* cluster,
                                 const int32_t* gid, int32_t* gidc, int32_t* goffc, hipStream_t s);
 // The graphs flagged in keep (vertex flags / new ids into flag[n], newid[n+1]).
