@@ -16,9 +16,11 @@ struct BHNode {
   float mass;
   int32_t skip;
   uint32_t ox, oy;
-  int32_t meta;   // depth | leaf << 8
+  int32_t meta;   // depth | c << 8: c = 0 for an internal node, else the leaf's
+                  // point count (kLeafCountSat and above: read mass)
   int32_t first;  // first point (sorted order)
 };
+constexpr int32_t kLeafCountSat = (1 << 23) - 1;
 
 struct BoxInfo {
   double xmin, ymin, scale;

@@ -341,7 +341,7 @@ __global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* _
   uint2 q = ixy[first];
   nd.ox = q.x & mask;
   nd.oy = q.y & mask;
-  nd.meta = depth | (leaf << 8);
+  nd.meta = depth | ((leaf ? min(cnt, kLeafCountSat) : 0) << 8);
   nd.first = first;
   nodes[p] = nd;
   if (export_nodes) {
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(BHS_T) void k_bh_small(
     const uint32_t mask = depth >= 24 ? 0xFFFFFFu : ~((1u << (24 - depth)) - 1u) & 0xFFFFFFu;
     nd.ox = compact24(c0) & mask;
     nd.oy = compact24(c0 >> 1) & mask;
-    nd.meta = depth | ((leaf ? 1 : 0) << 8);
+    nd.meta = depth | ((leaf ? min(cnt, kLeafCountSat) : 0) << 8);
     nd.first = first;
     nodes[p] = nd;
     if (export_nodes) {
@@ -544,63 +544,84 @@ constexpr int TR_WAVES = 4;
 
 // Interactions of one lane's target (xt, yt; quantum cell (qx2i, qy2i)
 // doubled) with node nd at index p: leaf terms, or the opening test and the
-// cell term.  Returns true when the lane opens the node.
-template <bool STATS>
-__device__ inline bool visit_node(const BHNode& nd, int32_t i, float xt, float yt, int32_t qx2i,
-                                  int32_t qy2i, float q, double theta2,
+// cell term.  Returns true when the lane opens the node.  CT: test whether
+// the cell contains u.  Without it the decisions are the same for
+// theta^2 <= 2: u in C means |d| <= S - 1 on both axes, so theta^2 d4 <=
+// 4 (S - 1)^2 < 4 S^2 (rounding is monotone and 4 (S - 1)^2 is exact), and
+// the cell fails the distance test anyway.
+template <bool STATS, bool CT>
+__device__ inline void visit_node(const BHNode& nd, bool act, int32_t i, float xt, float yt,
+                                  int32_t qx2i, int32_t qy2i, float q, double theta2,
                                   const float* __restrict__ xsx, const float* __restrict__ xsy,
-                                  float& fx, float& fy, unsigned long long& acc,
-                                  unsigned long long& pairs) {
-  if (nd.meta >> 8) {
-    // leaf: exact terms for its points (a single point's coordinates are in
-    // the node record)
-    const int32_t cnt = (int32_t)nd.mass;
-    if (cnt == 1) {
-      if (nd.first != i) {
-        const bool added = rq_add(xt - (float)nd.cx, yt - (float)nd.cy, q, 1.f, fx, fy);
-        if (STATS && added) pairs++;
-      }
-    } else {
-      for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
-        const float sx = xsx[j], sy = xsy[j];
-        if (j != i) {
-          const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
-          if (STATS && added) pairs++;
-        }
+                                  int32_t skipv, int32_t& wait, float& fx, float& fy,
+                                  unsigned long long& acc, unsigned long long& pairs) {
+  // An accepted cell and a single-point leaf (whose record holds the
+  // point's coordinates and mass 1) add the same term: rounding the FP64
+  // difference of two floats to FP32 gives their FP32 difference
+  // (53 >= 2 * 24 + 2).  The record is wave-uniform, so the node kind,
+  // mass and cell centre are scalars and the kind is a scalar branch.
+  const float m = __builtin_bit_cast(
+      float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int32_t, nd.mass)));
+  const int32_t lc = __builtin_amdgcn_readfirstlane(nd.meta >> 8);
+  if (lc == 0) {
+    // opening test in exact integers: offsets of u's quantum-cell centre
+    // from the cell centre (doubled); |d| < S on both axes <=> u in C;
+    // d4 < 2^52 and 4 S^2 are exact doubles, so theta^2 d4 > 4 S^2 rounds
+    // exactly as the same test written with 64-bit integers.  4 S^2 =
+    // 2^(2 sh + 2) is assembled from its exponent bits.
+    const int sh = 24 - (nd.meta & 0xff);
+    const int32_t S = 1 << sh;
+    const int32_t cx2 = __builtin_amdgcn_readfirstlane((int32_t)(2u * nd.ox + (uint32_t)S));
+    const int32_t cy2 = __builtin_amdgcn_readfirstlane((int32_t)(2u * nd.oy + (uint32_t)S));
+    const double s4 = __hiloint2double((1023 + 2 * sh + 2) << 20, 0);
+    if (act) {
+      const int32_t dxi = qx2i - cx2;
+      const int32_t dyi = qy2i - cy2;
+      const bool contains = CT && abs(dxi) < S && abs(dyi) < S;
+      const double dxd = (double)dxi, dyd = (double)dyi;
+      const double d4 = fma(dxd, dxd, dyd * dyd);
+      if (!contains && theta2 * d4 > s4) {
+        // accepted: the lane does not descend
+        wait = skipv;
+        rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, m, fx, fy);
+        if (STATS) acc++;
       }
     }
-    return false;
+  } else if (lc == 1) {
+    if (act) {
+      wait = skipv;
+      if (nd.first != i) {
+        const bool added =
+            rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, 1.f, fx, fy);
+        if (STATS && added) pairs++;
+      }
+    }
+  } else if (act) {
+    // leaf of several points: exact terms from the point arrays
+    wait = skipv;
+    const int32_t cnt = lc == kLeafCountSat ? (int32_t)m : lc;
+    for (int32_t j = nd.first; j < nd.first + cnt; ++j) {
+      const float sx = xsx[j], sy = xsy[j];
+      if (j != i) {
+        const bool added = rq_add(xt - sx, yt - sy, q, 1.f, fx, fy);
+        if (STATS && added) pairs++;
+      }
+    }
   }
-  // opening test in exact integers: offsets of u's quantum-cell centre from
-  // the cell centre (doubled); |d| < S on both axes <=> u in C; d4 < 2^52 and
-  // 4 S^2 are exact doubles, so theta^2 d4 > 4 S^2 rounds exactly as the same
-  // test written with 64-bit integers
-  const int depth = nd.meta & 0xff;
-  const int sh = 24 - depth;
-  const int32_t S = 1 << sh;
-  const int32_t dxi = qx2i - (int32_t)(2u * nd.ox + (uint32_t)S);
-  const int32_t dyi = qy2i - (int32_t)(2u * nd.oy + (uint32_t)S);
-  const bool contains = abs(dxi) < S && abs(dyi) < S;
-  const double dxd = (double)dxi, dyd = (double)dyi;
-  const double d4 = fma(dxd, dxd, dyd * dyd);
-  const bool accept = !contains && theta2 * d4 > (double)((int64_t)S * S * 4);
-  if (accept) {
-    rq_add((float)((double)xt - nd.cx), (float)((double)yt - nd.cy), q, nd.mass, fx, fy);
-    if (STATS) acc++;
-    return false;
-  }
-  return true;
 }
 
 // One wavefront walks the pre-order node array once for 64 Morton-consecutive
-// targets; a lane takes part at node p when its own walk is at p (next == p).
+// targets; a lane takes part at node p when its own walk is at p.
 // One tree (no batch): the wave's next node is p + 1 when some lane opens p,
 // else skip(p) -- a lane that is not at p waits at a node after p's subtree
-// (its walk never entered that subtree), i.e. at or after skip(p).  Both
-// candidate records are loaded as soon as p's record is there, so their
-// latency overlaps p's work.  Batches (one tree per graph, per-lane root and
-// end) take the minimum of the lanes' next nodes instead.
-template <bool STATS, bool SEG>
+// (its walk never entered that subtree), i.e. at or after skip(p).  So a lane
+// keeps only the node it waits for, `wait`, set when it does not open: a lane
+// that opens p is at p + 1, the wave's next node, and the lanes at the
+// wave's node p are exactly those with wait <= p.  Both candidate records
+// are loaded as soon as p's record is there, so their latency overlaps p's
+// work.  Batches (one tree per graph, per-lane root and end) take the
+// minimum of the lanes' next nodes instead.
+template <bool STATS, bool SEG, bool CT>
 __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     const BHNode* __restrict__ nodes, const int32_t* __restrict__ Np, const float* __restrict__ xsx,
     const float* __restrict__ xsy, const uint2* __restrict__ ixy, const int32_t* __restrict__ order,
@@ -618,19 +639,16 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
   float fx = 0.f, fy = 0.f;
   unsigned long long acc = 0, pairs = 0;
   if (!SEG) {
-    int32_t next = valid ? 0 : 0x7fffffff;
+    int32_t wait = valid ? 0 : 0x7fffffff;
     int32_t p = 0;
     BHNode nd = nodes[0];
     while (p < N) {
       const BHNode na = nodes[min(p + 1, N - 1)];
       const BHNode nb = nodes[min(nd.skip, N - 1)];
-      bool opened = false;
-      if (next == p) {
-        opened = visit_node<STATS>(nd, i, xt, yt, qx2i, qy2i, q, theta2, xsx, xsy, fx, fy, acc,
-                                   pairs);
-        next = opened ? p + 1 : (nd.skip >= N ? 0x7fffffff : nd.skip);
-      }
-      const bool down = __any(opened);
+      visit_node<STATS, CT>(nd, wait <= p, i, xt, yt, qx2i, qy2i, q, theta2, xsx, xsy,
+                            nd.skip >= N ? 0x7fffffff : nd.skip, wait, fx, fy, acc, pairs);
+      // the lanes that opened p are the ones still at or before it
+      const bool down = __builtin_amdgcn_ballot_w64(wait <= p) != 0;
       p = down ? p + 1 : nd.skip;
       nd = down ? na : nb;
     }
@@ -648,12 +666,12 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     while (p < N) {
       p = __builtin_amdgcn_readfirstlane(p);
       const BHNode nd = nodes[p];
-      bool opened = false;
-      if (next == p) {
-        opened = visit_node<STATS>(nd, i, xt, yt, qx2i, qy2i, q, theta2, xsx, xsy, fx, fy, acc,
-                                   pairs);
-        next = opened ? p + 1 : (nd.skip >= end ? 0x7fffffff : nd.skip);
-      }
+      // visit_node leaves `next` at p when the lane opens p
+      const bool act = next == p;
+      visit_node<STATS, CT>(nd, act, i, xt, yt, qx2i, qy2i, q, theta2, xsx, xsy,
+                            nd.skip >= end ? 0x7fffffff : nd.skip, next, fx, fy, acc, pairs);
+      const bool opened = act && next == p;
+      if (opened) next = p + 1;
       if (__any(opened)) p = p + 1;
       else p = wave_min(next);
     }
@@ -846,13 +864,18 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
   if (count_stats) MM_TRY(hipMemsetAsync(w->statc.p, 0, 2 * sizeof(unsigned long long), s));
   const int32_t nw = (n + 63) / 64;
   const int32_t nblk = (nw + TR_WAVES - 1) / TR_WAVES;
-#define MM_TR(ST, SG)                                                                            \
-  k_traverse<ST, SG><<<nblk, 64 * TR_WAVES, 0, s>>>(                                               \
+  // the containment test is needed only above theta^2 = 2 (visit_node)
+  const double theta2 = theta * theta;
+  const bool ct = theta2 > 2.0;
+#define MM_TR(ST, SG, CT)                                                                        \
+  k_traverse<ST, SG, CT><<<nblk, 64 * TR_WAVES, 0, s>>>(                                           \
       w->nodes.as<BHNode>(), Np, w->xsx.as<float>(), w->xsy.as<float>(), w->ix.as<uint2>(),       \
-      w->order.as<int32_t>(), n, (float)q, theta * theta, (float2*)F,                              \
+      w->order.as<int32_t>(), n, (float)q, theta2, (float2*)F,                                     \
       ST ? w->statc.as<unsigned long long>() : nullptr, sc, go, w->first_at.as<int32_t>())
-  if (count_stats) { if (seg) MM_TR(true, true); else MM_TR(true, false); }
-  else { if (seg) MM_TR(false, true); else MM_TR(false, false); }
+#define MM_TR2(ST, SG) { if (ct) MM_TR(ST, SG, true); else MM_TR(ST, SG, false); }
+  if (count_stats) { if (seg) MM_TR2(true, true) else MM_TR2(true, false) }
+  else { if (seg) MM_TR2(false, true) else MM_TR2(false, false) }
+#undef MM_TR2
 #undef MM_TR
   MM_TRY(hipGetLastError());
   if (codes_out) {

@@ -324,7 +324,8 @@ __device__ inline bool open_test(const BHNode& nd, int32_t qx2i, int32_t qy2i, d
   const int32_t dyi = qy2i - (int32_t)(2u * nd.oy + (uint32_t)S);
   if (abs(dxi) < S && abs(dyi) < S) return false;
   const double dxd = (double)dxi, dyd = (double)dyi;
-  return theta2 * fma(dxd, dxd, dyd * dyd) > (double)((int64_t)S * S * 4);
+  // 4 S^2 = 2^(2 sh + 2) from its exponent bits (exact)
+  return theta2 * fma(dxd, dxd, dyd * dyd) > __hiloint2double((1023 + 2 * sh + 2) << 20, 0);
 }
 
 // ---------------------------------------------------------------- traversal
