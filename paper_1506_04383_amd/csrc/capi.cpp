@@ -1328,10 +1328,10 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
           } else {
             if (!capture_one(s, &gx[d], [&]() -> hipError_t {
                   MM_TRY(hipEventRecord(ex, s));
+                  MM_TRY(sweep_sums(xin));
                   MM_TRY(hipStreamWaitEvent(s2, ex, 0));
                   MM_TRY(far(xin));
                   MM_TRY(hipEventRecord(ej, s2));
-                  MM_TRY(sweep_sums(xin));
                   MM_TRY(hipStreamWaitEvent(s, ej, 0));
                   return sweep_finish(xin, xout);
                 }))
@@ -1357,18 +1357,19 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
           HIPCHK(hipGraphLaunch(gx[parity], s));
           HIPCHK(hipEventRecord(E[3], s));
         } else {
-          // fork: the far field of xin on s2
+          // fork: the stress sums on s are enqueued first, so the GPU starts
+          // them while the host is still launching the far field of xin on s2
           HIPCHK(hipEventRecord(ex, s));
+          HIPCHK(hipEventRecord(E[0], s));
+          if (gx[parity]) HIPCHK(hipGraphLaunch(gx[2 + parity], s));
+          else HIPCHK(sweep_sums(xin));
+          HIPCHK(hipEventRecord(E[1], s));
           HIPCHK(hipStreamWaitEvent(s2, ex, 0));
           HIPCHK(hipEventRecord(E[4], s2));
           if (gx[parity]) HIPCHK(hipGraphLaunch(gx[parity], s2));
           else HIPCHK(far(xin));
           HIPCHK(hipEventRecord(E[5], s2));
-          // the stress sums on s, then join and combine
-          HIPCHK(hipEventRecord(E[0], s));
-          if (gx[parity]) HIPCHK(hipGraphLaunch(gx[2 + parity], s));
-          else HIPCHK(sweep_sums(xin));
-          HIPCHK(hipEventRecord(E[1], s));
+          // join, then the combine
           HIPCHK(hipStreamWaitEvent(s, E[5], 0));
           HIPCHK(hipEventRecord(E[2], s));
           if (gx[parity]) HIPCHK(hipGraphLaunch(gx[4 + parity], s));

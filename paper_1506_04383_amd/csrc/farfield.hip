@@ -163,33 +163,51 @@ __global__ void k_morton(const float2* __restrict__ xy, int32_t n, const BoxInfo
   ids[i] = i;
 }
 
-__global__ void k_gather_sorted(const float2* __restrict__ xy, const int32_t* __restrict__ order,
-                                const uint64_t* __restrict__ codes, int32_t n,
-                                float* __restrict__ xsx, float* __restrict__ xsy,
-                                uint2* __restrict__ ixy) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float2 p = xy[order[i]];
-  xsx[i] = p.x;
-  xsy[i] = p.y;
-  uint64_t c = codes[i];
-  ixy[i] = make_uint2(compact24(c), compact24(c >> 1));
-}
-
-// Inclusive-exclusive FP64 prefix sums of a float array (fixed tiles).
+// Inclusive-exclusive FP64 prefix sums of the sorted coordinates (fixed
+// tiles of PS_TILE points, both axes): tile sums, a scan of the tile sums,
+// then each tile's own scan.
 constexpr int PS_T = 256, PS_I = 8, PS_TILE = PS_T * PS_I;
-__global__ __launch_bounds__(PS_T) void k_fsum_tiles(const float* __restrict__ a, int32_t n,
-                                                     double* __restrict__ part) {
+
+// Points in sorted order (coordinates and quantum cells) and the FP64 sums
+// of both coordinates per tile (part[t], part[stride + t]); each thread takes
+// PS_I consecutive points and adds them in order.
+__global__ __launch_bounds__(PS_T) void k_gather_tiles(const float2* __restrict__ xy,
+                                                       const int32_t* __restrict__ order,
+                                                       const uint64_t* __restrict__ codes,
+                                                       int32_t n, float* __restrict__ xsx,
+                                                       float* __restrict__ xsy,
+                                                       uint2* __restrict__ ixy,
+                                                       double* __restrict__ part, int32_t stride,
+                                                       int32_t* __restrict__ counter) {
   __shared__ double sh[PS_T / 64 + 1];
-  int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
-  double s = 0.0;
-  for (int i = 0; i < PS_I; ++i) if (base + i < n) s += (double)a[base + i];
-  double tot;
-  block_excl_scan<double>(s, sh, &tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;  // node count of k_emit_nodes
+  const int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
+  double sx = 0.0, sy = 0.0;
+  for (int i = 0; i < PS_I; ++i) {
+    const int64_t j = base + i;
+    if (j < n) {
+      const float2 p = xy[order[j]];
+      xsx[j] = p.x;
+      xsy[j] = p.y;
+      const uint64_t c = codes[j];
+      ixy[j] = make_uint2(compact24(c), compact24(c >> 1));
+      sx += (double)p.x;
+      sy += (double)p.y;
+    }
+  }
+  double tx, ty;
+  block_excl_scan<double>(sx, sh, &tx);
+  block_excl_scan<double>(sy, sh, &ty);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = tx;
+    part[stride + blockIdx.x] = ty;
+  }
 }
-__global__ __launch_bounds__(1024) void k_fsum_parts(double* part, int32_t m) {
+// exclusive scan of one axis's m tile sums in place (block b: axis b, at
+// part + b * (m + 1)), the total in part[m]
+__global__ __launch_bounds__(1024) void k_fsum_parts(double* parts, int32_t m) {
   __shared__ double sh[1024 / 64 + 1];
+  double* part = parts + (int64_t)blockIdx.x * (m + 1);
   double carry = 0.0;
   for (int32_t b = 0; b < m; b += blockDim.x) {
     int32_t j = b + threadIdx.x;
@@ -201,10 +219,15 @@ __global__ __launch_bounds__(1024) void k_fsum_parts(double* part, int32_t m) {
   }
   if (threadIdx.x == 0) part[m] = carry;
 }
-__global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ a, int32_t n,
-                                                    const double* __restrict__ part,
-                                                    double* __restrict__ out) {
+// each tile's scan (blockIdx.y: axis)
+__global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ ax,
+                                                    const float* __restrict__ ay, int32_t n,
+                                                    const double* __restrict__ parts,
+                                                    double* __restrict__ ox, double* __restrict__ oy) {
   __shared__ double sh[PS_T / 64 + 1];
+  const float* a = blockIdx.y ? ay : ax;
+  const double* part = parts + (int64_t)blockIdx.y * (gridDim.x + 1);
+  double* out = blockIdx.y ? oy : ox;
   int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
   double v[PS_I], s = 0.0;
   for (int i = 0; i < PS_I; ++i) { v[i] = base + i < n ? (double)a[base + i] : 0.0; s += v[i]; }
@@ -217,12 +240,6 @@ __global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ a,
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
 }
 
-__global__ void k_fill_keys(uint64_t* __restrict__ keys, int32_t m, int32_t* __restrict__ counter) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) keys[i] = ~0ull;
-  if (i == 0) *counter = 0;
-}
-
 __device__ inline int lcp48(uint64_t a, uint64_t b) {
   uint64_t x = (a ^ b) << 16;  // codes live in the low 48 bits
   return x == 0 ? 48 : __clzll(x);
@@ -232,7 +249,7 @@ __device__ inline int lcp48(uint64_t a, uint64_t b) {
 // key = first << 5 | depth (leaves use depth code 31); val = temp index.
 // Node keys at fixed slots: the leaf of the run of equal codes starting at i
 // in slot 2i, the internal node owned by the pair (i, i+1) in slot 2i+1;
-// slots without a node keep the all-ones key from k_fill_keys and sort last.
+// slots without a node get the all-ones key and sort last.
 // Range ends are found by galloping from i (steps 1, 2, 4, ... then a binary
 // search inside the last step), so a node spanning m points costs O(log m)
 // loads.  The node count is added once per wave.
@@ -278,6 +295,10 @@ __global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
   int32_t made = 0;
   if (i < n) {
     const uint64_t ci = codes[i];
+    // (slots 2i and 2i + 1 are this thread's; a slot without a node gets the
+    // all-ones key, which sorts last)
+    keys[2 * i] = ~0ull;
+    keys[2 * i + 1] = ~0ull;
     if (i == 0 || codes[i - 1] != ci) {
       // leaf: run of equal codes starting at i
       const int32_t end = gallop_up(codes, i, n, ci, 0);
@@ -802,7 +823,7 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   const int nbb = std::min(1024, std::max(1, (n + BB_T - 1) / BB_T));
   MM_TRY(ensure<float4>(w->partial, nbb, s));
   const int32_t nps = (n + PS_TILE - 1) / PS_TILE;
-  MM_TRY(ensure<double>(w->pparts, (size_t)nps + 1, s));
+  MM_TRY(ensure<double>(w->pparts, 2 * ((size_t)nps + 1), s));
   DevBuf& pparts = w->pparts;
   MM_TRY(ensure<unsigned long long>(w->statc, 2, s));
 
@@ -819,34 +840,35 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
                                            w->order.as<int32_t>());
   MM_TRY(hipGetLastError());
   MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, cbits, s, &w->sort));
-  k_gather_sorted<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, w->order.as<int32_t>(),
-                                                  w->codes.as<uint64_t>(), n, w->xsx.as<float>(),
-                                                  w->xsy.as<float>(), w->ix.as<uint2>());
-  // FP64 prefix sums of sorted coordinates
-  for (int c = 0; c < 2; ++c) {
-    const float* a = c == 0 ? w->xsx.as<float>() : w->xsy.as<float>();
-    double* out = c == 0 ? w->px.as<double>() : w->py.as<double>();
-    k_fsum_tiles<<<nps, PS_T, 0, s>>>(a, n, pparts.as<double>());
-    k_fsum_parts<<<1, 1024, 0, s>>>(pparts.as<double>(), nps);
-    k_fsum_scan<<<nps, PS_T, 0, s>>>(a, n, pparts.as<double>(), out);
-  }
+  // sorted points, their tile sums, then the FP64 prefix sums of both axes
+  k_gather_tiles<<<nps, PS_T, 0, s>>>((const float2*)xy, w->order.as<int32_t>(),
+                                      w->codes.as<uint64_t>(), n, w->xsx.as<float>(),
+                                      w->xsy.as<float>(), w->ix.as<uint2>(), pparts.as<double>(),
+                                      nps + 1, w->counter.as<int32_t>());
+  k_fsum_parts<<<2, 1024, 0, s>>>(pparts.as<double>(), nps);
+  k_fsum_scan<<<dim3(nps, 2), PS_T, 0, s>>>(w->xsx.as<float>(), w->xsy.as<float>(), n,
+                                            pparts.as<double>(), w->px.as<double>(),
+                                            w->py.as<double>());
   // at most n leaves and n - 1 internal nodes; unused slots keep the all-ones
-  // key and sort last, so the node count never has to reach the host (fill
-  // kernels rather than memsets: this sequence is replayed from HIP graphs)
+  // key and sort last, so the node count never has to reach the host (the
+  // count is cleared by k_gather_tiles: no memsets, this sequence is
+  // replayed from HIP graphs)
   const int32_t NMAX = 2 * n;
-  k_fill_keys<<<(NMAX + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), NMAX,
-                                                 w->counter.as<int32_t>());
   k_emit_nodes<<<(n + 255) / 256, 256, 0, s>>>(w->codes.as<uint64_t>(), n, w->nkeys.as<uint64_t>(),
                                                w->nvals.as<int32_t>(), w->ntmp.as<int4>(),
                                                w->counter.as<int32_t>());
   MM_TRY(hipGetLastError());
   int kbits = 6;
   while ((1ll << (kbits - 6)) < (int64_t)n) kbits++;
-  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), NMAX, kbits, s, &w->sort));
+  // (sorted keys and values read where the passes left them: no copy back)
+  uint64_t* skeys = nullptr;
+  int32_t* svals = nullptr;
+  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), NMAX, kbits, s, &w->sort,
+                          &skeys, &svals));
   const int32_t* Np = w->counter.as<int32_t>();
-  k_first_at<<<(NMAX + 255) / 256, 256, 0, s>>>(w->nkeys.as<uint64_t>(), Np, w->first_at.as<int32_t>());
+  k_first_at<<<(NMAX + 255) / 256, 256, 0, s>>>(skeys, Np, w->first_at.as<int32_t>());
   k_finalize_nodes<<<(NMAX + 255) / 256, 256, 0, s>>>(
-      w->nvals.as<int32_t>(), w->ntmp.as<int4>(), Np, n, w->first_at.as<int32_t>(),
+      svals, w->ntmp.as<int4>(), Np, n, w->first_at.as<int32_t>(),
       w->px.as<double>(), w->py.as<double>(), w->xsx.as<float>(), w->xsy.as<float>(),
       w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
       w->codes.as<uint64_t>());

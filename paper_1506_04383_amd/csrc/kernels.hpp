@@ -86,10 +86,14 @@ hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t
 // iteration (no allocation after the first call: graph-capture safe as long
 // as the histogram scan stays on its single-launch path, <= 2^16 entries).
 struct SortWork {
-  DevBuf k2, v2, hist, offs, sparts;  // sparts: partial sums of the histogram scan
+  DevBuf k2, v2, hist, offs, sparts;  // sparts: per-chunk digit sums of the offset scan
 };
+// Stable LSD sort of (keys, vals) by the low `bits` bits of the keys.  The
+// result is in keys/vals, or, when kout and vout are given, wherever the
+// passes left it (*kout, *vout: keys/vals or the work buffers), with no copy.
 hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s,
-                            SortWork* ws = nullptr);
+                            SortWork* ws = nullptr, uint64_t** kout = nullptr,
+                            int32_t** vout = nullptr);
 hipError_t iota_i32(int32_t* out, int64_t n, hipStream_t s);
 hipError_t widen_i32_u64(const int32_t* in, uint64_t* out, int64_t n, hipStream_t s);
 

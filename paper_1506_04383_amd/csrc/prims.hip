@@ -162,13 +162,25 @@ hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s,
 }
 
 // ---------------------------------------------------------------- radix sort
+// LSD radix sort of (key, value) pairs, 8 bits per pass.  Per pass, block b
+// (RS_TILE consecutive elements) has its digit counts in hist[b * 256 + d]
+// (block-major) and its output bases in offs[b * 256 + d] = the count of all
+// digits below d plus the counts of digit d in blocks before b; the scatter
+// ranks equal digits in input order (stable).  The scatter of a pass also
+// counts the next pass's digits of the elements it writes, per output block
+// (integer atomics into the other of two histogram buffers, which the
+// offset kernel of the pass has cleared: the counts, and so the sort, do not
+// depend on the order of the atomics), so only the first pass launches a
+// histogram kernel.
 constexpr int RS_T = 256;
 constexpr int RS_TILE = 1024;  // elements per block (4 steps of RS_T; >= 2 blocks per CU from 2^19 keys)
+constexpr int RS_TILE_SH = 10;
 constexpr int RS_NW = RS_T / 64;
+constexpr int64_t RS_ONE_MAX = 512;  // blocks whose offsets one workgroup computes
+constexpr int64_t RS_CB = 64;        // blocks per chunk of the three-launch offset scan
 
 __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
-                                                  int shift, int nblocks,
-                                                  int32_t* __restrict__ hist) {
+                                                  int shift, int32_t* __restrict__ hist) {
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -179,19 +191,94 @@ __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ k
     atomicAdd(&h[d], 1);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// Offsets of all nb <= RS_ONE_MAX blocks in one workgroup: four groups of
+// 256 threads (one per digit) each take a quarter of the blocks; also clears
+// the next pass's histogram buffer (if any).
+__global__ __launch_bounds__(1024) void k_rs_offs_one(const int32_t* __restrict__ hist, int64_t nb,
+                                                      int64_t* __restrict__ offs,
+                                                      int32_t* __restrict__ clear) {
+  __shared__ int64_t part[4][256];
+  __shared__ int64_t base[256];
+  __shared__ int64_t sh[1024 / 64 + 1];
+  const int t = threadIdx.x, d = t & 255, g = t >> 8;
+  const int64_t per = (nb + 3) / 4;
+  const int64_t b0 = min(nb, g * per), b1 = min(nb, b0 + per);
+  int64_t sum = 0;
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) sum += hist[b * 256 + d];
+  part[g][d] = sum;
+  __syncthreads();
+  const int64_t tot = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+  int64_t all;
+  const int64_t ex = block_excl_scan<int64_t>(g == 0 ? tot : 0, sh, &all);
+  if (g == 0) base[d] = ex;
+  __syncthreads();
+  int64_t run = base[d];
+  for (int i = 0; i < g; ++i) run += part[i][d];
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) {
+    offs[b * 256 + d] = run;
+    run += hist[b * 256 + d];
+  }
+  if (clear) {
+    int4* c4 = reinterpret_cast<int4*>(clear);  // 256 ints per block: 64 int4
+    for (int64_t j = t; j < nb * 64; j += 1024) c4[j] = make_int4(0, 0, 0, 0);
+  }
+}
+
+// Larger nb, three launches: per chunk of RS_CB blocks the digit sums, one
+// workgroup turning them into chunk bases (in place), then per chunk the
+// running offsets (clearing the next pass's histogram as it goes).
+__global__ __launch_bounds__(256) void k_rs_colsum(const int32_t* __restrict__ hist, int64_t nb,
+                                                   int64_t* __restrict__ csum) {
+  const int d = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * RS_CB, b1 = min(nb, b0 + RS_CB);
+  int64_t sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += hist[b * 256 + d];
+  csum[(int64_t)blockIdx.x * 256 + d] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_rs_cbase(int64_t* __restrict__ csum, int64_t nc) {
+  __shared__ int64_t sh[256 / 64 + 1];
+  const int d = threadIdx.x;
+  int64_t tot = 0;
+  for (int64_t c = 0; c < nc; ++c) tot += csum[c * 256 + d];
+  int64_t all;
+  int64_t run = block_excl_scan<int64_t>(tot, sh, &all);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t v = csum[c * 256 + d];
+    csum[c * 256 + d] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rs_offs(const int32_t* __restrict__ hist, int64_t nb,
+                                                 const int64_t* __restrict__ cbase,
+                                                 int64_t* __restrict__ offs,
+                                                 int32_t* __restrict__ clear) {
+  const int d = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * RS_CB, b1 = min(nb, b0 + RS_CB);
+  int64_t run = cbase[(int64_t)blockIdx.x * 256 + d];
+  for (int64_t b = b0; b < b1; ++b) {
+    offs[b * 256 + d] = run;
+    run += hist[b * 256 + d];
+    if (clear) clear[b * 256 + d] = 0;
+  }
 }
 
 __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ vals, int64_t n,
-                                                     int shift, int nblocks,
-                                                     const int64_t* __restrict__ offs,
+                                                     int shift, const int64_t* __restrict__ offs,
                                                      uint64_t* __restrict__ okeys,
-                                                     int32_t* __restrict__ ovals) {
+                                                     int32_t* __restrict__ ovals,
+                                                     int32_t* __restrict__ nhist) {
   __shared__ int64_t base_d[256];
   __shared__ int32_t wc[RS_NW][256];
   const int t = threadIdx.x, w = t >> 6, l = lane_id();
-  base_d[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  base_d[t] = offs[(int64_t)blockIdx.x * 256 + t];
   int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
   int64_t end = tile0 + RS_TILE < n ? tile0 + RS_TILE : n;
   const uint64_t lt = lanemask_lt();
@@ -218,6 +305,8 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
       for (int i = 0; i < w; ++i) pos += wc[i][d];
       okeys[pos] = key;
       ovals[pos] = val;
+      if (nhist)
+        atomicAdd(&nhist[(pos >> RS_TILE_SH) * 256 + (int)((key >> (shift + 8)) & 255u)], 1);
     }
     __syncthreads();
     int add = 0;
@@ -260,11 +349,14 @@ hipError_t widen_i32_u64(const int32_t* in, uint64_t* out, int64_t n, hipStream_
 }
 
 hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s,
-                            SortWork* ws) {
+                            SortWork* ws, uint64_t** kout, int32_t** vout) {
+  if (kout) *kout = keys;
+  if (vout) *vout = vals;
   if (n <= 1 || bits <= 0) return hipSuccess;
   int passes = (bits + 7) / 8;
   int64_t nb = (n + RS_TILE - 1) / RS_TILE;
   if (nb > (1ll << 30)) return hipErrorInvalidValue;
+  const int64_t nc = (nb + RS_CB - 1) / RS_CB;
   SortWork local;
   SortWork& W = ws ? *ws : local;
   auto grow = [&](DevBuf& b, size_t bytes) -> hipError_t {
@@ -272,28 +364,38 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
   };
   MM_TRY(grow(W.k2, sizeof(uint64_t) * (size_t)n));
   MM_TRY(grow(W.v2, sizeof(int32_t) * (size_t)n));
-  MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)(256 * nb)));
-  MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb + 1)));
-  if (256 * nb > SCAN_SMALL_MAX)
-    MM_TRY(grow(W.sparts, sizeof(int64_t) * (size_t)((256 * nb + SCAN_TILE - 1) / SCAN_TILE + 1)));
-  DevBuf& k2 = W.k2;
-  DevBuf& v2 = W.v2;
-  DevBuf& hist = W.hist;
-  DevBuf& offs = W.offs;
+  MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)(2 * 256 * nb)));
+  MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb)));
+  if (nb > RS_ONE_MAX) MM_TRY(grow(W.sparts, sizeof(int64_t) * (size_t)(256 * nc)));
+  int32_t* hb[2] = {W.hist.as<int32_t>(), W.hist.as<int32_t>() + 256 * nb};
+  int64_t* offs = W.offs.as<int64_t>();
   uint64_t* ka = keys; int32_t* va = vals;
-  uint64_t* kb = k2.as<uint64_t>(); int32_t* vb = v2.as<int32_t>();
+  uint64_t* kb = W.k2.as<uint64_t>(); int32_t* vb = W.v2.as<int32_t>();
+  k_rs_hist<<<(unsigned)nb, RS_T, 0, s>>>(ka, n, 0, hb[0]);
   for (int p = 0; p < passes; ++p) {
-    int shift = 8 * p;
-    k_rs_hist<<<(unsigned)nb, RS_T, 0, s>>>(ka, n, shift, (int)nb, hist.as<int32_t>());
-    MM_TRY(scan_excl_impl<int32_t>(hist.as<int32_t>(), offs.as<int64_t>(), 256 * nb, s, &W.sparts));
-    k_rs_scatter<<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, shift, (int)nb, offs.as<int64_t>(), kb, vb);
+    int32_t* cur = hb[p & 1];
+    int32_t* nxt = p + 1 < passes ? hb[(p + 1) & 1] : nullptr;
+    if (nb <= RS_ONE_MAX) {
+      k_rs_offs_one<<<1, 1024, 0, s>>>(cur, nb, offs, nxt);
+    } else {
+      int64_t* cs = W.sparts.as<int64_t>();
+      k_rs_colsum<<<(unsigned)nc, 256, 0, s>>>(cur, nb, cs);
+      k_rs_cbase<<<1, 256, 0, s>>>(cs, nc);
+      k_rs_offs<<<(unsigned)nc, 256, 0, s>>>(cur, nb, cs, offs, nxt);
+    }
+    k_rs_scatter<<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, 8 * p, offs, kb, vb, nxt);
     MM_TRY(hipGetLastError());
     uint64_t* tk = ka; ka = kb; kb = tk;
     int32_t* tv = va; va = vb; vb = tv;
   }
   if (ka != keys) {
-    MM_TRY(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
-    MM_TRY(hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    if (kout && vout) {  // the caller reads the result where it is
+      *kout = ka;
+      *vout = va;
+    } else {
+      MM_TRY(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+      MM_TRY(hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    }
   }
   return hipGetLastError();
 }
