@@ -33,7 +33,7 @@ struct BoxInfo {
 // order, nodes[0..*counter) the pre-order node records, box the box.
 struct BHWork {
   int32_t cap = 0;
-  DevBuf codes, order, xsx, xsy, ix, px, py, nkeys, nvals, ntmp, first_at, nodes, counter, box,
+  DevBuf codes, order, xsx, xsy, ix, px, py, nmask, npart, ntmp, first_at, nodes, counter, box,
       partial, statc, pparts;
   SortWork sort;
   // learned far field: per-node moments and cell records, sample offsets

@@ -99,6 +99,13 @@ __device__ inline int32_t wave_incl_max(int32_t v) {
   v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false));
   return v;
 }
+// Issue priority of the calling wave above the default.  The far-field
+// kernels run beside the sweep kernel on a second stream; the sweep keeps
+// every SIMD's vector unit busy, so at default priority the far field's
+// waves, and with them its chain of short dependent kernels, would advance
+// only in the sweep's idle cycles.
+__device__ inline void raise_wave_priority() { __builtin_amdgcn_s_setprio(3); }
+
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 // Exclusive block scan (blockDim multiple of 64, <= 1024). Returns the

@@ -42,6 +42,7 @@ constexpr int BB_T = 256;
 
 __global__ __launch_bounds__(BB_T) void k_bbox_partial(const float2* __restrict__ xy, int32_t n,
                                                        float4* __restrict__ part) {
+  raise_wave_priority();
   float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
   for (int32_t i = blockIdx.x * BB_T + threadIdx.x; i < n; i += gridDim.x * BB_T) {
     float2 p = xy[i];
@@ -69,6 +70,7 @@ __device__ void make_box(float4 r, BoxInfo* box);
 
 // One wave reduces the block partials (min / max are exact in any order).
 __global__ void k_bbox_final(const float4* __restrict__ part, int nb, BoxInfo* box) {
+  raise_wave_priority();
   float4 r = part[0];
   for (int i = threadIdx.x; i < nb; i += 64) {
     const float4 p = part[i];
@@ -86,6 +88,7 @@ __global__ void k_bbox_final(const float4* __restrict__ part, int nb, BoxInfo* b
 __global__ __launch_bounds__(BB_T) void k_bbox_seg(const float2* __restrict__ xy,
                                                    const int32_t* __restrict__ goff,
                                                    BoxInfo* __restrict__ box) {
+  raise_wave_priority();
   const int32_t a = goff[blockIdx.x], b = goff[blockIdx.x + 1];
   float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
   for (int32_t i = a + threadIdx.x; i < b; i += BB_T) {
@@ -149,9 +152,11 @@ __device__ inline uint32_t compact24(uint64_t x) {
 // the 48 code bits and its own box is used.
 __global__ void k_morton(const float2* __restrict__ xy, int32_t n, const BoxInfo* __restrict__ box,
                          const int32_t* __restrict__ gid, uint64_t* __restrict__ codes,
-                         int32_t* __restrict__ ids) {
+                         int32_t* __restrict__ ids, uint32_t* __restrict__ nmask) {
+  raise_wave_priority();
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (nmask) nmask[i] = 0;  // node-start masks of k_emit_nodes
   const int32_t g = gid ? gid[i] : 0;
   const BoxInfo b = box[g];
   float2 p = xy[i];
@@ -179,6 +184,7 @@ __global__ __launch_bounds__(PS_T) void k_gather_tiles(const float2* __restrict_
                                                        uint2* __restrict__ ixy,
                                                        double* __restrict__ part, int32_t stride,
                                                        int32_t* __restrict__ counter) {
+  raise_wave_priority();
   __shared__ double sh[PS_T / 64 + 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;  // node count of k_emit_nodes
   const int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
@@ -206,6 +212,7 @@ __global__ __launch_bounds__(PS_T) void k_gather_tiles(const float2* __restrict_
 // exclusive scan of one axis's m tile sums in place (block b: axis b, at
 // part + b * (m + 1)), the total in part[m]
 __global__ __launch_bounds__(1024) void k_fsum_parts(double* parts, int32_t m) {
+  raise_wave_priority();
   __shared__ double sh[1024 / 64 + 1];
   double* part = parts + (int64_t)blockIdx.x * (m + 1);
   double carry = 0.0;
@@ -219,15 +226,10 @@ __global__ __launch_bounds__(1024) void k_fsum_parts(double* parts, int32_t m) {
   }
   if (threadIdx.x == 0) part[m] = carry;
 }
-// each tile's scan (blockIdx.y: axis)
-__global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ ax,
-                                                    const float* __restrict__ ay, int32_t n,
-                                                    const double* __restrict__ parts,
-                                                    double* __restrict__ ox, double* __restrict__ oy) {
-  __shared__ double sh[PS_T / 64 + 1];
-  const float* a = blockIdx.y ? ay : ax;
-  const double* part = parts + (int64_t)blockIdx.y * (gridDim.x + 1);
-  double* out = blockIdx.y ? oy : ox;
+// each tile's scan of one axis (m tiles)
+__device__ inline void fsum_scan_tile(const float* __restrict__ a, int32_t n,
+                                      const double* __restrict__ part, int32_t m,
+                                      double* __restrict__ out, double* sh) {
   int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
   double v[PS_I], s = 0.0;
   for (int i = 0; i < PS_I; ++i) { v[i] = base + i < n ? (double)a[base + i] : 0.0; s += v[i]; }
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(PS_T) void k_fsum_scan(const float* __restrict__ ax
     if (base + i < n) out[base + i] = ex;
     ex += v[i];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+  if ((int32_t)blockIdx.x == m - 1 && threadIdx.x == 0) out[n] = part[m];
 }
 
 __device__ inline int lcp48(uint64_t a, uint64_t b) {
@@ -246,13 +248,18 @@ __device__ inline int lcp48(uint64_t a, uint64_t b) {
 }
 
 // Emit nodes: leaves at bucket starts, internal nodes at owner pairs.
-// key = first << 5 | depth (leaves use depth code 31); val = temp index.
-// Node keys at fixed slots: the leaf of the run of equal codes starting at i
-// in slot 2i, the internal node owned by the pair (i, i+1) in slot 2i+1;
-// slots without a node get the all-ones key and sort last.
-// Range ends are found by galloping from i (steps 1, 2, 4, ... then a binary
-// search inside the last step), so a node spanning m points costs O(log m)
-// loads.  The node count is added once per wave.
+// Node records at fixed slots: the leaf of the run of equal codes starting
+// at i in slot 2i, the internal node owned by the pair (i, i+1) in slot
+// 2i+1 (a slot without a node is marked empty).  Pre-order is the order of
+// (first point, depth), a leaf after every internal node with the same first
+// point; so each point a keeps a mask of the depths of the nodes that start
+// at it (bit 31: its leaf), and a node's pre-order index is the number of
+// nodes that start before a (a prefix sum over the masks' bit counts) plus
+// the number of shallower nodes that start at a.  This gives exactly the
+// order of a sort of the keys (first << 5 | depth code).  Range ends are
+// found by galloping from i (steps 1, 2, 4, ... then a binary search inside
+// the last step), so a node spanning m points costs O(log m) loads.  The node
+// count is added once per wave.
 //
 // first index j in [lo, hi) at or after `from` whose key exceeds `key` under
 // the prefix shift sh (codes are sorted; the answer is > from)
@@ -289,23 +296,19 @@ __device__ inline int32_t gallop_down(const uint64_t* __restrict__ codes, int32_
 }
 
 __global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
-                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                             int4* __restrict__ tmp, int32_t* __restrict__ counter) {
+                             int4* __restrict__ tmp, uint32_t* __restrict__ nmask,
+                             int32_t* __restrict__ counter) {
+  raise_wave_priority();
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   int32_t made = 0;
   if (i < n) {
     const uint64_t ci = codes[i];
-    // (slots 2i and 2i + 1 are this thread's; a slot without a node gets the
-    // all-ones key, which sorts last)
-    keys[2 * i] = ~0ull;
-    keys[2 * i + 1] = ~0ull;
+    int4 leafrec = make_int4(0, 0, 0, -1), intrec = make_int4(0, 0, 0, -1);
     if (i == 0 || codes[i - 1] != ci) {
       // leaf: run of equal codes starting at i
       const int32_t end = gallop_up(codes, i, n, ci, 0);
-      const int32_t slot = 2 * i;
-      keys[slot] = ((uint64_t)i << 5) | 31u;
-      vals[slot] = slot;
-      tmp[slot] = make_int4(i, end - 1, 24, 1);
+      leafrec = make_int4(i, end - 1, 24, 1);
+      atomicOr(&nmask[i], 1u << 31);
       ++made;
     }
     if (i + 1 < n && codes[i + 1] != ci && (codes[i + 1] >> 48) == (ci >> 48)) {
@@ -317,39 +320,120 @@ __global__ void k_emit_nodes(const uint64_t* __restrict__ codes, int32_t n,
       // owner iff points a..i lie in the same child (no split of depth t left of i)
       if ((codes[a] >> (sh - 2)) == (ci >> (sh - 2))) {
         const int32_t end = gallop_up(codes, i, n, pre, sh);
-        const int32_t slot = 2 * i + 1;
-        keys[slot] = ((uint64_t)a << 5) | (uint32_t)t;
-        vals[slot] = slot;
-        tmp[slot] = make_int4(a, end - 1, t, 0);
+        intrec = make_int4(a, end - 1, t, 0);
+        atomicOr(&nmask[a], 1u << t);
         ++made;
       }
     }
+    tmp[2 * i] = leafrec;
+    tmp[2 * i + 1] = intrec;
   }
   made = wave_sum(made);
   if (lane_id() == 0 && made) atomicAdd(counter, made);
 }
 
-__global__ void k_first_at(const uint64_t* __restrict__ keys, const int32_t* __restrict__ Np,
-                           int32_t* __restrict__ first_at) {
-  int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= *Np) return;
-  int32_t f = (int32_t)(keys[p] >> 5);
-  if (p == 0 || (int32_t)(keys[p - 1] >> 5) != f) first_at[f] = p;
+// Node-start counts per tile of PS_TILE points (bit counts of the masks).
+__global__ __launch_bounds__(PS_T) void k_node_tiles(const uint32_t* __restrict__ nmask, int32_t n,
+                                                     int32_t* __restrict__ part) {
+  raise_wave_priority();
+  __shared__ int32_t sh[PS_T / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
+  int32_t c = 0;
+  for (int i = 0; i < PS_I; ++i)
+    if (base + i < n) c += __popc(nmask[base + i]);
+  int32_t tot;
+  block_excl_scan<int32_t>(c, sh, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+// Exclusive scan of m tile counts in place (one work-group), total in part[m].
+__global__ __launch_bounds__(1024) void k_node_parts(int32_t* part, int32_t m) {
+  raise_wave_priority();
+  __shared__ int32_t sh[1024 / 64 + 1];
+  int32_t carry = 0;
+  for (int32_t b = 0; b < m; b += blockDim.x) {
+    const int32_t j = b + threadIdx.x;
+    const int32_t v = j < m ? part[j] : 0;
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t>(v, sh, &tot);
+    if (j < m) part[j] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[m] = carry;
+}
+// first_at[a] = pre-order index of the first node that starts at point a
+// (the nodes starting before a); first_at[n] = the node count.  FUSED: each
+// tile adds the counts of the tiles before it itself (m <= NODE_FUSE_MAX),
+// else part holds their exclusive scan.  Shares its grid with the two FP64
+// coordinate scans (blockIdx.y 0, 1: k_fsum_scan's work; 2: this one).
+constexpr int32_t NODE_FUSE_MAX = 512;
+template <bool FUSED>
+__device__ inline void node_base(const uint32_t* __restrict__ nmask, int32_t n,
+                                 const int32_t* __restrict__ part, int32_t m,
+                                 int32_t* __restrict__ first_at, int32_t* sh) {
+  int32_t carry;
+  if (FUSED) {
+    int32_t c = 0;
+    for (int32_t j = threadIdx.x; j < (int32_t)blockIdx.x; j += PS_T) c += part[j];
+    block_excl_scan<int32_t>(c, sh, &carry);
+  } else {
+    carry = part[blockIdx.x];
+  }
+  const int64_t base = (int64_t)blockIdx.x * PS_TILE + threadIdx.x * PS_I;
+  int32_t v[PS_I], c = 0;
+  for (int i = 0; i < PS_I; ++i) {
+    v[i] = base + i < n ? __popc(nmask[base + i]) : 0;
+    c += v[i];
+  }
+  int32_t tot;
+  int32_t ex = block_excl_scan<int32_t>(c, sh, &tot) + carry;
+  for (int i = 0; i < PS_I; ++i) {
+    if (base + i < n) first_at[base + i] = ex;
+    ex += v[i];
+  }
+  if ((int32_t)blockIdx.x == m - 1 && threadIdx.x == 0) first_at[n] = carry + tot;
 }
 
-__global__ void k_finalize_nodes(const int32_t* __restrict__ vals, const int4* __restrict__ tmp,
-                                 const int32_t* __restrict__ Np, int32_t n,
-                                 const int32_t* __restrict__ first_at,
+// The last three scans of the build in one grid (m tiles x 3): rows 0 and 1
+// the FP64 prefix sums of x and y, row 2 the node bases.
+template <bool FUSED>
+__global__ __launch_bounds__(PS_T) void k_tile_scans(const float* __restrict__ ax,
+                                                     const float* __restrict__ ay, int32_t n,
+                                                     const double* __restrict__ parts,
+                                                     double* __restrict__ ox,
+                                                     double* __restrict__ oy,
+                                                     const uint32_t* __restrict__ nmask,
+                                                     const int32_t* __restrict__ npart,
+                                                     int32_t* __restrict__ first_at) {
+  raise_wave_priority();
+  __shared__ double sh[PS_T / 64 + 1];
+  const int32_t m = gridDim.x;
+  if (blockIdx.y < 2) {
+    fsum_scan_tile(blockIdx.y ? ay : ax, n, parts + (int64_t)blockIdx.y * (m + 1), m,
+                   blockIdx.y ? oy : ox, sh);
+  } else {
+    node_base<FUSED>(nmask, n, npart, m, first_at, reinterpret_cast<int32_t*>(sh));
+  }
+}
+
+// Node records in pre-order, one thread per slot of k_emit_nodes.
+__global__ void k_finalize_nodes(const int4* __restrict__ tmp, const uint32_t* __restrict__ nmask,
+                                 int32_t n, const int32_t* __restrict__ first_at,
                                  const double* __restrict__ px, const double* __restrict__ py,
                                  const float* __restrict__ xsx, const float* __restrict__ xsy,
                                  const uint2* __restrict__ ixy, BHNode* __restrict__ nodes,
                                  int64_t* __restrict__ export_nodes,
                                  const uint64_t* __restrict__ codes) {
-  int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t N = *Np;
-  if (p >= N) return;
-  int4 t = tmp[vals[p]];
+  raise_wave_priority();
+  const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= 2 * n) return;
+  const int4 t = tmp[sl];
+  if (t.w < 0) return;  // no node in this slot
   const int32_t first = t.x, last = t.y, depth = t.z, leaf = t.w;
+  const int32_t N = first_at[n];
+  // pre-order index: nodes starting before `first`, then the shallower ones
+  // starting at it (a leaf's depth code is 31)
+  const uint32_t below = leaf ? 0x7fffffffu : (1u << depth) - 1u;
+  const int32_t p = first_at[first] + __popc(nmask[first] & below);
   const int32_t cnt = last - first + 1;
   BHNode nd;
   // a single point keeps its own coordinates exactly (the traversal reads
@@ -402,6 +486,7 @@ __global__ __launch_bounds__(BHS_T) void k_bh_small(
     float* __restrict__ xsy, uint2* __restrict__ ixy, double* __restrict__ px,
     double* __restrict__ py, BHNode* __restrict__ nodes, int32_t* __restrict__ Np,
     int64_t* __restrict__ export_nodes) {
+  raise_wave_priority();
   // static LDS (112 KB for BHS_MAX = 4096; gfx950 work-groups may hold 160 KB)
   __shared__ uint64_t sk[BHS_MAX];      // code << 12 | id, then codes
   __shared__ uint64_t nk[2 * BHS_MAX];  // node keys
@@ -649,6 +734,7 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_traverse(
     int32_t n, float q, double theta2, float2* __restrict__ F, unsigned long long* __restrict__ stats,
     const uint64_t* __restrict__ scodes, const int32_t* __restrict__ goff,
     const int32_t* __restrict__ first_at) {
+  raise_wave_priority();
   const int l = lane_id();
   const int32_t i = (blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 + l;
   if ((blockIdx.x * TR_WAVES + (threadIdx.x >> 6)) * 64 >= n) return;
@@ -719,6 +805,7 @@ constexpr int EX_BLOCKS = 2048;  // target blocks x slabs to aim for (8 waves pe
 template <bool Q0>
 __global__ __launch_bounds__(EX_T) void k_exact(const float2* __restrict__ xy, int32_t n,
                                                 int32_t L, float q, float2* __restrict__ out) {
+  raise_wave_priority();
   const int32_t u = blockIdx.x * EX_T + threadIdx.x;
   const float2 xu = u < n ? xy[u] : make_float2(0.f, 0.f);
   const int32_t j0 = blockIdx.y * L;
@@ -754,6 +841,7 @@ __global__ __launch_bounds__(EX_T) void k_exact(const float2* __restrict__ xy, i
 
 __global__ void k_exact_sum(const float2* __restrict__ part, int32_t n, int32_t S,
                             float2* __restrict__ F) {
+  raise_wave_priority();
   const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
   float fx = 0.f, fy = 0.f;
@@ -803,10 +891,9 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   MM_TRY(ensure<uint2>(w->ix, n, s));
   MM_TRY(ensure<double>(w->px, n + 1, s));
   MM_TRY(ensure<double>(w->py, n + 1, s));
-  MM_TRY(ensure<uint64_t>(w->nkeys, N2, s));
-  MM_TRY(ensure<int32_t>(w->nvals, N2, s));
+  MM_TRY(ensure<uint32_t>(w->nmask, n, s));
   MM_TRY(ensure<int4>(w->ntmp, N2, s));
-  MM_TRY(ensure<int32_t>(w->first_at, n, s));
+  MM_TRY(ensure<int32_t>(w->first_at, (size_t)n + 1, s));
   MM_TRY(ensure<BHNode>(w->nodes, N2, s));
   MM_TRY(ensure<int32_t>(w->counter, 1, s));
   const int32_t M = seg ? seg->M : 1;
@@ -824,6 +911,7 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   MM_TRY(ensure<float4>(w->partial, nbb, s));
   const int32_t nps = (n + PS_TILE - 1) / PS_TILE;
   MM_TRY(ensure<double>(w->pparts, 2 * ((size_t)nps + 1), s));
+  MM_TRY(ensure<int32_t>(w->npart, (size_t)nps + 1, s));
   DevBuf& pparts = w->pparts;
   MM_TRY(ensure<unsigned long long>(w->statc, 2, s));
 
@@ -837,7 +925,7 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
   }
   k_morton<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(),
                                            seg ? seg->gid : nullptr, w->codes.as<uint64_t>(),
-                                           w->order.as<int32_t>());
+                                           w->order.as<int32_t>(), w->nmask.as<uint32_t>());
   MM_TRY(hipGetLastError());
   MM_TRY(radix_sort_pairs(w->codes.as<uint64_t>(), w->order.as<int32_t>(), n, cbits, s, &w->sort));
   // sorted points, their tile sums, then the FP64 prefix sums of both axes
@@ -845,33 +933,30 @@ hipError_t bh_build_tree(BHWork* w, int32_t n, const float* xy, int64_t* nodes_o
                                       w->codes.as<uint64_t>(), n, w->xsx.as<float>(),
                                       w->xsy.as<float>(), w->ix.as<uint2>(), pparts.as<double>(),
                                       nps + 1, w->counter.as<int32_t>());
-  k_fsum_parts<<<2, 1024, 0, s>>>(pparts.as<double>(), nps);
-  k_fsum_scan<<<dim3(nps, 2), PS_T, 0, s>>>(w->xsx.as<float>(), w->xsy.as<float>(), n,
-                                            pparts.as<double>(), w->px.as<double>(),
-                                            w->py.as<double>());
-  // at most n leaves and n - 1 internal nodes; unused slots keep the all-ones
-  // key and sort last, so the node count never has to reach the host (the
-  // count is cleared by k_gather_tiles: no memsets, this sequence is
+  // node records at fixed slots and the masks of the nodes starting at each
+  // point (at most n leaves and n - 1 internal nodes); the node count stays
+  // on the device (cleared by k_gather_tiles: no memsets, this sequence is
   // replayed from HIP graphs)
-  const int32_t NMAX = 2 * n;
-  k_emit_nodes<<<(n + 255) / 256, 256, 0, s>>>(w->codes.as<uint64_t>(), n, w->nkeys.as<uint64_t>(),
-                                               w->nvals.as<int32_t>(), w->ntmp.as<int4>(),
-                                               w->counter.as<int32_t>());
+  k_emit_nodes<<<(n + 255) / 256, 256, 0, s>>>(w->codes.as<uint64_t>(), n, w->ntmp.as<int4>(),
+                                               w->nmask.as<uint32_t>(), w->counter.as<int32_t>());
+  // scans: the FP64 tile sums of both axes, the node-start counts per tile,
+  // then each tile's FP64 prefix sums and first-node indices in one grid
+  k_fsum_parts<<<2, 1024, 0, s>>>(pparts.as<double>(), nps);
+  k_node_tiles<<<nps, PS_T, 0, s>>>(w->nmask.as<uint32_t>(), n, w->npart.as<int32_t>());
+  const bool fused = nps <= NODE_FUSE_MAX;
+  if (!fused) k_node_parts<<<1, 1024, 0, s>>>(w->npart.as<int32_t>(), nps);
+#define MM_SCANS(F)                                                                               \
+  k_tile_scans<F><<<dim3(nps, 3), PS_T, 0, s>>>(                                                  \
+      w->xsx.as<float>(), w->xsy.as<float>(), n, pparts.as<double>(), w->px.as<double>(),          \
+      w->py.as<double>(), w->nmask.as<uint32_t>(), w->npart.as<int32_t>(), w->first_at.as<int32_t>())
+  if (fused) MM_SCANS(true);
+  else MM_SCANS(false);
+#undef MM_SCANS
   MM_TRY(hipGetLastError());
-  int kbits = 6;
-  while ((1ll << (kbits - 6)) < (int64_t)n) kbits++;
-  // (sorted keys and values read where the passes left them: no copy back)
-  uint64_t* skeys = nullptr;
-  int32_t* svals = nullptr;
-  MM_TRY(radix_sort_pairs(w->nkeys.as<uint64_t>(), w->nvals.as<int32_t>(), NMAX, kbits, s, &w->sort,
-                          &skeys, &svals));
-  const int32_t* Np = w->counter.as<int32_t>();
-  k_first_at<<<(NMAX + 255) / 256, 256, 0, s>>>(skeys, Np, w->first_at.as<int32_t>());
-  k_finalize_nodes<<<(NMAX + 255) / 256, 256, 0, s>>>(
-      svals, w->ntmp.as<int4>(), Np, n, w->first_at.as<int32_t>(),
+  k_finalize_nodes<<<(unsigned)((N2 + 255) / 256), 256, 0, s>>>(
+      w->ntmp.as<int4>(), w->nmask.as<uint32_t>(), n, w->first_at.as<int32_t>(),
       w->px.as<double>(), w->py.as<double>(), w->xsx.as<float>(), w->xsy.as<float>(),
-      w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out,
-      w->codes.as<uint64_t>());
+      w->ix.as<uint2>(), w->nodes.as<BHNode>(), nodes_out, w->codes.as<uint64_t>());
   return hipGetLastError();
 }
 
@@ -905,7 +990,8 @@ hipError_t farfield_bh(BHWork* w, int32_t n, const float* xy, double q, double t
     DevBuf tmp;
     MM_TRY(tmp.alloc(sizeof(uint64_t) * (size_t)n, s));
     k_morton<<<(n + 255) / 256, 256, 0, s>>>((const float2*)xy, n, w->box.as<BoxInfo>(),
-                                             seg ? seg->gid : nullptr, codes_out, tmp.as<int32_t>());
+                                             seg ? seg->gid : nullptr, codes_out, tmp.as<int32_t>(),
+                                             nullptr);
   }
   if (order_out)
     MM_TRY(hipMemcpyAsync(order_out, w->order.p, sizeof(int32_t) * (size_t)n,

@@ -176,11 +176,12 @@ constexpr int RS_T = 256;
 constexpr int RS_TILE = 1024;  // elements per block (4 steps of RS_T; >= 2 blocks per CU from 2^19 keys)
 constexpr int RS_TILE_SH = 10;
 constexpr int RS_NW = RS_T / 64;
-constexpr int64_t RS_ONE_MAX = 512;  // blocks whose offsets one workgroup computes
+constexpr int64_t RS_ONE_MAX = 256;  // blocks whose offsets one workgroup computes
 constexpr int64_t RS_CB = 64;        // blocks per chunk of the three-launch offset scan
 
 __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
                                                   int shift, int32_t* __restrict__ hist) {
+  raise_wave_priority();
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -194,38 +195,29 @@ __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ k
   hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
-// Offsets of all nb <= RS_ONE_MAX blocks in one workgroup: four groups of
-// 256 threads (one per digit) each take a quarter of the blocks; also clears
-// the next pass's histogram buffer (if any).
-__global__ __launch_bounds__(1024) void k_rs_offs_one(const int32_t* __restrict__ hist, int64_t nb,
-                                                      int64_t* __restrict__ offs,
-                                                      int32_t* __restrict__ clear) {
-  __shared__ int64_t part[4][256];
-  __shared__ int64_t base[256];
-  __shared__ int64_t sh[1024 / 64 + 1];
-  const int t = threadIdx.x, d = t & 255, g = t >> 8;
-  const int64_t per = (nb + 3) / 4;
-  const int64_t b0 = min(nb, g * per), b1 = min(nb, b0 + per);
-  int64_t sum = 0;
+// Offsets of all nb <= RS_ONE_MAX blocks in one workgroup of 256 threads
+// (one per digit; a small workgroup finds room beside a running kernel
+// sooner than a large one); also clears the next pass's histogram buffer (if
+// any).
+__global__ __launch_bounds__(256) void k_rs_offs_one(const int32_t* __restrict__ hist, int64_t nb,
+                                                     int64_t* __restrict__ offs,
+                                                     int32_t* __restrict__ clear) {
+  raise_wave_priority();
+  __shared__ int64_t sh[256 / 64 + 1];
+  const int d = threadIdx.x;
+  int64_t tot = 0;
 #pragma unroll 8
-  for (int64_t b = b0; b < b1; ++b) sum += hist[b * 256 + d];
-  part[g][d] = sum;
-  __syncthreads();
-  const int64_t tot = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+  for (int64_t b = 0; b < nb; ++b) tot += hist[b * 256 + d];
   int64_t all;
-  const int64_t ex = block_excl_scan<int64_t>(g == 0 ? tot : 0, sh, &all);
-  if (g == 0) base[d] = ex;
-  __syncthreads();
-  int64_t run = base[d];
-  for (int i = 0; i < g; ++i) run += part[i][d];
+  int64_t run = block_excl_scan<int64_t>(tot, sh, &all);
 #pragma unroll 8
-  for (int64_t b = b0; b < b1; ++b) {
+  for (int64_t b = 0; b < nb; ++b) {
     offs[b * 256 + d] = run;
     run += hist[b * 256 + d];
   }
   if (clear) {
     int4* c4 = reinterpret_cast<int4*>(clear);  // 256 ints per block: 64 int4
-    for (int64_t j = t; j < nb * 64; j += 1024) c4[j] = make_int4(0, 0, 0, 0);
+    for (int64_t j = d; j < nb * 64; j += 256) c4[j] = make_int4(0, 0, 0, 0);
   }
 }
 
@@ -234,6 +226,7 @@ __global__ __launch_bounds__(1024) void k_rs_offs_one(const int32_t* __restrict_
 // running offsets (clearing the next pass's histogram as it goes).
 __global__ __launch_bounds__(256) void k_rs_colsum(const int32_t* __restrict__ hist, int64_t nb,
                                                    int64_t* __restrict__ csum) {
+  raise_wave_priority();
   const int d = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * RS_CB, b1 = min(nb, b0 + RS_CB);
   int64_t sum = 0;
@@ -242,6 +235,7 @@ __global__ __launch_bounds__(256) void k_rs_colsum(const int32_t* __restrict__ h
 }
 
 __global__ __launch_bounds__(256) void k_rs_cbase(int64_t* __restrict__ csum, int64_t nc) {
+  raise_wave_priority();
   __shared__ int64_t sh[256 / 64 + 1];
   const int d = threadIdx.x;
   int64_t tot = 0;
@@ -259,6 +253,7 @@ __global__ __launch_bounds__(256) void k_rs_offs(const int32_t* __restrict__ his
                                                  const int64_t* __restrict__ cbase,
                                                  int64_t* __restrict__ offs,
                                                  int32_t* __restrict__ clear) {
+  raise_wave_priority();
   const int d = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * RS_CB, b1 = min(nb, b0 + RS_CB);
   int64_t run = cbase[(int64_t)blockIdx.x * 256 + d];
@@ -275,6 +270,7 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
                                                      uint64_t* __restrict__ okeys,
                                                      int32_t* __restrict__ ovals,
                                                      int32_t* __restrict__ nhist) {
+  raise_wave_priority();
   __shared__ int64_t base_d[256];
   __shared__ int32_t wc[RS_NW][256];
   const int t = threadIdx.x, w = t >> 6, l = lane_id();
@@ -376,7 +372,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
     int32_t* cur = hb[p & 1];
     int32_t* nxt = p + 1 < passes ? hb[(p + 1) & 1] : nullptr;
     if (nb <= RS_ONE_MAX) {
-      k_rs_offs_one<<<1, 1024, 0, s>>>(cur, nb, offs, nxt);
+      k_rs_offs_one<<<1, 256, 0, s>>>(cur, nb, offs, nxt);
     } else {
       int64_t* cs = W.sparts.as<int64_t>();
       k_rs_colsum<<<(unsigned)nc, 256, 0, s>>>(cur, nb, cs);
