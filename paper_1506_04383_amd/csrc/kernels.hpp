@@ -86,7 +86,7 @@ hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t
 // iteration (no allocation after the first call: graph-capture safe as long
 // as the histogram scan stays on its single-launch path, <= 2^16 entries).
 struct SortWork {
-  DevBuf k2, v2, hist, offs, sparts;  // sparts: per-chunk digit sums of the offset scan
+  DevBuf k2, v2, hist, offs, sparts;  // sparts: partial sums of the histogram scan
 };
 // Stable LSD sort of (keys, vals) by the low `bits` bits of the keys.  The
 // result is in keys/vals, or, when kout and vout are given, wherever the

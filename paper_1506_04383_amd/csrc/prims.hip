@@ -162,25 +162,30 @@ hipError_t scan_excl_impl(const Tin* in, int64_t* out, int64_t n, hipStream_t s,
 }
 
 // ---------------------------------------------------------------- radix sort
-// LSD radix sort of (key, value) pairs, 8 bits per pass.  Per pass, block b
-// (RS_TILE consecutive elements) has its digit counts in hist[b * 256 + d]
-// (block-major) and its output bases in offs[b * 256 + d] = the count of all
-// digits below d plus the counts of digit d in blocks before b; the scatter
-// ranks equal digits in input order (stable).  The scatter of a pass also
-// counts the next pass's digits of the elements it writes, per output block
-// (integer atomics into the other of two histogram buffers, which the
-// offset kernel of the pass has cleared: the counts, and so the sort, do not
-// depend on the order of the atomics), so only the first pass launches a
-// histogram kernel.
+// LSD radix sort of (key, value) pairs, 8 bits per pass; block b holds
+// RS_TILE consecutive elements, and its output base for digit d is the count
+// of all digits below d plus the counts of digit d in blocks before b; the
+// scatter ranks equal digits in input order (stable).  Two forms of the
+// per-pass counts, chosen by the block count:
+// * up to RS_ONE_MAX blocks (few keys: the launch count matters): digit
+//   counts block-major (hist[b * 256 + d]); per pass one 256-thread work-group
+//   computes every block's bases, and the scatter also counts the next pass's
+//   digits of the elements it writes, per output block (integer atomics into
+//   the other of two histogram buffers, which the offset kernel of the pass
+//   has cleared: the counts, and so the sort, do not depend on the order of
+//   the atomics), so only the first pass has a histogram launch;
+// * more blocks: digit-major counts (hist[d * nb + b]) from a histogram
+//   launch per pass and their exclusive scan, which are the bases.
 constexpr int RS_T = 256;
 constexpr int RS_TILE = 1024;  // elements per block (4 steps of RS_T; >= 2 blocks per CU from 2^19 keys)
 constexpr int RS_TILE_SH = 10;
 constexpr int RS_NW = RS_T / 64;
-constexpr int64_t RS_ONE_MAX = 256;  // blocks whose offsets one workgroup computes
-constexpr int64_t RS_CB = 64;        // blocks per chunk of the three-launch offset scan
+constexpr int64_t RS_ONE_MAX = 256;  // block-major form up to this many blocks
 
+template <bool BM>
 __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
-                                                  int shift, int32_t* __restrict__ hist) {
+                                                  int shift, int64_t nb,
+                                                  int32_t* __restrict__ hist) {
   raise_wave_priority();
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
@@ -192,13 +197,14 @@ __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ k
     atomicAdd(&h[d], 1);
   }
   __syncthreads();
-  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+  if (BM) hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+  else hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Offsets of all nb <= RS_ONE_MAX blocks in one workgroup of 256 threads
-// (one per digit; a small workgroup finds room beside a running kernel
-// sooner than a large one); also clears the next pass's histogram buffer (if
-// any).
+// Block-major form: bases of all nb <= RS_ONE_MAX blocks in one work-group of
+// 256 threads (one per digit; a small work-group finds room beside a running
+// kernel sooner than a large one); also clears the next pass's histogram
+// buffer (if any).
 __global__ __launch_bounds__(256) void k_rs_offs_one(const int32_t* __restrict__ hist, int64_t nb,
                                                      int64_t* __restrict__ offs,
                                                      int32_t* __restrict__ clear) {
@@ -221,52 +227,11 @@ __global__ __launch_bounds__(256) void k_rs_offs_one(const int32_t* __restrict__
   }
 }
 
-// Larger nb, three launches: per chunk of RS_CB blocks the digit sums, one
-// workgroup turning them into chunk bases (in place), then per chunk the
-// running offsets (clearing the next pass's histogram as it goes).
-__global__ __launch_bounds__(256) void k_rs_colsum(const int32_t* __restrict__ hist, int64_t nb,
-                                                   int64_t* __restrict__ csum) {
-  raise_wave_priority();
-  const int d = threadIdx.x;
-  const int64_t b0 = (int64_t)blockIdx.x * RS_CB, b1 = min(nb, b0 + RS_CB);
-  int64_t sum = 0;
-  for (int64_t b = b0; b < b1; ++b) sum += hist[b * 256 + d];
-  csum[(int64_t)blockIdx.x * 256 + d] = sum;
-}
-
-__global__ __launch_bounds__(256) void k_rs_cbase(int64_t* __restrict__ csum, int64_t nc) {
-  raise_wave_priority();
-  __shared__ int64_t sh[256 / 64 + 1];
-  const int d = threadIdx.x;
-  int64_t tot = 0;
-  for (int64_t c = 0; c < nc; ++c) tot += csum[c * 256 + d];
-  int64_t all;
-  int64_t run = block_excl_scan<int64_t>(tot, sh, &all);
-  for (int64_t c = 0; c < nc; ++c) {
-    const int64_t v = csum[c * 256 + d];
-    csum[c * 256 + d] = run;
-    run += v;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_rs_offs(const int32_t* __restrict__ hist, int64_t nb,
-                                                 const int64_t* __restrict__ cbase,
-                                                 int64_t* __restrict__ offs,
-                                                 int32_t* __restrict__ clear) {
-  raise_wave_priority();
-  const int d = threadIdx.x;
-  const int64_t b0 = (int64_t)blockIdx.x * RS_CB, b1 = min(nb, b0 + RS_CB);
-  int64_t run = cbase[(int64_t)blockIdx.x * 256 + d];
-  for (int64_t b = b0; b < b1; ++b) {
-    offs[b * 256 + d] = run;
-    run += hist[b * 256 + d];
-    if (clear) clear[b * 256 + d] = 0;
-  }
-}
-
+template <bool BM>
 __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ vals, int64_t n,
-                                                     int shift, const int64_t* __restrict__ offs,
+                                                     int shift, int64_t nb,
+                                                     const int64_t* __restrict__ offs,
                                                      uint64_t* __restrict__ okeys,
                                                      int32_t* __restrict__ ovals,
                                                      int32_t* __restrict__ nhist) {
@@ -274,7 +239,7 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
   __shared__ int64_t base_d[256];
   __shared__ int32_t wc[RS_NW][256];
   const int t = threadIdx.x, w = t >> 6, l = lane_id();
-  base_d[t] = offs[(int64_t)blockIdx.x * 256 + t];
+  base_d[t] = BM ? offs[(int64_t)blockIdx.x * 256 + t] : offs[(int64_t)t * nb + blockIdx.x];
   int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
   int64_t end = tile0 + RS_TILE < n ? tile0 + RS_TILE : n;
   const uint64_t lt = lanemask_lt();
@@ -301,7 +266,7 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
       for (int i = 0; i < w; ++i) pos += wc[i][d];
       okeys[pos] = key;
       ovals[pos] = val;
-      if (nhist)
+      if (BM && nhist)
         atomicAdd(&nhist[(pos >> RS_TILE_SH) * 256 + (int)((key >> (shift + 8)) & 255u)], 1);
     }
     __syncthreads();
@@ -352,7 +317,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
   int passes = (bits + 7) / 8;
   int64_t nb = (n + RS_TILE - 1) / RS_TILE;
   if (nb > (1ll << 30)) return hipErrorInvalidValue;
-  const int64_t nc = (nb + RS_CB - 1) / RS_CB;
+  const bool bm = nb <= RS_ONE_MAX;
   SortWork local;
   SortWork& W = ws ? *ws : local;
   auto grow = [&](DevBuf& b, size_t bytes) -> hipError_t {
@@ -360,26 +325,26 @@ hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, 
   };
   MM_TRY(grow(W.k2, sizeof(uint64_t) * (size_t)n));
   MM_TRY(grow(W.v2, sizeof(int32_t) * (size_t)n));
-  MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)(2 * 256 * nb)));
-  MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb)));
-  if (nb > RS_ONE_MAX) MM_TRY(grow(W.sparts, sizeof(int64_t) * (size_t)(256 * nc)));
-  int32_t* hb[2] = {W.hist.as<int32_t>(), W.hist.as<int32_t>() + 256 * nb};
+  MM_TRY(grow(W.hist, sizeof(int32_t) * (size_t)((bm ? 2 : 1) * 256 * nb)));
+  MM_TRY(grow(W.offs, sizeof(int64_t) * (size_t)(256 * nb + 1)));
+  if (!bm && 256 * nb > SCAN_SMALL_MAX)
+    MM_TRY(grow(W.sparts, sizeof(int64_t) * (size_t)((256 * nb + SCAN_TILE - 1) / SCAN_TILE + 1)));
+  int32_t* hb[2] = {W.hist.as<int32_t>(), W.hist.as<int32_t>() + (bm ? 256 * nb : 0)};
   int64_t* offs = W.offs.as<int64_t>();
   uint64_t* ka = keys; int32_t* va = vals;
   uint64_t* kb = W.k2.as<uint64_t>(); int32_t* vb = W.v2.as<int32_t>();
-  k_rs_hist<<<(unsigned)nb, RS_T, 0, s>>>(ka, n, 0, hb[0]);
+  if (bm) k_rs_hist<true><<<(unsigned)nb, RS_T, 0, s>>>(ka, n, 0, nb, hb[0]);
   for (int p = 0; p < passes; ++p) {
-    int32_t* cur = hb[p & 1];
-    int32_t* nxt = p + 1 < passes ? hb[(p + 1) & 1] : nullptr;
-    if (nb <= RS_ONE_MAX) {
-      k_rs_offs_one<<<1, 256, 0, s>>>(cur, nb, offs, nxt);
+    if (bm) {
+      int32_t* nxt = p + 1 < passes ? hb[(p + 1) & 1] : nullptr;
+      k_rs_offs_one<<<1, 256, 0, s>>>(hb[p & 1], nb, offs, nxt);
+      k_rs_scatter<true><<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, 8 * p, nb, offs, kb, vb, nxt);
     } else {
-      int64_t* cs = W.sparts.as<int64_t>();
-      k_rs_colsum<<<(unsigned)nc, 256, 0, s>>>(cur, nb, cs);
-      k_rs_cbase<<<1, 256, 0, s>>>(cs, nc);
-      k_rs_offs<<<(unsigned)nc, 256, 0, s>>>(cur, nb, cs, offs, nxt);
+      k_rs_hist<false><<<(unsigned)nb, RS_T, 0, s>>>(ka, n, 8 * p, nb, hb[0]);
+      MM_TRY(scan_excl_impl<int32_t>(hb[0], offs, 256 * nb, s, &W.sparts));
+      k_rs_scatter<false><<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, 8 * p, nb, offs, kb, vb,
+                                                        nullptr);
     }
-    k_rs_scatter<<<(unsigned)nb, RS_T, 0, s>>>(ka, va, n, 8 * p, offs, kb, vb, nxt);
     MM_TRY(hipGetLastError());
     uint64_t* tk = ka; ka = kb; kb = tk;
     int32_t* tv = va; va = vb; vb = tv;
