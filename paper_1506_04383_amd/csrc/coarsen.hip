@@ -131,7 +131,12 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
   long long* sc;
   uint32_t mask;
   if (deg <= LP_SMALL) {
-    keys = skey[w]; sc = ssc[w]; mask = LP_SLOTS - 1;
+    // the wave's LDS table, cut to a power of two of at least 2 deg slots
+    // (and one per lane): it holds the same (label, score) pairs as the
+    // full table, so the choice below is the same, with less to clear and scan
+    uint32_t slots = 64;
+    while (slots < 2u * (uint32_t)deg) slots <<= 1;
+    keys = skey[w]; sc = ssc[w]; mask = slots - 1u;
   } else {
     keys = gkeys + hoff[v]; sc = gsc + hoff[v];
     mask = (uint32_t)(hoff[v + 1] - hoff[v]) - 1u;
