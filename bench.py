@@ -574,8 +574,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the layout is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the layout library "
+              "does not shard a layout across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
