@@ -30,6 +30,10 @@ constexpr int32_t kBatchReplay = 4;
 // iterations a single layout enqueues between two reads of its device-side
 // schedule state
 constexpr int32_t kIterChunk = 8;
+// Barnes-Hut levels below this many vertices run the tiled stress sums as
+// kCapPerCU persistent work-groups per compute unit (see mm_layout)
+constexpr int32_t kCapMaxN = 1 << 17;
+constexpr int32_t kCapPerCU = 3;
 // Single-graph levels replay far field and sweep from two graphs above this
 // many vertices, from one graph at or below it.
 constexpr int32_t kSplitMinN = 1 << 16;
@@ -42,6 +46,7 @@ struct mm_context {
   double* pinned = nullptr;      // 16 doubles for small read-backs
   float* alpha_dev = nullptr;
   hipStream_t far = nullptr;     // far field of mm_layout, beside the sweep on `work`
+  int32_t cus = 0;               // compute units of the device
   hipEvent_t ev[8] = {};
   // this device's copy of the fixed scratch of mm_sweep_noalloc (null if its
   // lookup failed; scratch_err then holds the HIP error)
@@ -390,6 +395,7 @@ mm_status mm_context_create(mm_context** out, int32_t device, void* stream) {
     c->bh = mm::bh_work_create();
     HIPCHK(hipHostMalloc((void**)&c->pinned, 16 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipMalloc((void**)&c->alpha_dev, sizeof(float)));
+    HIPCHK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device));
     HIPCHK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->far, hipStreamNonBlocking));
     for (auto& e : c->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDefault));
@@ -1248,11 +1254,18 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       int32_t max_iters = p->max_final_iters;  // every round at full length, then the cap
       for (double a0 = alpha_start; a0 > p->alpha_min; a0 = std::max(a0 * p->alpha_decay, p->alpha_min))
         max_iters += p->iters_per_round;
-      // the part of the sweep that does not read F (tiled levels)
+      // The part of the sweep that does not read F (tiled levels).  On
+      // Barnes-Hut levels below kCapMaxN vertices the far field's chain of
+      // short kernels takes longer than the sums; there the sums run as
+      // kCapPerCU persistent work-groups per compute unit (they fill every
+      // wave slot otherwise), so each kernel of the chain finds room at once.
+      const bool cap_lvl = !cf_lvl && !exact_lvl && !p->mlp_weights && nl < kCapMaxN;
+      const int32_t max_groups = cap_lvl ? kCapPerCU * ctx->cus : 0;
       auto sweep_sums = [&](const float* xin) -> hipError_t {
         if (!ts.built) return hipSuccess;
         return mm::sweep_tiled_partial(ts, lvl, sqrtc, p->coarse_dist_scale, xin, 0.0, p->q, s,
-                                       ctx->alpha_dev, group_lvl, nb_lvl);
+                                       ctx->alpha_dev, group_lvl, nb_lvl, nullptr, nullptr,
+                                       max_groups);
       };
       // the part that reads F, the relative-change sums and the schedule step
       auto sweep_finish = [&](const float* xin, float* xout) -> hipError_t {

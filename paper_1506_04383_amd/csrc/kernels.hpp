@@ -205,7 +205,8 @@ hipError_t sweep_tiled(const TiledSet& ts, int32_t level, const float* sqrtc, do
 hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                                const float* xy, double alpha, double q, hipStream_t s,
                                const float* alpha_dev = nullptr, int32_t group = 0, int32_t nb = 0,
-                               const int32_t* gid = nullptr, const float* galpha = nullptr);
+                               const int32_t* gid = nullptr, const float* galpha = nullptr,
+                               int32_t max_groups = 0);
 hipError_t sweep_tiled_combine(const TiledSet& ts, const float* rho, const float* xy,
                                const float* F, double alpha, float* xy_out, double* delta2_dev,
                                hipStream_t s, const float* alpha_dev = nullptr,

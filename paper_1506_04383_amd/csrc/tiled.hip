@@ -264,27 +264,31 @@ __global__ __launch_bounds__(TS_T) void k_sweep_sliced(
     const int32_t* __restrict__ chunk_slot, const uint16_t* __restrict__ ent,
     const float2* __restrict__ xy, const float* __restrict__ sqrtc, float scale, float alpha,
     float q, float2* __restrict__ partial, const float* __restrict__ alpha_dev,
-    const int32_t* __restrict__ gid, const float* __restrict__ galpha) {
+    const int32_t* __restrict__ gid, const float* __restrict__ galpha, int32_t nunits) {
   constexpr int32_t T = 1 << TB;
   __shared__ float2 slx[16 + T];  // hop table, then the tile's coordinates
   float2* const lut = slx;
   float2* const sx = slx + 16;
   __shared__ float2 ssc[COARSE ? T : 1];  // (sqrt c * scale, unused)
-  const int32_t tile = unit_tile[blockIdx.x];
-  const int32_t s0 = unit_s0[blockIdx.x], s1 = unit_s0[blockIdx.x + 1];
-  const int32_t v0 = tile * T;
-  const int32_t nv = min(T, n - v0);
-  for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
-    sx[i] = xy[v0 + i];
-    if (COARSE) ssc[i] = make_float2(sqrtc[v0 + i] * scale, 0.f);
-  }
   if (alpha_dev) alpha = *alpha_dev;
   if (threadIdx.x < 16) {
     lut[threadIdx.x] = hop_entry<COARSE, Q0>(threadIdx.x);
   }
-  __syncthreads();
   const int l = lane_id();
   const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  // work units blockIdx.x, + gridDim.x, ... (one per work-group unless the
+  // grid is capped to leave room for kernels running beside the sweep)
+  for (int32_t ub = blockIdx.x; ub < nunits; ub += gridDim.x) {
+  const int32_t tile = unit_tile[ub];
+  const int32_t s0 = unit_s0[ub], s1 = unit_s0[ub + 1];
+  const int32_t v0 = tile * T;
+  const int32_t nv = min(T, n - v0);
+  if (ub != (int32_t)blockIdx.x) __syncthreads();  // the previous unit's reads are done
+  for (int32_t i = threadIdx.x; i < nv; i += TS_T) {
+    sx[i] = xy[v0 + i];
+    if (COARSE) ssc[i] = make_float2(sqrtc[v0 + i] * scale, 0.f);
+  }
+  __syncthreads();
   for (int32_t sl = s0 + wv; sl < s1; sl += TS_T / 64) {
     // slice parameters are wave-uniform (scalar registers, scalar branches)
     const int32_t c0 = __builtin_amdgcn_readfirstlane(slice_c0[sl]);
@@ -326,6 +330,7 @@ __global__ __launch_bounds__(TS_T) void k_sweep_sliced(
         if (j + NB + b < h) sweep_block<COARSE, Q0>(bb[b], sx, ssc, lut, xu, scu, al, q, px, py);
     }
     if (lv) partial[chunk_slot[c]] = make_float2(px, py);
+  }
   }
 }
 
@@ -408,8 +413,9 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* sqrtc, double scale,
                                const float* xy, double alpha, double q, hipStream_t s,
                                const float* alpha_dev, int32_t group, int32_t nb,
-                               const int32_t* gid, const float* galpha) {
+                               const int32_t* gid, const float* galpha, int32_t max_groups) {
   const bool coarse = level > 0 && sqrtc != nullptr;
+  const int32_t sl_grid = max_groups > 0 ? std::min(ts.nunits, max_groups) : ts.nunits;
   const bool q0 = q == 0.0;
   if (ts.tbits < 11 || ts.tbits > 13) return hipErrorInvalidValue;
   // a group of G lanes (one 8-entry block each per step) per chunk
@@ -436,10 +442,10 @@ hipError_t sweep_tiled_partial(const TiledSet& ts, int32_t level, const float* s
     if (NB == 4) MM_TSN(GG, 4); else MM_TSN(GG, 2);  \
   } while (0)
 #define MM_SL(NBV, TBV, C, Q)                                                                   \
-  k_sweep_sliced<NBV, TBV, C, Q><<<ts.nunits, TS_T, 0, s>>>(                                     \
+  k_sweep_sliced<NBV, TBV, C, Q><<<sl_grid, TS_T, 0, s>>>(                                       \
       ts.n, ts.unit_c0, ts.unit_tile, ts.slice_base, ts.slice_h, ts.slice_c0, ts.chunk_row,      \
       ts.chunk_slot, ts.ent, (const float2*)xy, sqrtc, (float)scale, (float)alpha, (float)q, part, \
-      alpha_dev, gid, galpha)
+      alpha_dev, gid, galpha, ts.nunits)
 #define MM_SLT(NBV, TBV)                                                                       \
   do {                                                                                         \
     if (coarse) { if (q0) MM_SL(NBV, TBV, true, true); else MM_SL(NBV, TBV, true, false); }    \
