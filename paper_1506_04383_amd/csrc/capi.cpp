@@ -31,7 +31,8 @@ constexpr int32_t kBatchReplay = 4;
 // schedule state
 constexpr int32_t kIterChunk = 8;
 // Barnes-Hut levels below this many vertices run the tiled stress sums as
-// kCapPerCU persistent work-groups per compute unit (see mm_layout)
+// kCapPerCU persistent work-groups per compute unit (two below 2^16
+// vertices, where the far field's share is larger; see mm_layout)
 constexpr int32_t kCapMaxN = 1 << 17;
 constexpr int32_t kCapPerCU = 3;
 // Single-graph levels replay far field and sweep from two graphs above this
@@ -1260,7 +1261,7 @@ mm_status mm_layout(mm_context* ctx, const mm_graph* g, const mm_params* p,
       // kCapPerCU persistent work-groups per compute unit (they fill every
       // wave slot otherwise), so each kernel of the chain finds room at once.
       const bool cap_lvl = !cf_lvl && !exact_lvl && !p->mlp_weights && nl < kCapMaxN;
-      const int32_t max_groups = cap_lvl ? kCapPerCU * ctx->cus : 0;
+      const int32_t max_groups = cap_lvl ? (nl < (1 << 16) ? 2 : kCapPerCU) * ctx->cus : 0;
       auto sweep_sums = [&](const float* xin) -> hipError_t {
         if (!ts.built) return hipSuccess;
         return mm::sweep_tiled_partial(ts, lvl, sqrtc, p->coarse_dist_scale, xin, 0.0, p->q, s,
